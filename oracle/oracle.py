@@ -1,0 +1,382 @@
+"""ctypes binding of the FP64 CPU oracle (kqft_oracle.cpp) plus compositions.
+
+TEST INFRASTRUCTURE ONLY -- see the package docstring.  Everything here follows
+the paper's definitions directly: the bubble B_r(Gamma_L, Gamma_R) (Eq. B_a and
+the BSEs), the loop L(Gamma, G) (Sec. "The loop function"), the Schwinger-Dyson
+equation (Eq. SDE), the susceptibility (Sec. "Susceptibilities") and the
+multiloop flow equations (Eqs. 1l, 2l, 3l of the mfRG section).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "kqft_oracle.cpp")
+_LIB = os.path.join(_HERE, "libkqft_oracle.so")
+
+CH = {"a": 0, "p": 1, "t": 2}
+PREF = {0: 1.0, 1: 0.5, 2: -1.0}
+# class bits of bubble outputs
+C_K1, C_K2, C_K2P, C_K3 = 1, 2, 4, 8
+C_ALL = 15
+# parts of a vertex evaluation
+P_R, P_K1, P_K2, P_K2P, P_K3, P_OTHER, P_ALL = 1, 2, 4, 8, 16, 32, 63
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with g++ (plain IEEE FP64: no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+               "-fno-fast-math", _SRC, "-o", _LIB + ".tmp"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class OCh(C.Structure):
+    _fields_ = [("coef", C.c_double), ("K1", C.c_void_p), ("K2", C.c_void_p),
+                ("K2p", C.c_void_p), ("K3", C.c_void_p)]
+
+
+class OVert(C.Structure):
+    _fields_ = [("r0", C.c_double), ("dr0", C.c_double), ("n", C.c_int), ("L", C.c_double),
+                ("a", C.c_double), ("ch", OCh * 3)]
+
+
+class OProp(C.Structure):
+    _fields_ = [("Delta", C.c_double), ("dDelta", C.c_double), ("T", C.c_double), ("eps", C.c_double),
+                ("sn", C.c_int), ("sL", C.c_double), ("sa", C.c_double),
+                ("SigR", C.c_void_p), ("SigK", C.c_void_p)]
+
+
+class OQuad(C.Structure):
+    _fields_ = [("n", C.c_int), ("map", C.c_int), ("L", C.c_double), ("a", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        P = C.POINTER
+        _lib.oracle_grid_nodes.argtypes = [C.c_int, C.c_double, C.c_double, C.c_void_p]
+        _lib.oracle_gauss_legendre.argtypes = [C.c_int, C.c_void_p, C.c_void_p]
+        _lib.oracle_quad.argtypes = [P(OQuad), C.c_void_p, C.c_void_p]
+        _lib.oracle_grid_locate.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, P(C.c_int),
+                                            P(C.c_double)]
+        _lib.oracle_propagator.argtypes = [C.c_int, P(OProp), C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+        _lib.oracle_bubble_pi.argtypes = [C.c_int, P(OProp), C.c_int, C.c_int, C.c_double, C.c_double,
+                                          C.c_void_p]
+        _lib.oracle_vertex_eval.argtypes = [C.c_int, P(OVert), C.c_int, C.c_uint, C.c_int, C.c_void_p,
+                                            C.c_void_p]
+        _lib.oracle_vertex_legs.argtypes = [P(OVert), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        _lib.oracle_bubble.argtypes = [C.c_int, C.c_int, P(OVert), P(OVert), P(OProp), C.c_int, P(OQuad),
+                                       C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        _lib.oracle_bubble_points.argtypes = [C.c_int, C.c_int, P(OVert), P(OVert), P(OProp), C.c_int,
+                                              P(OQuad), C.c_int, C.c_void_p, C.c_void_p]
+        _lib.oracle_bubble_brute.argtypes = [C.c_int, P(OVert), P(OVert), P(OProp), C.c_int, P(OQuad),
+                                             C.c_double, C.c_double, C.c_double, C.c_void_p]
+        _lib.oracle_loop.argtypes = [C.c_int, P(OVert), P(OProp), C.c_int, P(OQuad), C.c_void_p]
+        _lib.oracle_chi.argtypes = [C.c_int, P(OVert), P(OProp), P(OQuad), C.c_void_p]
+    return _lib
+
+
+# ------------------------------------------------------------------ data model
+@dataclass
+class Grid:
+    """Tangent grid v_i = a tan(x_i atan(L/a)), x_i equidistant in [-1, 1]."""
+    n: int
+    L: float = 20.0
+    a: float = 1.0
+
+    def nodes(self) -> np.ndarray:
+        out = np.zeros(self.n)
+        lib().oracle_grid_nodes(self.n, self.L, self.a, out.ctypes.data)
+        return out
+
+
+@dataclass
+class Quad:
+    """n Gauss-Legendre nodes mapped by the tangent map to [-L, L] (map 0) or to R (map 1)."""
+    n: int
+    map: int = 0
+    L: float = 20.0
+    a: float = 1.0
+
+    def c(self) -> OQuad:
+        return OQuad(self.n, self.map, self.L, self.a)
+
+    def nodes_weights(self):
+        v = np.zeros(self.n)
+        w = np.zeros(self.n)
+        lib().oracle_quad(C.byref(self.c()), v.ctypes.data, w.ctypes.data)
+        return v, w
+
+
+@dataclass
+class Prop:
+    """Propagator parameters: G^R = 1/(v - eps + i Delta - Sigma^R), G^K by the
+    general Keldysh relation with the FDR for the bath; optional dynamic Sigma on a grid."""
+    Delta: float = 1.0
+    T: float = 0.1
+    eps: float = 0.0
+    dDelta: float = 0.0
+    sigma_grid: Optional[Grid] = None
+    SigR: Optional[np.ndarray] = None
+    SigK: Optional[np.ndarray] = None
+
+    def c(self, keep: list) -> OProp:
+        g = self.sigma_grid or Grid(2)
+        p = OProp(self.Delta, self.dDelta, self.T, self.eps, g.n, g.L, g.a, None, None)
+        for name in ("SigR", "SigK"):
+            arr = getattr(self, name)
+            if arr is not None:
+                arr = _as_c(arr)
+                keep.append(arr)
+                setattr(p, name, arr.ctypes.data)
+        return p
+
+
+def _as_c(arr: np.ndarray) -> np.ndarray:
+    """Complex128 arrays -> contiguous; dual arrays are float64 [..., 4] already."""
+    if np.iscomplexobj(arr):
+        return np.ascontiguousarray(arr, dtype=np.complex128)
+    return np.ascontiguousarray(arr, dtype=np.float64)
+
+
+@dataclass
+class Channel:
+    """gamma_r as asymptotic classes; arrays complex [2][n]..[16] (None = zero)."""
+    coef: float = 1.0
+    K1: Optional[np.ndarray] = None
+    K2: Optional[np.ndarray] = None
+    K2p: Optional[np.ndarray] = None
+    K3: Optional[np.ndarray] = None
+
+
+@dataclass
+class Vertex:
+    """Gamma = Gamma_0(r0) + sum_r coef_r gamma_r on one grid (parquet approximation R = Gamma_0)."""
+    grid: Grid
+    r0: float = 0.0
+    ch: list = field(default_factory=lambda: [Channel(0.0), Channel(0.0), Channel(0.0)])
+    dr0: float = 0.0
+
+    def c(self, keep: list) -> OVert:
+        v = OVert()
+        v.r0, v.dr0, v.n, v.L, v.a = self.r0, self.dr0, self.grid.n, self.grid.L, self.grid.a
+        for r in range(3):
+            chn = self.ch[r]
+            v.ch[r].coef = chn.coef
+            for name in ("K1", "K2", "K2p", "K3"):
+                arr = getattr(chn, name)
+                if arr is not None and chn.coef != 0.0:
+                    arr = _as_c(arr)
+                    keep.append(arr)
+                    setattr(v.ch[r], name, arr.ctypes.data)
+                else:
+                    setattr(v.ch[r], name, None)
+        return v
+
+
+def class_shapes(n: int):
+    return {"K1": (2, n, 16), "K2": (2, n, n, 16), "K2p": (2, n, n, 16), "K3": (2, n, n, n, 16)}
+
+
+def _alloc(shape, dual):
+    if dual:
+        return np.zeros(shape + (4,), dtype=np.float64)
+    return np.zeros(shape, dtype=np.complex128)
+
+
+# ------------------------------------------------------------------ primitives
+def propagator(P: Prop, nu, kind: int = 0, dual: bool = False) -> np.ndarray:
+    """Keldysh matrices [npts, 2, 2] of G (kind 0) or S = dG/dDelta (kind 1)."""
+    keep = []
+    nu = np.ascontiguousarray(np.atleast_1d(nu), dtype=np.float64)
+    out = _alloc((len(nu), 2, 2), dual)
+    pc = P.c(keep)
+    lib().oracle_propagator(int(dual), C.byref(pc), kind, len(nu), nu.ctypes.data, out.ctypes.data)
+    return out
+
+
+def bubble_pi(P: Prop, r: int, w: float, vq: float, kind: int = 0) -> np.ndarray:
+    keep = []
+    out = np.zeros(16, dtype=np.complex128)
+    pc = P.c(keep)
+    lib().oracle_bubble_pi(0, C.byref(pc), r, kind, w, vq, out.ctypes.data)
+    return out.reshape(4, 4)
+
+
+def vertex_eval(V: Vertex, r: int, pts, parts: int = P_ALL, dual: bool = False) -> np.ndarray:
+    """Vertex in channel r at points (w, v, v') -> [npts, 2, 16] (X, Y)."""
+    keep = []
+    pts = np.ascontiguousarray(np.atleast_2d(pts), dtype=np.float64)
+    out = _alloc((len(pts), 2, 16), dual)
+    vc = V.c(keep)
+    lib().oracle_vertex_eval(int(dual), C.byref(vc), r, parts, len(pts), pts.ctypes.data, out.ctypes.data)
+    return out
+
+
+def vertex_legs(V: Vertex, al, sg, nu) -> np.ndarray:
+    keep = []
+    al = np.ascontiguousarray(np.atleast_2d(al), dtype=np.int32)
+    sg = np.ascontiguousarray(np.atleast_2d(sg), dtype=np.int32)
+    nu = np.ascontiguousarray(np.atleast_2d(nu), dtype=np.float64)
+    out = np.zeros(len(al), dtype=np.complex128)
+    vc = V.c(keep)
+    lib().oracle_vertex_legs(C.byref(vc), len(al), al.ctypes.data, sg.ctypes.data, nu.ctypes.data, out.ctypes.data)
+    return out
+
+
+def bubble(r: int, left: Vertex, right: Vertex, P: Prop, q: Quad, kind: int = 0, cmask: int = C_ALL,
+           dual: bool = False) -> Channel:
+    """B_r(left, right) as the four asymptotic classes of channel r (coef 1)."""
+    n = left.grid.n
+    sh = class_shapes(n)
+    out = {k: _alloc(s, dual) for k, s in sh.items()}
+    keep = []
+    lc, rc, pc, qc = left.c(keep), right.c(keep), P.c(keep), q.c()
+    rc_ = lib().oracle_bubble(int(dual), r, C.byref(lc), C.byref(rc), C.byref(pc), kind, C.byref(qc), cmask,
+                              out["K1"].ctypes.data, out["K2"].ctypes.data, out["K2p"].ctypes.data,
+                              out["K3"].ctypes.data)
+    if rc_ != 0:
+        raise ValueError("oracle_bubble: bad arguments")
+    return Channel(1.0, out["K1"], out["K2"], out["K2p"], out["K3"])
+
+
+def bubble_points(r: int, left: Vertex, right: Vertex, P: Prop, q: Quad, pts, kind: int = 0,
+                  dual: bool = False) -> np.ndarray:
+    """Selected outputs: pts rows (class bit, iw, i, j) -> [npts, 2, 16]."""
+    pts = np.ascontiguousarray(np.atleast_2d(pts), dtype=np.int32)
+    out = _alloc((len(pts), 2, 16), dual)
+    keep = []
+    lc, rc, pc, qc = left.c(keep), right.c(keep), P.c(keep), q.c()
+    lib().oracle_bubble_points(int(dual), r, C.byref(lc), C.byref(rc), C.byref(pc), kind, C.byref(qc), len(pts),
+                               pts.ctypes.data, out.ctypes.data)
+    return out
+
+
+def bubble_brute(r: int, left: Vertex, right: Vertex, P: Prop, q: Quad, w: float, v: float, vp: float,
+                 kind: int = 0) -> np.ndarray:
+    out = np.zeros((2, 16), dtype=np.complex128)
+    keep = []
+    lc, rc, pc, qc = left.c(keep), right.c(keep), P.c(keep), q.c()
+    lib().oracle_bubble_brute(r, C.byref(lc), C.byref(rc), C.byref(pc), kind, C.byref(qc), w, v, vp,
+                              out.ctypes.data)
+    return out
+
+
+def loop(V: Vertex, P: Prop, q: Quad, kind: int = 0, dual: bool = False) -> np.ndarray:
+    """L(Gamma, G)(v_i) as [n, 4] = Sigma^{a1'|a1} at index 2*a1'+a1 (no overall sign)."""
+    out = _alloc((V.grid.n, 4), dual)
+    keep = []
+    vc, pc, qc = V.c(keep), P.c(keep), q.c()
+    lib().oracle_loop(int(dual), C.byref(vc), C.byref(pc), kind, C.byref(qc), out.ctypes.data)
+    return out
+
+
+def chi(V: Vertex, P: Prop, q: Quad, dual: bool = False) -> np.ndarray:
+    """Pair-space susceptibility chi_a^c(w) [2 (X, D), n, 16]."""
+    out = _alloc((2, V.grid.n, 16), dual)
+    keep = []
+    vc, pc, qc = V.c(keep), P.c(keep), q.c()
+    lib().oracle_chi(int(dual), C.byref(vc), C.byref(pc), C.byref(qc), out.ctypes.data)
+    return out
+
+
+# ------------------------------------------------------------------ compositions
+def bare(grid: Grid, U: float, dU: float = 0.0) -> Vertex:
+    """Gamma_0 only (parquet approximation R = Gamma_0)."""
+    return Vertex(grid, r0=U, dr0=dU)
+
+
+def pt2_k1(grid: Grid, U: float, P: Prop, q: Quad, dual: bool = False, dU: float = 0.0) -> list:
+    """Second-order vertex: K1_r = B_r(Gamma_0, Gamma_0) for r = a, p, t (Sec. PT2: vertexInSOPT
+    calls the bubble once per channel with two bare vertices; only K1 is non-zero)."""
+    g0 = bare(grid, U, dU)
+    return [bubble(r, g0, g0, P, q, 0, C_K1, dual).K1 for r in range(3)]
+
+
+def seeded_vertex(grid: Grid, U: float, P: Prop, q: Quad, noise: Optional[dict] = None, dual: bool = False,
+                  dU: float = 0.0) -> Vertex:
+    """PT2 vertex (K1 only) plus the given noise arrays (noise[r][cls], complex)."""
+    k1 = pt2_k1(grid, U, P, q, dual, dU)
+    chans = []
+    for r in range(3):
+        cls = {"K1": k1[r], "K2": None, "K2p": None, "K3": None}
+        if noise is not None:
+            for name in ("K1", "K2", "K2p", "K3"):
+                nz = noise[r][name]
+                if dual:
+                    d = np.zeros(nz.shape + (4,))
+                    d[..., 0] = nz.real
+                    d[..., 2] = nz.imag
+                    nz = d
+                cls[name] = nz if cls[name] is None else cls[name] + nz
+        chans.append(Channel(1.0, cls["K1"], cls["K2"], cls["K2p"], cls["K3"]))
+    return Vertex(grid, r0=U, dr0=dU, ch=chans)
+
+
+def sde(V: Vertex, P: Prop, q_bubble: Quad, q_loop: Quad, dual: bool = False) -> np.ndarray:
+    """Dynamic self-energy from the SDE (Eq. SDE, a-channel form):
+    Sigma = -1/2 L(Phi, G) with Phi = B_a(Gamma_0, Gamma).  The Hartree loop -L(Gamma_0, G)
+    equals U(<n> - 1/2) in the Keldysh-rotated basis and vanishes at particle-hole symmetry;
+    the constant U/2 Hartree shift is absorbed in G_H (Sec. Hartree-Fock)."""
+    g0 = bare(V.grid, V.r0, V.dr0)
+    phi = bubble(0, g0, V, P, q_bubble, 0, C_K1 | C_K2P, dual)
+    phi_v = Vertex(V.grid, r0=0.0, ch=[Channel(1.0, phi.K1, None, phi.K2p, None), Channel(0.0), Channel(0.0)])
+    L = loop(phi_v, P, q_loop, 0, dual)
+    return -0.5 * L
+
+
+def chi_scalar(chi_pair: np.ndarray) -> np.ndarray:
+    """chi^R(w) = u^T chi v with u on pairs {(0,0),(1,1)} and v on {(0,1),(1,0)}."""
+    m = chi_pair.reshape(chi_pair.shape[:-1] + (4, 4))
+    return m[..., [0, 3], :][..., :, [1, 2]].sum(axis=(-1, -2))
+
+
+def combine(grid: Grid, parts: Sequence[tuple], r0: float = 0.0) -> Vertex:
+    """Vertex from (channel index, Channel, coefficient) triples."""
+    chans = [Channel(0.0), Channel(0.0), Channel(0.0)]
+    for r, chn, c in parts:
+        chans[r] = Channel(c, chn.K1, chn.K2, chn.K2p, chn.K3)
+    return Vertex(grid, r0=r0, ch=chans)
+
+
+def mloop(V: Vertex, P: Prop, q: Quad, nloops: int, dual: bool = False) -> list:
+    """Multiloop insertions (mfRG flow equations, Eqs. 1l-3l):
+      l = 1: gdot_r = B_r(Gamma, Gamma; Pidot),
+      l = 2: gdot_r = B_r(gdot_rbar^(1), Gamma) + B_r(Gamma, gdot_rbar^(1)),
+      l >= 3: + B_r(Gamma, B_r(gdot_rbar^(l-2), Gamma)) (the centre term, as two explicit bubbles),
+    where gdot_rbar = sum of the two other channels.  Returns out[l-1][r] (Channel)."""
+    g = V.grid
+    out = []
+    for ell in range(1, nloops + 1):
+        this = []
+        for r in range(3):
+            if ell == 1:
+                this.append(bubble(r, V, V, P, q, 1, C_ALL, dual))
+                continue
+            prev = out[ell - 2]
+            rbar = combine(g, [(rr, prev[rr], 1.0) for rr in range(3) if rr != r])
+            Lt = bubble(r, rbar, V, P, q, 0, C_ALL, dual)
+            Rt = bubble(r, V, rbar, P, q, 0, C_ALL, dual)
+            tot = {k: getattr(Lt, k) + getattr(Rt, k) for k in ("K1", "K2", "K2p", "K3")}
+            if ell >= 3:
+                prev2 = out[ell - 3]
+                rbar2 = combine(g, [(rr, prev2[rr], 1.0) for rr in range(3) if rr != r])
+                inner = bubble(r, rbar2, V, P, q, 0, C_ALL, dual)
+                Ct = bubble(r, V, combine(g, [(r, inner, 1.0)]), P, q, 0, C_ALL, dual)
+                tot = {k: tot[k] + getattr(Ct, k) for k in tot}
+            this.append(Channel(1.0, tot["K1"], tot["K2"], tot["K2p"], tot["K3"]))
+        out.append(this)
+    return out
