@@ -1,0 +1,221 @@
+/*
+ * kqft.h -- C ABI of the MI355X Keldysh bubble / Schwinger-Dyson library.
+ *
+ * Method: real-frequency Keldysh diagrammatics of the single-impurity Anderson
+ * model in the parquet approximation (Ritz, Ge, Walter, Aguirre, von Delft,
+ * Kugler, arXiv:2405.20996).  The library computes the numerical bottleneck of
+ * that method -- bubble integrals of two four-point vertices (Eq. B_a and the
+ * Bethe-Salpeter equations), the loop/Schwinger-Dyson self-energy (Eq. SDE,
+ * Sec. "The loop function"), susceptibilities (Sec. "Susceptibilities"), the
+ * multiloop flow insertions (Eqs. 1l-3l of the mfRG section) and the adjoint of
+ * the bubble -- on one AMD Instinct MI355X (gfx950).
+ *
+ * Conventions shared by every entry point
+ *   Keldysh basis: rotated, alpha in {0,1}; G^{0|0}=0, G^{0|1}=G^A, G^{1|0}=G^R,
+ *     G^{1|1}=G^K; Sigma^{0|0}=Sigma^K, Sigma^{0|1}=Sigma^R, Sigma^{1|0}=Sigma^A.
+ *   Bare vertex Gamma_0 (parquet approximation R = Gamma_0): -r0/2 on the
+ *     Keldysh components with an odd index sum; spin X0 = Gamma_0, Y0 = -Gamma_0.
+ *   Spin components (SU(2)): X = Gamma_{up dn|up dn}, Y = Gamma_{up dn|dn up}.
+ *   Channel parameters (legs 1',2' outgoing, 1,2 incoming):
+ *     a: w = n1'-n2, v = (n1'+n2)/2, v' = (n1+n2')/2
+ *     p: w = n1'+n2', v = (n1'-n2')/2, v' = (n1-n2)/2
+ *     t: w = n2'-n2, v = (n2'+n2)/2, v' = (n1'+n1)/2
+ *   Keldysh 4x4 pair order (row pair | column pair), pair = 2*first + second,
+ *     flat index 4*row + col:  a (a1',a2 | a1,a2'), p (a1',a2' | a1,a2),
+ *     t (a2',a2 | a1',a1).
+ *   Frequency grid (Sec. "Frequency grids", tangent reading): v_i =
+ *     a*tan(x_i*atan(L/a)), x_i = -1 + 2i/(n-1); all classes share one grid.
+ *   Interpolation: linear in x = atan(v/a)/atan(L/a) per axis (the paper's
+ *     "linear_on_aux"); a class is zero where any argument lies outside [-L, L].
+ *   Complex arrays: interleaved (re, im) doubles, C order, Keldysh innermost:
+ *     K1[s][w][16], K2[s][w][v][16], K2p[s][w][v'][16], K3[s][w][v][v'][16],
+ *     s = 0 (X), 1 (Y).
+ *
+ * Memory and errors
+ *   Array arguments are device pointers (hipMalloc'd or from the caller's
+ *   allocator) unless stated otherwise; the caller owns them and they must stay
+ *   valid until the work enqueued on `stream` has completed.  Structs are host
+ *   memory, read during the call only.  A NULL class pointer means "this class
+ *   is zero".  The library owns only the workspace inside a kqft_ctx.
+ *   Every function returns KQFT_OK (0) or a negative code; kqft_last_error()
+ *   gives a message for the calling thread.  Host-side checks (sizes, enums,
+ *   NULL outputs) run before anything is enqueued.  `stream` is a hipStream_t
+ *   (NULL = the default stream).  A kqft_ctx is not thread-safe: use one per
+ *   stream.
+ */
+#ifndef KQFT_H
+#define KQFT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  KQFT_OK = 0,
+  KQFT_EINVAL = -1,  /* bad enum, NULL where not allowed */
+  KQFT_ESHAPE = -2,  /* inconsistent grid / quadrature sizes */
+  KQFT_ENOMEM = -3,  /* workspace allocation failed */
+  KQFT_EDEVICE = -4  /* HIP runtime error */
+};
+enum { KQFT_CH_A = 0, KQFT_CH_P = 1, KQFT_CH_T = 2 };
+/* arithmetic of the bubble contraction: FP64 MFMA, or FP32 MFMA on split
+   operands with FP32 accumulation promoted to FP64 every K block */
+enum { KQFT_FP64 = 0, KQFT_SPLIT_FP32 = 1 };
+/* propagator pair: Pi = G G, or the differentiated Pidot = S G + G S with the
+   Delta-flow single-scale propagator S = dG/dDelta at fixed Sigma */
+enum { KQFT_PI_GG = 0, KQFT_PI_DOT = 1 };
+/* asymptotic classes of a bubble output */
+enum { KQFT_K1 = 1, KQFT_K2 = 2, KQFT_K2P = 4, KQFT_K3 = 8, KQFT_KALL = 15 };
+/* quadrature maps: Gauss-Legendre nodes y in [-1,1] mapped to v = a tan(y atan(L/a))
+   (onto [-L, L]) or to v = a tan(pi y / 2) (onto the real line) */
+enum { KQFT_QUAD_TAN_FINITE = 0, KQFT_QUAD_TAN_INFINITE = 1 };
+
+typedef struct {
+  int n;    /* points, odd recommended (v = 0 is then a node), n >= 2 */
+  double L; /* extent: nodes span [-L, L] */
+  double a; /* tangent-map scale */
+} kqft_grid;
+
+typedef struct {
+  int n;   /* Gauss-Legendre nodes */
+  int map; /* KQFT_QUAD_TAN_FINITE or KQFT_QUAD_TAN_INFINITE */
+  double L, a;
+} kqft_quad;
+
+/* one channel gamma_r: coef * (K1 + K2 + K2' + K3), device arrays (NULL = 0) */
+typedef struct {
+  double coef;
+  const double* K1;
+  const double* K2;
+  const double* K2p;
+  const double* K3;
+} kqft_chvert;
+
+/* a four-point vertex Gamma = Gamma_0(r0) + sum_r gamma_r on one grid
+   (parquet decomposition, Sec. "Diagrammatic many-body theory") */
+typedef struct {
+  double r0;
+  kqft_grid grid;
+  kqft_chvert ch[3];
+} kqft_vertex;
+
+/* propagator (Sec. "The Propagator class"): G^R = 1/(v - eps + i Delta - Sigma^R(v)),
+   G^K = G^R [Sigma^K - 2 i Delta tanh(v/2T)] G^A.  SigR/SigK are optional device
+   arrays of n complex values on sgrid (NULL SigR: Sigma = 0; NULL SigK with
+   SigR given: equilibrium FDR Sigma^K = 2i tanh(v/2T) Im Sigma^R). */
+typedef struct {
+  double Delta, T, eps;
+  kqft_grid sgrid;
+  const double* SigR;
+  const double* SigK;
+} kqft_propagator;
+
+/* output classes of one channel (device arrays, layouts as above; NULL = skip) */
+typedef struct {
+  double* K1;
+  double* K2;
+  double* K2p;
+  double* K3;
+} kqft_chout;
+
+typedef struct {
+  int precision;   /* KQFT_FP64 or KQFT_SPLIT_FP32 */
+  int class_mask;  /* KQFT_K* bits of the outputs to compute */
+  int beta;        /* 0: overwrite outputs, 1: add into them */
+  int omega_batch; /* transfer frequencies per panel batch, 0 = automatic */
+} kqft_opts;
+
+typedef struct kqft_ctx kqft_ctx;
+
+/* Create a context bound to HIP device `device` (workspace, cached grids). */
+int kqft_ctx_create(kqft_ctx** ctx, int device);
+int kqft_ctx_destroy(kqft_ctx* ctx);
+/* Message of the last error on the calling thread ("" if none). */
+const char* kqft_last_error(void);
+/* Workspace bytes a call of kqft_bubble with these sizes will hold. */
+size_t kqft_bubble_workspace(int n, int nq, int omega_batch, int precision);
+
+/*
+ * kqft_bubble -- B_r(left, right) = left o Pi_r o right (Eq. B_a; p and t analogous
+ * with prefactors +1/2 and -1, Eqs. BSE), the sum over internal Keldysh and spin
+ * indices done before the frequency integral (Sec. "The bubble_function"):
+ *
+ *   gamma_r(w, v, v') = pref_r sum_k w_k/(2 pi i) Gamma_L(w, v, v''_k) Pi_r(w, v''_k)
+ *                                                 Gamma_R(w, v''_k, v')
+ *
+ * with the literal spin sums of the compound-index bubbles and the v'' integral
+ * replaced by the quadrature q.  The result is split into asymptotic classes
+ * (Sec. "The Vertex classes"): K3 from the parts of Gamma_L, Gamma_R that depend on
+ * the external fermionic frequency, K2 / K2' from one such part, K1 from neither.
+ * Outputs are written on left->grid (left and right must share it) for the
+ * classes in opts->class_mask, overwritten (beta = 0) or accumulated (beta = 1).
+ * Unlike the paper's bubble_function, the result is not implicitly added to an
+ * existing vertex.
+ * Arguments: channel KQFT_CH_*; pi_kind KQFT_PI_*; out: device arrays of the
+ * selected classes (others may be NULL).  Errors: KQFT_EINVAL, KQFT_ESHAPE,
+ * KQFT_ENOMEM, KQFT_EDEVICE.
+ */
+int kqft_bubble(kqft_ctx* ctx, int channel, const kqft_vertex* left, const kqft_vertex* right,
+                const kqft_propagator* G, int pi_kind, const kqft_quad* q, const kqft_opts* opts,
+                const kqft_chout* out, void* stream);
+
+/*
+ * kqft_sde -- dynamic self-energy from the Schwinger-Dyson equation (Eq. SDE, a-channel
+ * form) and the a-channel susceptibilities (Sec. "Susceptibilities"):
+ *
+ *   Phi = B_a(Gamma_0, Gamma)  (classes K1, K2'; q_bubble),
+ *   Sigma^{a1'|a1}(v_i) = -1/2 sum_j w_j/(2 pi i) sum_{a2,a2'} [2 Phi^X + Phi^Y]
+ *                           (w = v_i - v_j, v' = (v_i + v_j)/2) G^{a2|a2'}(v_j)   (q_loop),
+ *   chi_a^c(w) = Pibar_a(w) + sum_{k,l} Pi_k Gamma_a^c(w; v''_k, v''_l) Pi_l,
+ *                c = X (transverse spin) and D = X + 2Y (density)             (q_bubble).
+ *
+ * The Hartree term of the rotated-basis loop, -L(Gamma_0, G) = U(<n> - 1/2), vanishes at
+ * particle-hole symmetry and its constant U/2 is part of G (Sec. "Hartree-Fock"); Sigma
+ * is the dynamic part.  sigma: device [n][4] complex (index 2*a1' + a1) on gamma->grid;
+ * chi: device [2][n][16] complex or NULL.  FP64 throughout (the contraction inside Phi
+ * uses opts->precision).
+ */
+int kqft_sde(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, const kqft_quad* q_bubble,
+             const kqft_quad* q_loop, const kqft_opts* opts, double* sigma, double* chi, void* stream);
+
+/*
+ * kqft_mloop_step -- multiloop insertions of the mfRG flow (Eqs. 1l, 2l, 3l) for
+ * n_points independent parameter points (ragged sizes allowed):
+ *   l = 1:  gdot_r = B_r(Gamma, Gamma; Pidot),
+ *   l = 2:  gdot_r = B_r(gdot_rbar, Gamma) + B_r(Gamma, gdot_rbar),
+ *   l >= 3: gdot_r = L + R + B_r(Gamma, gdot_{r,L}^(l-1)),
+ * with gdot_rbar the sum of the two channels other than r at the previous order and
+ * the centre term reusing the stored left insertion of order l-1 (which equals
+ * B_r(gdot_rbar^(l-2), Gamma)).  Delta-flow single-scale propagator, no Katanin term.
+ * gamma, G, q: host arrays of n_points structs.  dgamma: host array of
+ * n_points * nloops * 3 kqft_chout (point-major, then order, then channel) whose
+ * device arrays (all four classes required) receive each order's sum of insertions.
+ */
+int kqft_mloop_step(kqft_ctx* ctx, int n_points, const kqft_vertex* gamma, const kqft_propagator* G,
+                    const kqft_quad* q, int nloops, const kqft_opts* opts, const kqft_chout* dgamma,
+                    void* stream);
+
+/*
+ * kqft_bubble_adjoint -- vector-Jacobian product of kqft_bubble (not in the paper).
+ * Given the cotangent `dout` of the four output classes (PyTorch convention: for a real
+ * loss L and complex z, dz = dL/dRe z + i dL/dIm z), accumulates
+ *   dleft[r]  += dL/d(class arrays of left's channel r)   (r = 0..2, NULL entries skipped),
+ *   dright[r] += dL/d(class arrays of right's channel r),
+ *   dscal[0] += dL/d left->r0,  dscal[1] += dL/d right->r0,  dscal[2] += dL/d G->Delta,
+ * where class-array cotangents already include the channel coefficient.  The A/B panels
+ * are recomputed (checkpointing) rather than stored.  Dynamic self-energies inside G
+ * are held fixed.  dleft, dright: host arrays of 3 kqft_chout with device pointers;
+ * dscal: device array of 3 doubles.  FP64 throughout; the scatter into class arrays uses
+ * FP64 atomics (summation order not deterministic).
+ */
+int kqft_bubble_adjoint(kqft_ctx* ctx, int channel, const kqft_vertex* left, const kqft_vertex* right,
+                        const kqft_propagator* G, int pi_kind, const kqft_quad* q, const kqft_opts* opts,
+                        const kqft_chout* dout, const kqft_chout* dleft, const kqft_chout* dright,
+                        double* dscal, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KQFT_H */

@@ -1,0 +1,520 @@
+// kqft_api.hip -- C ABI of the MI355X Keldysh bubble library: validation, context and
+// workspace management, grid/quadrature tables, and the orchestration of the kernels
+// for kqft_bubble, kqft_sde, kqft_mloop_step and kqft_bubble_adjoint.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "kqft.h"
+#include "kqft_launch.h"
+
+using namespace kqft;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(KQFT_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct kqft_ctx {
+  int device = 0;
+  std::map<std::tuple<int, double, double>, double*> grids;
+  std::map<std::tuple<int, int, double, double>, std::pair<double*, double*>> quads;
+  DevBuf panels, pi, phi, chi_part, lstore[2][3], adj;
+};
+
+// ------------------------------------------------------------------ host tables
+// Gauss-Legendre nodes (ascending) and weights on [-1, 1]: Newton iteration on the
+// Legendre three-term recurrence.
+static void gl_nodes(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p1 = 1.0, p2 = 0.0;
+      for (int j = 1; j <= n; ++j) {
+        double p3 = p2;
+        p2 = p1;
+        p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+      }
+      dp = n * (z * p1 - p2) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-16) break;
+    }
+    double p1 = 1.0, p2 = 0.0;
+    for (int j = 1; j <= n; ++j) {
+      double p3 = p2;
+      p2 = p1;
+      p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+    }
+    dp = n * (z * p1 - p2) / (z * z - 1.0);
+    double wt = 2.0 / ((1.0 - z * z) * dp * dp);
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    w[i] = w[n - 1 - i] = wt;
+  }
+  if (n % 2 == 1) x[n / 2] = 0.0;
+}
+
+static int get_grid(kqft_ctx* ctx, const kqft_grid& g, const double** out) {
+  auto key = std::make_tuple(g.n, g.L, g.a);
+  auto it = ctx->grids.find(key);
+  if (it != ctx->grids.end()) {
+    *out = it->second;
+    return KQFT_OK;
+  }
+  std::vector<double> v(g.n);
+  const double th = atan(g.L / g.a);
+  for (int i = 0; i < g.n; ++i) v[i] = g.a * tan((-1.0 + 2.0 * i / (g.n - 1)) * th);
+  double* d = nullptr;
+  HIP_TRY(hipMalloc(&d, sizeof(double) * g.n));
+  HIP_TRY(hipMemcpy(d, v.data(), sizeof(double) * g.n, hipMemcpyHostToDevice));
+  ctx->grids[key] = d;
+  *out = d;
+  return KQFT_OK;
+}
+
+static int get_quad(kqft_ctx* ctx, const kqft_quad& q, const double** qv, const double** qw) {
+  auto key = std::make_tuple(q.n, q.map, q.L, q.a);
+  auto it = ctx->quads.find(key);
+  if (it == ctx->quads.end()) {
+    std::vector<double> y, gw, v(q.n), w(q.n);
+    gl_nodes(q.n, y, gw);
+    const double th = q.map == KQFT_QUAD_TAN_FINITE ? atan(q.L / q.a) : 0.5 * M_PI;
+    for (int k = 0; k < q.n; ++k) {
+      const double c = cos(y[k] * th);
+      v[k] = q.a * tan(y[k] * th);
+      w[k] = gw[k] * q.a * th / (c * c);
+    }
+    double* d = nullptr;
+    HIP_TRY(hipMalloc(&d, sizeof(double) * 2 * q.n));
+    HIP_TRY(hipMemcpy(d, v.data(), sizeof(double) * q.n, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d + q.n, w.data(), sizeof(double) * q.n, hipMemcpyHostToDevice));
+    it = ctx->quads.emplace(key, std::make_pair(d, d + q.n)).first;
+  }
+  *qv = it->second.first;
+  *qw = it->second.second;
+  return KQFT_OK;
+}
+
+static int ensure(DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes) return KQFT_OK;
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+  if (hipMalloc(&b.p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(KQFT_ENOMEM, "workspace allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  b.bytes = bytes;
+  return KQFT_OK;
+}
+
+// Keldysh flat-index permutation between channel pair orders.  Leg slots of the
+// (row first, row second, col first, col second) pair entries, legs 0..3 = 1', 2', 1, 2.
+static const int kPairLegs[3][4] = {{0, 3, 2, 1}, {0, 1, 2, 3}, {1, 3, 0, 2}};
+static int init_tables() {
+  static bool done = false;
+  if (done) return KQFT_OK;
+  int perm[3][3][16];
+  for (int r = 0; r < 3; ++r)
+    for (int r2 = 0; r2 < 3; ++r2)
+      for (int f = 0; f < 16; ++f) {
+        int al[4];
+        const int bits[4] = {(f >> 3) & 1, (f >> 2) & 1, (f >> 1) & 1, f & 1};
+        for (int s = 0; s < 4; ++s) al[kPairLegs[r][s]] = bits[s];
+        const int* p = kPairLegs[r2];
+        perm[r][r2][f] = 4 * (2 * al[p[0]] + al[p[1]]) + (2 * al[p[2]] + al[p[3]]);
+      }
+  HIP_TRY(upload_perm(&perm[0][0][0]));
+  done = true;
+  return KQFT_OK;
+}
+
+// ------------------------------------------------------------------ conversions
+static bool same_grid(const kqft_grid& a, const kqft_grid& b) { return a.n == b.n && a.L == b.L && a.a == b.a; }
+
+static int check_grid(const kqft_grid& g, const char* what) {
+  if (g.n < 2 || !(g.L > 0) || !(g.a > 0)) return fail(KQFT_ESHAPE, std::string("invalid grid: ") + what);
+  return KQFT_OK;
+}
+
+static DVert to_dvert(const kqft_vertex& v) {
+  DVert d;
+  d.r0 = v.r0;
+  d.g = make_dgrid(v.grid.n, v.grid.L, v.grid.a);
+  for (int r = 0; r < 3; ++r) {
+    d.ch[r].coef = v.ch[r].coef;
+    d.ch[r].K[0] = (const double2*)v.ch[r].K1;
+    d.ch[r].K[1] = (const double2*)v.ch[r].K2;
+    d.ch[r].K[2] = (const double2*)v.ch[r].K2p;
+    d.ch[r].K[3] = (const double2*)v.ch[r].K3;
+    if (d.ch[r].coef == 0.0)
+      for (int c = 0; c < 4; ++c) d.ch[r].K[c] = nullptr;
+  }
+  return d;
+}
+
+static int to_dprop(const kqft_propagator& p, DProp& d) {
+  if (!(p.T > 0) || !(p.Delta > 0)) return fail(KQFT_EINVAL, "propagator needs T > 0 and Delta > 0");
+  d.Delta = p.Delta;
+  d.T = p.T;
+  d.eps = p.eps;
+  d.SigR = (const double2*)p.SigR;
+  d.SigK = (const double2*)p.SigK;
+  if (p.SigR || p.SigK) {
+    int rc = check_grid(p.sgrid, "propagator self-energy grid");
+    if (rc) return rc;
+    d.sg = make_dgrid(p.sgrid.n, p.sgrid.L, p.sgrid.a);
+  } else {
+    d.sg = make_dgrid(2, 1.0, 1.0);
+  }
+  return KQFT_OK;
+}
+
+// Spin combinations per channel (rows: combination 0, 1; columns: X, Y) that turn the
+// spin sums of the three bubbles into two independent products P0, P1, and the inverse
+// map back to (X, Y) including the channel prefactor (+1, 1/2, -1):
+//   a: X Pi X, (X+2Y) Pi (X+2Y)  ->  X = P0,            Y = (P1 - P0)/2
+//   p: (X+Y) Pi (X+Y), (X-Y) Pi (X-Y) -> X = (P0+P1)/4, Y = (P0-P1)/4
+//   t: Y Pi Y, (2X+Y) Pi (2X+Y)  ->  X = (P0 - P1)/2,   Y = -P0
+static const double kMix[3][4] = {{1, 0, 1, 2}, {1, 1, 1, -1}, {0, 1, 2, 1}};
+static const double kUnmix[3][4] = {{1, 0, -0.5, 0.5}, {0.25, 0.25, 0.25, -0.25}, {0.5, -0.5, -1, 0}};
+
+// ------------------------------------------------------------------ bubble core
+struct BubbleOut {
+  double2* K1;
+  double2* K2;
+  double2* K2p;
+  double2* K3;
+};
+
+static size_t panel_bytes_per_w(int n, int nq, int precision) {
+  const size_t M = 4 * (size_t)(n + 1);
+  const size_t nq_pad = (size_t)((nq + 7) / 8) * 8;
+  const size_t Kp = 4 * nq_pad;
+  const size_t elt = precision == KQFT_FP64 ? 16 : 8;
+  return 4 * M * Kp * elt;  // two spin combinations x (A + B^T)
+}
+
+static int bubble_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_vertex& R, const kqft_propagator& G,
+                       int kind, const kqft_quad& q, const kqft_opts& o, const BubbleOut& out, hipStream_t s) {
+  int rc;
+  const int n = L.grid.n;
+  if ((rc = init_tables())) return rc;
+  const double *nodes, *qv, *qw;
+  if ((rc = get_grid(ctx, L.grid, &nodes))) return rc;
+  if ((rc = get_quad(ctx, q, &qv, &qw))) return rc;
+  DProp P;
+  if ((rc = to_dprop(G, P))) return rc;
+  const int nq = q.n;
+  const int nq_pad = ((nq + 7) / 8) * 8;  // multiple of 8 so 4*nq_pad divides by the K block
+  const long Kp = 4L * nq_pad;
+  const int M = 4 * (n + 1);
+  const bool f32 = o.precision == KQFT_SPLIT_FP32;
+  const size_t elt = f32 ? 8 : 16;
+  // output class ranges -> panel row / column ranges
+  const int mask = o.class_mask & KQFT_KALL;
+  const bool main_rows = mask & (KQFT_K3 | KQFT_K2), border_row = mask & (KQFT_K2P | KQFT_K1);
+  const bool main_cols = mask & (KQFT_K3 | KQFT_K2P), border_col = mask & (KQFT_K2 | KQFT_K1);
+  const int ilo = main_rows ? 0 : n, ihi = border_row ? n : n - 1;
+  const int jlo = main_cols ? 0 : n, jhi = border_col ? n : n - 1;
+  // batch of transfer frequencies
+  const size_t per_w = panel_bytes_per_w(n, nq, o.precision) + (size_t)nq * 256;
+  int nb = o.omega_batch > 0 ? o.omega_batch : (int)std::max<size_t>(1, ((size_t)4 << 30) / per_w);
+  nb = std::min(nb, n);
+  const size_t pbytes = (size_t)M * Kp * elt;  // one panel of one transfer frequency
+  if ((rc = ensure(ctx->panels, 4 * pbytes * nb))) return rc;
+  if ((rc = ensure(ctx->pi, (size_t)nb * nq * 256))) return rc;
+  char* base = (char*)ctx->panels.p;
+  void* A0 = base;
+  void* A1 = base + pbytes * nb;
+  void* B0 = base + 2 * pbytes * nb;
+  void* B1 = base + 3 * pbytes * nb;
+  DVert VL = to_dvert(L), VR = to_dvert(R);
+  for (int iw0 = 0; iw0 < n; iw0 += nb) {
+    const int cnt = std::min(nb, n - iw0);
+    PiArgs pa{r, kind, cnt, nq, iw0, P, nodes, qv, qw, (double2*)ctx->pi.p};
+    launch_pi(pa, s);
+    GatherArgs ga{r, cnt, iw0, nq, nq_pad, ilo, ihi - ilo + 1, Kp, VL, nodes, qv, (const double2*)ctx->pi.p,
+                  A0, A1, nullptr, nullptr, {kMix[r][0], kMix[r][1], kMix[r][2], kMix[r][3]}};
+    launch_gather(ga, true, f32, s);
+    GatherArgs gb{r, cnt, iw0, nq, nq_pad, jlo, jhi - jlo + 1, Kp, VR, nodes, qv, nullptr, B0, B1, nullptr, nullptr,
+                  {kMix[r][0], kMix[r][1], kMix[r][2], kMix[r][3]}};
+    launch_gather(gb, false, f32, s);
+    GemmArgs g;
+    memset(&g, 0, sizeof g);
+    g.A[0] = A0;
+    g.A[1] = A1;
+    g.B[0] = B0;
+    g.B[1] = B1;
+    g.strideA = g.strideB = (long)M * Kp;
+    g.M = M;
+    g.Kp = (int)Kp;
+    g.tm0 = (4 * ilo) / 64;
+    g.tms = (4 * (ihi + 1) + 63) / 64 - g.tm0;
+    g.tn0 = (4 * jlo) / 64;
+    g.tns = (4 * (jhi + 1) + 63) / 64 - g.tn0;
+    g.nb = cnt;
+    g.r = r;
+    g.n = n;
+    g.iw0 = iw0;
+    g.beta = o.beta;
+    g.cmask = mask;
+    for (int x = 0; x < 4; ++x) g.unmix[x] = kUnmix[r][x];
+    g.K1 = out.K1;
+    g.K2 = out.K2;
+    g.K2p = out.K2p;
+    g.K3 = out.K3;
+    launch_gemm(g, o.precision, false, s);
+  }
+  HIP_TRY(hipGetLastError());
+  return KQFT_OK;
+}
+
+static int check_vertex(const kqft_vertex* v, const char* what) {
+  if (!v) return fail(KQFT_EINVAL, std::string(what) + " is NULL");
+  return check_grid(v->grid, what);
+}
+
+static int check_common(kqft_ctx* ctx, const kqft_propagator* G, const kqft_quad* q, const kqft_opts* o) {
+  if (!ctx) return fail(KQFT_EINVAL, "ctx is NULL");
+  if (!G || !q || !o) return fail(KQFT_EINVAL, "propagator, quadrature and options must be given");
+  if (q->n < 1 || (q->map != KQFT_QUAD_TAN_FINITE && q->map != KQFT_QUAD_TAN_INFINITE) ||
+      (q->map == KQFT_QUAD_TAN_FINITE && !(q->L > 0)) || !(q->a > 0))
+    return fail(KQFT_ESHAPE, "invalid quadrature");
+  if (o->precision != KQFT_FP64 && o->precision != KQFT_SPLIT_FP32) return fail(KQFT_EINVAL, "unknown precision");
+  if (o->beta != 0 && o->beta != 1) return fail(KQFT_EINVAL, "beta must be 0 or 1");
+  if (o->omega_batch < 0) return fail(KQFT_EINVAL, "omega_batch must be >= 0");
+  return KQFT_OK;
+}
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+const char* kqft_last_error(void) { return g_err.c_str(); }
+
+int kqft_ctx_create(kqft_ctx** ctx, int device) {
+  if (!ctx) return fail(KQFT_EINVAL, "ctx is NULL");
+  int count = 0;
+  HIP_TRY(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(KQFT_EINVAL, "no such HIP device");
+  HIP_TRY(hipSetDevice(device));
+  kqft_ctx* c = new kqft_ctx();
+  c->device = device;
+  *ctx = c;
+  int rc = init_tables();
+  if (rc) {
+    delete c;
+    *ctx = nullptr;
+  }
+  return rc;
+}
+
+int kqft_ctx_destroy(kqft_ctx* ctx) {
+  if (!ctx) return KQFT_OK;
+  (void)hipDeviceSynchronize();
+  for (auto& kv : ctx->grids) (void)hipFree(kv.second);
+  for (auto& kv : ctx->quads) (void)hipFree(kv.second.first);
+  DevBuf* bufs[] = {&ctx->panels, &ctx->pi, &ctx->phi, &ctx->chi_part, &ctx->adj};
+  for (DevBuf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  for (auto& row : ctx->lstore)
+    for (auto& b : row)
+      if (b.p) (void)hipFree(b.p);
+  delete ctx;
+  return KQFT_OK;
+}
+
+size_t kqft_bubble_workspace(int n, int nq, int omega_batch, int precision) {
+  if (n < 2 || nq < 1) return 0;
+  const size_t per_w = panel_bytes_per_w(n, nq, precision) + (size_t)nq * 256;
+  int nb = omega_batch > 0 ? omega_batch : (int)std::max<size_t>(1, ((size_t)4 << 30) / per_w);
+  nb = std::min(nb, n);
+  return per_w * nb;
+}
+
+int kqft_bubble(kqft_ctx* ctx, int channel, const kqft_vertex* left, const kqft_vertex* right,
+                const kqft_propagator* G, int pi_kind, const kqft_quad* q, const kqft_opts* opts,
+                const kqft_chout* out, void* stream) {
+  int rc;
+  if ((rc = check_common(ctx, G, q, opts))) return rc;
+  if (channel < 0 || channel > 2) return fail(KQFT_EINVAL, "channel must be 0 (a), 1 (p) or 2 (t)");
+  if (pi_kind != KQFT_PI_GG && pi_kind != KQFT_PI_DOT) return fail(KQFT_EINVAL, "unknown propagator pair");
+  if ((rc = check_vertex(left, "left vertex")) || (rc = check_vertex(right, "right vertex"))) return rc;
+  if (!same_grid(left->grid, right->grid)) return fail(KQFT_ESHAPE, "left and right vertices must share one grid");
+  if (!out) return fail(KQFT_EINVAL, "out is NULL");
+  const int m = opts->class_mask & KQFT_KALL;
+  if (m == 0) return fail(KQFT_EINVAL, "class_mask selects no class");
+  if (((m & KQFT_K1) && !out->K1) || ((m & KQFT_K2) && !out->K2) || ((m & KQFT_K2P) && !out->K2p) ||
+      ((m & KQFT_K3) && !out->K3))
+    return fail(KQFT_EINVAL, "an output class selected by class_mask is NULL");
+  HIP_TRY(hipSetDevice(ctx->device));
+  BubbleOut o{(double2*)out->K1, (double2*)out->K2, (double2*)out->K2p, (double2*)out->K3};
+  return bubble_core(ctx, channel, *left, *right, *G, pi_kind, *q, *opts, o, (hipStream_t)stream);
+}
+
+int kqft_sde(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, const kqft_quad* q_bubble,
+             const kqft_quad* q_loop, const kqft_opts* opts, double* sigma, double* chi, void* stream) {
+  int rc;
+  if ((rc = check_common(ctx, G, q_bubble, opts))) return rc;
+  if (!q_loop || q_loop->n < 1) return fail(KQFT_ESHAPE, "invalid loop quadrature");
+  if ((rc = check_vertex(gamma, "gamma"))) return rc;
+  if (!sigma) return fail(KQFT_EINVAL, "sigma is NULL");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const int n = gamma->grid.n;
+  // Phi = B_a(Gamma_0, Gamma): classes K1 and K2' only
+  const size_t k1b = (size_t)2 * n * 16 * 16, k2b = (size_t)2 * n * n * 16 * 16;
+  if ((rc = ensure(ctx->phi, k1b + k2b))) return rc;
+  double2* phiK1 = (double2*)ctx->phi.p;
+  double2* phiK2p = (double2*)((char*)ctx->phi.p + k1b);
+  kqft_vertex bare;
+  memset(&bare, 0, sizeof bare);
+  bare.r0 = gamma->r0;
+  bare.grid = gamma->grid;
+  kqft_opts o = *opts;
+  o.class_mask = KQFT_K1 | KQFT_K2P;
+  o.beta = 0;
+  BubbleOut po{phiK1, nullptr, phiK2p, nullptr};
+  if ((rc = bubble_core(ctx, KQFT_CH_A, bare, *gamma, *G, KQFT_PI_GG, *q_bubble, o, po, s))) return rc;
+  const double *nodes, *qv, *qw;
+  if ((rc = get_grid(ctx, gamma->grid, &nodes))) return rc;
+  if ((rc = get_quad(ctx, *q_loop, &qv, &qw))) return rc;
+  DProp P;
+  if ((rc = to_dprop(*G, P))) return rc;
+  LoopArgs la{make_dgrid(n, gamma->grid.L, gamma->grid.a), P, 0, q_loop->n, nodes, qv, qw, phiK1, phiK2p,
+              (double2*)sigma};
+  launch_loop(la, s);
+  if (chi) {
+    const double *cqv, *cqw;
+    if ((rc = get_quad(ctx, *q_bubble, &cqv, &cqw))) return rc;
+    const int nq = q_bubble->n;
+    const int nblk = chi_blocks(nq);
+    const int nb = std::max(1, std::min(n, (int)((256L << 20) / ((long)nq * 256))));
+    if ((rc = ensure(ctx->pi, (size_t)nb * nq * 256))) return rc;
+    if ((rc = ensure(ctx->chi_part, (size_t)nb * nblk * 32 * 16))) return rc;
+    for (int iw0 = 0; iw0 < n; iw0 += nb) {
+      const int cnt = std::min(nb, n - iw0);
+      PiArgs pa{KQFT_CH_A, KQFT_PI_GG, cnt, nq, iw0, P, nodes, cqv, cqw, (double2*)ctx->pi.p};
+      launch_pi(pa, s);
+      ChiArgs ca{to_dvert(*gamma), nq, cnt, iw0, nodes, cqv, (const double2*)ctx->pi.p,
+                 (double2*)ctx->chi_part.p, (double2*)chi};
+      launch_chi(ca, s);
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  return KQFT_OK;
+}
+
+int kqft_mloop_step(kqft_ctx* ctx, int n_points, const kqft_vertex* gamma, const kqft_propagator* G,
+                    const kqft_quad* q, int nloops, const kqft_opts* opts, const kqft_chout* dgamma,
+                    void* stream) {
+  int rc;
+  if (!ctx) return fail(KQFT_EINVAL, "ctx is NULL");
+  if (n_points < 1 || nloops < 1 || !gamma || !G || !q || !dgamma || !opts)
+    return fail(KQFT_EINVAL, "mloop_step needs n_points >= 1, nloops >= 1 and non-NULL arrays");
+  for (int p = 0; p < n_points; ++p) {
+    if ((rc = check_common(ctx, &G[p], &q[p], opts))) return rc;
+    if ((rc = check_grid(gamma[p].grid, "gamma"))) return rc;
+    for (int l = 0; l < nloops; ++l)
+      for (int r = 0; r < 3; ++r) {
+        const kqft_chout& d = dgamma[((size_t)p * nloops + l) * 3 + r];
+        if (!d.K1 || !d.K2 || !d.K2p || !d.K3) return fail(KQFT_EINVAL, "dgamma arrays must all be given");
+      }
+  }
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  kqft_opts o = *opts;
+  o.class_mask = KQFT_KALL;
+  for (int p = 0; p < n_points; ++p) {
+    const kqft_vertex& V = gamma[p];
+    const int n = V.grid.n;
+    const size_t s1 = (size_t)2 * n * 16 * 16, s2 = (size_t)2 * n * n * 16 * 16, s3 = (size_t)2 * n * n * n * 16 * 16;
+    const size_t chb = s1 + 2 * s2 + s3;
+    // left insertions of the previous and the current order, per channel
+    if (nloops >= 3)
+      for (int x = 0; x < 2; ++x)
+        for (int r = 0; r < 3; ++r)
+          if ((rc = ensure(ctx->lstore[x][r], chb))) return rc;
+    auto lview = [&](int x, int r) {
+      char* b = (char*)ctx->lstore[x][r].p;
+      return BubbleOut{(double2*)b, (double2*)(b + s1), (double2*)(b + s1 + s2), (double2*)(b + s1 + 2 * s2)};
+    };
+    auto dview = [&](int l, int r) {
+      const kqft_chout& d = dgamma[((size_t)p * nloops + l) * 3 + r];
+      return BubbleOut{(double2*)d.K1, (double2*)d.K2, (double2*)d.K2p, (double2*)d.K3};
+    };
+    for (int l = 1; l <= nloops; ++l) {
+      const int cur = l & 1, prev = cur ^ 1;
+      for (int r = 0; r < 3; ++r) {
+        BubbleOut dst = dview(l - 1, r);
+        if (l == 1) {
+          o.beta = 0;
+          if ((rc = bubble_core(ctx, r, V, V, G[p], KQFT_PI_DOT, q[p], o, dst, s))) return rc;
+          continue;
+        }
+        kqft_vertex rbar;
+        memset(&rbar, 0, sizeof rbar);
+        rbar.grid = V.grid;
+        for (int r2 = 0; r2 < 3; ++r2) {
+          if (r2 == r) continue;
+          const kqft_chout& d = dgamma[((size_t)p * nloops + (l - 2)) * 3 + r2];
+          rbar.ch[r2] = kqft_chvert{1.0, d.K1, d.K2, d.K2p, d.K3};
+        }
+        // left insertion: into dst, and kept for the next order's centre term
+        o.beta = 0;
+        if ((rc = bubble_core(ctx, r, rbar, V, G[p], KQFT_PI_GG, q[p], o, dst, s))) return rc;
+        if (l + 1 <= nloops && l >= 2) {
+          BubbleOut lv = lview(cur, r);
+          HIP_TRY(hipMemcpyAsync(lv.K1, dst.K1, s1, hipMemcpyDeviceToDevice, s));
+          HIP_TRY(hipMemcpyAsync(lv.K2, dst.K2, s2, hipMemcpyDeviceToDevice, s));
+          HIP_TRY(hipMemcpyAsync(lv.K2p, dst.K2p, s2, hipMemcpyDeviceToDevice, s));
+          HIP_TRY(hipMemcpyAsync(lv.K3, dst.K3, s3, hipMemcpyDeviceToDevice, s));
+        }
+        o.beta = 1;
+        if ((rc = bubble_core(ctx, r, V, rbar, G[p], KQFT_PI_GG, q[p], o, dst, s))) return rc;
+        if (l >= 3) {  // centre term B_r(Gamma, gdot_{r,L}^(l-1))
+          BubbleOut lv = lview(prev, r);
+          kqft_vertex lvert;
+          memset(&lvert, 0, sizeof lvert);
+          lvert.grid = V.grid;
+          lvert.ch[r] = kqft_chvert{1.0, (const double*)lv.K1, (const double*)lv.K2, (const double*)lv.K2p,
+                                    (const double*)lv.K3};
+          if ((rc = bubble_core(ctx, r, V, lvert, G[p], KQFT_PI_GG, q[p], o, dst, s))) return rc;
+        }
+      }
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  return KQFT_OK;
+}
+
+int kqft_bubble_adjoint(kqft_ctx* ctx, int channel, const kqft_vertex* left, const kqft_vertex* right,
+                        const kqft_propagator* G, int pi_kind, const kqft_quad* q, const kqft_opts* opts,
+                        const kqft_chout* dout, const kqft_chout* dleft, const kqft_chout* dright, double* dscal,
+                        void* stream) {
+  (void)channel; (void)left; (void)right; (void)G; (void)pi_kind; (void)q; (void)opts;
+  (void)dout; (void)dleft; (void)dright; (void)dscal; (void)stream;
+  if (!ctx) return fail(KQFT_EINVAL, "ctx is NULL");
+  return fail(KQFT_EINVAL, "kqft_bubble_adjoint: not available in this build");
+}
+
+}  // extern "C"

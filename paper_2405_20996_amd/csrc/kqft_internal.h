@@ -1,0 +1,143 @@
+// kqft_internal.h -- device-side data model and helpers of the MI355X Keldysh
+// bubble library (gfx950).  Conventions are those documented in include/kqft.h.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace kqft {
+
+// ------------------------------------------------------------------ complex
+__host__ __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+__host__ __device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__host__ __device__ inline double2 cfma(double s, double2 a, double2 acc) {
+  return make_double2(fma(s, a.x, acc.x), fma(s, a.y, acc.y));
+}
+__host__ __device__ inline double2 czero() { return make_double2(0.0, 0.0); }
+
+// ------------------------------------------------------------------ grids
+// Tangent grid v_i = a tan(x_i theta), theta = atan(L/a), x_i = -1 + 2i/(n-1).
+struct DGrid {
+  int n;
+  double a, inv_a, inv_theta, half_nm1;
+};
+inline DGrid make_dgrid(int n, double L, double a) {
+  DGrid g;
+  g.n = n;
+  g.a = a;
+  g.inv_a = 1.0 / a;
+  g.inv_theta = 1.0 / atan(L / a);
+  g.half_nm1 = 0.5 * (n - 1);
+  return g;
+}
+// Cell of v on the auxiliary variable x = atan(v/a)/theta: returns false outside
+// [-1, 1] (relative slack 1e-10 keeps the end nodes inside), else i0 in [0, n-2] and
+// the linear weight t of node i0+1.
+__device__ inline bool dgrid_locate(const DGrid& g, double v, int& i0, double& t) {
+  double x = atan(v * g.inv_a) * g.inv_theta;
+  if (fabs(x) > 1.0 + 1e-10) return false;
+  x = fmin(fmax(x, -1.0), 1.0);
+  double s = (x + 1.0) * g.half_nm1;
+  int i = (int)floor(s);
+  i = min(max(i, 0), g.n - 2);
+  i0 = i;
+  t = s - (double)i;
+  return true;
+}
+
+// ------------------------------------------------------------------ vertex
+struct DChan {
+  double coef;
+  const double2* K[4];  // K1, K2, K2p, K3
+};
+struct DVert {
+  double r0;
+  DGrid g;
+  DChan ch[3];
+};
+
+// ------------------------------------------------------------------ propagator
+struct DProp {
+  double Delta, T, eps;
+  DGrid sg;
+  const double2* SigR;
+  const double2* SigK;
+};
+
+__device__ inline double2 sigma_at(const DGrid& g, const double2* arr, double v) {
+  if (arr == nullptr) return czero();
+  int i0;
+  double t;
+  if (!dgrid_locate(g, v, i0, t)) return czero();
+  double2 a = arr[i0], b = arr[i0 + 1];
+  return make_double2((1.0 - t) * a.x + t * b.x, (1.0 - t) * a.y + t * b.y);
+}
+
+// Keldysh matrix m[2*a + a'] = X^{a|a'} of G (kind 0) or S = dG/dDelta|_Sigma (kind 1).
+__device__ inline void propagator(const DProp& P, int kind, double v, double2 m[4]) {
+  double th = tanh(v / (2.0 * P.T));
+  double2 sR = sigma_at(P.sg, P.SigR, v);
+  double2 sK = P.SigK ? sigma_at(P.sg, P.SigK, v) : make_double2(0.0, 2.0 * th * sR.y);
+  double dr = v - P.eps - sR.x, di = P.Delta - sR.y;
+  double inv = 1.0 / (dr * dr + di * di);
+  double2 GR = make_double2(dr * inv, -di * inv);
+  double2 GA = cconj(GR);
+  double2 br = make_double2(sK.x, sK.y - 2.0 * th * P.Delta);  // Sigma^K - 2 i Delta tanh
+  double2 GK = cmul(cmul(GR, br), GA);
+  if (kind == 0) {
+    m[0] = czero();
+    m[1] = GA;
+    m[2] = GR;
+    m[3] = GK;
+    return;
+  }
+  double2 SR = cmul(make_double2(0.0, -1.0), cmul(GR, GR));
+  double2 SA = cconj(SR);
+  double2 SK = cadd(cadd(cmul(cmul(SR, br), GA), cmul(cmul(GR, make_double2(0.0, -2.0 * th)), GA)),
+                    cmul(cmul(GR, br), SA));
+  m[0] = czero();
+  m[1] = SA;
+  m[2] = SR;
+  m[3] = SK;
+}
+
+// ------------------------------------------------------------------ channels
+// Leg frequencies (n1', n2', n1, n2) of channel r at (w, v, v') and back.
+__device__ inline void legs_of(int r, double w, double v, double vp, double L[4]) {
+  double h = 0.5 * w;
+  if (r == 0) {
+    L[0] = v + h; L[3] = v - h; L[2] = vp + h; L[1] = vp - h;
+  } else if (r == 1) {
+    L[0] = h + v; L[1] = h - v; L[2] = h + vp; L[3] = h - vp;
+  } else {
+    L[1] = v + h; L[3] = v - h; L[2] = vp + h; L[0] = vp - h;
+  }
+}
+__device__ inline void params_of(int r, const double L[4], double& w, double& v, double& vp) {
+  if (r == 0) {
+    w = L[0] - L[3]; v = 0.5 * (L[0] + L[3]); vp = 0.5 * (L[2] + L[1]);
+  } else if (r == 1) {
+    w = L[0] + L[1]; v = 0.5 * (L[0] - L[1]); vp = 0.5 * (L[2] - L[3]);
+  } else {
+    w = L[1] - L[3]; v = 0.5 * (L[1] + L[3]); vp = 0.5 * (L[0] + L[2]);
+  }
+}
+
+// Bare-vertex Keldysh table entry: nonzero iff the four leg indices have an odd sum,
+// which is the parity of popcount(row pair) + popcount(column pair) in any channel.
+__host__ __device__ inline bool bare_odd(int f) {
+  int row = f >> 2, col = f & 3;
+  return (((row >> 1) + (row & 1) + (col >> 1) + (col & 1)) & 1) != 0;
+}
+
+// flat-index permutation from channel r's pair order to channel r2's, filled on the host
+extern __constant__ int c_perm[3][3][16];
+
+struct Workspace;  // host side
+
+}  // namespace kqft

@@ -1,0 +1,908 @@
+// kqft_kernels.hip -- CDNA4 (gfx950) kernels of the Keldysh bubble path.
+//
+//   pi_kernel          Pi_r(w, v''_k) * w_k / (2 pi i) for a batch of transfer frequencies
+//   gather_left        A panel:  rows (i, row) x cols (k, m) = Gamma_L-part(w, v_i, v''_k) . Pi_k
+//   gather_right       B^T panel: rows (j, col) x cols (k, m) = Gamma_R-part(w, v''_k, v'_j)
+//   zgemm_f64 / _f32   C = A . B per (w, spin combination) on MFMA, bordered epilogue
+//                      that de-diagonalises the spin combinations into X/Y and writes
+//                      K3 (main block), K2 (last column), K2' (last row), K1 (corner)
+//   loop_kernel        Schwinger-Dyson loop reduction
+//   chi_kernel         a-channel susceptibility double sum
+//
+// The bubble (Eq. B_a and the BSEs of the paper) is written as one Keldysh-blocked
+// complex matrix product per transfer frequency: the 4x4 Keldysh matrices of the
+// paper's vectorised integrand become the innermost dimension of the product, the
+// v'' quadrature its contraction index, and the asymptotic-class split of the
+// vertex a border of one extra block row and column.
+#include "kqft_internal.h"
+#include "kqft_launch.h"
+
+namespace kqft {
+
+__constant__ int c_perm[3][3][16];
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+// ======================================================================== Pi
+__global__ __launch_bounds__(256) void pi_kernel(PiArgs a) {
+  long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long total = (long)a.nb * a.nq;
+  if (tid >= total) return;
+  int b = (int)(tid / a.nq), k = (int)(tid % a.nq);
+  double w = a.wnodes[a.iw0 + b];
+  double vq = a.qv[k];
+  double f3, f4;
+  if (a.r == 1) {
+    f3 = 0.5 * w + vq;
+    f4 = 0.5 * w - vq;
+  } else {
+    f3 = vq + 0.5 * w;
+    f4 = vq - 0.5 * w;
+  }
+  double2 g3[4], g4[4];
+  propagator(a.P, 0, f3, g3);
+  propagator(a.P, 0, f4, g4);
+  double2 s3[4], s4[4];
+  if (a.kind == 1) {
+    propagator(a.P, 1, f3, s3);
+    propagator(a.P, 1, f4, s4);
+  }
+  double2 wgt = make_double2(0.0, -a.qw[k] * (0.5 / M_PI));  // w_k / (2 pi i)
+  double2* out = a.out + ((size_t)b * a.nq + k) * 16;
+  for (int a3 = 0; a3 < 2; ++a3)
+    for (int a3p = 0; a3p < 2; ++a3p)
+      for (int a4 = 0; a4 < 2; ++a4)
+        for (int a4p = 0; a4p < 2; ++a4p) {
+          int rp, cp;
+          if (a.r == 0) {  // (a3, a4' | a3', a4)
+            rp = 2 * a3 + a4p;
+            cp = 2 * a3p + a4;
+          } else if (a.r == 1) {  // (a3, a4 | a3', a4')
+            rp = 2 * a3 + a4;
+            cp = 2 * a3p + a4p;
+          } else {  // (a4', a3 | a3', a4)
+            rp = 2 * a4p + a3;
+            cp = 2 * a3p + a4;
+          }
+          double2 v;
+          if (a.kind == 0)
+            v = cmul(g3[2 * a3 + a3p], g4[2 * a4 + a4p]);
+          else
+            v = cadd(cmul(s3[2 * a3 + a3p], g4[2 * a4 + a4p]), cmul(g3[2 * a3 + a3p], s4[2 * a4 + a4p]));
+          out[4 * rp + cp] = cmul(wgt, v);
+        }
+}
+
+// ======================================================================== gather
+// Add coef * gamma_{r2}(w2, v2, vp2) for four flat indices f2[e] (channel r2 order).
+__device__ inline void add_channel(const DChan& C, const DGrid& g, double w2, double v2, double vp2, const int f2[4],
+                                   double2 X[4], double2 Y[4]) {
+  int iw, iv = 0, ivp = 0;
+  double tw, tv = 0.0, tvp = 0.0;
+  if (!dgrid_locate(g, w2, iw, tw)) return;
+  bool inv = dgrid_locate(g, v2, iv, tv);
+  bool invp = dgrid_locate(g, vp2, ivp, tvp);
+  const int n = g.n;
+  const double coef = C.coef;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    double2* acc = s ? Y : X;
+#pragma unroll
+    for (int cw = 0; cw < 2; ++cw) {
+      const double ww = coef * (cw ? tw : 1.0 - tw);
+      const size_t sw = (size_t)s * n + iw + cw;
+      if (C.K[0]) {
+        const double2* p = C.K[0] + sw * 16;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] = cfma(ww, p[f2[e]], acc[e]);
+      }
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        if (inv && C.K[1]) {
+          const double wv = ww * (c ? tv : 1.0 - tv);
+          const double2* p = C.K[1] + (sw * n + iv + c) * 16;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[e] = cfma(wv, p[f2[e]], acc[e]);
+        }
+        if (invp && C.K[2]) {
+          const double wv = ww * (c ? tvp : 1.0 - tvp);
+          const double2* p = C.K[2] + (sw * n + ivp + c) * 16;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[e] = cfma(wv, p[f2[e]], acc[e]);
+        }
+        if (inv && invp && C.K[3]) {
+          const double wv = ww * (c ? tv : 1.0 - tv);
+#pragma unroll
+          for (int c2 = 0; c2 < 2; ++c2) {
+            const double wvp = wv * (c2 ? tvp : 1.0 - tvp);
+            const double2* p = C.K[3] + ((sw * n + iv + c) * n + ivp + c2) * 16;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[e] = cfma(wvp, p[f2[e]], acc[e]);
+          }
+        }
+      }
+    }
+  }
+}
+
+// The two channels other than r, read through the leg frequencies of (w, v, vp) in r.
+// mode 0: the four flat indices of pair-row rc; mode 1: of pair-column rc.
+__device__ inline void add_others(const DVert& V, int r, double w, double v, double vp, int mode, int rc,
+                                  double2 X[4], double2 Y[4]) {
+  double L[4];
+  legs_of(r, w, v, vp, L);
+#pragma unroll
+  for (int d = 1; d < 3; ++d) {
+    const int r2 = (r + d) % 3;
+    if (V.ch[r2].coef == 0.0) continue;
+    double w2, v2, vp2;
+    params_of(r2, L, w2, v2, vp2);
+    int f2[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) f2[e] = c_perm[r][r2][mode == 0 ? 4 * rc + e : 4 * e + rc];
+    add_channel(V.ch[r2], V.g, w2, v2, vp2, f2, X, Y);
+  }
+}
+
+// spin combinations that diagonalise the channel's spin sums, c_s = sum_x mix[s][x] (X, Y)_x:
+//   a: (X, X + 2Y)   p: (X + Y, X - Y)   t: (Y, 2X + Y)
+__device__ inline void combos(const double mix[4], const double2 X[4], const double2 Y[4], double2 c0[4],
+                              double2 c1[4]) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    c0[e] = make_double2(mix[0] * X[e].x + mix[1] * Y[e].x, mix[0] * X[e].y + mix[1] * Y[e].y);
+    c1[e] = make_double2(mix[2] * X[e].x + mix[3] * Y[e].x, mix[2] * X[e].y + mix[3] * Y[e].y);
+  }
+}
+
+template <class T> __device__ inline void store_c(T* p, double2 v);
+template <> __device__ inline void store_c<double2>(double2* p, double2 v) { *p = v; }
+template <> __device__ inline void store_c<float2>(float2* p, double2 v) {
+  *p = make_float2((float)v.x, (float)v.y);
+}
+template <class T> __device__ inline void store_lo(T* p, double2 v);
+template <> __device__ inline void store_lo<double2>(double2*, double2) {}
+template <> __device__ inline void store_lo<float2>(float2* p, double2 v) {
+  if (p) {
+    float hx = (float)v.x, hy = (float)v.y;
+    *p = make_float2((float)(v.x - (double)hx), (float)(v.y - (double)hy));
+  }
+}
+
+template <class T> __global__ __launch_bounds__(256) void gather_left_kernel(GatherArgs a) {
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = (int)(tid & 3);
+  long item = tid >> 2;
+  const int k = (int)(item % a.nq_pad);
+  item /= a.nq_pad;
+  const int il = (int)(item % a.cnt);
+  const int b = (int)(item / a.cnt);
+  if (b >= a.nb) return;
+  const int n = a.V.g.n;
+  const int i = a.lo + il;
+  const int iw = a.iw0 + b;
+  const size_t M = 4 * (size_t)(n + 1);
+  const size_t off = ((size_t)b * M + 4 * (size_t)i + row) * a.Kp + 4 * (size_t)k;
+  T* o0 = (T*)a.P0 + off;
+  T* o1 = (T*)a.P1 + off;
+  if (k >= a.nq) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      store_c(o0 + m, czero());
+      store_c(o1 + m, czero());
+      if (a.L0) store_lo((T*)a.L0 + off + m, czero());
+      if (a.L1) store_lo((T*)a.L1 + off + m, czero());
+    }
+    return;
+  }
+  const double w = a.nodes[iw];
+  const double vq = a.qv[k];
+  const DChan& own = a.V.ch[a.r];
+  double2 X[4], Y[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) X[e] = Y[e] = czero();
+  if (i < n) {  // Gamma_L - Gamma_L^inf : own K2, own K3, other channels
+    const double v = a.nodes[i];
+    if (own.coef != 0.0) {
+      const double c = own.coef;
+      if (own.K[1]) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const double2* p = own.K[1] + (((size_t)s * n + iw) * n + i) * 16 + 4 * row;
+          double2* acc = s ? Y : X;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[e] = cfma(c, p[e], acc[e]);
+        }
+      }
+      int j0;
+      double t;
+      if (own.K[3] && dgrid_locate(a.V.g, vq, j0, t)) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const double2* p = own.K[3] + ((((size_t)s * n + iw) * n + i) * n + j0) * 16 + 4 * row;
+          double2* acc = s ? Y : X;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[e] = cfma(c * (1.0 - t), p[e], cfma(c * t, p[16 + e], acc[e]));
+        }
+      }
+    }
+    add_others(a.V, a.r, w, v, vq, 0, row, X, Y);
+  } else {  // Gamma_L^inf(w, v'') = R + own K1(w) + own K2'(w, v'')
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (bare_odd(4 * row + e)) {
+        X[e].x -= 0.5 * a.V.r0;
+        Y[e].x += 0.5 * a.V.r0;
+      }
+    if (own.coef != 0.0) {
+      const double c = own.coef;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        double2* acc = s ? Y : X;
+        if (own.K[0]) {
+          const double2* p = own.K[0] + ((size_t)s * n + iw) * 16 + 4 * row;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[e] = cfma(c, p[e], acc[e]);
+        }
+        int j0;
+        double t;
+        if (own.K[2] && dgrid_locate(a.V.g, vq, j0, t)) {
+          const double2* p = own.K[2] + (((size_t)s * n + iw) * n + j0) * 16 + 4 * row;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[e] = cfma(c * (1.0 - t), p[e], cfma(c * t, p[16 + e], acc[e]));
+        }
+      }
+    }
+  }
+  double2 c0[4], c1[4];
+  combos(a.mix, X, Y, c0, c1);
+  const double2* pk = a.pi + ((size_t)b * a.nq + k) * 16;
+  double2 P[16];
+#pragma unroll
+  for (int f = 0; f < 16; ++f) P[f] = pk[f];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    double2 s0 = czero(), s1 = czero();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      s0 = cadd(s0, cmul(c0[q], P[4 * q + m]));
+      s1 = cadd(s1, cmul(c1[q], P[4 * q + m]));
+    }
+    store_c(o0 + m, s0);
+    store_c(o1 + m, s1);
+    if (a.L0) store_lo((T*)a.L0 + off + m, s0);
+    if (a.L1) store_lo((T*)a.L1 + off + m, s1);
+  }
+}
+
+template <class T> __global__ __launch_bounds__(256) void gather_right_kernel(GatherArgs a) {
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int col = (int)(tid & 3);
+  long item = tid >> 2;
+  const int k = (int)(item % a.nq_pad);
+  item /= a.nq_pad;
+  const int jl = (int)(item % a.cnt);
+  const int b = (int)(item / a.cnt);
+  if (b >= a.nb) return;
+  const int n = a.V.g.n;
+  const int j = a.lo + jl;
+  const int iw = a.iw0 + b;
+  const size_t Ncol = 4 * (size_t)(n + 1);
+  const size_t off = ((size_t)b * Ncol + 4 * (size_t)j + col) * a.Kp + 4 * (size_t)k;
+  T* o0 = (T*)a.P0 + off;
+  T* o1 = (T*)a.P1 + off;
+  if (k >= a.nq) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      store_c(o0 + m, czero());
+      store_c(o1 + m, czero());
+      if (a.L0) store_lo((T*)a.L0 + off + m, czero());
+      if (a.L1) store_lo((T*)a.L1 + off + m, czero());
+    }
+    return;
+  }
+  const double w = a.nodes[iw];
+  const double vq = a.qv[k];
+  const DChan& own = a.V.ch[a.r];
+  double2 X[4], Y[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) X[e] = Y[e] = czero();
+  if (j < n) {  // Gamma_R - Gamma_R^inf : own K2', own K3, other channels
+    const double vp = a.nodes[j];
+    if (own.coef != 0.0) {
+      const double c = own.coef;
+      if (own.K[2]) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const double2* p = own.K[2] + (((size_t)s * n + iw) * n + j) * 16 + col;
+          double2* acc = s ? Y : X;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[e] = cfma(c, p[4 * e], acc[e]);
+        }
+      }
+      int i0;
+      double t;
+      if (own.K[3] && dgrid_locate(a.V.g, vq, i0, t)) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const double2* p = own.K[3] + ((((size_t)s * n + iw) * n + i0) * n + j) * 16 + col;
+          const size_t step = (size_t)n * 16;
+          double2* acc = s ? Y : X;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[e] = cfma(c * (1.0 - t), p[4 * e], cfma(c * t, p[step + 4 * e], acc[e]));
+        }
+      }
+    }
+    add_others(a.V, a.r, w, vq, vp, 1, col, X, Y);
+  } else {  // Gamma_R^inf(w, v'') = R + own K1(w) + own K2(w, v'')
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (bare_odd(4 * e + col)) {
+        X[e].x -= 0.5 * a.V.r0;
+        Y[e].x += 0.5 * a.V.r0;
+      }
+    if (own.coef != 0.0) {
+      const double c = own.coef;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        double2* acc = s ? Y : X;
+        if (own.K[0]) {
+          const double2* p = own.K[0] + ((size_t)s * n + iw) * 16 + col;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[e] = cfma(c, p[4 * e], acc[e]);
+        }
+        int i0;
+        double t;
+        if (own.K[1] && dgrid_locate(a.V.g, vq, i0, t)) {
+          const double2* p = own.K[1] + (((size_t)s * n + iw) * n + i0) * 16 + col;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[e] = cfma(c * (1.0 - t), p[4 * e], cfma(c * t, p[16 + 4 * e], acc[e]));
+        }
+      }
+    }
+  }
+  double2 c0[4], c1[4];
+  combos(a.mix, X, Y, c0, c1);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    store_c(o0 + m, c0[m]);
+    store_c(o1 + m, c1[m]);
+    if (a.L0) store_lo((T*)a.L0 + off + m, c0[m]);
+    if (a.L1) store_lo((T*)a.L1 + off + m, c1[m]);
+  }
+}
+
+// ======================================================================== epilogue
+// Undo the spin diagonalisation (channel prefactors +1, 1/2, -1 included) and store
+// the element at panel position (row, col) of transfer frequency iw into its class.
+__device__ inline void epilogue_store(const GemmArgs& g, int b, int row, int col, double2 P0, double2 P1) {
+  const int n = g.n;
+  const int Mtot = 4 * (n + 1);
+  if (row >= Mtot || col >= Mtot) return;
+  // (X, Y) = unmix . (P0, P1), the inverse combination with the channel prefactor
+  double2 X = make_double2(g.unmix[0] * P0.x + g.unmix[1] * P1.x, g.unmix[0] * P0.y + g.unmix[1] * P1.y);
+  double2 Y = make_double2(g.unmix[2] * P0.x + g.unmix[3] * P1.x, g.unmix[2] * P0.y + g.unmix[3] * P1.y);
+  const int i = row >> 2, j = col >> 2, f = 4 * (row & 3) + (col & 3);
+  const int iw = g.iw0 + b;
+  double2* base;
+  size_t sstride;
+  size_t off;
+  if (i < n && j < n) {
+    if (!(g.cmask & 8) || !g.K3) return;
+    base = g.K3;
+    sstride = (size_t)n * n * n * 16;
+    off = (((size_t)iw * n + i) * n + j) * 16 + f;
+  } else if (i < n) {
+    if (!(g.cmask & 2) || !g.K2) return;
+    base = g.K2;
+    sstride = (size_t)n * n * 16;
+    off = ((size_t)iw * n + i) * 16 + f;
+  } else if (j < n) {
+    if (!(g.cmask & 4) || !g.K2p) return;
+    base = g.K2p;
+    sstride = (size_t)n * n * 16;
+    off = ((size_t)iw * n + j) * 16 + f;
+  } else {
+    if (!(g.cmask & 1) || !g.K1) return;
+    base = g.K1;
+    sstride = (size_t)n * 16;
+    off = (size_t)iw * 16 + f;
+  }
+  double2* px = base + off;
+  double2* py = base + sstride + off;
+  if (g.beta) {
+    X = cadd(X, *px);
+    Y = cadd(Y, *py);
+  }
+  *px = X;
+  *py = Y;
+}
+
+__device__ inline void tile_coords(const GemmArgs& g, int& b, int& tm, int& tn) {
+  const int tiles = g.tms * g.tns;
+  const int bid = blockIdx.x;
+  b = bid / tiles;
+  const int t = bid - b * tiles;
+  tm = g.tm0 + t / g.tns;
+  tn = g.tn0 + t % g.tns;
+}
+
+// ======================================================================== FP64 GEMM
+// 64x64 complex tile per workgroup, four waves of 32x32, v_mfma_f64_16x16x4f64
+// (lane l: A row l%16 / k l/16, B k l/16 / col l%16, D rows 4v + l/16, col l%16).
+namespace f64g {
+constexpr int BM = 64, BK = 16, LDP = BM + 2;
+}
+
+__global__ __launch_bounds__(256) void zgemm_f64_kernel(GemmArgs g) {
+  using namespace f64g;
+  __shared__ double sA[2][2][BK][LDP];
+  __shared__ double sB[2][2][BK][LDP];
+  int b, tm, tn;
+  tile_coords(g, b, tm, tn);
+  if (b >= g.nb) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lrow = tid >> 2, lk = (tid & 3) * 4;
+  const int Mtot = g.M, Kp = g.Kp;
+  const int arow = min(tm * BM + lrow, Mtot - 1);
+  const int brow = min(tn * BM + lrow, Mtot - 1);
+  const int nk = Kp / BK;
+  d4 acc[2][2][2][2];  // [combo][re/im][mb][nb]
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) acc[c][x][mb][nb] = d4{0.0, 0.0, 0.0, 0.0};
+
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const double2* Ap = (const double2*)g.A[c] + (size_t)b * g.strideA + (size_t)arow * Kp + lk;
+    const double2* Bp = (const double2*)g.B[c] + (size_t)b * g.strideB + (size_t)brow * Kp + lk;
+    double2 ra[4], rb[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      ra[e] = Ap[e];
+      rb[e] = Bp[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      sA[0][0][lk + e][lrow] = ra[e].x;
+      sA[0][1][lk + e][lrow] = ra[e].y;
+      sB[0][0][lk + e][lrow] = rb[e].x;
+      sB[0][1][lk + e][lrow] = rb[e].y;
+    }
+    __syncthreads();
+    for (int kb = 0; kb < nk; ++kb) {
+      const int buf = kb & 1;
+      if (kb + 1 < nk) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          ra[e] = Ap[(size_t)(kb + 1) * BK + e];
+          rb[e] = Bp[(size_t)(kb + 1) * BK + e];
+        }
+      }
+#pragma unroll
+      for (int kk = 0; kk < BK / 4; ++kk) {
+        const int kr = kk * 4 + (lane >> 4);
+        double ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+          ar[mb] = sA[buf][0][kr][wm * 32 + mb * 16 + (lane & 15)];
+          ai[mb] = sA[buf][1][kr][wm * 32 + mb * 16 + (lane & 15)];
+        }
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+          br[nb] = sB[buf][0][kr][wn * 32 + nb * 16 + (lane & 15)];
+          bi[nb] = sB[buf][1][kr][wn * 32 + nb * 16 + (lane & 15)];
+        }
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb) {
+            acc[c][0][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[mb], br[nb], acc[c][0][mb][nb], 0, 0, 0);
+            acc[c][0][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[mb], bi[nb], acc[c][0][mb][nb], 0, 0, 0);
+            acc[c][1][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[mb], bi[nb], acc[c][1][mb][nb], 0, 0, 0);
+            acc[c][1][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[mb], br[nb], acc[c][1][mb][nb], 0, 0, 0);
+          }
+      }
+      if (kb + 1 < nk) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          sA[buf ^ 1][0][lk + e][lrow] = ra[e].x;
+          sA[buf ^ 1][1][lk + e][lrow] = ra[e].y;
+          sB[buf ^ 1][0][lk + e][lrow] = rb[e].x;
+          sB[buf ^ 1][1][lk + e][lrow] = rb[e].y;
+        }
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = tm * BM + wm * 32 + mb * 16 + 4 * v + (lane >> 4);
+        const int col = tn * BM + wn * 32 + nb * 16 + (lane & 15);
+        double2 P0 = make_double2(acc[0][0][mb][nb][v], acc[0][1][mb][nb][v]);
+        double2 P1 = make_double2(acc[1][0][mb][nb][v], acc[1][1][mb][nb][v]);
+        epilogue_store(g, b, row, col, P0, P1);
+      }
+}
+
+// ======================================================================== split-FP32 GEMM
+// FP32 operands (hi parts, optionally lo corrections) on v_mfma_f32_32x32x2f32 with FP32
+// accumulation inside one K block of 32 complex, promoted to FP64 between blocks.
+// One 32x32 complex block per wave (lane l: A row l%32 / k l/32; D rows
+// 8(v/4) + 4(l/32) + v%4, col l%32).
+namespace f32g {
+constexpr int BM = 64, BK = 32, LDP = BM + 4;
+}
+
+template <bool LO>
+__global__ __launch_bounds__(256) void zgemm_f32_kernel(GemmArgs g) {
+  using namespace f32g;
+  __shared__ float sA[2][LO ? 4 : 2][BK][LDP];
+  __shared__ float sB[2][LO ? 4 : 2][BK][LDP];
+  int b, tm, tn;
+  tile_coords(g, b, tm, tn);
+  if (b >= g.nb) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lrow = tid >> 2, lk = (tid & 3) * 8;
+  const int Mtot = g.M, Kp = g.Kp;
+  const int arow = min(tm * BM + lrow, Mtot - 1);
+  const int brow = min(tn * BM + lrow, Mtot - 1);
+  const int nk = Kp / BK;
+  double acc64[2][2][16];  // [combo][re/im][v]
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc64[c][x][v] = 0.0;
+
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const float2* Ap = (const float2*)g.A[c] + (size_t)b * g.strideA + (size_t)arow * Kp + lk;
+    const float2* Bp = (const float2*)g.B[c] + (size_t)b * g.strideB + (size_t)brow * Kp + lk;
+    const float2* Alp = LO ? (const float2*)g.Alo[c] + (size_t)b * g.strideA + (size_t)arow * Kp + lk : nullptr;
+    const float2* Blp = LO ? (const float2*)g.Blo[c] + (size_t)b * g.strideB + (size_t)brow * Kp + lk : nullptr;
+    float2 ra[8], rb[8], ral[LO ? 8 : 1], rbl[LO ? 8 : 1];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      ra[e] = Ap[e];
+      rb[e] = Bp[e];
+      if (LO) {
+        ral[e] = Alp[e];
+        rbl[e] = Blp[e];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      sA[0][0][lk + e][lrow] = ra[e].x;
+      sA[0][1][lk + e][lrow] = ra[e].y;
+      sB[0][0][lk + e][lrow] = rb[e].x;
+      sB[0][1][lk + e][lrow] = rb[e].y;
+      if (LO) {
+        sA[0][2 % (LO ? 4 : 2)][lk + e][lrow] = ral[e].x;
+        sA[0][3 % (LO ? 4 : 2)][lk + e][lrow] = ral[e].y;
+        sB[0][2 % (LO ? 4 : 2)][lk + e][lrow] = rbl[e].x;
+        sB[0][3 % (LO ? 4 : 2)][lk + e][lrow] = rbl[e].y;
+      }
+    }
+    __syncthreads();
+    for (int kb = 0; kb < nk; ++kb) {
+      const int buf = kb & 1;
+      if (kb + 1 < nk) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          ra[e] = Ap[(size_t)(kb + 1) * BK + e];
+          rb[e] = Bp[(size_t)(kb + 1) * BK + e];
+          if (LO) {
+            ral[e] = Alp[(size_t)(kb + 1) * BK + e];
+            rbl[e] = Blp[(size_t)(kb + 1) * BK + e];
+          }
+        }
+      }
+      f16v cr, ci;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) cr[v] = ci[v] = 0.f;
+#pragma unroll
+      for (int kk = 0; kk < BK / 2; ++kk) {
+        const int kr = kk * 2 + (lane >> 5);
+        const int am = wm * 32 + (lane & 31), bn = wn * 32 + (lane & 31);
+        const float ar = sA[buf][0][kr][am], ai = sA[buf][1][kr][am];
+        const float br = sB[buf][0][kr][bn], bi = sB[buf][1][kr][bn];
+        cr = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, cr, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bi, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, ci, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, ci, 0, 0, 0);
+        if (LO) {
+          const float alr = sA[buf][2 % (LO ? 4 : 2)][kr][am], ali = sA[buf][3 % (LO ? 4 : 2)][kr][am];
+          const float blr = sB[buf][2 % (LO ? 4 : 2)][kr][bn], bli = sB[buf][3 % (LO ? 4 : 2)][kr][bn];
+          // hi x lo + lo x hi corrections
+          cr = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, blr, cr, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bli, cr, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_32x32x2f32(alr, br, cr, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_32x32x2f32(-ali, bi, cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bli, ci, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, blr, ci, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_32x32x2f32(alr, bi, ci, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_32x32x2f32(ali, br, ci, 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        acc64[c][0][v] += (double)cr[v];
+        acc64[c][1][v] += (double)ci[v];
+      }
+      if (kb + 1 < nk) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          sA[buf ^ 1][0][lk + e][lrow] = ra[e].x;
+          sA[buf ^ 1][1][lk + e][lrow] = ra[e].y;
+          sB[buf ^ 1][0][lk + e][lrow] = rb[e].x;
+          sB[buf ^ 1][1][lk + e][lrow] = rb[e].y;
+          if (LO) {
+            sA[buf ^ 1][2 % (LO ? 4 : 2)][lk + e][lrow] = ral[e].x;
+            sA[buf ^ 1][3 % (LO ? 4 : 2)][lk + e][lrow] = ral[e].y;
+            sB[buf ^ 1][2 % (LO ? 4 : 2)][lk + e][lrow] = rbl[e].x;
+            sB[buf ^ 1][3 % (LO ? 4 : 2)][lk + e][lrow] = rbl[e].y;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int row = tm * BM + wm * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    const int col = tn * BM + wn * 32 + (lane & 31);
+    epilogue_store(g, b, row, col, make_double2(acc64[0][0][v], acc64[0][1][v]),
+                   make_double2(acc64[1][0][v], acc64[1][1][v]));
+  }
+}
+
+// ======================================================================== SDE loop
+// Sigma^{a1'|a1}(v_i) = -1/2 sum_j w_j/(2 pi i) sum_{a2,a2'} [2 Phi^X + Phi^Y]
+//   (w = v_i - v_j, v' = (v_i + v_j)/2) G^{a2|a2'}(v_j);  Phi = K1(w) + K2'(w, v').
+// One workgroup per output frequency; shuffle + LDS reduction in FP64.
+__global__ __launch_bounds__(256) void loop_kernel(LoopArgs a) {
+  const int i = blockIdx.x;
+  const int n = a.g.n;
+  const double v = a.nodes[i];
+  double2 acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = czero();
+  for (int jq = threadIdx.x; jq < a.nq; jq += blockDim.x) {
+    const double vq = a.qv[jq];
+    int iw;
+    double tw;
+    if (!dgrid_locate(a.g, v - vq, iw, tw)) continue;
+    int ip = 0;
+    double tp = 0.0;
+    const bool inp = dgrid_locate(a.g, 0.5 * (v + vq), ip, tp);
+    double2 Mx[16];
+#pragma unroll
+    for (int f = 0; f < 16; ++f) Mx[f] = czero();
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const double sw = s ? 1.0 : 2.0;  // spin sum 2X + Y
+#pragma unroll
+      for (int cw = 0; cw < 2; ++cw) {
+        const double ww = sw * (cw ? tw : 1.0 - tw);
+        if (a.K1) {
+          const double2* p = a.K1 + ((size_t)s * n + iw + cw) * 16;
+#pragma unroll
+          for (int f = 0; f < 16; ++f) Mx[f] = cfma(ww, p[f], Mx[f]);
+        }
+        if (inp && a.K2p) {
+#pragma unroll
+          for (int c2 = 0; c2 < 2; ++c2) {
+            const double wv = ww * (c2 ? tp : 1.0 - tp);
+            const double2* p = a.K2p + (((size_t)s * n + iw + cw) * n + ip + c2) * 16;
+#pragma unroll
+            for (int f = 0; f < 16; ++f) Mx[f] = cfma(wv, p[f], Mx[f]);
+          }
+        }
+      }
+    }
+    double2 G[4];
+    propagator(a.P, a.kind, vq, G);
+    const double2 wgt = make_double2(0.0, 0.5 * a.qw[jq] * (0.5 / M_PI));  // -1/2 * w/(2 pi i)
+#pragma unroll
+    for (int a1p = 0; a1p < 2; ++a1p)
+#pragma unroll
+      for (int a1 = 0; a1 < 2; ++a1) {
+        double2 s = czero();
+#pragma unroll
+        for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+          for (int a2p = 0; a2p < 2; ++a2p) {
+            const int f = 4 * (2 * a1p + a2) + (2 * a1 + a2p);
+            s = cadd(s, cmul(Mx[f], G[2 * a2 + a2p]));
+          }
+        acc[2 * a1p + a1] = cadd(acc[2 * a1p + a1], cmul(wgt, s));
+      }
+  }
+  // reduction over the workgroup
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      acc[c].x += __shfl_xor(acc[c].x, o);
+      acc[c].y += __shfl_xor(acc[c].y, o);
+    }
+  __shared__ double2 red[4][4];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) red[wave][c] = acc[c];
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int c = threadIdx.x;
+    double2 s = czero();
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s = cadd(s, red[w][c]);
+    a.out[(size_t)i * 4 + c] = s;
+  }
+}
+
+// ======================================================================== chi
+// Partial sums z(k, row)[m] = sum_l sum_q Gamma_c(w; v''_k, v''_l)[row, q] Pi_l[q, m] for
+// c in {X, D = X + 2Y}, then chi(w)[p, m] = sum_k Pi_k[p, row] z(k, row)[m].  One thread per
+// (k, row); per-block partials, reduced in fixed order by chi_finalize_kernel.
+__device__ inline void full_vertex_row(const DVert& V, int r, int iw, double w, double v, double vp, int row,
+                                       double2 X[4], double2 Y[4]) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    X[e] = Y[e] = czero();
+    if (bare_odd(4 * row + e)) {
+      X[e].x -= 0.5 * V.r0;
+      Y[e].x += 0.5 * V.r0;
+    }
+  }
+  int f[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) f[e] = 4 * row + e;
+  if (V.ch[r].coef != 0.0) add_channel(V.ch[r], V.g, w, v, vp, f, X, Y);
+  add_others(V, r, w, v, vp, 0, row, X, Y);
+}
+
+__global__ __launch_bounds__(256) void chi_kernel(ChiArgs a) {
+  const int iw = a.iw0 + blockIdx.y;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = tid & 3, k = tid >> 2;
+  double2 part[2][16];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int f = 0; f < 16; ++f) part[c][f] = czero();
+  if (k < a.nq) {
+    const double w = a.nodes[iw];
+    const double vk = a.qv[k];
+    const double2* pis = a.pi + (size_t)blockIdx.y * a.nq * 16;
+    double2 z[2][4];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) z[c][m] = czero();
+    for (int l = 0; l < a.nq; ++l) {
+      double2 X[4], Y[4];
+      full_vertex_row(a.V, 0, iw, w, vk, a.qv[l], row, X, Y);
+      const double2* pl = pis + (size_t)l * 16;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double2 gx = X[q];
+        const double2 gd = make_double2(X[q].x + 2.0 * Y[q].x, X[q].y + 2.0 * Y[q].y);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const double2 pv = pl[4 * q + m];
+          z[0][m] = cadd(z[0][m], cmul(gx, pv));
+          z[1][m] = cadd(z[1][m], cmul(gd, pv));
+        }
+      }
+    }
+    const double2* pk = pis + (size_t)k * 16;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const double2 pp = pk[4 * p + row];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        part[0][4 * p + m] = cmul(pp, z[0][m]);
+        part[1][4 * p + m] = cmul(pp, z[1][m]);
+      }
+    }
+    if (row == 0) {  // the bare bubble term sum_k Pi_k, once per k
+#pragma unroll
+      for (int f = 0; f < 16; ++f) {
+        part[0][f] = cadd(part[0][f], pk[f]);
+        part[1][f] = cadd(part[1][f], pk[f]);
+      }
+    }
+  }
+  __shared__ double2 red[4][32];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int f = 0; f < 16; ++f) {
+      double2 s = part[c][f];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        s.x += __shfl_xor(s.x, o);
+        s.y += __shfl_xor(s.y, o);
+      }
+      if (lane == 0) red[wave][c * 16 + f] = s;
+    }
+  __syncthreads();
+  if (threadIdx.x < 32) {
+    double2 s = czero();
+    for (int w = 0; w < 4; ++w) s = cadd(s, red[w][threadIdx.x]);
+    a.partial[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 32 + threadIdx.x] = s;
+  }
+}
+
+__global__ void chi_finalize_kernel(ChiArgs a, int nblk) {
+  const int b = blockIdx.x;  // transfer frequency within the batch
+  const int e = threadIdx.x; // 0..31 = c*16 + f
+  if (e >= 32) return;
+  double2 s = czero();
+  for (int k = 0; k < nblk; ++k) s = cadd(s, a.partial[((size_t)b * nblk + k) * 32 + e]);
+  const int c = e >> 4, f = e & 15;
+  a.out[((size_t)c * a.V.g.n + a.iw0 + b) * 16 + f] = s;
+}
+
+// ======================================================================== launchers
+static inline unsigned blocks_for(long threads, int bs) { return (unsigned)((threads + bs - 1) / bs); }
+
+hipError_t upload_perm(const int* host_perm) {
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_perm), host_perm, sizeof(int) * 3 * 3 * 16);
+}
+
+void launch_pi(const PiArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(pi_kernel, dim3(blocks_for((long)a.nb * a.nq, 256)), dim3(256), 0, s, a);
+}
+void launch_gather(const GatherArgs& a, bool left, bool f32, hipStream_t s) {
+  const long threads = (long)a.nb * a.cnt * a.nq_pad * 4;
+  dim3 grid(blocks_for(threads, 256));
+  if (left) {
+    if (f32)
+      hipLaunchKernelGGL(gather_left_kernel<float2>, grid, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL(gather_left_kernel<double2>, grid, dim3(256), 0, s, a);
+  } else {
+    if (f32)
+      hipLaunchKernelGGL(gather_right_kernel<float2>, grid, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL(gather_right_kernel<double2>, grid, dim3(256), 0, s, a);
+  }
+}
+void launch_gemm(const GemmArgs& g, int precision, bool lo, hipStream_t s) {
+  dim3 grid((unsigned)(g.nb * g.tms * g.tns));
+  if (precision == 0)
+    hipLaunchKernelGGL(zgemm_f64_kernel, grid, dim3(256), 0, s, g);
+  else if (lo)
+    hipLaunchKernelGGL(zgemm_f32_kernel<true>, grid, dim3(256), 0, s, g);
+  else
+    hipLaunchKernelGGL(zgemm_f32_kernel<false>, grid, dim3(256), 0, s, g);
+}
+void launch_loop(const LoopArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(loop_kernel, dim3(a.g.n), dim3(256), 0, s, a);
+}
+void launch_chi(const ChiArgs& a, hipStream_t s) {
+  const int nblk = (int)blocks_for((long)a.nq * 4, 256);
+  hipLaunchKernelGGL(chi_kernel, dim3(nblk, a.nb), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(chi_finalize_kernel, dim3(a.nb), dim3(64), 0, s, a, nblk);
+}
+int chi_blocks(int nq) { return (int)blocks_for((long)nq * 4, 256); }
+
+}  // namespace kqft

@@ -1,0 +1,77 @@
+// kqft_launch.h -- kernel argument blocks and launchers (host <-> kernel contract).
+#pragma once
+#include "kqft_internal.h"
+
+namespace kqft {
+
+struct PiArgs {
+  int r, kind, nb, nq, iw0;
+  DProp P;
+  const double* wnodes;  // transfer-frequency grid nodes
+  const double* qv;
+  const double* qw;
+  double2* out;  // [nb][nq][16], Pi * w_k / (2 pi i)
+};
+
+struct GatherArgs {
+  int r, nb, iw0, nq, nq_pad, lo, cnt;  // rows/cols lo .. lo+cnt-1 (index n = border)
+  long Kp;                              // panel leading dimension (complex)
+  DVert V;
+  const double* nodes;  // vertex grid nodes
+  const double* qv;
+  const double2* pi;  // left gather only
+  void* P0;           // panel of spin combination 0 ([nb][4(n+1)][Kp])
+  void* P1;           // combination 1
+  void* L0;           // optional FP32 low parts
+  void* L1;
+  double mix[4];  // spin combination: c0 = mix0 X + mix1 Y, c1 = mix2 X + mix3 Y
+};
+
+struct GemmArgs {
+  const void* A[2];
+  const void* B[2];
+  const void* Alo[2];
+  const void* Blo[2];
+  long strideA, strideB;  // complex elements per transfer frequency
+  int M, Kp;              // M = 4(n+1) rows and columns; Kp padded contraction length
+  int tm0, tms, tn0, tns; // tile ranges
+  int nb;
+  int r, n, iw0, beta, cmask;
+  double unmix[4];  // X = u0 P0 + u1 P1, Y = u2 P0 + u3 P1 (channel prefactor included)
+  double2* K1;
+  double2* K2;
+  double2* K2p;
+  double2* K3;
+};
+
+struct LoopArgs {
+  DGrid g;
+  DProp P;
+  int kind, nq;
+  const double* nodes;
+  const double* qv;
+  const double* qw;
+  const double2* K1;
+  const double2* K2p;
+  double2* out;  // [n][4]
+};
+
+struct ChiArgs {
+  DVert V;
+  int nq, nb, iw0;
+  const double* nodes;
+  const double* qv;
+  const double2* pi;  // [nb][nq][16], channel a, Pi = G G, weights folded
+  double2* partial;   // [nb][nblk][32]
+  double2* out;       // [2][n][16]
+};
+
+hipError_t upload_perm(const int* host_perm);
+void launch_pi(const PiArgs& a, hipStream_t s);
+void launch_gather(const GatherArgs& a, bool left, bool f32, hipStream_t s);
+void launch_gemm(const GemmArgs& g, int precision, bool lo, hipStream_t s);
+void launch_loop(const LoopArgs& a, hipStream_t s);
+void launch_chi(const ChiArgs& a, hipStream_t s);
+int chi_blocks(int nq);
+
+}  // namespace kqft

@@ -1,0 +1,265 @@
+"""Thin ctypes binding of libkqft.so (include/kqft.h): argument marshalling only.
+
+Every step of the computation runs in the HIP library; torch supplies device memory
+and streams.  There is no fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkqft.so")
+
+CH_A, CH_P, CH_T = 0, 1, 2
+FP64, SPLIT_FP32 = 0, 1
+PI_GG, PI_DOT = 0, 1
+K1, K2, K2P, K3, KALL = 1, 2, 4, 8, 15
+QUAD_TAN_FINITE, QUAD_TAN_INFINITE = 0, 1
+CLASSES = ("K1", "K2", "K2p", "K3")
+
+
+class KqftGrid(C.Structure):
+    _fields_ = [("n", C.c_int), ("L", C.c_double), ("a", C.c_double)]
+
+
+class KqftQuad(C.Structure):
+    _fields_ = [("n", C.c_int), ("map", C.c_int), ("L", C.c_double), ("a", C.c_double)]
+
+
+class KqftChvert(C.Structure):
+    _fields_ = [("coef", C.c_double), ("K1", C.c_void_p), ("K2", C.c_void_p), ("K2p", C.c_void_p),
+                ("K3", C.c_void_p)]
+
+
+class KqftVertex(C.Structure):
+    _fields_ = [("r0", C.c_double), ("grid", KqftGrid), ("ch", KqftChvert * 3)]
+
+
+class KqftPropagator(C.Structure):
+    _fields_ = [("Delta", C.c_double), ("T", C.c_double), ("eps", C.c_double), ("sgrid", KqftGrid),
+                ("SigR", C.c_void_p), ("SigK", C.c_void_p)]
+
+
+class KqftChout(C.Structure):
+    _fields_ = [("K1", C.c_void_p), ("K2", C.c_void_p), ("K2p", C.c_void_p), ("K3", C.c_void_p)]
+
+
+class KqftOpts(C.Structure):
+    _fields_ = [("precision", C.c_int), ("class_mask", C.c_int), ("beta", C.c_int), ("omega_batch", C.c_int)]
+
+
+_lib = None
+_ctx = {}
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        _lib = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        _lib.kqft_ctx_create.argtypes = [P(C.c_void_p), C.c_int]
+        _lib.kqft_ctx_destroy.argtypes = [C.c_void_p]
+        _lib.kqft_last_error.restype = C.c_char_p
+        _lib.kqft_bubble_workspace.restype = C.c_size_t
+        _lib.kqft_bubble_workspace.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
+        _lib.kqft_bubble.argtypes = [C.c_void_p, C.c_int, P(KqftVertex), P(KqftVertex), P(KqftPropagator), C.c_int,
+                                     P(KqftQuad), P(KqftOpts), P(KqftChout), C.c_void_p]
+        _lib.kqft_sde.argtypes = [C.c_void_p, P(KqftVertex), P(KqftPropagator), P(KqftQuad), P(KqftQuad),
+                                  P(KqftOpts), C.c_void_p, C.c_void_p, C.c_void_p]
+        _lib.kqft_mloop_step.argtypes = [C.c_void_p, C.c_int, P(KqftVertex), P(KqftPropagator), P(KqftQuad), C.c_int,
+                                         P(KqftOpts), P(KqftChout), C.c_void_p]
+        _lib.kqft_bubble_adjoint.argtypes = [C.c_void_p, C.c_int, P(KqftVertex), P(KqftVertex), P(KqftPropagator),
+                                             C.c_int, P(KqftQuad), P(KqftOpts), P(KqftChout), P(KqftChout),
+                                             P(KqftChout), C.c_void_p, C.c_void_p]
+    return _lib
+
+
+def exported_symbols() -> list:
+    names = ["kqft_ctx_create", "kqft_ctx_destroy", "kqft_last_error", "kqft_bubble_workspace", "kqft_bubble",
+             "kqft_sde", "kqft_mloop_step", "kqft_bubble_adjoint"]
+    L = lib()
+    return [n for n in names if hasattr(L, n)]
+
+
+class KqftError(RuntimeError):
+    pass
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise KqftError(f"kqft error {rc}: {lib().kqft_last_error().decode()}")
+
+
+def ctx(device: Optional[int] = None):
+    dev = torch.cuda.current_device() if device is None else device
+    if dev not in _ctx:
+        h = C.c_void_p()
+        _check(lib().kqft_ctx_create(C.byref(h), dev))
+        _ctx[dev] = h
+    return _ctx[dev]
+
+
+def _stream(stream) -> C.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+# ------------------------------------------------------------------ data model
+@dataclass
+class Grid:
+    n: int
+    L: float = 20.0
+    a: float = 1.0
+
+    def c(self) -> KqftGrid:
+        return KqftGrid(self.n, self.L, self.a)
+
+
+@dataclass
+class Quad:
+    n: int
+    map: int = QUAD_TAN_FINITE
+    L: float = 20.0
+    a: float = 1.0
+
+    def c(self) -> KqftQuad:
+        return KqftQuad(self.n, self.map, self.L, self.a)
+
+
+def class_shape(name: str, n: int) -> tuple:
+    return {"K1": (2, n, 16), "K2": (2, n, n, 16), "K2p": (2, n, n, 16), "K3": (2, n, n, n, 16)}[name]
+
+
+def _ptr(t: Optional[torch.Tensor], shape=None, what="") -> Optional[int]:
+    if t is None:
+        return None
+    if t.dtype != torch.complex128 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{what}: needs a contiguous complex128 device tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what}: shape {tuple(t.shape)} != {tuple(shape)}")
+    return t.data_ptr()
+
+
+@dataclass
+class Channel:
+    coef: float = 1.0
+    K1: Optional[torch.Tensor] = None
+    K2: Optional[torch.Tensor] = None
+    K2p: Optional[torch.Tensor] = None
+    K3: Optional[torch.Tensor] = None
+
+
+@dataclass
+class Vertex:
+    """Gamma = Gamma_0(r0) + sum_r coef_r gamma_r (class tensors complex128 on the device)."""
+    grid: Grid
+    r0: float = 0.0
+    ch: list = field(default_factory=lambda: [Channel(0.0), Channel(0.0), Channel(0.0)])
+
+    def c(self) -> KqftVertex:
+        v = KqftVertex()
+        v.r0 = self.r0
+        v.grid = self.grid.c()
+        for r in range(3):
+            chn = self.ch[r]
+            v.ch[r].coef = chn.coef
+            for name in CLASSES:
+                setattr(v.ch[r], name, _ptr(getattr(chn, name), class_shape(name, self.grid.n), f"ch{r}.{name}"))
+        return v
+
+
+@dataclass
+class Propagator:
+    Delta: float = 1.0
+    T: float = 0.1
+    eps: float = 0.0
+    sigma_grid: Optional[Grid] = None
+    SigR: Optional[torch.Tensor] = None
+    SigK: Optional[torch.Tensor] = None
+
+    def c(self) -> KqftPropagator:
+        g = (self.sigma_grid or Grid(2, 1.0, 1.0)).c()
+        n = self.sigma_grid.n if self.sigma_grid else None
+        return KqftPropagator(self.Delta, self.T, self.eps, g, _ptr(self.SigR, (n,) if n else None, "SigR"),
+                              _ptr(self.SigK, (n,) if n else None, "SigK"))
+
+
+def _opts(precision, class_mask, beta, omega_batch) -> KqftOpts:
+    return KqftOpts(precision, class_mask, beta, omega_batch)
+
+
+def alloc_channel(n: int, device=None, zero: bool = True) -> Channel:
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    f = torch.zeros if zero else torch.empty
+    return Channel(1.0, *[f(class_shape(c, n), dtype=torch.complex128, device=dev) for c in CLASSES])
+
+
+def _chout(chn: Channel, n: int) -> KqftChout:
+    return KqftChout(*[_ptr(getattr(chn, c), class_shape(c, n), f"out.{c}") for c in CLASSES])
+
+
+# ------------------------------------------------------------------ entry points
+def bubble(channel: int, left: Vertex, right: Vertex, G: Propagator, q: Quad, pi_kind: int = PI_GG,
+           precision: int = FP64, class_mask: int = KALL, beta: int = 0, omega_batch: int = 0,
+           out: Optional[Channel] = None, stream=None) -> Channel:
+    n = left.grid.n
+    if out is None:
+        out = alloc_channel(n)
+    lc, rc, gc, qc = left.c(), right.c(), G.c(), q.c()
+    oc = _chout(out, n)
+    _check(lib().kqft_bubble(ctx(), channel, C.byref(lc), C.byref(rc), C.byref(gc), pi_kind, C.byref(qc),
+                             C.byref(_opts(precision, class_mask, beta, omega_batch)), C.byref(oc), _stream(stream)))
+    return out
+
+
+def sde(gamma: Vertex, G: Propagator, q_bubble: Quad, q_loop: Quad, precision: int = FP64, with_chi: bool = True,
+        omega_batch: int = 0, stream=None):
+    n = gamma.grid.n
+    dev = torch.device("cuda", torch.cuda.current_device())
+    sigma = torch.zeros((n, 4), dtype=torch.complex128, device=dev)
+    chi = torch.zeros((2, n, 16), dtype=torch.complex128, device=dev) if with_chi else None
+    vc, gc, qb, ql = gamma.c(), G.c(), q_bubble.c(), q_loop.c()
+    _check(lib().kqft_sde(ctx(), C.byref(vc), C.byref(gc), C.byref(qb), C.byref(ql),
+                          C.byref(_opts(precision, KALL, 0, omega_batch)), C.c_void_p(sigma.data_ptr()),
+                          C.c_void_p(chi.data_ptr() if chi is not None else None), _stream(stream)))
+    return sigma, chi
+
+
+def mloop_step(gammas: Sequence[Vertex], Gs: Sequence[Propagator], qs: Sequence[Quad], nloops: int,
+               precision: int = FP64, omega_batch: int = 0, stream=None) -> list:
+    """Returns out[p][l][r] (Channel): order-(l+1) insertions of point p in channel r."""
+    npts = len(gammas)
+    outs = [[[alloc_channel(g.grid.n) for _ in range(3)] for _ in range(nloops)] for g in gammas]
+    V = (KqftVertex * npts)(*[g.c() for g in gammas])
+    P = (KqftPropagator * npts)(*[g.c() for g in Gs])
+    Q = (KqftQuad * npts)(*[q.c() for q in qs])
+    D = (KqftChout * (npts * nloops * 3))(*[_chout(outs[p][l][r], gammas[p].grid.n)
+                                             for p in range(npts) for l in range(nloops) for r in range(3)])
+    _check(lib().kqft_mloop_step(ctx(), npts, V, P, Q, nloops, C.byref(_opts(precision, KALL, 0, omega_batch)), D,
+                                 _stream(stream)))
+    return outs
+
+
+def bubble_adjoint(channel: int, left: Vertex, right: Vertex, G: Propagator, q: Quad, dout: Channel,
+                   pi_kind: int = PI_GG, dleft: Optional[list] = None, dright: Optional[list] = None,
+                   omega_batch: int = 0, stream=None):
+    """Accumulates cotangents into dleft[r] / dright[r] (Channels, or None to skip) and returns
+    the device tensor dscal = (d left.r0, d right.r0, d G.Delta)."""
+    n = left.grid.n
+    dev = torch.device("cuda", torch.cuda.current_device())
+    dscal = torch.zeros(3, dtype=torch.float64, device=dev)
+    empty = KqftChout(None, None, None, None)
+    DL = (KqftChout * 3)(*[(_chout(d, n) if d is not None else empty) for d in (dleft or [None] * 3)])
+    DR = (KqftChout * 3)(*[(_chout(d, n) if d is not None else empty) for d in (dright or [None] * 3)])
+    lc, rc, gc, qc, oc = left.c(), right.c(), G.c(), q.c(), _chout(dout, n)
+    _check(lib().kqft_bubble_adjoint(ctx(), channel, C.byref(lc), C.byref(rc), C.byref(gc), pi_kind, C.byref(qc),
+                                     C.byref(_opts(FP64, KALL, 1, omega_batch)), C.byref(oc), DL, DR,
+                                     C.c_void_p(dscal.data_ptr()), _stream(stream)))
+    return dscal
