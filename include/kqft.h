@@ -134,6 +134,13 @@ int kqft_ctx_create(kqft_ctx** ctx, int device);
 int kqft_ctx_destroy(kqft_ctx* ctx);
 /* Message of the last error on the calling thread ("" if none). */
 const char* kqft_last_error(void);
+/* Kernel timing for measurement: while enabled, every kernel launch of the library is
+   bracketed by HIP events on the caller's stream.  kqft_ctx_profile_read synchronises
+   those events and returns, per kernel kind (0 = propagator pair, 1 = gather, 2 = GEMM,
+   3 = loop / susceptibility reductions), the summed milliseconds and the launch counts,
+   then clears them.  ms and launches: host arrays of 4. */
+int kqft_ctx_profile(kqft_ctx* ctx, int enable);
+int kqft_ctx_profile_read(kqft_ctx* ctx, double* ms, int* launches);
 /* Workspace bytes a call of kqft_bubble with these sizes will hold. */
 size_t kqft_bubble_workspace(int n, int nq, int omega_batch, int precision);
 

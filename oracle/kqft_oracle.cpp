@@ -570,14 +570,25 @@ static void bubble_full(int r, const OVert& Lv, const OVert& Rv, const OProp& P,
       bubble_pi<S>(P, r, kind, w, qv[k], &Pi[(size_t)k * 16]);
       for (int f = 0; f < 16; ++f) Pi[(size_t)k * 16 + f] = cmul(0.0, -qw[k] / (2.0 * M_PI), Pi[(size_t)k * 16 + f]);
     }
-    // left factors for rows i = 0..n-1 and the infinite row i = n; right factors likewise
-    std::vector<Cx<S>> LX((size_t)(n + 1) * nq * 16), LY(LX.size()), RX(LX.size()), RY(LX.size());
+    // left factors for rows i = 0..n-1 and the infinite row i = n; right factors likewise.
+    // Only the rows the selected classes use are built: finite-v rows for K3/K2 (left)
+    // and K3/K2' (right); row slot of i is i, or 0 when only the infinite row is kept.
+    bool need_l = cmask & (C_K3 | C_K2), need_r = cmask & (C_K3 | C_K2P);
+    size_t nl = need_l ? n + 1 : 1, nr = need_r ? n + 1 : 1;
+    std::vector<Cx<S>> LX(nl * nq * 16), LY(LX.size()), RX(nr * nq * 16), RY(RX.size());
+    auto lslot = [&](int i) { return need_l ? (size_t)i : 0; };
+    auto rslot = [&](int j) { return need_r ? (size_t)j : 0; };
     for (int i = 0; i <= n; ++i) {
       double v = i < n ? grid_node(VL.g, i) : 0.0;
       for (int k = 0; k < nq; ++k) {
-        size_t o = ((size_t)i * nq + k) * 16;
-        left_factor(VL, r, w, v, qv[k], i == n, &LX[o], &LY[o]);
-        right_factor(VR, r, w, qv[k], v, i == n, &RX[o], &RY[o]);
+        if (i == n || need_l) {
+          size_t o = (lslot(i) * nq + k) * 16;
+          left_factor(VL, r, w, v, qv[k], i == n, &LX[o], &LY[o]);
+        }
+        if (i == n || need_r) {
+          size_t o = (rslot(i) * nq + k) * 16;
+          right_factor(VR, r, w, qv[k], v, i == n, &RX[o], &RY[o]);
+        }
       }
     }
     for (int i = 0; i <= n; ++i)
@@ -588,7 +599,7 @@ static void bubble_full(int r, const OVert& Lv, const OVert& Rv, const OProp& P,
         for (int f = 0; f < 16; ++f) aX[f] = aY[f] = czero<S>();
         for (int k = 0; k < nq; ++k) {
           Cx<S> tX[16], tY[16];
-          size_t ol = ((size_t)i * nq + k) * 16, orr = ((size_t)j * nq + k) * 16;
+          size_t ol = (lslot(i) * nq + k) * 16, orr = (rslot(j) * nq + k) * 16;
           spin_sums<S>(r, &LX[ol], &LY[ol], &Pi[(size_t)k * 16], &RX[orr], &RY[orr], tX, tY);
           for (int f = 0; f < 16; ++f) {
             aX[f] = aX[f] + tX[f];

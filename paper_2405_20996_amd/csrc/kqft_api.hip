@@ -36,6 +36,25 @@ struct kqft_ctx {
   std::map<std::tuple<int, double, double>, double*> grids;
   std::map<std::tuple<int, int, double, double>, std::pair<double*, double*>> quads;
   DevBuf panels, pi, phi, chi_part, lstore[2][3], adj;
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[4];
+};
+
+// Optional event bracketing of one launch (kind: 0 Pi, 1 gather, 2 GEMM, 3 reductions).
+struct ProfScope {
+  kqft_ctx* c;
+  int kind;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(kqft_ctx* c_, int kind_, hipStream_t s_) : c(c_), kind(kind_), s(s_) {
+    if (c->prof && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) (void)hipEventRecord(a, s);
+  }
+  ~ProfScope() {
+    if (a && b) {
+      (void)hipEventRecord(b, s);
+      c->ev[kind].emplace_back(a, b);
+    }
+  }
 };
 
 // ------------------------------------------------------------------ host tables
@@ -252,13 +271,22 @@ static int bubble_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_ve
   for (int iw0 = 0; iw0 < n; iw0 += nb) {
     const int cnt = std::min(nb, n - iw0);
     PiArgs pa{r, kind, cnt, nq, iw0, P, nodes, qv, qw, (double2*)ctx->pi.p};
-    launch_pi(pa, s);
+    {
+      ProfScope ps(ctx, 0, s);
+      launch_pi(pa, s);
+    }
     GatherArgs ga{r, cnt, iw0, nq, nq_pad, ilo, ihi - ilo + 1, Kp, VL, nodes, qv, (const double2*)ctx->pi.p,
                   A0, A1, nullptr, nullptr, {kMix[r][0], kMix[r][1], kMix[r][2], kMix[r][3]}};
-    launch_gather(ga, true, f32, s);
+    {
+      ProfScope ps(ctx, 1, s);
+      launch_gather(ga, true, f32, s);
+    }
     GatherArgs gb{r, cnt, iw0, nq, nq_pad, jlo, jhi - jlo + 1, Kp, VR, nodes, qv, nullptr, B0, B1, nullptr, nullptr,
                   {kMix[r][0], kMix[r][1], kMix[r][2], kMix[r][3]}};
-    launch_gather(gb, false, f32, s);
+    {
+      ProfScope ps(ctx, 1, s);
+      launch_gather(gb, false, f32, s);
+    }
     GemmArgs g;
     memset(&g, 0, sizeof g);
     g.A[0] = A0;
@@ -283,7 +311,10 @@ static int bubble_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_ve
     g.K2 = out.K2;
     g.K2p = out.K2p;
     g.K3 = out.K3;
-    launch_gemm(g, o.precision, false, s);
+    {
+      ProfScope ps(ctx, 2, s);
+      launch_gemm(g, o.precision, false, s);
+    }
   }
   HIP_TRY(hipGetLastError());
   return KQFT_OK;
@@ -341,6 +372,34 @@ int kqft_ctx_destroy(kqft_ctx* ctx) {
       if (b.p) (void)hipFree(b.p);
   delete ctx;
   return KQFT_OK;
+}
+
+int kqft_ctx_profile(kqft_ctx* ctx, int enable) {
+  if (!ctx) return fail(KQFT_EINVAL, "ctx is NULL");
+  double ms[4];
+  int cnt[4];
+  kqft_ctx_profile_read(ctx, ms, cnt);
+  ctx->prof = enable != 0;
+  return KQFT_OK;
+}
+
+int kqft_ctx_profile_read(kqft_ctx* ctx, double* ms, int* launches) {
+  if (!ctx || !ms || !launches) return fail(KQFT_EINVAL, "NULL argument");
+  int rc = KQFT_OK;
+  for (int k = 0; k < 4; ++k) {
+    ms[k] = 0.0;
+    launches[k] = (int)ctx->ev[k].size();
+    for (auto& e : ctx->ev[k]) {
+      float t = 0.f;
+      if (hipEventSynchronize(e.second) != hipSuccess || hipEventElapsedTime(&t, e.first, e.second) != hipSuccess)
+        rc = fail(KQFT_EDEVICE, "event timing failed");
+      ms[k] += t;
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    ctx->ev[k].clear();
+  }
+  return rc;
 }
 
 size_t kqft_bubble_workspace(int n, int nq, int omega_batch, int precision) {
@@ -402,7 +461,10 @@ int kqft_sde(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, 
   if ((rc = to_dprop(*G, P))) return rc;
   LoopArgs la{make_dgrid(n, gamma->grid.L, gamma->grid.a), P, 0, q_loop->n, nodes, qv, qw, phiK1, phiK2p,
               (double2*)sigma};
-  launch_loop(la, s);
+  {
+    ProfScope ps(ctx, 3, s);
+    launch_loop(la, s);
+  }
   if (chi) {
     const double *cqv, *cqw;
     if ((rc = get_quad(ctx, *q_bubble, &cqv, &cqw))) return rc;
@@ -414,10 +476,16 @@ int kqft_sde(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, 
     for (int iw0 = 0; iw0 < n; iw0 += nb) {
       const int cnt = std::min(nb, n - iw0);
       PiArgs pa{KQFT_CH_A, KQFT_PI_GG, cnt, nq, iw0, P, nodes, cqv, cqw, (double2*)ctx->pi.p};
-      launch_pi(pa, s);
+      {
+        ProfScope ps(ctx, 0, s);
+        launch_pi(pa, s);
+      }
       ChiArgs ca{to_dvert(*gamma), nq, cnt, iw0, nodes, cqv, (const double2*)ctx->pi.p,
                  (double2*)ctx->chi_part.p, (double2*)chi};
-      launch_chi(ca, s);
+      {
+        ProfScope ps(ctx, 3, s);
+        launch_chi(ca, s);
+      }
     }
   }
   HIP_TRY(hipGetLastError());

@@ -67,6 +67,8 @@ def lib():
         _lib.kqft_ctx_create.argtypes = [P(C.c_void_p), C.c_int]
         _lib.kqft_ctx_destroy.argtypes = [C.c_void_p]
         _lib.kqft_last_error.restype = C.c_char_p
+        _lib.kqft_ctx_profile.argtypes = [C.c_void_p, C.c_int]
+        _lib.kqft_ctx_profile_read.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         _lib.kqft_bubble_workspace.restype = C.c_size_t
         _lib.kqft_bubble_workspace.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
         _lib.kqft_bubble.argtypes = [C.c_void_p, C.c_int, P(KqftVertex), P(KqftVertex), P(KqftPropagator), C.c_int,
@@ -82,7 +84,8 @@ def lib():
 
 
 def exported_symbols() -> list:
-    names = ["kqft_ctx_create", "kqft_ctx_destroy", "kqft_last_error", "kqft_bubble_workspace", "kqft_bubble",
+    names = ["kqft_ctx_create", "kqft_ctx_destroy", "kqft_last_error", "kqft_ctx_profile", "kqft_ctx_profile_read",
+             "kqft_bubble_workspace", "kqft_bubble",
              "kqft_sde", "kqft_mloop_step", "kqft_bubble_adjoint"]
     L = lib()
     return [n for n in names if hasattr(L, n)]
@@ -109,6 +112,18 @@ def ctx(device: Optional[int] = None):
 def _stream(stream) -> C.c_void_p:
     s = torch.cuda.current_stream() if stream is None else stream
     return C.c_void_p(s.cuda_stream)
+
+
+def profile(enable: bool = True):
+    _check(lib().kqft_ctx_profile(ctx(), int(enable)))
+
+
+def profile_read():
+    """Per kernel kind (pi, gather, gemm, reductions): (summed ms, launches), then cleared."""
+    ms = (C.c_double * 4)()
+    n = (C.c_int * 4)()
+    _check(lib().kqft_ctx_profile_read(ctx(), ms, n))
+    return {k: (ms[i], n[i]) for i, k in enumerate(("pi", "gather", "gemm", "reduce"))}
 
 
 # ------------------------------------------------------------------ data model

@@ -52,10 +52,12 @@ def class_shape(name: str, N: int) -> tuple:
 
 
 def complex_noise(rng: np.random.Generator, shape: tuple, amplitude: float = NOISE_AMPLITUDE) -> np.ndarray:
-    z = rng.standard_normal(shape + (2,))
+    """amplitude * (z0 + i z1) with (z0, z1) consecutive standard normals, written straight
+    into the interleaved (re, im) storage of the result."""
     out = np.empty(shape, dtype=np.complex128)
-    out.real = amplitude * z[..., 0]
-    out.imag = amplitude * z[..., 1]
+    view = out.view(np.float64).reshape(shape + (2,))
+    rng.standard_normal(out=view)
+    view *= amplitude
     return out
 
 
