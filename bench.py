@@ -47,6 +47,7 @@ def main():
     ap.add_argument("--cpu-points", type=int, default=0, help="oracle sample size (0 = about 20 s of CPU work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["both", "split", "fp64"], default="both")
+    ap.add_argument("--serial", action="store_true", help="no gather/GEMM overlap (per-kernel timing)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the bubble shards over transfer frequencies "
@@ -87,12 +88,12 @@ def main():
         prec = precs[name]
         out = K.alloc_channel(n)
         for _ in range(args.warmup):
-            K.bubble(0, V, V, P, q, precision=prec, omega_batch=args.omega_batch, out=out)
+            K.bubble(0, V, V, P, q, precision=prec, omega_batch=args.omega_batch, out=out, serial=args.serial)
         torch.cuda.synchronize()
         K.profile(True)
         t0 = time.perf_counter()
         for i in range(args.steps):
-            K.bubble(0, V, V, P, q, precision=prec, omega_batch=args.omega_batch, out=out)
+            K.bubble(0, V, V, P, q, precision=prec, omega_batch=args.omega_batch, out=out, serial=args.serial)
             log(f"{name} step {i + 1}/{args.steps} enqueued")
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
@@ -113,7 +114,8 @@ def main():
             "dtype": dtype,
         }
         outs[name] = out
-        log(f"{name}: {dt * 1e3:.1f} ms/step, {F / dt / 1e12:.2f} TFLOP/s; GEMM {gemm_ms_step:.1f} ms")
+        log(f"{name}: {dt * 1e3:.1f} ms/step, {F / dt / 1e12:.2f} TFLOP/s; GEMM {gemm_ms_step:.1f} ms, "
+            f"gather {prof['gather'][0] / args.steps:.1f} ms, pi {prof['pi'][0] / args.steps:.1f} ms")
 
     # accuracy of the split path against the FP64 path (parity-tested against the oracle)
     err = {}
@@ -200,7 +202,8 @@ def main():
         "config": {"workload": f"channel-a K3 bubble, SIAM at particle-hole symmetry, N={n}, Nq={nq}, U=1, "
                                f"T=0.1, Delta=1, PT2 seed + 1e-3 noise (seed 0)",
                    "n": n, "nq": nq, "channel": "a", "omega_batch": args.omega_batch,
-                   "algorithmic_tflop_per_step": round(F / 1e12, 4), "path": head},
+                   "algorithmic_tflop_per_step": round(F / 1e12, 4), "path": head,
+                   "overlap": not args.serial},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "paths": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}

@@ -125,6 +125,8 @@ typedef struct {
   int class_mask;  /* KQFT_K* bits of the outputs to compute */
   int beta;        /* 0: overwrite outputs, 1: add into them */
   int omega_batch; /* transfer frequencies per panel batch, 0 = automatic */
+  int serial;      /* 0: vertex gathers of the next batch overlap the current GEMM (two
+                      internal streams); 1: run them one after the other (for timing) */
 } kqft_opts;
 
 typedef struct kqft_ctx kqft_ctx;

@@ -35,7 +35,12 @@ struct kqft_ctx {
   int device = 0;
   std::map<std::tuple<int, double, double>, double*> grids;
   std::map<std::tuple<int, int, double, double>, std::pair<double*, double*>> quads;
-  DevBuf panels, pi, phi, chi_part, lstore[2][3], adj;
+  DevBuf panels[2], pi[2], phi, chi_part, lstore[2][3], adj, fused[2][3];
+  // internal streams (default priority, non-blocking): vertex gathers and GEMMs of
+  // consecutive transfer-frequency batches overlap, ordered by events
+  hipStream_t sg = nullptr, sm = nullptr;
+  std::vector<hipEvent_t> events;
+  size_t next_event = 0;
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[4];
 };
@@ -135,7 +140,10 @@ static int get_quad(kqft_ctx* ctx, const kqft_quad& q, const double** qv, const 
 
 static int ensure(DevBuf& b, size_t bytes) {
   if (b.bytes >= bytes) return KQFT_OK;
-  if (b.p) (void)hipFree(b.p);
+  if (b.p) {  // the old buffer may still be read by work of an earlier call
+    (void)hipDeviceSynchronize();
+    (void)hipFree(b.p);
+  }
   b.p = nullptr;
   b.bytes = 0;
   if (hipMalloc(&b.p, bytes) != hipSuccess) {
@@ -185,6 +193,8 @@ static DVert to_dvert(const kqft_vertex& v) {
     d.ch[r].K[1] = (const double2*)v.ch[r].K2;
     d.ch[r].K[2] = (const double2*)v.ch[r].K2p;
     d.ch[r].K[3] = (const double2*)v.ch[r].K3;
+    d.ch[r].Kf = nullptr;
+    d.ch[r].kf32 = 0;
     if (d.ch[r].coef == 0.0)
       for (int c = 0; c < 4; ++c) d.ch[r].K[c] = nullptr;
   }
@@ -233,11 +243,64 @@ static size_t panel_bytes_per_w(int n, int nq, int precision) {
   return 4 * M * Kp * elt;  // two spin combinations x (A + B^T)
 }
 
+static int next_event(kqft_ctx* ctx, hipEvent_t* ev) {
+  if (ctx->next_event == ctx->events.size()) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ctx->events.push_back(e);
+  }
+  *ev = ctx->events[ctx->next_event++];
+  return KQFT_OK;
+}
+
+static int ensure_streams(kqft_ctx* ctx) {
+  if (!ctx->sg) HIP_TRY(hipStreamCreateWithFlags(&ctx->sg, hipStreamNonBlocking));
+  if (!ctx->sm) HIP_TRY(hipStreamCreateWithFlags(&ctx->sm, hipStreamNonBlocking));
+  return KQFT_OK;
+}
+
+static bool same_channel(const kqft_chvert& a, const kqft_chvert& b) {
+  return a.coef != 0.0 && b.coef != 0.0 && a.K1 == b.K1 && a.K2 == b.K2 && a.K2p == b.K2p && a.K3 == b.K3;
+}
+
+// Fused K1+K2+K2'+K3 tables of the channels other than r that carry a K3 class; the
+// right side reuses the left side's table when both point at the same arrays.
+static int build_fused(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_vertex& R, DVert& VL, DVert& VR,
+                       bool f32, hipStream_t s) {
+  const int n = L.grid.n;
+  const size_t bytes = (size_t)2 * n * n * n * 16 * (f32 ? sizeof(float2) : sizeof(double2));
+  const kqft_vertex* side[2] = {&L, &R};
+  DVert* dv[2] = {&VL, &VR};
+  for (int sd = 0; sd < 2; ++sd)
+    for (int r2 = 0; r2 < 3; ++r2) {
+      dv[sd]->ch[r2].Kf = nullptr;
+      const kqft_chvert& c = side[sd]->ch[r2];
+      if (r2 == r || c.coef == 0.0 || !c.K3) continue;
+      if (sd == 1 && same_channel(L.ch[r2], c) && VL.ch[r2].Kf) {
+        VR.ch[r2].Kf = VL.ch[r2].Kf;
+        VR.ch[r2].kf32 = VL.ch[r2].kf32;
+        continue;
+      }
+      int rc = ensure(ctx->fused[sd][r2], bytes);
+      if (rc) return rc;
+      FuseArgs fa{n, (const double2*)c.K1, (const double2*)c.K2, (const double2*)c.K2p, (const double2*)c.K3,
+                  ctx->fused[sd][r2].p};
+      {
+        ProfScope ps(ctx, 1, s);
+        launch_fuse(fa, f32, s);
+      }
+      dv[sd]->ch[r2].Kf = ctx->fused[sd][r2].p;
+      dv[sd]->ch[r2].kf32 = f32 ? 1 : 0;
+    }
+  return KQFT_OK;
+}
+
 static int bubble_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_vertex& R, const kqft_propagator& G,
                        int kind, const kqft_quad& q, const kqft_opts& o, const BubbleOut& out, hipStream_t s) {
   int rc;
   const int n = L.grid.n;
   if ((rc = init_tables())) return rc;
+  if ((rc = ensure_streams(ctx))) return rc;
   const double *nodes, *qv, *qw;
   if ((rc = get_grid(ctx, L.grid, &nodes))) return rc;
   if ((rc = get_quad(ctx, q, &qv, &qw))) return rc;
@@ -255,38 +318,58 @@ static int bubble_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_ve
   const bool main_cols = mask & (KQFT_K3 | KQFT_K2P), border_col = mask & (KQFT_K2 | KQFT_K1);
   const int ilo = main_rows ? 0 : n, ihi = border_row ? n : n - 1;
   const int jlo = main_cols ? 0 : n, jhi = border_col ? n : n - 1;
-  // batch of transfer frequencies
-  const size_t per_w = panel_bytes_per_w(n, nq, o.precision) + (size_t)nq * 256;
+  // batch of transfer frequencies (two panel buffers in flight)
+  const size_t per_w = panel_bytes_per_w(n, nq, o.precision);
   int nb = o.omega_batch > 0 ? o.omega_batch : (int)std::max<size_t>(1, ((size_t)4 << 30) / per_w);
   nb = std::min(nb, n);
   const size_t pbytes = (size_t)M * Kp * elt;  // one panel of one transfer frequency
-  if ((rc = ensure(ctx->panels, 4 * pbytes * nb))) return rc;
-  if ((rc = ensure(ctx->pi, (size_t)nb * nq * 256))) return rc;
-  char* base = (char*)ctx->panels.p;
-  void* A0 = base;
-  void* A1 = base + pbytes * nb;
-  void* B0 = base + 2 * pbytes * nb;
-  void* B1 = base + 3 * pbytes * nb;
+  for (int x = 0; x < 2; ++x) {
+    if ((rc = ensure(ctx->panels[x], 4 * pbytes * nb))) return rc;
+    if ((rc = ensure(ctx->pi[x], (size_t)nb * nq * 256))) return rc;
+  }
   DVert VL = to_dvert(L), VR = to_dvert(R);
-  for (int iw0 = 0; iw0 < n; iw0 += nb) {
+  ctx->next_event = 0;
+  hipEvent_t start;
+  if ((rc = next_event(ctx, &start))) return rc;
+  HIP_TRY(hipEventRecord(start, s));
+  HIP_TRY(hipStreamWaitEvent(ctx->sg, start, 0));
+  HIP_TRY(hipStreamWaitEvent(ctx->sm, start, 0));
+  if (main_rows || main_cols)
+    if ((rc = build_fused(ctx, r, L, R, VL, VR, f32, ctx->sg))) return rc;
+  std::vector<hipEvent_t> gemm_done;
+  int batch = 0;
+  for (int iw0 = 0; iw0 < n; iw0 += nb, ++batch) {
     const int cnt = std::min(nb, n - iw0);
-    PiArgs pa{r, kind, cnt, nq, iw0, P, nodes, qv, qw, (double2*)ctx->pi.p};
+    const int x = batch & 1;
+    char* base = (char*)ctx->panels[x].p;
+    void* A0 = base;
+    void* A1 = base + pbytes * nb;
+    void* B0 = base + 2 * pbytes * nb;
+    void* B1 = base + 3 * pbytes * nb;
+    double2* pib = (double2*)ctx->pi[x].p;
+    if (o.serial && batch >= 1) HIP_TRY(hipStreamWaitEvent(ctx->sg, gemm_done[batch - 1], 0));
+    if (batch >= 2) HIP_TRY(hipStreamWaitEvent(ctx->sg, gemm_done[batch - 2], 0));
+    PiArgs pa{r, kind, cnt, nq, iw0, P, nodes, qv, qw, pib};
     {
-      ProfScope ps(ctx, 0, s);
-      launch_pi(pa, s);
+      ProfScope ps(ctx, 0, ctx->sg);
+      launch_pi(pa, ctx->sg);
     }
-    GatherArgs ga{r, cnt, iw0, nq, nq_pad, ilo, ihi - ilo + 1, Kp, VL, nodes, qv, (const double2*)ctx->pi.p,
-                  A0, A1, nullptr, nullptr, {kMix[r][0], kMix[r][1], kMix[r][2], kMix[r][3]}};
+    GatherArgs ga{r, cnt, iw0, nq, nq_pad, ilo, ihi - ilo + 1, Kp, VL, nodes, qv, pib, A0, A1, nullptr, nullptr,
+                  {kMix[r][0], kMix[r][1], kMix[r][2], kMix[r][3]}};
     {
-      ProfScope ps(ctx, 1, s);
-      launch_gather(ga, true, f32, s);
+      ProfScope ps(ctx, 1, ctx->sg);
+      launch_gather(ga, true, f32, ctx->sg);
     }
     GatherArgs gb{r, cnt, iw0, nq, nq_pad, jlo, jhi - jlo + 1, Kp, VR, nodes, qv, nullptr, B0, B1, nullptr, nullptr,
                   {kMix[r][0], kMix[r][1], kMix[r][2], kMix[r][3]}};
     {
-      ProfScope ps(ctx, 1, s);
-      launch_gather(gb, false, f32, s);
+      ProfScope ps(ctx, 1, ctx->sg);
+      launch_gather(gb, false, f32, ctx->sg);
     }
+    hipEvent_t gdone, mdone;
+    if ((rc = next_event(ctx, &gdone)) || (rc = next_event(ctx, &mdone))) return rc;
+    HIP_TRY(hipEventRecord(gdone, ctx->sg));
+    HIP_TRY(hipStreamWaitEvent(ctx->sm, gdone, 0));
     GemmArgs g;
     memset(&g, 0, sizeof g);
     g.A[0] = A0;
@@ -306,16 +389,20 @@ static int bubble_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_ve
     g.iw0 = iw0;
     g.beta = o.beta;
     g.cmask = mask;
-    for (int x = 0; x < 4; ++x) g.unmix[x] = kUnmix[r][x];
+    for (int u = 0; u < 4; ++u) g.unmix[u] = kUnmix[r][u];
     g.K1 = out.K1;
     g.K2 = out.K2;
     g.K2p = out.K2p;
     g.K3 = out.K3;
     {
-      ProfScope ps(ctx, 2, s);
-      launch_gemm(g, o.precision, false, s);
+      ProfScope ps(ctx, 2, ctx->sm);
+      launch_gemm(g, o.precision, false, ctx->sm);
     }
+    HIP_TRY(hipEventRecord(mdone, ctx->sm));
+    gemm_done.push_back(mdone);
   }
+  // the caller's stream resumes after the last GEMM (which followed every gather)
+  HIP_TRY(hipStreamWaitEvent(s, gemm_done.back(), 0));
   HIP_TRY(hipGetLastError());
   return KQFT_OK;
 }
@@ -334,6 +421,7 @@ static int check_common(kqft_ctx* ctx, const kqft_propagator* G, const kqft_quad
   if (o->precision != KQFT_FP64 && o->precision != KQFT_SPLIT_FP32) return fail(KQFT_EINVAL, "unknown precision");
   if (o->beta != 0 && o->beta != 1) return fail(KQFT_EINVAL, "beta must be 0 or 1");
   if (o->omega_batch < 0) return fail(KQFT_EINVAL, "omega_batch must be >= 0");
+  if (o->serial != 0 && o->serial != 1) return fail(KQFT_EINVAL, "serial must be 0 or 1");
   return KQFT_OK;
 }
 
@@ -364,12 +452,19 @@ int kqft_ctx_destroy(kqft_ctx* ctx) {
   (void)hipDeviceSynchronize();
   for (auto& kv : ctx->grids) (void)hipFree(kv.second);
   for (auto& kv : ctx->quads) (void)hipFree(kv.second.first);
-  DevBuf* bufs[] = {&ctx->panels, &ctx->pi, &ctx->phi, &ctx->chi_part, &ctx->adj};
+  DevBuf* bufs[] = {&ctx->panels[0], &ctx->panels[1], &ctx->pi[0], &ctx->pi[1], &ctx->phi, &ctx->chi_part,
+                    &ctx->adj};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (auto& row : ctx->lstore)
     for (auto& b : row)
       if (b.p) (void)hipFree(b.p);
+  for (auto& row : ctx->fused)
+    for (auto& b : row)
+      if (b.p) (void)hipFree(b.p);
+  for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+  if (ctx->sg) (void)hipStreamDestroy(ctx->sg);
+  if (ctx->sm) (void)hipStreamDestroy(ctx->sm);
   delete ctx;
   return KQFT_OK;
 }
@@ -404,10 +499,11 @@ int kqft_ctx_profile_read(kqft_ctx* ctx, double* ms, int* launches) {
 
 size_t kqft_bubble_workspace(int n, int nq, int omega_batch, int precision) {
   if (n < 2 || nq < 1) return 0;
-  const size_t per_w = panel_bytes_per_w(n, nq, precision) + (size_t)nq * 256;
+  const size_t per_w = panel_bytes_per_w(n, nq, precision);
   int nb = omega_batch > 0 ? omega_batch : (int)std::max<size_t>(1, ((size_t)4 << 30) / per_w);
   nb = std::min(nb, n);
-  return per_w * nb;
+  // two panel buffers, two propagator-pair buffers, up to four fused class tables
+  return 2 * (per_w + (size_t)nq * 256) * nb + (size_t)4 * 2 * n * n * n * 16 * 16;
 }
 
 int kqft_bubble(kqft_ctx* ctx, int channel, const kqft_vertex* left, const kqft_vertex* right,
@@ -471,16 +567,16 @@ int kqft_sde(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, 
     const int nq = q_bubble->n;
     const int nblk = chi_blocks(nq);
     const int nb = std::max(1, std::min(n, (int)((256L << 20) / ((long)nq * 256))));
-    if ((rc = ensure(ctx->pi, (size_t)nb * nq * 256))) return rc;
+    if ((rc = ensure(ctx->pi[0], (size_t)nb * nq * 256))) return rc;
     if ((rc = ensure(ctx->chi_part, (size_t)nb * nblk * 32 * 16))) return rc;
     for (int iw0 = 0; iw0 < n; iw0 += nb) {
       const int cnt = std::min(nb, n - iw0);
-      PiArgs pa{KQFT_CH_A, KQFT_PI_GG, cnt, nq, iw0, P, nodes, cqv, cqw, (double2*)ctx->pi.p};
+      PiArgs pa{KQFT_CH_A, KQFT_PI_GG, cnt, nq, iw0, P, nodes, cqv, cqw, (double2*)ctx->pi[0].p};
       {
         ProfScope ps(ctx, 0, s);
         launch_pi(pa, s);
       }
-      ChiArgs ca{to_dvert(*gamma), nq, cnt, iw0, nodes, cqv, (const double2*)ctx->pi.p,
+      ChiArgs ca{to_dvert(*gamma), nq, cnt, iw0, nodes, cqv, (const double2*)ctx->pi[0].p,
                  (double2*)ctx->chi_part.p, (double2*)chi};
       {
         ProfScope ps(ctx, 3, s);

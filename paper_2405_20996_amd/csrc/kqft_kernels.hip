@@ -75,6 +75,35 @@ __global__ __launch_bounds__(256) void pi_kernel(PiArgs a) {
 }
 
 // ======================================================================== gather
+__device__ inline double2 ld2(const double2* p) { return *p; }
+__device__ inline double2 ld2(const float2* p) {
+  const float2 v = *p;
+  return make_double2((double)v.x, (double)v.y);
+}
+
+// Trilinear interpolation of a fused class table at cell (iw, iv, ivp) with weights t*.
+template <class TT>
+__device__ inline void fused_taps(const TT* Kf, int n, double coef, int iw, double tw, int iv, double tv, int ivp,
+                                  double tvp, const int f2[4], double2 X[4], double2 Y[4]) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    double2* acc = s ? Y : X;
+#pragma unroll
+    for (int cw = 0; cw < 2; ++cw) {
+      const double ww = coef * (cw ? tw : 1.0 - tw);
+      const size_t sw = (size_t)s * n + iw + cw;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const double wv = ww * (c ? tv : 1.0 - tv);
+        const TT* p = Kf + ((sw * n + iv + c) * n + ivp) * 16;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          acc[e] = cfma(wv * (1.0 - tvp), ld2(p + f2[e]), cfma(wv * tvp, ld2(p + 16 + f2[e]), acc[e]));
+      }
+    }
+  }
+}
+
 // Add coef * gamma_{r2}(w2, v2, vp2) for four flat indices f2[e] (channel r2 order).
 __device__ inline void add_channel(const DChan& C, const DGrid& g, double w2, double v2, double vp2, const int f2[4],
                                    double2 X[4], double2 Y[4]) {
@@ -85,6 +114,13 @@ __device__ inline void add_channel(const DChan& C, const DGrid& g, double w2, do
   bool invp = dgrid_locate(g, vp2, ivp, tvp);
   const int n = g.n;
   const double coef = C.coef;
+  if (inv && invp && C.Kf) {
+    if (C.kf32)
+      fused_taps((const float2*)C.Kf, n, coef, iw, tw, iv, tv, ivp, tvp, f2, X, Y);
+    else
+      fused_taps((const double2*)C.Kf, n, coef, iw, tw, iv, tv, ivp, tvp, f2, X, Y);
+    return;
+  }
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     double2* acc = s ? Y : X;
@@ -419,11 +455,19 @@ __device__ inline void epilogue_store(const GemmArgs& g, int b, int row, int col
   *py = Y;
 }
 
+// Workgroups are dispatched round-robin over the eight XCDs (block id mod 8), each with
+// its own L2.  Give every XCD a contiguous range of logical tiles -- consecutive tiles of
+// one transfer frequency, row-major -- so that the workgroups sharing an A row strip or a
+// B column strip run on the same XCD at the same time and reuse it from that L2.
+constexpr int kXcds = 8;
 __device__ inline void tile_coords(const GemmArgs& g, int& b, int& tm, int& tn) {
   const int tiles = g.tms * g.tns;
+  const int total = g.nb * tiles;
+  const int per_xcd = (total + kXcds - 1) / kXcds;
   const int bid = blockIdx.x;
-  b = bid / tiles;
-  const int t = bid - b * tiles;
+  const int logical = (bid % kXcds) * per_xcd + bid / kXcds;
+  b = logical / tiles;  // >= nb for the padding blocks of the last XCD: they exit
+  const int t = logical - b * tiles;
   tm = g.tm0 + t / g.tns;
   tn = g.tn0 + t % g.tns;
 }
@@ -861,6 +905,29 @@ __global__ void chi_finalize_kernel(ChiArgs a, int nblk) {
   a.out[((size_t)c * a.V.g.n + a.iw0 + b) * 16 + f] = s;
 }
 
+// ======================================================================== fused class table
+// Kf[s][w][v][v'] = K1[s][w] + K2[s][w][v] + K2'[s][w][v'] + K3[s][w][v][v'] (absent classes = 0)
+__device__ inline void st2(double2* p, double2 v) { *p = v; }
+__device__ inline void st2(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+
+template <class TT> __global__ __launch_bounds__(256) void fuse_kernel(FuseArgs a) {
+  const size_t n = a.n;
+  const size_t total = 2 * n * n * n * 16;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t f = e & 15;
+    size_t rest = e >> 4;
+    const size_t vp = rest % n;
+    rest /= n;
+    const size_t v = rest % n;
+    const size_t sw = rest / n;  // s * n + w
+    double2 x = a.K3 ? a.K3[e] : czero();
+    if (a.K1) x = cadd(x, a.K1[sw * 16 + f]);
+    if (a.K2) x = cadd(x, a.K2[(sw * n + v) * 16 + f]);
+    if (a.K2p) x = cadd(x, a.K2p[(sw * n + vp) * 16 + f]);
+    st2((TT*)a.out + e, x);
+  }
+}
+
 // ======================================================================== launchers
 static inline unsigned blocks_for(long threads, int bs) { return (unsigned)((threads + bs - 1) / bs); }
 
@@ -868,6 +935,12 @@ hipError_t upload_perm(const int* host_perm) {
   return hipMemcpyToSymbol(HIP_SYMBOL(c_perm), host_perm, sizeof(int) * 3 * 3 * 16);
 }
 
+void launch_fuse(const FuseArgs& a, bool f32, hipStream_t s) {
+  if (f32)
+    hipLaunchKernelGGL(fuse_kernel<float2>, dim3(4096), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(fuse_kernel<double2>, dim3(4096), dim3(256), 0, s, a);
+}
 void launch_pi(const PiArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(pi_kernel, dim3(blocks_for((long)a.nb * a.nq, 256)), dim3(256), 0, s, a);
 }
@@ -887,7 +960,8 @@ void launch_gather(const GatherArgs& a, bool left, bool f32, hipStream_t s) {
   }
 }
 void launch_gemm(const GemmArgs& g, int precision, bool lo, hipStream_t s) {
-  dim3 grid((unsigned)(g.nb * g.tms * g.tns));
+  const int total = g.nb * g.tms * g.tns;
+  dim3 grid((unsigned)(((total + kXcds - 1) / kXcds) * kXcds));
   if (precision == 0)
     hipLaunchKernelGGL(zgemm_f64_kernel, grid, dim3(256), 0, s, g);
   else if (lo)

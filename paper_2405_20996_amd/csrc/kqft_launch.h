@@ -66,7 +66,17 @@ struct ChiArgs {
   double2* out;       // [2][n][16]
 };
 
+struct FuseArgs {
+  int n;
+  const double2* K1;
+  const double2* K2;
+  const double2* K2p;
+  const double2* K3;
+  void* out;  // double2 or float2 table
+};
+
 hipError_t upload_perm(const int* host_perm);
+void launch_fuse(const FuseArgs& a, bool f32, hipStream_t s);
 void launch_pi(const PiArgs& a, hipStream_t s);
 void launch_gather(const GatherArgs& a, bool left, bool f32, hipStream_t s);
 void launch_gemm(const GemmArgs& g, int precision, bool lo, hipStream_t s);

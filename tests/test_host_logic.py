@@ -1,0 +1,53 @@
+"""CPU tests of host-side logic: seeded inputs, workload definitions, bench guard rails."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+from workload import CONFIGS, C4_POINTS, class_shape, complex_noise, random_channel, seed_noise
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_noise_is_seeded_and_ordered():
+    a = seed_noise(5, 0)
+    b = seed_noise(5, 0)
+    for r in range(3):
+        for c in ("K1", "K2", "K2p", "K3"):
+            assert a[r][c].shape == class_shape(c, 5)
+            assert np.array_equal(a[r][c], b[r][c])
+    # one generator drawn in the order channel a, p, t x K1, K2, K2', K3
+    rng = np.random.default_rng(0)
+    first = complex_noise(rng, class_shape("K1", 5))
+    assert np.array_equal(first, a[0]["K1"])
+    assert abs(np.std(a[0]["K3"].real) - 1e-3) < 1e-4
+
+
+def test_complex_noise_layout_matches_pairs_of_normals():
+    rng = np.random.default_rng(3)
+    x = complex_noise(rng, (4, 3), 2.0)
+    rng = np.random.default_rng(3)
+    z = rng.standard_normal((4, 3, 2))
+    assert np.array_equal(x, 2.0 * (z[..., 0] + 1j * z[..., 1]))
+
+
+def test_workloads():
+    c3 = CONFIGS["c3_bubble_a_n201"]
+    assert (c3.N, c3.Nq, c3.U, c3.T) == (201, 2001, 1.0, 0.1)
+    assert len(C4_POINTS) == 12 and {p[2] for p in C4_POINTS} == {51, 101, 151, 201}
+    rc = random_channel(3, 1)
+    assert set(rc) == {"K1", "K2", "K2p", "K3"}
+
+
+def test_bench_rejects_more_than_one_gpu():
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=120)
+    assert res.returncode == 2 and "one GPU" in res.stderr
+
+
+def test_bench_flop_count():
+    sys.path.insert(0, ROOT)
+    import bench
+    assert abs(bench.algorithmic_flops(201, 2001) / 1e12 - 16.8053) < 1e-3
+    assert abs(bench.algorithmic_flops(31, 201) / 1e9 - 6.5337) < 1e-3
