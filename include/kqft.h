@@ -224,6 +224,18 @@ int kqft_bubble_adjoint(kqft_ctx* ctx, int channel, const kqft_vertex* left, con
                         const kqft_chout* dout, const kqft_chout* dleft, const kqft_chout* dright,
                         double* dscal, void* stream);
 
+/*
+ * kqft_sde_adjoint -- vector-Jacobian product of the self-energy of kqft_sde (not in the
+ * paper).  Given dsigma (device [n][4] complex, cotangent of sigma), accumulates
+ *   dgamma[r] += dL/d(class arrays of gamma's channel r),
+ *   dscal[0] += dL/d gamma->r0 (through both Gamma_0 of the Schwinger-Dyson bubble and gamma),
+ *   dscal[1] += dL/d G->Delta.
+ * Phi is recomputed.  dgamma: host array of 3 kqft_chout; dscal: device array of 2 doubles.
+ */
+int kqft_sde_adjoint(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, const kqft_quad* q_bubble,
+                     const kqft_quad* q_loop, const kqft_opts* opts, const double* dsigma, const kqft_chout* dgamma,
+                     double* dscal, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

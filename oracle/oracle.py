@@ -380,3 +380,23 @@ def mloop(V: Vertex, P: Prop, q: Quad, nloops: int, dual: bool = False) -> list:
             this.append(Channel(1.0, tot["K1"], tot["K2"], tot["K2p"], tot["K3"]))
         out.append(this)
     return out
+
+
+def to_dual(arr: Optional[np.ndarray]) -> Optional[np.ndarray]:
+    """Complex array -> dual layout [..., 4] = (re, d re, im, d im) with zero derivative."""
+    if arr is None:
+        return None
+    d = np.zeros(arr.shape + (4,))
+    d[..., 0] = arr.real
+    d[..., 2] = arr.imag
+    return d
+
+
+def dual_parts(d: np.ndarray):
+    """(value, derivative) complex arrays of a dual array."""
+    return d[..., 0] + 1j * d[..., 2], d[..., 1] + 1j * d[..., 3]
+
+
+def dual_vertex(V: Vertex, dr0: float = 0.0) -> Vertex:
+    chans = [Channel(c.coef, *[to_dual(getattr(c, k)) for k in ("K1", "K2", "K2p", "K3")]) for c in V.ch]
+    return Vertex(V.grid, V.r0, chans, dr0=dr0)

@@ -13,7 +13,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # packed FP32 VALU ops are disabled on this target
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+         "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
+         "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
 
 
 def build(verbose: bool = False) -> str:

@@ -9,6 +9,8 @@
 #include <tuple>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "kqft.h"
 #include "kqft_launch.h"
 
@@ -39,6 +41,8 @@ struct kqft_ctx {
   // internal streams (default priority, non-blocking): vertex gathers and GEMMs of
   // consecutive transfer-frequency batches overlap, ordered by events
   hipStream_t sg = nullptr, sm = nullptr;
+  rocblas_handle blas = nullptr;
+  DevBuf adjw, dkf[2][3], phigrad;
   std::vector<hipEvent_t> events;
   size_t next_event = 0;
   bool prof = false;
@@ -425,6 +429,151 @@ static int check_common(kqft_ctx* ctx, const kqft_propagator* G, const kqft_quad
   return KQFT_OK;
 }
 
+// ------------------------------------------------------------------ adjoint core
+static int blas_ok(rocblas_status st, const char* what) {
+  if (st != rocblas_status_success) return fail(KQFT_EDEVICE, std::string(what) + ": rocBLAS status " + std::to_string((int)st));
+  return KQFT_OK;
+}
+
+// Reverse pass of one bubble (FP64).  dr0_left / dr0_right / dDelta: device doubles that
+// receive the accumulated cotangents (dr0_left may equal dr0_right).
+static int adjoint_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_vertex& R, const kqft_propagator& G,
+                        int kind, const kqft_quad& q, const kqft_chout& dout, const kqft_chout* dleft,
+                        const kqft_chout* dright, double* dr0_left, double* dr0_right, double* dDelta,
+                        hipStream_t s) {
+  int rc;
+  const int n = L.grid.n;
+  if ((rc = init_tables())) return rc;
+  if (!ctx->blas) {
+    if ((rc = blas_ok(rocblas_create_handle(&ctx->blas), "rocblas_create_handle"))) return rc;
+  }
+  if ((rc = blas_ok(rocblas_set_stream(ctx->blas, s), "rocblas_set_stream"))) return rc;
+  const double *nodes, *qv, *qw;
+  if ((rc = get_grid(ctx, L.grid, &nodes))) return rc;
+  if ((rc = get_quad(ctx, q, &qv, &qw))) return rc;
+  DProp P;
+  if ((rc = to_dprop(G, P))) return rc;
+  const int nq = q.n;
+  const int nq_pad = ((nq + 7) / 8) * 8;
+  const long Kp = 4L * nq_pad;
+  const long M = 4L * (n + 1);
+  // per transfer frequency: raw L (2), A (2), B (2), conj dA (2), conj dB (2), conj dP (2), Pi
+  const size_t pan = (size_t)M * Kp * 16, dpan = (size_t)M * M * 16, pib = (size_t)nq * 256;
+  const size_t per_w = 10 * pan + 2 * dpan + pib;
+  int nb = (int)std::max<size_t>(1, ((size_t)3 << 30) / per_w);
+  nb = std::min(nb, n);
+  if ((rc = ensure(ctx->adjw, per_w * nb))) return rc;
+  char* w = (char*)ctx->adjw.p;
+  double2* Lr[2] = {(double2*)w, (double2*)(w + pan * nb)};
+  double2* Ap[2] = {(double2*)(w + 2 * pan * nb), (double2*)(w + 3 * pan * nb)};
+  double2* Bp[2] = {(double2*)(w + 4 * pan * nb), (double2*)(w + 5 * pan * nb)};
+  double2* GA[2] = {(double2*)(w + 6 * pan * nb), (double2*)(w + 7 * pan * nb)};
+  double2* GB[2] = {(double2*)(w + 8 * pan * nb), (double2*)(w + 9 * pan * nb)};
+  double2* Dp[2] = {(double2*)(w + 10 * pan * nb), (double2*)(w + 10 * pan * nb + dpan * nb)};
+  double2* pi = (double2*)(w + 10 * pan * nb + 2 * dpan * nb);
+  DVert VL = to_dvert(L), VR = to_dvert(R);
+  if ((rc = build_fused(ctx, r, L, R, VL, VR, false, s))) return rc;
+  // fused cotangent tables of the other channels (zeroed), un-fused into the classes at the end
+  const kqft_vertex* side[2] = {&L, &R};
+  const kqft_chout* dside[2] = {dleft, dright};
+  AdjScatterArgs sa[2];
+  const size_t fbytes = (size_t)2 * n * n * n * 16 * 16;
+  for (int sd = 0; sd < 2; ++sd) {
+    memset(&sa[sd], 0, sizeof sa[sd]);
+    for (int r2 = 0; r2 < 3; ++r2) {
+      const kqft_chout& d = dside[sd][r2];
+      const bool active = side[sd]->ch[r2].coef != 0.0;
+      sa[sd].dK[r2][0] = active ? (double2*)d.K1 : nullptr;
+      sa[sd].dK[r2][1] = active ? (double2*)d.K2 : nullptr;
+      sa[sd].dK[r2][2] = active ? (double2*)d.K2p : nullptr;
+      sa[sd].dK[r2][3] = active ? (double2*)d.K3 : nullptr;
+      sa[sd].dKf[r2] = nullptr;
+      if (r2 != r && active && d.K3) {
+        if ((rc = ensure(ctx->dkf[sd][r2], fbytes))) return rc;
+        HIP_TRY(hipMemsetAsync(ctx->dkf[sd][r2].p, 0, fbytes, s));
+        sa[sd].dKf[r2] = (double2*)ctx->dkf[sd][r2].p;
+      }
+    }
+  }
+  const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
+  for (int iw0 = 0; iw0 < n; iw0 += nb) {
+    const int cnt = std::min(nb, n - iw0);
+    PiArgs pa{r, kind, cnt, nq, iw0, P, nodes, qv, qw, pi};
+    launch_pi(pa, s);
+    GatherArgs ga{r, cnt, iw0, nq, nq_pad, 0, n + 1, Kp, VL, nodes, qv, nullptr, Lr[0], Lr[1], nullptr, nullptr,
+                  {kMix[r][0], kMix[r][1], kMix[r][2], kMix[r][3]}};
+    launch_gather(ga, true, false, s);
+    ApplyPiArgs ap{n, cnt, nq, nq_pad, Kp, pi, Lr[0], Lr[1], Ap[0], Ap[1]};
+    launch_apply_pi(ap, s);
+    GatherArgs gb{r, cnt, iw0, nq, nq_pad, 0, n + 1, Kp, VR, nodes, qv, nullptr, Bp[0], Bp[1], nullptr, nullptr,
+                  {kMix[r][0], kMix[r][1], kMix[r][2], kMix[r][3]}};
+    launch_gather(gb, false, false, s);
+    DPanelArgs dp{n, cnt, iw0, {kUnmix[r][0], kUnmix[r][1], kUnmix[r][2], kUnmix[r][3]},
+                  (const double2*)dout.K1, (const double2*)dout.K2, (const double2*)dout.K2p,
+                  (const double2*)dout.K3, Dp[0], Dp[1]};
+    launch_dpanel(dp, s);
+    for (int c = 0; c < 2; ++c) {
+      // conj(dA)^T = B . conj(dP)^T  (column-major views of the row-major panels)
+      if ((rc = blas_ok(rocblas_zgemm_strided_batched(
+               ctx->blas, rocblas_operation_none, rocblas_operation_none, (int)Kp, (int)M, (int)M, &one,
+               (const rocblas_double_complex*)Bp[c], (int)Kp, M * Kp, (const rocblas_double_complex*)Dp[c], (int)M,
+               M * M, &zero, (rocblas_double_complex*)GA[c], (int)Kp, M * Kp, cnt),
+                        "zgemm dA")))
+        return rc;
+      // conj(dB) = A^T . conj(dP)
+      if ((rc = blas_ok(rocblas_zgemm_strided_batched(
+               ctx->blas, rocblas_operation_none, rocblas_operation_transpose, (int)Kp, (int)M, (int)M, &one,
+               (const rocblas_double_complex*)Ap[c], (int)Kp, M * Kp, (const rocblas_double_complex*)Dp[c],
+               (int)M, M * M, &zero, (rocblas_double_complex*)GB[c], (int)Kp, M * Kp, cnt),
+                        "zgemm dB")))
+        return rc;
+    }
+    AdjScatterArgs al = sa[0];
+    al.r = r;
+    al.nb = cnt;
+    al.iw0 = iw0;
+    al.nq = nq;
+    al.Kp = Kp;
+    al.V = VL;
+    al.nodes = nodes;
+    al.qv = qv;
+    al.pi = pi;
+    al.G0 = GA[0];
+    al.G1 = GA[1];
+    for (int x = 0; x < 4; ++x) al.mix[x] = kMix[r][x];
+    al.dr0 = dr0_left;
+    launch_adj_left(al, s);
+    AdjScatterArgs ar = sa[1];
+    ar.r = r;
+    ar.nb = cnt;
+    ar.iw0 = iw0;
+    ar.nq = nq;
+    ar.Kp = Kp;
+    ar.V = VR;
+    ar.nodes = nodes;
+    ar.qv = qv;
+    ar.pi = nullptr;
+    ar.G0 = GB[0];
+    ar.G1 = GB[1];
+    for (int x = 0; x < 4; ++x) ar.mix[x] = kMix[r][x];
+    ar.dr0 = dr0_right;
+    launch_adj_right(ar, s);
+    DPiArgs di{r, kind, cnt, nq, iw0, n, Kp, P, nodes, qv, qw, Lr[0], Lr[1], GA[0], GA[1], dDelta};
+    launch_dpi(di, s);
+  }
+  for (int sd = 0; sd < 2; ++sd)
+    for (int r2 = 0; r2 < 3; ++r2)
+      if (sa[sd].dKf[r2]) {
+        UnfuseArgs ua{n, sa[sd].dKf[r2], sa[sd].dK[r2][0], sa[sd].dK[r2][1], sa[sd].dK[r2][2], nullptr};
+        launch_unfuse(ua, s);
+        // the K3 class takes the table itself
+        UnfuseArgs u3{n, sa[sd].dKf[r2], nullptr, nullptr, nullptr, sa[sd].dK[r2][3]};
+        launch_unfuse(u3, s);
+      }
+  HIP_TRY(hipGetLastError());
+  return KQFT_OK;
+}
+
 // ------------------------------------------------------------------ C ABI
 extern "C" {
 
@@ -463,6 +612,12 @@ int kqft_ctx_destroy(kqft_ctx* ctx) {
     for (auto& b : row)
       if (b.p) (void)hipFree(b.p);
   for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+  for (auto& row : ctx->dkf)
+    for (auto& b : row)
+      if (b.p) (void)hipFree(b.p);
+  if (ctx->adjw.p) (void)hipFree(ctx->adjw.p);
+  if (ctx->phigrad.p) (void)hipFree(ctx->phigrad.p);
+  if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
   if (ctx->sg) (void)hipStreamDestroy(ctx->sg);
   if (ctx->sm) (void)hipStreamDestroy(ctx->sm);
   delete ctx;
@@ -675,10 +830,64 @@ int kqft_bubble_adjoint(kqft_ctx* ctx, int channel, const kqft_vertex* left, con
                         const kqft_propagator* G, int pi_kind, const kqft_quad* q, const kqft_opts* opts,
                         const kqft_chout* dout, const kqft_chout* dleft, const kqft_chout* dright, double* dscal,
                         void* stream) {
-  (void)channel; (void)left; (void)right; (void)G; (void)pi_kind; (void)q; (void)opts;
-  (void)dout; (void)dleft; (void)dright; (void)dscal; (void)stream;
-  if (!ctx) return fail(KQFT_EINVAL, "ctx is NULL");
-  return fail(KQFT_EINVAL, "kqft_bubble_adjoint: not available in this build");
+  int rc;
+  if ((rc = check_common(ctx, G, q, opts))) return rc;
+  if (channel < 0 || channel > 2) return fail(KQFT_EINVAL, "channel must be 0 (a), 1 (p) or 2 (t)");
+  if (pi_kind != KQFT_PI_GG && pi_kind != KQFT_PI_DOT) return fail(KQFT_EINVAL, "unknown propagator pair");
+  if ((rc = check_vertex(left, "left vertex")) || (rc = check_vertex(right, "right vertex"))) return rc;
+  if (!same_grid(left->grid, right->grid)) return fail(KQFT_ESHAPE, "left and right vertices must share one grid");
+  if (!dout || !dleft || !dright || !dscal) return fail(KQFT_EINVAL, "dout, dleft, dright and dscal must be given");
+  HIP_TRY(hipSetDevice(ctx->device));
+  return adjoint_core(ctx, channel, *left, *right, *G, pi_kind, *q, *dout, dleft, dright, dscal, dscal + 1,
+                      dscal + 2, (hipStream_t)stream);
+}
+
+int kqft_sde_adjoint(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, const kqft_quad* q_bubble,
+                     const kqft_quad* q_loop, const kqft_opts* opts, const double* dsigma, const kqft_chout* dgamma,
+                     double* dscal, void* stream) {
+  int rc;
+  if ((rc = check_common(ctx, G, q_bubble, opts))) return rc;
+  if (!q_loop || q_loop->n < 1) return fail(KQFT_ESHAPE, "invalid loop quadrature");
+  if ((rc = check_vertex(gamma, "gamma"))) return rc;
+  if (!dsigma || !dgamma || !dscal) return fail(KQFT_EINVAL, "dsigma, dgamma and dscal must be given");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const int n = gamma->grid.n;
+  // recompute Phi = B_a(Gamma_0, Gamma) (classes K1, K2')
+  const size_t k1b = (size_t)2 * n * 16 * 16, k2b = (size_t)2 * n * n * 16 * 16;
+  if ((rc = ensure(ctx->phi, k1b + k2b))) return rc;
+  if ((rc = ensure(ctx->phigrad, k1b + k2b))) return rc;
+  double2* phiK1 = (double2*)ctx->phi.p;
+  double2* phiK2p = (double2*)((char*)ctx->phi.p + k1b);
+  double2* dK1 = (double2*)ctx->phigrad.p;
+  double2* dK2p = (double2*)((char*)ctx->phigrad.p + k1b);
+  kqft_vertex bare;
+  memset(&bare, 0, sizeof bare);
+  bare.r0 = gamma->r0;
+  bare.grid = gamma->grid;
+  kqft_opts o = *opts;
+  o.precision = KQFT_FP64;
+  o.class_mask = KQFT_K1 | KQFT_K2P;
+  o.beta = 0;
+  o.serial = 0;
+  BubbleOut po{phiK1, nullptr, phiK2p, nullptr};
+  if ((rc = bubble_core(ctx, KQFT_CH_A, bare, *gamma, *G, KQFT_PI_GG, *q_bubble, o, po, s))) return rc;
+  // loop adjoint: dSigma -> dPhi, dDelta
+  const double *nodes, *qv, *qw;
+  if ((rc = get_grid(ctx, gamma->grid, &nodes))) return rc;
+  if ((rc = get_quad(ctx, *q_loop, &qv, &qw))) return rc;
+  DProp P;
+  if ((rc = to_dprop(*G, P))) return rc;
+  HIP_TRY(hipMemsetAsync(ctx->phigrad.p, 0, k1b + k2b, s));
+  LoopAdjArgs la{make_dgrid(n, gamma->grid.L, gamma->grid.a), P, q_loop->n, nodes, qv, qw, phiK1, phiK2p,
+                 (const double2*)dsigma, dK1, dK2p, dscal + 1};
+  launch_loop_adjoint(la, s);
+  // bubble adjoint of Phi: the bare vertex on the left carries gamma->r0 as well
+  kqft_chout dphi{(double*)dK1, nullptr, (double*)dK2p, nullptr};
+  kqft_chout none[3];
+  memset(none, 0, sizeof none);
+  return adjoint_core(ctx, KQFT_CH_A, bare, *gamma, *G, KQFT_PI_GG, *q_bubble, dphi, none, dgamma, dscal, dscal,
+                      dscal + 1, s);
 }
 
 }  // extern "C"

@@ -113,6 +113,46 @@ __device__ inline void propagator(const DProp& P, int kind, double v, double2 m[
   m[3] = SK;
 }
 
+// Value m and Delta-derivative dm (at fixed Sigma) of G (kind 0: dm = S) or of the
+// single-scale propagator S (kind 1: dm = dS/dDelta).  With br = Sigma^K - 2 i Delta tanh:
+//   dS^R = -2 (G^R)^3,  dS^K = dS^R br G^A + 2 S^R br S^A + G^R br dS^A
+//                               + 2 (-2 i tanh)(S^R G^A + G^R S^A).
+__device__ inline void propagator_dDelta(const DProp& P, int kind, double v, double2 m[4], double2 dm[4]) {
+  double th = tanh(v / (2.0 * P.T));
+  double2 sR = sigma_at(P.sg, P.SigR, v);
+  double2 sK = P.SigK ? sigma_at(P.sg, P.SigK, v) : make_double2(0.0, 2.0 * th * sR.y);
+  double dr = v - P.eps - sR.x, di = P.Delta - sR.y;
+  double inv = 1.0 / (dr * dr + di * di);
+  double2 GR = make_double2(dr * inv, -di * inv);
+  double2 GA = cconj(GR);
+  double2 br = make_double2(sK.x, sK.y - 2.0 * th * P.Delta);
+  double2 dbr = make_double2(0.0, -2.0 * th);
+  double2 SR = cmul(make_double2(0.0, -1.0), cmul(GR, GR));
+  double2 SA = cconj(SR);
+  double2 SK = cadd(cadd(cmul(cmul(SR, br), GA), cmul(cmul(GR, dbr), GA)), cmul(cmul(GR, br), SA));
+  m[0] = czero();
+  dm[0] = czero();
+  if (kind == 0) {
+    m[1] = GA;
+    m[2] = GR;
+    m[3] = cmul(cmul(GR, br), GA);
+    dm[1] = SA;
+    dm[2] = SR;
+    dm[3] = SK;
+    return;
+  }
+  double2 dSR = cscale(-2.0, cmul(GR, cmul(GR, GR)));
+  double2 dSA = cconj(dSR);
+  double2 dSK = cadd(cadd(cmul(cmul(dSR, br), GA), cscale(2.0, cmul(cmul(SR, br), SA))),
+                     cadd(cmul(cmul(GR, br), dSA), cscale(2.0, cmul(dbr, cadd(cmul(SR, GA), cmul(GR, SA))))));
+  m[1] = SA;
+  m[2] = SR;
+  m[3] = SK;
+  dm[1] = dSA;
+  dm[2] = dSR;
+  dm[3] = dSK;
+}
+
 // ------------------------------------------------------------------ channels
 // Leg frequencies (n1', n2', n1, n2) of channel r at (w, v, v') and back.
 __device__ inline void legs_of(int r, double w, double v, double vp, double L[4]) {

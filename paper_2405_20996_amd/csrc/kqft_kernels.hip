@@ -293,6 +293,14 @@ template <class T> __global__ __launch_bounds__(256) void gather_left_kernel(Gat
   }
   double2 c0[4], c1[4];
   combos(a.mix, X, Y, c0, c1);
+  if (a.pi == nullptr) {  // raw left factor, without the propagator pair (adjoint)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      store_c(o0 + m, c0[m]);
+      store_c(o1 + m, c1[m]);
+    }
+    return;
+  }
   const double2* pk = a.pi + ((size_t)b * a.nq + k) * 16;
   double2 P[16];
 #pragma unroll
@@ -928,6 +936,579 @@ template <class TT> __global__ __launch_bounds__(256) void fuse_kernel(FuseArgs 
   }
 }
 
+
+// ======================================================================== adjoint
+// Reverse pass of the bubble: the cotangent panel conj(dP) is built from the class
+// cotangents (transpose of the epilogue), the two transposed products are batched
+// ZGEMMs, and the kernels below scatter through Pi and the interpolation taps (the
+// transpose of the gathers) and reduce dPi into the Delta-derivative.
+
+__device__ inline void atomic_c(double2* p, double2 v) {
+  atomicAdd(&p->x, v.x);
+  atomicAdd(&p->y, v.y);
+}
+
+__device__ inline void pi_index(int r, int a3, int a3p, int a4, int a4p, int& rp, int& cp) {
+  if (r == 0) {
+    rp = 2 * a3 + a4p;
+    cp = 2 * a3p + a4;
+  } else if (r == 1) {
+    rp = 2 * a3 + a4;
+    cp = 2 * a3p + a4p;
+  } else {
+    rp = 2 * a4p + a3;
+    cp = 2 * a3p + a4;
+  }
+}
+
+__global__ __launch_bounds__(256) void dpanel_kernel(DPanelArgs a) {
+  const int n = a.n;
+  const long M = 4L * (n + 1);
+  const long total = (long)a.nb * M * M;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long C = e % M, R = (e / M) % M;
+    const int b = (int)(e / (M * M));
+    const int i = (int)(R >> 2), j = (int)(C >> 2), f = 4 * (int)(R & 3) + (int)(C & 3);
+    const size_t iw = (size_t)(a.iw0 + b);
+    const double2* base;
+    size_t sstride, off;
+    if (i < n && j < n) {
+      base = a.dK3;
+      sstride = (size_t)n * n * n * 16;
+      off = ((iw * n + i) * n + j) * 16 + f;
+    } else if (i < n) {
+      base = a.dK2;
+      sstride = (size_t)n * n * 16;
+      off = (iw * n + i) * 16 + f;
+    } else if (j < n) {
+      base = a.dK2p;
+      sstride = (size_t)n * n * 16;
+      off = (iw * n + j) * 16 + f;
+    } else {
+      base = a.dK1;
+      sstride = (size_t)n * 16;
+      off = iw * 16 + f;
+    }
+    double2 dX = base ? base[off] : czero();
+    double2 dY = base ? base[sstride + off] : czero();
+    double2 p0 = make_double2(a.unmix[0] * dX.x + a.unmix[2] * dY.x, a.unmix[0] * dX.y + a.unmix[2] * dY.y);
+    double2 p1 = make_double2(a.unmix[1] * dX.x + a.unmix[3] * dY.x, a.unmix[1] * dX.y + a.unmix[3] * dY.y);
+    const size_t o = ((size_t)b * M + R) * M + C;
+    a.D0[o] = cconj(p0);
+    a.D1[o] = cconj(p1);
+  }
+}
+
+__global__ __launch_bounds__(256) void apply_pi_kernel(ApplyPiArgs a) {
+  const long M = 4L * (a.n + 1);
+  const long total = (long)a.nb * M * a.nq_pad;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int k = (int)(e % a.nq_pad);
+    const long R = (e / a.nq_pad) % M;
+    const int b = (int)(e / (a.nq_pad * M));
+    const size_t off = ((size_t)b * M + R) * a.Kp + 4 * (size_t)k;
+    if (k >= a.nq) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) a.A0[off + m] = a.A1[off + m] = czero();
+      continue;
+    }
+    const double2* pk = a.pi + ((size_t)b * a.nq + k) * 16;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      double2 s0 = czero(), s1 = czero();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        s0 = cadd(s0, cmul(a.L0[off + q], pk[4 * q + m]));
+        s1 = cadd(s1, cmul(a.L1[off + q], pk[4 * q + m]));
+      }
+      a.A0[off + m] = s0;
+      a.A1[off + m] = s1;
+    }
+  }
+}
+
+// Transpose of add_channel: coef * weight * (dX, dY) into the class cotangents of one
+// channel, through the fused cotangent table where all three arguments are on the grid.
+__device__ inline void scatter_channel(double2* const dK[4], double2* dKf, double coef, const DGrid& g, double w2,
+                                       double v2, double vp2, const int f2[4], const double2 dX[4],
+                                       const double2 dY[4]) {
+  int iw, iv = 0, ivp = 0;
+  double tw, tv = 0.0, tvp = 0.0;
+  if (!dgrid_locate(g, w2, iw, tw)) return;
+  const bool inv = dgrid_locate(g, v2, iv, tv);
+  const bool invp = dgrid_locate(g, vp2, ivp, tvp);
+  const int n = g.n;
+  for (int s = 0; s < 2; ++s) {
+    const double2* d = s ? dY : dX;
+    for (int cw = 0; cw < 2; ++cw) {
+      const double ww = coef * (cw ? tw : 1.0 - tw);
+      const size_t sw = (size_t)s * n + iw + cw;
+      if (inv && invp && dKf) {
+        for (int c = 0; c < 2; ++c)
+          for (int c2 = 0; c2 < 2; ++c2) {
+            const double wt = ww * (c ? tv : 1.0 - tv) * (c2 ? tvp : 1.0 - tvp);
+            double2* p = dKf + ((sw * n + iv + c) * n + ivp + c2) * 16;
+            for (int e = 0; e < 4; ++e) atomic_c(p + f2[e], cscale(wt, d[e]));
+          }
+        continue;
+      }
+      if (dK[0]) {
+        double2* p = dK[0] + sw * 16;
+        for (int e = 0; e < 4; ++e) atomic_c(p + f2[e], cscale(ww, d[e]));
+      }
+      for (int c = 0; c < 2; ++c) {
+        if (inv && dK[1]) {
+          double2* p = dK[1] + (sw * n + iv + c) * 16;
+          const double wt = ww * (c ? tv : 1.0 - tv);
+          for (int e = 0; e < 4; ++e) atomic_c(p + f2[e], cscale(wt, d[e]));
+        }
+        if (invp && dK[2]) {
+          double2* p = dK[2] + (sw * n + ivp + c) * 16;
+          const double wt = ww * (c ? tvp : 1.0 - tvp);
+          for (int e = 0; e < 4; ++e) atomic_c(p + f2[e], cscale(wt, d[e]));
+        }
+        if (inv && invp && dK[3])
+          for (int c2 = 0; c2 < 2; ++c2) {
+            double2* p = dK[3] + ((sw * n + iv + c) * n + ivp + c2) * 16;
+            const double wt = ww * (c ? tv : 1.0 - tv) * (c2 ? tvp : 1.0 - tvp);
+            for (int e = 0; e < 4; ++e) atomic_c(p + f2[e], cscale(wt, d[e]));
+          }
+      }
+    }
+  }
+}
+
+__device__ inline void scatter_others(const AdjScatterArgs& a, double w, double v, double vp, int mode, int rc,
+                                      const double2 dX[4], const double2 dY[4]) {
+  double L[4];
+  legs_of(a.r, w, v, vp, L);
+  for (int d = 1; d < 3; ++d) {
+    const int r2 = (a.r + d) % 3;
+    if (a.V.ch[r2].coef == 0.0) continue;
+    double w2, v2, vp2;
+    params_of(r2, L, w2, v2, vp2);
+    int f2[4];
+    for (int e = 0; e < 4; ++e) f2[e] = c_perm[a.r][r2][mode == 0 ? 4 * rc + e : 4 * e + rc];
+    scatter_channel(a.dK[r2], a.dKf[r2], a.V.ch[r2].coef, a.V.g, w2, v2, vp2, f2, dX, dY);
+  }
+}
+
+// Sum over the 64 slots (lane bits 2..5 and the four waves) of per-thread partials that
+// share the lane's row (or column) index; returns the sums in the threads 0..3.
+__device__ inline void reduce_slots(double2 x[8], double& r, double2 (*red)[4][8], double* redr) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+#pragma unroll
+    for (int o = 4; o < 64; o <<= 1) {
+      x[q].x += __shfl_xor(x[q].x, o);
+      x[q].y += __shfl_xor(x[q].y, o);
+    }
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) r += __shfl_xor(r, o);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane < 4)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) red[wave][lane][q] = x[q];
+  if (lane == 0) redr[wave] = r;
+  __syncthreads();
+  if (threadIdx.x < 4) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      x[q] = czero();
+      for (int wv = 0; wv < 4; ++wv) x[q] = cadd(x[q], red[wv][threadIdx.x][q]);
+    }
+    r = redr[0] + redr[1] + redr[2] + redr[3];
+  }
+}
+
+// Left side: block (i, batch), threads = 64 quadrature slots x 4 pair rows.
+__global__ __launch_bounds__(256) void adj_left_kernel(AdjScatterArgs a) {
+  __shared__ double2 red[4][4][8];
+  __shared__ double redr[4];
+  const int i = blockIdx.x, b = blockIdx.y;
+  const int row = threadIdx.x & 3, slot = threadIdx.x >> 2;
+  const int n = a.V.g.n, iw = a.iw0 + b;
+  const size_t M = 4 * (size_t)(n + 1);
+  const double w = a.nodes[iw];
+  const DChan& own = a.V.ch[a.r];
+  const double co = own.coef;
+  double2* const* dKo = a.dK[a.r];
+  double2 acc[8];  // own K2 (i < n) or own K1 (i = n) cotangent partials, X then Y
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = czero();
+  double accr = 0.0;
+  for (int k = slot; k < a.nq; k += 64) {
+    const size_t off = ((size_t)b * M + 4 * (size_t)i + row) * a.Kp + 4 * (size_t)k;
+    const double2* pk = a.pi + ((size_t)b * a.nq + k) * 16;
+    double2 dX[4], dY[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double2 l0 = czero(), l1 = czero();
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const double2 cp = cconj(pk[4 * q + m]);
+        l0 = cadd(l0, cmul(cconj(a.G0[off + m]), cp));
+        l1 = cadd(l1, cmul(cconj(a.G1[off + m]), cp));
+      }
+      dX[q] = make_double2(a.mix[0] * l0.x + a.mix[2] * l1.x, a.mix[0] * l0.y + a.mix[2] * l1.y);
+      dY[q] = make_double2(a.mix[1] * l0.x + a.mix[3] * l1.x, a.mix[1] * l0.y + a.mix[3] * l1.y);
+    }
+    const double vq = a.qv[k];
+    if (i < n) {
+      if (co != 0.0) {
+        if (dKo[1])
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            acc[e] = cfma(co, dX[e], acc[e]);
+            acc[4 + e] = cfma(co, dY[e], acc[4 + e]);
+          }
+        int j0;
+        double t;
+        if (dKo[3] && dgrid_locate(a.V.g, vq, j0, t))
+          for (int s = 0; s < 2; ++s) {
+            double2* p = dKo[3] + ((((size_t)s * n + iw) * n + i) * n + j0) * 16 + 4 * row;
+            const double2* d = s ? dY : dX;
+            for (int e = 0; e < 4; ++e) {
+              atomic_c(p + e, cscale(co * (1.0 - t), d[e]));
+              atomic_c(p + 16 + e, cscale(co * t, d[e]));
+            }
+          }
+      }
+      scatter_others(a, w, a.nodes[i], vq, 0, row, dX, dY);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (bare_odd(4 * row + e)) accr += -0.5 * dX[e].x + 0.5 * dY[e].x;
+      if (co != 0.0) {
+        if (dKo[0])
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            acc[e] = cfma(co, dX[e], acc[e]);
+            acc[4 + e] = cfma(co, dY[e], acc[4 + e]);
+          }
+        int j0;
+        double t;
+        if (dKo[2] && dgrid_locate(a.V.g, vq, j0, t))
+          for (int s = 0; s < 2; ++s) {
+            double2* p = dKo[2] + (((size_t)s * n + iw) * n + j0) * 16 + 4 * row;
+            const double2* d = s ? dY : dX;
+            for (int e = 0; e < 4; ++e) {
+              atomic_c(p + e, cscale(co * (1.0 - t), d[e]));
+              atomic_c(p + 16 + e, cscale(co * t, d[e]));
+            }
+          }
+      }
+    }
+  }
+  reduce_slots(acc, accr, red, redr);
+  if (threadIdx.x < 4) {
+    const int rw = threadIdx.x;
+    double2* tgt = nullptr;
+    size_t base = 0, sstride = 0;
+    if (i < n && dKo[1]) {
+      tgt = dKo[1];
+      base = (((size_t)iw) * n + i) * 16;
+      sstride = (size_t)n * n * 16;
+    } else if (i == n && dKo[0]) {
+      tgt = dKo[0];
+      base = (size_t)iw * 16;
+      sstride = (size_t)n * 16;
+    }
+    if (tgt && co != 0.0)
+      for (int e = 0; e < 4; ++e) {
+        atomic_c(tgt + base + 4 * rw + e, acc[e]);
+        atomic_c(tgt + sstride + base + 4 * rw + e, acc[4 + e]);
+      }
+    if (rw == 0 && i == n && a.dr0) atomicAdd(a.dr0, accr);
+  }
+}
+
+// Right side: block (j, batch), threads = 64 quadrature slots x 4 pair columns.
+__global__ __launch_bounds__(256) void adj_right_kernel(AdjScatterArgs a) {
+  __shared__ double2 red[4][4][8];
+  __shared__ double redr[4];
+  const int j = blockIdx.x, b = blockIdx.y;
+  const int col = threadIdx.x & 3, slot = threadIdx.x >> 2;
+  const int n = a.V.g.n, iw = a.iw0 + b;
+  const size_t M = 4 * (size_t)(n + 1);
+  const double w = a.nodes[iw];
+  const DChan& own = a.V.ch[a.r];
+  const double co = own.coef;
+  double2* const* dKo = a.dK[a.r];
+  double2 acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = czero();
+  double accr = 0.0;
+  for (int k = slot; k < a.nq; k += 64) {
+    const size_t off = ((size_t)b * M + 4 * (size_t)j + col) * a.Kp + 4 * (size_t)k;
+    double2 dX[4], dY[4];  // cotangents of R[m][col], m = 0..3
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const double2 g0 = cconj(a.G0[off + m]), g1 = cconj(a.G1[off + m]);
+      dX[m] = make_double2(a.mix[0] * g0.x + a.mix[2] * g1.x, a.mix[0] * g0.y + a.mix[2] * g1.y);
+      dY[m] = make_double2(a.mix[1] * g0.x + a.mix[3] * g1.x, a.mix[1] * g0.y + a.mix[3] * g1.y);
+    }
+    const double vq = a.qv[k];
+    if (j < n) {
+      if (co != 0.0) {
+        if (dKo[2])
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            acc[e] = cfma(co, dX[e], acc[e]);
+            acc[4 + e] = cfma(co, dY[e], acc[4 + e]);
+          }
+        int i0;
+        double t;
+        if (dKo[3] && dgrid_locate(a.V.g, vq, i0, t))
+          for (int s = 0; s < 2; ++s) {
+            double2* p = dKo[3] + ((((size_t)s * n + iw) * n + i0) * n + j) * 16 + col;
+            const size_t step = (size_t)n * 16;
+            const double2* d = s ? dY : dX;
+            for (int e = 0; e < 4; ++e) {
+              atomic_c(p + 4 * e, cscale(co * (1.0 - t), d[e]));
+              atomic_c(p + step + 4 * e, cscale(co * t, d[e]));
+            }
+          }
+      }
+      scatter_others(a, w, vq, a.nodes[j], 1, col, dX, dY);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (bare_odd(4 * e + col)) accr += -0.5 * dX[e].x + 0.5 * dY[e].x;
+      if (co != 0.0) {
+        if (dKo[0])
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            acc[e] = cfma(co, dX[e], acc[e]);
+            acc[4 + e] = cfma(co, dY[e], acc[4 + e]);
+          }
+        int i0;
+        double t;
+        if (dKo[1] && dgrid_locate(a.V.g, vq, i0, t))
+          for (int s = 0; s < 2; ++s) {
+            double2* p = dKo[1] + (((size_t)s * n + iw) * n + i0) * 16 + col;
+            const double2* d = s ? dY : dX;
+            for (int e = 0; e < 4; ++e) {
+              atomic_c(p + 4 * e, cscale(co * (1.0 - t), d[e]));
+              atomic_c(p + 16 + 4 * e, cscale(co * t, d[e]));
+            }
+          }
+      }
+    }
+  }
+  reduce_slots(acc, accr, red, redr);
+  if (threadIdx.x < 4) {
+    const int cl = threadIdx.x;
+    double2* tgt = nullptr;
+    size_t base = 0, sstride = 0;
+    if (j < n && dKo[2]) {
+      tgt = dKo[2];
+      base = (((size_t)iw) * n + j) * 16;
+      sstride = (size_t)n * n * 16;
+    } else if (j == n && dKo[0]) {
+      tgt = dKo[0];
+      base = (size_t)iw * 16;
+      sstride = (size_t)n * 16;
+    }
+    if (tgt && co != 0.0)
+      for (int e = 0; e < 4; ++e) {
+        atomic_c(tgt + base + 4 * e + cl, acc[e]);
+        atomic_c(tgt + sstride + base + 4 * e + cl, acc[4 + e]);
+      }
+    if (cl == 0 && j == n && a.dr0) atomicAdd(a.dr0, accr);
+  }
+}
+
+// dPi_k[q][m] = sum_c sum_rows conj(L_c[row][(k,q)]) dA_c[row][(k,m)], then
+// dDelta += Re sum conj(dPi_k/dDelta) dPi_k with dPi_k/dDelta by the product rule.
+__global__ __launch_bounds__(256) void dpi_kernel(DPiArgs a) {
+  __shared__ double2 red[4][16];
+  const int k = blockIdx.x, b = blockIdx.y;
+  const long M = 4L * (a.n + 1);
+  double2 acc[16];
+#pragma unroll
+  for (int f = 0; f < 16; ++f) acc[f] = czero();
+  for (long R = threadIdx.x; R < M; R += blockDim.x) {
+    const size_t off = ((size_t)b * M + R) * a.Kp + 4 * (size_t)k;
+    double2 l0[4], l1[4], g0[4], g1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      l0[q] = cconj(a.L0[off + q]);
+      l1[q] = cconj(a.L1[off + q]);
+      g0[q] = cconj(a.G0[off + q]);
+      g1[q] = cconj(a.G1[off + q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) acc[4 * q + m] = cadd(acc[4 * q + m], cadd(cmul(l0[q], g0[m]), cmul(l1[q], g1[m])));
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int f = 0; f < 16; ++f) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      acc[f].x += __shfl_xor(acc[f].x, o);
+      acc[f].y += __shfl_xor(acc[f].y, o);
+    }
+    if (lane == 0) red[wave][f] = acc[f];
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double2 dpi[16];
+  for (int f = 0; f < 16; ++f) dpi[f] = cadd(cadd(red[0][f], red[1][f]), cadd(red[2][f], red[3][f]));
+  const double w = a.wnodes[a.iw0 + b], vq = a.qv[k];
+  double f3, f4;
+  if (a.r == 1) {
+    f3 = 0.5 * w + vq;
+    f4 = 0.5 * w - vq;
+  } else {
+    f3 = vq + 0.5 * w;
+    f4 = vq - 0.5 * w;
+  }
+  double2 G3[4], S3[4], G4[4], S4[4], dS3[4], dS4[4];
+  propagator_dDelta(a.P, 0, f3, G3, S3);
+  propagator_dDelta(a.P, 0, f4, G4, S4);
+  if (a.kind == 1) {
+    double2 t3[4], t4[4];
+    propagator_dDelta(a.P, 1, f3, t3, dS3);
+    propagator_dDelta(a.P, 1, f4, t4, dS4);
+  }
+  const double2 wgt = make_double2(0.0, -a.qw[k] * (0.5 / M_PI));
+  double sum = 0.0;
+  for (int a3 = 0; a3 < 2; ++a3)
+    for (int a3p = 0; a3p < 2; ++a3p)
+      for (int a4 = 0; a4 < 2; ++a4)
+        for (int a4p = 0; a4p < 2; ++a4p) {
+          int rp, cp;
+          pi_index(a.r, a3, a3p, a4, a4p, rp, cp);
+          const int x = 2 * a3 + a3p, y = 2 * a4 + a4p;
+          double2 d;
+          if (a.kind == 0)
+            d = cadd(cmul(S3[x], G4[y]), cmul(G3[x], S4[y]));
+          else
+            d = cadd(cadd(cmul(dS3[x], G4[y]), cscale(2.0, cmul(S3[x], S4[y]))), cmul(G3[x], dS4[y]));
+          d = cmul(wgt, d);
+          const double2 g = dpi[4 * rp + cp];
+          sum += d.x * g.x + d.y * g.y;  // Re(conj(d) g)
+        }
+  atomicAdd(a.dDelta, sum);
+}
+
+__global__ __launch_bounds__(256) void unfuse_kernel(UnfuseArgs a, int cls) {
+  const size_t n = a.n;
+  size_t total;
+  if (cls == 3) total = 2 * n * n * n * 16;
+  else if (cls == 0) total = 2 * n * 16;
+  else total = 2 * n * n * 16;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t f = e & 15;
+    if (cls == 3) {
+      a.dK3[e] = cadd(a.dK3[e], a.dKf[e]);
+      continue;
+    }
+    double2 s = czero();
+    if (cls == 0) {  // K1[s][w]: sum over v, v'
+      const size_t sw = e >> 4;
+      for (size_t v = 0; v < n; ++v)
+        for (size_t vp = 0; vp < n; ++vp) s = cadd(s, a.dKf[((sw * n + v) * n + vp) * 16 + f]);
+      a.dK1[e] = cadd(a.dK1[e], s);
+    } else if (cls == 1) {  // K2[s][w][v]: sum over v'
+      const size_t swv = e >> 4;
+      for (size_t vp = 0; vp < n; ++vp) s = cadd(s, a.dKf[(swv * n + vp) * 16 + f]);
+      a.dK2[e] = cadd(a.dK2[e], s);
+    } else {  // K2'[s][w][v']: sum over v
+      const size_t vp = (e >> 4) % n, sw = (e >> 4) / n;
+      for (size_t v = 0; v < n; ++v) s = cadd(s, a.dKf[((sw * n + v) * n + vp) * 16 + f]);
+      a.dK2p[e] = cadd(a.dK2p[e], s);
+    }
+  }
+}
+
+
+// Transpose of loop_kernel.  With M = 2 Phi^X + Phi^Y and c = 2 a1' + a1:
+//   dM[f(a1',a2',a1,a2)] = conj(wgt G^{a2|a2'}) dSigma[c],  dPhi^X = 2 dM, dPhi^Y = dM,
+//   dG^{a2|a2'} = sum_c conj(wgt M[f]) dSigma[c],  dDelta += Re conj(S^{a2|a2'}) dG.
+__global__ __launch_bounds__(256) void loop_adjoint_kernel(LoopAdjArgs a) {
+  const int i = blockIdx.x;
+  const int n = a.g.n;
+  const double v = a.nodes[i];
+  double2 ds[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) ds[c] = a.dsig[(size_t)i * 4 + c];
+  double dD = 0.0;
+  for (int jq = threadIdx.x; jq < a.nq; jq += blockDim.x) {
+    const double vq = a.qv[jq];
+    int iw;
+    double tw;
+    if (!dgrid_locate(a.g, v - vq, iw, tw)) continue;
+    int ip = 0;
+    double tp = 0.0;
+    const bool inp = dgrid_locate(a.g, 0.5 * (v + vq), ip, tp);
+    double2 Gm[4], Sm[4];
+    propagator_dDelta(a.P, 0, vq, Gm, Sm);
+    const double2 wgt = make_double2(0.0, 0.5 * a.qw[jq] * (0.5 / M_PI));
+    // Phi at the point (for dG) and dM
+    double2 Mx[16], dM[16];
+#pragma unroll
+    for (int f = 0; f < 16; ++f) Mx[f] = czero();
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const double sw = s ? 1.0 : 2.0;
+#pragma unroll
+      for (int cw = 0; cw < 2; ++cw) {
+        const double ww = sw * (cw ? tw : 1.0 - tw);
+        if (a.K1) {
+          const double2* p = a.K1 + ((size_t)s * n + iw + cw) * 16;
+#pragma unroll
+          for (int f = 0; f < 16; ++f) Mx[f] = cfma(ww, p[f], Mx[f]);
+        }
+        if (inp && a.K2p)
+#pragma unroll
+          for (int c2 = 0; c2 < 2; ++c2) {
+            const double2* p = a.K2p + (((size_t)s * n + iw + cw) * n + ip + c2) * 16;
+            const double wv = ww * (c2 ? tp : 1.0 - tp);
+#pragma unroll
+            for (int f = 0; f < 16; ++f) Mx[f] = cfma(wv, p[f], Mx[f]);
+          }
+      }
+    }
+#pragma unroll
+    for (int a1p = 0; a1p < 2; ++a1p)
+#pragma unroll
+      for (int a1 = 0; a1 < 2; ++a1)
+#pragma unroll
+        for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+          for (int a2p = 0; a2p < 2; ++a2p) {
+            const int f = 4 * (2 * a1p + a2) + (2 * a1 + a2p);
+            const double2 d = ds[2 * a1p + a1];
+            dM[f] = cmul(cconj(cmul(wgt, Gm[2 * a2 + a2p])), d);
+            const double2 dg = cmul(cconj(cmul(wgt, Mx[f])), d);
+            dD += Sm[2 * a2 + a2p].x * dg.x + Sm[2 * a2 + a2p].y * dg.y;
+          }
+    for (int s = 0; s < 2; ++s) {
+      const double sw = s ? 1.0 : 2.0;
+      for (int cw = 0; cw < 2; ++cw) {
+        const double ww = sw * (cw ? tw : 1.0 - tw);
+        if (a.dK1) {
+          double2* p = a.dK1 + ((size_t)s * n + iw + cw) * 16;
+          for (int f = 0; f < 16; ++f) atomic_c(p + f, cscale(ww, dM[f]));
+        }
+        if (inp && a.dK2p)
+          for (int c2 = 0; c2 < 2; ++c2) {
+            double2* p = a.dK2p + (((size_t)s * n + iw + cw) * n + ip + c2) * 16;
+            const double wv = ww * (c2 ? tp : 1.0 - tp);
+            for (int f = 0; f < 16; ++f) atomic_c(p + f, cscale(wv, dM[f]));
+          }
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) dD += __shfl_xor(dD, o);
+  if ((threadIdx.x & 63) == 0) atomicAdd(a.dDelta, dD);
+}
+
 // ======================================================================== launchers
 static inline unsigned blocks_for(long threads, int bs) { return (unsigned)((threads + bs - 1) / bs); }
 
@@ -976,6 +1557,30 @@ void launch_chi(const ChiArgs& a, hipStream_t s) {
   const int nblk = (int)blocks_for((long)a.nq * 4, 256);
   hipLaunchKernelGGL(chi_kernel, dim3(nblk, a.nb), dim3(256), 0, s, a);
   hipLaunchKernelGGL(chi_finalize_kernel, dim3(a.nb), dim3(64), 0, s, a, nblk);
+}
+void launch_loop_adjoint(const LoopAdjArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(loop_adjoint_kernel, dim3(a.g.n), dim3(256), 0, s, a);
+}
+void launch_dpanel(const DPanelArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(dpanel_kernel, dim3(4096), dim3(256), 0, s, a);
+}
+void launch_apply_pi(const ApplyPiArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(apply_pi_kernel, dim3(4096), dim3(256), 0, s, a);
+}
+void launch_adj_left(const AdjScatterArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(adj_left_kernel, dim3(a.V.g.n + 1, a.nb), dim3(256), 0, s, a);
+}
+void launch_adj_right(const AdjScatterArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(adj_right_kernel, dim3(a.V.g.n + 1, a.nb), dim3(256), 0, s, a);
+}
+void launch_dpi(const DPiArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(dpi_kernel, dim3(a.nq, a.nb), dim3(256), 0, s, a);
+}
+void launch_unfuse(const UnfuseArgs& a, hipStream_t s) {
+  if (a.dK3) hipLaunchKernelGGL(unfuse_kernel, dim3(4096), dim3(256), 0, s, a, 3);
+  if (a.dK2) hipLaunchKernelGGL(unfuse_kernel, dim3(1024), dim3(256), 0, s, a, 1);
+  if (a.dK2p) hipLaunchKernelGGL(unfuse_kernel, dim3(1024), dim3(256), 0, s, a, 2);
+  if (a.dK1) hipLaunchKernelGGL(unfuse_kernel, dim3(64), dim3(256), 0, s, a, 0);
 }
 int chi_blocks(int nq) { return (int)blocks_for((long)nq * 4, 256); }
 

@@ -75,6 +75,86 @@ struct FuseArgs {
   void* out;  // double2 or float2 table
 };
 
+// ------------------------------------------------------------------ adjoint
+// cotangent panel D'_c[(i,row),(j,col)] = conj(dP_c), dP_c from the class cotangents
+struct DPanelArgs {
+  int n, nb, iw0;
+  double unmix[4];
+  const double2* dK1;
+  const double2* dK2;
+  const double2* dK2p;
+  const double2* dK3;
+  double2* D0;
+  double2* D1;
+};
+// A = L . Pi from a raw left panel
+struct ApplyPiArgs {
+  int n, nb, nq, nq_pad;
+  long Kp;
+  const double2* pi;
+  const double2* L0;
+  const double2* L1;
+  double2* A0;
+  double2* A1;
+};
+struct AdjScatterArgs {
+  int r, nb, iw0, nq;
+  long Kp;
+  DVert V;
+  const double* nodes;
+  const double* qv;
+  const double2* pi;      // left side only: Pi * w/(2 pi i)
+  const double2* G0;      // conj(dA_c) (left) or conj(dB_c) (right) panels
+  const double2* G1;
+  double mix[4];
+  double2* dK[3][4];      // class cotangent targets of this side (NULL = not requested)
+  double2* dKf[3];        // fused cotangent tables of the other channels (NULL = per class)
+  double* dr0;            // cotangent of this side's r0
+};
+struct DPiArgs {
+  int r, kind, nb, nq, iw0, n;
+  long Kp;
+  DProp P;
+  const double* wnodes;
+  const double* qv;
+  const double* qw;
+  const double2* L0;  // raw left panels
+  const double2* L1;
+  const double2* G0;  // conj(dA_c) panels
+  const double2* G1;
+  double* dDelta;
+};
+struct UnfuseArgs {
+  int n;
+  const double2* dKf;
+  double2* dK1;
+  double2* dK2;
+  double2* dK2p;
+  double2* dK3;
+};
+// loop adjoint: dSigma -> cotangents of Phi's K1/K2' (atomics) and dDelta
+struct LoopAdjArgs {
+  DGrid g;
+  DProp P;
+  int nq;
+  const double* nodes;
+  const double* qv;
+  const double* qw;
+  const double2* K1;   // Phi
+  const double2* K2p;
+  const double2* dsig; // [n][4]
+  double2* dK1;
+  double2* dK2p;
+  double* dDelta;
+};
+void launch_loop_adjoint(const LoopAdjArgs& a, hipStream_t s);
+void launch_dpanel(const DPanelArgs& a, hipStream_t s);
+void launch_apply_pi(const ApplyPiArgs& a, hipStream_t s);
+void launch_adj_left(const AdjScatterArgs& a, hipStream_t s);
+void launch_adj_right(const AdjScatterArgs& a, hipStream_t s);
+void launch_dpi(const DPiArgs& a, hipStream_t s);
+void launch_unfuse(const UnfuseArgs& a, hipStream_t s);
+
 hipError_t upload_perm(const int* host_perm);
 void launch_fuse(const FuseArgs& a, bool f32, hipStream_t s);
 void launch_pi(const PiArgs& a, hipStream_t s);

@@ -78,6 +78,8 @@ def lib():
                                   P(KqftOpts), C.c_void_p, C.c_void_p, C.c_void_p]
         _lib.kqft_mloop_step.argtypes = [C.c_void_p, C.c_int, P(KqftVertex), P(KqftPropagator), P(KqftQuad), C.c_int,
                                          P(KqftOpts), P(KqftChout), C.c_void_p]
+        _lib.kqft_sde_adjoint.argtypes = [C.c_void_p, P(KqftVertex), P(KqftPropagator), P(KqftQuad), P(KqftQuad),
+                                          P(KqftOpts), C.c_void_p, P(KqftChout), C.c_void_p, C.c_void_p]
         _lib.kqft_bubble_adjoint.argtypes = [C.c_void_p, C.c_int, P(KqftVertex), P(KqftVertex), P(KqftPropagator),
                                              C.c_int, P(KqftQuad), P(KqftOpts), P(KqftChout), P(KqftChout),
                                              P(KqftChout), C.c_void_p, C.c_void_p]
@@ -87,7 +89,7 @@ def lib():
 def exported_symbols() -> list:
     names = ["kqft_ctx_create", "kqft_ctx_destroy", "kqft_last_error", "kqft_ctx_profile", "kqft_ctx_profile_read",
              "kqft_bubble_workspace", "kqft_bubble",
-             "kqft_sde", "kqft_mloop_step", "kqft_bubble_adjoint"]
+             "kqft_sde", "kqft_mloop_step", "kqft_bubble_adjoint", "kqft_sde_adjoint"]
     L = lib()
     return [n for n in names if hasattr(L, n)]
 
@@ -221,6 +223,12 @@ def _chout(chn: Channel, n: int) -> KqftChout:
     return KqftChout(*[_ptr(getattr(chn, c), class_shape(c, n), f"out.{c}") for c in CLASSES])
 
 
+def _chout_opt(chn: Optional[Channel], n: int) -> KqftChout:
+    if chn is None:
+        return KqftChout(None, None, None, None)
+    return _chout(chn, n)
+
+
 # ------------------------------------------------------------------ entry points
 def bubble(channel: int, left: Vertex, right: Vertex, G: Propagator, q: Quad, pi_kind: int = PI_GG,
            precision: int = FP64, class_mask: int = KALL, beta: int = 0, omega_batch: int = 0,
@@ -272,11 +280,27 @@ def bubble_adjoint(channel: int, left: Vertex, right: Vertex, G: Propagator, q: 
     n = left.grid.n
     dev = torch.device("cuda", torch.cuda.current_device())
     dscal = torch.zeros(3, dtype=torch.float64, device=dev)
-    empty = KqftChout(None, None, None, None)
-    DL = (KqftChout * 3)(*[(_chout(d, n) if d is not None else empty) for d in (dleft or [None] * 3)])
-    DR = (KqftChout * 3)(*[(_chout(d, n) if d is not None else empty) for d in (dright or [None] * 3)])
+    DL = (KqftChout * 3)(*[_chout_opt(d, n) for d in (dleft or [None] * 3)])
+    DR = (KqftChout * 3)(*[_chout_opt(d, n) for d in (dright or [None] * 3)])
     lc, rc, gc, qc, oc = left.c(), right.c(), G.c(), q.c(), _chout(dout, n)
     _check(lib().kqft_bubble_adjoint(ctx(), channel, C.byref(lc), C.byref(rc), C.byref(gc), pi_kind, C.byref(qc),
                                      C.byref(_opts(FP64, KALL, 1, omega_batch)), C.byref(oc), DL, DR,
                                      C.c_void_p(dscal.data_ptr()), _stream(stream)))
+    return dscal
+
+
+def sde_adjoint(gamma: Vertex, G: Propagator, q_bubble: Quad, q_loop: Quad, dsigma: torch.Tensor,
+                dgamma: Optional[list] = None, stream=None):
+    """Accumulates into dgamma[r] (Channels or None) and returns dscal = (d gamma.r0, d G.Delta)."""
+    n = gamma.grid.n
+    dev = torch.device("cuda", torch.cuda.current_device())
+    dscal = torch.zeros(2, dtype=torch.float64, device=dev)
+    empty = KqftChout(None, None, None, None)
+    DG = (KqftChout * 3)(*[(_chout(d, n) if d is not None else empty) for d in (dgamma or [None] * 3)])
+    vc, gc, qb, ql = gamma.c(), G.c(), q_bubble.c(), q_loop.c()
+    ds = dsigma.contiguous()
+    _ptr(ds, (n, 4), "dsigma")
+    _check(lib().kqft_sde_adjoint(ctx(), C.byref(vc), C.byref(gc), C.byref(qb), C.byref(ql),
+                                  C.byref(_opts(FP64, KALL, 0, 0)), C.c_void_p(ds.data_ptr()), DG,
+                                  C.c_void_p(dscal.data_ptr()), _stream(stream)))
     return dscal
