@@ -813,14 +813,19 @@ static void loop_full(const OVert& Gv, const OProp& P, int kind, const OQuad& q,
 // chi_a^c(w) = Pibar + sum_{k,l} Pi_k Gamma_a^c(w; v''_k, v''_l) Pi_l with Pi_k carrying
 // w_k/(2 pi i); c = 0: X, c = 1: D = X + 2Y.  out[c][iw][16].
 template <class S>
-static void chi_full(const OVert& Gv, const OProp& P, const OQuad& q, Cx<S>* out) {
+static void chi_full(const OVert& Gv, const OProp& P, const OQuad& q, Cx<S>* out, int nw = -1,
+                     const int* wlist = nullptr) {
   Vtx<S> V = make_vtx<S>(Gv);
   int n = V.g.n;
   std::vector<double> qv, qw;
   make_quad(q, qv, qw);
   int nq = q.n;
+  // all transfer frequencies, or the listed ones (out then holds [2][nw][16])
+  const int cnt = nw < 0 ? n : nw;
+  const int ostride = nw < 0 ? n : nw;
 #pragma omp parallel for schedule(dynamic)
-  for (int iw = 0; iw < n; ++iw) {
+  for (int ii = 0; ii < cnt; ++ii) {
+    const int iw = wlist ? wlist[ii] : ii;
     double w = grid_node(V.g, iw);
     std::vector<Cx<S>> Pi((size_t)nq * 16);
     for (int k = 0; k < nq; ++k) {
@@ -841,7 +846,7 @@ static void chi_full(const OVert& Gv, const OProp& P, const OQuad& q, Cx<S>* out
           matmul4(M, &Pi[(size_t)l * 16], T);
           for (int f = 0; f < 16; ++f) acc[f] = acc[f] + T[f];
         }
-      for (int f = 0; f < 16; ++f) out[((size_t)c * n + iw) * 16 + f] = acc[f];
+      for (int f = 0; f < 16; ++f) out[((size_t)c * ostride + ii) * 16 + f] = acc[f];
     }
   }
 }
@@ -948,6 +953,11 @@ int oracle_loop(int dual, const OVert* G, const OProp* P, int kind, const OQuad*
     loop_full<Dual>(*G, *P, kind, *q, (Cx<Dual>*)out);
   else
     loop_full<double>(*G, *P, kind, *q, (Cx<double>*)out);
+  return 0;
+}
+
+int oracle_chi_points(const OVert* G, const OProp* P, const OQuad* q, int nw, const int* wlist, double* out) {
+  chi_full<double>(*G, *P, *q, (Cx<double>*)out, nw, wlist);
   return 0;
 }
 

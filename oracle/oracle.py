@@ -86,6 +86,7 @@ def lib():
                                              C.c_double, C.c_double, C.c_double, C.c_void_p]
         _lib.oracle_loop.argtypes = [C.c_int, P(OVert), P(OProp), C.c_int, P(OQuad), C.c_void_p]
         _lib.oracle_chi.argtypes = [C.c_int, P(OVert), P(OProp), P(OQuad), C.c_void_p]
+        _lib.oracle_chi_points.argtypes = [P(OVert), P(OProp), P(OQuad), C.c_int, C.c_void_p, C.c_void_p]
     return _lib
 
 
@@ -290,6 +291,16 @@ def chi(V: Vertex, P: Prop, q: Quad, dual: bool = False) -> np.ndarray:
     keep = []
     vc, pc, qc = V.c(keep), P.c(keep), q.c()
     lib().oracle_chi(int(dual), C.byref(vc), C.byref(pc), C.byref(qc), out.ctypes.data)
+    return out
+
+
+def chi_points(V: Vertex, P: Prop, q: Quad, iws) -> np.ndarray:
+    """chi_a^c at the listed transfer-frequency indices: [2 (X, D), len(iws), 16]."""
+    iws = np.ascontiguousarray(np.atleast_1d(iws), dtype=np.int32)
+    out = np.zeros((2, len(iws), 16), dtype=np.complex128)
+    keep = []
+    vc, pc, qc = V.c(keep), P.c(keep), q.c()
+    lib().oracle_chi_points(C.byref(vc), C.byref(pc), C.byref(qc), len(iws), iws.ctypes.data, out.ctypes.data)
     return out
 
 
