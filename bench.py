@@ -48,6 +48,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["both", "split", "fp64"], default="both")
     ap.add_argument("--serial", action="store_true", help="no gather/GEMM overlap (per-kernel timing)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a device-to-device copy of 1 GiB three times (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the bubble shards over transfer frequencies "
@@ -56,6 +58,17 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_read_bytes": nbytes, "copy_write_bytes": nbytes, "launches": 3}), flush=True)
+        return
 
     from paper_2405_20996_amd import kqft as K
     from workload import seed_noise
