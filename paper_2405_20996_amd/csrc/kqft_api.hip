@@ -37,7 +37,7 @@ struct kqft_ctx {
   int device = 0;
   std::map<std::tuple<int, double, double>, double*> grids;
   std::map<std::tuple<int, int, double, double>, std::pair<double*, double*>> quads;
-  DevBuf panels[2], pi[2], phi, chi_part, lstore[2][3], adj, fused[2][3];
+  DevBuf panels[2], pi[2], phi, chi_part, lstore[2][3], adj, tab[2][2];
   // internal streams (default priority, non-blocking): vertex gathers and GEMMs of
   // consecutive transfer-frequency batches overlap, ordered by events
   hipStream_t sg = nullptr, sm = nullptr;
@@ -197,8 +197,6 @@ static DVert to_dvert(const kqft_vertex& v) {
     d.ch[r].K[1] = (const double2*)v.ch[r].K2;
     d.ch[r].K[2] = (const double2*)v.ch[r].K2p;
     d.ch[r].K[3] = (const double2*)v.ch[r].K3;
-    d.ch[r].Kf = nullptr;
-    d.ch[r].kf32 = 0;
     if (d.ch[r].coef == 0.0)
       for (int c = 0; c < 4; ++c) d.ch[r].K[c] = nullptr;
   }
@@ -269,34 +267,84 @@ static bool same_channel(const kqft_chvert& a, const kqft_chvert& b) {
 
 // Fused K1+K2+K2'+K3 tables of the channels other than r that carry a K3 class; the
 // right side reuses the left side's table when both point at the same arrays.
-static int build_fused(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_vertex& R, DVert& VL, DVert& VR,
-                       bool f32, hipStream_t s) {
-  const int n = L.grid.n;
-  const size_t bytes = (size_t)2 * n * n * n * 16 * (f32 ? sizeof(float2) : sizeof(double2));
+// Tables of the two other channels (r + 1, r + 2) in channel r's Keldysh order, with r's spin
+// combinations and the channel coefficients applied, for each side of the bubble.  The right
+// side shares a left table when its channel is the same (arrays and coefficient).
+struct SideTables {
+  const void* T[2] = {nullptr, nullptr};
+};
+
+static int build_tables(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_vertex& R, bool f32,
+                        SideTables& tl, SideTables& tr, hipStream_t s) {
+  const size_t n = L.grid.n;
+  const size_t bytes = (n * n * n + 2 * n * n + n) * 32 * (f32 ? sizeof(float2) : sizeof(double2));
   const kqft_vertex* side[2] = {&L, &R};
-  DVert* dv[2] = {&VL, &VR};
+  SideTables* out[2] = {&tl, &tr};
   for (int sd = 0; sd < 2; ++sd)
-    for (int r2 = 0; r2 < 3; ++r2) {
-      dv[sd]->ch[r2].Kf = nullptr;
+    for (int d = 0; d < 2; ++d) {
+      const int r2 = (r + 1 + d) % 3;
+      out[sd]->T[d] = nullptr;
       const kqft_chvert& c = side[sd]->ch[r2];
-      if (r2 == r || c.coef == 0.0 || !c.K3) continue;
-      if (sd == 1 && same_channel(L.ch[r2], c) && VL.ch[r2].Kf) {
-        VR.ch[r2].Kf = VL.ch[r2].Kf;
-        VR.ch[r2].kf32 = VL.ch[r2].kf32;
+      if (c.coef == 0.0 || (!c.K1 && !c.K2 && !c.K2p && !c.K3)) continue;
+      if (sd == 1 && same_channel(L.ch[r2], c) && tl.T[d]) {
+        tr.T[d] = tl.T[d];
         continue;
       }
-      int rc = ensure(ctx->fused[sd][r2], bytes);
+      int rc = ensure(ctx->tab[sd][d], bytes);
       if (rc) return rc;
-      FuseArgs fa{n, (const double2*)c.K1, (const double2*)c.K2, (const double2*)c.K2p, (const double2*)c.K3,
-                  ctx->fused[sd][r2].p};
+      TableArgs ta;
+      memset(&ta, 0, sizeof ta);
+      ta.n = (int)n;
+      ta.r = r;
+      ta.r2 = r2;
+      ta.coef = c.coef;
+      for (int u = 0; u < 4; ++u) ta.mix[u] = kMix[r][u];
+      ta.K[0] = (const double2*)c.K1;
+      ta.K[1] = (const double2*)c.K2;
+      ta.K[2] = (const double2*)c.K2p;
+      ta.K[3] = (const double2*)c.K3;
+      ta.out = ctx->tab[sd][d].p;
       {
         ProfScope ps(ctx, 1, s);
-        launch_fuse(fa, f32, s);
+        launch_table(ta, f32, s);
       }
-      dv[sd]->ch[r2].Kf = ctx->fused[sd][r2].p;
-      dv[sd]->ch[r2].kf32 = f32 ? 1 : 0;
+      out[sd]->T[d] = ctx->tab[sd][d].p;
     }
   return KQFT_OK;
+}
+
+static GatherArgs make_gather(int r, int nb, int iw0, int nq, int nq_pad, int lo, int cnt, long Kp,
+                              const kqft_vertex& V, const SideTables& T, const double* nodes, const double* qv,
+                              const double2* pi, void* P0, void* P1) {
+  GatherArgs g;
+  memset(&g, 0, sizeof g);
+  g.r = r;
+  g.nb = nb;
+  g.iw0 = iw0;
+  g.nq = nq;
+  g.nq_pad = nq_pad;
+  g.lo = lo;
+  g.cnt = cnt;
+  g.Kp = Kp;
+  g.g = make_dgrid(V.grid.n, V.grid.L, V.grid.a);
+  g.r0 = V.r0;
+  const kqft_chvert& c = V.ch[r];
+  g.coef = c.coef;
+  if (c.coef != 0.0) {
+    g.K[0] = (const double2*)c.K1;
+    g.K[1] = (const double2*)c.K2;
+    g.K[2] = (const double2*)c.K2p;
+    g.K[3] = (const double2*)c.K3;
+  }
+  g.T[0] = T.T[0];
+  g.T[1] = T.T[1];
+  for (int u = 0; u < 4; ++u) g.mix[u] = kMix[r][u];
+  g.nodes = nodes;
+  g.qv = qv;
+  g.pi = pi;
+  g.P0 = P0;
+  g.P1 = P1;
+  return g;
 }
 
 static int bubble_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_vertex& R, const kqft_propagator& G,
@@ -331,7 +379,7 @@ static int bubble_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_ve
     if ((rc = ensure(ctx->panels[x], 4 * pbytes * nb))) return rc;
     if ((rc = ensure(ctx->pi[x], (size_t)nb * nq * 256))) return rc;
   }
-  DVert VL = to_dvert(L), VR = to_dvert(R);
+  SideTables TL, TR;
   ctx->next_event = 0;
   hipEvent_t start;
   if ((rc = next_event(ctx, &start))) return rc;
@@ -339,7 +387,7 @@ static int bubble_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_ve
   HIP_TRY(hipStreamWaitEvent(ctx->sg, start, 0));
   HIP_TRY(hipStreamWaitEvent(ctx->sm, start, 0));
   if (main_rows || main_cols)
-    if ((rc = build_fused(ctx, r, L, R, VL, VR, f32, ctx->sg))) return rc;
+    if ((rc = build_tables(ctx, r, L, R, f32, TL, TR, ctx->sg))) return rc;
   std::vector<hipEvent_t> gemm_done;
   int batch = 0;
   for (int iw0 = 0; iw0 < n; iw0 += nb, ++batch) {
@@ -358,14 +406,12 @@ static int bubble_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_ve
       ProfScope ps(ctx, 0, ctx->sg);
       launch_pi(pa, ctx->sg);
     }
-    GatherArgs ga{r, cnt, iw0, nq, nq_pad, ilo, ihi - ilo + 1, Kp, VL, nodes, qv, pib, A0, A1, nullptr, nullptr,
-                  {kMix[r][0], kMix[r][1], kMix[r][2], kMix[r][3]}};
+    GatherArgs ga = make_gather(r, cnt, iw0, nq, nq_pad, ilo, ihi - ilo + 1, Kp, L, TL, nodes, qv, pib, A0, A1);
     {
       ProfScope ps(ctx, 1, ctx->sg);
       launch_gather(ga, true, f32, ctx->sg);
     }
-    GatherArgs gb{r, cnt, iw0, nq, nq_pad, jlo, jhi - jlo + 1, Kp, VR, nodes, qv, nullptr, B0, B1, nullptr, nullptr,
-                  {kMix[r][0], kMix[r][1], kMix[r][2], kMix[r][3]}};
+    GatherArgs gb = make_gather(r, cnt, iw0, nq, nq_pad, jlo, jhi - jlo + 1, Kp, R, TR, nodes, qv, nullptr, B0, B1);
     {
       ProfScope ps(ctx, 1, ctx->sg);
       launch_gather(gb, false, f32, ctx->sg);
@@ -400,7 +446,7 @@ static int bubble_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_ve
     g.K3 = out.K3;
     {
       ProfScope ps(ctx, 2, ctx->sm);
-      launch_gemm(g, o.precision, false, ctx->sm);
+      launch_gemm(g, o.precision, ctx->sm);
     }
     HIP_TRY(hipEventRecord(mdone, ctx->sm));
     gemm_done.push_back(mdone);
@@ -472,7 +518,8 @@ static int adjoint_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_v
   double2* Dp[2] = {(double2*)(w + 10 * pan * nb), (double2*)(w + 10 * pan * nb + dpan * nb)};
   double2* pi = (double2*)(w + 10 * pan * nb + 2 * dpan * nb);
   DVert VL = to_dvert(L), VR = to_dvert(R);
-  if ((rc = build_fused(ctx, r, L, R, VL, VR, false, s))) return rc;
+  SideTables TL, TR;
+  if ((rc = build_tables(ctx, r, L, R, false, TL, TR, s))) return rc;
   // fused cotangent tables of the other channels (zeroed), un-fused into the classes at the end
   const kqft_vertex* side[2] = {&L, &R};
   const kqft_chout* dside[2] = {dleft, dright};
@@ -500,13 +547,11 @@ static int adjoint_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_v
     const int cnt = std::min(nb, n - iw0);
     PiArgs pa{r, kind, cnt, nq, iw0, P, nodes, qv, qw, pi};
     launch_pi(pa, s);
-    GatherArgs ga{r, cnt, iw0, nq, nq_pad, 0, n + 1, Kp, VL, nodes, qv, nullptr, Lr[0], Lr[1], nullptr, nullptr,
-                  {kMix[r][0], kMix[r][1], kMix[r][2], kMix[r][3]}};
+    GatherArgs ga = make_gather(r, cnt, iw0, nq, nq_pad, 0, n + 1, Kp, L, TL, nodes, qv, nullptr, Lr[0], Lr[1]);
     launch_gather(ga, true, false, s);
     ApplyPiArgs ap{n, cnt, nq, nq_pad, Kp, pi, Lr[0], Lr[1], Ap[0], Ap[1]};
     launch_apply_pi(ap, s);
-    GatherArgs gb{r, cnt, iw0, nq, nq_pad, 0, n + 1, Kp, VR, nodes, qv, nullptr, Bp[0], Bp[1], nullptr, nullptr,
-                  {kMix[r][0], kMix[r][1], kMix[r][2], kMix[r][3]}};
+    GatherArgs gb = make_gather(r, cnt, iw0, nq, nq_pad, 0, n + 1, Kp, R, TR, nodes, qv, nullptr, Bp[0], Bp[1]);
     launch_gather(gb, false, false, s);
     DPanelArgs dp{n, cnt, iw0, {kUnmix[r][0], kUnmix[r][1], kUnmix[r][2], kUnmix[r][3]},
                   (const double2*)dout.K1, (const double2*)dout.K2, (const double2*)dout.K2p,
@@ -608,7 +653,7 @@ int kqft_ctx_destroy(kqft_ctx* ctx) {
   for (auto& row : ctx->lstore)
     for (auto& b : row)
       if (b.p) (void)hipFree(b.p);
-  for (auto& row : ctx->fused)
+  for (auto& row : ctx->tab)
     for (auto& b : row)
       if (b.p) (void)hipFree(b.p);
   for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
@@ -657,8 +702,10 @@ size_t kqft_bubble_workspace(int n, int nq, int omega_batch, int precision) {
   const size_t per_w = panel_bytes_per_w(n, nq, precision);
   int nb = omega_batch > 0 ? omega_batch : (int)std::max<size_t>(1, ((size_t)4 << 30) / per_w);
   nb = std::min(nb, n);
-  // two panel buffers, two propagator-pair buffers, up to four fused class tables
-  return 2 * (per_w + (size_t)nq * 256) * nb + (size_t)4 * 2 * n * n * n * 16 * 16;
+  // two panel buffers, two propagator-pair buffers, up to four target-order class tables
+  const size_t nn = n;
+  const size_t table = (nn * nn * nn + 2 * nn * nn + nn) * 32 * (precision == KQFT_SPLIT_FP32 ? 8 : 16);
+  return 2 * (per_w + (size_t)nq * 256) * nb + 4 * table;
 }
 
 int kqft_bubble(kqft_ctx* ctx, int channel, const kqft_vertex* left, const kqft_vertex* right,

@@ -54,13 +54,6 @@ __device__ inline bool dgrid_locate(const DGrid& g, double v, int& i0, double& t
 struct DChan {
   double coef;
   const double2* K[4];  // K1, K2, K2p, K3
-  // optional fused table K1 + K2 + K2' + K3 on the three-dimensional grid ([s][w][v][v'][16]):
-  // where all three arguments lie on the grid, the sum of the classes' multilinear
-  // interpolations equals the trilinear interpolation of this table (a class constant
-  // along an axis interpolates identically in one dimension less).  Stored in FP64, or in
-  // FP32 (kf32 = 1) when the contraction itself runs on FP32 operands.
-  const void* Kf;
-  int kf32;
 };
 struct DVert {
   double r0;

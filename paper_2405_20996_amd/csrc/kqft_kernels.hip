@@ -1,6 +1,7 @@
 // kqft_kernels.hip -- CDNA4 (gfx950) kernels of the Keldysh bubble path.
 //
 //   pi_kernel          Pi_r(w, v''_k) * w_k / (2 pi i) for a batch of transfer frequencies
+//   table_kernel       the other channels' classes in the bubble channel's Keldysh order
 //   gather_left        A panel:  rows (i, row) x cols (k, m) = Gamma_L-part(w, v_i, v''_k) . Pi_k
 //   gather_right       B^T panel: rows (j, col) x cols (k, m) = Gamma_R-part(w, v''_k, v'_j)
 //   zgemm_f64 / _f32   C = A . B per (w, spin combination) on MFMA, bordered epilogue
@@ -74,37 +75,9 @@ __global__ __launch_bounds__(256) void pi_kernel(PiArgs a) {
         }
 }
 
-// ======================================================================== gather
-__device__ inline double2 ld2(const double2* p) { return *p; }
-__device__ inline double2 ld2(const float2* p) {
-  const float2 v = *p;
-  return make_double2((double)v.x, (double)v.y);
-}
-
-// Trilinear interpolation of a fused class table at cell (iw, iv, ivp) with weights t*.
-template <class TT>
-__device__ inline void fused_taps(const TT* Kf, int n, double coef, int iw, double tw, int iv, double tv, int ivp,
-                                  double tvp, const int f2[4], double2 X[4], double2 Y[4]) {
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    double2* acc = s ? Y : X;
-#pragma unroll
-    for (int cw = 0; cw < 2; ++cw) {
-      const double ww = coef * (cw ? tw : 1.0 - tw);
-      const size_t sw = (size_t)s * n + iw + cw;
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const double wv = ww * (c ? tv : 1.0 - tv);
-        const TT* p = Kf + ((sw * n + iv + c) * n + ivp) * 16;
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          acc[e] = cfma(wv * (1.0 - tvp), ld2(p + f2[e]), cfma(wv * tvp, ld2(p + 16 + f2[e]), acc[e]));
-      }
-    }
-  }
-}
-
-// Add coef * gamma_{r2}(w2, v2, vp2) for four flat indices f2[e] (channel r2 order).
+// ======================================================================== vertex evaluation (chi)
+// Add coef * gamma_{r2}(w2, v2, vp2) for four flat indices f2[e] (channel r2 order), each
+// class interpolated multilinearly on the auxiliary variable, zero off the grid.
 __device__ inline void add_channel(const DChan& C, const DGrid& g, double w2, double v2, double vp2, const int f2[4],
                                    double2 X[4], double2 Y[4]) {
   int iw, iv = 0, ivp = 0;
@@ -114,13 +87,6 @@ __device__ inline void add_channel(const DChan& C, const DGrid& g, double w2, do
   bool invp = dgrid_locate(g, vp2, ivp, tvp);
   const int n = g.n;
   const double coef = C.coef;
-  if (inv && invp && C.Kf) {
-    if (C.kf32)
-      fused_taps((const float2*)C.Kf, n, coef, iw, tw, iv, tv, ivp, tvp, f2, X, Y);
-    else
-      fused_taps((const double2*)C.Kf, n, coef, iw, tw, iv, tv, ivp, tvp, f2, X, Y);
-    return;
-  }
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     double2* acc = s ? Y : X;
@@ -181,14 +147,188 @@ __device__ inline void add_others(const DVert& V, int r, double w, double v, dou
   }
 }
 
-// spin combinations that diagonalise the channel's spin sums, c_s = sum_x mix[s][x] (X, Y)_x:
-//   a: (X, X + 2Y)   p: (X + Y, X - Y)   t: (Y, 2X + Y)
-__device__ inline void combos(const double mix[4], const double2 X[4], const double2 Y[4], double2 c0[4],
-                              double2 c1[4]) {
+// ======================================================================== target-order tables
+// For a bubble in channel r every other channel r2 is tabulated once per call in r's
+// Keldysh order, with r's spin combinations and r2's coefficient applied:
+//   rec(f, c) = coef_{r2} * sum_s mix[c][s] * K_{r2, s}[perm_{r -> r2}(f)],
+// one record of 32 values (16 flat indices f x 2 combinations c) per grid cell, for
+//   F3[w][v][v'] = K1 + K2 + K2' + K3   (all three arguments on the grid)
+//   F2v[w][v]    = K1 + K2              (v' off the grid)
+//   F2p[w][v']   = K1 + K2'             (v off the grid)
+//   F1[w]        = K1                   (v and v' off the grid)
+// stored back to back.  Absent classes count as zero.  Inside a record, (f, c) sits where
+// lane l of an 8-lane group finds (f = l, l + 8; c = 0, 1) with 16-byte loads that cover
+// whole cache lines across the group:
+//   FP32 record (256 B): float2 position 2f + c
+//   FP64 record (512 B): double2 position 16 (f / 8) + 8c + f % 8
+__host__ __device__ inline int rec_pos(int f, int c, bool f32) {
+  return f32 ? 2 * f + c : 16 * (f >> 3) + 8 * c + (f & 7);
+}
+__device__ inline void st2(double2* p, double2 v) { *p = v; }
+__device__ inline void st2(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+
+template <class TT> __global__ __launch_bounds__(256) void table_kernel(TableArgs a) {
+  const size_t n = a.n, n2 = n * n, n3 = n2 * n;
+  const size_t total = (n3 + 2 * n2 + n) * 16;
+  const bool f32 = sizeof(TT) == sizeof(float2);
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int f = (int)(e & 15);
+    const size_t rec = e >> 4;
+    size_t w, v = 0, vp = 0;
+    bool has_v = false, has_vp = false;
+    if (rec < n3) {
+      vp = rec % n;
+      v = (rec / n) % n;
+      w = rec / n2;
+      has_v = has_vp = true;
+    } else if (rec < n3 + n2) {
+      v = (rec - n3) % n;
+      w = (rec - n3) / n;
+      has_v = true;
+    } else if (rec < n3 + 2 * n2) {
+      vp = (rec - n3 - n2) % n;
+      w = (rec - n3 - n2) / n;
+      has_vp = true;
+    } else {
+      w = rec - n3 - 2 * n2;
+    }
+    const int pf = c_perm[a.r][a.r2][f];
+    double2 xy[2];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    c0[e] = make_double2(mix[0] * X[e].x + mix[1] * Y[e].x, mix[0] * X[e].y + mix[1] * Y[e].y);
-    c1[e] = make_double2(mix[2] * X[e].x + mix[3] * Y[e].x, mix[2] * X[e].y + mix[3] * Y[e].y);
+    for (int s = 0; s < 2; ++s) {
+      double2 x = czero();
+      const size_t sw = (size_t)s * n + w;
+      if (a.K[0]) x = cadd(x, a.K[0][sw * 16 + pf]);
+      if (has_v && a.K[1]) x = cadd(x, a.K[1][(sw * n + v) * 16 + pf]);
+      if (has_vp && a.K[2]) x = cadd(x, a.K[2][(sw * n + vp) * 16 + pf]);
+      if (has_v && has_vp && a.K[3]) x = cadd(x, a.K[3][((sw * n + v) * n + vp) * 16 + pf]);
+      xy[s] = x;
+    }
+    TT* out = (TT*)a.out + rec * 32;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const double m0 = a.coef * a.mix[2 * c], m1 = a.coef * a.mix[2 * c + 1];
+      st2(out + rec_pos(f, c, f32), make_double2(m0 * xy[0].x + m1 * xy[1].x, m0 * xy[0].y + m1 * xy[1].y));
+    }
+  }
+}
+
+// ======================================================================== gathers
+// One 8-lane group per panel item (transfer frequency w, fermionic index i or j, node k).
+// Lane l accumulates the spin combinations c = 0, 1 of the flat indices f = l and f = l + 8
+// (channel r order): acc = {(l, 0), (l, 1), (l + 8, 0), (l + 8, 1)}.
+
+// one tap of a table record, weight wgt
+__device__ inline void rec_tap(const float2* rec, int l, double wgt, double2 acc[4]) {
+  const float4* p = reinterpret_cast<const float4*>(rec);
+  const float4 u = p[l], v = p[8 + l];
+  acc[0] = make_double2(fma(wgt, (double)u.x, acc[0].x), fma(wgt, (double)u.y, acc[0].y));
+  acc[1] = make_double2(fma(wgt, (double)u.z, acc[1].x), fma(wgt, (double)u.w, acc[1].y));
+  acc[2] = make_double2(fma(wgt, (double)v.x, acc[2].x), fma(wgt, (double)v.y, acc[2].y));
+  acc[3] = make_double2(fma(wgt, (double)v.z, acc[3].x), fma(wgt, (double)v.w, acc[3].y));
+}
+__device__ inline void rec_tap(const double2* rec, int l, double wgt, double2 acc[4]) {
+  acc[0] = cfma(wgt, rec[l], acc[0]);
+  acc[1] = cfma(wgt, rec[8 + l], acc[1]);
+  acc[2] = cfma(wgt, rec[16 + l], acc[2]);
+  acc[3] = cfma(wgt, rec[24 + l], acc[3]);
+}
+
+// Other channel from its tables at cell (iw, iv, ivp) with weights (tw, tv, tvp); an index
+// of -1 marks an argument off the grid.
+template <class TT>
+__device__ inline void table_taps(const TT* T, int n, int iw, double tw, int iv, double tv, int ivp, double tvp,
+                                  int l, double2 acc[4]) {
+  if (iw < 0) return;
+  const size_t nn = n, n2 = nn * nn, n3 = n2 * nn;
+#pragma unroll
+  for (int cw = 0; cw < 2; ++cw) {
+    const double ww = cw ? tw : 1.0 - tw;
+    const size_t w = (size_t)iw + cw;
+    if (iv >= 0 && ivp >= 0) {
+#pragma unroll
+      for (int cv = 0; cv < 2; ++cv)
+#pragma unroll
+        for (int cp = 0; cp < 2; ++cp)
+          rec_tap(T + ((w * nn + iv + cv) * nn + ivp + cp) * 32, l,
+                  ww * (cv ? tv : 1.0 - tv) * (cp ? tvp : 1.0 - tvp), acc);
+    } else if (iv >= 0) {
+#pragma unroll
+      for (int cv = 0; cv < 2; ++cv) rec_tap(T + (n3 + w * nn + iv + cv) * 32, l, ww * (cv ? tv : 1.0 - tv), acc);
+    } else if (ivp >= 0) {
+#pragma unroll
+      for (int cp = 0; cp < 2; ++cp)
+        rec_tap(T + (n3 + n2 + w * nn + ivp + cp) * 32, l, ww * (cp ? tvp : 1.0 - tvp), acc);
+    } else {
+      rec_tap(T + (n3 + 2 * n2 + w) * 32, l, ww, acc);
+    }
+  }
+}
+
+// Own-channel class entry (channel order, both spins) for f = l, l + 8:
+// xy = {X(l), X(l + 8), Y(l), Y(l + 8)} += wgt * entry; sstride = spin stride in double2.
+__device__ inline void own_tap(const double2* p, size_t sstride, int l, double wgt, double2 xy[4]) {
+  xy[0] = cfma(wgt, p[l], xy[0]);
+  xy[1] = cfma(wgt, p[8 + l], xy[1]);
+  xy[2] = cfma(wgt, p[sstride + l], xy[2]);
+  xy[3] = cfma(wgt, p[sstride + 8 + l], xy[3]);
+}
+
+// acc += combinations of coef * xy, plus the bare vertex on the border (r0 != 0)
+__device__ inline void own_mix(const GatherArgs& a, int l, double r0, const double2 xy[4], double2 acc[4]) {
+  const double c = a.coef;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int f = l + 8 * h;
+    const double2 X = xy[h], Y = xy[2 + h];
+    const double bare = bare_odd(f) ? 0.5 * r0 : 0.0;  // X_R = -r0/2, Y_R = +r0/2 on odd f
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+      const double m0 = a.mix[2 * cc], m1 = a.mix[2 * cc + 1];
+      acc[2 * h + cc].x += c * (m0 * X.x + m1 * Y.x) + (m1 - m0) * bare;
+      acc[2 * h + cc].y += c * (m0 * X.y + m1 * Y.y);
+    }
+  }
+}
+
+// Seven grid locations per item, one per lane, shared across the 8-lane group:
+// slot 0 = v'' (own channel), slots 1-3 / 4-6 = (w, v, v') of channels r + 1 / r + 2.
+// loc[j] = cell index (-1 off the grid), wt[j] = weight of the upper node.
+__device__ inline void group_locate(const GatherArgs& a, int l, bool others, double w, double v, double vp,
+                                    double vq, int loc[7], double wt[7]) {
+  double arg = vq;
+  if (others && l >= 1 && l <= 6) {
+    double L[4];
+    legs_of(a.r, w, v, vp, L);
+    const int d = l <= 3 ? 1 : 2, which = (l - 1) % 3;
+    double w2, v2, vp2;
+    params_of((a.r + d) % 3, L, w2, v2, vp2);
+    arg = which == 0 ? w2 : (which == 1 ? v2 : vp2);
+  }
+  int ic;
+  double tc;
+  if (!dgrid_locate(a.g, arg, ic, tc)) {
+    ic = -1;
+    tc = 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < 7; ++j) {
+    loc[j] = __shfl(ic, j, 8);
+    wt[j] = __shfl(tc, j, 8);
+  }
+}
+
+template <int Q> __device__ inline double quad_bcast(double v) {
+  constexpr int ctrl = Q | (Q << 2) | (Q << 4) | (Q << 6);  // quad_perm [Q, Q, Q, Q]
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int Q> __device__ inline void pi_step(const double2 acc[4], double2 P, double2 s[4]) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const double2 x = make_double2(quad_bcast<Q>(acc[u].x), quad_bcast<Q>(acc[u].y));
+    s[u] = cadd(s[u], cmul(x, P));
   }
 }
 
@@ -197,224 +337,154 @@ template <> __device__ inline void store_c<double2>(double2* p, double2 v) { *p 
 template <> __device__ inline void store_c<float2>(float2* p, double2 v) {
   *p = make_float2((float)v.x, (float)v.y);
 }
-template <class T> __device__ inline void store_lo(T* p, double2 v);
-template <> __device__ inline void store_lo<double2>(double2*, double2) {}
-template <> __device__ inline void store_lo<float2>(float2* p, double2 v) {
-  if (p) {
-    float hx = (float)v.x, hy = (float)v.y;
-    *p = make_float2((float)(v.x - (double)hx), (float)(v.y - (double)hy));
-  }
-}
 
+// A panel: row (i, row) x column (k, m) = sum_q (Gamma_L - Gamma_L^inf)(w, v_i, v''_k)[row, q]
+// Pi_k[q, m] for i < n, Gamma_L^inf(w, v''_k) Pi_k on the border row block i = n; without
+// Pi (a.pi == nullptr) the raw left factor.  Lane l holds rows l/4 and 2 + l/4, column l%4.
 template <class T> __global__ __launch_bounds__(256) void gather_left_kernel(GatherArgs a) {
   const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int row = (int)(tid & 3);
-  long item = tid >> 2;
+  const int l = (int)(tid & 7);
+  long item = tid >> 3;
   const int k = (int)(item % a.nq_pad);
   item /= a.nq_pad;
   const int il = (int)(item % a.cnt);
   const int b = (int)(item / a.cnt);
-  if (b >= a.nb) return;
-  const int n = a.V.g.n;
-  const int i = a.lo + il;
-  const int iw = a.iw0 + b;
+  if (b >= a.nb) return;  // whole groups: nq_pad, cnt and the block size are multiples of 8
+  const int n = a.g.n, i = a.lo + il, iw = a.iw0 + b, h = l >> 2, q4 = l & 3;
   const size_t M = 4 * (size_t)(n + 1);
-  const size_t off = ((size_t)b * M + 4 * (size_t)i + row) * a.Kp + 4 * (size_t)k;
-  T* o0 = (T*)a.P0 + off;
-  T* o1 = (T*)a.P1 + off;
+  const size_t off0 = ((size_t)b * M + 4 * (size_t)i + h) * a.Kp + 4 * (size_t)k + q4;
+  const size_t off1 = off0 + 2 * a.Kp;
+  T* o0 = (T*)a.P0;
+  T* o1 = (T*)a.P1;
   if (k >= a.nq) {
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      store_c(o0 + m, czero());
-      store_c(o1 + m, czero());
-      if (a.L0) store_lo((T*)a.L0 + off + m, czero());
-      if (a.L1) store_lo((T*)a.L1 + off + m, czero());
-    }
+    store_c(o0 + off0, czero());
+    store_c(o1 + off0, czero());
+    store_c(o0 + off1, czero());
+    store_c(o1 + off1, czero());
     return;
   }
-  const double w = a.nodes[iw];
-  const double vq = a.qv[k];
-  const DChan& own = a.V.ch[a.r];
-  double2 X[4], Y[4];
+  const bool main = i < n;
+  const double w = a.nodes[iw], vq = a.qv[k];
+  int loc[7];
+  double wt[7];
+  group_locate(a, l, main, w, main ? a.nodes[i] : 0.0, vq, vq, loc, wt);
+  double2 acc[4], xy[4];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) X[e] = Y[e] = czero();
-  if (i < n) {  // Gamma_L - Gamma_L^inf : own K2, own K3, other channels
-    const double v = a.nodes[i];
-    if (own.coef != 0.0) {
-      const double c = own.coef;
-      if (own.K[1]) {
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          const double2* p = own.K[1] + (((size_t)s * n + iw) * n + i) * 16 + 4 * row;
-          double2* acc = s ? Y : X;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) acc[e] = cfma(c, p[e], acc[e]);
-        }
+  for (int u = 0; u < 4; ++u) acc[u] = xy[u] = czero();
+  const size_t nn = n, n2 = nn * nn, n3 = n2 * nn;
+  const int j0 = loc[0];
+  const double t = wt[0];
+  if (main) {  // Gamma_L - Gamma_L^inf: own K2(w, v_i) + K3(w, v_i, v''), the other channels
+    if (a.coef != 0.0) {
+      if (a.K[1]) own_tap(a.K[1] + ((size_t)iw * nn + i) * 16, n2 * 16, l, 1.0, xy);
+      if (a.K[3] && j0 >= 0) {
+        const double2* p = a.K[3] + (((size_t)iw * nn + i) * nn + j0) * 16;
+        own_tap(p, n3 * 16, l, 1.0 - t, xy);
+        own_tap(p + 16, n3 * 16, l, t, xy);
       }
-      int j0;
-      double t;
-      if (own.K[3] && dgrid_locate(a.V.g, vq, j0, t)) {
+      own_mix(a, l, 0.0, xy, acc);
+    }
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          const double2* p = own.K[3] + ((((size_t)s * n + iw) * n + i) * n + j0) * 16 + 4 * row;
-          double2* acc = s ? Y : X;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) acc[e] = cfma(c * (1.0 - t), p[e], cfma(c * t, p[16 + e], acc[e]));
-        }
+    for (int d = 0; d < 2; ++d)
+      if (a.T[d])
+        table_taps((const T*)a.T[d], n, loc[1 + 3 * d], wt[1 + 3 * d], loc[2 + 3 * d], wt[2 + 3 * d],
+                   loc[3 + 3 * d], wt[3 + 3 * d], l, acc);
+  } else {  // Gamma_L^inf(w, v'') = R + own K1(w) + K2'(w, v'')
+    if (a.coef != 0.0) {
+      if (a.K[0]) own_tap(a.K[0] + (size_t)iw * 16, nn * 16, l, 1.0, xy);
+      if (a.K[2] && j0 >= 0) {
+        const double2* p = a.K[2] + ((size_t)iw * nn + j0) * 16;
+        own_tap(p, n2 * 16, l, 1.0 - t, xy);
+        own_tap(p + 16, n2 * 16, l, t, xy);
       }
     }
-    add_others(a.V, a.r, w, v, vq, 0, row, X, Y);
-  } else {  // Gamma_L^inf(w, v'') = R + own K1(w) + own K2'(w, v'')
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-      if (bare_odd(4 * row + e)) {
-        X[e].x -= 0.5 * a.V.r0;
-        Y[e].x += 0.5 * a.V.r0;
-      }
-    if (own.coef != 0.0) {
-      const double c = own.coef;
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        double2* acc = s ? Y : X;
-        if (own.K[0]) {
-          const double2* p = own.K[0] + ((size_t)s * n + iw) * 16 + 4 * row;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) acc[e] = cfma(c, p[e], acc[e]);
-        }
-        int j0;
-        double t;
-        if (own.K[2] && dgrid_locate(a.V.g, vq, j0, t)) {
-          const double2* p = own.K[2] + (((size_t)s * n + iw) * n + j0) * 16 + 4 * row;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) acc[e] = cfma(c * (1.0 - t), p[e], cfma(c * t, p[16 + e], acc[e]));
-        }
-      }
-    }
+    own_mix(a, l, a.r0, xy, acc);
   }
-  double2 c0[4], c1[4];
-  combos(a.mix, X, Y, c0, c1);
-  if (a.pi == nullptr) {  // raw left factor, without the propagator pair (adjoint)
+  if (a.pi != nullptr) {  // (Gamma_L . Pi_k)[row, m], m = l % 4, from the quad's four q
+    const double2* pk = a.pi + ((size_t)b * a.nq + k) * 16 + q4;
+    const double2 P0 = pk[0], P1 = pk[4], P2 = pk[8], P3 = pk[12];
+    double2 s[4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      store_c(o0 + m, c0[m]);
-      store_c(o1 + m, c1[m]);
-    }
-    return;
+    for (int u = 0; u < 4; ++u) s[u] = czero();
+    pi_step<0>(acc, P0, s);
+    pi_step<1>(acc, P1, s);
+    pi_step<2>(acc, P2, s);
+    pi_step<3>(acc, P3, s);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = s[u];
   }
-  const double2* pk = a.pi + ((size_t)b * a.nq + k) * 16;
-  double2 P[16];
-#pragma unroll
-  for (int f = 0; f < 16; ++f) P[f] = pk[f];
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    double2 s0 = czero(), s1 = czero();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      s0 = cadd(s0, cmul(c0[q], P[4 * q + m]));
-      s1 = cadd(s1, cmul(c1[q], P[4 * q + m]));
-    }
-    store_c(o0 + m, s0);
-    store_c(o1 + m, s1);
-    if (a.L0) store_lo((T*)a.L0 + off + m, s0);
-    if (a.L1) store_lo((T*)a.L1 + off + m, s1);
-  }
+  store_c(o0 + off0, acc[0]);
+  store_c(o1 + off0, acc[1]);
+  store_c(o0 + off1, acc[2]);
+  store_c(o1 + off1, acc[3]);
 }
 
+// B^T panel: row (j, col) x column (k, e) = (Gamma_R - Gamma_R^inf)(w, v''_k, v'_j)[e, col]
+// for j < n, Gamma_R^inf(w, v''_k)[e, col] on the border block j = n.  Lane l holds
+// column l%4, rows e = l/4 and 2 + l/4.
 template <class T> __global__ __launch_bounds__(256) void gather_right_kernel(GatherArgs a) {
   const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int col = (int)(tid & 3);
-  long item = tid >> 2;
+  const int l = (int)(tid & 7);
+  long item = tid >> 3;
   const int k = (int)(item % a.nq_pad);
   item /= a.nq_pad;
   const int jl = (int)(item % a.cnt);
   const int b = (int)(item / a.cnt);
   if (b >= a.nb) return;
-  const int n = a.V.g.n;
-  const int j = a.lo + jl;
-  const int iw = a.iw0 + b;
+  const int n = a.g.n, j = a.lo + jl, iw = a.iw0 + b, h = l >> 2, q4 = l & 3;
   const size_t Ncol = 4 * (size_t)(n + 1);
-  const size_t off = ((size_t)b * Ncol + 4 * (size_t)j + col) * a.Kp + 4 * (size_t)k;
-  T* o0 = (T*)a.P0 + off;
-  T* o1 = (T*)a.P1 + off;
+  const size_t off0 = ((size_t)b * Ncol + 4 * (size_t)j + q4) * a.Kp + 4 * (size_t)k + h;
+  const size_t off1 = off0 + 2;
+  T* o0 = (T*)a.P0;
+  T* o1 = (T*)a.P1;
   if (k >= a.nq) {
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      store_c(o0 + m, czero());
-      store_c(o1 + m, czero());
-      if (a.L0) store_lo((T*)a.L0 + off + m, czero());
-      if (a.L1) store_lo((T*)a.L1 + off + m, czero());
-    }
+    store_c(o0 + off0, czero());
+    store_c(o1 + off0, czero());
+    store_c(o0 + off1, czero());
+    store_c(o1 + off1, czero());
     return;
   }
-  const double w = a.nodes[iw];
-  const double vq = a.qv[k];
-  const DChan& own = a.V.ch[a.r];
-  double2 X[4], Y[4];
+  const bool main = j < n;
+  const double w = a.nodes[iw], vq = a.qv[k];
+  int loc[7];
+  double wt[7];
+  group_locate(a, l, main, w, vq, main ? a.nodes[j] : 0.0, vq, loc, wt);
+  double2 acc[4], xy[4];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) X[e] = Y[e] = czero();
-  if (j < n) {  // Gamma_R - Gamma_R^inf : own K2', own K3, other channels
-    const double vp = a.nodes[j];
-    if (own.coef != 0.0) {
-      const double c = own.coef;
-      if (own.K[2]) {
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          const double2* p = own.K[2] + (((size_t)s * n + iw) * n + j) * 16 + col;
-          double2* acc = s ? Y : X;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) acc[e] = cfma(c, p[4 * e], acc[e]);
-        }
+  for (int u = 0; u < 4; ++u) acc[u] = xy[u] = czero();
+  const size_t nn = n, n2 = nn * nn, n3 = n2 * nn;
+  const int i0 = loc[0];
+  const double t = wt[0];
+  if (main) {  // Gamma_R - Gamma_R^inf: own K2'(w, v'_j) + K3(w, v'', v'_j), the other channels
+    if (a.coef != 0.0) {
+      if (a.K[2]) own_tap(a.K[2] + ((size_t)iw * nn + j) * 16, n2 * 16, l, 1.0, xy);
+      if (a.K[3] && i0 >= 0) {
+        const double2* p = a.K[3] + (((size_t)iw * nn + i0) * nn + j) * 16;
+        own_tap(p, n3 * 16, l, 1.0 - t, xy);
+        own_tap(p + nn * 16, n3 * 16, l, t, xy);
       }
-      int i0;
-      double t;
-      if (own.K[3] && dgrid_locate(a.V.g, vq, i0, t)) {
+      own_mix(a, l, 0.0, xy, acc);
+    }
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          const double2* p = own.K[3] + ((((size_t)s * n + iw) * n + i0) * n + j) * 16 + col;
-          const size_t step = (size_t)n * 16;
-          double2* acc = s ? Y : X;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) acc[e] = cfma(c * (1.0 - t), p[4 * e], cfma(c * t, p[step + 4 * e], acc[e]));
-        }
+    for (int d = 0; d < 2; ++d)
+      if (a.T[d])
+        table_taps((const T*)a.T[d], n, loc[1 + 3 * d], wt[1 + 3 * d], loc[2 + 3 * d], wt[2 + 3 * d],
+                   loc[3 + 3 * d], wt[3 + 3 * d], l, acc);
+  } else {  // Gamma_R^inf(w, v'') = R + own K1(w) + K2(w, v'')
+    if (a.coef != 0.0) {
+      if (a.K[0]) own_tap(a.K[0] + (size_t)iw * 16, nn * 16, l, 1.0, xy);
+      if (a.K[1] && i0 >= 0) {
+        const double2* p = a.K[1] + ((size_t)iw * nn + i0) * 16;
+        own_tap(p, n2 * 16, l, 1.0 - t, xy);
+        own_tap(p + 16, n2 * 16, l, t, xy);
       }
     }
-    add_others(a.V, a.r, w, vq, vp, 1, col, X, Y);
-  } else {  // Gamma_R^inf(w, v'') = R + own K1(w) + own K2(w, v'')
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-      if (bare_odd(4 * e + col)) {
-        X[e].x -= 0.5 * a.V.r0;
-        Y[e].x += 0.5 * a.V.r0;
-      }
-    if (own.coef != 0.0) {
-      const double c = own.coef;
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        double2* acc = s ? Y : X;
-        if (own.K[0]) {
-          const double2* p = own.K[0] + ((size_t)s * n + iw) * 16 + col;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) acc[e] = cfma(c, p[4 * e], acc[e]);
-        }
-        int i0;
-        double t;
-        if (own.K[1] && dgrid_locate(a.V.g, vq, i0, t)) {
-          const double2* p = own.K[1] + (((size_t)s * n + iw) * n + i0) * 16 + col;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) acc[e] = cfma(c * (1.0 - t), p[4 * e], cfma(c * t, p[16 + 4 * e], acc[e]));
-        }
-      }
-    }
+    own_mix(a, l, a.r0, xy, acc);
   }
-  double2 c0[4], c1[4];
-  combos(a.mix, X, Y, c0, c1);
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    store_c(o0 + m, c0[m]);
-    store_c(o1 + m, c1[m]);
-    if (a.L0) store_lo((T*)a.L0 + off + m, c0[m]);
-    if (a.L1) store_lo((T*)a.L1 + off + m, c1[m]);
-  }
+  store_c(o0 + off0, acc[0]);
+  store_c(o1 + off0, acc[1]);
+  store_c(o0 + off1, acc[2]);
+  store_c(o1 + off1, acc[3]);
 }
 
 // ======================================================================== epilogue
@@ -590,19 +660,17 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(GemmArgs g) {
 }
 
 // ======================================================================== split-FP32 GEMM
-// FP32 operands (hi parts, optionally lo corrections) on v_mfma_f32_32x32x2f32 with FP32
-// accumulation inside one K block of 32 complex, promoted to FP64 between blocks.
-// One 32x32 complex block per wave (lane l: A row l%32 / k l/32; D rows
-// 8(v/4) + 4(l/32) + v%4, col l%32).
+// FP32 operands on v_mfma_f32_32x32x2f32 with FP32 accumulation inside one K block of 32
+// complex, promoted to FP64 between blocks.  One 32x32 complex block per wave (lane l:
+// A row l%32 / k l/32; D rows 8(v/4) + 4(l/32) + v%4, col l%32).
 namespace f32g {
 constexpr int BM = 64, BK = 32, LDP = BM + 4;
 }
 
-template <bool LO>
 __global__ __launch_bounds__(256) void zgemm_f32_kernel(GemmArgs g) {
   using namespace f32g;
-  __shared__ float sA[2][LO ? 4 : 2][BK][LDP];
-  __shared__ float sB[2][LO ? 4 : 2][BK][LDP];
+  __shared__ float sA[2][2][BK][LDP];
+  __shared__ float sB[2][2][BK][LDP];
   int b, tm, tn;
   tile_coords(g, b, tm, tn);
   if (b >= g.nb) return;
@@ -625,17 +693,11 @@ __global__ __launch_bounds__(256) void zgemm_f32_kernel(GemmArgs g) {
   for (int c = 0; c < 2; ++c) {
     const float2* Ap = (const float2*)g.A[c] + (size_t)b * g.strideA + (size_t)arow * Kp + lk;
     const float2* Bp = (const float2*)g.B[c] + (size_t)b * g.strideB + (size_t)brow * Kp + lk;
-    const float2* Alp = LO ? (const float2*)g.Alo[c] + (size_t)b * g.strideA + (size_t)arow * Kp + lk : nullptr;
-    const float2* Blp = LO ? (const float2*)g.Blo[c] + (size_t)b * g.strideB + (size_t)brow * Kp + lk : nullptr;
-    float2 ra[8], rb[8], ral[LO ? 8 : 1], rbl[LO ? 8 : 1];
+    float2 ra[8], rb[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       ra[e] = Ap[e];
       rb[e] = Bp[e];
-      if (LO) {
-        ral[e] = Alp[e];
-        rbl[e] = Blp[e];
-      }
     }
     __syncthreads();
 #pragma unroll
@@ -644,12 +706,6 @@ __global__ __launch_bounds__(256) void zgemm_f32_kernel(GemmArgs g) {
       sA[0][1][lk + e][lrow] = ra[e].y;
       sB[0][0][lk + e][lrow] = rb[e].x;
       sB[0][1][lk + e][lrow] = rb[e].y;
-      if (LO) {
-        sA[0][2 % (LO ? 4 : 2)][lk + e][lrow] = ral[e].x;
-        sA[0][3 % (LO ? 4 : 2)][lk + e][lrow] = ral[e].y;
-        sB[0][2 % (LO ? 4 : 2)][lk + e][lrow] = rbl[e].x;
-        sB[0][3 % (LO ? 4 : 2)][lk + e][lrow] = rbl[e].y;
-      }
     }
     __syncthreads();
     for (int kb = 0; kb < nk; ++kb) {
@@ -659,10 +715,6 @@ __global__ __launch_bounds__(256) void zgemm_f32_kernel(GemmArgs g) {
         for (int e = 0; e < 8; ++e) {
           ra[e] = Ap[(size_t)(kb + 1) * BK + e];
           rb[e] = Bp[(size_t)(kb + 1) * BK + e];
-          if (LO) {
-            ral[e] = Alp[(size_t)(kb + 1) * BK + e];
-            rbl[e] = Blp[(size_t)(kb + 1) * BK + e];
-          }
         }
       }
       f16v cr, ci;
@@ -678,19 +730,6 @@ __global__ __launch_bounds__(256) void zgemm_f32_kernel(GemmArgs g) {
         cr = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bi, cr, 0, 0, 0);
         ci = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, ci, 0, 0, 0);
         ci = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, ci, 0, 0, 0);
-        if (LO) {
-          const float alr = sA[buf][2 % (LO ? 4 : 2)][kr][am], ali = sA[buf][3 % (LO ? 4 : 2)][kr][am];
-          const float blr = sB[buf][2 % (LO ? 4 : 2)][kr][bn], bli = sB[buf][3 % (LO ? 4 : 2)][kr][bn];
-          // hi x lo + lo x hi corrections
-          cr = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, blr, cr, 0, 0, 0);
-          cr = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bli, cr, 0, 0, 0);
-          cr = __builtin_amdgcn_mfma_f32_32x32x2f32(alr, br, cr, 0, 0, 0);
-          cr = __builtin_amdgcn_mfma_f32_32x32x2f32(-ali, bi, cr, 0, 0, 0);
-          ci = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bli, ci, 0, 0, 0);
-          ci = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, blr, ci, 0, 0, 0);
-          ci = __builtin_amdgcn_mfma_f32_32x32x2f32(alr, bi, ci, 0, 0, 0);
-          ci = __builtin_amdgcn_mfma_f32_32x32x2f32(ali, br, ci, 0, 0, 0);
-        }
       }
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
@@ -704,12 +743,6 @@ __global__ __launch_bounds__(256) void zgemm_f32_kernel(GemmArgs g) {
           sA[buf ^ 1][1][lk + e][lrow] = ra[e].y;
           sB[buf ^ 1][0][lk + e][lrow] = rb[e].x;
           sB[buf ^ 1][1][lk + e][lrow] = rb[e].y;
-          if (LO) {
-            sA[buf ^ 1][2 % (LO ? 4 : 2)][lk + e][lrow] = ral[e].x;
-            sA[buf ^ 1][3 % (LO ? 4 : 2)][lk + e][lrow] = ral[e].y;
-            sB[buf ^ 1][2 % (LO ? 4 : 2)][lk + e][lrow] = rbl[e].x;
-            sB[buf ^ 1][3 % (LO ? 4 : 2)][lk + e][lrow] = rbl[e].y;
-          }
         }
       }
       __syncthreads();
@@ -912,30 +945,6 @@ __global__ void chi_finalize_kernel(ChiArgs a, int nblk) {
   const int c = e >> 4, f = e & 15;
   a.out[((size_t)c * a.V.g.n + a.iw0 + b) * 16 + f] = s;
 }
-
-// ======================================================================== fused class table
-// Kf[s][w][v][v'] = K1[s][w] + K2[s][w][v] + K2'[s][w][v'] + K3[s][w][v][v'] (absent classes = 0)
-__device__ inline void st2(double2* p, double2 v) { *p = v; }
-__device__ inline void st2(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
-
-template <class TT> __global__ __launch_bounds__(256) void fuse_kernel(FuseArgs a) {
-  const size_t n = a.n;
-  const size_t total = 2 * n * n * n * 16;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-    const size_t f = e & 15;
-    size_t rest = e >> 4;
-    const size_t vp = rest % n;
-    rest /= n;
-    const size_t v = rest % n;
-    const size_t sw = rest / n;  // s * n + w
-    double2 x = a.K3 ? a.K3[e] : czero();
-    if (a.K1) x = cadd(x, a.K1[sw * 16 + f]);
-    if (a.K2) x = cadd(x, a.K2[(sw * n + v) * 16 + f]);
-    if (a.K2p) x = cadd(x, a.K2p[(sw * n + vp) * 16 + f]);
-    st2((TT*)a.out + e, x);
-  }
-}
-
 
 // ======================================================================== adjoint
 // Reverse pass of the bubble: the cotangent panel conj(dP) is built from the class
@@ -1516,17 +1525,17 @@ hipError_t upload_perm(const int* host_perm) {
   return hipMemcpyToSymbol(HIP_SYMBOL(c_perm), host_perm, sizeof(int) * 3 * 3 * 16);
 }
 
-void launch_fuse(const FuseArgs& a, bool f32, hipStream_t s) {
+void launch_table(const TableArgs& a, bool f32, hipStream_t s) {
   if (f32)
-    hipLaunchKernelGGL(fuse_kernel<float2>, dim3(4096), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(table_kernel<float2>, dim3(8192), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL(fuse_kernel<double2>, dim3(4096), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(table_kernel<double2>, dim3(8192), dim3(256), 0, s, a);
 }
 void launch_pi(const PiArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(pi_kernel, dim3(blocks_for((long)a.nb * a.nq, 256)), dim3(256), 0, s, a);
 }
 void launch_gather(const GatherArgs& a, bool left, bool f32, hipStream_t s) {
-  const long threads = (long)a.nb * a.cnt * a.nq_pad * 4;
+  const long threads = (long)a.nb * a.cnt * a.nq_pad * 8;
   dim3 grid(blocks_for(threads, 256));
   if (left) {
     if (f32)
@@ -1540,15 +1549,13 @@ void launch_gather(const GatherArgs& a, bool left, bool f32, hipStream_t s) {
       hipLaunchKernelGGL(gather_right_kernel<double2>, grid, dim3(256), 0, s, a);
   }
 }
-void launch_gemm(const GemmArgs& g, int precision, bool lo, hipStream_t s) {
+void launch_gemm(const GemmArgs& g, int precision, hipStream_t s) {
   const int total = g.nb * g.tms * g.tns;
   dim3 grid((unsigned)(((total + kXcds - 1) / kXcds) * kXcds));
   if (precision == 0)
     hipLaunchKernelGGL(zgemm_f64_kernel, grid, dim3(256), 0, s, g);
-  else if (lo)
-    hipLaunchKernelGGL(zgemm_f32_kernel<true>, grid, dim3(256), 0, s, g);
   else
-    hipLaunchKernelGGL(zgemm_f32_kernel<false>, grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL(zgemm_f32_kernel, grid, dim3(256), 0, s, g);
 }
 void launch_loop(const LoopArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(loop_kernel, dim3(a.g.n), dim3(256), 0, s, a);

@@ -16,22 +16,31 @@ struct PiArgs {
 struct GatherArgs {
   int r, nb, iw0, nq, nq_pad, lo, cnt;  // rows/cols lo .. lo+cnt-1 (index n = border)
   long Kp;                              // panel leading dimension (complex)
-  DVert V;
+  DGrid g;
+  double r0;
+  double coef;          // own channel coefficient
+  const double2* K[4];  // own channel K1, K2, K2', K3 (FP64, channel order; nullptr = absent)
+  const void* T[2];     // tables of channels r + 1, r + 2 (nullptr = inactive)
+  double mix[4];        // spin combination: c0 = mix0 X + mix1 Y, c1 = mix2 X + mix3 Y
   const double* nodes;  // vertex grid nodes
   const double* qv;
-  const double2* pi;  // left gather only
+  const double2* pi;  // left gather: Pi * w / (2 pi i); nullptr = raw left factor
   void* P0;           // panel of spin combination 0 ([nb][4(n+1)][Kp])
   void* P1;           // combination 1
-  void* L0;           // optional FP32 low parts
-  void* L1;
-  double mix[4];  // spin combination: c0 = mix0 X + mix1 Y, c1 = mix2 X + mix3 Y
+};
+
+// target-order class tables of channel r2 for a bubble in channel r
+struct TableArgs {
+  int n, r, r2;
+  double coef;
+  double mix[4];
+  const double2* K[4];  // K1, K2, K2', K3 of channel r2 (nullptr = absent)
+  void* out;            // F3 [n^3] | F2v [n^2] | F2p [n^2] | F1 [n] records of 32 values
 };
 
 struct GemmArgs {
   const void* A[2];
   const void* B[2];
-  const void* Alo[2];
-  const void* Blo[2];
   long strideA, strideB;  // complex elements per transfer frequency
   int M, Kp;              // M = 4(n+1) rows and columns; Kp padded contraction length
   int tm0, tms, tn0, tns; // tile ranges
@@ -66,14 +75,6 @@ struct ChiArgs {
   double2* out;       // [2][n][16]
 };
 
-struct FuseArgs {
-  int n;
-  const double2* K1;
-  const double2* K2;
-  const double2* K2p;
-  const double2* K3;
-  void* out;  // double2 or float2 table
-};
 
 // ------------------------------------------------------------------ adjoint
 // cotangent panel D'_c[(i,row),(j,col)] = conj(dP_c), dP_c from the class cotangents
@@ -156,10 +157,10 @@ void launch_dpi(const DPiArgs& a, hipStream_t s);
 void launch_unfuse(const UnfuseArgs& a, hipStream_t s);
 
 hipError_t upload_perm(const int* host_perm);
-void launch_fuse(const FuseArgs& a, bool f32, hipStream_t s);
+void launch_table(const TableArgs& a, bool f32, hipStream_t s);
 void launch_pi(const PiArgs& a, hipStream_t s);
 void launch_gather(const GatherArgs& a, bool left, bool f32, hipStream_t s);
-void launch_gemm(const GemmArgs& g, int precision, bool lo, hipStream_t s);
+void launch_gemm(const GemmArgs& g, int precision, hipStream_t s);
 void launch_loop(const LoopArgs& a, hipStream_t s);
 void launch_chi(const ChiArgs& a, hipStream_t s);
 int chi_blocks(int nq);
