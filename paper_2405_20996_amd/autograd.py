@@ -60,19 +60,19 @@ def _flat_grads(chans):
 class _Bubble(torch.autograd.Function):
     @staticmethod
     def forward(ctx, meta, r0L, r0R, Delta, *tensors):
-        channel, kind, grid, q, T, eps, coefsL, coefsR, precision = meta
+        channel, kind, grid, q, T, eps, coefsL, coefsR, precision, cmask = meta
         fl, fr = list(tensors[:12]), list(tensors[12:])
         L = _kvertex(grid, r0L, coefsL, fl)
         R = _kvertex(grid, r0R, coefsR, fr)
         P = K.Propagator(float(Delta), T, eps)
-        out = K.bubble(channel, L, R, P, q, pi_kind=kind, precision=precision)
+        out = K.bubble(channel, L, R, P, q, pi_kind=kind, precision=precision, class_mask=cmask)
         ctx.meta = meta
         ctx.save_for_backward(r0L, r0R, Delta, *tensors)
         return out.K1, out.K2, out.K2p, out.K3
 
     @staticmethod
     def backward(ctx, g1, g2, g2p, g3):
-        channel, kind, grid, q, T, eps, coefsL, coefsR, _ = ctx.meta
+        channel, kind, grid, q, T, eps, coefsL, coefsR, _, _ = ctx.meta
         saved = ctx.saved_tensors
         r0L, r0R, Delta = saved[:3]
         fl, fr = list(saved[3:15]), list(saved[15:27])
@@ -91,8 +91,9 @@ class _Bubble(torch.autograd.Function):
 
 
 def bubble(channel: int, left: TVertex, right: TVertex, Delta: torch.Tensor, q: K.Quad, T: float,
-           eps: float = 0.0, kind: int = K.PI_GG, precision: int = K.FP64) -> dict:
-    meta = (channel, kind, left.grid, q, T, eps, left.coefs, right.coefs, precision)
+           eps: float = 0.0, kind: int = K.PI_GG, precision: int = K.FP64, class_mask: int = K.KALL) -> dict:
+    """B_channel(left, right) as a dict of class tensors; classes outside class_mask are zero."""
+    meta = (channel, kind, left.grid, q, T, eps, left.coefs, right.coefs, precision, class_mask)
     outs = _Bubble.apply(meta, left.r0, right.r0, Delta, *left.flat(), *right.flat())
     return dict(zip(K.CLASSES, outs))
 
@@ -123,3 +124,97 @@ def sde(gamma: TVertex, Delta: torch.Tensor, q_bubble: K.Quad, q_loop: K.Quad, T
     """Dynamic self-energy [n][4] from the Schwinger-Dyson equation (a-channel form)."""
     meta = (gamma.grid, q_bubble, q_loop, T, eps, gamma.coefs)
     return _SDE.apply(meta, gamma.r0, Delta, *gamma.flat())
+
+
+def _sum(a: dict, b: dict) -> dict:
+    return {x: a[x] + b[x] for x in K.CLASSES}
+
+
+def mloop(gamma: TVertex, Delta: torch.Tensor, q: K.Quad, T: float, nloops: int, eps: float = 0.0,
+          precision: int = K.FP64) -> list:
+    """Multiloop insertions through differentiable bubbles (mfRG flow, Eqs. 1l-3l; Delta-flow
+    single-scale propagator, no Katanin term):
+      l = 1:  gdot_r = B_r(Gamma, Gamma; Pidot)
+      l = 2:  gdot_r = B_r(gdot_rbar^(1), Gamma) + B_r(Gamma, gdot_rbar^(1))
+      l >= 3: the same plus the centre term B_r(Gamma, L_r^(l-1)), L_r^(l-1) = B_r(gdot_rbar^(l-2), Gamma)
+    with gdot_rbar the sum of the two channels other than r.  Returns out[l-1][r] (class dicts)."""
+    g = gamma.grid
+    zero = torch.zeros((), dtype=torch.float64)
+    out, lefts = [], []
+    for ell in range(1, nloops + 1):
+        this, this_l = [], []
+        for r in range(3):
+            if ell == 1:
+                this.append(bubble(r, gamma, gamma, Delta, q, T, eps, kind=K.PI_DOT, precision=precision))
+                this_l.append(None)
+                continue
+            prev = out[ell - 2]
+            rbar = TVertex(g, zero, (1.0, 1.0, 1.0), [dict(prev[rr]) if rr != r else {} for rr in range(3)])
+            lt = bubble(r, rbar, gamma, Delta, q, T, eps, precision=precision)
+            tot = _sum(lt, bubble(r, gamma, rbar, Delta, q, T, eps, precision=precision))
+            if ell >= 3:
+                inner = TVertex(g, zero, (1.0, 1.0, 1.0), [dict(lefts[ell - 2][r]) if rr == r else {} for rr in range(3)])
+                tot = _sum(tot, bubble(r, gamma, inner, Delta, q, T, eps, precision=precision))
+            this.append(tot)
+            this_l.append(lt)
+        out.append(this)
+        lefts.append(this_l)
+    return out
+
+
+# ------------------------------------------------------------------ forward mode
+# The bubble is bilinear in its two vertices, so at a fixed propagator its tangent along
+# vertex tangents (dL, dR) is B(dL, R) + B(L, dR): two more bubbles.  A tangent vertex holds
+# the tangent of r0 and of the class arrays (channels without tangent arrays carry none).
+
+def bubble_jvp(channel: int, L: K.Vertex, dL: K.Vertex, R: K.Vertex, dR: K.Vertex, G: K.Propagator, q: K.Quad,
+               kind: int = K.PI_GG, precision: int = K.FP64, class_mask: int = K.KALL):
+    out = K.bubble(channel, L, R, G, q, pi_kind=kind, precision=precision, class_mask=class_mask)
+    dout = K.bubble(channel, dL, R, G, q, pi_kind=kind, precision=precision, class_mask=class_mask)
+    K.bubble(channel, L, dR, G, q, pi_kind=kind, precision=precision, class_mask=class_mask, out=dout, beta=1)
+    return out, dout
+
+
+def _vertex(grid: K.Grid, r0: float, chans) -> K.Vertex:
+    return K.Vertex(grid, r0, [c if c is not None else K.Channel(0.0) for c in chans])
+
+
+def _add(a: K.Channel, b: K.Channel, s: float = 1.0) -> K.Channel:
+    return K.Channel(1.0, *[getattr(a, x) + s * getattr(b, x) for x in K.CLASSES])
+
+
+def mloop_jvp(gamma: K.Vertex, dgamma: K.Vertex, G: K.Propagator, q: K.Quad, nloops: int,
+              precision: int = K.FP64):
+    """Multiloop insertions (as `mloop`) and their tangents along the vertex tangent dgamma, at a
+    fixed propagator.  Returns (out, dout), each out[l-1][r] a Channel."""
+    g = gamma.grid
+    out, dout, lefts, dlefts = [], [], [], []
+    for ell in range(1, nloops + 1):
+        this, dthis, this_l, dthis_l = [], [], [], []
+        for r in range(3):
+            if ell == 1:
+                o, d = bubble_jvp(r, gamma, dgamma, gamma, dgamma, G, q, K.PI_DOT, precision)
+                this.append(o)
+                dthis.append(d)
+                this_l.append(None)
+                dthis_l.append(None)
+                continue
+            rbar = _vertex(g, 0.0, [out[ell - 2][rr] if rr != r else None for rr in range(3)])
+            drbar = _vertex(g, 0.0, [dout[ell - 2][rr] if rr != r else None for rr in range(3)])
+            lt, dlt = bubble_jvp(r, rbar, drbar, gamma, dgamma, G, q, K.PI_GG, precision)
+            rt, drt = bubble_jvp(r, gamma, dgamma, rbar, drbar, G, q, K.PI_GG, precision)
+            tot, dtot = _add(lt, rt), _add(dlt, drt)
+            if ell >= 3:
+                inner = _vertex(g, 0.0, [lefts[ell - 2][r] if rr == r else None for rr in range(3)])
+                dinner = _vertex(g, 0.0, [dlefts[ell - 2][r] if rr == r else None for rr in range(3)])
+                ct, dct = bubble_jvp(r, gamma, dgamma, inner, dinner, G, q, K.PI_GG, precision)
+                tot, dtot = _add(tot, ct), _add(dtot, dct)
+            this.append(tot)
+            dthis.append(dtot)
+            this_l.append(lt)
+            dthis_l.append(dlt)
+        out.append(this)
+        dout.append(dthis)
+        lefts.append(this_l)
+        dlefts.append(dthis_l)
+    return out, dout

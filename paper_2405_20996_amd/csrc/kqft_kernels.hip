@@ -664,7 +664,7 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(GemmArgs g) {
 // complex, promoted to FP64 between blocks.  One 32x32 complex block per wave (lane l:
 // A row l%32 / k l/32; D rows 8(v/4) + 4(l/32) + v%4, col l%32).
 namespace f32g {
-constexpr int BM = 64, BK = 32, LDP = BM + 4;
+constexpr int BM = 64, BK = 32, LDP = BM + 1;  // odd pitch: conflict-free transposed LDS stores
 }
 
 __global__ __launch_bounds__(256) void zgemm_f32_kernel(GemmArgs g) {

@@ -1,0 +1,199 @@
+"""Derivatives of the composite map of the gradient workload (seed -> multiloop -> SDE / chi):
+
+    Gamma(U, Delta)  = Gamma_0(U) + PT2 K1(U, Delta) in every channel + fixed noise
+    dGamma           = sum_{l <= 3} multiloop insertions of Gamma (Delta-flow, Pidot at l = 1)
+    Gamma'           = Gamma + h dGamma,   h = 0.1
+    Sigma            = SDE(Gamma'),        chi = chi_a(Gamma')
+
+Reverse mode (torch.autograd over the hand-written bubble and SDE adjoints) gives
+d Sigma^R(v = 0) / dU and projections of d Sigma^R(v) / dDelta; forward mode (the bubble is
+bilinear in its vertices) gives d chi^R(w) / dU for all w in one tangent pass.  At the full
+size (N = 151, Nq = 1501) they are checked against central finite differences of the FP64
+GPU forward map (step 1e-5, relative 1e-5); at a reduced size against the oracle's
+dual-number derivatives of the same map (relative 1e-10).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from workload import seed_noise
+
+pytestmark = pytest.mark.gpu
+
+CL = ("K1", "K2", "K2p", "K3")
+T, H, NLOOPS = 0.1, 0.1, 3
+
+
+def _mods():
+    from paper_2405_20996_amd import autograd as A
+    from paper_2405_20996_amd import kqft as K
+    return K, A
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def forward_autograd(n, nq, Ut, Dt, noise):
+    """Sigma (autograd graph in U and Delta) and the vertex Gamma'."""
+    K, A = _mods()
+    g, q = K.Grid(n), K.Quad(nq)
+    bare = A.TVertex(g, Ut)
+    chans = []
+    for r in range(3):
+        k1 = A.bubble(r, bare, bare, Dt, q, T, class_mask=K.K1)["K1"]
+        d = {x: to_dev(noise[r][x]) for x in CL}
+        d["K1"] = d["K1"] + k1
+        chans.append(d)
+    V = A.TVertex(g, Ut, (1.0, 1.0, 1.0), chans)
+    ins = A.mloop(V, Dt, q, T, NLOOPS)
+    chans2 = []
+    for r in range(3):
+        c = dict(chans[r])
+        for ell in range(NLOOPS):
+            c = {x: c[x] + H * ins[ell][r][x] for x in CL}
+        chans2.append(c)
+    V2 = A.TVertex(g, Ut, (1.0, 1.0, 1.0), chans2)
+    return A.sde(V2, Dt, q, q, T)
+
+
+def seed_plain(K, g, q, P, U, noise, n):
+    bare = K.Vertex(g, U)
+    chans = []
+    for r in range(3):
+        c = K.Channel(1.0, *[to_dev(noise[r][x]) for x in CL])
+        c.K1 = c.K1 + K.bubble(r, bare, bare, P, q, class_mask=K.K1).K1
+        chans.append(c)
+    return K.Vertex(g, U, chans)
+
+
+def forward_plain(n, nq, U, D, noise):
+    """(Sigma, chi) of the same map through kqft_mloop_step (no autograd)."""
+    K, _ = _mods()
+    g, q, P = K.Grid(n), K.Quad(nq), K.Propagator(D, T)
+    V = seed_plain(K, g, q, P, U, noise, n)
+    ins = K.mloop_step([V], [P], [q], NLOOPS)[0]
+    chans = []
+    for r in range(3):
+        c = K.Channel(1.0, *[getattr(V.ch[r], x).clone() for x in CL])
+        for ell in range(NLOOPS):
+            for x in CL:
+                setattr(c, x, getattr(c, x) + H * getattr(ins[ell][r], x))
+        chans.append(c)
+    sig, chi = K.sde(K.Vertex(g, U, chans), P, q, q)
+    torch.cuda.synchronize()
+    return sig.cpu().numpy(), chi.cpu().numpy()
+
+
+def chi_tangent_u(n, nq, U, D, noise):
+    """d chi / dU of the map, all transfer frequencies, by one forward-mode pass."""
+    K, A = _mods()
+    g, q, P = K.Grid(n), K.Quad(nq), K.Propagator(D, T)
+    bare, dbare = K.Vertex(g, U), K.Vertex(g, 1.0)
+    chans, dchans = [], []
+    for r in range(3):
+        k1, dk1 = A.bubble_jvp(r, bare, dbare, bare, dbare, P, q, class_mask=K.K1)
+        c = K.Channel(1.0, *[to_dev(noise[r][x]) for x in CL])
+        c.K1 = c.K1 + k1.K1
+        chans.append(c)
+        dchans.append(K.Channel(1.0, dk1.K1, torch.zeros_like(c.K2), torch.zeros_like(c.K2p), torch.zeros_like(c.K3)))
+    V, dV = K.Vertex(g, U, chans), K.Vertex(g, 1.0, dchans)
+    out, dout = A.mloop_jvp(V, dV, P, q, NLOOPS)
+    dchans2 = []
+    for r in range(3):
+        c = K.Channel(1.0, *[getattr(dchans[r], x).clone() for x in CL])
+        for ell in range(NLOOPS):
+            for x in CL:
+                setattr(c, x, getattr(c, x) + H * getattr(dout[ell][r], x))
+        dchans2.append(c)
+    # chi is affine in the vertex: chi(dGamma') - chi(0) is its derivative
+    _, chi_t = K.sde(K.Vertex(g, 1.0, dchans2), P, q, q)
+    _, chi_0 = K.sde(K.Vertex(g, 0.0), P, q, q)
+    torch.cuda.synchronize()
+    return (chi_t - chi_0).cpu().numpy()
+
+
+def test_gradient_workload_n151_vs_finite_differences():
+    K, A = _mods()
+    n, nq, U, D = 151, 1501, 1.0, 1.0
+    noise = seed_noise(n, 0)
+    rng = np.random.default_rng(5)
+    cr, ci = rng.standard_normal(n), rng.standard_normal(n)
+    print(f"gradient workload n={n} nq={nq}: autograd forward", flush=True)
+    Ut = torch.tensor(U, dtype=torch.float64, requires_grad=True)
+    Dt = torch.tensor(D, dtype=torch.float64, requires_grad=True)
+    sig = forward_autograd(n, nq, Ut, Dt, noise)
+    s0 = sig[n // 2, 1]  # Sigma^R(v = 0)
+    projD = (torch.from_numpy(cr).cuda() * sig[:, 1].real).sum() + (torch.from_numpy(ci).cuda() * sig[:, 1].imag).sum()
+    print("reverse passes", flush=True)
+    gu_re, = torch.autograd.grad(s0.real, Ut, retain_graph=True)
+    gu_im, = torch.autograd.grad(s0.imag, Ut, retain_graph=True)
+    gd, = torch.autograd.grad(projD, Dt)
+    sig_val = sig.detach().cpu().numpy()
+    del sig, s0, projD
+    torch.cuda.empty_cache()
+    print("finite differences", flush=True)
+    e = 1e-5
+    sp, chp = forward_plain(n, nq, U + e, D, noise)
+    sm, chm = forward_plain(n, nq, U - e, D, noise)
+    fd_u = (sp[n // 2, 1] - sm[n // 2, 1]) / (2 * e)
+    fd_chi = (O.chi_scalar(chp[0]) - O.chi_scalar(chm[0])) / (2 * e)
+    sp, _ = forward_plain(n, nq, U, D + e, noise)
+    sm, _ = forward_plain(n, nq, U, D - e, noise)
+    dsd = (sp[:, 1] - sm[:, 1]) / (2 * e)
+    fd_d = float(np.sum(cr * dsd.real) + np.sum(ci * dsd.imag))
+    # the autograd composition and kqft_mloop_step agree on the forward value
+    s_plain, _ = forward_plain(n, nq, U, D, noise)
+    assert np.abs(s_plain - sig_val).max() < 1e-11 * np.abs(s_plain).max()
+    got_u = complex(float(gu_re), float(gu_im))
+    print(f"dSigmaR(0)/dU adjoint {got_u:.10e} fd {fd_u:.10e}; projected dSigma/dDelta adjoint "
+          f"{float(gd):.10e} fd {fd_d:.10e}", flush=True)
+    assert abs(got_u - fd_u) < 1e-5 * abs(fd_u)
+    assert abs(float(gd) - fd_d) < 1e-5 * abs(fd_d)
+    print("forward-mode dchi/dU", flush=True)
+    dchi = O.chi_scalar(chi_tangent_u(n, nq, U, D, noise)[0])
+    err = np.abs(dchi - fd_chi).max() / np.abs(fd_chi).max()
+    print(f"dchiR/dU vs fd: max rel {err:.3e}", flush=True)
+    assert err < 1e-5
+
+
+def test_gradient_map_reduced_size_vs_oracle_duals():
+    """N = 21, Nq = 81: full d Sigma^R(v)/dDelta (one reverse pass per v), d Sigma^R(0)/dU and
+    d chi^R(w)/dU against the oracle's forward-mode dual numbers of the same map."""
+    K, A = _mods()
+    n, nq, U, D = 21, 81, 1.0, 1.0
+    noise = seed_noise(n, 0)
+    Ut = torch.tensor(U, dtype=torch.float64, requires_grad=True)
+    Dt = torch.tensor(D, dtype=torch.float64, requires_grad=True)
+    sig = forward_autograd(n, nq, Ut, Dt, noise)
+    gu = complex(float(torch.autograd.grad(sig[n // 2, 1].real, Ut, retain_graph=True)[0]),
+                 float(torch.autograd.grad(sig[n // 2, 1].imag, Ut, retain_graph=True)[0]))
+    gd = np.zeros(n, dtype=np.complex128)
+    for i in range(n):
+        re, = torch.autograd.grad(sig[i, 1].real, Dt, retain_graph=True)
+        im, = torch.autograd.grad(sig[i, 1].imag, Dt, retain_graph=True)
+        gd[i] = complex(float(re), float(im))
+    dchi = O.chi_scalar(chi_tangent_u(n, nq, U, D, noise)[0])
+
+    def oracle_map(dU, dD):
+        og, oq = O.Grid(n), O.Quad(nq)
+        P = O.Prop(D, T, dDelta=dD)
+        ov = O.seeded_vertex(og, U, P, oq, noise, dual=True, dU=dU)
+        ins = O.mloop(ov, P, oq, NLOOPS, dual=True)
+        chans = []
+        for r in range(3):
+            c = {x: getattr(ov.ch[r], x) for x in CL}
+            for ell in range(NLOOPS):
+                c = {x: c[x] + H * getattr(ins[ell][r], x) for x in CL}
+            chans.append(O.Channel(1.0, *[c[x] for x in CL]))
+        v2 = O.Vertex(og, U, chans, dr0=dU)
+        return O.dual_parts(O.sde(v2, P, oq, oq, dual=True)), O.dual_parts(O.chi(v2, P, oq, dual=True))
+
+    (s_val, s_du), (_, chi_du) = oracle_map(1.0, 0.0)
+    (_, s_dd), _ = oracle_map(0.0, 1.0)
+    assert np.abs(sig.detach().cpu().numpy() - s_val).max() < 1e-12 * np.abs(s_val).max()
+    assert abs(gu - s_du[n // 2, 1]) < 1e-10 * abs(s_du[n // 2, 1])
+    assert np.abs(gd - s_dd[:, 1]).max() < 1e-10 * np.abs(s_dd[:, 1]).max()
+    ref_chi = O.chi_scalar(chi_du[0])
+    assert np.abs(dchi - ref_chi).max() < 1e-10 * np.abs(ref_chi).max()
