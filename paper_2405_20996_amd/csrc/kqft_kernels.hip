@@ -552,12 +552,13 @@ __device__ inline void tile_coords(const GemmArgs& g, int& b, int& tm, int& tn) 
 
 // ======================================================================== FP64 GEMM
 // 64x64 complex tile per workgroup, four waves of 32x32, v_mfma_f64_16x16x4f64
-// (lane l: A row l%16 / k l/16, B k l/16 / col l%16, D rows 4v + l/16, col l%16).
+// (lane l: A row l%16 / k l/16, B k l/16 / col l%16, D rows 4v + l/16, col l%16); three
+// real products per complex multiply-add (Gauss), as in the split-FP32 kernel.
 namespace f64g {
 constexpr int BM = 64, BK = 16, LDP = BM + 2;
 }
 
-__global__ __launch_bounds__(256) void zgemm_f64_kernel(GemmArgs g) {
+__global__ __launch_bounds__(256, 2) void zgemm_f64_kernel(GemmArgs g) {
   using namespace f64g;
   __shared__ double sA[2][2][BK][LDP];
   __shared__ double sB[2][2][BK][LDP];
@@ -585,6 +586,13 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(GemmArgs g) {
   for (int c = 0; c < 2; ++c) {
     const double2* Ap = (const double2*)g.A[c] + (size_t)b * g.strideA + (size_t)arow * Kp + lk;
     const double2* Bp = (const double2*)g.B[c] + (size_t)b * g.strideB + (size_t)brow * Kp + lk;
+    d4 p[3][2][2];  // Gauss products ar br, ai bi, (ar + ai)(br + bi) of this combination
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) p[x][mb][nb] = d4{0.0, 0.0, 0.0, 0.0};
     double2 ra[4], rb[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -623,14 +631,19 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(GemmArgs g) {
           br[nb] = sB[buf][0][kr][wn * 32 + nb * 16 + (lane & 15)];
           bi[nb] = sB[buf][1][kr][wn * 32 + nb * 16 + (lane & 15)];
         }
+        double sa[2], sb[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          sa[u] = ar[u] + ai[u];
+          sb[u] = br[u] + bi[u];
+        }
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
           for (int nb = 0; nb < 2; ++nb) {
-            acc[c][0][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[mb], br[nb], acc[c][0][mb][nb], 0, 0, 0);
-            acc[c][0][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[mb], bi[nb], acc[c][0][mb][nb], 0, 0, 0);
-            acc[c][1][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[mb], bi[nb], acc[c][1][mb][nb], 0, 0, 0);
-            acc[c][1][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[mb], br[nb], acc[c][1][mb][nb], 0, 0, 0);
+            p[0][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[mb], br[nb], p[0][mb][nb], 0, 0, 0);
+            p[1][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[mb], bi[nb], p[1][mb][nb], 0, 0, 0);
+            p[2][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[mb], sb[nb], p[2][mb][nb], 0, 0, 0);
           }
       }
       if (kb + 1 < nk) {
@@ -644,6 +657,13 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(GemmArgs g) {
       }
       __syncthreads();
     }
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        acc[c][0][mb][nb] = p[0][mb][nb] - p[1][mb][nb];
+        acc[c][1][mb][nb] = p[2][mb][nb] - p[0][mb][nb] - p[1][mb][nb];
+      }
   }
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
@@ -662,12 +682,14 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(GemmArgs g) {
 // ======================================================================== split-FP32 GEMM
 // FP32 operands on v_mfma_f32_32x32x2f32 with FP32 accumulation inside one K block of 32
 // complex, promoted to FP64 between blocks.  One 32x32 complex block per wave (lane l:
-// A row l%32 / k l/32; D rows 8(v/4) + 4(l/32) + v%4, col l%32).
+// A row l%32 / k l/32; D rows 8(v/4) + 4(l/32) + v%4, col l%32).  Complex products take
+// three real products (Gauss): P1 = ar br, P2 = ai bi, P3 = (ar + ai)(br + bi), so that
+// Re = P1 - P2 and Im = P3 - P1 - P2 -- 6 instead of 8 real flops per complex multiply-add.
 namespace f32g {
 constexpr int BM = 64, BK = 32, LDP = BM + 1;  // odd pitch: conflict-free transposed LDS stores
 }
 
-__global__ __launch_bounds__(256) void zgemm_f32_kernel(GemmArgs g) {
+__global__ __launch_bounds__(256, 2) void zgemm_f32_kernel(GemmArgs g) {
   using namespace f32g;
   __shared__ float sA[2][2][BK][LDP];
   __shared__ float sB[2][2][BK][LDP];
@@ -717,24 +739,23 @@ __global__ __launch_bounds__(256) void zgemm_f32_kernel(GemmArgs g) {
           rb[e] = Bp[(size_t)(kb + 1) * BK + e];
         }
       }
-      f16v cr, ci;
+      f16v p1, p2, p3;
 #pragma unroll
-      for (int v = 0; v < 16; ++v) cr[v] = ci[v] = 0.f;
+      for (int v = 0; v < 16; ++v) p1[v] = p2[v] = p3[v] = 0.f;
 #pragma unroll
       for (int kk = 0; kk < BK / 2; ++kk) {
         const int kr = kk * 2 + (lane >> 5);
         const int am = wm * 32 + (lane & 31), bn = wn * 32 + (lane & 31);
         const float ar = sA[buf][0][kr][am], ai = sA[buf][1][kr][am];
         const float br = sB[buf][0][kr][bn], bi = sB[buf][1][kr][bn];
-        cr = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, cr, 0, 0, 0);
-        cr = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bi, cr, 0, 0, 0);
-        ci = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, ci, 0, 0, 0);
-        ci = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, ci, 0, 0, 0);
+        p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, p1, 0, 0, 0);
+        p2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bi, p2, 0, 0, 0);
+        p3 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar + ai, br + bi, p3, 0, 0, 0);
       }
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        acc64[c][0][v] += (double)cr[v];
-        acc64[c][1][v] += (double)ci[v];
+        acc64[c][0][v] += (double)(p1[v] - p2[v]);
+        acc64[c][1][v] += (double)(p3[v] - p1[v] - p2[v]);
       }
       if (kb + 1 < nk) {
 #pragma unroll
