@@ -125,8 +125,10 @@ typedef struct {
   int class_mask;  /* KQFT_K* bits of the outputs to compute */
   int beta;        /* 0: overwrite outputs, 1: add into them */
   int omega_batch; /* transfer frequencies per panel batch, 0 = automatic */
-  int serial;      /* 0: vertex gathers of the next batch overlap the current GEMM (two
-                      internal streams); 1: run them one after the other (for timing) */
+  int overlap;     /* 0: panel gathers and GEMMs of consecutive transfer-frequency batches run
+                      one after the other (the faster schedule on gfx950: both kernels want
+                      the whole chip); 1: the gathers of the next batch run concurrently with
+                      the current GEMM on a second internal stream */
 } kqft_opts;
 
 typedef struct kqft_ctx kqft_ctx;

@@ -399,7 +399,7 @@ static int bubble_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_ve
     void* B0 = base + 2 * pbytes * nb;
     void* B1 = base + 3 * pbytes * nb;
     double2* pib = (double2*)ctx->pi[x].p;
-    if (o.serial && batch >= 1) HIP_TRY(hipStreamWaitEvent(ctx->sg, gemm_done[batch - 1], 0));
+    if (!o.overlap && batch >= 1) HIP_TRY(hipStreamWaitEvent(ctx->sg, gemm_done[batch - 1], 0));
     if (batch >= 2) HIP_TRY(hipStreamWaitEvent(ctx->sg, gemm_done[batch - 2], 0));
     PiArgs pa{r, kind, cnt, nq, iw0, P, nodes, qv, qw, pib};
     {
@@ -471,7 +471,7 @@ static int check_common(kqft_ctx* ctx, const kqft_propagator* G, const kqft_quad
   if (o->precision != KQFT_FP64 && o->precision != KQFT_SPLIT_FP32) return fail(KQFT_EINVAL, "unknown precision");
   if (o->beta != 0 && o->beta != 1) return fail(KQFT_EINVAL, "beta must be 0 or 1");
   if (o->omega_batch < 0) return fail(KQFT_EINVAL, "omega_batch must be >= 0");
-  if (o->serial != 0 && o->serial != 1) return fail(KQFT_EINVAL, "serial must be 0 or 1");
+  if (o->overlap != 0 && o->overlap != 1) return fail(KQFT_EINVAL, "overlap must be 0 or 1");
   return KQFT_OK;
 }
 
@@ -916,7 +916,7 @@ int kqft_sde_adjoint(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propaga
   o.precision = KQFT_FP64;
   o.class_mask = KQFT_K1 | KQFT_K2P;
   o.beta = 0;
-  o.serial = 0;
+  o.overlap = 0;
   BubbleOut po{phiK1, nullptr, phiK2p, nullptr};
   if ((rc = bubble_core(ctx, KQFT_CH_A, bare, *gamma, *G, KQFT_PI_GG, *q_bubble, o, po, s))) return rc;
   // loop adjoint: dSigma -> dPhi, dDelta

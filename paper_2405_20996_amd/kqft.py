@@ -51,7 +51,7 @@ class KqftChout(C.Structure):
 
 class KqftOpts(C.Structure):
     _fields_ = [("precision", C.c_int), ("class_mask", C.c_int), ("beta", C.c_int), ("omega_batch", C.c_int),
-                ("serial", C.c_int)]
+                ("overlap", C.c_int)]
 
 
 _lib = None
@@ -209,8 +209,8 @@ class Propagator:
                               _ptr(self.SigK, (n,) if n else None, "SigK"))
 
 
-def _opts(precision, class_mask, beta, omega_batch, serial=0) -> KqftOpts:
-    return KqftOpts(precision, class_mask, beta, omega_batch, serial)
+def _opts(precision, class_mask, beta, omega_batch, overlap=0) -> KqftOpts:
+    return KqftOpts(precision, class_mask, beta, omega_batch, overlap)
 
 
 def alloc_channel(n: int, device=None, zero: bool = True) -> Channel:
@@ -232,14 +232,14 @@ def _chout_opt(chn: Optional[Channel], n: int) -> KqftChout:
 # ------------------------------------------------------------------ entry points
 def bubble(channel: int, left: Vertex, right: Vertex, G: Propagator, q: Quad, pi_kind: int = PI_GG,
            precision: int = FP64, class_mask: int = KALL, beta: int = 0, omega_batch: int = 0,
-           out: Optional[Channel] = None, stream=None, serial: bool = False) -> Channel:
+           out: Optional[Channel] = None, stream=None, overlap: bool = False) -> Channel:
     n = left.grid.n
     if out is None:
         out = alloc_channel(n)
     lc, rc, gc, qc = left.c(), right.c(), G.c(), q.c()
     oc = _chout(out, n)
     _check(lib().kqft_bubble(ctx(), channel, C.byref(lc), C.byref(rc), C.byref(gc), pi_kind, C.byref(qc),
-                             C.byref(_opts(precision, class_mask, beta, omega_batch, int(serial))), C.byref(oc),
+                             C.byref(_opts(precision, class_mask, beta, omega_batch, int(overlap))), C.byref(oc),
                              _stream(stream)))
     return out
 

@@ -125,8 +125,8 @@ def test_config1_bubble_a_fp64_and_split():
     out32 = K.bubble(0, kv, kv, P, q, precision=K.SPLIT_FP32)
     torch.cuda.synchronize()
     compare(out32, ref, 1e-6)
-    # serialised gather/GEMM schedule and small batches: the same FP64 result
-    out_s = K.bubble(0, kv, kv, P, q, omega_batch=4, serial=True)
+    # overlapped gather/GEMM schedule and small batches: the same FP64 result
+    out_s = K.bubble(0, kv, kv, P, q, omega_batch=4, overlap=True)
     torch.cuda.synchronize()
     compare(out_s, ref, 1e-12)
 

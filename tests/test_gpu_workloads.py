@@ -68,19 +68,19 @@ def check_points(out, ref_full_max, pts, ref, tol):
 
 def test_headline_workload_n201_sampled_parity():
     """Channel-a bubble at N = 201, Nq = 2001 (U = 1, T = 0.1) in the benchmark's launch
-    configuration (transfer-frequency batches of 24, gathers overlapped with GEMMs)."""
+    configuration (three batches of 67 transfer frequencies, gathers and GEMMs in sequence)."""
     K = _K()
     n, nq = 201, 2001
     noise = seed_noise(n, 0)
     ov, kv, (og, oq, op), (g, q, P) = seeded(n, nq, 1.0, 0.1, noise)
     pts = sample_points(n, 48, 3)
     ref = O.bubble_points(0, ov, ov, op, oq, pts)
-    out64 = K.bubble(0, kv, kv, P, q, omega_batch=24)
+    out64 = K.bubble(0, kv, kv, P, q, omega_batch=67)
     torch.cuda.synchronize()
     mx = {c: float(getattr(out64, c).abs().max()) for c in CL}
     check_points(out64, mx, pts, ref, 1e-12)
     del out64
-    out32 = K.bubble(0, kv, kv, P, q, precision=K.SPLIT_FP32, omega_batch=24)
+    out32 = K.bubble(0, kv, kv, P, q, precision=K.SPLIT_FP32, omega_batch=67)
     torch.cuda.synchronize()
     check_points(out32, mx, pts, ref, 1e-6)
 
