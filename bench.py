@@ -166,13 +166,14 @@ def main():
         rng = np.random.default_rng(1)
         npts = args.cpu_points
         cores = len(os.sched_getaffinity(0))
-        if npts <= 0:  # size the sample to about 20 s of CPU work
+        if npts <= 0:  # size the sample to 10-30 s of CPU work
             m = 8 * cores
             probe = np.stack([np.full(m, 8), rng.integers(0, n, m), rng.integers(0, n, m), rng.integers(0, n, m)], 1)
             t0 = time.perf_counter()
             O.bubble_points(0, ov, ov, op, oq, probe)
             per = (time.perf_counter() - t0) / m
-            npts = int(max(64, min(200000, 20.0 / max(per, 1e-7))))
+            # the probe overestimates the per-block time (start-up); aim at 15-20 s measured
+            npts = int(max(64, min(400000, 45.0 / max(per, 1e-7))))
         pts = np.stack([np.full(npts, 8), rng.integers(0, n, npts), rng.integers(0, n, npts),
                         rng.integers(0, n, npts)], 1)
         pts[: min(8, npts), 0] = [1, 2, 4, 8, 1, 2, 4, 8][: min(8, npts)]

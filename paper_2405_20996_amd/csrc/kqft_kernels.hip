@@ -680,8 +680,8 @@ __global__ __launch_bounds__(256, 2) void zgemm_f64_kernel(GemmArgs g) {
 }
 
 // ======================================================================== split-FP32 GEMM
-// FP32 operands on v_mfma_f32_32x32x2f32 with FP32 accumulation inside one K block of 32
-// complex, promoted to FP64 between blocks.  One 32x32 complex block per wave (lane l:
+// FP32 operands on v_mfma_f32_32x32x2f32 with FP32 accumulation over two K blocks of 32
+// complex, promoted to FP64 between them.  One 32x32 complex block per wave (lane l:
 // A row l%32 / k l/32; D rows 8(v/4) + 4(l/32) + v%4, col l%32).  Complex products take
 // three real products (Gauss): P1 = ar br, P2 = ai bi, P3 = (ar + ai)(br + bi), so that
 // Re = P1 - P2 and Im = P3 - P1 - P2 -- 6 instead of 8 real flops per complex multiply-add.
@@ -703,6 +703,7 @@ __global__ __launch_bounds__(256, 2) void zgemm_f32_kernel(GemmArgs g) {
   const int arow = min(tm * BM + lrow, Mtot - 1);
   const int brow = min(tn * BM + lrow, Mtot - 1);
   const int nk = Kp / BK;
+  const int am = wm * 32 + (lane & 31), bn = wn * 32 + (lane & 31);
   double acc64[2][2][16];  // [combo][re/im][v]
 #pragma unroll
   for (int c = 0; c < 2; ++c)
@@ -730,7 +731,9 @@ __global__ __launch_bounds__(256, 2) void zgemm_f32_kernel(GemmArgs g) {
       sB[0][1][lk + e][lrow] = rb[e].y;
     }
     __syncthreads();
-    for (int kb = 0; kb < nk; ++kb) {
+    f16v p1, p2, p3;
+    // one K block from LDS buffer kb & 1, prefetching block kb + 1 through registers
+    auto kblock = [&](int kb) {
       const int buf = kb & 1;
       if (kb + 1 < nk) {
 #pragma unroll
@@ -739,23 +742,14 @@ __global__ __launch_bounds__(256, 2) void zgemm_f32_kernel(GemmArgs g) {
           rb[e] = Bp[(size_t)(kb + 1) * BK + e];
         }
       }
-      f16v p1, p2, p3;
-#pragma unroll
-      for (int v = 0; v < 16; ++v) p1[v] = p2[v] = p3[v] = 0.f;
 #pragma unroll
       for (int kk = 0; kk < BK / 2; ++kk) {
         const int kr = kk * 2 + (lane >> 5);
-        const int am = wm * 32 + (lane & 31), bn = wn * 32 + (lane & 31);
         const float ar = sA[buf][0][kr][am], ai = sA[buf][1][kr][am];
         const float br = sB[buf][0][kr][bn], bi = sB[buf][1][kr][bn];
         p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, p1, 0, 0, 0);
         p2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bi, p2, 0, 0, 0);
         p3 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar + ai, br + bi, p3, 0, 0, 0);
-      }
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        acc64[c][0][v] += (double)(p1[v] - p2[v]);
-        acc64[c][1][v] += (double)(p3[v] - p1[v] - p2[v]);
       }
       if (kb + 1 < nk) {
 #pragma unroll
@@ -767,6 +761,18 @@ __global__ __launch_bounds__(256, 2) void zgemm_f32_kernel(GemmArgs g) {
         }
       }
       __syncthreads();
+    };
+    // FP32 partial sums over two K blocks (64 complex terms), then promoted to FP64
+    for (int kb = 0; kb < nk; kb += 2) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) p1[v] = p2[v] = p3[v] = 0.f;
+      kblock(kb);
+      if (kb + 1 < nk) kblock(kb + 1);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        acc64[c][0][v] += (double)(p1[v] - p2[v]);
+        acc64[c][1][v] += (double)(p3[v] - p1[v] - p2[v]);
+      }
     }
   }
 #pragma unroll
