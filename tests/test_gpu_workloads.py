@@ -141,3 +141,25 @@ def test_three_channel_pipeline_n31():
     # the scalar retarded susceptibility of the D combination stays finite and the X one is enhanced
     cx = O.chi_scalar(chi.cpu().numpy()[0])
     assert np.all(np.isfinite(cx))
+
+
+def test_headline_workload_n201_sde_and_chi():
+    """Self-energy (in full) and chi (at five transfer frequencies) of the headline vertex,
+    N = 201, Nq = 2001 for both the Phi bubble and the loop, FP64."""
+    K = _K()
+    n, nq = 201, 2001
+    noise = seed_noise(n, 0)
+    ov, kv, (og, oq, op), (g, q, P) = seeded(n, nq, 1.0, 0.1, noise)
+    import time
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sig, chi = K.sde(kv, P, q, q)
+    torch.cuda.synchronize()
+    print(f"sde + chi at n={n}: {time.perf_counter() - t0:.2f} s", flush=True)
+    ref_sig = O.sde(ov, op, oq, oq)
+    s = sig.cpu().numpy()
+    assert np.abs(s - ref_sig).max() < 1e-12 * np.abs(ref_sig).max()
+    iws = [0, 50, 100, 101, 200]
+    ref_chi = O.chi_points(ov, op, oq, iws)
+    c = chi.cpu().numpy()[:, iws]
+    assert np.abs(c - ref_chi).max() < 1e-12 * np.abs(ref_chi).max()
