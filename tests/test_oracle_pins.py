@@ -509,6 +509,44 @@ def test_multiloop_orders_are_multilinear_and_l2_symmetric():
     assert np.abs(o1[0][0].K3).max() == 0.0
 
 
+def test_multiloop_total_derivative_at_third_order():
+    """The multiloop flow reproduces the total derivative of the parquet vertex (Sec. mfRG:
+    multiloop flow equations).  At third order in U the parquet vertex of channel r is
+    gamma_r^(3) = B_r(Gamma_0, Gamma^(2)) + B_r(I_r^(2), Gamma_0) with Gamma^(2) = sum_r' gamma_r'^(2),
+    I_r^(2) = sum_{r' != r} gamma_r'^(2), gamma^(2) = the PT2 K1; its Delta-derivative (dual
+    numbers) equals the third-order part of the l = 1 and l = 2 insertions of
+    Gamma_0 + gamma^(2): B_r(Gamma_0, Gamma^(2); Pidot) + B_r(Gamma^(2), Gamma_0; Pidot)
+    + B_r(gdot_rbar^(2), Gamma_0) + B_r(Gamma_0, gdot_rbar^(2)), gdot^(2) = B_r'(Gamma_0, Gamma_0; Pidot).
+    The identity is exact in the discrete scheme (the bubble is linear in each vertex and the
+    vertices enter on the grid), so a wrong channel sum, prefactor or Pidot fails it."""
+    g, q = O.Grid(9), O.Quad(31)
+    Pd = O.Prop(D, T, dDelta=1.0)
+    P = O.Prop(D, T)
+    g0d = O.bare(g, U)
+    g0 = O.bare(g, U)
+    k1d = [O.bubble(rr, g0d, g0d, Pd, q, 0, O.C_K1, dual=True).K1 for rr in range(3)]
+    k1 = [O.dual_parts(x)[0] for x in k1d]
+    kdot = [O.bubble(rr, g0, g0, P, q, 1, O.C_K1).K1 for rr in range(3)]
+    # the PT2 derivative itself is the l = 1 insertion of Gamma_0
+    for rr in range(3):
+        assert np.abs(O.dual_parts(k1d[rr])[1] - kdot[rr]).max() < 1e-12 * np.abs(kdot[rr]).max()
+    for r in range(3):
+        all2d = O.Vertex(g, 0.0, [O.Channel(1.0, k1d[rr]) for rr in range(3)])
+        i2d = O.Vertex(g, 0.0, [O.Channel(1.0, k1d[rr]) if rr != r else O.Channel(0.0) for rr in range(3)])
+        a = O.bubble(r, g0d, all2d, Pd, q, 0, O.C_ALL, dual=True)
+        b = O.bubble(r, i2d, g0d, Pd, q, 0, O.C_ALL, dual=True)
+        all2 = O.Vertex(g, 0.0, [O.Channel(1.0, k1[rr]) for rr in range(3)])
+        rbar = O.Vertex(g, 0.0, [O.Channel(1.0, kdot[rr]) if rr != r else O.Channel(0.0) for rr in range(3)])
+        parts = [O.bubble(r, g0, all2, P, q, 1), O.bubble(r, all2, g0, P, q, 1),
+                 O.bubble(r, rbar, g0, P, q, 0), O.bubble(r, g0, rbar, P, q, 0)]
+        scale = max(np.abs(sum(getattr(x, c) for x in parts)).max() for c in ("K1", "K2", "K2p"))
+        assert scale > 0
+        for c in ("K1", "K2", "K2p", "K3"):  # third order: K3 vanishes on both sides
+            deriv = O.dual_parts(getattr(a, c))[1] + O.dual_parts(getattr(b, c))[1]
+            ml = sum(getattr(x, c) for x in parts)
+            assert np.abs(deriv - ml).max() < 1e-12 * scale, (r, c)
+
+
 # ---------------------------------------------------------------- P13: sum rule
 def test_spectral_sum_rule_with_dyson_self_energy():
     """int A(v) dv = 1 (Sec. Sum rule for the spectral function) for G^R = 1/(v + i Delta - Sigma^R)
