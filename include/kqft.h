@@ -185,8 +185,8 @@ int kqft_bubble(kqft_ctx* ctx, int channel, const kqft_vertex* left, const kqft_
  * The Hartree term of the rotated-basis loop, -L(Gamma_0, G) = U(<n> - 1/2), vanishes at
  * particle-hole symmetry and its constant U/2 is part of G (Sec. "Hartree-Fock"); Sigma
  * is the dynamic part.  sigma: device [n][4] complex (index 2*a1' + a1) on gamma->grid;
- * chi: device [2][n][16] complex or NULL.  FP64 throughout (the contraction inside Phi
- * uses opts->precision).
+ * chi: device [2][n][16] complex or NULL (when given, q_bubble->n <= 46340, else
+ * KQFT_ESHAPE).  FP64 throughout (the contraction inside Phi uses opts->precision).
  */
 int kqft_sde(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, const kqft_quad* q_bubble,
              const kqft_quad* q_loop, const kqft_opts* opts, double* sigma, double* chi, void* stream);

@@ -733,6 +733,7 @@ int kqft_sde(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, 
   int rc;
   if ((rc = check_common(ctx, G, q_bubble, opts))) return rc;
   if (!q_loop || q_loop->n < 1) return fail(KQFT_ESHAPE, "invalid loop quadrature");
+  if (chi && q_bubble->n > 46340) return fail(KQFT_ESHAPE, "chi needs q_bubble->n <= 46340");
   if ((rc = check_vertex(gamma, "gamma"))) return rc;
   if (!sigma) return fail(KQFT_EINVAL, "sigma is NULL");
   HIP_TRY(hipSetDevice(ctx->device));
@@ -771,6 +772,9 @@ int kqft_sde(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, 
     const int nb = std::max(1, std::min(n, (int)((256L << 20) / ((long)nq * 256))));
     if ((rc = ensure(ctx->pi[0], (size_t)nb * nq * 256))) return rc;
     if ((rc = ensure(ctx->chi_part, (size_t)nb * nblk * 32 * 16))) return rc;
+    // the p and t channels in the a-channel Keldysh order with its spin combinations (X, D)
+    SideTables tabs, unused;
+    if ((rc = build_tables(ctx, KQFT_CH_A, *gamma, *gamma, false, tabs, unused, s))) return rc;
     for (int iw0 = 0; iw0 < n; iw0 += nb) {
       const int cnt = std::min(nb, n - iw0);
       PiArgs pa{KQFT_CH_A, KQFT_PI_GG, cnt, nq, iw0, P, nodes, cqv, cqw, (double2*)ctx->pi[0].p};
@@ -778,8 +782,29 @@ int kqft_sde(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, 
         ProfScope ps(ctx, 0, s);
         launch_pi(pa, s);
       }
-      ChiArgs ca{to_dvert(*gamma), nq, cnt, iw0, nodes, cqv, (const double2*)ctx->pi[0].p,
-                 (double2*)ctx->chi_part.p, (double2*)chi};
+      ChiArgs ca;
+      memset(&ca, 0, sizeof ca);
+      ca.nq = nq;
+      ca.nb = cnt;
+      ca.iw0 = iw0;
+      ca.g = make_dgrid(n, gamma->grid.L, gamma->grid.a);
+      ca.r0 = gamma->r0;
+      const kqft_chvert& own = gamma->ch[KQFT_CH_A];
+      ca.coef = own.coef;
+      if (own.coef != 0.0) {
+        ca.K[0] = (const double2*)own.K1;
+        ca.K[1] = (const double2*)own.K2;
+        ca.K[2] = (const double2*)own.K2p;
+        ca.K[3] = (const double2*)own.K3;
+      }
+      ca.T[0] = tabs.T[0];
+      ca.T[1] = tabs.T[1];
+      for (int u = 0; u < 4; ++u) ca.mix[u] = kMix[KQFT_CH_A][u];
+      ca.nodes = nodes;
+      ca.qv = cqv;
+      ca.pi = (const double2*)ctx->pi[0].p;
+      ca.partial = (double2*)ctx->chi_part.p;
+      ca.out = (double2*)chi;
       {
         ProfScope ps(ctx, 3, s);
         launch_chi(ca, s);

@@ -8,13 +8,15 @@
 //                      that de-diagonalises the spin combinations into X/Y and writes
 //                      K3 (main block), K2 (last column), K2' (last row), K1 (corner)
 //   loop_kernel        Schwinger-Dyson loop reduction
-//   chi_kernel         a-channel susceptibility double sum
+//   chi_kernel         a-channel susceptibility double sum (table gathers + Pi contractions)
 //
 // The bubble (Eq. B_a and the BSEs of the paper) is written as one Keldysh-blocked
 // complex matrix product per transfer frequency: the 4x4 Keldysh matrices of the
 // paper's vectorised integrand become the innermost dimension of the product, the
 // v'' quadrature its contraction index, and the asymptotic-class split of the
 // vertex a border of one extra block row and column.
+#include <algorithm>
+
 #include "kqft_internal.h"
 #include "kqft_launch.h"
 
@@ -73,78 +75,6 @@ __global__ __launch_bounds__(256) void pi_kernel(PiArgs a) {
             v = cadd(cmul(s3[2 * a3 + a3p], g4[2 * a4 + a4p]), cmul(g3[2 * a3 + a3p], s4[2 * a4 + a4p]));
           out[4 * rp + cp] = cmul(wgt, v);
         }
-}
-
-// ======================================================================== vertex evaluation (chi)
-// Add coef * gamma_{r2}(w2, v2, vp2) for four flat indices f2[e] (channel r2 order), each
-// class interpolated multilinearly on the auxiliary variable, zero off the grid.
-__device__ inline void add_channel(const DChan& C, const DGrid& g, double w2, double v2, double vp2, const int f2[4],
-                                   double2 X[4], double2 Y[4]) {
-  int iw, iv = 0, ivp = 0;
-  double tw, tv = 0.0, tvp = 0.0;
-  if (!dgrid_locate(g, w2, iw, tw)) return;
-  bool inv = dgrid_locate(g, v2, iv, tv);
-  bool invp = dgrid_locate(g, vp2, ivp, tvp);
-  const int n = g.n;
-  const double coef = C.coef;
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    double2* acc = s ? Y : X;
-#pragma unroll
-    for (int cw = 0; cw < 2; ++cw) {
-      const double ww = coef * (cw ? tw : 1.0 - tw);
-      const size_t sw = (size_t)s * n + iw + cw;
-      if (C.K[0]) {
-        const double2* p = C.K[0] + sw * 16;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) acc[e] = cfma(ww, p[f2[e]], acc[e]);
-      }
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        if (inv && C.K[1]) {
-          const double wv = ww * (c ? tv : 1.0 - tv);
-          const double2* p = C.K[1] + (sw * n + iv + c) * 16;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) acc[e] = cfma(wv, p[f2[e]], acc[e]);
-        }
-        if (invp && C.K[2]) {
-          const double wv = ww * (c ? tvp : 1.0 - tvp);
-          const double2* p = C.K[2] + (sw * n + ivp + c) * 16;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) acc[e] = cfma(wv, p[f2[e]], acc[e]);
-        }
-        if (inv && invp && C.K[3]) {
-          const double wv = ww * (c ? tv : 1.0 - tv);
-#pragma unroll
-          for (int c2 = 0; c2 < 2; ++c2) {
-            const double wvp = wv * (c2 ? tvp : 1.0 - tvp);
-            const double2* p = C.K[3] + ((sw * n + iv + c) * n + ivp + c2) * 16;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) acc[e] = cfma(wvp, p[f2[e]], acc[e]);
-          }
-        }
-      }
-    }
-  }
-}
-
-// The two channels other than r, read through the leg frequencies of (w, v, vp) in r.
-// mode 0: the four flat indices of pair-row rc; mode 1: of pair-column rc.
-__device__ inline void add_others(const DVert& V, int r, double w, double v, double vp, int mode, int rc,
-                                  double2 X[4], double2 Y[4]) {
-  double L[4];
-  legs_of(r, w, v, vp, L);
-#pragma unroll
-  for (int d = 1; d < 3; ++d) {
-    const int r2 = (r + d) % 3;
-    if (V.ch[r2].coef == 0.0) continue;
-    double w2, v2, vp2;
-    params_of(r2, L, w2, v2, vp2);
-    int f2[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) f2[e] = c_perm[r][r2][mode == 0 ? 4 * rc + e : 4 * e + rc];
-    add_channel(V.ch[r2], V.g, w2, v2, vp2, f2, X, Y);
-  }
 }
 
 // ======================================================================== target-order tables
@@ -274,9 +204,9 @@ __device__ inline void own_tap(const double2* p, size_t sstride, int l, double w
   xy[3] = cfma(wgt, p[sstride + 8 + l], xy[3]);
 }
 
-// acc += combinations of coef * xy, plus the bare vertex on the border (r0 != 0)
-__device__ inline void own_mix(const GatherArgs& a, int l, double r0, const double2 xy[4], double2 acc[4]) {
-  const double c = a.coef;
+// acc += combinations (mix) of coef * xy, plus the bare vertex when r0 != 0
+__device__ inline void own_mix(double c, const double mix[4], int l, double r0, const double2 xy[4],
+                               double2 acc[4]) {
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int f = l + 8 * h;
@@ -284,7 +214,7 @@ __device__ inline void own_mix(const GatherArgs& a, int l, double r0, const doub
     const double bare = bare_odd(f) ? 0.5 * r0 : 0.0;  // X_R = -r0/2, Y_R = +r0/2 on odd f
 #pragma unroll
     for (int cc = 0; cc < 2; ++cc) {
-      const double m0 = a.mix[2 * cc], m1 = a.mix[2 * cc + 1];
+      const double m0 = mix[2 * cc], m1 = mix[2 * cc + 1];
       acc[2 * h + cc].x += c * (m0 * X.x + m1 * Y.x) + (m1 - m0) * bare;
       acc[2 * h + cc].y += c * (m0 * X.y + m1 * Y.y);
     }
@@ -330,6 +260,20 @@ template <int Q> __device__ inline void pi_step(const double2 acc[4], double2 P,
     const double2 x = make_double2(quad_bcast<Q>(acc[u].x), quad_bcast<Q>(acc[u].y));
     s[u] = cadd(s[u], cmul(x, P));
   }
+}
+
+// (acc . Pi)[row, m] for m = l % 4 from the quad's four q (pk = Pi entries of one node)
+__device__ inline void apply_pi(const double2* pk, int q4, double2 acc[4]) {
+  const double2 P0 = pk[q4], P1 = pk[4 + q4], P2 = pk[8 + q4], P3 = pk[12 + q4];
+  double2 s[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) s[u] = czero();
+  pi_step<0>(acc, P0, s);
+  pi_step<1>(acc, P1, s);
+  pi_step<2>(acc, P2, s);
+  pi_step<3>(acc, P3, s);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = s[u];
 }
 
 template <class T> __device__ inline void store_c(T* p, double2 v);
@@ -382,7 +326,7 @@ template <class T> __global__ __launch_bounds__(256) void gather_left_kernel(Gat
         own_tap(p, n3 * 16, l, 1.0 - t, xy);
         own_tap(p + 16, n3 * 16, l, t, xy);
       }
-      own_mix(a, l, 0.0, xy, acc);
+      own_mix(a.coef, a.mix, l, 0.0, xy, acc);
     }
 #pragma unroll
     for (int d = 0; d < 2; ++d)
@@ -398,21 +342,9 @@ template <class T> __global__ __launch_bounds__(256) void gather_left_kernel(Gat
         own_tap(p + 16, n2 * 16, l, t, xy);
       }
     }
-    own_mix(a, l, a.r0, xy, acc);
+    own_mix(a.coef, a.mix, l, a.r0, xy, acc);
   }
-  if (a.pi != nullptr) {  // (Gamma_L . Pi_k)[row, m], m = l % 4, from the quad's four q
-    const double2* pk = a.pi + ((size_t)b * a.nq + k) * 16 + q4;
-    const double2 P0 = pk[0], P1 = pk[4], P2 = pk[8], P3 = pk[12];
-    double2 s[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) s[u] = czero();
-    pi_step<0>(acc, P0, s);
-    pi_step<1>(acc, P1, s);
-    pi_step<2>(acc, P2, s);
-    pi_step<3>(acc, P3, s);
-#pragma unroll
-    for (int u = 0; u < 4; ++u) acc[u] = s[u];
-  }
+  if (a.pi != nullptr) apply_pi(a.pi + ((size_t)b * a.nq + k) * 16, q4, acc);  // (Gamma_L . Pi_k)
   store_c(o0 + off0, acc[0]);
   store_c(o1 + off0, acc[1]);
   store_c(o0 + off1, acc[2]);
@@ -463,7 +395,7 @@ template <class T> __global__ __launch_bounds__(256) void gather_right_kernel(Ga
         own_tap(p, n3 * 16, l, 1.0 - t, xy);
         own_tap(p + nn * 16, n3 * 16, l, t, xy);
       }
-      own_mix(a, l, 0.0, xy, acc);
+      own_mix(a.coef, a.mix, l, 0.0, xy, acc);
     }
 #pragma unroll
     for (int d = 0; d < 2; ++d)
@@ -479,7 +411,7 @@ template <class T> __global__ __launch_bounds__(256) void gather_right_kernel(Ga
         own_tap(p + 16, n2 * 16, l, t, xy);
       }
     }
-    own_mix(a, l, a.r0, xy, acc);
+    own_mix(a.coef, a.mix, l, a.r0, xy, acc);
   }
   store_c(o0 + off0, acc[0]);
   store_c(o1 + off0, acc[1]);
@@ -869,100 +801,120 @@ __global__ __launch_bounds__(256) void loop_kernel(LoopArgs a) {
 }
 
 // ======================================================================== chi
-// Partial sums z(k, row)[m] = sum_l sum_q Gamma_c(w; v''_k, v''_l)[row, q] Pi_l[q, m] for
-// c in {X, D = X + 2Y}, then chi(w)[p, m] = sum_k Pi_k[p, row] z(k, row)[m].  One thread per
-// (k, row); per-block partials, reduced in fixed order by chi_finalize_kernel.
-__device__ inline void full_vertex_row(const DVert& V, int r, int iw, double w, double v, double vp, int row,
-                                       double2 X[4], double2 Y[4]) {
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    X[e] = Y[e] = czero();
-    if (bare_odd(4 * row + e)) {
-      X[e].x -= 0.5 * V.r0;
-      Y[e].x += 0.5 * V.r0;
-    }
-  }
-  int f[4];
-#pragma unroll
-  for (int e = 0; e < 4; ++e) f[e] = 4 * row + e;
-  if (V.ch[r].coef != 0.0) add_channel(V.ch[r], V.g, w, v, vp, f, X, Y);
-  add_others(V, r, w, v, vp, 0, row, X, Y);
-}
-
+// chi_a^c(w)[p, m] = sum_k Pi_k[p, m]
+//   + sum_{k,l} sum_{row,q} Pi_k[p, row] Gamma_c(w; v''_k, v''_l)[row, q] Pi_l[q, m]
+// for c in {X, D = X + 2Y} (the a-channel spin combinations), Pi with the weights folded in.
+// One 8-lane group per node pair (k, l), grid-stride over the pairs of one transfer
+// frequency.  Lane l8 evaluates the full vertex (bare part, own classes, the other channels
+// through their target-order tables) at f = l8, l8 + 8 -- rows l8/4 and 2 + l8/4, column
+// q = l8 % 4 -- multiplies by Pi_l from the right through quad broadcasts and by Pi_k from
+// the left for its two rows.  Per-lane partial sums, reduced over the block in a fixed tree;
+// chi_finalize_kernel adds the per-block partials in fixed order (deterministic).
 __global__ __launch_bounds__(256) void chi_kernel(ChiArgs a) {
-  const int iw = a.iw0 + blockIdx.y;
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int row = tid & 3, k = tid >> 2;
-  double2 part[2][16];
+  const int b = blockIdx.y, iw = a.iw0 + b;
+  const int l8 = threadIdx.x & 7, h = l8 >> 2, q4 = l8 & 3;
+  // 32-bit indices: the host keeps nq * nq below 2^31
+  const unsigned grp = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const unsigned ngrp = (gridDim.x * blockDim.x) >> 3;
+  const unsigned total = (unsigned)a.nq * (unsigned)a.nq;
+  const int n = a.g.n;
+  const size_t nn = n, n2 = nn * nn, n3 = n2 * nn;
+  const double w = a.nodes[iw];
+  const double2* pis = a.pi + (size_t)b * a.nq * 16;
+  double2 part[2][4];  // [combination][p] for m = q4, rows h and 2 + h
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int f = 0; f < 16; ++f) part[c][f] = czero();
-  if (k < a.nq) {
-    const double w = a.nodes[iw];
-    const double vk = a.qv[k];
-    const double2* pis = a.pi + (size_t)blockIdx.y * a.nq * 16;
-    double2 z[2][4];
+    for (int p = 0; p < 4; ++p) part[c][p] = czero();
+  for (unsigned t = grp; t < total; t += ngrp) {
+    const int kq = (int)(t / (unsigned)a.nq), lq = (int)(t - (unsigned)kq * (unsigned)a.nq);
+    const double vk = a.qv[kq], vl = a.qv[lq];
+    // grid locations: lane 0 v''_k, lane 1 v''_l, lanes 2-4 / 5-7 (w, v, v') of channels p / t
+    double arg = l8 == 0 ? vk : vl;
+    if (l8 >= 2) {
+      double L[4];
+      legs_of(0, w, vk, vl, L);
+      const int d = l8 <= 4 ? 1 : 2, which = (l8 - 2) % 3;
+      double w2, v2, vp2;
+      params_of(d, L, w2, v2, vp2);
+      arg = which == 0 ? w2 : (which == 1 ? v2 : vp2);
+    }
+    int ic;
+    double tc;
+    if (!dgrid_locate(a.g, arg, ic, tc)) {
+      ic = -1;
+      tc = 0.0;
+    }
+    const int i0 = __shfl(ic, 0, 8), j0 = __shfl(ic, 1, 8);
+    const double ti = __shfl(tc, 0, 8), tj = __shfl(tc, 1, 8);
+    double2 acc[4], xy[4];
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int u = 0; u < 4; ++u) acc[u] = xy[u] = czero();
+    if (a.coef != 0.0) {  // own channel: K1(w) + K2(w, v''_k) + K2'(w, v''_l) + K3(w, v''_k, v''_l)
+      if (a.K[0]) own_tap(a.K[0] + (size_t)iw * 16, nn * 16, l8, 1.0, xy);
+      if (a.K[1] && i0 >= 0) {
+        const double2* p = a.K[1] + ((size_t)iw * nn + i0) * 16;
+        own_tap(p, n2 * 16, l8, 1.0 - ti, xy);
+        own_tap(p + 16, n2 * 16, l8, ti, xy);
+      }
+      if (a.K[2] && j0 >= 0) {
+        const double2* p = a.K[2] + ((size_t)iw * nn + j0) * 16;
+        own_tap(p, n2 * 16, l8, 1.0 - tj, xy);
+        own_tap(p + 16, n2 * 16, l8, tj, xy);
+      }
+      if (a.K[3] && i0 >= 0 && j0 >= 0) {
 #pragma unroll
-      for (int m = 0; m < 4; ++m) z[c][m] = czero();
-    for (int l = 0; l < a.nq; ++l) {
-      double2 X[4], Y[4];
-      full_vertex_row(a.V, 0, iw, w, vk, a.qv[l], row, X, Y);
-      const double2* pl = pis + (size_t)l * 16;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const double2 gx = X[q];
-        const double2 gd = make_double2(X[q].x + 2.0 * Y[q].x, X[q].y + 2.0 * Y[q].y);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const double2 pv = pl[4 * q + m];
-          z[0][m] = cadd(z[0][m], cmul(gx, pv));
-          z[1][m] = cadd(z[1][m], cmul(gd, pv));
+        for (int ci = 0; ci < 2; ++ci) {
+          const double2* p = a.K[3] + (((size_t)iw * nn + i0 + ci) * nn + j0) * 16;
+          const double wi = ci ? ti : 1.0 - ti;
+          own_tap(p, n3 * 16, l8, wi * (1.0 - tj), xy);
+          own_tap(p + 16, n3 * 16, l8, wi * tj, xy);
         }
       }
     }
-    const double2* pk = pis + (size_t)k * 16;
+    own_mix(a.coef, a.mix, l8, a.r0, xy, acc);
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+      if (a.T[d]) {
+        const int s0 = 2 + 3 * d;
+        table_taps((const double2*)a.T[d], n, __shfl(ic, s0, 8), __shfl(tc, s0, 8), __shfl(ic, s0 + 1, 8),
+                   __shfl(tc, s0 + 1, 8), __shfl(ic, s0 + 2, 8), __shfl(tc, s0 + 2, 8), l8, acc);
+      }
+    apply_pi(pis + (size_t)lq * 16, q4, acc);  // (Gamma . Pi_l)[row, m]
+    const double2* pk = pis + (size_t)kq * 16;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-      const double2 pp = pk[4 * p + row];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        part[0][4 * p + m] = cmul(pp, z[0][m]);
-        part[1][4 * p + m] = cmul(pp, z[1][m]);
-      }
-    }
-    if (row == 0) {  // the bare bubble term sum_k Pi_k, once per k
-#pragma unroll
-      for (int f = 0; f < 16; ++f) {
-        part[0][f] = cadd(part[0][f], pk[f]);
-        part[1][f] = cadd(part[1][f], pk[f]);
-      }
+      const double2 P0 = pk[4 * p + h], P1 = pk[4 * p + 2 + h];
+      part[0][p] = cadd(part[0][p], cadd(cmul(P0, acc[0]), cmul(P1, acc[2])));
+      part[1][p] = cadd(part[1][p], cadd(cmul(P0, acc[1]), cmul(P1, acc[3])));
     }
   }
-  __shared__ double2 red[4][32];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // rows h = 0, 1 (lanes l8, l8 ^ 4), then the eight groups of the wave
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int f = 0; f < 16; ++f) {
-      double2 s = part[c][f];
+    for (int p = 0; p < 4; ++p)
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        s.x += __shfl_xor(s.x, o);
-        s.y += __shfl_xor(s.y, o);
+      for (int o = 4; o < 64; o <<= 1) {
+        part[c][p].x += __shfl_xor(part[c][p].x, o);
+        part[c][p].y += __shfl_xor(part[c][p].y, o);
       }
-      if (lane == 0) red[wave][c * 16 + f] = s;
-    }
+  __shared__ double2 red[4][32];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane < 4)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int p = 0; p < 4; ++p) red[wave][c * 16 + 4 * p + lane] = part[c][p];
   __syncthreads();
   if (threadIdx.x < 32) {
     double2 s = czero();
-    for (int w = 0; w < 4; ++w) s = cadd(s, red[w][threadIdx.x]);
-    a.partial[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 32 + threadIdx.x] = s;
+    for (int wv = 0; wv < 4; ++wv) s = cadd(s, red[wv][threadIdx.x]);
+    a.partial[((size_t)b * gridDim.x + blockIdx.x) * 32 + threadIdx.x] = s;
   }
 }
 
+// out[c][w][f] = sum of the block partials (fixed order) + sum_k Pi_k[f]
 __global__ void chi_finalize_kernel(ChiArgs a, int nblk) {
   const int b = blockIdx.x;  // transfer frequency within the batch
   const int e = threadIdx.x; // 0..31 = c*16 + f
@@ -970,7 +922,9 @@ __global__ void chi_finalize_kernel(ChiArgs a, int nblk) {
   double2 s = czero();
   for (int k = 0; k < nblk; ++k) s = cadd(s, a.partial[((size_t)b * nblk + k) * 32 + e]);
   const int c = e >> 4, f = e & 15;
-  a.out[((size_t)c * a.V.g.n + a.iw0 + b) * 16 + f] = s;
+  const double2* pis = a.pi + (size_t)b * a.nq * 16;
+  for (int k = 0; k < a.nq; ++k) s = cadd(s, pis[(size_t)k * 16 + f]);
+  a.out[((size_t)c * a.g.n + a.iw0 + b) * 16 + f] = s;
 }
 
 // ======================================================================== adjoint
@@ -1588,7 +1542,7 @@ void launch_loop(const LoopArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(loop_kernel, dim3(a.g.n), dim3(256), 0, s, a);
 }
 void launch_chi(const ChiArgs& a, hipStream_t s) {
-  const int nblk = (int)blocks_for((long)a.nq * 4, 256);
+  const int nblk = chi_blocks(a.nq);
   hipLaunchKernelGGL(chi_kernel, dim3(nblk, a.nb), dim3(256), 0, s, a);
   hipLaunchKernelGGL(chi_finalize_kernel, dim3(a.nb), dim3(64), 0, s, a, nblk);
 }
@@ -1616,6 +1570,6 @@ void launch_unfuse(const UnfuseArgs& a, hipStream_t s) {
   if (a.dK2p) hipLaunchKernelGGL(unfuse_kernel, dim3(1024), dim3(256), 0, s, a, 2);
   if (a.dK1) hipLaunchKernelGGL(unfuse_kernel, dim3(64), dim3(256), 0, s, a, 0);
 }
-int chi_blocks(int nq) { return (int)blocks_for((long)nq * 4, 256); }
+int chi_blocks(int nq) { return (int)std::min<long>(512, std::max<long>(1, ((long)nq * nq + 255) / 256)); }
 
 }  // namespace kqft

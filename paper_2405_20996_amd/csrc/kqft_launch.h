@@ -66,8 +66,13 @@ struct LoopArgs {
 };
 
 struct ChiArgs {
-  DVert V;
   int nq, nb, iw0;
+  DGrid g;
+  double r0;
+  double coef;          // channel a coefficient
+  const double2* K[4];  // channel a K1, K2, K2', K3 (nullptr = absent)
+  const void* T[2];     // FP64 target-order tables of channels p and t (nullptr = inactive)
+  double mix[4];        // the a-channel spin combinations (X, X + 2Y)
   const double* nodes;
   const double* qv;
   const double2* pi;  // [nb][nq][16], channel a, Pi = G G, weights folded
