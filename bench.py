@@ -28,20 +28,24 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 KERNEL_SRC = os.path.join(ROOT, "paper_2405_20996_amd", "csrc", "kqft_kernels.hip")
 # HBM bytes per GEMM launch from two rocprofv3 --pmc passes over this workload (FETCH_SIZE
 # x 2.000 and WRITE_SIZE x 1.000, the factors that make a 1 GiB device copy read and write
-# 1 GiB), valid for the kernel source they were taken on (first 16 hex digits of its
-# SHA-256) and the batch of 67 transfer frequencies.
+# 1 GiB), valid for the GEMM source they were taken on (first 16 hex digits of the SHA-256
+# of the kernel file's GEMM section) and the batch of 67 transfer frequencies.
 MEASURED_TRAFFIC = {
-    "zgemm_f32_kernel": {"src": "4166f860150c6d56", "omega_batch": 67, "n": 201, "nq": 2001,
+    "zgemm_f32_kernel": {"src": "a8b5e0f131787fde", "omega_batch": 67, "n": 201, "nq": 2001,
                          "read_bytes": 87.934e9, "write_bytes": 1.400e9},
-    "zgemm_f64_kernel": {"src": "4166f860150c6d56", "omega_batch": 67, "n": 201, "nq": 2001,
+    "zgemm_f64_kernel": {"src": "a8b5e0f131787fde", "omega_batch": 67, "n": 201, "nq": 2001,
                          "read_bytes": 236.032e9, "write_bytes": 1.504e9},
 }
 
 
 def kernel_src_digest() -> str:
+    """Digest of the GEMM section of the kernel source (epilogue, tile order, both GEMMs)."""
     import hashlib
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    with open(KERNEL_SRC, "r", encoding="utf-8") as f:
+        src = f.read()
+    a = src.index("// ======================================================================== epilogue")
+    b = src.index("// ======================================================================== SDE loop")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
 def measured_traffic(kernel, n, nq, omega_batch):
