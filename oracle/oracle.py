@@ -411,3 +411,64 @@ def dual_parts(d: np.ndarray):
 def dual_vertex(V: Vertex, dr0: float = 0.0) -> Vertex:
     chans = [Channel(c.coef, *[to_dual(getattr(c, k)) for k in ("K1", "K2", "K2p", "K3")]) for c in V.ch]
     return Vertex(V.grid, V.r0, chans, dr0=dr0)
+
+
+# ------------------------------------------------------------------ parquet iteration
+CLASSES = ("K1", "K2", "K2p", "K3")
+
+
+def sigma_prop(grid: Grid, Delta: float, T: float, sigma: Optional[np.ndarray]) -> Prop:
+    """Propagator with a dynamic self-energy given on the vertex grid as [n, 4] (index 2*a'+a:
+    Sigma^K at 0, Sigma^R at 1), linearly interpolated on the auxiliary variable."""
+    if sigma is None:
+        return Prop(Delta, T)
+    return Prop(Delta, T, sigma_grid=grid, SigR=np.ascontiguousarray(sigma[:, 1]),
+                SigK=np.ascontiguousarray(sigma[:, 0]))
+
+
+def parquet_iteration(V: Vertex, P: Prop, q_bubble: Quad, q_loop: Quad):
+    """Right-hand sides of the parquet equations for the state (Gamma, Sigma) (Sec. parquet
+    solver): the Bethe-Salpeter equations gamma_r = I_r Pi_r Gamma with the irreducible vertex
+    I_r = Gamma - gamma_r, symmetrized as 1/2 [B_r(I_r, Gamma) + B_r(Gamma, I_r)], and the
+    Schwinger-Dyson equation (a-channel form) for Sigma.  P carries Sigma of the state.
+    Returns ([gamma_a', gamma_p', gamma_t'] as Channels, Sigma' [n, 4])."""
+    g = V.grid
+    out = []
+    for r in range(3):
+        ir = Vertex(g, V.r0, [V.ch[rr] if rr != r else Channel(0.0) for rr in range(3)])
+        a = bubble(r, ir, V, P, q_bubble)
+        b = bubble(r, V, ir, P, q_bubble)
+        out.append(Channel(1.0, *[0.5 * (getattr(a, c) + getattr(b, c)) for c in CLASSES]))
+    return out, sde(V, P, q_bubble, q_loop)
+
+
+def parquet_solve(grid: Grid, U: float, Delta: float, T: float, q_bubble: Quad, q_loop: Quad,
+                  alpha: float = 0.5, iterations: int = 10, tol: float = 0.0):
+    """Parquet solver with linear mixing (Sec. parquet solver): start from PT2 (vertex K1 in
+    every channel, Sigma^(2) from the SDE of Gamma_0), then x <- x + alpha (F(x) - x) for the
+    three channels and Sigma, until the relative max-norm change max over arrays of
+    ||F(x) - x|| / ||F(x)|| falls below tol or after `iterations` steps.
+    Returns (channels, Sigma, residuals per step)."""
+    P0 = Prop(Delta, T)
+    k1 = pt2_k1(grid, U, P0, q_bubble)
+    chans = [Channel(1.0, k1[r], np.zeros((2, grid.n, grid.n, 16), complex),
+                     np.zeros((2, grid.n, grid.n, 16), complex), np.zeros((2, grid.n, grid.n, grid.n, 16), complex))
+             for r in range(3)]
+    sigma = sde(bare(grid, U), P0, q_bubble, q_loop)
+    res = []
+    for _ in range(iterations):
+        V = Vertex(grid, U, chans)
+        new, snew = parquet_iteration(V, sigma_prop(grid, Delta, T, sigma), q_bubble, q_loop)
+        r_ = 0.0
+        for r in range(3):
+            for c in CLASSES:
+                x, f = getattr(chans[r], c), getattr(new[r], c)
+                r_ = max(r_, float(np.abs(f - x).max() / max(np.abs(f).max(), 1e-300)))
+        r_ = max(r_, float(np.abs(snew - sigma).max() / max(np.abs(snew).max(), 1e-300)))
+        res.append(r_)
+        chans = [Channel(1.0, *[getattr(chans[r], c) + alpha * (getattr(new[r], c) - getattr(chans[r], c))
+                                for c in CLASSES]) for r in range(3)]
+        sigma = sigma + alpha * (snew - sigma)
+        if r_ < tol:
+            break
+    return chans, sigma, res
