@@ -192,6 +192,37 @@ int kqft_sde(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, 
              const kqft_quad* q_loop, const kqft_opts* opts, double* sigma, double* chi, void* stream);
 
 /*
+ * kqft_parquet_iteration -- right-hand sides of the parquet equations (Sec. "parquet
+ * solver"; BSEs and Eq. SDE) for the state (gamma, Sigma in G):
+ *   gamma_r' = 1/2 [B_r(I_r, Gamma) + B_r(Gamma, I_r)],  I_r = Gamma without channel r
+ *              (the symmetrized Bethe-Salpeter equations, r = a, p, t),
+ *   Sigma'   = the Schwinger-Dyson self-energy of Gamma (a-channel form, as kqft_sde),
+ * Gamma = Gamma_0(r0) + sum_r coef_r gamma_r.  gamma_out[3]: device arrays of the three
+ * channels (all four classes required; must not alias the inputs); sigma_out: device
+ * [n][4] complex.  Bubbles in opts->precision, Sigma in FP64.
+ */
+int kqft_parquet_iteration(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G,
+                           const kqft_quad* q_bubble, const kqft_quad* q_loop, const kqft_opts* opts,
+                           const kqft_chout* gamma_out, double* sigma_out, void* stream);
+
+/*
+ * kqft_parquet_solve -- parquet solver with linear mixing (Sec. "parquet solver"): starts
+ * from the PT2 state (gamma_r = K1_r = B_r(Gamma_0, Gamma_0), Sigma = SDE(Gamma_0) with the
+ * bare propagator), then x <- x + alpha (F(x) - x) for the three channels and Sigma, where
+ * F is kqft_parquet_iteration with the propagator dressed by the state's Sigma (Sigma^R and
+ * Sigma^K on `grid`, Delta and T of the bath, eps = 0).  Stops when the relative change
+ * max over arrays of max|F(x) - x| / max|F(x)| falls below tol or after max_iterations.
+ * gamma[3] (device, out): the channels of the final state; sigma (device [n][4], out);
+ * residuals (host [max_iterations] or NULL): the relative change of every iteration;
+ * iterations (host, out): iterations done.  Synchronises `stream` once per iteration.
+ * 0 < alpha <= 1 and max_iterations >= 1, else KQFT_EINVAL.
+ */
+int kqft_parquet_solve(kqft_ctx* ctx, const kqft_grid* grid, double U, double Delta, double T,
+                       const kqft_quad* q_bubble, const kqft_quad* q_loop, const kqft_opts* opts, double alpha,
+                       int max_iterations, double tol, const kqft_chout* gamma, double* sigma, double* residuals,
+                       int* iterations, void* stream);
+
+/*
  * kqft_mloop_step -- multiloop insertions of the mfRG flow (Eqs. 1l, 2l, 3l) for
  * n_points independent parameter points (ragged sizes allowed):
  *   l = 1:  gdot_r = B_r(Gamma, Gamma; Pidot),

@@ -42,7 +42,7 @@ struct kqft_ctx {
   // consecutive transfer-frequency batches overlap, ordered by events
   hipStream_t sg = nullptr, sm = nullptr;
   rocblas_handle blas = nullptr;
-  DevBuf adjw, dkf[2][3], phigrad;
+  DevBuf adjw, dkf[2][3], phigrad, pq, pqsig, pqred;
   std::vector<hipEvent_t> events;
   size_t next_event = 0;
   bool prof = false;
@@ -348,7 +348,8 @@ static GatherArgs make_gather(int r, int nb, int iw0, int nq, int nq_pad, int lo
 }
 
 static int bubble_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_vertex& R, const kqft_propagator& G,
-                       int kind, const kqft_quad& q, const kqft_opts& o, const BubbleOut& out, hipStream_t s) {
+                       int kind, const kqft_quad& q, const kqft_opts& o, const BubbleOut& out, hipStream_t s,
+                       double scale = 1.0) {
   int rc;
   const int n = L.grid.n;
   if ((rc = init_tables())) return rc;
@@ -439,7 +440,7 @@ static int bubble_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_ve
     g.iw0 = iw0;
     g.beta = o.beta;
     g.cmask = mask;
-    for (int u = 0; u < 4; ++u) g.unmix[u] = kUnmix[r][u];
+    for (int u = 0; u < 4; ++u) g.unmix[u] = scale * kUnmix[r][u];  // output scale folded in
     g.K1 = out.K1;
     g.K2 = out.K2;
     g.K2p = out.K2p;
@@ -620,6 +621,134 @@ static int adjoint_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_v
 }
 
 // ------------------------------------------------------------------ C ABI
+// Sigma (and chi when given) of the vertex `gamma` (the body of kqft_sde; arguments checked).
+static int sde_core(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, const kqft_quad* q_bubble,
+                    const kqft_quad* q_loop, const kqft_opts* opts, double* sigma, double* chi, hipStream_t s) {
+  int rc;
+  const int n = gamma->grid.n;
+  // Phi = B_a(Gamma_0, Gamma): classes K1 and K2' only
+  const size_t k1b = (size_t)2 * n * 16 * 16, k2b = (size_t)2 * n * n * 16 * 16;
+  if ((rc = ensure(ctx->phi, k1b + k2b))) return rc;
+  double2* phiK1 = (double2*)ctx->phi.p;
+  double2* phiK2p = (double2*)((char*)ctx->phi.p + k1b);
+  kqft_vertex bare;
+  memset(&bare, 0, sizeof bare);
+  bare.r0 = gamma->r0;
+  bare.grid = gamma->grid;
+  kqft_opts o = *opts;
+  o.class_mask = KQFT_K1 | KQFT_K2P;
+  o.beta = 0;
+  BubbleOut po{phiK1, nullptr, phiK2p, nullptr};
+  if ((rc = bubble_core(ctx, KQFT_CH_A, bare, *gamma, *G, KQFT_PI_GG, *q_bubble, o, po, s))) return rc;
+  const double *nodes, *qv, *qw;
+  if ((rc = get_grid(ctx, gamma->grid, &nodes))) return rc;
+  if ((rc = get_quad(ctx, *q_loop, &qv, &qw))) return rc;
+  DProp P;
+  if ((rc = to_dprop(*G, P))) return rc;
+  LoopArgs la{make_dgrid(n, gamma->grid.L, gamma->grid.a), P, 0, q_loop->n, nodes, qv, qw, phiK1, phiK2p,
+              (double2*)sigma};
+  {
+    ProfScope ps(ctx, 3, s);
+    launch_loop(la, s);
+  }
+  if (chi) {
+    const double *cqv, *cqw;
+    if ((rc = get_quad(ctx, *q_bubble, &cqv, &cqw))) return rc;
+    const int nq = q_bubble->n;
+    const int nblk = chi_blocks(nq);
+    const int nb = std::max(1, std::min(n, (int)((256L << 20) / ((long)nq * 256))));
+    if ((rc = ensure(ctx->pi[0], (size_t)nb * nq * 256))) return rc;
+    if ((rc = ensure(ctx->chi_part, (size_t)nb * nblk * 32 * 16))) return rc;
+    // the p and t channels in the a-channel Keldysh order with its spin combinations (X, D)
+    SideTables tabs, unused;
+    if ((rc = build_tables(ctx, KQFT_CH_A, *gamma, *gamma, false, tabs, unused, s))) return rc;
+    for (int iw0 = 0; iw0 < n; iw0 += nb) {
+      const int cnt = std::min(nb, n - iw0);
+      PiArgs pa{KQFT_CH_A, KQFT_PI_GG, cnt, nq, iw0, P, nodes, cqv, cqw, (double2*)ctx->pi[0].p};
+      {
+        ProfScope ps(ctx, 0, s);
+        launch_pi(pa, s);
+      }
+      ChiArgs ca;
+      memset(&ca, 0, sizeof ca);
+      ca.nq = nq;
+      ca.nb = cnt;
+      ca.iw0 = iw0;
+      ca.g = make_dgrid(n, gamma->grid.L, gamma->grid.a);
+      ca.r0 = gamma->r0;
+      const kqft_chvert& own = gamma->ch[KQFT_CH_A];
+      ca.coef = own.coef;
+      if (own.coef != 0.0) {
+        ca.K[0] = (const double2*)own.K1;
+        ca.K[1] = (const double2*)own.K2;
+        ca.K[2] = (const double2*)own.K2p;
+        ca.K[3] = (const double2*)own.K3;
+      }
+      ca.T[0] = tabs.T[0];
+      ca.T[1] = tabs.T[1];
+      for (int u = 0; u < 4; ++u) ca.mix[u] = kMix[KQFT_CH_A][u];
+      ca.nodes = nodes;
+      ca.qv = cqv;
+      ca.pi = (const double2*)ctx->pi[0].p;
+      ca.partial = (double2*)ctx->chi_part.p;
+      ca.out = (double2*)chi;
+      {
+        ProfScope ps(ctx, 3, s);
+        launch_chi(ca, s);
+      }
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  return KQFT_OK;
+}
+
+// ------------------------------------------------------------------ parquet
+// Right-hand sides of the parquet equations for the state `V` (Sec. parquet solver): the
+// symmetrized Bethe-Salpeter equations gamma_r' = 1/2 [B_r(I_r, Gamma) + B_r(Gamma, I_r)],
+// I_r = Gamma without channel r, and Sigma' from the Schwinger-Dyson equation.
+static int parquet_core(kqft_ctx* ctx, const kqft_vertex& V, const kqft_propagator& G, const kqft_quad& qb,
+                        const kqft_quad& ql, const kqft_opts& opts, const BubbleOut out[3], double* sigma_out,
+                        hipStream_t s) {
+  int rc;
+  kqft_opts o = opts;
+  o.class_mask = KQFT_KALL;
+  for (int r = 0; r < 3; ++r) {
+    kqft_vertex I = V;
+    I.ch[r] = kqft_chvert{0.0, nullptr, nullptr, nullptr, nullptr};
+    o.beta = 0;
+    if ((rc = bubble_core(ctx, r, I, V, G, KQFT_PI_GG, qb, o, out[r], s, 0.5))) return rc;
+    o.beta = 1;
+    if ((rc = bubble_core(ctx, r, V, I, G, KQFT_PI_GG, qb, o, out[r], s, 0.5))) return rc;
+  }
+  return sde_core(ctx, &V, &G, &qb, &ql, &opts, sigma_out, nullptr, s);
+}
+
+// max over the arrays of max|f - x| / max|f| (each array reduced on the device, the last
+// step on the host after a stream synchronisation)
+static int rel_change(kqft_ctx* ctx, const std::vector<std::pair<const double2*, const double2*>>& xf,
+                      const std::vector<size_t>& counts, hipStream_t s, double* out) {
+  const int nblk = 256;
+  int rc;
+  if ((rc = ensure(ctx->pqred, xf.size() * nblk * 2 * sizeof(double)))) return rc;
+  double* part = (double*)ctx->pqred.p;
+  for (size_t a = 0; a < xf.size(); ++a) launch_maxdiff(xf[a].first, xf[a].second, counts[a], part + a * nblk * 2, nblk, s);
+  std::vector<double> h(xf.size() * nblk * 2);
+  HIP_TRY(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  double worst = 0.0;
+  for (size_t a = 0; a < xf.size(); ++a) {
+    double md = 0.0, mf = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+      md = std::max(md, h[(a * nblk + b) * 2]);
+      mf = std::max(mf, h[(a * nblk + b) * 2 + 1]);
+    }
+    if (mf > 0.0) worst = std::max(worst, md / mf);
+    else if (md > 0.0) worst = std::max(worst, 1.0);
+  }
+  *out = worst;
+  return KQFT_OK;
+}
+
 extern "C" {
 
 const char* kqft_last_error(void) { return g_err.c_str(); }
@@ -661,6 +790,8 @@ int kqft_ctx_destroy(kqft_ctx* ctx) {
     for (auto& b : row)
       if (b.p) (void)hipFree(b.p);
   if (ctx->adjw.p) (void)hipFree(ctx->adjw.p);
+  for (DevBuf* b : {&ctx->pq, &ctx->pqsig, &ctx->pqred})
+    if (b->p) (void)hipFree(b->p);
   if (ctx->phigrad.p) (void)hipFree(ctx->phigrad.p);
   if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
   if (ctx->sg) (void)hipStreamDestroy(ctx->sg);
@@ -737,80 +868,128 @@ int kqft_sde(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, 
   if ((rc = check_vertex(gamma, "gamma"))) return rc;
   if (!sigma) return fail(KQFT_EINVAL, "sigma is NULL");
   HIP_TRY(hipSetDevice(ctx->device));
+  return sde_core(ctx, gamma, G, q_bubble, q_loop, opts, sigma, chi, (hipStream_t)stream);
+}
+
+int kqft_parquet_iteration(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G,
+                           const kqft_quad* q_bubble, const kqft_quad* q_loop, const kqft_opts* opts,
+                           const kqft_chout* gamma_out, double* sigma_out, void* stream) {
+  int rc;
+  if ((rc = check_common(ctx, G, q_bubble, opts))) return rc;
+  if (!q_loop || q_loop->n < 1) return fail(KQFT_ESHAPE, "invalid loop quadrature");
+  if ((rc = check_vertex(gamma, "gamma"))) return rc;
+  if (!gamma_out || !sigma_out) return fail(KQFT_EINVAL, "gamma_out and sigma_out must be given");
+  for (int r = 0; r < 3; ++r)
+    if (!gamma_out[r].K1 || !gamma_out[r].K2 || !gamma_out[r].K2p || !gamma_out[r].K3)
+      return fail(KQFT_EINVAL, "gamma_out arrays must all be given");
+  HIP_TRY(hipSetDevice(ctx->device));
+  BubbleOut out[3];
+  for (int r = 0; r < 3; ++r)
+    out[r] = BubbleOut{(double2*)gamma_out[r].K1, (double2*)gamma_out[r].K2, (double2*)gamma_out[r].K2p,
+                       (double2*)gamma_out[r].K3};
+  return parquet_core(ctx, *gamma, *G, *q_bubble, *q_loop, *opts, out, sigma_out, (hipStream_t)stream);
+}
+
+int kqft_parquet_solve(kqft_ctx* ctx, const kqft_grid* grid, double U, double Delta, double T,
+                       const kqft_quad* q_bubble, const kqft_quad* q_loop, const kqft_opts* opts, double alpha,
+                       int max_iterations, double tol, const kqft_chout* gamma, double* sigma, double* residuals,
+                       int* iterations, void* stream) {
+  int rc;
+  if (!grid || (rc = check_grid(*grid, "grid"))) return grid ? rc : fail(KQFT_EINVAL, "grid is NULL");
+  kqft_propagator G0;
+  memset(&G0, 0, sizeof G0);
+  G0.Delta = Delta;
+  G0.T = T;
+  G0.sgrid = *grid;
+  if ((rc = check_common(ctx, &G0, q_bubble, opts))) return rc;
+  if (!q_loop || q_loop->n < 1) return fail(KQFT_ESHAPE, "invalid loop quadrature");
+  if (!(Delta > 0) || !(T > 0)) return fail(KQFT_EINVAL, "Delta and T must be positive");
+  if (!(alpha > 0) || alpha > 1 || max_iterations < 1) return fail(KQFT_EINVAL, "need 0 < alpha <= 1, max_iterations >= 1");
+  if (!gamma || !sigma || !iterations) return fail(KQFT_EINVAL, "gamma, sigma and iterations must be given");
+  for (int r = 0; r < 3; ++r)
+    if (!gamma[r].K1 || !gamma[r].K2 || !gamma[r].K2p || !gamma[r].K3)
+      return fail(KQFT_EINVAL, "gamma arrays must all be given");
+  HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
-  const int n = gamma->grid.n;
-  // Phi = B_a(Gamma_0, Gamma): classes K1 and K2' only
-  const size_t k1b = (size_t)2 * n * 16 * 16, k2b = (size_t)2 * n * n * 16 * 16;
-  if ((rc = ensure(ctx->phi, k1b + k2b))) return rc;
-  double2* phiK1 = (double2*)ctx->phi.p;
-  double2* phiK2p = (double2*)((char*)ctx->phi.p + k1b);
+  const int n = grid->n;
+  const size_t c1 = (size_t)2 * n * 16, c2 = (size_t)2 * n * n * 16, c3 = (size_t)2 * n * n * n * 16;
+  const size_t cnt[4] = {c1, c2, c2, c3};
+  const size_t chb = (c1 + 2 * c2 + c3) * sizeof(double2);
+  // F(x): three channels, then Sigma [n][4]; Sigma^R, Sigma^K of the state
+  if ((rc = ensure(ctx->pq, 3 * chb + (size_t)n * 4 * sizeof(double2)))) return rc;
+  if ((rc = ensure(ctx->pqsig, (size_t)2 * n * sizeof(double2)))) return rc;
+  char* fb = (char*)ctx->pq.p;
+  BubbleOut F[3];
+  double2* Fx[3][4];
+  for (int r = 0; r < 3; ++r) {
+    double2* base = (double2*)(fb + r * chb);
+    Fx[r][0] = base;
+    Fx[r][1] = base + c1;
+    Fx[r][2] = base + c1 + c2;
+    Fx[r][3] = base + c1 + 2 * c2;
+    F[r] = BubbleOut{Fx[r][0], Fx[r][1], Fx[r][2], Fx[r][3]};
+  }
+  double* Fsig = (double*)(fb + 3 * chb);
+  double2* sigR = (double2*)ctx->pqsig.p;
+  double2* sigK = sigR + n;
+  double2* X[3][4];
+  for (int r = 0; r < 3; ++r) {
+    X[r][0] = (double2*)gamma[r].K1;
+    X[r][1] = (double2*)gamma[r].K2;
+    X[r][2] = (double2*)gamma[r].K2p;
+    X[r][3] = (double2*)gamma[r].K3;
+  }
+  // PT2 start: K1_r = B_r(Gamma_0, Gamma_0), Sigma^(2) = SDE(Gamma_0) with the bare propagator
   kqft_vertex bare;
   memset(&bare, 0, sizeof bare);
-  bare.r0 = gamma->r0;
-  bare.grid = gamma->grid;
+  bare.r0 = U;
+  bare.grid = *grid;
+  for (int r = 0; r < 3; ++r)
+    for (int c = 1; c < 4; ++c) HIP_TRY(hipMemsetAsync(X[r][c], 0, cnt[c] * sizeof(double2), s));
   kqft_opts o = *opts;
-  o.class_mask = KQFT_K1 | KQFT_K2P;
   o.beta = 0;
-  BubbleOut po{phiK1, nullptr, phiK2p, nullptr};
-  if ((rc = bubble_core(ctx, KQFT_CH_A, bare, *gamma, *G, KQFT_PI_GG, *q_bubble, o, po, s))) return rc;
-  const double *nodes, *qv, *qw;
-  if ((rc = get_grid(ctx, gamma->grid, &nodes))) return rc;
-  if ((rc = get_quad(ctx, *q_loop, &qv, &qw))) return rc;
-  DProp P;
-  if ((rc = to_dprop(*G, P))) return rc;
-  LoopArgs la{make_dgrid(n, gamma->grid.L, gamma->grid.a), P, 0, q_loop->n, nodes, qv, qw, phiK1, phiK2p,
-              (double2*)sigma};
-  {
-    ProfScope ps(ctx, 3, s);
-    launch_loop(la, s);
+  o.class_mask = KQFT_K1;
+  for (int r = 0; r < 3; ++r) {
+    BubbleOut k1{X[r][0], nullptr, nullptr, nullptr};
+    if ((rc = bubble_core(ctx, r, bare, bare, G0, KQFT_PI_GG, *q_bubble, o, k1, s))) return rc;
   }
-  if (chi) {
-    const double *cqv, *cqw;
-    if ((rc = get_quad(ctx, *q_bubble, &cqv, &cqw))) return rc;
-    const int nq = q_bubble->n;
-    const int nblk = chi_blocks(nq);
-    const int nb = std::max(1, std::min(n, (int)((256L << 20) / ((long)nq * 256))));
-    if ((rc = ensure(ctx->pi[0], (size_t)nb * nq * 256))) return rc;
-    if ((rc = ensure(ctx->chi_part, (size_t)nb * nblk * 32 * 16))) return rc;
-    // the p and t channels in the a-channel Keldysh order with its spin combinations (X, D)
-    SideTables tabs, unused;
-    if ((rc = build_tables(ctx, KQFT_CH_A, *gamma, *gamma, false, tabs, unused, s))) return rc;
-    for (int iw0 = 0; iw0 < n; iw0 += nb) {
-      const int cnt = std::min(nb, n - iw0);
-      PiArgs pa{KQFT_CH_A, KQFT_PI_GG, cnt, nq, iw0, P, nodes, cqv, cqw, (double2*)ctx->pi[0].p};
-      {
-        ProfScope ps(ctx, 0, s);
-        launch_pi(pa, s);
-      }
-      ChiArgs ca;
-      memset(&ca, 0, sizeof ca);
-      ca.nq = nq;
-      ca.nb = cnt;
-      ca.iw0 = iw0;
-      ca.g = make_dgrid(n, gamma->grid.L, gamma->grid.a);
-      ca.r0 = gamma->r0;
-      const kqft_chvert& own = gamma->ch[KQFT_CH_A];
-      ca.coef = own.coef;
-      if (own.coef != 0.0) {
-        ca.K[0] = (const double2*)own.K1;
-        ca.K[1] = (const double2*)own.K2;
-        ca.K[2] = (const double2*)own.K2p;
-        ca.K[3] = (const double2*)own.K3;
-      }
-      ca.T[0] = tabs.T[0];
-      ca.T[1] = tabs.T[1];
-      for (int u = 0; u < 4; ++u) ca.mix[u] = kMix[KQFT_CH_A][u];
-      ca.nodes = nodes;
-      ca.qv = cqv;
-      ca.pi = (const double2*)ctx->pi[0].p;
-      ca.partial = (double2*)ctx->chi_part.p;
-      ca.out = (double2*)chi;
-      {
-        ProfScope ps(ctx, 3, s);
-        launch_chi(ca, s);
-      }
+  G0.sgrid = kqft_grid{2, 1.0, 1.0};
+  if ((rc = sde_core(ctx, &bare, &G0, q_bubble, q_loop, opts, sigma, nullptr, s))) return rc;
+  kqft_vertex V;
+  memset(&V, 0, sizeof V);
+  V.r0 = U;
+  V.grid = *grid;
+  for (int r = 0; r < 3; ++r)
+    V.ch[r] = kqft_chvert{1.0, (const double*)X[r][0], (const double*)X[r][1], (const double*)X[r][2],
+                          (const double*)X[r][3]};
+  kqft_propagator Gs;
+  memset(&Gs, 0, sizeof Gs);
+  Gs.Delta = Delta;
+  Gs.T = T;
+  Gs.sgrid = *grid;
+  Gs.SigR = (const double*)sigR;
+  Gs.SigK = (const double*)sigK;
+  std::vector<std::pair<const double2*, const double2*>> xf;
+  std::vector<size_t> counts;
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 4; ++c) {
+      xf.push_back({X[r][c], Fx[r][c]});
+      counts.push_back(cnt[c]);
     }
+  xf.push_back({(const double2*)sigma, (const double2*)Fsig});
+  counts.push_back((size_t)n * 4);
+  int it = 0;
+  for (; it < max_iterations;) {
+    launch_sigma_split(n, (const double2*)sigma, sigR, sigK, s);
+    if ((rc = parquet_core(ctx, V, Gs, *q_bubble, *q_loop, *opts, F, Fsig, s))) return rc;
+    double res = 0.0;
+    if ((rc = rel_change(ctx, xf, counts, s, &res))) return rc;
+    for (size_t a = 0; a < xf.size(); ++a) launch_mix((double2*)xf[a].first, xf[a].second, counts[a], alpha, s);
+    if (residuals) residuals[it] = res;
+    ++it;
+    if (res < tol) break;
   }
+  *iterations = it;
   HIP_TRY(hipGetLastError());
   return KQFT_OK;
 }

@@ -927,6 +927,55 @@ __global__ void chi_finalize_kernel(ChiArgs a, int nblk) {
   a.out[((size_t)c * a.g.n + a.iw0 + b) * 16 + f] = s;
 }
 
+// ======================================================================== parquet helpers
+// Sigma^R and Sigma^K (contiguous, for the propagator) from a self-energy [n][4]
+__global__ void sigma_split_kernel(int n, const double2* sigma, double2* sigR, double2* sigK) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  sigR[i] = sigma[4 * i + 1];
+  sigK[i] = sigma[4 * i + 0];
+}
+
+// per block: max |f - x| and max |f| over its grid-stride share of `count` entries
+__global__ __launch_bounds__(256) void maxdiff_kernel(const double2* x, const double2* f, size_t count,
+                                                      double* partial) {
+  double md = 0.0, mf = 0.0;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x) {
+    const double2 a = x[e], b = f[e];
+    md = fmax(md, hypot(b.x - a.x, b.y - a.y));
+    mf = fmax(mf, hypot(b.x, b.y));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    md = fmax(md, __shfl_xor(md, o));
+    mf = fmax(mf, __shfl_xor(mf, o));
+  }
+  __shared__ double red[4][2];
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[wave][0] = md;
+    red[wave][1] = mf;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = red[0][0], b = red[0][1];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+      a = fmax(a, red[w][0]);
+      b = fmax(b, red[w][1]);
+    }
+    partial[2 * blockIdx.x] = a;
+    partial[2 * blockIdx.x + 1] = b;
+  }
+}
+
+// linear mixing x <- x + alpha (f - x)
+__global__ __launch_bounds__(256) void mix_kernel(double2* x, const double2* f, size_t count, double alpha) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x) {
+    const double2 a = x[e], b = f[e];
+    x[e] = make_double2(fma(alpha, b.x - a.x, a.x), fma(alpha, b.y - a.y, a.y));
+  }
+}
+
 // ======================================================================== adjoint
 // Reverse pass of the bubble: the cotangent panel conj(dP) is built from the class
 // cotangents (transpose of the epilogue), the two transposed products are batched
@@ -1569,6 +1618,15 @@ void launch_unfuse(const UnfuseArgs& a, hipStream_t s) {
   if (a.dK2) hipLaunchKernelGGL(unfuse_kernel, dim3(1024), dim3(256), 0, s, a, 1);
   if (a.dK2p) hipLaunchKernelGGL(unfuse_kernel, dim3(1024), dim3(256), 0, s, a, 2);
   if (a.dK1) hipLaunchKernelGGL(unfuse_kernel, dim3(64), dim3(256), 0, s, a, 0);
+}
+void launch_sigma_split(int n, const double2* sigma, double2* sigR, double2* sigK, hipStream_t s) {
+  hipLaunchKernelGGL(sigma_split_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, sigma, sigR, sigK);
+}
+void launch_maxdiff(const double2* x, const double2* f, size_t count, double* partial, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(maxdiff_kernel, dim3(nblk), dim3(256), 0, s, x, f, count, partial);
+}
+void launch_mix(double2* x, const double2* f, size_t count, double alpha, hipStream_t s) {
+  hipLaunchKernelGGL(mix_kernel, dim3(2048), dim3(256), 0, s, x, f, count, alpha);
 }
 int chi_blocks(int nq) { return (int)std::min<long>(512, std::max<long>(1, ((long)nq * nq + 255) / 256)); }
 

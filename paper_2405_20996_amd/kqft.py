@@ -83,6 +83,11 @@ def lib():
         _lib.kqft_bubble_adjoint.argtypes = [C.c_void_p, C.c_int, P(KqftVertex), P(KqftVertex), P(KqftPropagator),
                                              C.c_int, P(KqftQuad), P(KqftOpts), P(KqftChout), P(KqftChout),
                                              P(KqftChout), C.c_void_p, C.c_void_p]
+        _lib.kqft_parquet_iteration.argtypes = [C.c_void_p, P(KqftVertex), P(KqftPropagator), P(KqftQuad),
+                                                P(KqftQuad), P(KqftOpts), P(KqftChout), C.c_void_p, C.c_void_p]
+        _lib.kqft_parquet_solve.argtypes = [C.c_void_p, P(KqftGrid), C.c_double, C.c_double, C.c_double,
+                                            P(KqftQuad), P(KqftQuad), P(KqftOpts), C.c_double, C.c_int, C.c_double,
+                                            P(KqftChout), C.c_void_p, P(C.c_double), P(C.c_int), C.c_void_p]
     return _lib
 
 
@@ -270,6 +275,39 @@ def mloop_step(gammas: Sequence[Vertex], Gs: Sequence[Propagator], qs: Sequence[
     _check(lib().kqft_mloop_step(ctx(), npts, V, P, Q, nloops, C.byref(_opts(precision, KALL, 0, omega_batch)), D,
                                  _stream(stream)))
     return outs
+
+
+def parquet_iteration(gamma: Vertex, G: Propagator, q_bubble: Quad, q_loop: Quad, precision: int = FP64,
+                      stream=None):
+    """(gamma_a', gamma_p', gamma_t') as Channels and Sigma' [n][4]: the symmetrized BSEs and the SDE."""
+    n = gamma.grid.n
+    outs = [alloc_channel(n) for _ in range(3)]
+    dev = torch.device("cuda", torch.cuda.current_device())
+    sigma = torch.zeros((n, 4), dtype=torch.complex128, device=dev)
+    D = (KqftChout * 3)(*[_chout(o, n) for o in outs])
+    vc, gc, qb, ql = gamma.c(), G.c(), q_bubble.c(), q_loop.c()
+    _check(lib().kqft_parquet_iteration(ctx(), C.byref(vc), C.byref(gc), C.byref(qb), C.byref(ql),
+                                        C.byref(_opts(precision, KALL, 0, 0)), D, C.c_void_p(sigma.data_ptr()),
+                                        _stream(stream)))
+    return outs, sigma
+
+
+def parquet_solve(grid: Grid, U: float, Delta: float, T: float, q_bubble: Quad, q_loop: Quad, alpha: float = 0.5,
+                  max_iterations: int = 20, tol: float = 0.0, precision: int = FP64, stream=None):
+    """Parquet solver from the PT2 state with linear mixing; returns (channels, Sigma, residuals)."""
+    n = grid.n
+    outs = [alloc_channel(n) for _ in range(3)]
+    dev = torch.device("cuda", torch.cuda.current_device())
+    sigma = torch.zeros((n, 4), dtype=torch.complex128, device=dev)
+    res = (C.c_double * max_iterations)()
+    its = C.c_int(0)
+    D = (KqftChout * 3)(*[_chout(o, n) for o in outs])
+    gc, qb, ql = grid.c(), q_bubble.c(), q_loop.c()
+    _check(lib().kqft_parquet_solve(ctx(), C.byref(gc), C.c_double(U), C.c_double(Delta), C.c_double(T),
+                                    C.byref(qb), C.byref(ql), C.byref(_opts(precision, KALL, 0, 0)),
+                                    C.c_double(alpha), max_iterations, C.c_double(tol), D,
+                                    C.c_void_p(sigma.data_ptr()), res, C.byref(its), _stream(stream)))
+    return outs, sigma, [res[i] for i in range(its.value)]
 
 
 def bubble_adjoint(channel: int, left: Vertex, right: Vertex, G: Propagator, q: Quad, dout: Channel,
