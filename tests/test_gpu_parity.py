@@ -185,3 +185,21 @@ def test_invalid_arguments_raise():
     _, kv7 = make_pair(7, (1, 2, 3))
     with pytest.raises(K.KqftError):
         K.bubble(0, kv, kv7, K.Propagator(D, T), K.Quad(9))
+
+
+@pytest.mark.parametrize("n,nq,batch", [(2, 1, 1), (2, 3, 5), (15, 16, 3), (16, 9, 16), (3, 1, 2)])
+def test_bubble_edge_sizes(n, nq, batch):
+    """Degenerate and boundary sizes: the smallest grid (n = 2), a single quadrature node,
+    a panel height 4(n + 1) of exactly one tile (n = 15) and one row past it (n = 16), batches
+    of one and of more transfer frequencies than the grid has; all channels, both paths."""
+    K = _K()
+    ovL, kvL = make_pair(n, (91, 92, 93))
+    ovR, kvR = make_pair(n, (94, 95, 96), r0=0.3)
+    P, q = O.Prop(D, T), O.Quad(nq)
+    for r in range(3):
+        ref = O.bubble(r, ovL, ovR, P, q)
+        out = K.bubble(r, kvL, kvR, K.Propagator(D, T), K.Quad(nq), omega_batch=batch)
+        out32 = K.bubble(r, kvL, kvR, K.Propagator(D, T), K.Quad(nq), omega_batch=batch, precision=K.SPLIT_FP32)
+        torch.cuda.synchronize()
+        compare(out, ref, 1e-12)
+        compare(out32, ref, 1e-6)
