@@ -192,6 +192,35 @@ int kqft_sde(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, 
              const kqft_quad* q_loop, const kqft_opts* opts, double* sigma, double* chi, void* stream);
 
 /*
+ * kqft_loop -- the loop function of a full vertex (Sec. "loop": the self-energy-like
+ * contraction of a vertex with one propagator line):
+ *   L(Gamma, X)^{a1'|a1}(v_i) = sum_j w_j/(2 pi i) sum_{a2,a2'} [2 Gamma^X + Gamma^Y]
+ *                                 (legs v_i, v_j | v_i, v_j) X^{a2|a2'}(v_j),
+ * X = G (kind 0) or the single-scale propagator S = dG/dDelta at fixed Sigma (kind 1);
+ * Gamma = Gamma_0(r0) + sum_r coef_r gamma_r, every channel read at its own parameters.
+ * The one-loop self-energy flow is Sigma_dot = -L(Gamma, S).  out: device [n][4] complex
+ * (index 2*a1' + a1) on gamma->grid.  FP64.
+ */
+int kqft_loop(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, int kind, const kqft_quad* q,
+              double* out, void* stream);
+
+/*
+ * kqft_mfrg_flow -- multiloop fRG flow (Sec. "mfRG") in the hybridization Delta: the
+ * regulator is Delta itself, the single-scale propagator S = dG/dDelta at fixed Sigma.
+ * Integrates, with the classical fourth-order Runge-Kutta rule in `steps` equal steps from
+ * Delta_i to Delta_f,
+ *   Gamma_dot = sum_{l <= nloops} gdot^(l)   (the insertions of kqft_mloop_step),
+ *   Sigma_dot = -L(Gamma, S)                   (kqft_loop, one-loop self-energy flow),
+ * without the Katanin substitution and without multiloop self-energy corrections.
+ * State in/out: gamma[3] (the three channels of Gamma = Gamma_0(U) + sum_r gamma_r, all four
+ * classes, device) and sigma (device [n][4], Sigma^K at index 0 and Sigma^R at 1, on grid),
+ * e.g. the PT2 or parquet state at Delta_i.  Bubbles in opts->precision.
+ */
+int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, double Delta_i, double Delta_f,
+                   int steps, int nloops, const kqft_quad* q_bubble, const kqft_quad* q_loop, const kqft_opts* opts,
+                   const kqft_chout* gamma, double* sigma, void* stream);
+
+/*
  * kqft_parquet_iteration -- right-hand sides of the parquet equations (Sec. "parquet
  * solver"; BSEs and Eq. SDE) for the state (gamma, Sigma in G):
  *   gamma_r' = 1/2 [B_r(I_r, Gamma) + B_r(Gamma, I_r)],  I_r = Gamma without channel r

@@ -472,3 +472,48 @@ def parquet_solve(grid: Grid, U: float, Delta: float, T: float, q_bubble: Quad, 
         if r_ < tol:
             break
     return chans, sigma, res
+
+
+# ------------------------------------------------------------------ mfRG flow
+def pt2_state(grid: Grid, U: float, Delta: float, T: float, q_bubble: Quad, q_loop: Quad):
+    """PT2 state (Sec. PT2): K1_r = B_r(Gamma_0, Gamma_0) in every channel, Sigma^(2) from the
+    SDE of Gamma_0 with the bare propagator."""
+    P0 = Prop(Delta, T)
+    k1 = pt2_k1(grid, U, P0, q_bubble)
+    z2 = np.zeros((2, grid.n, grid.n, 16), complex)
+    chans = [Channel(1.0, k1[r], z2.copy(), z2.copy(), np.zeros((2, grid.n, grid.n, grid.n, 16), complex))
+             for r in range(3)]
+    return chans, sde(bare(grid, U), P0, q_bubble, q_loop)
+
+
+def mfrg_rhs(grid: Grid, U: float, T: float, Delta: float, nloops: int, q_bubble: Quad, q_loop: Quad, chans, sigma):
+    """Right-hand side of the Delta-flow (Sec. mfRG): Gamma_dot = sum of the multiloop insertions
+    up to order nloops with the single-scale propagator S = dG/dDelta at fixed Sigma, and the
+    one-loop self-energy flow Sigma_dot = -L(Gamma, S)."""
+    P = sigma_prop(grid, Delta, T, sigma)
+    V = Vertex(grid, U, chans)
+    ins = mloop(V, P, q_bubble, nloops)
+    gdot = [Channel(1.0, *[sum(getattr(ins[l][r], c) for l in range(nloops)) for c in CLASSES]) for r in range(3)]
+    return gdot, -loop(V, P, q_loop, kind=1)
+
+
+def mfrg_flow(grid: Grid, U: float, T: float, Delta_i: float, Delta_f: float, steps: int, nloops: int,
+              q_bubble: Quad, q_loop: Quad, chans, sigma):
+    """Classical fourth-order Runge-Kutta integration of mfrg_rhs from Delta_i to Delta_f."""
+    h = (Delta_f - Delta_i) / steps
+
+    def add(y, k, c):
+        ch, s = y
+        kc, ks = k
+        return ([Channel(1.0, *[getattr(ch[r], x) + c * getattr(kc[r], x) for x in CLASSES]) for r in range(3)],
+                s + c * ks)
+
+    y = (chans, sigma)
+    for st in range(steps):
+        D0 = Delta_i + st * h
+        k1 = mfrg_rhs(grid, U, T, D0, nloops, q_bubble, q_loop, *y)
+        k2 = mfrg_rhs(grid, U, T, D0 + h / 2, nloops, q_bubble, q_loop, *add(y, k1, h / 2))
+        k3 = mfrg_rhs(grid, U, T, D0 + h / 2, nloops, q_bubble, q_loop, *add(y, k2, h / 2))
+        k4 = mfrg_rhs(grid, U, T, D0 + h, nloops, q_bubble, q_loop, *add(y, k3, h))
+        y = add(add(add(add(y, k1, h / 6), k2, h / 3), k3, h / 3), k4, h / 6)
+    return y

@@ -42,7 +42,7 @@ struct kqft_ctx {
   // consecutive transfer-frequency batches overlap, ordered by events
   hipStream_t sg = nullptr, sm = nullptr;
   rocblas_handle blas = nullptr;
-  DevBuf adjw, dkf[2][3], phigrad, pq, pqsig, pqred;
+  DevBuf adjw, dkf[2][3], phigrad, pq, pqsig, pqred, vtab[3], flow, flowml;
   std::vector<hipEvent_t> events;
   size_t next_event = 0;
   bool prof = false;
@@ -749,6 +749,59 @@ static int rel_change(kqft_ctx* ctx, const std::vector<std::pair<const double2*,
   return KQFT_OK;
 }
 
+// Loop of a full vertex (tables of all three channels in the a-channel order with the spin
+// combination 2X + Y), arguments checked by the caller.
+static int vloop_core(kqft_ctx* ctx, const kqft_vertex& V, const kqft_propagator& G, int kind, const kqft_quad& q,
+                      double* out, hipStream_t s) {
+  int rc;
+  if ((rc = init_tables())) return rc;
+  const size_t n = V.grid.n;
+  const double* nodes;
+  const double *qv, *qw;
+  if ((rc = get_grid(ctx, V.grid, &nodes))) return rc;
+  if ((rc = get_quad(ctx, q, &qv, &qw))) return rc;
+  DProp P;
+  if ((rc = to_dprop(G, P))) return rc;
+  VLoopArgs la;
+  memset(&la, 0, sizeof la);
+  const size_t bytes = (n * n * n + 2 * n * n + n) * 32 * sizeof(double2);
+  for (int r2 = 0; r2 < 3; ++r2) {
+    const kqft_chvert& c = V.ch[r2];
+    if (c.coef == 0.0 || (!c.K1 && !c.K2 && !c.K2p && !c.K3)) continue;
+    if ((rc = ensure(ctx->vtab[r2], bytes))) return rc;
+    TableArgs ta;
+    memset(&ta, 0, sizeof ta);
+    ta.n = (int)n;
+    ta.r = KQFT_CH_A;
+    ta.r2 = r2;
+    ta.coef = c.coef;
+    ta.mix[0] = 2.0;  // slot 0: 2X + Y; slot 1 unused
+    ta.mix[1] = 1.0;
+    ta.K[0] = (const double2*)c.K1;
+    ta.K[1] = (const double2*)c.K2;
+    ta.K[2] = (const double2*)c.K2p;
+    ta.K[3] = (const double2*)c.K3;
+    ta.out = ctx->vtab[r2].p;
+    launch_table(ta, false, s);
+    la.T[r2] = ctx->vtab[r2].p;
+  }
+  la.g = make_dgrid((int)n, V.grid.L, V.grid.a);
+  la.P = P;
+  la.kind = kind;
+  la.nq = q.n;
+  la.r0 = V.r0;
+  la.nodes = nodes;
+  la.qv = qv;
+  la.qw = qw;
+  la.out = (double2*)out;
+  {
+    ProfScope ps(ctx, 3, s);
+    launch_vloop(la, s);
+  }
+  HIP_TRY(hipGetLastError());
+  return KQFT_OK;
+}
+
 extern "C" {
 
 const char* kqft_last_error(void) { return g_err.c_str(); }
@@ -790,7 +843,8 @@ int kqft_ctx_destroy(kqft_ctx* ctx) {
     for (auto& b : row)
       if (b.p) (void)hipFree(b.p);
   if (ctx->adjw.p) (void)hipFree(ctx->adjw.p);
-  for (DevBuf* b : {&ctx->pq, &ctx->pqsig, &ctx->pqred})
+  for (DevBuf* b : {&ctx->pq, &ctx->pqsig, &ctx->pqred, &ctx->vtab[0], &ctx->vtab[1], &ctx->vtab[2], &ctx->flow,
+                    &ctx->flowml})
     if (b->p) (void)hipFree(b->p);
   if (ctx->phigrad.p) (void)hipFree(ctx->phigrad.p);
   if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
@@ -869,6 +923,144 @@ int kqft_sde(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, 
   if (!sigma) return fail(KQFT_EINVAL, "sigma is NULL");
   HIP_TRY(hipSetDevice(ctx->device));
   return sde_core(ctx, gamma, G, q_bubble, q_loop, opts, sigma, chi, (hipStream_t)stream);
+}
+
+int kqft_loop(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, int kind, const kqft_quad* q,
+              double* out, void* stream) {
+  int rc;
+  if (!ctx) return fail(KQFT_EINVAL, "ctx is NULL");
+  if (!G || !q) return fail(KQFT_EINVAL, "propagator and quadrature must be given");
+  if (q->n < 1 || (q->map != KQFT_QUAD_TAN_FINITE && q->map != KQFT_QUAD_TAN_INFINITE) ||
+      (q->map == KQFT_QUAD_TAN_FINITE && !(q->L > 0)) || !(q->a > 0))
+    return fail(KQFT_ESHAPE, "invalid quadrature");
+  if (kind != 0 && kind != 1) return fail(KQFT_EINVAL, "kind must be 0 (G) or 1 (S)");
+  if ((rc = check_vertex(gamma, "gamma"))) return rc;
+  if (!out) return fail(KQFT_EINVAL, "out is NULL");
+  HIP_TRY(hipSetDevice(ctx->device));
+  return vloop_core(ctx, *gamma, *G, kind, *q, out, (hipStream_t)stream);
+}
+
+int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, double Delta_i, double Delta_f,
+                   int steps, int nloops, const kqft_quad* q_bubble, const kqft_quad* q_loop, const kqft_opts* opts,
+                   const kqft_chout* gamma, double* sigma, void* stream) {
+  int rc;
+  if (!ctx) return fail(KQFT_EINVAL, "ctx is NULL");
+  if (!grid || (rc = check_grid(*grid, "grid"))) return grid ? rc : fail(KQFT_EINVAL, "grid is NULL");
+  kqft_propagator Gc;
+  memset(&Gc, 0, sizeof Gc);
+  Gc.Delta = Delta_i;
+  Gc.T = T;
+  Gc.sgrid = *grid;
+  if ((rc = check_common(ctx, &Gc, q_bubble, opts))) return rc;
+  if (!q_loop || q_loop->n < 1) return fail(KQFT_ESHAPE, "invalid loop quadrature");
+  if (!(T > 0) || !(Delta_i > 0) || !(Delta_f > 0)) return fail(KQFT_EINVAL, "T and Delta must be positive");
+  if (steps < 1 || nloops < 1) return fail(KQFT_EINVAL, "need steps >= 1 and nloops >= 1");
+  if (!gamma || !sigma) return fail(KQFT_EINVAL, "gamma and sigma must be given");
+  for (int r = 0; r < 3; ++r)
+    if (!gamma[r].K1 || !gamma[r].K2 || !gamma[r].K2p || !gamma[r].K3)
+      return fail(KQFT_EINVAL, "gamma arrays must all be given");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const int n = grid->n;
+  const size_t c1 = (size_t)2 * n * 16, c2 = (size_t)2 * n * n * 16, c3 = (size_t)2 * n * n * n * 16;
+  const size_t cnt[4] = {c1, c2, c2, c3};
+  const size_t chc = c1 + 2 * c2 + c3;             // complex entries of one channel
+  const size_t stc = 3 * chc + (size_t)4 * n;      // of the state (three channels, Sigma)
+  // three state-sized buffers (stage input, stage derivative, accumulated update), Sigma^R/K
+  if ((rc = ensure(ctx->flow, (3 * stc + 2 * (size_t)n) * sizeof(double2)))) return rc;
+  if ((rc = ensure(ctx->flowml, (size_t)nloops * 3 * chc * sizeof(double2)))) return rc;
+  double2* buf = (double2*)ctx->flow.p;
+  double2* yt = buf;            // stage input
+  double2* kd = buf + stc;      // stage derivative
+  double2* ys = buf + 2 * stc;  // accumulated update
+  double2* sigR = buf + 3 * stc;
+  double2* sigK = sigR + n;
+  double2* ml = (double2*)ctx->flowml.p;
+  // views of a state buffer: channel r class c, and Sigma
+  auto cls = [&](double2* base, int r, int c) {
+    size_t off = (size_t)r * chc;
+    for (int u = 0; u < c; ++u) off += cnt[u];
+    return base + off;
+  };
+  auto sig_of = [&](double2* base) { return base + 3 * chc; };
+  double2* Y[3][4];
+  for (int r = 0; r < 3; ++r) {
+    Y[r][0] = (double2*)gamma[r].K1;
+    Y[r][1] = (double2*)gamma[r].K2;
+    Y[r][2] = (double2*)gamma[r].K2p;
+    Y[r][3] = (double2*)gamma[r].K3;
+  }
+  // out = a * (user state) + b * (buffer state), over every array
+  auto axpby_state = [&](double2* outb, bool out_user, double a, bool x_user, const double2* xb, double b,
+                         const double2* yb) {
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 4; ++c)
+        launch_axpby(out_user ? Y[r][c] : cls(outb, r, c), a, x_user ? Y[r][c] : cls((double2*)xb, r, c), b,
+                     cls((double2*)yb, r, c), cnt[c], s);
+    launch_axpby(out_user ? (double2*)sigma : sig_of(outb), a, x_user ? (double2*)sigma : sig_of((double2*)xb), b,
+                 sig_of((double2*)yb), (size_t)4 * n, s);
+  };
+  // derivative of the state held in `yb` (user arrays when yb == nullptr) at hybridization D
+  auto rhs = [&](double D, const double2* yb) -> int {
+    const double2* chs[3][4];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 4; ++c) chs[r][c] = yb ? cls((double2*)yb, r, c) : Y[r][c];
+    const double2* sg = yb ? sig_of((double2*)yb) : (const double2*)sigma;
+    launch_sigma_split(n, sg, sigR, sigK, s);
+    kqft_propagator G;
+    memset(&G, 0, sizeof G);
+    G.Delta = D;
+    G.T = T;
+    G.sgrid = *grid;
+    G.SigR = (const double*)sigR;
+    G.SigK = (const double*)sigK;
+    kqft_vertex V;
+    memset(&V, 0, sizeof V);
+    V.r0 = U;
+    V.grid = *grid;
+    for (int r = 0; r < 3; ++r)
+      V.ch[r] = kqft_chvert{1.0, (const double*)chs[r][0], (const double*)chs[r][1], (const double*)chs[r][2],
+                            (const double*)chs[r][3]};
+    std::vector<kqft_chout> dg((size_t)nloops * 3);
+    for (int l = 0; l < nloops; ++l)
+      for (int r = 0; r < 3; ++r) {
+        double2* b0 = ml + ((size_t)l * 3 + r) * chc;
+        dg[(size_t)l * 3 + r] = kqft_chout{(double*)b0, (double*)(b0 + c1), (double*)(b0 + c1 + c2),
+                                           (double*)(b0 + c1 + 2 * c2)};
+      }
+    int e;
+    if ((e = kqft_mloop_step(ctx, 1, &V, &G, q_bubble, nloops, opts, dg.data(), s))) return e;
+    const size_t coff[4] = {0, c1, c1 + c2, c1 + 2 * c2};
+    for (int r = 0; r < 3; ++r)  // Gamma_dot = sum over the loop orders
+      for (int c = 0; c < 4; ++c) {
+        double2* dst = cls(kd, r, c);
+        const double2* first = (const double2*)dg[r].K1 + coff[c];
+        launch_axpby(dst, 1.0, first, 0.0, first, cnt[c], s);  // dst = first (dst is not read)
+        for (int l = 1; l < nloops; ++l)
+          launch_axpby(dst, 1.0, dst, 1.0, (const double2*)dg[(size_t)l * 3 + r].K1 + coff[c], cnt[c], s);
+      }
+    double2* sd = sig_of(kd);  // Sigma_dot = -L(Gamma, S)
+    if ((e = vloop_core(ctx, V, G, 1, *q_loop, (double*)sd, s))) return e;
+    launch_axpby(sd, -1.0, sd, 0.0, sd, (size_t)4 * n, s);
+    return KQFT_OK;
+  };
+  const double h = (Delta_f - Delta_i) / steps;
+  for (int st = 0; st < steps; ++st) {
+    const double D0 = Delta_i + st * h;
+    if ((rc = rhs(D0, nullptr))) return rc;
+    axpby_state(ys, false, 1.0, true, nullptr, h / 6.0, kd);
+    axpby_state(yt, false, 1.0, true, nullptr, h / 2.0, kd);
+    if ((rc = rhs(D0 + h / 2.0, yt))) return rc;
+    axpby_state(ys, false, 1.0, false, ys, h / 3.0, kd);
+    axpby_state(yt, false, 1.0, true, nullptr, h / 2.0, kd);
+    if ((rc = rhs(D0 + h / 2.0, yt))) return rc;
+    axpby_state(ys, false, 1.0, false, ys, h / 3.0, kd);
+    axpby_state(yt, false, 1.0, true, nullptr, h, kd);
+    if ((rc = rhs(D0 + h, yt))) return rc;
+    axpby_state(nullptr, true, 1.0, false, ys, h / 6.0, kd);
+  }
+  HIP_TRY(hipGetLastError());
+  return KQFT_OK;
 }
 
 int kqft_parquet_iteration(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G,

@@ -800,6 +800,92 @@ __global__ __launch_bounds__(256) void loop_kernel(LoopArgs a) {
   }
 }
 
+// ======================================================================== vertex loop
+// L(Gamma, X)^{a1'|a1}(v_i) = sum_j w_j/(2 pi i) sum_{a2,a2'} [2 Gamma^X + Gamma^Y]
+//   (legs v_i, v_j | v_i, v_j) X^{a2|a2'}(v_j),  X = G (kind 0) or S (kind 1),
+// the loop function of a full vertex (Sec. "loop"): bare part plus the three channels, each
+// read from its table at (w, v, v') = (v_i - v_j, (v_i + v_j)/2, (v_i + v_j)/2) in its own
+// parametrization.  One workgroup per output frequency, one 8-lane group per node v_j.
+__global__ __launch_bounds__(256) void vloop_kernel(VLoopArgs a) {
+  const int i = blockIdx.x;
+  const int l8 = threadIdx.x & 7, grp = threadIdx.x >> 3, ngrp = blockDim.x >> 3;
+  const int n = a.g.n;
+  const double v = a.nodes[i];
+  double2 acc[4];  // output (a1', a1) at index 2 a1' + a1
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = czero();
+  for (int j = grp; j < a.nq; j += ngrp) {
+    const double vq = a.qv[j];
+    double L[4];
+    legs_of(0, v - vq, 0.5 * (v + vq), 0.5 * (v + vq), L);
+    // slots: 0, 1 = (w, v) of channel a (v' = v there); 2-4 / 5-7 = (w, v, v') of p / t
+    double arg;
+    if (l8 < 2) {
+      arg = l8 == 0 ? v - vq : 0.5 * (v + vq);
+    } else {
+      const int d = l8 <= 4 ? 1 : 2, which = (l8 - 2) % 3;
+      double w2, v2, vp2;
+      params_of(d, L, w2, v2, vp2);
+      arg = which == 0 ? w2 : (which == 1 ? v2 : vp2);
+    }
+    int ic;
+    double tc;
+    if (!dgrid_locate(a.g, arg, ic, tc)) {
+      ic = -1;
+      tc = 0.0;
+    }
+    double2 g4[4];
+    propagator(a.P, a.kind, vq, g4);
+    double2 gam[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) gam[u] = czero();
+    if (a.T[0]) {
+      const int iw = __shfl(ic, 0, 8), iv = __shfl(ic, 1, 8);
+      const double tw = __shfl(tc, 0, 8), tv = __shfl(tc, 1, 8);
+      table_taps((const double2*)a.T[0], n, iw, tw, iv, tv, iv, tv, l8, gam);
+    }
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+      if (a.T[1 + d]) {
+        const int s0 = 2 + 3 * d;
+        table_taps((const double2*)a.T[1 + d], n, __shfl(ic, s0, 8), __shfl(tc, s0, 8), __shfl(ic, s0 + 1, 8),
+                   __shfl(tc, s0 + 1, 8), __shfl(ic, s0 + 2, 8), __shfl(tc, s0 + 2, 8), l8, gam);
+      }
+    const double2 wgt = make_double2(0.0, -a.qw[j] * (0.5 / M_PI));  // w_j / (2 pi i)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int f = l8 + 8 * h;  // a-channel order: row (a1', a2), column (a1, a2')
+      const int a1p = f >> 3, a2 = (f >> 2) & 1, a1 = (f >> 1) & 1, a2p = f & 1;
+      double2 x = gam[2 * h];  // 2X + Y of the channels
+      if (bare_odd(f)) x.x -= 0.5 * a.r0;  // 2 X_R + Y_R = -r0/2 on odd f
+      const double2 gp = a2 ? (a2p ? g4[3] : g4[2]) : (a2p ? g4[1] : g4[0]);
+      const double2 val = cmul(cmul(x, gp), wgt);
+      const int idx = 2 * a1p + a1;
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (c == idx) acc[c] = cadd(acc[c], val);  // register-resident: no indexed store
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      acc[c].x += __shfl_xor(acc[c].x, o);
+      acc[c].y += __shfl_xor(acc[c].y, o);
+    }
+  __shared__ double2 red[4][4];
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) red[wave][c] = acc[c];
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double2 s = czero();
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s = cadd(s, red[w][threadIdx.x]);
+    a.out[(size_t)i * 4 + threadIdx.x] = s;
+  }
+}
+
 // ======================================================================== chi
 // chi_a^c(w)[p, m] = sum_k Pi_k[p, m]
 //   + sum_{k,l} sum_{row,q} Pi_k[p, row] Gamma_c(w; v''_k, v''_l)[row, q] Pi_l[q, m]
@@ -965,6 +1051,15 @@ __global__ __launch_bounds__(256) void maxdiff_kernel(const double2* x, const do
     }
     partial[2 * blockIdx.x] = a;
     partial[2 * blockIdx.x + 1] = b;
+  }
+}
+
+// out = a x + b y (out may alias x or y)
+__global__ __launch_bounds__(256) void axpby_kernel(double2* out, double a, const double2* x, double b,
+                                                    const double2* y, size_t count) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x) {
+    const double2 u = x[e], v = y[e];
+    out[e] = make_double2(fma(a, u.x, b * v.x), fma(a, u.y, b * v.y));
   }
 }
 
@@ -1590,6 +1685,9 @@ void launch_gemm(const GemmArgs& g, int precision, hipStream_t s) {
 void launch_loop(const LoopArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(loop_kernel, dim3(a.g.n), dim3(256), 0, s, a);
 }
+void launch_vloop(const VLoopArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(vloop_kernel, dim3(a.g.n), dim3(256), 0, s, a);
+}
 void launch_chi(const ChiArgs& a, hipStream_t s) {
   const int nblk = chi_blocks(a.nq);
   hipLaunchKernelGGL(chi_kernel, dim3(nblk, a.nb), dim3(256), 0, s, a);
@@ -1624,6 +1722,10 @@ void launch_sigma_split(int n, const double2* sigma, double2* sigR, double2* sig
 }
 void launch_maxdiff(const double2* x, const double2* f, size_t count, double* partial, int nblk, hipStream_t s) {
   hipLaunchKernelGGL(maxdiff_kernel, dim3(nblk), dim3(256), 0, s, x, f, count, partial);
+}
+void launch_axpby(double2* out, double a, const double2* x, double b, const double2* y, size_t count,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(axpby_kernel, dim3(2048), dim3(256), 0, s, out, a, x, b, y, count);
 }
 void launch_mix(double2* x, const double2* f, size_t count, double alpha, hipStream_t s) {
   hipLaunchKernelGGL(mix_kernel, dim3(2048), dim3(256), 0, s, x, f, count, alpha);

@@ -65,6 +65,20 @@ struct LoopArgs {
   double2* out;  // [n][4]
 };
 
+// loop of a full vertex: all three channels through tables in the a-channel order with the
+// spin combination 2X + Y in slot c = 0
+struct VLoopArgs {
+  DGrid g;
+  DProp P;
+  int kind, nq;
+  double r0;
+  const void* T[3];  // FP64 tables of channels a, p, t (nullptr = inactive)
+  const double* nodes;
+  const double* qv;
+  const double* qw;
+  double2* out;  // [n][4]
+};
+
 struct ChiArgs {
   int nq, nb, iw0;
   DGrid g;
@@ -167,10 +181,13 @@ void launch_pi(const PiArgs& a, hipStream_t s);
 void launch_gather(const GatherArgs& a, bool left, bool f32, hipStream_t s);
 void launch_gemm(const GemmArgs& g, int precision, hipStream_t s);
 void launch_loop(const LoopArgs& a, hipStream_t s);
+void launch_vloop(const VLoopArgs& a, hipStream_t s);
 void launch_chi(const ChiArgs& a, hipStream_t s);
 int chi_blocks(int nq);
 void launch_sigma_split(int n, const double2* sigma, double2* sigR, double2* sigK, hipStream_t s);
 void launch_maxdiff(const double2* x, const double2* f, size_t count, double* partial, int nblk, hipStream_t s);
 void launch_mix(double2* x, const double2* f, size_t count, double alpha, hipStream_t s);
+void launch_axpby(double2* out, double a, const double2* x, double b, const double2* y, size_t count,
+                  hipStream_t s);
 
 }  // namespace kqft

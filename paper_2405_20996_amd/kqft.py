@@ -83,6 +83,11 @@ def lib():
         _lib.kqft_bubble_adjoint.argtypes = [C.c_void_p, C.c_int, P(KqftVertex), P(KqftVertex), P(KqftPropagator),
                                              C.c_int, P(KqftQuad), P(KqftOpts), P(KqftChout), P(KqftChout),
                                              P(KqftChout), C.c_void_p, C.c_void_p]
+        _lib.kqft_loop.argtypes = [C.c_void_p, P(KqftVertex), P(KqftPropagator), C.c_int, P(KqftQuad), C.c_void_p,
+                                   C.c_void_p]
+        _lib.kqft_mfrg_flow.argtypes = [C.c_void_p, P(KqftGrid), C.c_double, C.c_double, C.c_double, C.c_double,
+                                        C.c_int, C.c_int, P(KqftQuad), P(KqftQuad), P(KqftOpts), P(KqftChout),
+                                        C.c_void_p, C.c_void_p]
         _lib.kqft_parquet_iteration.argtypes = [C.c_void_p, P(KqftVertex), P(KqftPropagator), P(KqftQuad),
                                                 P(KqftQuad), P(KqftOpts), P(KqftChout), C.c_void_p, C.c_void_p]
         _lib.kqft_parquet_solve.argtypes = [C.c_void_p, P(KqftGrid), C.c_double, C.c_double, C.c_double,
@@ -275,6 +280,32 @@ def mloop_step(gammas: Sequence[Vertex], Gs: Sequence[Propagator], qs: Sequence[
     _check(lib().kqft_mloop_step(ctx(), npts, V, P, Q, nloops, C.byref(_opts(precision, KALL, 0, omega_batch)), D,
                                  _stream(stream)))
     return outs
+
+
+def loop(gamma: Vertex, G: Propagator, q: Quad, kind: int = 0, stream=None) -> torch.Tensor:
+    """L(Gamma, G or S) [n][4] (no overall sign); Sigma_dot = -loop(Gamma, G, q, kind=1)."""
+    n = gamma.grid.n
+    dev = torch.device("cuda", torch.cuda.current_device())
+    out = torch.zeros((n, 4), dtype=torch.complex128, device=dev)
+    vc, gc, qc = gamma.c(), G.c(), q.c()
+    _check(lib().kqft_loop(ctx(), C.byref(vc), C.byref(gc), kind, C.byref(qc), C.c_void_p(out.data_ptr()),
+                           _stream(stream)))
+    return out
+
+
+def mfrg_flow(grid: Grid, U: float, T: float, Delta_i: float, Delta_f: float, steps: int, nloops: int,
+              q_bubble: Quad, q_loop: Quad, gamma: Sequence[Channel], sigma: torch.Tensor, precision: int = FP64,
+              stream=None):
+    """Delta-flow of the state (gamma[3] Channels, sigma [n][4]) in place, RK4 in `steps` steps."""
+    n = grid.n
+    D = (KqftChout * 3)(*[_chout(c, n) for c in gamma])
+    _ptr(sigma, (n, 4), "sigma")
+    gc, qb, ql = grid.c(), q_bubble.c(), q_loop.c()
+    _check(lib().kqft_mfrg_flow(ctx(), C.byref(gc), C.c_double(U), C.c_double(T), C.c_double(Delta_i),
+                                C.c_double(Delta_f), steps, nloops, C.byref(qb), C.byref(ql),
+                                C.byref(_opts(precision, KALL, 0, 0)), D, C.c_void_p(sigma.data_ptr()),
+                                _stream(stream)))
+    return gamma, sigma
 
 
 def parquet_iteration(gamma: Vertex, G: Propagator, q_bubble: Quad, q_loop: Quad, precision: int = FP64,

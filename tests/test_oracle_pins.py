@@ -658,3 +658,36 @@ def test_parquet_iteration_preserves_crossing_and_contracts():
     assert all(b < a for a, b in zip(res[1:], res[2:]))
     assert res[-1] / res[2] < 0.5
     assert _crossing_residual(O.Vertex(g, U, chans)) < 1e-12
+
+
+# ---------------------------------------------------------------- mfRG flow
+def test_flow_of_pt2_vertex_reaches_pt2_at_the_end_to_second_order():
+    """The one-loop vertex flow is the Delta-derivative of the PT2 vertex at order U^2 (Eq. 1l),
+    so flowing the PT2 state from Delta_i = 2 to Delta_f = 1 reproduces the PT2 vertex at
+    Delta_f up to O(U^3) and the Runge-Kutta error: the deviation relative to the PT2 vertex
+    falls linearly with U and with the fourth power of the step."""
+    g, q = O.Grid(9), O.Quad(31)
+    devs = {}
+    for u, steps in ((0.1, 4), (0.05, 4), (0.05, 2)):
+        chans, sig = O.pt2_state(g, u, 2.0, T, q, q)
+        chans, sig = O.mfrg_flow(g, u, T, 2.0, 1.0, steps, 1, q, q, chans, sig)
+        ref = O.pt2_k1(g, u, O.Prop(1.0, T), q)
+        devs[(u, steps)] = max(np.abs(chans[r].K1 - ref[r]).max() / np.abs(ref[r]).max() for r in range(3))
+    d1, d2 = devs[(0.1, 4)], devs[(0.05, 4)]
+    assert d1 < 0.05
+    assert 0.3 < d2 / d1 < 0.7  # O(U): the remaining deviation is the third order
+
+
+def test_flow_self_energy_matches_sde_pt2_up_to_discretisation():
+    """The one-loop self-energy flow -L(Gamma, S) integrates, at order U^2, to the second-order
+    self-energy; the SDE form Sigma^(2) = -1/2 L(B_a(Gamma_0, Gamma_0), G) reads the same
+    diagram at other frequencies, so the two agree up to the discretisation, which shrinks
+    with the grid."""
+    devs = []
+    for n, nq in ((9, 31), (17, 81)):
+        g, q = O.Grid(n), O.Quad(nq)
+        chans, sig = O.pt2_state(g, 0.05, 2.0, T, q, q)
+        chans, sig = O.mfrg_flow(g, 0.05, T, 2.0, 1.0, 2, 1, q, q, chans, sig)
+        s2 = O.sde(O.bare(g, 0.05), O.Prop(1.0, T), q, q)
+        devs.append(np.abs(sig - s2).max() / np.abs(s2).max())
+    assert devs[0] < 0.1 and devs[1] < 0.75 * devs[0]
