@@ -110,12 +110,20 @@ typedef struct {
 } OVert;
 // propagator: G^R = 1/(v - eps + i Delta - Sigma^R(v)),
 // G^K = G^R [Sigma^K - 2 i Delta tanh(v/2T)] G^A; Sigma optional on its own grid.
+// reg selects the flow parameter Lambda of S = dG/dLambda at fixed Sigma (Sec. "Flow
+// schemes"): 0 Delta (Lambda = Delta), 1 interaction flow (G_0 -> Lambda G_0, Lambda = lam),
+// 2 temperature (Lambda = T), 3 frequency regulator Theta = v/(v + i lam) (Lambda = lam).
+// dSigR/dSigK: optional Sigma_dot on the Sigma grid (Katanin: S -> S + G Sigma_dot G).
 typedef struct {
   double Delta, dDelta, T, eps;
   int sn;
   double sL, sa;
   const double* SigR;
   const double* SigK;
+  int reg;
+  double lam;
+  const double* dSigR;
+  const double* dSigK;
 } OProp;
 // quadrature: n Gauss-Legendre nodes, map 0 = tangent onto [-L, L] with scale a,
 // map 1 = v = a tan(pi y / 2) onto the real line.
@@ -206,8 +214,7 @@ static void make_quad(const OQuad& q, std::vector<double>& nu, std::vector<doubl
 }
 
 // ---------------------------------------------------------------- propagator
-// Keldysh matrix of G (kind 0) or of the single-scale propagator S = dG/dDelta at
-// fixed Sigma (kind 1), the Delta-flow regulator (Sec. "Flow schemes").
+// Sigma on its grid, linear interpolation on the auxiliary variable; zero outside.
 template <class S>
 static Cx<S> sigma_interp(const OProp& P, const double* arr, double v) {
   Cx<S> z = czero<S>();
@@ -224,8 +231,20 @@ template <class S> static S param_delta(const OProp& P);
 template <> double param_delta<double>(const OProp& P) { return P.Delta; }
 template <> Dual param_delta<Dual>(const OProp& P) { return Dual{P.Delta, P.dDelta}; }
 
+template <class S> static Cx<S> lift(double re, double im) {
+  return Cx<S>{mk(re, (S*)nullptr), mk(im, (S*)nullptr)};
+}
+
+// Keldysh matrix g[a][a'] of
+//   kind 0: G, with G^R = 1/(G_0^{-1,R} - Sigma^R), G^K = G^R [Sigma^K - G_0^{-1,K}] G^A and
+//           G_0^{-1,K} = 2 i tanh(v/2T) Im G_0^{-1,R} (the bath in equilibrium);
+//   kind 1: the single-scale propagator S = dG/dLambda at fixed Sigma of the regulator reg,
+//           plus G Sigma_dot G when Sigma_dot is given (Katanin substitution);
+//   kind 2: G Sigma_dot G alone.
+// G_0^{-1,R} per regulator, with D = v - eps + i Delta:  Delta: D;  interaction: D / lam;
+// temperature: D (the flow enters through tanh);  frequency: D (v + i lam) / v.
 template <class S> static void propagator(const OProp& P, int kind, double v, Cx<S> g[2][2]) {
-  S D = param_delta<S>(P);
+  S Dl = param_delta<S>(P);
   S zero = mk(0.0, (S*)nullptr);
   double th = std::tanh(v / (2.0 * P.T));
   Cx<S> sR = sigma_interp<S>(P, P.SigR, v);
@@ -235,27 +254,62 @@ template <class S> static void propagator(const OProp& P, int kind, double v, Cx
   } else {  // equilibrium FDR for the self-energy: Sigma^K = 2 i tanh Im Sigma^R
     sK = Cx<S>{zero, 2.0 * th * sR.im};
   }
-  Cx<S> den = Cx<S>{mk(v - P.eps, (S*)nullptr) - sR.re, D - sR.im};
-  Cx<S> GR = inv(den);
-  Cx<S> GA = conj(GR);
-  Cx<S> bracket = Cx<S>{sK.re, sK.im - 2.0 * th * D};  // Sigma^K - 2 i Delta tanh
-  Cx<S> GK = GR * bracket * GA;
-  if (kind == 0) {
-    g[0][0] = czero<S>();
-    g[0][1] = GA;
-    g[1][0] = GR;
-    g[1][1] = GK;
-    return;
+  const Cx<S> Dc = Cx<S>{mk(v - P.eps, (S*)nullptr), Dl};
+  Cx<S> GR, SR, br, dbr;  // br = Sigma^K - G_0^{-1,K}, dbr = -dG_0^{-1,K}/dLambda
+  if (P.reg == 1) {
+    const double L = P.lam;
+    const Cx<S> d = inv(Dc - L * sR);
+    GR = L * d;
+    SR = Dc * d * d;  // d/dL [L / (D - L Sigma)] = D / (D - L Sigma)^2
+    br = Cx<S>{sK.re, sK.im - (2.0 * th / L) * Dl};
+    dbr = Cx<S>{zero, (2.0 * th / (L * L)) * Dl};
+  } else if (P.reg == 2) {
+    GR = inv(Dc - sR);
+    SR = czero<S>();
+    const double dth = -(v / (2.0 * P.T * P.T)) * (1.0 - th * th);  // d tanh(v/2T) / dT
+    br = Cx<S>{sK.re, sK.im - 2.0 * th * Dl};
+    dbr = Cx<S>{zero, (-2.0 * dth) * Dl};
+  } else if (P.reg == 3) {
+    const double L = P.lam;
+    // Theta = v / (v + i L) and Theta^2 / v = v / (v + i L)^2, finite at v = 0
+    const double dd = v * v + L * L;
+    const Cx<S> theta = lift<S>(v * v / dd, -v * L / dd);
+    const Cx<S> t2v = lift<S>(v * (v * v - L * L) / (dd * dd), -2.0 * v * v * L / (dd * dd));
+    const double th_v = v == 0.0 ? 1.0 / (2.0 * P.T) : th / v;  // tanh(v/2T) / v
+    const Cx<S> d = inv(Dc - theta * sR);
+    GR = theta * d;
+    SR = cmul(0.0, -1.0, Dc * t2v * d * d);
+    // Im G_0^{-1,R} = Delta + lam (v - eps) / v, its lam-derivative (v - eps) / v
+    br = Cx<S>{sK.re, sK.im - 2.0 * th * Dl - mk(2.0 * L * (v - P.eps) * th_v, (S*)nullptr)};
+    dbr = lift<S>(0.0, -2.0 * (v - P.eps) * th_v);
+  } else {
+    GR = inv(Dc - sR);
+    SR = cmul(0.0, -1.0, GR * GR);  // d/dDelta 1/(D - Sigma) = -i G^2
+    br = Cx<S>{sK.re, sK.im - 2.0 * th * Dl};
+    dbr = lift<S>(0.0, -2.0 * th);
   }
-  // S^R = dG^R/dDelta = -i (G^R)^2, S^A = conj, S^K by the product rule on G^K.
-  Cx<S> SR = cmul(0.0, -1.0, GR * GR);
-  Cx<S> SA = conj(SR);
-  Cx<S> dbr = Cx<S>{zero, mk(-2.0 * th, (S*)nullptr)};
-  Cx<S> SK = SR * bracket * GA + GR * dbr * GA + GR * bracket * SA;
+  const Cx<S> GA = conj(GR);
+  const Cx<S> GK = GR * br * GA;
+  Cx<S> R = czero<S>(), K = czero<S>();
+  if (kind == 0) {
+    R = GR;
+    K = GK;
+  }
+  if (kind == 1) {  // product rule on G^K = G^R br G^A
+    R = SR;
+    K = SR * br * GA + GR * dbr * GA + GR * br * conj(SR);
+  }
+  if ((kind == 1 || kind == 2) && P.dSigR) {
+    // G Sigma_dot G: R = G^R s^R G^R, K = G^R s^R G^K + G^R s^K G^A + G^K s^A G^A
+    const Cx<S> dR = sigma_interp<S>(P, P.dSigR, v);
+    const Cx<S> dK = sigma_interp<S>(P, P.dSigK, v);
+    R = R + GR * dR * GR;
+    K = K + GR * dR * GK + GR * dK * GA + GK * conj(dR) * GA;
+  }
   g[0][0] = czero<S>();
-  g[0][1] = SA;
-  g[1][0] = SR;
-  g[1][1] = SK;
+  g[0][1] = conj(R);
+  g[1][0] = R;
+  g[1][1] = K;
 }
 
 // ---------------------------------------------------------------- channels

@@ -52,7 +52,8 @@ class OVert(C.Structure):
 class OProp(C.Structure):
     _fields_ = [("Delta", C.c_double), ("dDelta", C.c_double), ("T", C.c_double), ("eps", C.c_double),
                 ("sn", C.c_int), ("sL", C.c_double), ("sa", C.c_double),
-                ("SigR", C.c_void_p), ("SigK", C.c_void_p)]
+                ("SigR", C.c_void_p), ("SigK", C.c_void_p), ("reg", C.c_int), ("lam", C.c_double),
+                ("dSigR", C.c_void_p), ("dSigK", C.c_void_p)]
 
 
 class OQuad(C.Structure):
@@ -122,10 +123,16 @@ class Quad:
         return v, w
 
 
+REG_DELTA, REG_U, REG_T, REG_NU = 0, 1, 2, 3
+
+
 @dataclass
 class Prop:
-    """Propagator parameters: G^R = 1/(v - eps + i Delta - Sigma^R), G^K by the
-    general Keldysh relation with the FDR for the bath; optional dynamic Sigma on a grid."""
+    """Propagator parameters (Sec. Propagator class, Sec. Flow schemes): G^R = 1/(G_0^{-1,R} -
+    Sigma^R) with G_0^{-1,R} = v - eps + i Delta (regulator reg = REG_DELTA or REG_T),
+    (v - eps + i Delta) / lam (REG_U) or (v - eps + i Delta)(v + i lam)/v (REG_NU); G^K by the
+    general Keldysh relation with the FDR for the bath; optional dynamic Sigma on a grid and
+    optional Sigma_dot there (Katanin substitution in the single-scale propagator)."""
     Delta: float = 1.0
     T: float = 0.1
     eps: float = 0.0
@@ -133,11 +140,18 @@ class Prop:
     sigma_grid: Optional[Grid] = None
     SigR: Optional[np.ndarray] = None
     SigK: Optional[np.ndarray] = None
+    reg: int = REG_DELTA
+    lam: float = 1.0
+    dSigR: Optional[np.ndarray] = None
+    dSigK: Optional[np.ndarray] = None
 
     def c(self, keep: list) -> OProp:
         g = self.sigma_grid or Grid(2)
-        p = OProp(self.Delta, self.dDelta, self.T, self.eps, g.n, g.L, g.a, None, None)
-        for name in ("SigR", "SigK"):
+        p = OProp(self.Delta, self.dDelta, self.T, self.eps, g.n, g.L, g.a, None, None, self.reg, self.lam,
+                  None, None)
+        if (self.dSigR is None) != (self.dSigK is None):
+            raise ValueError("Sigma_dot needs both its retarded and its Keldysh component")
+        for name in ("SigR", "SigK", "dSigR", "dSigK"):
             arr = getattr(self, name)
             if arr is not None:
                 arr = _as_c(arr)
@@ -363,12 +377,13 @@ def combine(grid: Grid, parts: Sequence[tuple], r0: float = 0.0) -> Vertex:
     return Vertex(grid, r0=r0, ch=chans)
 
 
-def mloop(V: Vertex, P: Prop, q: Quad, nloops: int, dual: bool = False) -> list:
+def mloop(V: Vertex, P: Prop, q: Quad, nloops: int, dual: bool = False, centres: Optional[list] = None) -> list:
     """Multiloop insertions (mfRG flow equations, Eqs. 1l-3l):
       l = 1: gdot_r = B_r(Gamma, Gamma; Pidot),
       l = 2: gdot_r = B_r(gdot_rbar^(1), Gamma) + B_r(Gamma, gdot_rbar^(1)),
       l >= 3: + B_r(Gamma, B_r(gdot_rbar^(l-2), Gamma)) (the centre term, as two explicit bubbles),
-    where gdot_rbar = sum of the two other channels.  Returns out[l-1][r] (Channel)."""
+    where gdot_rbar = sum of the two other channels.  Returns out[l-1][r] (Channel).  When a
+    list is given as `centres`, the centre terms are appended to it as centres[l-3][r]."""
     g = V.grid
     out = []
     for ell in range(1, nloops + 1):
@@ -388,6 +403,10 @@ def mloop(V: Vertex, P: Prop, q: Quad, nloops: int, dual: bool = False) -> list:
                 inner = bubble(r, rbar2, V, P, q, 0, C_ALL, dual)
                 Ct = bubble(r, V, combine(g, [(r, inner, 1.0)]), P, q, 0, C_ALL, dual)
                 tot = {k: tot[k] + getattr(Ct, k) for k in tot}
+                if centres is not None:
+                    if r == 0:
+                        centres.append([])
+                    centres[-1].append(Ct)
             this.append(Channel(1.0, tot["K1"], tot["K2"], tot["K2p"], tot["K3"]))
         out.append(this)
     return out
@@ -486,34 +505,194 @@ def pt2_state(grid: Grid, U: float, Delta: float, T: float, q_bubble: Quad, q_lo
     return chans, sde(bare(grid, U), P0, q_bubble, q_loop)
 
 
-def mfrg_rhs(grid: Grid, U: float, T: float, Delta: float, nloops: int, q_bubble: Quad, q_loop: Quad, chans, sigma):
-    """Right-hand side of the Delta-flow (Sec. mfRG): Gamma_dot = sum of the multiloop insertions
-    up to order nloops with the single-scale propagator S = dG/dDelta at fixed Sigma, and the
-    one-loop self-energy flow Sigma_dot = -L(Gamma, S)."""
+# Regulators of the flow (Sec. Flow schemes) and the flow parameter of the ODE solver
+# (Sec. Details on the ODE solver): the Delta-flow integrates in t with
+# Lambda(t) = 5 t |t| / sqrt(1 - t^2); the other flows integrate in Lambda itself.
+def flow_lambda(reg: int, t: float) -> float:
+    return 5.0 * t * abs(t) / np.sqrt(1.0 - t * t) if reg == REG_DELTA else t
+
+
+def flow_t(reg: int, lam: float) -> float:
+    """Inverse of flow_lambda: 25 t^4 + Lambda^2 t^2 - Lambda^2 = 0 for the Delta-flow."""
+    if reg != REG_DELTA:
+        return lam
+    l2 = lam * lam
+    return float(np.sign(lam) * np.sqrt((-l2 + np.sqrt(l2 * l2 + 100.0 * l2)) / 50.0))
+
+
+def flow_dlambda_dt(reg: int, t: float) -> float:
+    return 5.0 * abs(t) * (2.0 - t * t) / (1.0 - t * t) ** 1.5 if reg == REG_DELTA else 1.0
+
+
+def flow_prop(grid: Grid, reg: int, lam: float, Delta: float, T: float, sigma, dsigma=None) -> Prop:
+    """Propagator at flow parameter lam: the hybridization for the Delta-flow, the
+    temperature for the T-flow, the regulator parameter of the interaction and frequency flows."""
     P = sigma_prop(grid, Delta, T, sigma)
+    if reg == REG_DELTA:
+        P.Delta = lam
+    elif reg == REG_T:
+        P.T = lam
+    P.reg, P.lam = reg, lam if reg in (REG_U, REG_NU) else 1.0
+    if dsigma is not None:
+        P.sigma_grid = grid
+        P.dSigR = np.ascontiguousarray(dsigma[:, 1])
+        P.dSigK = np.ascontiguousarray(dsigma[:, 0])
+    return P
+
+
+def state_pack(chans, sigma) -> np.ndarray:
+    """Flat state vector: channels a, p, t with classes K1, K2, K2', K3 each, then Sigma."""
+    return np.concatenate([getattr(chans[r], c).ravel() for r in range(3) for c in CLASSES] + [sigma.ravel()])
+
+
+def state_unpack(vec: np.ndarray, n: int):
+    shapes = class_shapes(n)
+    chans, off = [], 0
+    for r in range(3):
+        arrs = []
+        for c in CLASSES:
+            sz = int(np.prod(shapes[c]))
+            arrs.append(vec[off:off + sz].reshape(shapes[c]))
+            off += sz
+        chans.append(Channel(1.0, *arrs))
+    return chans, vec[off:].reshape(n, 4)
+
+
+@dataclass
+class FlowOptions:
+    """Options of the mfRG flow: regulator, Katanin substitution, self-energy corrections
+    (iterated while the max-norm change of Sigma_dot exceeds se_atol + se_rtol max|Sigma_dot|,
+    at most se_iterations times; 0 = none) and the ODE method (fixed-step classical RK4 or
+    Cash-Karp with step control on max_i |err_i| / (atol + rtol max(|y_i|, |y4_i|)))."""
+    reg: int = REG_DELTA
+    Delta: float = 1.0  # the hybridization of the flows other than the Delta-flow
+    katanin: bool = True
+    se_iterations: int = 0
+    se_atol: float = 1e-9
+    se_rtol: float = 1e-5
+    adaptive: bool = False
+    atol: float = 1e-8
+    rtol: float = 1e-5
+    max_steps: int = 200
+
+
+def mfrg_rhs(grid: Grid, U: float, T: float, lam: float, nloops: int, q_bubble: Quad, q_loop: Quad, chans, sigma,
+             fo: Optional[FlowOptions] = None, info: Optional[dict] = None):
+    """Right-hand side of the flow (Sec. mfRG) at flow parameter lam:
+      Sigma_dot^(1) = -L(Gamma, S)                            (one-loop self-energy flow)
+      Gamma_dot     = sum_{l <= nloops} gdot^(l), with the l = 1 bubble differentiated along
+                      S + G Sigma_dot G (Katanin) or S
+    and, with self-energy corrections (nloops >= 3), iterated from there:
+      Sigma_dot_tbar = -L(gdot_{a,C} + gdot_{p,C}, G)          (centre terms summed over l)
+      Sigma_dot_t    = -L(Gamma, G Sigma_dot_tbar G)
+      Sigma_dot      = Sigma_dot^(1) + Sigma_dot_tbar + Sigma_dot_t,
+    re-evaluating Gamma_dot with the new Sigma_dot after each update."""
+    fo = fo or FlowOptions()
+    P = flow_prop(grid, fo.reg, lam, fo.Delta, T, sigma)
     V = Vertex(grid, U, chans)
-    ins = mloop(V, P, q_bubble, nloops)
+    sd1 = -loop(V, P, q_loop, kind=1)
+    sd = sd1
+    it = 0
+    while True:
+        Pk = flow_prop(grid, fo.reg, lam, fo.Delta, T, sigma, sd if fo.katanin else None)
+        cen = []
+        ins = mloop(V, Pk, q_bubble, nloops, centres=cen)
+        if fo.se_iterations <= 0 or nloops < 3:
+            break
+        ca = Channel(1.0, *[sum(getattr(cen[l][0], c) for l in range(len(cen))) for c in CLASSES])
+        cp = Channel(1.0, *[sum(getattr(cen[l][1], c) for l in range(len(cen))) for c in CLASSES])
+        tbar = -loop(Vertex(grid, 0.0, [ca, cp, Channel(0.0)]), P, q_loop, kind=0)
+        st = -loop(V, flow_prop(grid, fo.reg, lam, fo.Delta, T, sigma, tbar), q_loop, kind=2)
+        new = sd1 + tbar + st
+        change = float(np.abs(new - sd).max())
+        sd = new
+        it += 1
+        if change <= fo.se_atol + fo.se_rtol * float(np.abs(new).max()) or it >= fo.se_iterations:
+            break
+    if info is not None:
+        info["se_iterations"] = info.get("se_iterations", 0) + it
+        info["rhs"] = info.get("rhs", 0) + 1
     gdot = [Channel(1.0, *[sum(getattr(ins[l][r], c) for l in range(nloops)) for c in CLASSES]) for r in range(3)]
-    return gdot, -loop(V, P, q_loop, kind=1)
+    return gdot, sd
 
 
-def mfrg_flow(grid: Grid, U: float, T: float, Delta_i: float, Delta_f: float, steps: int, nloops: int,
-              q_bubble: Quad, q_loop: Quad, chans, sigma):
-    """Classical fourth-order Runge-Kutta integration of mfrg_rhs from Delta_i to Delta_f."""
-    h = (Delta_f - Delta_i) / steps
+# Cash-Karp embedded Runge-Kutta pair (Cash and Karp 1990): nodes, stage matrix, weights of
+# the fifth- and of the fourth-order solution.
+CK_C = (0.0, 1 / 5, 3 / 10, 3 / 5, 1.0, 7 / 8)
+CK_A = ((),
+        (1 / 5,),
+        (3 / 40, 9 / 40),
+        (3 / 10, -9 / 10, 6 / 5),
+        (-11 / 54, 5 / 2, -70 / 27, 35 / 27),
+        (1631 / 55296, 175 / 512, 575 / 13824, 44275 / 110592, 253 / 4096))
+CK_B5 = (37 / 378, 0.0, 250 / 621, 125 / 594, 0.0, 512 / 1771)
+CK_B4 = (2825 / 27648, 0.0, 18575 / 48384, 13525 / 55296, 277 / 14336, 1 / 4)
 
-    def add(y, k, c):
-        ch, s = y
-        kc, ks = k
-        return ([Channel(1.0, *[getattr(ch[r], x) + c * getattr(kc[r], x) for x in CLASSES]) for r in range(3)],
-                s + c * ks)
 
-    y = (chans, sigma)
-    for st in range(steps):
-        D0 = Delta_i + st * h
-        k1 = mfrg_rhs(grid, U, T, D0, nloops, q_bubble, q_loop, *y)
-        k2 = mfrg_rhs(grid, U, T, D0 + h / 2, nloops, q_bubble, q_loop, *add(y, k1, h / 2))
-        k3 = mfrg_rhs(grid, U, T, D0 + h / 2, nloops, q_bubble, q_loop, *add(y, k2, h / 2))
-        k4 = mfrg_rhs(grid, U, T, D0 + h, nloops, q_bubble, q_loop, *add(y, k3, h))
-        y = add(add(add(add(y, k1, h / 6), k2, h / 3), k3, h / 3), k4, h / 6)
-    return y
+def ode_solve(f, y0: np.ndarray, t0: float, t1: float, steps: int, adaptive: bool = False, atol: float = 1e-8,
+              rtol: float = 1e-5, max_steps: int = 200):
+    """Integrate y' = f(t, y) from t0 to t1.  Fixed: classical RK4 in `steps` equal steps.
+    Adaptive: Cash-Karp, advancing with the fourth-order solution; err = max_i |e_i| /
+    (atol + rtol max(|y_i|, |y4_i|)) with e = h sum_j (b5_j - b4_j) k_j; accept when err <= 1
+    and grow h by min(5, 0.9 err^(-1/5)), else shrink by max(0.1, 0.9 err^(-1/4)) and retry;
+    the first trial step is (t1 - t0) / steps and the last one is cut to land on t1.
+    Returns (y, accepted t values including t0, number of rejected steps)."""
+    y, t = y0, t0
+    ts = [t0]
+    if not adaptive:
+        h = (t1 - t0) / steps
+        for st in range(steps):
+            ta = t0 + st * h
+            k1 = f(ta, y)
+            k2 = f(ta + h / 2, y + (h / 2) * k1)
+            k3 = f(ta + h / 2, y + (h / 2) * k2)
+            k4 = f(ta + h, y + h * k3)
+            y = y + (h / 6) * k1 + (h / 3) * k2 + (h / 3) * k3 + (h / 6) * k4
+            ts.append(t0 + (st + 1) * h)
+        return y, ts, 0
+    h = (t1 - t0) / steps
+    rejected, k1 = 0, None
+    for _ in range(max_steps):
+        last = (t + h - t1) * np.sign(t1 - t0) >= 0.0
+        if last:
+            h = t1 - t
+        if k1 is None:
+            k1 = f(t, y)
+        ks = [k1]
+        for i in range(1, 6):
+            yi = y + h * sum(a * k for a, k in zip(CK_A[i], ks))
+            ks.append(f(t + CK_C[i] * h, yi))
+        y4 = y + h * sum(b * k for b, k in zip(CK_B4, ks))
+        e = h * sum((b5 - b4) * k for b5, b4, k in zip(CK_B5, CK_B4, ks))
+        err = float((np.abs(e) / (atol + rtol * np.maximum(np.abs(y), np.abs(y4)))).max())
+        if err <= 1.0:
+            y, t, k1 = y4, (t1 if last else t + h), None
+            ts.append(t)
+            if last:
+                return y, ts, rejected
+            h *= 5.0 if err == 0.0 else min(5.0, 0.9 * err ** -0.2)
+        else:
+            rejected += 1
+            h *= max(0.1, 0.9 * err ** -0.25)
+    raise RuntimeError("ode_solve: step limit reached")
+
+
+def mfrg_flow(grid: Grid, U: float, T: float, lam_i: float, lam_f: float, steps: int, nloops: int,
+              q_bubble: Quad, q_loop: Quad, chans, sigma, fo: Optional[FlowOptions] = None):
+    """Integrate the flow (mfrg_rhs) of the state (chans, sigma) from lam_i to lam_f (Sec. ODE
+    solver).  Returns (chans, sigma, info) with info["lambdas"] the accepted flow parameters."""
+    fo = fo or FlowOptions()
+    n = grid.n
+    info = {}
+
+    def f(t, vec):
+        ch, sg = state_unpack(vec, n)
+        gd, sd = mfrg_rhs(grid, U, T, flow_lambda(fo.reg, t), nloops, q_bubble, q_loop, ch, sg, fo, info)
+        return flow_dlambda_dt(fo.reg, t) * state_pack(gd, sd)
+
+    y, ts, rej = ode_solve(f, state_pack(chans, sigma), flow_t(fo.reg, lam_i), flow_t(fo.reg, lam_f), steps,
+                           fo.adaptive, fo.atol, fo.rtol, fo.max_steps)
+    info["lambdas"] = [flow_lambda(fo.reg, t) for t in ts]
+    info["rejected"] = rej
+    ch, sg = state_unpack(y, n)
+    return ch, sg, info

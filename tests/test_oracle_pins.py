@@ -670,7 +670,7 @@ def test_flow_of_pt2_vertex_reaches_pt2_at_the_end_to_second_order():
     devs = {}
     for u, steps in ((0.1, 4), (0.05, 4), (0.05, 2)):
         chans, sig = O.pt2_state(g, u, 2.0, T, q, q)
-        chans, sig = O.mfrg_flow(g, u, T, 2.0, 1.0, steps, 1, q, q, chans, sig)
+        chans, sig, _ = O.mfrg_flow(g, u, T, 2.0, 1.0, steps, 1, q, q, chans, sig)
         ref = O.pt2_k1(g, u, O.Prop(1.0, T), q)
         devs[(u, steps)] = max(np.abs(chans[r].K1 - ref[r]).max() / np.abs(ref[r]).max() for r in range(3))
     d1, d2 = devs[(0.1, 4)], devs[(0.05, 4)]
@@ -687,7 +687,7 @@ def test_flow_self_energy_matches_sde_pt2_up_to_discretisation():
     for n, nq in ((9, 31), (17, 81)):
         g, q = O.Grid(n), O.Quad(nq)
         chans, sig = O.pt2_state(g, 0.05, 2.0, T, q, q)
-        chans, sig = O.mfrg_flow(g, 0.05, T, 2.0, 1.0, 2, 1, q, q, chans, sig)
+        chans, sig, _ = O.mfrg_flow(g, 0.05, T, 2.0, 1.0, 2, 1, q, q, chans, sig)
         s2 = O.sde(O.bare(g, 0.05), O.Prop(1.0, T), q, q)
         devs.append(np.abs(sig - s2).max() / np.abs(s2).max())
     assert devs[0] < 0.1 and devs[1] < 0.75 * devs[0]
