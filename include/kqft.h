@@ -57,15 +57,24 @@ enum {
   KQFT_EINVAL = -1,  /* bad enum, NULL where not allowed */
   KQFT_ESHAPE = -2,  /* inconsistent grid / quadrature sizes */
   KQFT_ENOMEM = -3,  /* workspace allocation failed */
-  KQFT_EDEVICE = -4  /* HIP runtime error */
+  KQFT_EDEVICE = -4, /* HIP runtime error */
+  KQFT_ENOCONV = -5  /* an iteration or step limit was reached (flow step control) */
 };
 enum { KQFT_CH_A = 0, KQFT_CH_P = 1, KQFT_CH_T = 2 };
 /* arithmetic of the bubble contraction: FP64 MFMA, or FP32 MFMA on split
    operands with FP32 accumulation promoted to FP64 every K block */
 enum { KQFT_FP64 = 0, KQFT_SPLIT_FP32 = 1 };
 /* propagator pair: Pi = G G, or the differentiated Pidot = S G + G S with the
-   Delta-flow single-scale propagator S = dG/dDelta at fixed Sigma */
+   single-scale propagator S = dG/dLambda at fixed Sigma of the propagator's regulator
+   (S + G Sigma_dot G when the propagator carries Sigma_dot: Katanin substitution) */
 enum { KQFT_PI_GG = 0, KQFT_PI_DOT = 1 };
+/* regulators (Sec. "Flow schemes"), the flow parameter Lambda of S = dG/dLambda:
+   DELTA: Lambda = Delta;  U: G_0 -> Lambda G_0 (interaction flow, Lambda = lam);
+   T: Lambda = T (temperature flow);  NU: G_0 -> Theta G_0, Theta = v / (v + i lam) (lam > 0) */
+enum { KQFT_REG_DELTA = 0, KQFT_REG_U = 1, KQFT_REG_T = 2, KQFT_REG_NU = 3 };
+/* line of a loop (kqft_loop): G, the single-scale propagator (with Katanin, if Sigma_dot is
+   given), or G Sigma_dot G */
+enum { KQFT_LINE_G = 0, KQFT_LINE_S = 1, KQFT_LINE_GSG = 2 };
 /* asymptotic classes of a bubble output */
 enum { KQFT_K1 = 1, KQFT_K2 = 2, KQFT_K2P = 4, KQFT_K3 = 8, KQFT_KALL = 15 };
 /* quadrature maps: Gauss-Legendre nodes y in [-1,1] mapped to v = a tan(y atan(L/a))
@@ -101,15 +110,26 @@ typedef struct {
   kqft_chvert ch[3];
 } kqft_vertex;
 
-/* propagator (Sec. "The Propagator class"): G^R = 1/(v - eps + i Delta - Sigma^R(v)),
-   G^K = G^R [Sigma^K - 2 i Delta tanh(v/2T)] G^A.  SigR/SigK are optional device
-   arrays of n complex values on sgrid (NULL SigR: Sigma = 0; NULL SigK with
-   SigR given: equilibrium FDR Sigma^K = 2i tanh(v/2T) Im Sigma^R). */
+/* propagator (Sec. "The Propagator class", Sec. "Flow schemes"):
+     G^R = 1/(G_0^{-1,R}(v) - Sigma^R(v)),  G^K = G^R [Sigma^K - G_0^{-1,K}] G^A,
+     G_0^{-1,K} = 2 i tanh(v/2T) Im G_0^{-1,R}  (bath in equilibrium),
+   G_0^{-1,R} = v - eps + i Delta (reg DELTA and T), (v - eps + i Delta) / lam (reg U),
+   (v - eps + i Delta)(v + i lam) / v (reg NU).  SigR/SigK are optional device arrays of n
+   complex values on sgrid (NULL SigR: Sigma = 0; NULL SigK with SigR given: equilibrium
+   FDR Sigma^K = 2i tanh(v/2T) Im Sigma^R).  dSigR/dSigK: optional Sigma_dot on sgrid (both
+   or neither); with them the single-scale line becomes S + G Sigma_dot G (Katanin) and the
+   GSG line of a loop is G Sigma_dot G,
+     (G s G)^R = G^R s^R G^R,  (G s G)^K = G^R s^R G^K + G^R s^K G^A + G^K s^A G^A.
+   A zero-initialised struct (reg 0, no Sigma_dot) is the plain Delta-regulated propagator. */
 typedef struct {
   double Delta, T, eps;
   kqft_grid sgrid;
   const double* SigR;
   const double* SigK;
+  int reg;    /* KQFT_REG_* */
+  double lam; /* regulator parameter of reg U (> 0) and NU (> 0); unused otherwise */
+  const double* dSigR;
+  const double* dSigK;
 } kqft_propagator;
 
 /* output classes of one channel (device arrays, layouts as above; NULL = skip) */
@@ -196,7 +216,9 @@ int kqft_sde(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, 
  * contraction of a vertex with one propagator line):
  *   L(Gamma, X)^{a1'|a1}(v_i) = sum_j w_j/(2 pi i) sum_{a2,a2'} [2 Gamma^X + Gamma^Y]
  *                                 (legs v_i, v_j | v_i, v_j) X^{a2|a2'}(v_j),
- * X = G (kind 0) or the single-scale propagator S = dG/dDelta at fixed Sigma (kind 1);
+ * X = G (KQFT_LINE_G), the single-scale propagator S = dG/dLambda at fixed Sigma of G's
+ * regulator, plus G Sigma_dot G when G carries Sigma_dot (KQFT_LINE_S), or G Sigma_dot G
+ * alone (KQFT_LINE_GSG, needs Sigma_dot);
  * Gamma = Gamma_0(r0) + sum_r coef_r gamma_r, every channel read at its own parameters.
  * The one-loop self-energy flow is Sigma_dot = -L(Gamma, S).  out: device [n][4] complex
  * (index 2*a1' + a1) on gamma->grid.  FP64.
@@ -204,21 +226,57 @@ int kqft_sde(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, 
 int kqft_loop(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, int kind, const kqft_quad* q,
               double* out, void* stream);
 
+/* options of kqft_mfrg_flow */
+typedef struct {
+  int reg;               /* KQFT_REG_*: the flow parameter */
+  double Delta;          /* hybridization of the flows other than the Delta-flow */
+  int katanin;           /* 1: the differentiated bubble uses S + G Sigma_dot G; 0: S */
+  int se_iterations;     /* multiloop self-energy corrections (nloops >= 3): at most this many
+                            iterations per right-hand side; 0: none */
+  double se_tol_abs;     /* stop when max|Sigma_dot_new - Sigma_dot| <= abs + rel max|Sigma_dot_new| */
+  double se_tol_rel;
+  int adaptive;          /* 0: classical RK4 in `steps` equal steps; 1: Cash-Karp step control */
+  double ode_tol_abs;    /* accept a step when max_i |e_i| / (abs + rel max(|y_i|, |y4_i|)) <= 1 */
+  double ode_tol_rel;
+  int max_steps;         /* accepted + rejected steps (adaptive); KQFT_ENOCONV beyond */
+} kqft_flow_opts;
+
+/* what a flow did */
+typedef struct {
+  int accepted;          /* accepted steps */
+  int rejected;          /* rejected trial steps */
+  int rhs_evaluations;   /* right-hand sides evaluated */
+  int se_iterations;     /* self-energy correction iterations, summed over the right-hand sides */
+} kqft_flow_info;
+
 /*
- * kqft_mfrg_flow -- multiloop fRG flow (Sec. "mfRG") in the hybridization Delta: the
- * regulator is Delta itself, the single-scale propagator S = dG/dDelta at fixed Sigma.
- * Integrates, with the classical fourth-order Runge-Kutta rule in `steps` equal steps from
- * Delta_i to Delta_f,
- *   Gamma_dot = sum_{l <= nloops} gdot^(l)   (the insertions of kqft_mloop_step),
- *   Sigma_dot = -L(Gamma, S)                   (kqft_loop, one-loop self-energy flow),
- * without the Katanin substitution and without multiloop self-energy corrections.
- * State in/out: gamma[3] (the three channels of Gamma = Gamma_0(U) + sum_r gamma_r, all four
- * classes, device) and sigma (device [n][4], Sigma^K at index 0 and Sigma^R at 1, on grid),
- * e.g. the PT2 or parquet state at Delta_i.  Bubbles in opts->precision.
+ * kqft_mfrg_flow -- multiloop fRG flow (Sec. "mfRG", Sec. "Details on the ODE-solver",
+ * Sec. "Flow schemes") of the state (Gamma = Gamma_0(U) + sum_r gamma_r, Sigma) from
+ * Lambda_i to Lambda_f.  Right-hand side at Lambda, with G dressed by the state's Sigma:
+ *   Sigma_dot^(1) = -L(Gamma, S)                         (one-loop self-energy flow),
+ *   Gamma_dot     = sum_{l <= nloops} gdot^(l)          (the insertions of kqft_mloop_step,
+ *                   the l = 1 bubble along S + G Sigma_dot G with katanin, else S),
+ * and with se_iterations > 0 and nloops >= 3, iterated from there:
+ *   Sigma_dot_tbar = -L(sum_l (gdot_{a,C}^(l) + gdot_{p,C}^(l)), G)   (centre terms),
+ *   Sigma_dot_t    = -L(Gamma, G Sigma_dot_tbar G),
+ *   Sigma_dot      = Sigma_dot^(1) + Sigma_dot_tbar + Sigma_dot_t,
+ * re-evaluating Gamma_dot with each new Sigma_dot until the change is within tolerance.
+ * The ODE runs in t with Lambda(t) = 5 t|t| / sqrt(1 - t^2) for the Delta-flow and
+ * Lambda = t otherwise; classical RK4 in `steps` equal steps in t, or Cash-Karp advancing
+ * the fourth-order solution with the first trial step (t_f - t_i)/steps, growth by
+ * min(5, 0.9 err^-1/5) after an accepted and shrinkage by max(0.1, 0.9 err^-1/4) after a
+ * rejected step, the last step cut to land on t_f.
+ * State in/out: gamma[3] (the three channels, all four classes, device) and sigma (device
+ * [n][4], Sigma^K at index 0 and Sigma^R at 1, on grid).  lambdas (host, capacity
+ * max_steps + 1 for adaptive, steps + 1 otherwise, or NULL): the accepted Lambda values,
+ * starting with Lambda_i; info (host, or NULL).  Bubbles in opts->precision, loops FP64.
+ * Synchronises `stream` once per trial step (adaptive) and per correction iteration.
+ * Working memory: 9 (adaptive) or 4 states plus nloops x 3 channels.
  */
-int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, double Delta_i, double Delta_f,
+int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, double Lambda_i, double Lambda_f,
                    int steps, int nloops, const kqft_quad* q_bubble, const kqft_quad* q_loop, const kqft_opts* opts,
-                   const kqft_chout* gamma, double* sigma, void* stream);
+                   const kqft_flow_opts* flow, const kqft_chout* gamma, double* sigma, double* lambdas,
+                   kqft_flow_info* info, void* stream);
 
 /*
  * kqft_parquet_iteration -- right-hand sides of the parquet equations (Sec. "parquet

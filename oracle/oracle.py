@@ -633,7 +633,8 @@ def ode_solve(f, y0: np.ndarray, t0: float, t1: float, steps: int, adaptive: boo
               rtol: float = 1e-5, max_steps: int = 200):
     """Integrate y' = f(t, y) from t0 to t1.  Fixed: classical RK4 in `steps` equal steps.
     Adaptive: Cash-Karp, advancing with the fourth-order solution; err = max_i |e_i| /
-    (atol + rtol max(|y_i|, |y4_i|)) with e = h sum_j (b5_j - b4_j) k_j; accept when err <= 1
+    (atol + rtol max(|y_i|, |y4_i|)) (entries with e_i = 0 count as 0, a NaN makes err
+    infinite) with e = h sum_j (b5_j - b4_j) k_j; accept when err <= 1
     and grow h by min(5, 0.9 err^(-1/5)), else shrink by max(0.1, 0.9 err^(-1/4)) and retry;
     the first trial step is (t1 - t0) / steps and the last one is cut to land on t1.
     Returns (y, accepted t values including t0, number of rejected steps)."""
@@ -664,7 +665,12 @@ def ode_solve(f, y0: np.ndarray, t0: float, t1: float, steps: int, adaptive: boo
             ks.append(f(t + CK_C[i] * h, yi))
         y4 = y + h * sum(b * k for b, k in zip(CK_B4, ks))
         e = h * sum((b5 - b4) * k for b5, b4, k in zip(CK_B5, CK_B4, ks))
-        err = float((np.abs(e) / (atol + rtol * np.maximum(np.abs(y), np.abs(y4)))).max())
+        ae = np.abs(e)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            ratio = np.where(ae == 0.0, 0.0, ae / (atol + rtol * np.maximum(np.abs(y), np.abs(y4))))
+        err = float(ratio.max())
+        if not np.isfinite(err):
+            err = np.inf
         if err <= 1.0:
             y, t, k1 = y4, (t1 if last else t + h), None
             ts.append(t)

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <string>
 #include <tuple>
@@ -42,7 +43,7 @@ struct kqft_ctx {
   // consecutive transfer-frequency batches overlap, ordered by events
   hipStream_t sg = nullptr, sm = nullptr;
   rocblas_handle blas = nullptr;
-  DevBuf adjw, dkf[2][3], phigrad, pq, pqsig, pqred, vtab[3], flow, flowml;
+  DevBuf adjw, dkf[2][3], phigrad, pq, pqsig, pqred, vtab[3], flow, flowml, ctmp, flowred;
   std::vector<hipEvent_t> events;
   size_t next_event = 0;
   bool prof = false;
@@ -205,12 +206,21 @@ static DVert to_dvert(const kqft_vertex& v) {
 
 static int to_dprop(const kqft_propagator& p, DProp& d) {
   if (!(p.T > 0) || !(p.Delta > 0)) return fail(KQFT_EINVAL, "propagator needs T > 0 and Delta > 0");
+  if (p.reg < KQFT_REG_DELTA || p.reg > KQFT_REG_NU) return fail(KQFT_EINVAL, "unknown regulator");
+  if ((p.reg == KQFT_REG_U || p.reg == KQFT_REG_NU) && !(p.lam > 0))
+    return fail(KQFT_EINVAL, "the interaction and frequency regulators need lam > 0");
+  if ((p.dSigR == nullptr) != (p.dSigK == nullptr))
+    return fail(KQFT_EINVAL, "Sigma_dot needs both dSigR and dSigK");
   d.Delta = p.Delta;
   d.T = p.T;
   d.eps = p.eps;
   d.SigR = (const double2*)p.SigR;
   d.SigK = (const double2*)p.SigK;
-  if (p.SigR || p.SigK) {
+  d.reg = p.reg;
+  d.lam = p.lam;
+  d.dSigR = (const double2*)p.dSigR;
+  d.dSigK = (const double2*)p.dSigK;
+  if (p.SigR || p.SigK || p.dSigR) {
     int rc = check_grid(p.sgrid, "propagator self-energy grid");
     if (rc) return rc;
     d.sg = make_dgrid(p.sgrid.n, p.sgrid.L, p.sgrid.a);
@@ -844,7 +854,7 @@ int kqft_ctx_destroy(kqft_ctx* ctx) {
       if (b.p) (void)hipFree(b.p);
   if (ctx->adjw.p) (void)hipFree(ctx->adjw.p);
   for (DevBuf* b : {&ctx->pq, &ctx->pqsig, &ctx->pqred, &ctx->vtab[0], &ctx->vtab[1], &ctx->vtab[2], &ctx->flow,
-                    &ctx->flowml})
+                    &ctx->flowml, &ctx->ctmp, &ctx->flowred})
     if (b->p) (void)hipFree(b->p);
   if (ctx->phigrad.p) (void)hipFree(ctx->phigrad.p);
   if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
@@ -933,28 +943,69 @@ int kqft_loop(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G,
   if (q->n < 1 || (q->map != KQFT_QUAD_TAN_FINITE && q->map != KQFT_QUAD_TAN_INFINITE) ||
       (q->map == KQFT_QUAD_TAN_FINITE && !(q->L > 0)) || !(q->a > 0))
     return fail(KQFT_ESHAPE, "invalid quadrature");
-  if (kind != 0 && kind != 1) return fail(KQFT_EINVAL, "kind must be 0 (G) or 1 (S)");
+  if (kind < KQFT_LINE_G || kind > KQFT_LINE_GSG) return fail(KQFT_EINVAL, "kind must be a KQFT_LINE_* value");
+  if (kind == KQFT_LINE_GSG && !G->dSigR) return fail(KQFT_EINVAL, "the G Sigma_dot G line needs Sigma_dot");
   if ((rc = check_vertex(gamma, "gamma"))) return rc;
   if (!out) return fail(KQFT_EINVAL, "out is NULL");
   HIP_TRY(hipSetDevice(ctx->device));
   return vloop_core(ctx, *gamma, *G, kind, *q, out, (hipStream_t)stream);
 }
 
-int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, double Delta_i, double Delta_f,
+static int mloop_core(kqft_ctx* ctx, const kqft_vertex& V, const kqft_propagator& G, const kqft_quad& q, int nloops,
+                      kqft_opts o, const std::function<BubbleOut(int, int)>& dview, const BubbleOut* centre,
+                      hipStream_t s);
+
+// Flow parameter of the ODE (Sec. "Details on the ODE-solver"): the Delta-flow runs in t with
+// Lambda(t) = 5 t|t| / sqrt(1 - t^2), the other flows in Lambda itself.
+static double flow_lambda(int reg, double t) { return reg == KQFT_REG_DELTA ? 5.0 * t * fabs(t) / sqrt(1.0 - t * t) : t; }
+static double flow_t(int reg, double lam) {
+  if (reg != KQFT_REG_DELTA) return lam;
+  const double l2 = lam * lam;  // 25 t^4 + Lambda^2 t^2 - Lambda^2 = 0
+  return copysign(sqrt((-l2 + sqrt(l2 * l2 + 100.0 * l2)) / 50.0), lam);
+}
+static double flow_dlambda_dt(int reg, double t) {
+  return reg == KQFT_REG_DELTA ? 5.0 * fabs(t) * (2.0 - t * t) / pow(1.0 - t * t, 1.5) : 1.0;
+}
+
+// Cash-Karp embedded pair (Cash and Karp 1990): nodes, stage matrix, fifth- and fourth-order weights.
+static const double kCkC[6] = {0.0, 1.0 / 5, 3.0 / 10, 3.0 / 5, 1.0, 7.0 / 8};
+static const double kCkA[6][5] = {{0, 0, 0, 0, 0},
+                                  {1.0 / 5, 0, 0, 0, 0},
+                                  {3.0 / 40, 9.0 / 40, 0, 0, 0},
+                                  {3.0 / 10, -9.0 / 10, 6.0 / 5, 0, 0},
+                                  {-11.0 / 54, 5.0 / 2, -70.0 / 27, 35.0 / 27, 0},
+                                  {1631.0 / 55296, 175.0 / 512, 575.0 / 13824, 44275.0 / 110592, 253.0 / 4096}};
+static const double kCkB5[6] = {37.0 / 378, 0.0, 250.0 / 621, 125.0 / 594, 0.0, 512.0 / 1771};
+static const double kCkB4[6] = {2825.0 / 27648, 0.0, 18575.0 / 48384, 13525.0 / 55296, 277.0 / 14336, 1.0 / 4};
+
+int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, double Lambda_i, double Lambda_f,
                    int steps, int nloops, const kqft_quad* q_bubble, const kqft_quad* q_loop, const kqft_opts* opts,
-                   const kqft_chout* gamma, double* sigma, void* stream) {
+                   const kqft_flow_opts* flow, const kqft_chout* gamma, double* sigma, double* lambdas,
+                   kqft_flow_info* info, void* stream) {
   int rc;
   if (!ctx) return fail(KQFT_EINVAL, "ctx is NULL");
+  if (!flow) return fail(KQFT_EINVAL, "flow options must be given");
   if (!grid || (rc = check_grid(*grid, "grid"))) return grid ? rc : fail(KQFT_EINVAL, "grid is NULL");
+  const kqft_flow_opts fo = *flow;
+  if (fo.reg < KQFT_REG_DELTA || fo.reg > KQFT_REG_NU) return fail(KQFT_EINVAL, "unknown regulator");
+  const double Dphys = fo.reg == KQFT_REG_DELTA ? Lambda_i : fo.Delta;
+  if (!(T > 0) || !(Dphys > 0)) return fail(KQFT_EINVAL, "T and Delta must be positive");
+  if (!(Lambda_i > 0) || !(Lambda_f > 0)) return fail(KQFT_EINVAL, "the flow parameter must stay positive");
+  if (fo.reg == KQFT_REG_DELTA && (Lambda_i > 1e6 || Lambda_f > 1e6))
+    return fail(KQFT_EINVAL, "Delta-flow parameter beyond the reparametrisation's range");
   kqft_propagator Gc;
   memset(&Gc, 0, sizeof Gc);
-  Gc.Delta = Delta_i;
+  Gc.Delta = Dphys;
   Gc.T = T;
   Gc.sgrid = *grid;
   if ((rc = check_common(ctx, &Gc, q_bubble, opts))) return rc;
   if (!q_loop || q_loop->n < 1) return fail(KQFT_ESHAPE, "invalid loop quadrature");
-  if (!(T > 0) || !(Delta_i > 0) || !(Delta_f > 0)) return fail(KQFT_EINVAL, "T and Delta must be positive");
   if (steps < 1 || nloops < 1) return fail(KQFT_EINVAL, "need steps >= 1 and nloops >= 1");
+  if (fo.se_iterations < 0 || !(fo.se_tol_abs >= 0) || !(fo.se_tol_rel >= 0))
+    return fail(KQFT_EINVAL, "self-energy correction settings must be non-negative");
+  if (fo.adaptive && (fo.max_steps < 1 || !(fo.ode_tol_abs >= 0) || !(fo.ode_tol_rel >= 0) ||
+                      !(fo.ode_tol_abs + fo.ode_tol_rel > 0)))
+    return fail(KQFT_EINVAL, "adaptive steps need max_steps >= 1 and positive tolerances");
   if (!gamma || !sigma) return fail(KQFT_EINVAL, "gamma and sigma must be given");
   for (int r = 0; r < 3; ++r)
     if (!gamma[r].K1 || !gamma[r].K2 || !gamma[r].K2p || !gamma[r].K3)
@@ -964,53 +1015,74 @@ int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, dou
   const int n = grid->n;
   const size_t c1 = (size_t)2 * n * 16, c2 = (size_t)2 * n * n * 16, c3 = (size_t)2 * n * n * n * 16;
   const size_t cnt[4] = {c1, c2, c2, c3};
-  const size_t chc = c1 + 2 * c2 + c3;             // complex entries of one channel
-  const size_t stc = 3 * chc + (size_t)4 * n;      // of the state (three channels, Sigma)
-  // three state-sized buffers (stage input, stage derivative, accumulated update), Sigma^R/K
-  if ((rc = ensure(ctx->flow, (3 * stc + 2 * (size_t)n) * sizeof(double2)))) return rc;
+  const size_t chc = c1 + 2 * c2 + c3;         // complex entries of one channel
+  const size_t stc = 3 * chc + (size_t)4 * n;  // of the state: channels a, p, t (K1, K2, K2', K3), Sigma
+  const bool corr = fo.se_iterations > 0 && nloops >= 3;
+  // states: Y, stage input, y4 and six stage derivatives (adaptive) or one (RK4) plus the
+  // RK4 accumulator; then Sigma-sized work arrays and two centre sums
+  const int nst = fo.adaptive ? 9 : 4;
+  const size_t aux = (size_t)22 * n;
+  if ((rc = ensure(ctx->flow, ((size_t)nst * stc + aux + (corr ? 2 * chc : 0)) * sizeof(double2)))) return rc;
   if ((rc = ensure(ctx->flowml, (size_t)nloops * 3 * chc * sizeof(double2)))) return rc;
+  const int nblk = (int)std::min<size_t>(1024, (stc + 255) / 256);
+  if ((rc = ensure(ctx->flowred, (size_t)2 * nblk * sizeof(double)))) return rc;
   double2* buf = (double2*)ctx->flow.p;
-  double2* yt = buf;            // stage input
-  double2* kd = buf + stc;      // stage derivative
-  double2* ys = buf + 2 * stc;  // accumulated update
-  double2* sigR = buf + 3 * stc;
-  double2* sigK = sigR + n;
+  double2* st[9];
+  for (int k = 0; k < nst; ++k) st[k] = buf + (size_t)k * stc;
+  double2* ax = buf + (size_t)nst * stc;
+  double2 *sigR = ax, *sigK = ax + n, *dsR = ax + 2 * n, *dsK = ax + 3 * n, *tR = ax + 4 * n, *tK = ax + 5 * n;
+  double2 *sd1 = ax + 6 * n, *tb = ax + 10 * n, *sdt = ax + 14 * n, *snew = ax + 18 * n;
+  double2* cen = ax + aux;
   double2* ml = (double2*)ctx->flowml.p;
-  // views of a state buffer: channel r class c, and Sigma
+  double* red = (double*)ctx->flowred.p;
   auto cls = [&](double2* base, int r, int c) {
     size_t off = (size_t)r * chc;
     for (int u = 0; u < c; ++u) off += cnt[u];
     return base + off;
   };
   auto sig_of = [&](double2* base) { return base + 3 * chc; };
-  double2* Y[3][4];
-  for (int r = 0; r < 3; ++r) {
-    Y[r][0] = (double2*)gamma[r].K1;
-    Y[r][1] = (double2*)gamma[r].K2;
-    Y[r][2] = (double2*)gamma[r].K2p;
-    Y[r][3] = (double2*)gamma[r].K3;
-  }
-  // out = a * (user state) + b * (buffer state), over every array
-  auto axpby_state = [&](double2* outb, bool out_user, double a, bool x_user, const double2* xb, double b,
-                         const double2* yb) {
-    for (int r = 0; r < 3; ++r)
-      for (int c = 0; c < 4; ++c)
-        launch_axpby(out_user ? Y[r][c] : cls(outb, r, c), a, x_user ? Y[r][c] : cls((double2*)xb, r, c), b,
-                     cls((double2*)yb, r, c), cnt[c], s);
-    launch_axpby(out_user ? (double2*)sigma : sig_of(outb), a, x_user ? (double2*)sigma : sig_of((double2*)xb), b,
-                 sig_of((double2*)yb), (size_t)4 * n, s);
+  auto chan_view = [&](double2* b0) { return BubbleOut{b0, b0 + c1, b0 + c1 + c2, b0 + c1 + 2 * c2}; };
+  auto lincomb = [&](double2* out, const double2* x, int nt, const double2* const* k, const double* c, size_t count) {
+    LinComb a;
+    memset(&a, 0, sizeof a);
+    a.out = out;
+    a.x = x;
+    a.nt = nt;
+    a.count = count;
+    for (int j = 0; j < nt; ++j) {
+      a.k[j] = k[j];
+      a.c[j] = c[j];
+    }
+    launch_lincomb(a, s);
   };
-  // derivative of the state held in `yb` (user arrays when yb == nullptr) at hybridization D
-  auto rhs = [&](double D, const double2* yb) -> int {
-    const double2* chs[3][4];
-    for (int r = 0; r < 3; ++r)
-      for (int c = 0; c < 4; ++c) chs[r][c] = yb ? cls((double2*)yb, r, c) : Y[r][c];
-    const double2* sg = yb ? sig_of((double2*)yb) : (const double2*)sigma;
-    launch_sigma_split(n, sg, sigR, sigK, s);
+  // max-norms (change, value) of f - x and f over count entries, on the host
+  auto maxdiff = [&](const double2* x, const double2* f, size_t count, double& md, double& mf) -> int {
+    const int nb = (int)std::min<size_t>(1024, (count + 255) / 256);
+    launch_maxdiff(x, f, count, red, nb, s);
+    std::vector<double> h((size_t)2 * nb);
+    HIP_TRY(hipMemcpyAsync(h.data(), red, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    md = mf = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      md = std::max(md, h[2 * (size_t)b]);
+      mf = std::max(mf, h[2 * (size_t)b + 1]);
+    }
+    return KQFT_OK;
+  };
+  kqft_flow_info inf;
+  memset(&inf, 0, sizeof inf);
+  // derivative dY/dt of the state yb at flow time t into kout
+  auto rhs = [&](double t, double2* yb, double2* kout) -> int {
+    int e;
+    const double lam = flow_lambda(fo.reg, t);
+    ++inf.rhs_evaluations;
+    launch_sigma_split(n, sig_of(yb), sigR, sigK, s);
     kqft_propagator G;
     memset(&G, 0, sizeof G);
-    G.Delta = D;
-    G.T = T;
+    G.Delta = fo.reg == KQFT_REG_DELTA ? lam : fo.Delta;
+    G.T = fo.reg == KQFT_REG_T ? lam : T;
+    G.reg = fo.reg;
+    G.lam = (fo.reg == KQFT_REG_U || fo.reg == KQFT_REG_NU) ? lam : 1.0;
     G.sgrid = *grid;
     G.SigR = (const double*)sigR;
     G.SigK = (const double*)sigK;
@@ -1019,48 +1091,169 @@ int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, dou
     V.r0 = U;
     V.grid = *grid;
     for (int r = 0; r < 3; ++r)
-      V.ch[r] = kqft_chvert{1.0, (const double*)chs[r][0], (const double*)chs[r][1], (const double*)chs[r][2],
-                            (const double*)chs[r][3]};
-    std::vector<kqft_chout> dg((size_t)nloops * 3);
-    for (int l = 0; l < nloops; ++l)
-      for (int r = 0; r < 3; ++r) {
-        double2* b0 = ml + ((size_t)l * 3 + r) * chc;
-        dg[(size_t)l * 3 + r] = kqft_chout{(double*)b0, (double*)(b0 + c1), (double*)(b0 + c1 + c2),
-                                           (double*)(b0 + c1 + 2 * c2)};
+      V.ch[r] = kqft_chvert{1.0, (const double*)cls(yb, r, 0), (const double*)cls(yb, r, 1),
+                            (const double*)cls(yb, r, 2), (const double*)cls(yb, r, 3)};
+    auto dview = [&](int l, int r) { return chan_view(ml + ((size_t)l * 3 + r) * chc); };
+    double2* sd = sig_of(kout);
+    // one-loop self-energy flow Sigma_dot^(1) = -L(Gamma, S)
+    if ((e = vloop_core(ctx, V, G, KQFT_LINE_S, *q_loop, (double*)sd1, s))) return e;
+    launch_axpby(sd1, -1.0, sd1, 0.0, sd1, (size_t)4 * n, s);
+    launch_axpby(sd, 1.0, sd1, 0.0, sd1, (size_t)4 * n, s);
+    BubbleOut centre[2] = {chan_view(cen), chan_view(cen + chc)};
+    for (int it = 0;;) {
+      kqft_propagator Gk = G;
+      if (fo.katanin) {
+        launch_sigma_split(n, sd, dsR, dsK, s);
+        Gk.dSigR = (const double*)dsR;
+        Gk.dSigK = (const double*)dsK;
       }
-    int e;
-    if ((e = kqft_mloop_step(ctx, 1, &V, &G, q_bubble, nloops, opts, dg.data(), s))) return e;
-    const size_t coff[4] = {0, c1, c1 + c2, c1 + 2 * c2};
-    for (int r = 0; r < 3; ++r)  // Gamma_dot = sum over the loop orders
+      if ((e = mloop_core(ctx, V, Gk, *q_bubble, nloops, *opts, dview, corr ? centre : nullptr, s))) return e;
+      if (!corr) break;
+      // Sigma_dot_tbar = -L(centre_a + centre_p, G); Sigma_dot_t = -L(Gamma, G Sigma_dot_tbar G)
+      kqft_vertex Vc;
+      memset(&Vc, 0, sizeof Vc);
+      Vc.grid = *grid;
+      for (int r = 0; r < 2; ++r)
+        Vc.ch[r] = kqft_chvert{1.0, (const double*)centre[r].K1, (const double*)centre[r].K2,
+                               (const double*)centre[r].K2p, (const double*)centre[r].K3};
+      if ((e = vloop_core(ctx, Vc, G, KQFT_LINE_G, *q_loop, (double*)tb, s))) return e;
+      launch_axpby(tb, -1.0, tb, 0.0, tb, (size_t)4 * n, s);
+      launch_sigma_split(n, tb, tR, tK, s);
+      kqft_propagator Gt = G;
+      Gt.dSigR = (const double*)tR;
+      Gt.dSigK = (const double*)tK;
+      if ((e = vloop_core(ctx, V, Gt, KQFT_LINE_GSG, *q_loop, (double*)sdt, s))) return e;
+      const double2* ks[2] = {tb, sdt};
+      const double cs[2] = {1.0, -1.0};
+      lincomb(snew, sd1, 2, ks, cs, (size_t)4 * n);
+      double md, mf;
+      if ((e = maxdiff(sd, snew, (size_t)4 * n, md, mf))) return e;
+      launch_axpby(sd, 1.0, snew, 0.0, snew, (size_t)4 * n, s);
+      ++it;
+      ++inf.se_iterations;
+      if (md <= fo.se_tol_abs + fo.se_tol_rel * mf || it >= fo.se_iterations) break;
+    }
+    // Gamma_dot = sum over the loop orders; everything times dLambda/dt
+    const double dl = flow_dlambda_dt(fo.reg, t);
+    for (int r = 0; r < 3; ++r)
       for (int c = 0; c < 4; ++c) {
-        double2* dst = cls(kd, r, c);
-        const double2* first = (const double2*)dg[r].K1 + coff[c];
-        launch_axpby(dst, 1.0, first, 0.0, first, cnt[c], s);  // dst = first (dst is not read)
-        for (int l = 1; l < nloops; ++l)
-          launch_axpby(dst, 1.0, dst, 1.0, (const double2*)dg[(size_t)l * 3 + r].K1 + coff[c], cnt[c], s);
+        double2* dst = cls(kout, r, c);
+        for (int l0 = 0; l0 < nloops; l0 += 6) {
+          const int nt = std::min(6, nloops - l0);
+          const double2* ks[6];
+          double cs[6];
+          for (int j = 0; j < nt; ++j) {
+            ks[j] = cls(ml + (size_t)(l0 + j) * 3 * chc, r, c);
+            cs[j] = dl;
+          }
+          lincomb(dst, l0 == 0 ? nullptr : dst, nt, ks, cs, cnt[c]);
+        }
       }
-    double2* sd = sig_of(kd);  // Sigma_dot = -L(Gamma, S)
-    if ((e = vloop_core(ctx, V, G, 1, *q_loop, (double*)sd, s))) return e;
-    launch_axpby(sd, -1.0, sd, 0.0, sd, (size_t)4 * n, s);
+    if (dl != 1.0) launch_axpby(sd, dl, sd, 0.0, sd, (size_t)4 * n, s);
     return KQFT_OK;
   };
-  const double h = (Delta_f - Delta_i) / steps;
-  for (int st = 0; st < steps; ++st) {
-    const double D0 = Delta_i + st * h;
-    if ((rc = rhs(D0, nullptr))) return rc;
-    axpby_state(ys, false, 1.0, true, nullptr, h / 6.0, kd);
-    axpby_state(yt, false, 1.0, true, nullptr, h / 2.0, kd);
-    if ((rc = rhs(D0 + h / 2.0, yt))) return rc;
-    axpby_state(ys, false, 1.0, false, ys, h / 3.0, kd);
-    axpby_state(yt, false, 1.0, true, nullptr, h / 2.0, kd);
-    if ((rc = rhs(D0 + h / 2.0, yt))) return rc;
-    axpby_state(ys, false, 1.0, false, ys, h / 3.0, kd);
-    axpby_state(yt, false, 1.0, true, nullptr, h, kd);
-    if ((rc = rhs(D0 + h, yt))) return rc;
-    axpby_state(nullptr, true, 1.0, false, ys, h / 6.0, kd);
+  // the user's state into Y
+  double2* Y = st[0];
+  for (int r = 0; r < 3; ++r) {
+    const double* src[4] = {gamma[r].K1, gamma[r].K2, gamma[r].K2p, gamma[r].K3};
+    for (int c = 0; c < 4; ++c)
+      HIP_TRY(hipMemcpyAsync(cls(Y, r, c), src[c], cnt[c] * sizeof(double2), hipMemcpyDeviceToDevice, s));
   }
+  HIP_TRY(hipMemcpyAsync(sig_of(Y), sigma, (size_t)4 * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  const double ti = flow_t(fo.reg, Lambda_i), tf = flow_t(fo.reg, Lambda_f);
+  int nl = 0;
+  auto record = [&](double t) {
+    if (lambdas) lambdas[nl] = flow_lambda(fo.reg, t);
+    ++nl;
+  };
+  record(ti);
+  int status = KQFT_OK;
+  if (!fo.adaptive) {
+    double2 *yt = st[1], *kd = st[2], *ys = st[3];
+    const double h = (tf - ti) / steps;
+    for (int k = 0; k < steps; ++k) {
+      const double ta = ti + k * h;
+      const double2* kk[1] = {kd};
+      double c[1];
+      if ((rc = rhs(ta, Y, kd))) return rc;
+      c[0] = h / 6.0;
+      lincomb(ys, Y, 1, kk, c, stc);
+      c[0] = h / 2.0;
+      lincomb(yt, Y, 1, kk, c, stc);
+      if ((rc = rhs(ta + h / 2.0, yt, kd))) return rc;
+      c[0] = h / 3.0;
+      lincomb(ys, ys, 1, kk, c, stc);
+      c[0] = h / 2.0;
+      lincomb(yt, Y, 1, kk, c, stc);
+      if ((rc = rhs(ta + h / 2.0, yt, kd))) return rc;
+      c[0] = h / 3.0;
+      lincomb(ys, ys, 1, kk, c, stc);
+      c[0] = h;
+      lincomb(yt, Y, 1, kk, c, stc);
+      if ((rc = rhs(ta + h, yt, kd))) return rc;
+      c[0] = h / 6.0;
+      lincomb(Y, ys, 1, kk, c, stc);
+      ++inf.accepted;
+      record(ti + (k + 1) * h);
+    }
+  } else {
+    double2 *yt = st[1], *y4 = st[2], *K[6];
+    for (int k = 0; k < 6; ++k) K[k] = st[3 + k];
+    const double dir = tf >= ti ? 1.0 : -1.0;
+    double t = ti, h = (tf - ti) / steps;
+    bool have_k1 = false, done = false;
+    std::vector<double> hr(nblk);
+    for (int trial = 0; trial < fo.max_steps && !done; ++trial) {
+      const bool last = (t + h - tf) * dir >= 0.0;
+      if (last) h = tf - t;
+      if (!have_k1) {
+        if ((rc = rhs(t, Y, K[0]))) return rc;
+        have_k1 = true;
+      }
+      for (int i = 1; i < 6; ++i) {
+        double c[5];
+        for (int j = 0; j < i; ++j) c[j] = h * kCkA[i][j];
+        lincomb(yt, Y, i, K, c, stc);
+        if ((rc = rhs(t + kCkC[i] * h, yt, K[i]))) return rc;
+      }
+      double c4[6], ce[6];
+      for (int j = 0; j < 6; ++j) {
+        c4[j] = h * kCkB4[j];
+        ce[j] = h * (kCkB5[j] - kCkB4[j]);
+      }
+      lincomb(y4, Y, 6, K, c4, stc);
+      lincomb(yt, nullptr, 6, K, ce, stc);
+      launch_errnorm(yt, Y, y4, fo.ode_tol_abs, fo.ode_tol_rel, stc, red, nblk, s);
+      HIP_TRY(hipMemcpyAsync(hr.data(), red, (size_t)nblk * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      double err = 0.0;
+      for (int b = 0; b < nblk; ++b) err = std::max(err, hr[b]);
+      if (err <= 1.0) {
+        std::swap(Y, y4);
+        st[2] = y4;
+        t = last ? tf : t + h;
+        have_k1 = false;
+        ++inf.accepted;
+        record(t);
+        if (last) done = true;
+        h *= err == 0.0 ? 5.0 : std::min(5.0, 0.9 * pow(err, -0.2));
+      } else {
+        ++inf.rejected;
+        h *= std::max(0.1, 0.9 * pow(err, -0.25));
+      }
+    }
+    if (!done) status = fail(KQFT_ENOCONV, "flow step limit reached before Lambda_f");
+  }
+  // Y back to the user's arrays
+  for (int r = 0; r < 3; ++r) {
+    double* dst[4] = {gamma[r].K1, gamma[r].K2, gamma[r].K2p, gamma[r].K3};
+    for (int c = 0; c < 4; ++c)
+      HIP_TRY(hipMemcpyAsync(dst[c], cls(Y, r, c), cnt[c] * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  }
+  HIP_TRY(hipMemcpyAsync(sigma, sig_of(Y), (size_t)4 * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipGetLastError());
-  return KQFT_OK;
+  if (info) *info = inf;
+  return status;
 }
 
 int kqft_parquet_iteration(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G,
@@ -1186,6 +1379,90 @@ int kqft_parquet_solve(kqft_ctx* ctx, const kqft_grid* grid, double U, double De
   return KQFT_OK;
 }
 
+// Multiloop insertions of one parameter point into dview(l - 1, r) (Eqs. 1l, 2l, 3l).  With
+// `centre` (two outputs, channels a and p), the centre terms of those channels are also
+// summed over l >= 3 into centre[0], centre[1] (written when nloops >= 3).
+static int mloop_core(kqft_ctx* ctx, const kqft_vertex& V, const kqft_propagator& G, const kqft_quad& q, int nloops,
+                      kqft_opts o, const std::function<BubbleOut(int, int)>& dview, const BubbleOut* centre,
+                      hipStream_t s) {
+  int rc;
+  o.class_mask = KQFT_KALL;
+  const int n = V.grid.n;
+  const size_t c1 = (size_t)2 * n * 16, c2 = (size_t)2 * n * n * 16, c3 = (size_t)2 * n * n * n * 16;
+  const size_t s1 = c1 * sizeof(double2), s2 = c2 * sizeof(double2), s3 = c3 * sizeof(double2);
+  const size_t chb = s1 + 2 * s2 + s3;
+  // left insertions of the previous and the current order, per channel
+  if (nloops >= 3)
+    for (int x = 0; x < 2; ++x)
+      for (int r = 0; r < 3; ++r)
+        if ((rc = ensure(ctx->lstore[x][r], chb))) return rc;
+  if (centre && nloops >= 3 && (rc = ensure(ctx->ctmp, chb))) return rc;
+  auto view_of = [&](void* p) {
+    char* b = (char*)p;
+    return BubbleOut{(double2*)b, (double2*)(b + s1), (double2*)(b + s1 + s2), (double2*)(b + s1 + 2 * s2)};
+  };
+  // out = a x + b y, class by class
+  auto comb = [&](const BubbleOut& out, double a, const BubbleOut& x, double b, const BubbleOut& y) {
+    launch_axpby(out.K1, a, x.K1, b, y.K1, c1, s);
+    launch_axpby(out.K2, a, x.K2, b, y.K2, c2, s);
+    launch_axpby(out.K2p, a, x.K2p, b, y.K2p, c2, s);
+    launch_axpby(out.K3, a, x.K3, b, y.K3, c3, s);
+  };
+  for (int l = 1; l <= nloops; ++l) {
+    const int cur = l & 1, prev = cur ^ 1;
+    for (int r = 0; r < 3; ++r) {
+      BubbleOut dst = dview(l - 1, r);
+      if (l == 1) {
+        o.beta = 0;
+        if ((rc = bubble_core(ctx, r, V, V, G, KQFT_PI_DOT, q, o, dst, s))) return rc;
+        continue;
+      }
+      kqft_vertex rbar;
+      memset(&rbar, 0, sizeof rbar);
+      rbar.grid = V.grid;
+      for (int r2 = 0; r2 < 3; ++r2) {
+        if (r2 == r) continue;
+        const BubbleOut d = dview(l - 2, r2);
+        rbar.ch[r2] = kqft_chvert{1.0, (const double*)d.K1, (const double*)d.K2, (const double*)d.K2p,
+                                  (const double*)d.K3};
+      }
+      // left insertion: into dst, and kept for the next order's centre term
+      o.beta = 0;
+      if ((rc = bubble_core(ctx, r, rbar, V, G, KQFT_PI_GG, q, o, dst, s))) return rc;
+      if (l + 1 <= nloops && l >= 2) {
+        BubbleOut lv = view_of(ctx->lstore[cur][r].p);
+        HIP_TRY(hipMemcpyAsync(lv.K1, dst.K1, s1, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(lv.K2, dst.K2, s2, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(lv.K2p, dst.K2p, s2, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(lv.K3, dst.K3, s3, hipMemcpyDeviceToDevice, s));
+      }
+      o.beta = 1;
+      if ((rc = bubble_core(ctx, r, V, rbar, G, KQFT_PI_GG, q, o, dst, s))) return rc;
+      if (l >= 3) {  // centre term B_r(Gamma, gdot_{r,L}^(l-1))
+        BubbleOut lv = view_of(ctx->lstore[prev][r].p);
+        kqft_vertex lvert;
+        memset(&lvert, 0, sizeof lvert);
+        lvert.grid = V.grid;
+        lvert.ch[r] = kqft_chvert{1.0, (const double*)lv.K1, (const double*)lv.K2, (const double*)lv.K2p,
+                                  (const double*)lv.K3};
+        if (centre && r < 2) {
+          BubbleOut ct = view_of(ctx->ctmp.p);
+          o.beta = 0;
+          if ((rc = bubble_core(ctx, r, V, lvert, G, KQFT_PI_GG, q, o, ct, s))) return rc;
+          comb(dst, 1.0, dst, 1.0, ct);
+          if (l == 3)
+            comb(centre[r], 1.0, ct, 0.0, ct);
+          else
+            comb(centre[r], 1.0, centre[r], 1.0, ct);
+        } else {
+          if ((rc = bubble_core(ctx, r, V, lvert, G, KQFT_PI_GG, q, o, dst, s))) return rc;
+        }
+      }
+    }
+  }
+  return KQFT_OK;
+}
+
 int kqft_mloop_step(kqft_ctx* ctx, int n_points, const kqft_vertex* gamma, const kqft_propagator* G,
                     const kqft_quad* q, int nloops, const kqft_opts* opts, const kqft_chout* dgamma,
                     void* stream) {
@@ -1204,68 +1481,21 @@ int kqft_mloop_step(kqft_ctx* ctx, int n_points, const kqft_vertex* gamma, const
   }
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
-  kqft_opts o = *opts;
-  o.class_mask = KQFT_KALL;
   for (int p = 0; p < n_points; ++p) {
-    const kqft_vertex& V = gamma[p];
-    const int n = V.grid.n;
-    const size_t s1 = (size_t)2 * n * 16 * 16, s2 = (size_t)2 * n * n * 16 * 16, s3 = (size_t)2 * n * n * n * 16 * 16;
-    const size_t chb = s1 + 2 * s2 + s3;
-    // left insertions of the previous and the current order, per channel
-    if (nloops >= 3)
-      for (int x = 0; x < 2; ++x)
-        for (int r = 0; r < 3; ++r)
-          if ((rc = ensure(ctx->lstore[x][r], chb))) return rc;
-    auto lview = [&](int x, int r) {
-      char* b = (char*)ctx->lstore[x][r].p;
-      return BubbleOut{(double2*)b, (double2*)(b + s1), (double2*)(b + s1 + s2), (double2*)(b + s1 + 2 * s2)};
-    };
     auto dview = [&](int l, int r) {
       const kqft_chout& d = dgamma[((size_t)p * nloops + l) * 3 + r];
       return BubbleOut{(double2*)d.K1, (double2*)d.K2, (double2*)d.K2p, (double2*)d.K3};
     };
-    for (int l = 1; l <= nloops; ++l) {
-      const int cur = l & 1, prev = cur ^ 1;
-      for (int r = 0; r < 3; ++r) {
-        BubbleOut dst = dview(l - 1, r);
-        if (l == 1) {
-          o.beta = 0;
-          if ((rc = bubble_core(ctx, r, V, V, G[p], KQFT_PI_DOT, q[p], o, dst, s))) return rc;
-          continue;
-        }
-        kqft_vertex rbar;
-        memset(&rbar, 0, sizeof rbar);
-        rbar.grid = V.grid;
-        for (int r2 = 0; r2 < 3; ++r2) {
-          if (r2 == r) continue;
-          const kqft_chout& d = dgamma[((size_t)p * nloops + (l - 2)) * 3 + r2];
-          rbar.ch[r2] = kqft_chvert{1.0, d.K1, d.K2, d.K2p, d.K3};
-        }
-        // left insertion: into dst, and kept for the next order's centre term
-        o.beta = 0;
-        if ((rc = bubble_core(ctx, r, rbar, V, G[p], KQFT_PI_GG, q[p], o, dst, s))) return rc;
-        if (l + 1 <= nloops && l >= 2) {
-          BubbleOut lv = lview(cur, r);
-          HIP_TRY(hipMemcpyAsync(lv.K1, dst.K1, s1, hipMemcpyDeviceToDevice, s));
-          HIP_TRY(hipMemcpyAsync(lv.K2, dst.K2, s2, hipMemcpyDeviceToDevice, s));
-          HIP_TRY(hipMemcpyAsync(lv.K2p, dst.K2p, s2, hipMemcpyDeviceToDevice, s));
-          HIP_TRY(hipMemcpyAsync(lv.K3, dst.K3, s3, hipMemcpyDeviceToDevice, s));
-        }
-        o.beta = 1;
-        if ((rc = bubble_core(ctx, r, V, rbar, G[p], KQFT_PI_GG, q[p], o, dst, s))) return rc;
-        if (l >= 3) {  // centre term B_r(Gamma, gdot_{r,L}^(l-1))
-          BubbleOut lv = lview(prev, r);
-          kqft_vertex lvert;
-          memset(&lvert, 0, sizeof lvert);
-          lvert.grid = V.grid;
-          lvert.ch[r] = kqft_chvert{1.0, (const double*)lv.K1, (const double*)lv.K2, (const double*)lv.K2p,
-                                    (const double*)lv.K3};
-          if ((rc = bubble_core(ctx, r, V, lvert, G[p], KQFT_PI_GG, q[p], o, dst, s))) return rc;
-        }
-      }
-    }
+    if ((rc = mloop_core(ctx, gamma[p], G[p], q[p], nloops, *opts, dview, nullptr, s))) return rc;
   }
   HIP_TRY(hipGetLastError());
+  return KQFT_OK;
+}
+
+// The adjoints differentiate the Delta-regulated propagator without Sigma_dot only.
+static int check_adjoint_prop(const kqft_propagator& G) {
+  if (G.reg != KQFT_REG_DELTA || G.dSigR || G.dSigK)
+    return fail(KQFT_EINVAL, "adjoints take the Delta-regulated propagator without Sigma_dot");
   return KQFT_OK;
 }
 
@@ -1275,6 +1505,7 @@ int kqft_bubble_adjoint(kqft_ctx* ctx, int channel, const kqft_vertex* left, con
                         void* stream) {
   int rc;
   if ((rc = check_common(ctx, G, q, opts))) return rc;
+  if ((rc = check_adjoint_prop(*G))) return rc;
   if (channel < 0 || channel > 2) return fail(KQFT_EINVAL, "channel must be 0 (a), 1 (p) or 2 (t)");
   if (pi_kind != KQFT_PI_GG && pi_kind != KQFT_PI_DOT) return fail(KQFT_EINVAL, "unknown propagator pair");
   if ((rc = check_vertex(left, "left vertex")) || (rc = check_vertex(right, "right vertex"))) return rc;
@@ -1290,6 +1521,7 @@ int kqft_sde_adjoint(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propaga
                      double* dscal, void* stream) {
   int rc;
   if ((rc = check_common(ctx, G, q_bubble, opts))) return rc;
+  if ((rc = check_adjoint_prop(*G))) return rc;
   if (!q_loop || q_loop->n < 1) return fail(KQFT_ESHAPE, "invalid loop quadrature");
   if ((rc = check_vertex(gamma, "gamma"))) return rc;
   if (!dsigma || !dgamma || !dscal) return fail(KQFT_EINVAL, "dsigma, dgamma and dscal must be given");

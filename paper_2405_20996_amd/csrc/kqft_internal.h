@@ -67,6 +67,10 @@ struct DProp {
   DGrid sg;
   const double2* SigR;
   const double2* SigK;
+  int reg;     // regulator: 0 Delta, 1 interaction (lam), 2 temperature, 3 frequency (lam)
+  double lam;
+  const double2* dSigR;  // Sigma_dot on sg (Katanin, G Sigma_dot G), or null
+  const double2* dSigK;
 };
 
 __device__ inline double2 sigma_at(const DGrid& g, const double2* arr, double v) {
@@ -78,34 +82,79 @@ __device__ inline double2 sigma_at(const DGrid& g, const double2* arr, double v)
   return make_double2((1.0 - t) * a.x + t * b.x, (1.0 - t) * a.y + t * b.y);
 }
 
-// Keldysh matrix m[2*a + a'] = X^{a|a'} of G (kind 0) or S = dG/dDelta|_Sigma (kind 1).
-__device__ inline void propagator(const DProp& P, int kind, double v, double2 m[4]) {
-  double th = tanh(v / (2.0 * P.T));
-  double2 sR = sigma_at(P.sg, P.SigR, v);
-  double2 sK = P.SigK ? sigma_at(P.sg, P.SigK, v) : make_double2(0.0, 2.0 * th * sR.y);
-  double dr = v - P.eps - sR.x, di = P.Delta - sR.y;
-  double inv = 1.0 / (dr * dr + di * di);
-  double2 GR = make_double2(dr * inv, -di * inv);
-  double2 GA = cconj(GR);
-  double2 br = make_double2(sK.x, sK.y - 2.0 * th * P.Delta);  // Sigma^K - 2 i Delta tanh
-  double2 GK = cmul(cmul(GR, br), GA);
-  if (kind == 0) {
-    m[0] = czero();
-    m[1] = GA;
-    m[2] = GR;
-    m[3] = GK;
-    return;
-  }
-  double2 SR = cmul(make_double2(0.0, -1.0), cmul(GR, GR));
-  double2 SA = cconj(SR);
-  double2 SK = cadd(cadd(cmul(cmul(SR, br), GA), cmul(cmul(GR, make_double2(0.0, -2.0 * th)), GA)),
-                    cmul(cmul(GR, br), SA));
-  m[0] = czero();
-  m[1] = SA;
-  m[2] = SR;
-  m[3] = SK;
+__device__ inline double2 cinv(double2 a) {
+  const double d = 1.0 / (a.x * a.x + a.y * a.y);
+  return make_double2(a.x * d, -a.y * d);
 }
 
+// Keldysh matrix m[2*a + a'] = X^{a|a'} of
+//   kind 0: G;  kind 1: S = dG/dLambda at fixed Sigma (+ G Sigma_dot G with Sigma_dot);
+//   kind 2: G Sigma_dot G.
+// With D = v - eps + i Delta and br = Sigma^K - G_0^{-1,K} (G^K = G^R br G^A), per regulator
+//   Delta:       G^R = 1/(D - Sigma),         S^R = -i (G^R)^2,             dbr = -2i tanh
+//   interaction: G^R = lam/(D - lam Sigma),   S^R = D/(D - lam Sigma)^2,    br, dbr with Delta/lam
+//   temperature: G^R = 1/(D - Sigma),         S^R = 0,                      dbr = -2i Delta dtanh/dT
+//   frequency:   G^R = Th/(D - Th Sigma),     S^R = -i D (Th^2/v)/(D - Th Sigma)^2,
+//                Th = v/(v + i lam), Im G_0^{-1,R} = Delta + lam (v - eps)/v
+// and S^K = S^R br G^A + G^R dbr G^A + G^R br S^A.
+__device__ inline void propagator(const DProp& P, int kind, double v, double2 m[4]) {
+  const double th = tanh(v / (2.0 * P.T));
+  const double2 sR = sigma_at(P.sg, P.SigR, v);
+  const double2 sK = P.SigK ? sigma_at(P.sg, P.SigK, v) : make_double2(0.0, 2.0 * th * sR.y);
+  const double2 D = make_double2(v - P.eps, P.Delta);
+  double2 GR, SR, br, dbr;
+  if (P.reg == 1) {
+    const double2 d = cinv(csub(D, cscale(P.lam, sR)));
+    GR = cscale(P.lam, d);
+    SR = cmul(D, cmul(d, d));
+    br = make_double2(sK.x, sK.y - 2.0 * th * P.Delta / P.lam);
+    dbr = make_double2(0.0, 2.0 * th * P.Delta / (P.lam * P.lam));
+  } else if (P.reg == 2) {
+    GR = cinv(csub(D, sR));
+    SR = czero();
+    const double dth = -(v / (2.0 * P.T * P.T)) * (1.0 - th * th);
+    br = make_double2(sK.x, sK.y - 2.0 * th * P.Delta);
+    dbr = make_double2(0.0, -2.0 * dth * P.Delta);
+  } else if (P.reg == 3) {
+    const double L = P.lam, dd = v * v + L * L, idd = 1.0 / dd;
+    const double2 theta = make_double2(v * v * idd, -v * L * idd);
+    const double2 t2v = make_double2(v * (v * v - L * L) * idd * idd, -2.0 * v * v * L * idd * idd);
+    const double th_v = v == 0.0 ? 0.5 / P.T : th / v;
+    const double2 d = cinv(csub(D, cmul(theta, sR)));
+    GR = cmul(theta, d);
+    const double2 q = cmul(cmul(D, t2v), cmul(d, d));
+    SR = make_double2(q.y, -q.x);  // -i q
+    br = make_double2(sK.x, sK.y - 2.0 * th * P.Delta - 2.0 * L * (v - P.eps) * th_v);
+    dbr = make_double2(0.0, -2.0 * (v - P.eps) * th_v);
+  } else {
+    GR = cinv(csub(D, sR));
+    const double2 g2 = cmul(GR, GR);
+    SR = make_double2(g2.y, -g2.x);  // -i (G^R)^2
+    br = make_double2(sK.x, sK.y - 2.0 * th * P.Delta);
+    dbr = make_double2(0.0, -2.0 * th);
+  }
+  const double2 GA = cconj(GR);
+  const double2 GK = cmul(cmul(GR, br), GA);
+  double2 R = czero(), K = czero();
+  if (kind == 0) {
+    R = GR;
+    K = GK;
+  } else if (kind == 1) {
+    R = SR;
+    K = cadd(cadd(cmul(cmul(SR, br), GA), cmul(cmul(GR, dbr), GA)), cmul(cmul(GR, br), cconj(SR)));
+  }
+  if (kind != 0 && P.dSigR) {
+    const double2 dR = sigma_at(P.sg, P.dSigR, v), dK = sigma_at(P.sg, P.dSigK, v);
+    R = cadd(R, cmul(cmul(GR, dR), GR));
+    K = cadd(K, cadd(cadd(cmul(cmul(GR, dR), GK), cmul(cmul(GR, dK), GA)), cmul(cmul(GK, cconj(dR)), GA)));
+  }
+  m[0] = czero();
+  m[1] = cconj(R);
+  m[2] = R;
+  m[3] = K;
+}
+
+// (Adjoint paths: the Delta regulator without Sigma_dot only.)
 // Value m and Delta-derivative dm (at fixed Sigma) of G (kind 0: dm = S) or of the
 // single-scale propagator S (kind 1: dm = dS/dDelta).  With br = Sigma^K - 2 i Delta tanh:
 //   dS^R = -2 (G^R)^3,  dS^K = dS^R br G^A + 2 S^R br S^A + G^R br dS^A

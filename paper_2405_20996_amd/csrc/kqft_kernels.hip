@@ -1063,6 +1063,42 @@ __global__ __launch_bounds__(256) void axpby_kernel(double2* out, double a, cons
   }
 }
 
+// out = x + sum_{j < nt} c_j k_j (x may be null; out may alias x or any k_j)
+__global__ __launch_bounds__(256) void lincomb_kernel(LinComb a) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.count; e += (size_t)gridDim.x * blockDim.x) {
+    double2 acc = a.x ? a.x[e] : czero();
+    for (int j = 0; j < a.nt; ++j) {
+      const double2 u = a.k[j][e];
+      acc = make_double2(fma(a.c[j], u.x, acc.x), fma(a.c[j], u.y, acc.y));
+    }
+    a.out[e] = acc;
+  }
+}
+
+// Step error of the embedded Runge-Kutta pair: per-block max of |e| / (atol + rtol max(|y|, |y4|)),
+// zero where e is zero; a NaN or infinite entry counts as +inf (fmax alone would drop NaN).
+__global__ __launch_bounds__(256) void errnorm_kernel(const double2* err, const double2* y, const double2* y4,
+                                                      double atol, double rtol, size_t count, double* partial) {
+  double m = 0.0;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x) {
+    const double2 d = err[e], u = y[e], w = y4[e];
+    const double ad = hypot(d.x, d.y);
+    double r = ad == 0.0 ? 0.0 : ad / (atol + rtol * fmax(hypot(u.x, u.y), hypot(w.x, w.y)));
+    if (!(r <= 1.7976931348623157e308)) r = __builtin_inf();
+    m = fmax(m, r);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) b = fmax(b, red[w]);
+    partial[blockIdx.x] = b;
+  }
+}
+
 // linear mixing x <- x + alpha (f - x)
 __global__ __launch_bounds__(256) void mix_kernel(double2* x, const double2* f, size_t count, double alpha) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x) {
@@ -1726,6 +1762,13 @@ void launch_maxdiff(const double2* x, const double2* f, size_t count, double* pa
 void launch_axpby(double2* out, double a, const double2* x, double b, const double2* y, size_t count,
                   hipStream_t s) {
   hipLaunchKernelGGL(axpby_kernel, dim3(2048), dim3(256), 0, s, out, a, x, b, y, count);
+}
+void launch_lincomb(const LinComb& a, hipStream_t s) {
+  hipLaunchKernelGGL(lincomb_kernel, dim3(2048), dim3(256), 0, s, a);
+}
+void launch_errnorm(const double2* err, const double2* y, const double2* y4, double atol, double rtol, size_t count,
+                    double* partial, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(errnorm_kernel, dim3(nblk), dim3(256), 0, s, err, y, y4, atol, rtol, count, partial);
 }
 void launch_mix(double2* x, const double2* f, size_t count, double alpha, hipStream_t s) {
   hipLaunchKernelGGL(mix_kernel, dim3(2048), dim3(256), 0, s, x, f, count, alpha);

@@ -187,6 +187,18 @@ int chi_blocks(int nq);
 void launch_sigma_split(int n, const double2* sigma, double2* sigR, double2* sigK, hipStream_t s);
 void launch_maxdiff(const double2* x, const double2* f, size_t count, double* partial, int nblk, hipStream_t s);
 void launch_mix(double2* x, const double2* f, size_t count, double alpha, hipStream_t s);
+// out = x + sum_{j < nt} c_j k_j over count complex entries (x may be null, nt <= 6)
+struct LinComb {
+  double2* out;
+  const double2* x;
+  const double2* k[6];
+  double c[6];
+  int nt;
+  size_t count;
+};
+void launch_lincomb(const LinComb& a, hipStream_t s);
+void launch_errnorm(const double2* err, const double2* y, const double2* y4, double atol, double rtol, size_t count,
+                    double* partial, int nblk, hipStream_t s);
 void launch_axpby(double2* out, double a, const double2* x, double b, const double2* y, size_t count,
                   hipStream_t s);
 

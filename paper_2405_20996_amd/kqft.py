@@ -18,6 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libkqft.so")
 CH_A, CH_P, CH_T = 0, 1, 2
 FP64, SPLIT_FP32 = 0, 1
 PI_GG, PI_DOT = 0, 1
+REG_DELTA, REG_U, REG_T, REG_NU = 0, 1, 2, 3
+LINE_G, LINE_S, LINE_GSG = 0, 1, 2
+ENOCONV = -5
 K1, K2, K2P, K3, KALL = 1, 2, 4, 8, 15
 QUAD_TAN_FINITE, QUAD_TAN_INFINITE = 0, 1
 CLASSES = ("K1", "K2", "K2p", "K3")
@@ -42,7 +45,19 @@ class KqftVertex(C.Structure):
 
 class KqftPropagator(C.Structure):
     _fields_ = [("Delta", C.c_double), ("T", C.c_double), ("eps", C.c_double), ("sgrid", KqftGrid),
-                ("SigR", C.c_void_p), ("SigK", C.c_void_p)]
+                ("SigR", C.c_void_p), ("SigK", C.c_void_p), ("reg", C.c_int), ("lam", C.c_double),
+                ("dSigR", C.c_void_p), ("dSigK", C.c_void_p)]
+
+
+class KqftFlowOpts(C.Structure):
+    _fields_ = [("reg", C.c_int), ("Delta", C.c_double), ("katanin", C.c_int), ("se_iterations", C.c_int),
+                ("se_tol_abs", C.c_double), ("se_tol_rel", C.c_double), ("adaptive", C.c_int),
+                ("ode_tol_abs", C.c_double), ("ode_tol_rel", C.c_double), ("max_steps", C.c_int)]
+
+
+class KqftFlowInfo(C.Structure):
+    _fields_ = [("accepted", C.c_int), ("rejected", C.c_int), ("rhs_evaluations", C.c_int),
+                ("se_iterations", C.c_int)]
 
 
 class KqftChout(C.Structure):
@@ -86,8 +101,8 @@ def lib():
         _lib.kqft_loop.argtypes = [C.c_void_p, P(KqftVertex), P(KqftPropagator), C.c_int, P(KqftQuad), C.c_void_p,
                                    C.c_void_p]
         _lib.kqft_mfrg_flow.argtypes = [C.c_void_p, P(KqftGrid), C.c_double, C.c_double, C.c_double, C.c_double,
-                                        C.c_int, C.c_int, P(KqftQuad), P(KqftQuad), P(KqftOpts), P(KqftChout),
-                                        C.c_void_p, C.c_void_p]
+                                        C.c_int, C.c_int, P(KqftQuad), P(KqftQuad), P(KqftOpts), P(KqftFlowOpts),
+                                        P(KqftChout), C.c_void_p, C.c_void_p, P(KqftFlowInfo), C.c_void_p]
         _lib.kqft_parquet_iteration.argtypes = [C.c_void_p, P(KqftVertex), P(KqftPropagator), P(KqftQuad),
                                                 P(KqftQuad), P(KqftOpts), P(KqftChout), C.c_void_p, C.c_void_p]
         _lib.kqft_parquet_solve.argtypes = [C.c_void_p, P(KqftGrid), C.c_double, C.c_double, C.c_double,
@@ -205,18 +220,44 @@ class Vertex:
 
 @dataclass
 class Propagator:
+    """G^R = 1/(G_0^{-1,R} - Sigma^R) with the regulator `reg` (lam for REG_U / REG_NU);
+    dSigR/dSigK: optional Sigma_dot (Katanin substitution, G Sigma_dot G line)."""
     Delta: float = 1.0
     T: float = 0.1
     eps: float = 0.0
     sigma_grid: Optional[Grid] = None
     SigR: Optional[torch.Tensor] = None
     SigK: Optional[torch.Tensor] = None
+    reg: int = REG_DELTA
+    lam: float = 1.0
+    dSigR: Optional[torch.Tensor] = None
+    dSigK: Optional[torch.Tensor] = None
 
     def c(self) -> KqftPropagator:
         g = (self.sigma_grid or Grid(2, 1.0, 1.0)).c()
         n = self.sigma_grid.n if self.sigma_grid else None
-        return KqftPropagator(self.Delta, self.T, self.eps, g, _ptr(self.SigR, (n,) if n else None, "SigR"),
-                              _ptr(self.SigK, (n,) if n else None, "SigK"))
+        sh = (n,) if n else None
+        return KqftPropagator(self.Delta, self.T, self.eps, g, _ptr(self.SigR, sh, "SigR"), _ptr(self.SigK, sh, "SigK"),
+                              self.reg, self.lam, _ptr(self.dSigR, sh, "dSigR"), _ptr(self.dSigK, sh, "dSigK"))
+
+
+@dataclass
+class FlowOptions:
+    """kqft_flow_opts: regulator, Katanin substitution, self-energy corrections, ODE method."""
+    reg: int = REG_DELTA
+    Delta: float = 1.0
+    katanin: bool = True
+    se_iterations: int = 0
+    se_atol: float = 1e-9
+    se_rtol: float = 1e-5
+    adaptive: bool = False
+    atol: float = 1e-8
+    rtol: float = 1e-5
+    max_steps: int = 200
+
+    def c(self) -> KqftFlowOpts:
+        return KqftFlowOpts(self.reg, self.Delta, int(self.katanin), self.se_iterations, self.se_atol, self.se_rtol,
+                            int(self.adaptive), self.atol, self.rtol, self.max_steps)
 
 
 def _opts(precision, class_mask, beta, omega_batch, overlap=0) -> KqftOpts:
@@ -282,8 +323,9 @@ def mloop_step(gammas: Sequence[Vertex], Gs: Sequence[Propagator], qs: Sequence[
     return outs
 
 
-def loop(gamma: Vertex, G: Propagator, q: Quad, kind: int = 0, stream=None) -> torch.Tensor:
-    """L(Gamma, G or S) [n][4] (no overall sign); Sigma_dot = -loop(Gamma, G, q, kind=1)."""
+def loop(gamma: Vertex, G: Propagator, q: Quad, kind: int = LINE_G, stream=None) -> torch.Tensor:
+    """L(Gamma, X) [n][4] (no overall sign), X = G, S (+ G Sigma_dot G) or G Sigma_dot G by kind;
+    the one-loop self-energy flow is -loop(Gamma, G, q, LINE_S)."""
     n = gamma.grid.n
     dev = torch.device("cuda", torch.cuda.current_device())
     out = torch.zeros((n, 4), dtype=torch.complex128, device=dev)
@@ -293,19 +335,27 @@ def loop(gamma: Vertex, G: Propagator, q: Quad, kind: int = 0, stream=None) -> t
     return out
 
 
-def mfrg_flow(grid: Grid, U: float, T: float, Delta_i: float, Delta_f: float, steps: int, nloops: int,
-              q_bubble: Quad, q_loop: Quad, gamma: Sequence[Channel], sigma: torch.Tensor, precision: int = FP64,
-              stream=None):
-    """Delta-flow of the state (gamma[3] Channels, sigma [n][4]) in place, RK4 in `steps` steps."""
+def mfrg_flow(grid: Grid, U: float, T: float, lam_i: float, lam_f: float, steps: int, nloops: int,
+              q_bubble: Quad, q_loop: Quad, gamma: Sequence[Channel], sigma: torch.Tensor,
+              flow: Optional[FlowOptions] = None, precision: int = FP64, stream=None):
+    """Flow of the state (gamma[3] Channels, sigma [n][4]) from lam_i to lam_f, in place.
+    Returns (gamma, sigma, info) with info the accepted flow parameters and step counts."""
     n = grid.n
+    fo = flow or FlowOptions()
     D = (KqftChout * 3)(*[_chout(c, n) for c in gamma])
     _ptr(sigma, (n, 4), "sigma")
     gc, qb, ql = grid.c(), q_bubble.c(), q_loop.c()
-    _check(lib().kqft_mfrg_flow(ctx(), C.byref(gc), C.c_double(U), C.c_double(T), C.c_double(Delta_i),
-                                C.c_double(Delta_f), steps, nloops, C.byref(qb), C.byref(ql),
-                                C.byref(_opts(precision, KALL, 0, 0)), D, C.c_void_p(sigma.data_ptr()),
-                                _stream(stream)))
-    return gamma, sigma
+    cap = (fo.max_steps if fo.adaptive else steps) + 1
+    lams = (C.c_double * cap)()
+    inf = KqftFlowInfo()
+    rc = lib().kqft_mfrg_flow(ctx(), C.byref(gc), C.c_double(U), C.c_double(T), C.c_double(lam_i),
+                              C.c_double(lam_f), steps, nloops, C.byref(qb), C.byref(ql),
+                              C.byref(_opts(precision, KALL, 0, 0)), C.byref(fo.c()), D, C.c_void_p(sigma.data_ptr()),
+                              lams, C.byref(inf), _stream(stream))
+    _check(rc)
+    info = {"lambdas": list(lams[:inf.accepted + 1]), "accepted": inf.accepted, "rejected": inf.rejected,
+            "rhs": inf.rhs_evaluations, "se_iterations": inf.se_iterations}
+    return gamma, sigma, info
 
 
 def parquet_iteration(gamma: Vertex, G: Propagator, q_bubble: Quad, q_loop: Quad, precision: int = FP64,
