@@ -461,36 +461,85 @@ def parquet_iteration(V: Vertex, P: Prop, q_bubble: Quad, q_loop: Quad):
     return out, sde(V, P, q_bubble, q_loop)
 
 
-def parquet_solve(grid: Grid, U: float, Delta: float, T: float, q_bubble: Quad, q_loop: Quad,
-                  alpha: float = 0.5, iterations: int = 10, tol: float = 0.0):
-    """Parquet solver with linear mixing (Sec. parquet solver): start from PT2 (vertex K1 in
-    every channel, Sigma^(2) from the SDE of Gamma_0), then x <- x + alpha (F(x) - x) for the
-    three channels and Sigma, until the relative max-norm change max over arrays of
-    ||F(x) - x|| / ||F(x)|| falls below tol or after `iterations` steps.
-    Returns (channels, Sigma, residuals per step)."""
-    P0 = Prop(Delta, T)
-    k1 = pt2_k1(grid, U, P0, q_bubble)
-    chans = [Channel(1.0, k1[r], np.zeros((2, grid.n, grid.n, 16), complex),
-                     np.zeros((2, grid.n, grid.n, 16), complex), np.zeros((2, grid.n, grid.n, grid.n, 16), complex))
-             for r in range(3)]
-    sigma = sde(bare(grid, U), P0, q_bubble, q_loop)
-    res = []
-    for _ in range(iterations):
-        V = Vertex(grid, U, chans)
-        new, snew = parquet_iteration(V, sigma_prop(grid, Delta, T, sigma), q_bubble, q_loop)
-        r_ = 0.0
-        for r in range(3):
-            for c in CLASSES:
-                x, f = getattr(chans[r], c), getattr(new[r], c)
-                r_ = max(r_, float(np.abs(f - x).max() / max(np.abs(f).max(), 1e-300)))
-        r_ = max(r_, float(np.abs(snew - sigma).max() / max(np.abs(snew).max(), 1e-300)))
-        res.append(r_)
-        chans = [Channel(1.0, *[getattr(chans[r], c) + alpha * (getattr(new[r], c) - getattr(chans[r], c))
-                                for c in CLASSES]) for r in range(3)]
-        sigma = sigma + alpha * (snew - sigma)
-        if r_ < tol:
+def fixed_point_solve(Fmap, x0: np.ndarray, residual, alpha: float = 0.5, depth: int = 0, iterations: int = 10,
+                      tol: float = 0.0, reduce_alpha: bool = False, alpha_min: float = 0.01):
+    """Fixed-point iteration x = F(x) on complex vectors (Sec. parquet solver: mixing and
+    Anderson acceleration).  Per iteration k: g_k = F(x_k), f_k = g_k - x_k, r_k =
+    residual(x_k, g_k).  With reduce_alpha, r_k > r_{k-1} halves alpha (not below alpha_min)
+    and clears the Anderson history.  Anderson (Walker and Ni 2011) of depth m over the real
+    inner product Re <a, b>: the columns dF_i = f_{i+1} - f_i, dG_i = g_{i+1} - g_i of the last
+    m iterations, gamma from the normal equations (dF^T dF + eps I) gamma = dF^T f_k with
+    eps = 1e-14 max_i (dF^T dF)_ii, and
+        x_{k+1} = x_k + alpha f_k - sum_i gamma_i (dG_i - (1 - alpha) dF_i);
+    depth 0 (or an empty history) is linear mixing x_{k+1} = x_k + alpha f_k.  Stops after
+    the update of the first iteration with r_k < tol.  Returns (x, residuals, final alpha)."""
+    x = x0
+    res, dF, dG = [], [], []
+    f_prev = g_prev = None
+    for k in range(iterations):
+        g = Fmap(x)
+        f = g - x
+        r = residual(x, g)
+        if reduce_alpha and res and r > res[-1]:
+            alpha = max(0.5 * alpha, alpha_min)
+            dF, dG = [], []
+        elif depth > 0 and f_prev is not None:
+            dF.append(f - f_prev)
+            dG.append(g - g_prev)
+            if len(dF) > depth:
+                dF.pop(0)
+                dG.pop(0)
+        res.append(r)
+        f_prev, g_prev = f, g
+        step = x + alpha * f
+        if dF:
+            m = len(dF)
+            A = np.array([[np.vdot(dF[i], dF[j]).real for j in range(m)] for i in range(m)])
+            b = np.array([np.vdot(dF[i], f).real for i in range(m)])
+            A = A + 1e-14 * A.diagonal().max() * np.eye(m)
+            gam = np.linalg.solve(A, b)
+            for i in range(m):
+                step = step - gam[i] * (dG[i] - (1.0 - alpha) * dF[i])
+        x = step
+        if r < tol:
             break
-    return chans, sigma, res
+    return x, res, alpha
+
+
+def _rel_residual(n: int):
+    """max over the arrays of max|F - x| / max|F| (three channels x four classes, Sigma)."""
+    def resid(x, g):
+        xc, xs = state_unpack(x, n)
+        gc, gs = state_unpack(g, n)
+        worst = 0.0
+        pairs = [(getattr(xc[r], c), getattr(gc[r], c)) for r in range(3) for c in CLASSES] + [(xs, gs)]
+        for a, f in pairs:
+            md, mf = float(np.abs(f - a).max()), float(np.abs(f).max())
+            worst = max(worst, md / mf if mf > 0 else (1.0 if md > 0 else 0.0))
+        return worst
+    return resid
+
+
+def parquet_solve(grid: Grid, U: float, Delta: float, T: float, q_bubble: Quad, q_loop: Quad,
+                  alpha: float = 0.5, iterations: int = 10, tol: float = 0.0, depth: int = 0,
+                  reduce_alpha: bool = False, alpha_min: float = 0.01):
+    """Parquet solver (Sec. parquet solver): start from PT2 (vertex K1 in every channel,
+    Sigma^(2) from the SDE of Gamma_0), then fixed_point_solve on the state (three channels,
+    Sigma) with F = parquet_iteration at the propagator dressed by the state's Sigma; the
+    residual is the relative max-norm change, max over the arrays of ||F(x) - x|| / ||F(x)||.
+    Returns (channels, Sigma, residuals per step)."""
+    chans, sigma = pt2_state(grid, U, Delta, T, q_bubble, q_loop)
+    n = grid.n
+
+    def Fmap(vec):
+        ch, sg = state_unpack(vec, n)
+        new, snew = parquet_iteration(Vertex(grid, U, ch), sigma_prop(grid, Delta, T, sg), q_bubble, q_loop)
+        return state_pack(new, snew)
+
+    x, res, _ = fixed_point_solve(Fmap, state_pack(chans, sigma), _rel_residual(n), alpha, depth, iterations, tol,
+                                  reduce_alpha, alpha_min)
+    ch, sg = state_unpack(x, n)
+    return ch, sg, res
 
 
 # ------------------------------------------------------------------ mfRG flow
