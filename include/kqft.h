@@ -292,21 +292,37 @@ int kqft_parquet_iteration(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_p
                            const kqft_quad* q_bubble, const kqft_quad* q_loop, const kqft_opts* opts,
                            const kqft_chout* gamma_out, double* sigma_out, void* stream);
 
+/* options of kqft_parquet_solve (Sec. "parquet solver": mixing, Anderson acceleration) */
+typedef struct {
+  double alpha;        /* mixing factor, 0 < alpha <= 1 */
+  int max_iterations;  /* >= 1 */
+  double tol;          /* stop after the update of the first iteration with residual < tol */
+  int anderson_depth;  /* m: 0 = linear mixing, else Anderson acceleration over the last m
+                          iterations (0 <= m <= 32) */
+  int reduce_alpha;    /* 1: an iteration whose residual exceeds the previous one halves alpha
+                          (not below alpha_min) and clears the Anderson history */
+  double alpha_min;    /* 0 < alpha_min <= alpha when reduce_alpha */
+} kqft_parquet_opts;
+
 /*
- * kqft_parquet_solve -- parquet solver with linear mixing (Sec. "parquet solver"): starts
- * from the PT2 state (gamma_r = K1_r = B_r(Gamma_0, Gamma_0), Sigma = SDE(Gamma_0) with the
- * bare propagator), then x <- x + alpha (F(x) - x) for the three channels and Sigma, where
- * F is kqft_parquet_iteration with the propagator dressed by the state's Sigma (Sigma^R and
- * Sigma^K on `grid`, Delta and T of the bath, eps = 0).  Stops when the relative change
- * max over arrays of max|F(x) - x| / max|F(x)| falls below tol or after max_iterations.
+ * kqft_parquet_solve -- parquet solver (Sec. "parquet solver"): starts from the PT2 state
+ * (gamma_r = K1_r = B_r(Gamma_0, Gamma_0), Sigma = SDE(Gamma_0) with the bare propagator),
+ * then iterates the fixed point x = F(x) of the state x = (three channels, Sigma), F being
+ * kqft_parquet_iteration with the propagator dressed by the state's Sigma (Sigma^R and
+ * Sigma^K on `grid`, Delta and T of the bath, eps = 0).  Per iteration k: g = F(x_k),
+ * f = g - x_k, residual r_k = max over arrays of max|f| / max|g|; then
+ *   x_{k+1} = x_k + alpha f - sum_i gamma_i (dG_i - (1 - alpha) dF_i)
+ * with the Anderson columns dF_i, dG_i (differences of f and g between consecutive
+ * iterations, the last m of them) and gamma solving the normal equations
+ * (dF^T dF + eps I) gamma = dF^T f over the real inner product Re <a, b> of the state
+ * vectors, eps = 1e-14 max_i (dF^T dF)_ii (Walker and Ni 2011); no columns: linear mixing.
  * gamma[3] (device, out): the channels of the final state; sigma (device [n][4], out);
- * residuals (host [max_iterations] or NULL): the relative change of every iteration;
- * iterations (host, out): iterations done.  Synchronises `stream` once per iteration.
- * 0 < alpha <= 1 and max_iterations >= 1, else KQFT_EINVAL.
+ * residuals (host [max_iterations] or NULL); iterations (host, out).  Synchronises `stream`
+ * once per iteration.  Working memory: (3 + 2m) states besides F(x).
  */
 int kqft_parquet_solve(kqft_ctx* ctx, const kqft_grid* grid, double U, double Delta, double T,
-                       const kqft_quad* q_bubble, const kqft_quad* q_loop, const kqft_opts* opts, double alpha,
-                       int max_iterations, double tol, const kqft_chout* gamma, double* sigma, double* residuals,
+                       const kqft_quad* q_bubble, const kqft_quad* q_loop, const kqft_opts* opts,
+                       const kqft_parquet_opts* popts, const kqft_chout* gamma, double* sigma, double* residuals,
                        int* iterations, void* stream);
 
 /*

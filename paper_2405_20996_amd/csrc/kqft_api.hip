@@ -43,7 +43,7 @@ struct kqft_ctx {
   // consecutive transfer-frequency batches overlap, ordered by events
   hipStream_t sg = nullptr, sm = nullptr;
   rocblas_handle blas = nullptr;
-  DevBuf adjw, dkf[2][3], phigrad, pq, pqsig, pqred, vtab[3], flow, flowml, ctmp, flowred;
+  DevBuf adjw, dkf[2][3], phigrad, pq, pqsig, pqred, vtab[3], flow, flowml, ctmp, flowred, pqx;
   std::vector<hipEvent_t> events;
   size_t next_event = 0;
   bool prof = false;
@@ -759,6 +759,72 @@ static int rel_change(kqft_ctx* ctx, const std::vector<std::pair<const double2*,
   return KQFT_OK;
 }
 
+// out = x + sum_{j < nt} c_j k_j (x may be null), in launches of at most six terms; out must
+// not alias any k_j
+static void lincomb_n(double2* out, const double2* x, int nt, const double2* const* k, const double* c, size_t count,
+                     hipStream_t s) {
+  int j0 = 0;
+  do {
+    LinComb a;
+    memset(&a, 0, sizeof a);
+    a.out = out;
+    a.x = j0 == 0 ? x : out;
+    a.nt = std::min(6, nt - j0);
+    a.count = count;
+    for (int j = 0; j < a.nt; ++j) {
+      a.k[j] = k[j0 + j];
+      a.c[j] = c[j0 + j];
+    }
+    launch_lincomb(a, s);
+    j0 += 6;
+  } while (j0 < nt);
+}
+
+// Re <a_i, b_i> for several pairs over count entries: per-block partials on the device, summed
+// on the host in block order after one stream synchronisation.
+static int dots(kqft_ctx* ctx, const std::vector<std::pair<const double2*, const double2*>>& ab, size_t count,
+                hipStream_t s, std::vector<double>& out) {
+  const int nblk = 256;
+  int rc;
+  if ((rc = ensure(ctx->pqred, std::max<size_t>(ab.size(), 1) * nblk * sizeof(double)))) return rc;
+  double* part = (double*)ctx->pqred.p;
+  for (size_t i = 0; i < ab.size(); ++i) launch_dot(ab[i].first, ab[i].second, count, part + i * nblk, nblk, s);
+  std::vector<double> h(ab.size() * nblk);
+  HIP_TRY(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  out.assign(ab.size(), 0.0);
+  for (size_t i = 0; i < ab.size(); ++i)
+    for (int b = 0; b < nblk; ++b) out[i] += h[i * nblk + b];
+  return KQFT_OK;
+}
+
+// Solve A x = b (m x m, row-major) by Gaussian elimination with partial pivoting; false if
+// a pivot vanishes.
+static bool solve_small(std::vector<double> A, std::vector<double> b, int m, std::vector<double>& x) {
+  for (int col = 0; col < m; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < m; ++r)
+      if (fabs(A[(size_t)r * m + col]) > fabs(A[(size_t)piv * m + col])) piv = r;
+    if (A[(size_t)piv * m + col] == 0.0) return false;
+    if (piv != col) {
+      for (int c = 0; c < m; ++c) std::swap(A[(size_t)piv * m + c], A[(size_t)col * m + c]);
+      std::swap(b[piv], b[col]);
+    }
+    for (int r = col + 1; r < m; ++r) {
+      const double f = A[(size_t)r * m + col] / A[(size_t)col * m + col];
+      for (int c = col; c < m; ++c) A[(size_t)r * m + c] -= f * A[(size_t)col * m + c];
+      b[r] -= f * b[col];
+    }
+  }
+  x.assign(m, 0.0);
+  for (int r = m - 1; r >= 0; --r) {
+    double t = b[r];
+    for (int c = r + 1; c < m; ++c) t -= A[(size_t)r * m + c] * x[c];
+    x[r] = t / A[(size_t)r * m + r];
+  }
+  return true;
+}
+
 // Loop of a full vertex (tables of all three channels in the a-channel order with the spin
 // combination 2X + Y), arguments checked by the caller.
 static int vloop_core(kqft_ctx* ctx, const kqft_vertex& V, const kqft_propagator& G, int kind, const kqft_quad& q,
@@ -854,7 +920,7 @@ int kqft_ctx_destroy(kqft_ctx* ctx) {
       if (b.p) (void)hipFree(b.p);
   if (ctx->adjw.p) (void)hipFree(ctx->adjw.p);
   for (DevBuf* b : {&ctx->pq, &ctx->pqsig, &ctx->pqred, &ctx->vtab[0], &ctx->vtab[1], &ctx->vtab[2], &ctx->flow,
-                    &ctx->flowml, &ctx->ctmp, &ctx->flowred})
+                    &ctx->flowml, &ctx->ctmp, &ctx->flowred, &ctx->pqx})
     if (b->p) (void)hipFree(b->p);
   if (ctx->phigrad.p) (void)hipFree(ctx->phigrad.p);
   if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
@@ -1276,8 +1342,8 @@ int kqft_parquet_iteration(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_p
 }
 
 int kqft_parquet_solve(kqft_ctx* ctx, const kqft_grid* grid, double U, double Delta, double T,
-                       const kqft_quad* q_bubble, const kqft_quad* q_loop, const kqft_opts* opts, double alpha,
-                       int max_iterations, double tol, const kqft_chout* gamma, double* sigma, double* residuals,
+                       const kqft_quad* q_bubble, const kqft_quad* q_loop, const kqft_opts* opts,
+                       const kqft_parquet_opts* popts, const kqft_chout* gamma, double* sigma, double* residuals,
                        int* iterations, void* stream) {
   int rc;
   if (!grid || (rc = check_grid(*grid, "grid"))) return grid ? rc : fail(KQFT_EINVAL, "grid is NULL");
@@ -1289,64 +1355,70 @@ int kqft_parquet_solve(kqft_ctx* ctx, const kqft_grid* grid, double U, double De
   if ((rc = check_common(ctx, &G0, q_bubble, opts))) return rc;
   if (!q_loop || q_loop->n < 1) return fail(KQFT_ESHAPE, "invalid loop quadrature");
   if (!(Delta > 0) || !(T > 0)) return fail(KQFT_EINVAL, "Delta and T must be positive");
-  if (!(alpha > 0) || alpha > 1 || max_iterations < 1) return fail(KQFT_EINVAL, "need 0 < alpha <= 1, max_iterations >= 1");
+  if (!popts) return fail(KQFT_EINVAL, "solver options must be given");
+  const kqft_parquet_opts po = *popts;
+  if (!(po.alpha > 0) || po.alpha > 1 || po.max_iterations < 1)
+    return fail(KQFT_EINVAL, "need 0 < alpha <= 1, max_iterations >= 1");
+  if (po.anderson_depth < 0 || po.anderson_depth > 32) return fail(KQFT_EINVAL, "need 0 <= anderson_depth <= 32");
+  if (po.reduce_alpha && (!(po.alpha_min > 0) || po.alpha_min > po.alpha))
+    return fail(KQFT_EINVAL, "need 0 < alpha_min <= alpha");
   if (!gamma || !sigma || !iterations) return fail(KQFT_EINVAL, "gamma, sigma and iterations must be given");
   for (int r = 0; r < 3; ++r)
     if (!gamma[r].K1 || !gamma[r].K2 || !gamma[r].K2p || !gamma[r].K3)
       return fail(KQFT_EINVAL, "gamma arrays must all be given");
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
-  const int n = grid->n;
+  const int n = grid->n, m = po.anderson_depth;
   const size_t c1 = (size_t)2 * n * 16, c2 = (size_t)2 * n * n * 16, c3 = (size_t)2 * n * n * n * 16;
   const size_t cnt[4] = {c1, c2, c2, c3};
-  const size_t chb = (c1 + 2 * c2 + c3) * sizeof(double2);
-  // F(x): three channels, then Sigma [n][4]; Sigma^R, Sigma^K of the state
-  if ((rc = ensure(ctx->pq, 3 * chb + (size_t)n * 4 * sizeof(double2)))) return rc;
+  const size_t chc = c1 + 2 * c2 + c3;
+  const size_t stc = 3 * chc + (size_t)4 * n;  // state: channels a, p, t (K1, K2, K2', K3), Sigma
+  // g = F(x) in pq; x, f, the previous f and g, and 2m Anderson columns in pqx
+  if ((rc = ensure(ctx->pq, stc * sizeof(double2)))) return rc;
+  if ((rc = ensure(ctx->pqx, (size_t)(4 + 2 * m) * stc * sizeof(double2)))) return rc;
   if ((rc = ensure(ctx->pqsig, (size_t)2 * n * sizeof(double2)))) return rc;
-  char* fb = (char*)ctx->pq.p;
-  BubbleOut F[3];
-  double2* Fx[3][4];
-  for (int r = 0; r < 3; ++r) {
-    double2* base = (double2*)(fb + r * chb);
-    Fx[r][0] = base;
-    Fx[r][1] = base + c1;
-    Fx[r][2] = base + c1 + c2;
-    Fx[r][3] = base + c1 + 2 * c2;
-    F[r] = BubbleOut{Fx[r][0], Fx[r][1], Fx[r][2], Fx[r][3]};
+  double2* g = (double2*)ctx->pq.p;
+  double2* xb = (double2*)ctx->pqx.p;
+  double2 *fr = xb + stc, *fprev = xb + 2 * stc, *gprev = xb + 3 * stc;
+  std::vector<double2*> dF(m), dG(m);
+  for (int i = 0; i < m; ++i) {
+    dF[i] = xb + (size_t)(4 + i) * stc;
+    dG[i] = xb + (size_t)(4 + m + i) * stc;
   }
-  double* Fsig = (double*)(fb + 3 * chb);
+  auto cls = [&](double2* base, int r, int c) {
+    size_t off = (size_t)r * chc;
+    for (int u = 0; u < c; ++u) off += cnt[u];
+    return base + off;
+  };
+  auto chan_out = [&](double2* base, int r) {
+    return BubbleOut{cls(base, r, 0), cls(base, r, 1), cls(base, r, 2), cls(base, r, 3)};
+  };
+  double2* xsig = xb + 3 * chc;
   double2* sigR = (double2*)ctx->pqsig.p;
   double2* sigK = sigR + n;
-  double2* X[3][4];
-  for (int r = 0; r < 3; ++r) {
-    X[r][0] = (double2*)gamma[r].K1;
-    X[r][1] = (double2*)gamma[r].K2;
-    X[r][2] = (double2*)gamma[r].K2p;
-    X[r][3] = (double2*)gamma[r].K3;
-  }
   // PT2 start: K1_r = B_r(Gamma_0, Gamma_0), Sigma^(2) = SDE(Gamma_0) with the bare propagator
   kqft_vertex bare;
   memset(&bare, 0, sizeof bare);
   bare.r0 = U;
   bare.grid = *grid;
   for (int r = 0; r < 3; ++r)
-    for (int c = 1; c < 4; ++c) HIP_TRY(hipMemsetAsync(X[r][c], 0, cnt[c] * sizeof(double2), s));
+    for (int c = 1; c < 4; ++c) HIP_TRY(hipMemsetAsync(cls(xb, r, c), 0, cnt[c] * sizeof(double2), s));
   kqft_opts o = *opts;
   o.beta = 0;
   o.class_mask = KQFT_K1;
   for (int r = 0; r < 3; ++r) {
-    BubbleOut k1{X[r][0], nullptr, nullptr, nullptr};
+    BubbleOut k1{cls(xb, r, 0), nullptr, nullptr, nullptr};
     if ((rc = bubble_core(ctx, r, bare, bare, G0, KQFT_PI_GG, *q_bubble, o, k1, s))) return rc;
   }
   G0.sgrid = kqft_grid{2, 1.0, 1.0};
-  if ((rc = sde_core(ctx, &bare, &G0, q_bubble, q_loop, opts, sigma, nullptr, s))) return rc;
+  if ((rc = sde_core(ctx, &bare, &G0, q_bubble, q_loop, opts, (double*)xsig, nullptr, s))) return rc;
   kqft_vertex V;
   memset(&V, 0, sizeof V);
   V.r0 = U;
   V.grid = *grid;
   for (int r = 0; r < 3; ++r)
-    V.ch[r] = kqft_chvert{1.0, (const double*)X[r][0], (const double*)X[r][1], (const double*)X[r][2],
-                          (const double*)X[r][3]};
+    V.ch[r] = kqft_chvert{1.0, (const double*)cls(xb, r, 0), (const double*)cls(xb, r, 1),
+                          (const double*)cls(xb, r, 2), (const double*)cls(xb, r, 3)};
   kqft_propagator Gs;
   memset(&Gs, 0, sizeof Gs);
   Gs.Delta = Delta;
@@ -1354,26 +1426,90 @@ int kqft_parquet_solve(kqft_ctx* ctx, const kqft_grid* grid, double U, double De
   Gs.sgrid = *grid;
   Gs.SigR = (const double*)sigR;
   Gs.SigK = (const double*)sigK;
+  BubbleOut F[3] = {chan_out(g, 0), chan_out(g, 1), chan_out(g, 2)};
   std::vector<std::pair<const double2*, const double2*>> xf;
   std::vector<size_t> counts;
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 4; ++c) {
-      xf.push_back({X[r][c], Fx[r][c]});
+      xf.push_back({cls(xb, r, c), cls(g, r, c)});
       counts.push_back(cnt[c]);
     }
-  xf.push_back({(const double2*)sigma, (const double2*)Fsig});
+  xf.push_back({xsig, g + 3 * chc});
   counts.push_back((size_t)n * 4);
-  int it = 0;
-  for (; it < max_iterations;) {
-    launch_sigma_split(n, (const double2*)sigma, sigR, sigK, s);
-    if ((rc = parquet_core(ctx, V, Gs, *q_bubble, *q_loop, *opts, F, Fsig, s))) return rc;
+  double alpha = po.alpha, prev_res = 0.0;
+  int ncol = 0, head = 0, it = 0;
+  bool have_prev = false;
+  for (; it < po.max_iterations;) {
+    launch_sigma_split(n, xsig, sigR, sigK, s);
+    if ((rc = parquet_core(ctx, V, Gs, *q_bubble, *q_loop, *opts, F, (double*)(g + 3 * chc), s))) return rc;
     double res = 0.0;
     if ((rc = rel_change(ctx, xf, counts, s, &res))) return rc;
-    for (size_t a = 0; a < xf.size(); ++a) launch_mix((double2*)xf[a].first, xf[a].second, counts[a], alpha, s);
+    {  // f = g - x
+      const double2* k[2] = {g, xb};
+      const double c[2] = {1.0, -1.0};
+      lincomb_n(fr, nullptr, 2, k, c, stc, s);
+    }
+    if (po.reduce_alpha && it > 0 && res > prev_res) {
+      alpha = std::max(0.5 * alpha, po.alpha_min);
+      ncol = 0;
+    } else if (m > 0 && have_prev) {  // newest columns dF = f - f_prev, dG = g - g_prev
+      const int slot = head % m;
+      const double2* k[2] = {fr, fprev};
+      const double c[2] = {1.0, -1.0};
+      lincomb_n(dF[slot], nullptr, 2, k, c, stc, s);
+      const double2* kg[2] = {g, gprev};
+      lincomb_n(dG[slot], nullptr, 2, kg, c, stc, s);
+      ++head;
+      ncol = std::min(ncol + 1, m);
+    }
+    if (m > 0) {
+      HIP_TRY(hipMemcpyAsync(fprev, fr, stc * sizeof(double2), hipMemcpyDeviceToDevice, s));
+      HIP_TRY(hipMemcpyAsync(gprev, g, stc * sizeof(double2), hipMemcpyDeviceToDevice, s));
+      have_prev = true;
+    }
+    // x <- x + alpha f - sum_i gamma_i (dG_i - (1 - alpha) dF_i)
+    std::vector<const double2*> ks{fr};
+    std::vector<double> cs{alpha};
+    if (ncol > 0) {
+      std::vector<int> cols;
+      for (int i = 0; i < ncol; ++i) cols.push_back((head - ncol + i) % m);  // oldest first
+      std::vector<std::pair<const double2*, const double2*>> ab;
+      for (int i = 0; i < ncol; ++i)
+        for (int j = 0; j <= i; ++j) ab.push_back({dF[cols[i]], dF[cols[j]]});
+      for (int i = 0; i < ncol; ++i) ab.push_back({dF[cols[i]], fr});
+      std::vector<double> d;
+      if ((rc = dots(ctx, ab, stc, s, d))) return rc;
+      std::vector<double> A((size_t)ncol * ncol), b(ncol), gam;
+      size_t q = 0;
+      for (int i = 0; i < ncol; ++i)
+        for (int j = 0; j <= i; ++j, ++q) A[(size_t)i * ncol + j] = A[(size_t)j * ncol + i] = d[q];
+      double dmax = 0.0;
+      for (int i = 0; i < ncol; ++i) {
+        b[i] = d[q + i];
+        dmax = std::max(dmax, A[(size_t)i * ncol + i]);
+      }
+      for (int i = 0; i < ncol; ++i) A[(size_t)i * ncol + i] += 1e-14 * dmax;
+      if (!solve_small(A, b, ncol, gam)) return fail(KQFT_ENOCONV, "singular Anderson system");
+      for (int i = 0; i < ncol; ++i) {
+        ks.push_back(dG[cols[i]]);
+        cs.push_back(-gam[i]);
+        ks.push_back(dF[cols[i]]);
+        cs.push_back(gam[i] * (1.0 - alpha));
+      }
+    }
+    lincomb_n(xb, xb, (int)ks.size(), ks.data(), cs.data(), stc, s);
     if (residuals) residuals[it] = res;
+    prev_res = res;
     ++it;
-    if (res < tol) break;
+    if (res < po.tol) break;
   }
+  // the state back into the caller's arrays
+  for (int r = 0; r < 3; ++r) {
+    double* dst[4] = {gamma[r].K1, gamma[r].K2, gamma[r].K2p, gamma[r].K3};
+    for (int c = 0; c < 4; ++c)
+      HIP_TRY(hipMemcpyAsync(dst[c], cls(xb, r, c), cnt[c] * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  }
+  HIP_TRY(hipMemcpyAsync(sigma, xsig, (size_t)4 * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
   *iterations = it;
   HIP_TRY(hipGetLastError());
   return KQFT_OK;

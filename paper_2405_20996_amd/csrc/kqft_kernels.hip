@@ -1099,6 +1099,25 @@ __global__ __launch_bounds__(256) void errnorm_kernel(const double2* err, const 
   }
 }
 
+// Per-block partial sums of Re <a, b> = sum_e (a.x b.x + a.y b.y); fixed grid and order.
+__global__ __launch_bounds__(256) void dot_kernel(const double2* a, const double2* b, size_t count, double* partial) {
+  double acc = 0.0;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x) {
+    const double2 u = a[e], v = b[e];
+    acc = fma(u.x, v.x, fma(u.y, v.y, acc));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    partial[blockIdx.x] = t;
+  }
+}
+
 // linear mixing x <- x + alpha (f - x)
 __global__ __launch_bounds__(256) void mix_kernel(double2* x, const double2* f, size_t count, double alpha) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x) {
@@ -1762,6 +1781,9 @@ void launch_maxdiff(const double2* x, const double2* f, size_t count, double* pa
 void launch_axpby(double2* out, double a, const double2* x, double b, const double2* y, size_t count,
                   hipStream_t s) {
   hipLaunchKernelGGL(axpby_kernel, dim3(2048), dim3(256), 0, s, out, a, x, b, y, count);
+}
+void launch_dot(const double2* a, const double2* b, size_t count, double* partial, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(dot_kernel, dim3(nblk), dim3(256), 0, s, a, b, count, partial);
 }
 void launch_lincomb(const LinComb& a, hipStream_t s) {
   hipLaunchKernelGGL(lincomb_kernel, dim3(2048), dim3(256), 0, s, a);

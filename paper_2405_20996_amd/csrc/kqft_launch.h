@@ -197,6 +197,8 @@ struct LinComb {
   size_t count;
 };
 void launch_lincomb(const LinComb& a, hipStream_t s);
+// per-block partial sums of Re <a, b> over count complex entries (nblk blocks)
+void launch_dot(const double2* a, const double2* b, size_t count, double* partial, int nblk, hipStream_t s);
 void launch_errnorm(const double2* err, const double2* y, const double2* y4, double atol, double rtol, size_t count,
                     double* partial, int nblk, hipStream_t s);
 void launch_axpby(double2* out, double a, const double2* x, double b, const double2* y, size_t count,

@@ -55,6 +55,11 @@ class KqftFlowOpts(C.Structure):
                 ("ode_tol_abs", C.c_double), ("ode_tol_rel", C.c_double), ("max_steps", C.c_int)]
 
 
+class KqftParquetOpts(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("max_iterations", C.c_int), ("tol", C.c_double),
+                ("anderson_depth", C.c_int), ("reduce_alpha", C.c_int), ("alpha_min", C.c_double)]
+
+
 class KqftFlowInfo(C.Structure):
     _fields_ = [("accepted", C.c_int), ("rejected", C.c_int), ("rhs_evaluations", C.c_int),
                 ("se_iterations", C.c_int)]
@@ -106,7 +111,7 @@ def lib():
         _lib.kqft_parquet_iteration.argtypes = [C.c_void_p, P(KqftVertex), P(KqftPropagator), P(KqftQuad),
                                                 P(KqftQuad), P(KqftOpts), P(KqftChout), C.c_void_p, C.c_void_p]
         _lib.kqft_parquet_solve.argtypes = [C.c_void_p, P(KqftGrid), C.c_double, C.c_double, C.c_double,
-                                            P(KqftQuad), P(KqftQuad), P(KqftOpts), C.c_double, C.c_int, C.c_double,
+                                            P(KqftQuad), P(KqftQuad), P(KqftOpts), P(KqftParquetOpts),
                                             P(KqftChout), C.c_void_p, P(C.c_double), P(C.c_int), C.c_void_p]
     return _lib
 
@@ -374,8 +379,10 @@ def parquet_iteration(gamma: Vertex, G: Propagator, q_bubble: Quad, q_loop: Quad
 
 
 def parquet_solve(grid: Grid, U: float, Delta: float, T: float, q_bubble: Quad, q_loop: Quad, alpha: float = 0.5,
-                  max_iterations: int = 20, tol: float = 0.0, precision: int = FP64, stream=None):
-    """Parquet solver from the PT2 state with linear mixing; returns (channels, Sigma, residuals)."""
+                  max_iterations: int = 20, tol: float = 0.0, precision: int = FP64, depth: int = 0,
+                  reduce_alpha: bool = False, alpha_min: float = 0.01, stream=None):
+    """Parquet solver from the PT2 state with linear mixing or Anderson acceleration of the
+    given depth; returns (channels, Sigma, residuals)."""
     n = grid.n
     outs = [alloc_channel(n) for _ in range(3)]
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -384,10 +391,10 @@ def parquet_solve(grid: Grid, U: float, Delta: float, T: float, q_bubble: Quad, 
     its = C.c_int(0)
     D = (KqftChout * 3)(*[_chout(o, n) for o in outs])
     gc, qb, ql = grid.c(), q_bubble.c(), q_loop.c()
+    po = KqftParquetOpts(alpha, max_iterations, tol, depth, int(reduce_alpha), alpha_min)
     _check(lib().kqft_parquet_solve(ctx(), C.byref(gc), C.c_double(U), C.c_double(Delta), C.c_double(T),
-                                    C.byref(qb), C.byref(ql), C.byref(_opts(precision, KALL, 0, 0)),
-                                    C.c_double(alpha), max_iterations, C.c_double(tol), D,
-                                    C.c_void_p(sigma.data_ptr()), res, C.byref(its), _stream(stream)))
+                                    C.byref(qb), C.byref(ql), C.byref(_opts(precision, KALL, 0, 0)), C.byref(po),
+                                    D, C.c_void_p(sigma.data_ptr()), res, C.byref(its), _stream(stream)))
     return outs, sigma, [res[i] for i in range(its.value)]
 
 
