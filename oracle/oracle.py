@@ -117,10 +117,17 @@ class Quad:
         return OQuad(self.n, self.map, self.L, self.a)
 
     def nodes_weights(self):
-        v = np.zeros(self.n)
-        w = np.zeros(self.n)
-        lib().oracle_quad(C.byref(self.c()), v.ctypes.data, w.ctypes.data)
-        return v, w
+        key = (self.n, self.map, self.L, self.a)
+        if key not in _QUAD_CACHE:
+            v = np.zeros(self.n)
+            w = np.zeros(self.n)
+            lib().oracle_quad(C.byref(self.c()), v.ctypes.data, w.ctypes.data)
+            _QUAD_CACHE[key] = (v, w)
+        v, w = _QUAD_CACHE[key]
+        return v.copy(), w.copy()
+
+
+_QUAD_CACHE = {}
 
 
 REG_DELTA, REG_U, REG_T, REG_NU = 0, 1, 2, 3
@@ -430,6 +437,43 @@ def dual_parts(d: np.ndarray):
 def dual_vertex(V: Vertex, dr0: float = 0.0) -> Vertex:
     chans = [Channel(c.coef, *[to_dual(getattr(c, k)) for k in ("K1", "K2", "K2p", "K3")]) for c in V.ch]
     return Vertex(V.grid, V.r0, chans, dr0=dr0)
+
+
+# ------------------------------------------------------------------ Hartree term
+def occupation(E: float, Delta: float, T: float, q: Quad, grid: Optional[Grid] = None,
+               sigma: Optional[np.ndarray] = None) -> float:
+    """<n_sigma> = -(1/pi) int dv n_F(v) Im G^R(v) with G^R = 1/(v - E + i Delta - Sigma^R_dyn(v))
+    (the integrand of Eq. Hartree with G^< = -2i n_F Im G^R), n_F(v) = (1 - tanh(v/2T))/2, by the
+    quadrature q (the full-line map for the Lorentzian tails)."""
+    v, w = q.nodes_weights()
+    P = sigma_prop(grid, Delta, T, sigma) if sigma is not None else Prop(Delta, T)
+    P.eps = E
+    GR = propagator(P, v)[:, 1, 0]
+    nF = 0.5 * (1.0 - np.tanh(v / (2.0 * T)))
+    return float(-np.sum(w * nF * GR.imag) / np.pi)
+
+
+def hartree(U: float, eps_d: float, Delta: float, T: float, q: Quad, grid: Optional[Grid] = None,
+            sigma: Optional[np.ndarray] = None, self_consistent: bool = True, tol: float = 1e-12,
+            sigma_H: float = 0.0, max_iterations: int = 200):
+    """Hartree term Sigma_H = U <n_sigma> of the level eps_d (Sec. Hartree-Fock, Eq. Hartree) with
+    the dynamic self-energy sigma ([n, 4] on grid, or none).  One-shot: U n(eps_d + sigma_H).
+    Self-consistent: bisection of f(x) = x - U n(eps_d + x) on [0, U] (f(0) <= 0 <= f(U) for
+    U >= 0, f increasing) until the bracket is narrower than tol.  Returns (Sigma_H, steps)."""
+    if U < 0:
+        raise ValueError("the bracketing assumes U >= 0")
+    if not self_consistent:
+        return U * occupation(eps_d + sigma_H, Delta, T, q, grid, sigma), 1
+    lo, hi = 0.0, U
+    it = 0
+    while hi - lo > tol and it < max_iterations:
+        mid = 0.5 * (lo + hi)
+        if mid - U * occupation(eps_d + mid, Delta, T, q, grid, sigma) > 0.0:
+            hi = mid
+        else:
+            lo = mid
+        it += 1
+    return 0.5 * (lo + hi), it
 
 
 # ------------------------------------------------------------------ parquet iteration
