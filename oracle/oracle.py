@@ -442,15 +442,16 @@ def dual_vertex(V: Vertex, dr0: float = 0.0) -> Vertex:
 # ------------------------------------------------------------------ Hartree term
 def occupation(E: float, Delta: float, T: float, q: Quad, grid: Optional[Grid] = None,
                sigma: Optional[np.ndarray] = None) -> float:
-    """<n_sigma> = -(1/pi) int dv n_F(v) Im G^R(v) with G^R = 1/(v - E + i Delta - Sigma^R_dyn(v))
-    (the integrand of Eq. Hartree with G^< = -2i n_F Im G^R), n_F(v) = (1 - tanh(v/2T))/2, by the
-    quadrature q (the full-line map for the Lorentzian tails)."""
+    """<n_sigma> of G^R = 1/(v - E + i Delta - Sigma^R_dyn(v)) (Eq. Hartree with G^< = -2i n_F Im G^R
+    in equilibrium, Sec. Hartree-Fock), written with n_F = (1 - tanh(v/2T))/2 and the spectral sum
+    rule int A = 1 for the constant half: <n> = 1/2 + (1/2 pi) int dv tanh(v/2T) Im G^R(v).  The two
+    forms agree for every causal G; this one keeps <n> = 1/2 exact at particle-hole symmetry when
+    Sigma is only known on a grid.  Quadrature q: the full-line map (Lorentzian tails)."""
     v, w = q.nodes_weights()
     P = sigma_prop(grid, Delta, T, sigma) if sigma is not None else Prop(Delta, T)
     P.eps = E
     GR = propagator(P, v)[:, 1, 0]
-    nF = 0.5 * (1.0 - np.tanh(v / (2.0 * T)))
-    return float(-np.sum(w * nF * GR.imag) / np.pi)
+    return float(0.5 + np.sum(w * np.tanh(v / (2.0 * T)) * GR.imag) / (2.0 * np.pi))
 
 
 def hartree(U: float, eps_d: float, Delta: float, T: float, q: Quad, grid: Optional[Grid] = None,
@@ -566,31 +567,60 @@ def _rel_residual(n: int):
 
 def parquet_solve(grid: Grid, U: float, Delta: float, T: float, q_bubble: Quad, q_loop: Quad,
                   alpha: float = 0.5, iterations: int = 10, tol: float = 0.0, depth: int = 0,
-                  reduce_alpha: bool = False, alpha_min: float = 0.01):
+                  reduce_alpha: bool = False, alpha_min: float = 0.01, eps_d: Optional[float] = None,
+                  q_hartree: Optional[Quad] = None, hartree_tol: float = 1e-12):
     """Parquet solver (Sec. parquet solver): start from PT2 (vertex K1 in every channel,
     Sigma^(2) from the SDE of Gamma_0), then fixed_point_solve on the state (three channels,
     Sigma) with F = parquet_iteration at the propagator dressed by the state's Sigma; the
     residual is the relative max-norm change, max over the arrays of ||F(x) - x|| / ||F(x)||.
-    Returns (channels, Sigma, residuals per step)."""
-    chans, sigma = pt2_state(grid, U, Delta, T, q_bubble, q_loop)
+    With eps_d (the asymmetric model, Sec. Hartree-Fock) the level of G is eps_d + Sigma_H:
+    the PT2 start takes the self-consistent Sigma_H of the bare level, the state carries
+    Sigma_H as one more entry, and F updates it once per iteration (one shot, U <n> of the
+    state's propagator).  Without eps_d the level is 0 (particle-hole symmetry).
+    Returns (channels, Sigma, residuals per step), plus Sigma_H with eps_d."""
     n = grid.n
+    aam = eps_d is not None
+    sH = 0.0
+    if aam:
+        sH, _ = hartree(U, eps_d, Delta, T, q_hartree, tol=hartree_tol)
+    chans, sigma = pt2_state(grid, U, Delta, T, q_bubble, q_loop, eps=(eps_d + sH) if aam else 0.0)
 
     def Fmap(vec):
-        ch, sg = state_unpack(vec, n)
-        new, snew = parquet_iteration(Vertex(grid, U, ch), sigma_prop(grid, Delta, T, sg), q_bubble, q_loop)
-        return state_pack(new, snew)
+        ch, sg = state_unpack(vec[:-1] if aam else vec, n)
+        P = sigma_prop(grid, Delta, T, sg)
+        if aam:
+            P.eps = eps_d + vec[-1].real
+        new, snew = parquet_iteration(Vertex(grid, U, ch), P, q_bubble, q_loop)
+        out = state_pack(new, snew)
+        if aam:
+            h, _ = hartree(U, eps_d, Delta, T, q_hartree, grid, sg, self_consistent=False, sigma_H=vec[-1].real)
+            out = np.concatenate([out, [h + 0j]])
+        return out
 
-    x, res, _ = fixed_point_solve(Fmap, state_pack(chans, sigma), _rel_residual(n), alpha, depth, iterations, tol,
-                                  reduce_alpha, alpha_min)
-    ch, sg = state_unpack(x, n)
+    base = _rel_residual(n)
+
+    def resid(x, g):
+        if not aam:
+            return base(x, g)
+        r = base(x[:-1], g[:-1])
+        md, mf = abs(g[-1] - x[-1]), abs(g[-1])
+        return max(r, md / mf if mf > 0 else (1.0 if md > 0 else 0.0))
+
+    x0 = state_pack(chans, sigma)
+    if aam:
+        x0 = np.concatenate([x0, [sH + 0j]])
+    x, res, _ = fixed_point_solve(Fmap, x0, resid, alpha, depth, iterations, tol, reduce_alpha, alpha_min)
+    ch, sg = state_unpack(x[:-1] if aam else x, n)
+    if aam:
+        return ch, sg, res, float(x[-1].real)
     return ch, sg, res
 
 
 # ------------------------------------------------------------------ mfRG flow
-def pt2_state(grid: Grid, U: float, Delta: float, T: float, q_bubble: Quad, q_loop: Quad):
+def pt2_state(grid: Grid, U: float, Delta: float, T: float, q_bubble: Quad, q_loop: Quad, eps: float = 0.0):
     """PT2 state (Sec. PT2): K1_r = B_r(Gamma_0, Gamma_0) in every channel, Sigma^(2) from the
-    SDE of Gamma_0 with the bare propagator."""
-    P0 = Prop(Delta, T)
+    SDE of Gamma_0 with the Hartree propagator (level eps = eps_d + Sigma_H)."""
+    P0 = Prop(Delta, T, eps=eps)
     k1 = pt2_k1(grid, U, P0, q_bubble)
     z2 = np.zeros((2, grid.n, grid.n, 16), complex)
     chans = [Channel(1.0, k1[r], z2.copy(), z2.copy(), np.zeros((2, grid.n, grid.n, grid.n, 16), complex))

@@ -1,7 +1,8 @@
 """Pins of the oracle's Hartree term (Sec. Hartree-Fock, Eq. Hartree): the occupation of a
 Lorentzian level against its closed form at finite temperature (digamma function), the
 self-consistent term at particle-hole symmetry, the Friedel sum rule as T -> 0, and the
-one-shot term with a dynamic self-energy against an independent adaptive integration."""
+one-shot term with a dynamic self-energy against an independent adaptive integration, and
+the asymmetric parquet solver at eps_d = -U/2 reproducing the particle-hole symmetric one.""" 
 import numpy as np
 import scipy.integrate as si
 import scipy.special as sp
@@ -61,10 +62,34 @@ def test_one_shot_hartree_with_dynamic_self_energy():
         return np.interp(y, xs, sr.real) + 1j * np.interp(y, xs, sr.imag)
 
     E = eps_d + sH
-    nF = lambda x: 0.5 * (1 - np.tanh(x / (2 * T)))
-    f = lambda x: -nF(x) * (1.0 / (x - E + 1j * D - sig_at(x))).imag / np.pi
+    # <n> = 1/2 + (1/2 pi) int tanh(v/2T) Im G^R (n_F = (1 - tanh)/2 and the sum rule for the 1/2)
+    f = lambda x: np.tanh(x / (2 * T)) * (1.0 / (x - E + 1j * D - sig_at(x))).imag / (2 * np.pi)
     pts = [-g.L, -2, -1, 0, 1, 2, g.L]
-    n = sum(si.quad(f, a, b, epsabs=1e-13, epsrel=1e-12, limit=400)[0] for a, b in zip(pts[:-1], pts[1:]))
+    n = 0.5 + sum(si.quad(f, a, b, epsabs=1e-13, epsrel=1e-12, limit=400)[0] for a, b in zip(pts[:-1], pts[1:]))
     n += si.quad(f, -np.inf, -g.L, epsabs=1e-14, limit=200)[0] + si.quad(f, g.L, np.inf, epsabs=1e-14, limit=200)[0]
     got, _ = O.hartree(U, eps_d, D, T, O.Quad(20001, 1, 0.0, 1.0), g, sig, self_consistent=False, sigma_H=sH)
     assert abs(got - U * n) < 1e-6 * U
+
+
+def test_asymmetric_parquet_solver_at_half_filling_is_the_symmetric_one():
+    g, q = O.Grid(9), O.Quad(31)
+    U = 1.0
+    c0, s0, r0 = O.parquet_solve(g, U, D, 0.1, q, q, iterations=4)
+    c1, s1, r1, sH = O.parquet_solve(g, U, D, 0.1, q, q, iterations=4, eps_d=-U / 2, q_hartree=Q, hartree_tol=1e-14)
+    assert abs(sH - U / 2) < 1e-13
+    assert np.allclose(r0, r1, rtol=1e-10, atol=0)
+    for r in range(3):
+        for x in O.CLASSES:
+            a, b = getattr(c0[r], x), getattr(c1[r], x)
+            assert np.abs(a - b).max() <= 1e-12 * max(np.abs(a).max(), 1e-300)
+    assert np.abs(s1 - s0).max() < 1e-12 * np.abs(s0).max()
+
+
+def test_asymmetric_parquet_solver_contracts_with_the_hartree_entry():
+    """Away from half filling the Hartree term stays within (0, U) (occupation within (0, 1)) and
+    the solver with the Hartree entry in its state contracts."""
+    g, q = O.Grid(9), O.Quad(31)
+    U, eps_d = 1.0, -0.2
+    _, _, res, sH = O.parquet_solve(g, U, D, 0.1, q, q, iterations=6, eps_d=eps_d, q_hartree=Q)
+    assert 0.0 < sH < U and res[-1] < 0.15 * res[0]
+    assert res[-1] < res[-2] < res[-3]
