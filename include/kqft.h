@@ -226,6 +226,25 @@ int kqft_sde(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, 
 int kqft_loop(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, int kind, const kqft_quad* q,
               double* out, void* stream);
 
+/*
+ * kqft_hartree -- Hartree term of the impurity level eps_d (Sec. "Hartree-Fock", Eq. Hartree):
+ *   Sigma_H = U <n_sigma>,   <n_sigma> = 1/2 + (1/2 pi) int dv tanh(v/2T) Im G_H^R(v),
+ *   G_H^R(v) = 1/(v - eps_d - Sigma_H + i Delta - Sigma^R_dyn(v))
+ * (Eq. Hartree with G^< = -2i n_F Im G^R in equilibrium, n_F = (1 - tanh(v/2T))/2, and the
+ * spectral sum rule int A = 1 for the constant half, which keeps <n> = 1/2 exact at
+ * particle-hole symmetry for a self-energy given on a grid), integrated with the quadrature q
+ * (use KQFT_QUAD_TAN_INFINITE: the integrand has Lorentzian tails).  G supplies Delta, T and the
+ * optional dynamic self-energy (SigR on sgrid); G->eps is replaced by eps_d + Sigma_H; the
+ * regulator must be KQFT_REG_DELTA without Sigma_dot.
+ *   self_consistent = 0: one shot; *sigma_H in: the Hartree term inside G_H, out: U <n>.
+ *   self_consistent = 1: bisection of f(x) = x - U n(eps_d + x) on [0, U] (f is increasing,
+ *   f(0) <= 0 <= f(U)) until the bracket is narrower than tol; *sigma_H out: the midpoint.
+ * U >= 0, tol > 0 (self-consistent).  iterations (host, or NULL): evaluations of <n>.
+ * Synchronises `stream` once per evaluation.  FP64.
+ */
+int kqft_hartree(kqft_ctx* ctx, double U, double eps_d, const kqft_propagator* G, const kqft_quad* q,
+                 int self_consistent, double tol, double* sigma_H, int* iterations, void* stream);
+
 /* options of kqft_mfrg_flow */
 typedef struct {
   int reg;               /* KQFT_REG_*: the flow parameter */

@@ -1021,6 +1021,71 @@ static int mloop_core(kqft_ctx* ctx, const kqft_vertex& V, const kqft_propagator
                       kqft_opts o, const std::function<BubbleOut(int, int)>& dview, const BubbleOut* centre,
                       hipStream_t s);
 
+// <n_sigma> = 1/2 + (1/2 pi) sum_j w_j tanh(v_j/2T) Im G^R(v_j) at level E (Eq. Hartree with the
+// spectral sum rule for the constant half); device partial sums, host total
+static int occupation(kqft_ctx* ctx, const kqft_propagator& G, double E, const kqft_quad& q, hipStream_t s,
+                      double* n_out) {
+  int rc;
+  const double *qv, *qw;
+  if ((rc = get_quad(ctx, q, &qv, &qw))) return rc;
+  kqft_propagator Ge = G;
+  Ge.eps = E;
+  DProp P;
+  if ((rc = to_dprop(Ge, P))) return rc;
+  const int nblk = std::max(1, std::min(64, (q.n + 255) / 256));
+  if ((rc = ensure(ctx->flowred, std::max(ctx->flowred.bytes, (size_t)nblk * sizeof(double))))) return rc;
+  double* part = (double*)ctx->flowred.p;
+  launch_occupation(P, qv, qw, q.n, part, nblk, s);
+  std::vector<double> h(nblk);
+  HIP_TRY(hipMemcpyAsync(h.data(), part, (size_t)nblk * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  double t = 0.0;
+  for (int b = 0; b < nblk; ++b) t += h[b];
+  *n_out = 0.5 + t / (2.0 * M_PI);
+  return KQFT_OK;
+}
+
+// Hartree term, one shot (sigma_H in -> U n) or self-consistent by bisection on [0, U].
+static int hartree_core(kqft_ctx* ctx, double U, double eps_d, const kqft_propagator& G, const kqft_quad& q,
+                        bool self_consistent, double tol, double* sigma_H, int* evals, hipStream_t s) {
+  int rc;
+  double n = 0.0;
+  int ev = 0;
+  if (!self_consistent) {
+    if ((rc = occupation(ctx, G, eps_d + *sigma_H, q, s, &n))) return rc;
+    *sigma_H = U * n;
+    ev = 1;
+  } else {
+    double lo = 0.0, hi = U;
+    while (hi - lo > tol && ev < 200) {
+      const double mid = 0.5 * (lo + hi);
+      if ((rc = occupation(ctx, G, eps_d + mid, q, s, &n))) return rc;
+      if (mid - U * n > 0.0)
+        hi = mid;
+      else
+        lo = mid;
+      ++ev;
+    }
+    *sigma_H = 0.5 * (lo + hi);
+  }
+  if (evals) *evals = ev;
+  return KQFT_OK;
+}
+
+int kqft_hartree(kqft_ctx* ctx, double U, double eps_d, const kqft_propagator* G, const kqft_quad* q,
+                 int self_consistent, double tol, double* sigma_H, int* iterations, void* stream) {
+  if (!ctx) return fail(KQFT_EINVAL, "ctx is NULL");
+  if (!G || !q || !sigma_H) return fail(KQFT_EINVAL, "propagator, quadrature and sigma_H must be given");
+  if (q->n < 1 || (q->map != KQFT_QUAD_TAN_FINITE && q->map != KQFT_QUAD_TAN_INFINITE) ||
+      (q->map == KQFT_QUAD_TAN_FINITE && !(q->L > 0)) || !(q->a > 0))
+    return fail(KQFT_ESHAPE, "invalid quadrature");
+  if (G->reg != KQFT_REG_DELTA || G->dSigR) return fail(KQFT_EINVAL, "the Hartree term takes the plain propagator");
+  if (!(U >= 0)) return fail(KQFT_EINVAL, "the bracketing needs U >= 0");
+  if (self_consistent && !(tol > 0)) return fail(KQFT_EINVAL, "tol must be positive");
+  HIP_TRY(hipSetDevice(ctx->device));
+  return hartree_core(ctx, U, eps_d, *G, *q, self_consistent != 0, tol, sigma_H, iterations, (hipStream_t)stream);
+}
+
 // Flow parameter of the ODE (Sec. "Details on the ODE-solver"): the Delta-flow runs in t with
 // Lambda(t) = 5 t|t| / sqrt(1 - t^2), the other flows in Lambda itself.
 static double flow_lambda(int reg, double t) { return reg == KQFT_REG_DELTA ? 5.0 * t * fabs(t) / sqrt(1.0 - t * t) : t; }

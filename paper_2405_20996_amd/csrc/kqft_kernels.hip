@@ -1118,6 +1118,29 @@ __global__ __launch_bounds__(256) void dot_kernel(const double2* a, const double
   }
 }
 
+// Per-block partial sums of w_j tanh(v_j/2T) Im G^R(v_j) over the quadrature nodes: the occupation
+// of the Hartree term is 1/2 + (this sum)/(2 pi); fixed grid and order.
+__global__ __launch_bounds__(256) void occupation_kernel(DProp P, const double* nodes, const double* weights, int nq,
+                                                         double* partial) {
+  double acc = 0.0;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < nq; j += gridDim.x * blockDim.x) {
+    const double v = nodes[j];
+    double2 m[4];
+    propagator(P, 0, v, m);
+    acc = fma(weights[j] * tanh(v / (2.0 * P.T)), m[2].y, acc);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    partial[blockIdx.x] = t;
+  }
+}
+
 // linear mixing x <- x + alpha (f - x)
 __global__ __launch_bounds__(256) void mix_kernel(double2* x, const double2* f, size_t count, double alpha) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x) {
@@ -1781,6 +1804,10 @@ void launch_maxdiff(const double2* x, const double2* f, size_t count, double* pa
 void launch_axpby(double2* out, double a, const double2* x, double b, const double2* y, size_t count,
                   hipStream_t s) {
   hipLaunchKernelGGL(axpby_kernel, dim3(2048), dim3(256), 0, s, out, a, x, b, y, count);
+}
+void launch_occupation(const DProp& P, const double* nodes, const double* weights, int nq, double* partial, int nblk,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(occupation_kernel, dim3(nblk), dim3(256), 0, s, P, nodes, weights, nq, partial);
 }
 void launch_dot(const double2* a, const double2* b, size_t count, double* partial, int nblk, hipStream_t s) {
   hipLaunchKernelGGL(dot_kernel, dim3(nblk), dim3(256), 0, s, a, b, count, partial);

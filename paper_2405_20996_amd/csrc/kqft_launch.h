@@ -197,6 +197,9 @@ struct LinComb {
   size_t count;
 };
 void launch_lincomb(const LinComb& a, hipStream_t s);
+// per-block partial sums of w_j tanh(v_j/2T) Im G^R(v_j) (P.eps is the level)
+void launch_occupation(const DProp& P, const double* nodes, const double* weights, int nq, double* partial, int nblk,
+                       hipStream_t s);
 // per-block partial sums of Re <a, b> over count complex entries (nblk blocks)
 void launch_dot(const double2* a, const double2* b, size_t count, double* partial, int nblk, hipStream_t s);
 void launch_errnorm(const double2* err, const double2* y, const double2* y4, double atol, double rtol, size_t count,

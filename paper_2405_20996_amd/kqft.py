@@ -110,6 +110,8 @@ def lib():
                                         P(KqftChout), C.c_void_p, C.c_void_p, P(KqftFlowInfo), C.c_void_p]
         _lib.kqft_parquet_iteration.argtypes = [C.c_void_p, P(KqftVertex), P(KqftPropagator), P(KqftQuad),
                                                 P(KqftQuad), P(KqftOpts), P(KqftChout), C.c_void_p, C.c_void_p]
+        _lib.kqft_hartree.argtypes = [C.c_void_p, C.c_double, C.c_double, P(KqftPropagator), P(KqftQuad), C.c_int,
+                                      C.c_double, P(C.c_double), P(C.c_int), C.c_void_p]
         _lib.kqft_parquet_solve.argtypes = [C.c_void_p, P(KqftGrid), C.c_double, C.c_double, C.c_double,
                                             P(KqftQuad), P(KqftQuad), P(KqftOpts), P(KqftParquetOpts),
                                             P(KqftChout), C.c_void_p, P(C.c_double), P(C.c_int), C.c_void_p]
@@ -376,6 +378,18 @@ def parquet_iteration(gamma: Vertex, G: Propagator, q_bubble: Quad, q_loop: Quad
                                         C.byref(_opts(precision, KALL, 0, 0)), D, C.c_void_p(sigma.data_ptr()),
                                         _stream(stream)))
     return outs, sigma
+
+
+def hartree(U: float, eps_d: float, G: Propagator, q: Quad, self_consistent: bool = True, tol: float = 1e-12,
+            sigma_H: float = 0.0, stream=None):
+    """Hartree term Sigma_H = U <n> of the level eps_d (one shot from sigma_H, or self-consistent);
+    returns (Sigma_H, evaluations of <n>)."""
+    val = C.c_double(sigma_H)
+    its = C.c_int(0)
+    gc, qc = G.c(), q.c()
+    _check(lib().kqft_hartree(ctx(), C.c_double(U), C.c_double(eps_d), C.byref(gc), C.byref(qc),
+                              int(self_consistent), C.c_double(tol), C.byref(val), C.byref(its), _stream(stream)))
+    return val.value, its.value
 
 
 def parquet_solve(grid: Grid, U: float, Delta: float, T: float, q_bubble: Quad, q_loop: Quad, alpha: float = 0.5,
