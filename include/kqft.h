@@ -321,6 +321,11 @@ typedef struct {
   int reduce_alpha;    /* 1: an iteration whose residual exceeds the previous one halves alpha
                           (not below alpha_min) and clears the Anderson history */
   double alpha_min;    /* 0 < alpha_min <= alpha when reduce_alpha */
+  int hartree;         /* 0: level 0 (particle-hole symmetric model, Sigma_H = U/2 absorbed);
+                          1: asymmetric model with level eps_d + Sigma_H (Sec. "Hartree-Fock") */
+  double eps_d;        /* bare level (hartree = 1) */
+  kqft_quad q_hartree; /* quadrature of the occupation (hartree = 1; full-line map) */
+  double hartree_tol;  /* bracket width of the self-consistent Hartree term of the PT2 start */
 } kqft_parquet_opts;
 
 /*
@@ -335,14 +340,19 @@ typedef struct {
  * iterations, the last m of them) and gamma solving the normal equations
  * (dF^T dF + eps I) gamma = dF^T f over the real inner product Re <a, b> of the state
  * vectors, eps = 1e-14 max_i (dF^T dF)_ii (Walker and Ni 2011); no columns: linear mixing.
+ * With hartree = 1 (asymmetric model) the level of G is eps_d + Sigma_H: the PT2 start uses
+ * the self-consistent Sigma_H of the bare level (kqft_hartree), the state carries Sigma_H as
+ * one more entry, and F updates it once per iteration by the one-shot Hartree term of the
+ * state's propagator (its Sigma and Sigma_H); its relative change enters the residual.
  * gamma[3] (device, out): the channels of the final state; sigma (device [n][4], out);
- * residuals (host [max_iterations] or NULL); iterations (host, out).  Synchronises `stream`
- * once per iteration.  Working memory: (3 + 2m) states besides F(x).
+ * sigma_H (host, out, or NULL): the final Hartree term (U/2 with hartree = 0); residuals
+ * (host [max_iterations] or NULL); iterations (host, out).  Synchronises `stream` once per
+ * iteration.  Working memory: (3 + 2m) states besides F(x).
  */
 int kqft_parquet_solve(kqft_ctx* ctx, const kqft_grid* grid, double U, double Delta, double T,
                        const kqft_quad* q_bubble, const kqft_quad* q_loop, const kqft_opts* opts,
-                       const kqft_parquet_opts* popts, const kqft_chout* gamma, double* sigma, double* residuals,
-                       int* iterations, void* stream);
+                       const kqft_parquet_opts* popts, const kqft_chout* gamma, double* sigma, double* sigma_H,
+                       double* residuals, int* iterations, void* stream);
 
 /*
  * kqft_mloop_step -- multiloop insertions of the mfRG flow (Eqs. 1l, 2l, 3l) for

@@ -1408,8 +1408,8 @@ int kqft_parquet_iteration(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_p
 
 int kqft_parquet_solve(kqft_ctx* ctx, const kqft_grid* grid, double U, double Delta, double T,
                        const kqft_quad* q_bubble, const kqft_quad* q_loop, const kqft_opts* opts,
-                       const kqft_parquet_opts* popts, const kqft_chout* gamma, double* sigma, double* residuals,
-                       int* iterations, void* stream) {
+                       const kqft_parquet_opts* popts, const kqft_chout* gamma, double* sigma, double* sigma_H,
+                       double* residuals, int* iterations, void* stream) {
   int rc;
   if (!grid || (rc = check_grid(*grid, "grid"))) return grid ? rc : fail(KQFT_EINVAL, "grid is NULL");
   kqft_propagator G0;
@@ -1427,6 +1427,14 @@ int kqft_parquet_solve(kqft_ctx* ctx, const kqft_grid* grid, double U, double De
   if (po.anderson_depth < 0 || po.anderson_depth > 32) return fail(KQFT_EINVAL, "need 0 <= anderson_depth <= 32");
   if (po.reduce_alpha && (!(po.alpha_min > 0) || po.alpha_min > po.alpha))
     return fail(KQFT_EINVAL, "need 0 < alpha_min <= alpha");
+  const bool aam = po.hartree != 0;
+  if (aam) {
+    const kqft_quad& qh = po.q_hartree;
+    if (qh.n < 1 || (qh.map != KQFT_QUAD_TAN_FINITE && qh.map != KQFT_QUAD_TAN_INFINITE) ||
+        (qh.map == KQFT_QUAD_TAN_FINITE && !(qh.L > 0)) || !(qh.a > 0))
+      return fail(KQFT_ESHAPE, "invalid Hartree quadrature");
+    if (!(U >= 0) || !(po.hartree_tol > 0)) return fail(KQFT_EINVAL, "the Hartree term needs U >= 0 and tol > 0");
+  }
   if (!gamma || !sigma || !iterations) return fail(KQFT_EINVAL, "gamma, sigma and iterations must be given");
   for (int r = 0; r < 3; ++r)
     if (!gamma[r].K1 || !gamma[r].K2 || !gamma[r].K2p || !gamma[r].K3)
@@ -1437,7 +1445,8 @@ int kqft_parquet_solve(kqft_ctx* ctx, const kqft_grid* grid, double U, double De
   const size_t c1 = (size_t)2 * n * 16, c2 = (size_t)2 * n * n * 16, c3 = (size_t)2 * n * n * n * 16;
   const size_t cnt[4] = {c1, c2, c2, c3};
   const size_t chc = c1 + 2 * c2 + c3;
-  const size_t stc = 3 * chc + (size_t)4 * n;  // state: channels a, p, t (K1, K2, K2', K3), Sigma
+  // state: channels a, p, t (K1, K2, K2', K3), Sigma, and Sigma_H for the asymmetric model
+  const size_t stc = 3 * chc + (size_t)4 * n + (aam ? 1 : 0);
   // g = F(x) in pq; x, f, the previous f and g, and 2m Anderson columns in pqx
   if ((rc = ensure(ctx->pq, stc * sizeof(double2)))) return rc;
   if ((rc = ensure(ctx->pqx, (size_t)(4 + 2 * m) * stc * sizeof(double2)))) return rc;
@@ -1468,6 +1477,14 @@ int kqft_parquet_solve(kqft_ctx* ctx, const kqft_grid* grid, double U, double De
   bare.grid = *grid;
   for (int r = 0; r < 3; ++r)
     for (int c = 1; c < 4; ++c) HIP_TRY(hipMemsetAsync(cls(xb, r, c), 0, cnt[c] * sizeof(double2), s));
+  double sH = 0.5 * U;
+  if (aam) {  // self-consistent Hartree term of the bare level, into the state
+    if ((rc = hartree_core(ctx, U, po.eps_d, G0, po.q_hartree, true, po.hartree_tol, &sH, nullptr, s))) return rc;
+    G0.eps = po.eps_d + sH;
+    const double2 hv = make_double2(sH, 0.0);
+    HIP_TRY(hipMemcpyAsync(xsig + 4 * n, &hv, sizeof hv, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
   kqft_opts o = *opts;
   o.beta = 0;
   o.class_mask = KQFT_K1;
@@ -1501,11 +1518,27 @@ int kqft_parquet_solve(kqft_ctx* ctx, const kqft_grid* grid, double U, double De
     }
   xf.push_back({xsig, g + 3 * chc});
   counts.push_back((size_t)n * 4);
+  if (aam) {
+    xf.push_back({xsig + 4 * n, g + 3 * chc + 4 * n});
+    counts.push_back(1);
+  }
   double alpha = po.alpha, prev_res = 0.0;
   int ncol = 0, head = 0, it = 0;
   bool have_prev = false;
   for (; it < po.max_iterations;) {
     launch_sigma_split(n, xsig, sigR, sigK, s);
+    if (aam) {  // the state's Hartree term sets the level
+      double2 hv;
+      HIP_TRY(hipMemcpyAsync(&hv, xsig + 4 * n, sizeof hv, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      Gs.eps = po.eps_d + hv.x;
+      double h = hv.x;
+      kqft_propagator Gh = Gs;
+      if ((rc = hartree_core(ctx, U, po.eps_d, Gh, po.q_hartree, false, 0.0, &h, nullptr, s))) return rc;
+      const double2 hn = make_double2(h, 0.0);
+      HIP_TRY(hipMemcpyAsync(g + 3 * chc + 4 * n, &hn, sizeof hn, hipMemcpyHostToDevice, s));
+      HIP_TRY(hipStreamSynchronize(s));
+    }
     if ((rc = parquet_core(ctx, V, Gs, *q_bubble, *q_loop, *opts, F, (double*)(g + 3 * chc), s))) return rc;
     double res = 0.0;
     if ((rc = rel_change(ctx, xf, counts, s, &res))) return rc;
@@ -1575,6 +1608,13 @@ int kqft_parquet_solve(kqft_ctx* ctx, const kqft_grid* grid, double U, double De
       HIP_TRY(hipMemcpyAsync(dst[c], cls(xb, r, c), cnt[c] * sizeof(double2), hipMemcpyDeviceToDevice, s));
   }
   HIP_TRY(hipMemcpyAsync(sigma, xsig, (size_t)4 * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  if (aam) {
+    double2 hv;
+    HIP_TRY(hipMemcpyAsync(&hv, xsig + 4 * n, sizeof hv, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    sH = hv.x;
+  }
+  if (sigma_H) *sigma_H = sH;
   *iterations = it;
   HIP_TRY(hipGetLastError());
   return KQFT_OK;

@@ -57,7 +57,8 @@ class KqftFlowOpts(C.Structure):
 
 class KqftParquetOpts(C.Structure):
     _fields_ = [("alpha", C.c_double), ("max_iterations", C.c_int), ("tol", C.c_double),
-                ("anderson_depth", C.c_int), ("reduce_alpha", C.c_int), ("alpha_min", C.c_double)]
+                ("anderson_depth", C.c_int), ("reduce_alpha", C.c_int), ("alpha_min", C.c_double),
+                ("hartree", C.c_int), ("eps_d", C.c_double), ("q_hartree", KqftQuad), ("hartree_tol", C.c_double)]
 
 
 class KqftFlowInfo(C.Structure):
@@ -114,7 +115,8 @@ def lib():
                                       C.c_double, P(C.c_double), P(C.c_int), C.c_void_p]
         _lib.kqft_parquet_solve.argtypes = [C.c_void_p, P(KqftGrid), C.c_double, C.c_double, C.c_double,
                                             P(KqftQuad), P(KqftQuad), P(KqftOpts), P(KqftParquetOpts),
-                                            P(KqftChout), C.c_void_p, P(C.c_double), P(C.c_int), C.c_void_p]
+                                            P(KqftChout), C.c_void_p, P(C.c_double), P(C.c_double), P(C.c_int),
+                                            C.c_void_p]
     return _lib
 
 
@@ -394,22 +396,32 @@ def hartree(U: float, eps_d: float, G: Propagator, q: Quad, self_consistent: boo
 
 def parquet_solve(grid: Grid, U: float, Delta: float, T: float, q_bubble: Quad, q_loop: Quad, alpha: float = 0.5,
                   max_iterations: int = 20, tol: float = 0.0, precision: int = FP64, depth: int = 0,
-                  reduce_alpha: bool = False, alpha_min: float = 0.01, stream=None):
+                  reduce_alpha: bool = False, alpha_min: float = 0.01, eps_d: Optional[float] = None,
+                  q_hartree: Optional[Quad] = None, hartree_tol: float = 1e-12, stream=None):
     """Parquet solver from the PT2 state with linear mixing or Anderson acceleration of the
-    given depth; returns (channels, Sigma, residuals)."""
+    given depth; with eps_d, the asymmetric model with the Hartree term in the state.
+    Returns (channels, Sigma, residuals), plus Sigma_H with eps_d."""
     n = grid.n
     outs = [alloc_channel(n) for _ in range(3)]
     dev = torch.device("cuda", torch.cuda.current_device())
     sigma = torch.zeros((n, 4), dtype=torch.complex128, device=dev)
     res = (C.c_double * max_iterations)()
     its = C.c_int(0)
+    sH = C.c_double(0.0)
     D = (KqftChout * 3)(*[_chout(o, n) for o in outs])
     gc, qb, ql = grid.c(), q_bubble.c(), q_loop.c()
-    po = KqftParquetOpts(alpha, max_iterations, tol, depth, int(reduce_alpha), alpha_min)
+    aam = eps_d is not None
+    if aam and q_hartree is None:
+        raise ValueError("the asymmetric model needs q_hartree")
+    qh = q_hartree.c() if aam else KqftQuad(1, QUAD_TAN_INFINITE, 0.0, 1.0)
+    po = KqftParquetOpts(alpha, max_iterations, tol, depth, int(reduce_alpha), alpha_min, int(aam),
+                         eps_d if aam else 0.0, qh, hartree_tol)
     _check(lib().kqft_parquet_solve(ctx(), C.byref(gc), C.c_double(U), C.c_double(Delta), C.c_double(T),
                                     C.byref(qb), C.byref(ql), C.byref(_opts(precision, KALL, 0, 0)), C.byref(po),
-                                    D, C.c_void_p(sigma.data_ptr()), res, C.byref(its), _stream(stream)))
-    return outs, sigma, [res[i] for i in range(its.value)]
+                                    D, C.c_void_p(sigma.data_ptr()), C.byref(sH), res, C.byref(its),
+                                    _stream(stream)))
+    out = (outs, sigma, [res[i] for i in range(its.value)])
+    return out + (sH.value,) if aam else out
 
 
 def bubble_adjoint(channel: int, left: Vertex, right: Vertex, G: Propagator, q: Quad, dout: Channel,

@@ -48,3 +48,24 @@ def test_self_consistent_hartree_matches_oracle(U, eps_d):
     assert abs(got - ref) <= 2 * tol + 1e-14 and abs(it - rit) <= 1
     if eps_d == -U / 2:
         assert abs(got - U / 2) < 2 * tol
+
+
+@pytest.mark.parametrize("eps_d,depth", [(-0.5, 0), (-0.2, 0), (0.3, 2)])
+def test_asymmetric_parquet_solver_matches_oracle(eps_d, depth):
+    """Asymmetric model (level eps_d + Sigma_H, Hartree term in the state): residuals, final
+    state and Hartree term as the oracle's, n = 9, N_q = 31, U = 1."""
+    K = _K()
+    n, nq, U, iters = 9, 31, 1.0, 6
+    qh = (4001, 1, 0.0, 1.0)
+    oc, osig, ores, osH = O.parquet_solve(O.Grid(n), U, D, T, O.Quad(nq), O.Quad(nq), alpha=0.5, iterations=iters,
+                                          depth=depth, eps_d=eps_d, q_hartree=O.Quad(*qh), hartree_tol=1e-13)
+    kc, ksig, kres, ksH = K.parquet_solve(K.Grid(n), U, D, T, K.Quad(nq), K.Quad(nq), alpha=0.5, max_iterations=iters,
+                                          depth=depth, eps_d=eps_d, q_hartree=K.Quad(*qh), hartree_tol=1e-13)
+    torch.cuda.synchronize()
+    print(f"eps_d={eps_d} depth={depth}: Sigma_H {ksH:.12f}, residuals {['%.2e' % x for x in kres]}", flush=True)
+    assert abs(ksH - osH) < 1e-10 and np.allclose(kres, ores, rtol=1e-7, atol=0)
+    for r in range(3):
+        for x in ("K1", "K2", "K2p", "K3"):
+            a, b = getattr(kc[r], x).cpu().numpy(), getattr(oc[r], x)
+            assert np.abs(a - b).max() < 1e-9 * np.abs(b).max(), (r, x)
+    assert np.abs(ksig.cpu().numpy() - osig).max() < 1e-9 * np.abs(osig).max()
