@@ -713,6 +713,34 @@ static void bubble_points(int r, const OVert& Lv, const OVert& Rv, const OProp& 
   }
 }
 
+// Integrand of the bubble at output (cls, iw, i, j) and loop frequencies vq[k]: the summand of
+// bubble_points with Pi / (2 pi i) and no quadrature weight; out[p][k][2][16].
+static void bubble_integrand(int r, const OVert& Lv, const OVert& Rv, const OProp& P, int kind, int npts,
+                             const int* pts, int nv, const double* vq, Cx<double>* out) {
+  Vtx<double> VL = make_vtx<double>(Lv), VR = make_vtx<double>(Rv);
+#pragma omp parallel for schedule(dynamic)
+  for (int p = 0; p < npts; ++p) {
+    int cls = pts[4 * p], iw = pts[4 * p + 1], i = pts[4 * p + 2], j = pts[4 * p + 3];
+    bool linf = (cls == C_K2P || cls == C_K1), rinf = (cls == C_K2 || cls == C_K1);
+    double w = grid_node(VL.g, iw);
+    double v = linf ? 0.0 : grid_node(VL.g, i);
+    double vp = rinf ? 0.0 : grid_node(VL.g, j);
+    for (int k = 0; k < nv; ++k) {
+      Cx<double> Pi[16], LX[16], LY[16], RX[16], RY[16], tX[16], tY[16];
+      bubble_pi<double>(P, r, kind, w, vq[k], Pi);
+      for (int f = 0; f < 16; ++f) Pi[f] = cmul(0.0, -1.0 / (2.0 * M_PI), Pi[f]);
+      left_factor(VL, r, w, v, vq[k], linf, LX, LY);
+      right_factor(VR, r, w, vq[k], vp, rinf, RX, RY);
+      spin_sums<double>(r, LX, LY, Pi, RX, RY, tX, tY);
+      Cx<double>* o = out + ((size_t)p * nv + k) * 32;
+      for (int f = 0; f < 16; ++f) {
+        o[f] = tX[f];
+        o[16 + f] = tY[f];
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- brute force
 // Full vertex Gamma(1'2'|12) from leg quantum numbers (Keldysh al, spin sg in
 // {0=up,1=down}, frequencies nu), summing every channel through its own
@@ -941,6 +969,11 @@ void oracle_propagator(int dual, const OProp* P, int kind, int npts, const doubl
       o[0] = m[0][0]; o[1] = m[0][1]; o[2] = m[1][0]; o[3] = m[1][1];
     }
   }
+}
+
+void oracle_bubble_integrand(int r, const OVert* L, const OVert* R, const OProp* P, int kind, int npts,
+                             const int* pts, int nv, const double* vq, double* out) {
+  bubble_integrand(r, *L, *R, *P, kind, npts, pts, nv, vq, (Cx<double>*)out);
 }
 
 void oracle_bubble_pi(int dual, const OProp* P, int r, int kind, double w, double vq, double* out16) {

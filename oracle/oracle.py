@@ -83,6 +83,8 @@ def lib():
                                        C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         _lib.oracle_bubble_points.argtypes = [C.c_int, C.c_int, P(OVert), P(OVert), P(OProp), C.c_int,
                                               P(OQuad), C.c_int, C.c_void_p, C.c_void_p]
+        _lib.oracle_bubble_integrand.argtypes = [C.c_int, P(OVert), P(OVert), P(OProp), C.c_int, C.c_int,
+                                                 C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         _lib.oracle_bubble_brute.argtypes = [C.c_int, P(OVert), P(OVert), P(OProp), C.c_int, P(OQuad),
                                              C.c_double, C.c_double, C.c_double, C.c_void_p]
         _lib.oracle_loop.argtypes = [C.c_int, P(OVert), P(OProp), C.c_int, P(OQuad), C.c_void_p]
@@ -285,6 +287,134 @@ def bubble_points(r: int, left: Vertex, right: Vertex, P: Prop, q: Quad, pts, ki
     lib().oracle_bubble_points(int(dual), r, C.byref(lc), C.byref(rc), C.byref(pc), kind, C.byref(qc), len(pts),
                                pts.ctypes.data, out.ctypes.data)
     return out
+
+
+def bubble_integrand(r: int, left: Vertex, right: Vertex, P: Prop, pts, vq, kind: int = 0) -> np.ndarray:
+    """Summand of the bubble at outputs pts[p] = (class, iw, i, j) and loop frequencies vq:
+    [p][k][2 (X, Y)][16], Pi / (2 pi i) without quadrature weight."""
+    pts = np.ascontiguousarray(pts, dtype=np.int32).reshape(-1, 4)
+    vq = np.ascontiguousarray(np.atleast_1d(vq), dtype=np.float64)
+    out = np.zeros((len(pts), len(vq), 2, 16), dtype=np.complex128)
+    keep = []
+    lc, rc, pc = left.c(keep), right.c(keep), P.c(keep)
+    lib().oracle_bubble_integrand(r, C.byref(lc), C.byref(rc), C.byref(pc), kind, len(pts), pts.ctypes.data,
+                                  len(vq), vq.ctypes.data, out.ctypes.data)
+    return out
+
+
+# ------------------------------------------------------------------ adaptive integration
+# Gauss-Lobatto 4-point rule with its 7-point Kronrod extension and the 13-point extension of
+# that (Sec. Frequency integration), on [-1, 1].  Every rule is derived from its definition:
+# symmetric nodes containing the lower rule's nodes, weights and the new nodes fixed by exact
+# integration of the even monomials up to the rule's degree (GL4: 5, GLK7: 9, GLK13: 18).
+def _symmetric_rule(fixed, new_guess, degree):
+    """Nodes = +-fixed (0 allowed), +-new; solve the even-moment equations for the new positive
+    nodes and all weights (Newton from new_guess).  Returns (nodes ascending, weights)."""
+    fixed = list(fixed)
+    new = np.array(new_guess, dtype=float)
+
+    def assemble(newn):
+        pos = sorted(set(fixed) | set(newn.tolist()))
+        return pos
+
+    for _ in range(100):
+        pos = assemble(new)
+        # weights of the positive nodes (node 0 counted once) from the first len(pos) even moments
+        ks = np.arange(0, degree + 1, 2)
+        A = np.array([[(2.0 if x > 0 else 1.0) * x ** k for x in pos] for k in ks])
+        b = np.array([2.0 / (k + 1) for k in ks])
+        m = len(pos)
+        if len(new) == 0:
+            w = np.linalg.solve(A[:m], b[:m])
+            break
+        # residual of the moments as a function of the new nodes, weights eliminated from the first m moments
+
+        def resid(newn):
+            p = assemble(newn)
+            Am = np.array([[(2.0 if x > 0 else 1.0) * x ** k for x in p] for k in ks])
+            ww = np.linalg.solve(Am[:m], b[:m])
+            return Am[m:] @ ww - b[m:], ww
+
+        r0, w = resid(new)
+        if np.abs(r0).max() < 1e-15:
+            break
+        J = np.zeros((len(r0), len(new)))
+        h = 1e-7
+        for c in range(len(new)):
+            d = np.zeros_like(new)
+            d[c] = h
+            J[:, c] = (resid(new + d)[0] - resid(new - d)[0]) / (2 * h)
+        new = new - np.linalg.lstsq(J, r0, rcond=None)[0]
+    pos = assemble(new)
+    nodes = np.array([-x for x in reversed(pos) if x > 0] + pos)
+    wpos = dict(zip(pos, w))
+    weights = np.array([wpos[abs(x)] if abs(x) in wpos else wpos[-x] for x in nodes])
+    return nodes, weights
+
+
+def glk_rules():
+    """(GL4, GLK7, GLK13) as (nodes, weights) on [-1, 1]; GL4 and GLK7 share GLK7's nodes
+    (GL4 weight 0 on the Kronrod nodes)."""
+    if "rules" not in _RULES:
+        gl4 = _symmetric_rule([1.0], [0.45], 5)
+        glk7 = _symmetric_rule([1.0, gl4[0][-2], 0.0], [0.8], 9)
+        glk13 = _symmetric_rule(list(glk7[0][glk7[0] >= 0]), [0.94, 0.64, 0.24], 18)
+        w4 = np.array([dict(zip(np.round(gl4[0], 14), gl4[1])).get(round(x, 14), 0.0) for x in glk7[0]])
+        _RULES["rules"] = ((glk7[0], w4), glk7, glk13)
+    return _RULES["rules"]
+
+
+_RULES = {}
+
+
+def adaptive_glk(f, a: float, b: float, eps: float, min_width: float = 1e-12, max_depth: int = 40):
+    """Adaptive Gauss-Lobatto-Kronrod integration of a vector-valued f over [a, b] (Sec. Frequency
+    integration): I_s = GLK13 over [a, b] once (when it vanishes, (b - a) max|f| at its nodes
+    stands in, else 1); on each interval I1 = GL4, I2 = GLK7 (same seven nodes); accept I2
+    when max|I2 - I1| <= eps max|I_s|, else split at the seven nodes into six
+    intervals and recurse (an interval narrower than min_width or deeper than max_depth is
+    accepted as is).  f maps an array of points to [len(points), ...].
+    Returns (integral, number of accepted intervals)."""
+    (x7, w4), (_, w7), (x13, w13) = glk_rules()
+    m, h = 0.5 * (a + b), 0.5 * (b - a)
+    F13 = f(m + h * x13)
+    Is = h * np.tensordot(w13, F13, axes=1)
+    scale = float(np.abs(Is).max())
+    if scale == 0.0:  # a vanishing estimate: the integrand's size on the domain, else 1
+        scale = (b - a) * float(np.abs(F13).max()) or 1.0
+    count = [0]
+
+    def rec(lo, hi, depth):
+        mm, hh = 0.5 * (lo + hi), 0.5 * (hi - lo)
+        x = mm + hh * x7
+        F = f(x)
+        I1 = hh * np.tensordot(w4, F, axes=1)
+        I2 = hh * np.tensordot(w7, F, axes=1)
+        if float(np.abs(I2 - I1).max()) <= eps * scale or hi - lo < min_width or depth >= max_depth:
+            count[0] += 1
+            return I2
+        return sum(rec(x[k], x[k + 1], depth + 1) for k in range(6))
+
+    return rec(a, b, 0), count[0]
+
+
+def bubble_adaptive_points(r: int, left: Vertex, right: Vertex, P: Prop, q: Quad, pts, eps: float, kind: int = 0):
+    """Bubble outputs at pts[p] = (class, iw, i, j) by adaptive_glk over the auxiliary variable y
+    of the quadrature's tangent map onto [-L, L] (v'' = a tan(y atan(L/a)), dv''/dy the
+    Jacobian), each output integrated on its own: [p][2][16], and the accepted intervals."""
+    if q.map != 0:
+        raise ValueError("the adaptive bubble integrates over the finite tangent map")
+    th = np.arctan(q.L / q.a)
+    out = np.zeros((len(pts), 2, 16), dtype=np.complex128)
+    counts = []
+    for p, pt in enumerate(pts):
+        def f(y):
+            v = q.a * np.tan(y * th)
+            jac = q.a * th / np.cos(y * th) ** 2
+            return bubble_integrand(r, left, right, P, [pt], v, kind)[0] * jac[:, None, None]
+        out[p], c = adaptive_glk(f, -1.0, 1.0, eps)
+        counts.append(c)
+    return out, counts
 
 
 def bubble_brute(r: int, left: Vertex, right: Vertex, P: Prop, q: Quad, w: float, v: float, vp: float,
