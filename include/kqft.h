@@ -226,6 +226,32 @@ int kqft_sde(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, 
 int kqft_loop(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, int kind, const kqft_quad* q,
               double* out, void* stream);
 
+/* what an adaptive bubble did */
+typedef struct {
+  long long intervals;   /* accepted intervals, summed over the outputs */
+  int generations;       /* refinement generations */
+  long long evaluations; /* integrand evaluations (nodes x outputs, the error scales included) */
+} kqft_adapt_info;
+
+/*
+ * kqft_bubble_adaptive -- the bubble B_r(left, right) of kqft_bubble with the loop integral
+ * done by adaptive Gauss-Lobatto-Kronrod quadrature per output entry (Sec. "Frequency
+ * integration") instead of a fixed Gauss-Legendre rule.  For every selected output (class,
+ * w, v, v') the vector of its 32 entries (16 Keldysh x X, Y) is integrated over the auxiliary
+ * variable y in [-1, 1] of q's tangent map v'' = q->a tan(y atan(q->L / q->a)) (q->map must
+ * be KQFT_QUAD_TAN_FINITE; q->n is unused) with the Jacobian: I_s = GLK13 over [-1, 1] sets
+ * the error scale max|I_s| ((b - a) max|F| at its nodes if that vanishes, else 1); an
+ * interval is accepted with its GLK7 value when max|GLK7 - GL4| <= eps max|I_s|, narrower
+ * than 1e-12 or 40 subdivisions deep, else split at the seven GLK7 nodes into six.  The work
+ * proceeds breadth first over all outputs (one wavefront per output interval).  FP64; outputs
+ * overwritten for the classes of opts->class_mask (precision, beta, omega_batch ignored).
+ * info (host, or NULL).  Errors as kqft_bubble, KQFT_ENOMEM when the work list exceeds
+ * max(2^20, 48 x outputs) intervals, KQFT_ENOCONV when the refinement does not end.
+ */
+int kqft_bubble_adaptive(kqft_ctx* ctx, int channel, const kqft_vertex* left, const kqft_vertex* right,
+                         const kqft_propagator* G, int pi_kind, const kqft_quad* q, double eps, const kqft_opts* opts,
+                         const kqft_chout* out, kqft_adapt_info* info, void* stream);
+
 /*
  * kqft_hartree -- Hartree term of the impurity level eps_d (Sec. "Hartree-Fock", Eq. Hartree):
  *   Sigma_H = U <n_sigma>,   <n_sigma> = 1/2 + (1/2 pi) int dv tanh(v/2T) Im G_H^R(v),

@@ -1,6 +1,7 @@
 // kqft_api.hip -- C ABI of the MI355X Keldysh bubble library: validation, context and
 // workspace management, grid/quadrature tables, and the orchestration of the kernels
 // for kqft_bubble, kqft_sde, kqft_mloop_step and kqft_bubble_adjoint.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -43,7 +44,7 @@ struct kqft_ctx {
   // consecutive transfer-frequency batches overlap, ordered by events
   hipStream_t sg = nullptr, sm = nullptr;
   rocblas_handle blas = nullptr;
-  DevBuf adjw, dkf[2][3], phigrad, pq, pqsig, pqred, vtab[3], flow, flowml, ctmp, flowred, pqx;
+  DevBuf adjw, dkf[2][3], phigrad, pq, pqsig, pqred, vtab[3], flow, flowml, ctmp, flowred, pqx, adapt;
   std::vector<hipEvent_t> events;
   size_t next_event = 0;
   bool prof = false;
@@ -920,7 +921,7 @@ int kqft_ctx_destroy(kqft_ctx* ctx) {
       if (b.p) (void)hipFree(b.p);
   if (ctx->adjw.p) (void)hipFree(ctx->adjw.p);
   for (DevBuf* b : {&ctx->pq, &ctx->pqsig, &ctx->pqred, &ctx->vtab[0], &ctx->vtab[1], &ctx->vtab[2], &ctx->flow,
-                    &ctx->flowml, &ctx->ctmp, &ctx->flowred, &ctx->pqx})
+                    &ctx->flowml, &ctx->ctmp, &ctx->flowred, &ctx->pqx, &ctx->adapt})
     if (b->p) (void)hipFree(b->p);
   if (ctx->phigrad.p) (void)hipFree(ctx->phigrad.p);
   if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
@@ -987,6 +988,213 @@ int kqft_bubble(kqft_ctx* ctx, int channel, const kqft_vertex* left, const kqft_
   HIP_TRY(hipSetDevice(ctx->device));
   BubbleOut o{(double2*)out->K1, (double2*)out->K2, (double2*)out->K2p, (double2*)out->K3};
   return bubble_core(ctx, channel, *left, *right, *G, pi_kind, *q, *opts, o, (hipStream_t)stream);
+}
+
+// Gauss-Lobatto-Kronrod rules on [-1, 1] (Sec. Frequency integration).  GL4 and its 7-point
+// Kronrod extension in closed form; the 13-point extension (the GLK7 nodes plus three new
+// symmetric pairs, exact for even degrees up to 18) from its moment equations: weights by a
+// linear solve of the moments of degree 0..12, the new nodes by Newton on those of degree
+// 14, 16, 18.  Nodes ascending.
+struct GlkRules {
+  double x7[7], w4[7], w7[7], x13[13], w13[13];
+  bool ok = false;
+};
+static bool glk13_weights(const double pos[7], double wpos[7]) {
+  std::vector<double> A(49), b(7), x;
+  for (int k = 0; k < 7; ++k) {
+    for (int c = 0; c < 7; ++c) A[(size_t)k * 7 + c] = (pos[c] == 0.0 ? 1.0 : 2.0) * pow(pos[c], 2.0 * k);
+    b[k] = 2.0 / (2.0 * k + 1.0);
+  }
+  if (!solve_small(A, b, 7, x)) return false;
+  for (int c = 0; c < 7; ++c) wpos[c] = x[c];
+  return true;
+}
+static const GlkRules& glk_rules() {
+  static GlkRules R;
+  if (R.ok) return R;
+  const double s5 = 1.0 / sqrt(5.0), s23 = sqrt(2.0 / 3.0);
+  const double x7[7] = {-1.0, -s23, -s5, 0.0, s5, s23, 1.0};
+  const double w4[7] = {1.0 / 6.0, 0.0, 5.0 / 6.0, 0.0, 5.0 / 6.0, 0.0, 1.0 / 6.0};
+  const double w7[7] = {11.0 / 210.0, 72.0 / 245.0, 125.0 / 294.0, 16.0 / 35.0, 125.0 / 294.0, 72.0 / 245.0,
+                        11.0 / 210.0};
+  for (int k = 0; k < 7; ++k) {
+    R.x7[k] = x7[k];
+    R.w4[k] = w4[k];
+    R.w7[k] = w7[k];
+  }
+  double t[3] = {0.94, 0.64, 0.24};  // the new positive nodes
+  auto resid = [&](const double tt[3], double out[3], double wpos[7], double pos[7]) -> bool {
+    const double p[7] = {0.0, s5, s23, 1.0, tt[0], tt[1], tt[2]};
+    for (int c = 0; c < 7; ++c) pos[c] = p[c];
+    if (!glk13_weights(pos, wpos)) return false;
+    for (int q = 0; q < 3; ++q) {
+      const double k = 14.0 + 2.0 * q;
+      double m = 0.0;
+      for (int c = 0; c < 7; ++c) m += (pos[c] == 0.0 ? 1.0 : 2.0) * wpos[c] * pow(pos[c], k);
+      out[q] = m - 2.0 / (k + 1.0);
+    }
+    return true;
+  };
+  double wpos[7], pos[7], r0[3];
+  for (int itn = 0; itn < 60; ++itn) {
+    if (!resid(t, r0, wpos, pos)) return R;
+    if (fabs(r0[0]) + fabs(r0[1]) + fabs(r0[2]) < 1e-16) break;
+    std::vector<double> J(9), rhs(3), dx;
+    for (int c = 0; c < 3; ++c) {
+      double tp[3] = {t[0], t[1], t[2]}, tm[3] = {t[0], t[1], t[2]}, rp[3], rm[3], wd[7], pd[7];
+      tp[c] += 1e-7;
+      tm[c] -= 1e-7;
+      if (!resid(tp, rp, wd, pd) || !resid(tm, rm, wd, pd)) return R;
+      for (int q = 0; q < 3; ++q) J[(size_t)q * 3 + c] = (rp[q] - rm[q]) / 2e-7;
+    }
+    for (int q = 0; q < 3; ++q) rhs[q] = r0[q];
+    if (!solve_small(J, rhs, 3, dx)) return R;
+    for (int c = 0; c < 3; ++c) t[c] -= dx[c];
+  }
+  if (!resid(t, r0, wpos, pos)) return R;
+  // ascending nodes: -pos (descending magnitude), 0, +pos
+  std::vector<std::pair<double, double>> nw;
+  for (int c = 0; c < 7; ++c) {
+    nw.push_back({pos[c], wpos[c]});
+    if (pos[c] != 0.0) nw.push_back({-pos[c], wpos[c]});
+  }
+  std::sort(nw.begin(), nw.end());
+  if (nw.size() != 13) return R;
+  for (int k = 0; k < 13; ++k) {
+    R.x13[k] = nw[k].first;
+    R.w13[k] = nw[k].second;
+  }
+  R.ok = true;
+  return R;
+}
+
+int kqft_bubble_adaptive(kqft_ctx* ctx, int channel, const kqft_vertex* left, const kqft_vertex* right,
+                         const kqft_propagator* G, int pi_kind, const kqft_quad* q, double eps, const kqft_opts* opts,
+                         const kqft_chout* out, kqft_adapt_info* info, void* stream) {
+  int rc;
+  if ((rc = check_common(ctx, G, q, opts))) return rc;
+  if (channel < 0 || channel > 2) return fail(KQFT_EINVAL, "channel must be 0 (a), 1 (p) or 2 (t)");
+  if (pi_kind != KQFT_PI_GG && pi_kind != KQFT_PI_DOT) return fail(KQFT_EINVAL, "unknown propagator pair");
+  if (q->map != KQFT_QUAD_TAN_FINITE) return fail(KQFT_EINVAL, "the adaptive bubble integrates over [-L, L]");
+  if (!(eps > 0)) return fail(KQFT_EINVAL, "eps must be positive");
+  if ((rc = check_vertex(left, "left vertex")) || (rc = check_vertex(right, "right vertex"))) return rc;
+  if (!same_grid(left->grid, right->grid)) return fail(KQFT_ESHAPE, "left and right vertices must share one grid");
+  if (!out) return fail(KQFT_EINVAL, "out is NULL");
+  const int msk = opts->class_mask & KQFT_KALL;
+  if (msk == 0) return fail(KQFT_EINVAL, "class_mask selects no class");
+  if (((msk & KQFT_K1) && !out->K1) || ((msk & KQFT_K2) && !out->K2) || ((msk & KQFT_K2P) && !out->K2p) ||
+      ((msk & KQFT_K3) && !out->K3))
+    return fail(KQFT_EINVAL, "an output class selected by class_mask is NULL");
+  const GlkRules& gr = glk_rules();
+  if (!gr.ok) return fail(KQFT_EDEVICE, "Gauss-Lobatto-Kronrod rule construction failed");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const int r = channel, n = left->grid.n;
+  if ((rc = init_tables())) return rc;
+  const double* nodes;
+  if ((rc = get_grid(ctx, left->grid, &nodes))) return rc;
+  DProp P;
+  if ((rc = to_dprop(*G, P))) return rc;
+  SideTables TL, TR;
+  if ((rc = build_tables(ctx, r, *left, *right, false, TL, TR, s))) return rc;
+  // outputs in the order K1, K2, K2', K3 of the selected classes
+  const long long cnts[4] = {n, (long long)n * n, (long long)n * n, (long long)n * n * n};
+  const int bits[4] = {KQFT_K1, KQFT_K2, KQFT_K2P, KQFT_K3};
+  double2* outs[4] = {(double2*)out->K1, (double2*)out->K2, (double2*)out->K2p, (double2*)out->K3};
+  long long nout_tot = 0;
+  AdaptArgs A;
+  memset(&A, 0, sizeof A);
+  for (int c = 0; c < 4; ++c) {
+    A.cstart[c] = (int)nout_tot;
+    A.ccount[c] = (msk & bits[c]) ? (int)cnts[c] : 0;
+    nout_tot += A.ccount[c];
+    A.K[c] = (msk & bits[c]) ? outs[c] : nullptr;
+    if (msk & bits[c]) HIP_TRY(hipMemsetAsync(outs[c], 0, 2 * (size_t)cnts[c] * 16 * sizeof(double2), s));
+  }
+  if (nout_tot > (1LL << 28)) return fail(KQFT_ESHAPE, "too many outputs for the adaptive bubble");
+  const long long cap = std::max<long long>(1LL << 20, 48 * nout_tot);
+  if (cap > (1LL << 30)) return fail(KQFT_ESHAPE, "adaptive work list too large");
+  // device memory: two rules (78 doubles), scale per output, two work lists, counters
+  const size_t rule_b = 2 * 39 * sizeof(double), scale_b = (size_t)nout_tot * sizeof(double);
+  const size_t list_b = (size_t)cap * sizeof(AdaptItem);
+  const size_t off_scale = 1024, off_l0 = off_scale + ((scale_b + 255) / 256) * 256, off_l1 = off_l0 + list_b,
+               off_cnt = off_l1 + list_b;
+  if ((rc = ensure(ctx->adapt, off_cnt + 256))) return rc;
+  char* base = (char*)ctx->adapt.p;
+  double* rules = (double*)base;
+  double* scale = (double*)(base + off_scale);
+  AdaptItem* lists[2] = {(AdaptItem*)(base + off_l0), (AdaptItem*)(base + off_l1)};
+  int* counters = (int*)(base + off_cnt);  // next count, overflow
+  std::vector<double> hr(78, 0.0);
+  for (int k = 0; k < 13; ++k) {
+    hr[k] = gr.x13[k];
+    hr[13 + k] = gr.w13[k];
+  }
+  for (int k = 0; k < 7; ++k) {
+    hr[39 + k] = gr.x7[k];
+    hr[39 + 13 + k] = gr.w4[k];
+    hr[39 + 26 + k] = gr.w7[k];
+  }
+  std::vector<AdaptItem> init((size_t)nout_tot);
+  for (long long o = 0; o < nout_tot; ++o) init[(size_t)o] = AdaptItem{-1.0, 1.0, (int)o, 0};
+  HIP_TRY(hipMemcpyAsync(rules, hr.data(), rule_b, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(lists[0], init.data(), (size_t)nout_tot * sizeof(AdaptItem), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(counters, 0, 2 * sizeof(int), s));
+  A.L = make_gather(r, 1, 0, 0, 0, 0, 0, 0, *left, TL, nodes, nullptr, nullptr, nullptr, nullptr);
+  A.R = make_gather(r, 1, 0, 0, 0, 0, 0, 0, *right, TR, nodes, nullptr, nullptr, nullptr, nullptr);
+  A.P = P;
+  A.r = r;
+  A.kind = pi_kind;
+  A.n = n;
+  for (int u = 0; u < 4; ++u) A.unmix[u] = kUnmix[r][u];
+  A.qa = q->a;
+  A.qth = atan(q->L / q->a);
+  A.eps = eps;
+  A.min_width = 1e-12;
+  A.max_depth = 40;
+  A.scale = scale;
+  A.nout = counters;
+  A.overflow = counters + 1;
+  A.cap = (int)cap;
+  // error scales: GLK13 over the whole interval of every output
+  A.phase = 0;
+  A.nn = 13;
+  A.rule = rules;
+  A.in = lists[0];
+  A.nin = (int)nout_tot;
+  A.out = lists[1];
+  launch_adaptive(A, s);
+  HIP_TRY(hipGetLastError());
+  // generations of GL4 / GLK7 steps
+  A.phase = 1;
+  A.nn = 7;
+  A.rule = rules + 39;
+  int cur = 0, gens = 0;
+  long long nin = nout_tot, accepted = 0, evals = 13 * nout_tot;
+  while (nin > 0) {
+    if (gens > A.max_depth + 1) return fail(KQFT_ENOCONV, "adaptive bubble did not terminate");
+    HIP_TRY(hipMemsetAsync(counters, 0, sizeof(int), s));
+    A.in = lists[cur];
+    A.nin = (int)nin;
+    A.out = lists[cur ^ 1];
+    launch_adaptive(A, s);
+    HIP_TRY(hipGetLastError());
+    int hc[2];
+    HIP_TRY(hipMemcpyAsync(hc, counters, sizeof hc, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hc[1]) return fail(KQFT_ENOMEM, "adaptive work list overflow");
+    evals += 7 * nin;
+    accepted += nin - hc[0] / 6;
+    nin = hc[0];
+    cur ^= 1;
+    ++gens;
+  }
+  if (info) {
+    info->intervals = accepted;
+    info->generations = gens;
+    info->evaluations = evals;
+  }
+  return KQFT_OK;
 }
 
 int kqft_sde(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, const kqft_quad* q_bubble,

@@ -282,37 +282,18 @@ template <> __device__ inline void store_c<float2>(float2* p, double2 v) {
   *p = make_float2((float)v.x, (float)v.y);
 }
 
-// A panel: row (i, row) x column (k, m) = sum_q (Gamma_L - Gamma_L^inf)(w, v_i, v''_k)[row, q]
-// Pi_k[q, m] for i < n, Gamma_L^inf(w, v''_k) Pi_k on the border row block i = n; without
-// Pi (a.pi == nullptr) the raw left factor.  Lane l holds rows l/4 and 2 + l/4, column l%4.
-template <class T> __global__ __launch_bounds__(256) void gather_left_kernel(GatherArgs a) {
-  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int l = (int)(tid & 7);
-  long item = tid >> 3;
-  const int k = (int)(item % a.nq_pad);
-  item /= a.nq_pad;
-  const int il = (int)(item % a.cnt);
-  const int b = (int)(item / a.cnt);
-  if (b >= a.nb) return;  // whole groups: nq_pad, cnt and the block size are multiples of 8
-  const int n = a.g.n, i = a.lo + il, iw = a.iw0 + b, h = l >> 2, q4 = l & 3;
-  const size_t M = 4 * (size_t)(n + 1);
-  const size_t off0 = ((size_t)b * M + 4 * (size_t)i + h) * a.Kp + 4 * (size_t)k + q4;
-  const size_t off1 = off0 + 2 * a.Kp;
-  T* o0 = (T*)a.P0;
-  T* o1 = (T*)a.P1;
-  if (k >= a.nq) {
-    store_c(o0 + off0, czero());
-    store_c(o1 + off0, czero());
-    store_c(o0 + off1, czero());
-    store_c(o1 + off1, czero());
-    return;
-  }
-  const bool main = i < n;
-  const double w = a.nodes[iw], vq = a.qv[k];
+// Left factor of one (w_iw, v_i, v'') for the lanes of an 8-lane group: Gamma_L - Gamma_L^inf
+// at (w, v_i, v'') when main, else Gamma_L^inf(w, v''); lane l gets rows l/4 and 2 + l/4 at
+// column l%4 for both spin combinations: acc = {c0 row h, c1 row h, c0 row 2+h, c1 row 2+h}.
+template <class T>
+__device__ __forceinline__ void left_vals(const GatherArgs& a, int l, int iw, int i, bool main, double vq,
+                                          double2 acc[4]) {
+  const int n = a.g.n;
+  const double w = a.nodes[iw];
   int loc[7];
   double wt[7];
   group_locate(a, l, main, w, main ? a.nodes[i] : 0.0, vq, vq, loc, wt);
-  double2 acc[4], xy[4];
+  double2 xy[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) acc[u] = xy[u] = czero();
   const size_t nn = n, n2 = nn * nn, n3 = n2 * nn;
@@ -344,6 +325,80 @@ template <class T> __global__ __launch_bounds__(256) void gather_left_kernel(Gat
     }
     own_mix(a.coef, a.mix, l, a.r0, xy, acc);
   }
+}
+
+// Right factor of one (w_iw, v'', v'_j): Gamma_R - Gamma_R^inf at (w, v'', v'_j) when main, else
+// Gamma_R^inf(w, v''); lane l gets column l%4 of rows e = l/4 and 2 + l/4, both combinations:
+// acc = {c0 row h, c1 row h, c0 row 2+h, c1 row 2+h}.
+template <class T>
+__device__ __forceinline__ void right_vals(const GatherArgs& a, int l, int iw, int j, bool main, double vq,
+                                           double2 acc[4]) {
+  const int n = a.g.n;
+  const double w = a.nodes[iw];
+  int loc[7];
+  double wt[7];
+  group_locate(a, l, main, w, vq, main ? a.nodes[j] : 0.0, vq, loc, wt);
+  double2 xy[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = xy[u] = czero();
+  const size_t nn = n, n2 = nn * nn, n3 = n2 * nn;
+  const int i0 = loc[0];
+  const double t = wt[0];
+  if (main) {  // Gamma_R - Gamma_R^inf: own K2'(w, v'_j) + K3(w, v'', v'_j), the other channels
+    if (a.coef != 0.0) {
+      if (a.K[2]) own_tap(a.K[2] + ((size_t)iw * nn + j) * 16, n2 * 16, l, 1.0, xy);
+      if (a.K[3] && i0 >= 0) {
+        const double2* p = a.K[3] + (((size_t)iw * nn + i0) * nn + j) * 16;
+        own_tap(p, n3 * 16, l, 1.0 - t, xy);
+        own_tap(p + nn * 16, n3 * 16, l, t, xy);
+      }
+      own_mix(a.coef, a.mix, l, 0.0, xy, acc);
+    }
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+      if (a.T[d])
+        table_taps((const T*)a.T[d], n, loc[1 + 3 * d], wt[1 + 3 * d], loc[2 + 3 * d], wt[2 + 3 * d],
+                   loc[3 + 3 * d], wt[3 + 3 * d], l, acc);
+  } else {  // Gamma_R^inf(w, v'') = R + own K1(w) + K2(w, v'')
+    if (a.coef != 0.0) {
+      if (a.K[0]) own_tap(a.K[0] + (size_t)iw * 16, nn * 16, l, 1.0, xy);
+      if (a.K[1] && i0 >= 0) {
+        const double2* p = a.K[1] + ((size_t)iw * nn + i0) * 16;
+        own_tap(p, n2 * 16, l, 1.0 - t, xy);
+        own_tap(p + 16, n2 * 16, l, t, xy);
+      }
+    }
+    own_mix(a.coef, a.mix, l, a.r0, xy, acc);
+  }
+}
+
+// A panel: row (i, row) x column (k, m) = sum_q (Gamma_L - Gamma_L^inf)(w, v_i, v''_k)[row, q]
+// Pi_k[q, m] for i < n, Gamma_L^inf(w, v''_k) Pi_k on the border row block i = n; without
+// Pi (a.pi == nullptr) the raw left factor.  Lane l holds rows l/4 and 2 + l/4, column l%4.
+template <class T> __global__ __launch_bounds__(256) void gather_left_kernel(GatherArgs a) {
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int l = (int)(tid & 7);
+  long item = tid >> 3;
+  const int k = (int)(item % a.nq_pad);
+  item /= a.nq_pad;
+  const int il = (int)(item % a.cnt);
+  const int b = (int)(item / a.cnt);
+  if (b >= a.nb) return;  // whole groups: nq_pad, cnt and the block size are multiples of 8
+  const int n = a.g.n, i = a.lo + il, iw = a.iw0 + b, h = l >> 2, q4 = l & 3;
+  const size_t M = 4 * (size_t)(n + 1);
+  const size_t off0 = ((size_t)b * M + 4 * (size_t)i + h) * a.Kp + 4 * (size_t)k + q4;
+  const size_t off1 = off0 + 2 * a.Kp;
+  T* o0 = (T*)a.P0;
+  T* o1 = (T*)a.P1;
+  if (k >= a.nq) {
+    store_c(o0 + off0, czero());
+    store_c(o1 + off0, czero());
+    store_c(o0 + off1, czero());
+    store_c(o1 + off1, czero());
+    return;
+  }
+  double2 acc[4];
+  left_vals<T>(a, l, iw, i, i < n, a.qv[k], acc);
   if (a.pi != nullptr) apply_pi(a.pi + ((size_t)b * a.nq + k) * 16, q4, acc);  // (Gamma_L . Pi_k)
   store_c(o0 + off0, acc[0]);
   store_c(o1 + off0, acc[1]);
@@ -376,47 +431,239 @@ template <class T> __global__ __launch_bounds__(256) void gather_right_kernel(Ga
     store_c(o1 + off1, czero());
     return;
   }
-  const bool main = j < n;
-  const double w = a.nodes[iw], vq = a.qv[k];
-  int loc[7];
-  double wt[7];
-  group_locate(a, l, main, w, vq, main ? a.nodes[j] : 0.0, vq, loc, wt);
-  double2 acc[4], xy[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) acc[u] = xy[u] = czero();
-  const size_t nn = n, n2 = nn * nn, n3 = n2 * nn;
-  const int i0 = loc[0];
-  const double t = wt[0];
-  if (main) {  // Gamma_R - Gamma_R^inf: own K2'(w, v'_j) + K3(w, v'', v'_j), the other channels
-    if (a.coef != 0.0) {
-      if (a.K[2]) own_tap(a.K[2] + ((size_t)iw * nn + j) * 16, n2 * 16, l, 1.0, xy);
-      if (a.K[3] && i0 >= 0) {
-        const double2* p = a.K[3] + (((size_t)iw * nn + i0) * nn + j) * 16;
-        own_tap(p, n3 * 16, l, 1.0 - t, xy);
-        own_tap(p + nn * 16, n3 * 16, l, t, xy);
-      }
-      own_mix(a.coef, a.mix, l, 0.0, xy, acc);
-    }
-#pragma unroll
-    for (int d = 0; d < 2; ++d)
-      if (a.T[d])
-        table_taps((const T*)a.T[d], n, loc[1 + 3 * d], wt[1 + 3 * d], loc[2 + 3 * d], wt[2 + 3 * d],
-                   loc[3 + 3 * d], wt[3 + 3 * d], l, acc);
-  } else {  // Gamma_R^inf(w, v'') = R + own K1(w) + K2(w, v'')
-    if (a.coef != 0.0) {
-      if (a.K[0]) own_tap(a.K[0] + (size_t)iw * 16, nn * 16, l, 1.0, xy);
-      if (a.K[1] && i0 >= 0) {
-        const double2* p = a.K[1] + ((size_t)iw * nn + i0) * 16;
-        own_tap(p, n2 * 16, l, 1.0 - t, xy);
-        own_tap(p + 16, n2 * 16, l, t, xy);
-      }
-    }
-    own_mix(a.coef, a.mix, l, a.r0, xy, acc);
-  }
+  double2 acc[4];
+  right_vals<T>(a, l, iw, j, j < n, a.qv[k], acc);
   store_c(o0 + off0, acc[0]);
   store_c(o1 + off0, acc[1]);
   store_c(o0 + off1, acc[2]);
   store_c(o1 + off1, acc[3]);
+}
+
+// ======================================================================== adaptive bubble
+// Gauss-Lobatto-Kronrod integration per output (Sec. Frequency integration), breadth first:
+// every work item (output o, interval [ya, yb] of the auxiliary variable y of the tangent
+// map v'' = qa tan(y qth)) is one wavefront; its 8-lane groups evaluate the rule's nodes
+// (left factor . Pi, right factor, the 4x4 product per spin combination, as the panels and
+// the GEMM do for fixed nodes), the groups are summed, and the combinations are unmixed to
+// X, Y.  Phase 0 stores the error scale of the output (GLK13 on the item's interval);
+// phase 1 compares GL4 with GLK7 and either adds GLK7 into the outputs (FP64 atomics) or
+// appends the six subintervals between the GLK7 nodes to the next work list.
+
+__device__ inline double2 sel4(const double2 g[4], int k) {
+  return k == 0 ? g[0] : (k == 1 ? g[1] : (k == 2 ? g[2] : g[3]));
+}
+
+// Pi_r[e][q4] (e = 0..3) at (w, v'') times 1/(2 pi i), the column this lane multiplies with
+__device__ inline void pi_column(const DProp& P, int r, int kind, double w, double vq, int q4, double2 col[4]) {
+  double f3, f4;
+  if (r == 1) {
+    f3 = 0.5 * w + vq;
+    f4 = 0.5 * w - vq;
+  } else {
+    f3 = vq + 0.5 * w;
+    f4 = vq - 0.5 * w;
+  }
+  double2 g3[4], g4[4], s3[4], s4[4];
+  propagator(P, 0, f3, g3);
+  propagator(P, 0, f4, g4);
+  if (kind == 1) {
+    propagator(P, 1, f3, s3);
+    propagator(P, 1, f4, s4);
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    int a3, a3p, a4, a4p;
+    if (r == 0) {  // rows (a3, a4'), columns (a3', a4)
+      a3 = e >> 1;
+      a4p = e & 1;
+      a3p = q4 >> 1;
+      a4 = q4 & 1;
+    } else if (r == 1) {  // rows (a3, a4), columns (a3', a4')
+      a3 = e >> 1;
+      a4 = e & 1;
+      a3p = q4 >> 1;
+      a4p = q4 & 1;
+    } else {  // rows (a4', a3), columns (a3', a4)
+      a4p = e >> 1;
+      a3 = e & 1;
+      a3p = q4 >> 1;
+      a4 = q4 & 1;
+    }
+    const int i3 = 2 * a3 + a3p, i4 = 2 * a4 + a4p;
+    double2 v = cmul(sel4(g3, i3), sel4(g4, i4));
+    if (kind == 1) v = cadd(cmul(sel4(s3, i3), sel4(g4, i4)), cmul(sel4(g3, i3), sel4(s4, i4)));
+    col[e] = make_double2(v.y * (0.5 / M_PI), -v.x * (0.5 / M_PI));  // v / (2 pi i)
+  }
+}
+
+__device__ inline void apply_pi_col(const double2 col[4], double2 acc[4]) {
+  double2 s[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) s[u] = czero();
+  pi_step<0>(acc, col[0], s);
+  pi_step<1>(acc, col[1], s);
+  pi_step<2>(acc, col[2], s);
+  pi_step<3>(acc, col[3], s);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = s[u];
+}
+
+__device__ inline double cabs2(double2 z) { return hypot(z.x, z.y); }
+
+__global__ __launch_bounds__(256) void adaptive_kernel(AdaptArgs a) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int item = blockIdx.x * 4 + wave;
+  if (item >= a.nin) return;  // whole wavefronts leave together; no block-level barrier follows
+  const int grp = lane >> 3, l = lane & 7, h = l >> 2, q4 = l & 3;
+  const AdaptItem it = a.in[item];
+  int cls = 0, rel = it.o;
+  for (int c = 0; c < 4; ++c)
+    if (a.ccount[c] > 0 && it.o >= a.cstart[c] && it.o < a.cstart[c] + a.ccount[c]) {
+      cls = c;
+      rel = it.o - a.cstart[c];
+    }
+  const int n = a.n;
+  int iw, i = 0, j = 0;
+  if (cls == 0) {
+    iw = rel;
+  } else if (cls == 1) {
+    iw = rel / n;
+    i = rel % n;
+  } else if (cls == 2) {
+    iw = rel / n;
+    j = rel % n;
+  } else {
+    iw = rel / (n * n);
+    i = (rel / n) % n;
+    j = rel % n;
+  }
+  const bool mainl = cls == 1 || cls == 3, mainr = cls == 2 || cls == 3;
+  const double w = a.L.nodes[iw];
+  const double m = 0.5 * (it.ya + it.yb), hw = 0.5 * (it.yb - it.ya);
+  double2 Ia[4], Ib[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) Ia[u] = Ib[u] = czero();
+  double fmx = 0.0;
+  for (int base = 0; base < a.nn; base += 8) {
+    const int node = base + grp;
+    if (node >= a.nn) continue;  // uniform over the 8-lane group
+    const double y = m + hw * a.rule[node];
+    const double vq = a.qa * tan(y * a.qth);
+    const double cy = cos(y * a.qth);
+    const double jac = a.qa * a.qth / (cy * cy);
+    double2 lv[4], rv[4], col[4];
+    left_vals<double2>(a.L, l, iw, i, mainl, vq, lv);
+    pi_column(a.P, a.r, a.kind, w, vq, q4, col);
+    apply_pi_col(col, lv);
+    right_vals<double2>(a.R, l, iw, j, mainr, vq, rv);
+    double2 C[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) C[u] = czero();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {  // C[row, q4] += (L Pi)[row, e] R[e, q4], per combination
+      const int sl = 4 * h + e, sr = 4 * (e & 1) + q4;
+      double2 lp[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) lp[u] = make_double2(__shfl(lv[u].x, sl, 8), __shfl(lv[u].y, sl, 8));
+      const double2 ra = make_double2(__shfl(rv[e < 2 ? 0 : 2].x, sr, 8), __shfl(rv[e < 2 ? 0 : 2].y, sr, 8));
+      const double2 rb = make_double2(__shfl(rv[e < 2 ? 1 : 3].x, sr, 8), __shfl(rv[e < 2 ? 1 : 3].y, sr, 8));
+      C[0] = cadd(C[0], cmul(lp[0], ra));
+      C[1] = cadd(C[1], cmul(lp[1], rb));
+      C[2] = cadd(C[2], cmul(lp[2], ra));
+      C[3] = cadd(C[3], cmul(lp[3], rb));
+    }
+    const double fa = hw * jac * a.rule[13 + node], fb = hw * jac * a.rule[26 + node];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      Ia[u] = cadd(Ia[u], cscale(fa, C[u]));
+      Ib[u] = cadd(Ib[u], cscale(fb, C[u]));
+    }
+    // size of the integrand (times the Jacobian) in X, Y, for a vanishing error scale
+    const double2 X0 = cadd(cscale(a.unmix[0], C[0]), cscale(a.unmix[1], C[1]));
+    const double2 Y0 = cadd(cscale(a.unmix[2], C[0]), cscale(a.unmix[3], C[1]));
+    const double2 X1 = cadd(cscale(a.unmix[0], C[2]), cscale(a.unmix[1], C[3]));
+    const double2 Y1 = cadd(cscale(a.unmix[2], C[2]), cscale(a.unmix[3], C[3]));
+    fmx = fmax(fmx, jac * fmax(fmax(cabs2(X0), cabs2(Y0)), fmax(cabs2(X1), cabs2(Y1))));
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int off = 8; off < 64; off <<= 1) {
+      Ia[u].x += __shfl_xor(Ia[u].x, off);
+      Ia[u].y += __shfl_xor(Ia[u].y, off);
+      Ib[u].x += __shfl_xor(Ib[u].x, off);
+      Ib[u].y += __shfl_xor(Ib[u].y, off);
+    }
+  // X, Y of this lane's two flat indices f = 4h + q4 (row h) and 8 + 4h + q4 (row 2 + h)
+  double2 Xa[2], Ya[2], Xb[2], Yb[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    Xa[t] = cadd(cscale(a.unmix[0], Ia[2 * t]), cscale(a.unmix[1], Ia[2 * t + 1]));
+    Ya[t] = cadd(cscale(a.unmix[2], Ia[2 * t]), cscale(a.unmix[3], Ia[2 * t + 1]));
+    Xb[t] = cadd(cscale(a.unmix[0], Ib[2 * t]), cscale(a.unmix[1], Ib[2 * t + 1]));
+    Yb[t] = cadd(cscale(a.unmix[2], Ib[2 * t]), cscale(a.unmix[3], Ib[2 * t + 1]));
+  }
+  if (a.phase == 0) {
+    double sc = fmax(fmax(cabs2(Xa[0]), cabs2(Ya[0])), fmax(cabs2(Xa[1]), cabs2(Ya[1])));
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      sc = fmax(sc, __shfl_xor(sc, off));
+      fmx = fmax(fmx, __shfl_xor(fmx, off));
+    }
+    if (sc == 0.0) sc = (it.yb - it.ya) * fmx;
+    if (sc == 0.0) sc = 1.0;
+    if (lane == 0) a.scale[it.o] = sc;
+    return;
+  }
+  double err = fmax(fmax(cabs2(csub(Xb[0], Xa[0])), cabs2(csub(Yb[0], Ya[0]))),
+                    fmax(cabs2(csub(Xb[1], Xa[1])), cabs2(csub(Yb[1], Ya[1]))));
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) err = fmax(err, __shfl_xor(err, off));
+  const bool accept = err <= a.eps * a.scale[it.o] || it.yb - it.ya < a.min_width || it.depth >= a.max_depth;
+  if (accept) {
+    if (lane < 8) {
+      const size_t nn = n;
+      size_t base;
+      if (cls == 0)
+        base = (size_t)iw;
+      else if (cls == 1)
+        base = (size_t)iw * nn + i;
+      else if (cls == 2)
+        base = (size_t)iw * nn + j;
+      else
+        base = ((size_t)iw * nn + i) * nn + j;
+      const size_t sstride = cls == 0 ? nn : (cls == 3 ? nn * nn * nn : nn * nn);
+      double2* out = cls == 0 ? a.K[0] : (cls == 1 ? a.K[1] : (cls == 2 ? a.K[2] : a.K[3]));
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const size_t f = 8 * t + 4 * h + q4;
+        double* px = (double*)(out + base * 16 + f);
+        double* py = (double*)(out + (sstride + base) * 16 + f);
+        atomicAdd(px, Xb[t].x);
+        atomicAdd(px + 1, Xb[t].y);
+        atomicAdd(py, Yb[t].x);
+        atomicAdd(py + 1, Yb[t].y);
+      }
+    }
+  } else if (lane == 0) {
+    const int pos = atomicAdd(a.nout, 6);
+    if (pos + 6 <= a.cap) {
+      double yk[7];
+#pragma unroll
+      for (int k = 0; k < 7; ++k) yk[k] = m + hw * a.rule[k];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        AdaptItem c;
+        c.ya = yk[k];
+        c.yb = yk[k + 1];
+        c.o = it.o;
+        c.depth = it.depth + 1;
+        a.out[pos + k] = c;
+      }
+    } else {
+      atomicMax(a.overflow, 1);
+    }
+  }
 }
 
 // ======================================================================== epilogue
@@ -1808,6 +2055,9 @@ void launch_axpby(double2* out, double a, const double2* x, double b, const doub
 void launch_occupation(const DProp& P, const double* nodes, const double* weights, int nq, double* partial, int nblk,
                        hipStream_t s) {
   hipLaunchKernelGGL(occupation_kernel, dim3(nblk), dim3(256), 0, s, P, nodes, weights, nq, partial);
+}
+void launch_adaptive(const AdaptArgs& a, hipStream_t s) {
+  if (a.nin > 0) hipLaunchKernelGGL(adaptive_kernel, dim3((a.nin + 3) / 4), dim3(256), 0, s, a);
 }
 void launch_dot(const double2* a, const double2* b, size_t count, double* partial, int nblk, hipStream_t s) {
   hipLaunchKernelGGL(dot_kernel, dim3(nblk), dim3(256), 0, s, a, b, count, partial);

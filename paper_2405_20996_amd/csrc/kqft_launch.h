@@ -197,6 +197,33 @@ struct LinComb {
   size_t count;
 };
 void launch_lincomb(const LinComb& a, hipStream_t s);
+// adaptive bubble: one work item = one output and one interval of the auxiliary variable
+struct AdaptItem {
+  double ya, yb;
+  int o, depth;
+};
+struct AdaptArgs {
+  GatherArgs L, R;  // left / right factors (FP64 tables; panel fields unused)
+  DProp P;
+  int r, kind, n;
+  int phase;                 // 0: error scale from the rule's nodes and weights a; 1: a (GL4) vs b (GLK7)
+  int nn;                    // nodes of the rule
+  const double* rule;        // device: nodes [13], weights a [13], weights b [13]
+  int cstart[4], ccount[4];  // output ranges of K1, K2, K2', K3 (count 0: not computed)
+  double unmix[4];           // combinations -> X, Y with the channel prefactor
+  double qa, qth;            // v'' = qa tan(y qth), y in [-1, 1]
+  double eps, min_width;
+  int max_depth;
+  const AdaptItem* in;
+  int nin;
+  AdaptItem* out;  // next work list
+  int* nout;
+  int cap;
+  int* overflow;
+  double* scale;     // per output
+  double2* K[4];     // outputs, accumulated
+};
+void launch_adaptive(const AdaptArgs& a, hipStream_t s);
 // per-block partial sums of w_j tanh(v_j/2T) Im G^R(v_j) (P.eps is the level)
 void launch_occupation(const DProp& P, const double* nodes, const double* weights, int nq, double* partial, int nblk,
                        hipStream_t s);

@@ -61,6 +61,10 @@ class KqftParquetOpts(C.Structure):
                 ("hartree", C.c_int), ("eps_d", C.c_double), ("q_hartree", KqftQuad), ("hartree_tol", C.c_double)]
 
 
+class KqftAdaptInfo(C.Structure):
+    _fields_ = [("intervals", C.c_longlong), ("generations", C.c_int), ("evaluations", C.c_longlong)]
+
+
 class KqftFlowInfo(C.Structure):
     _fields_ = [("accepted", C.c_int), ("rejected", C.c_int), ("rhs_evaluations", C.c_int),
                 ("se_iterations", C.c_int)]
@@ -111,6 +115,9 @@ def lib():
                                         P(KqftChout), C.c_void_p, C.c_void_p, P(KqftFlowInfo), C.c_void_p]
         _lib.kqft_parquet_iteration.argtypes = [C.c_void_p, P(KqftVertex), P(KqftPropagator), P(KqftQuad),
                                                 P(KqftQuad), P(KqftOpts), P(KqftChout), C.c_void_p, C.c_void_p]
+        _lib.kqft_bubble_adaptive.argtypes = [C.c_void_p, C.c_int, P(KqftVertex), P(KqftVertex), P(KqftPropagator),
+                                              C.c_int, P(KqftQuad), C.c_double, P(KqftOpts), P(KqftChout),
+                                              P(KqftAdaptInfo), C.c_void_p]
         _lib.kqft_hartree.argtypes = [C.c_void_p, C.c_double, C.c_double, P(KqftPropagator), P(KqftQuad), C.c_int,
                                       C.c_double, P(C.c_double), P(C.c_int), C.c_void_p]
         _lib.kqft_parquet_solve.argtypes = [C.c_void_p, P(KqftGrid), C.c_double, C.c_double, C.c_double,
@@ -380,6 +387,22 @@ def parquet_iteration(gamma: Vertex, G: Propagator, q_bubble: Quad, q_loop: Quad
                                         C.byref(_opts(precision, KALL, 0, 0)), D, C.c_void_p(sigma.data_ptr()),
                                         _stream(stream)))
     return outs, sigma
+
+
+def bubble_adaptive(channel: int, left: Vertex, right: Vertex, G: Propagator, q: Quad, eps: float = 1e-5,
+                    pi_kind: int = PI_GG, class_mask: int = KALL, out: Optional[Channel] = None, stream=None):
+    """B_channel(left, right) with adaptive Gauss-Lobatto-Kronrod integration per output over q's
+    finite tangent map; returns (Channel of outputs, info dict)."""
+    n = left.grid.n
+    if out is None:
+        out = alloc_channel(n, zero=False)
+    lc, rc_, gc, qc = left.c(), right.c(), G.c(), q.c()
+    co = _chout_opt(out, n)
+    inf = KqftAdaptInfo()
+    _check(lib().kqft_bubble_adaptive(ctx(), channel, C.byref(lc), C.byref(rc_), C.byref(gc), pi_kind, C.byref(qc),
+                                      C.c_double(eps), C.byref(_opts(FP64, class_mask, 0, 0)), C.byref(co),
+                                      C.byref(inf), _stream(stream)))
+    return out, {"intervals": inf.intervals, "generations": inf.generations, "evaluations": inf.evaluations}
 
 
 def hartree(U: float, eps_d: float, G: Propagator, q: Quad, self_consistent: bool = True, tol: float = 1e-12,

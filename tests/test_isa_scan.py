@@ -1,6 +1,6 @@
 """CPU check of the gfx950 code generated from the HIP sources: no scalar-cache writes
 (scalar stores, scalar atomics, scalar cache write-back), no packed FP32 VALU ops, and
-FP64 atomics only as vector global atomics."""
+atomics only as vector global atomics (FP64 ones as native adds)."""
 import os
 import re
 import subprocess
@@ -31,6 +31,8 @@ def test_no_packed_fp32(isa):
     assert not re.search(r"v_pk_(fma|add|mul)_f32", isa)
 
 
-def test_fp64_atomics_are_vector_global(isa):
+def test_atomics_are_vector_global(isa):
+    """FP64 atomics are native vector global adds (no compare-and-swap loops); the integer
+    atomics of the adaptive work list are vector global too."""
     ops = set(re.findall(r"\b((?:global|flat|buffer|ds)_atomic_\w+)", isa))
-    assert ops <= {"global_atomic_add_f64"}, ops
+    assert ops <= {"global_atomic_add_f64", "global_atomic_add", "global_atomic_smax"}, ops
