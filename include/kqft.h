@@ -243,10 +243,12 @@ typedef struct {
  * the error scale max|I_s| ((b - a) max|F| at its nodes if that vanishes, else 1); an
  * interval is accepted with its GLK7 value when max|GLK7 - GL4| <= eps max|I_s|, narrower
  * than 1e-12 or 40 subdivisions deep, else split at the seven GLK7 nodes into six.  The work
- * proceeds breadth first over all outputs (one wavefront per output interval).  FP64; outputs
+ * proceeds breadth first over batches of up to 8192 outputs (one wavefront per output
+ * interval, one synchronisation per generation).  FP64; outputs
  * overwritten for the classes of opts->class_mask (precision, beta, omega_batch ignored).
- * info (host, or NULL).  Errors as kqft_bubble, KQFT_ENOMEM when the work list exceeds
- * max(2^20, 48 x outputs) intervals, KQFT_ENOCONV when the refinement does not end.
+ * info (host, or NULL).  Errors as kqft_bubble, KQFT_ENOMEM when one generation of a batch
+ * exceeds 2^24 intervals (two such lists of 24 bytes per interval are held), KQFT_ENOCONV
+ * when the refinement does not end.
  */
 int kqft_bubble_adaptive(kqft_ctx* ctx, int channel, const kqft_vertex* left, const kqft_vertex* right,
                          const kqft_propagator* G, int pi_kind, const kqft_quad* q, double eps, const kqft_opts* opts,

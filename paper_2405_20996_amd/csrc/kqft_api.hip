@@ -1112,8 +1112,10 @@ int kqft_bubble_adaptive(kqft_ctx* ctx, int channel, const kqft_vertex* left, co
     if (msk & bits[c]) HIP_TRY(hipMemsetAsync(outs[c], 0, 2 * (size_t)cnts[c] * 16 * sizeof(double2), s));
   }
   if (nout_tot > (1LL << 28)) return fail(KQFT_ESHAPE, "too many outputs for the adaptive bubble");
-  const long long cap = std::max<long long>(1LL << 20, 48 * nout_tot);
-  if (cap > (1LL << 30)) return fail(KQFT_ESHAPE, "adaptive work list too large");
+  // outputs in batches of at most 8192, each refined to the end before the next: one
+  // generation's list then holds at most 2048 intervals per output on average
+  const long long cap = 1LL << 24;
+  const long long bsz = std::min<long long>(nout_tot, 8192);
   // device memory: two rules (78 doubles), scale per output, two work lists, counters
   const size_t rule_b = 2 * 39 * sizeof(double), scale_b = (size_t)nout_tot * sizeof(double);
   const size_t list_b = (size_t)cap * sizeof(AdaptItem);
@@ -1135,10 +1137,7 @@ int kqft_bubble_adaptive(kqft_ctx* ctx, int channel, const kqft_vertex* left, co
     hr[39 + 13 + k] = gr.w4[k];
     hr[39 + 26 + k] = gr.w7[k];
   }
-  std::vector<AdaptItem> init((size_t)nout_tot);
-  for (long long o = 0; o < nout_tot; ++o) init[(size_t)o] = AdaptItem{-1.0, 1.0, (int)o, 0};
   HIP_TRY(hipMemcpyAsync(rules, hr.data(), rule_b, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(lists[0], init.data(), (size_t)nout_tot * sizeof(AdaptItem), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemsetAsync(counters, 0, 2 * sizeof(int), s));
   A.L = make_gather(r, 1, 0, 0, 0, 0, 0, 0, *left, TL, nodes, nullptr, nullptr, nullptr, nullptr);
   A.R = make_gather(r, 1, 0, 0, 0, 0, 0, 0, *right, TR, nodes, nullptr, nullptr, nullptr, nullptr);
@@ -1156,42 +1155,52 @@ int kqft_bubble_adaptive(kqft_ctx* ctx, int channel, const kqft_vertex* left, co
   A.nout = counters;
   A.overflow = counters + 1;
   A.cap = (int)cap;
-  // error scales: GLK13 over the whole interval of every output
-  A.phase = 0;
-  A.nn = 13;
-  A.rule = rules;
-  A.in = lists[0];
-  A.nin = (int)nout_tot;
-  A.out = lists[1];
-  launch_adaptive(A, s);
-  HIP_TRY(hipGetLastError());
-  // generations of GL4 / GLK7 steps
-  A.phase = 1;
-  A.nn = 7;
-  A.rule = rules + 39;
-  int cur = 0, gens = 0;
-  long long nin = nout_tot, accepted = 0, evals = 13 * nout_tot;
-  while (nin > 0) {
-    if (gens > A.max_depth + 1) return fail(KQFT_ENOCONV, "adaptive bubble did not terminate");
-    HIP_TRY(hipMemsetAsync(counters, 0, sizeof(int), s));
-    A.in = lists[cur];
-    A.nin = (int)nin;
-    A.out = lists[cur ^ 1];
+  int gens_max = 0;
+  long long accepted = 0, evals = 0;
+  std::vector<AdaptItem> init((size_t)bsz);
+  for (long long o0 = 0; o0 < nout_tot; o0 += bsz) {
+    const long long nb = std::min(bsz, nout_tot - o0);
+    for (long long o = 0; o < nb; ++o) init[(size_t)o] = AdaptItem{-1.0, 1.0, (int)(o0 + o), 0};
+    HIP_TRY(hipMemcpyAsync(lists[0], init.data(), (size_t)nb * sizeof(AdaptItem), hipMemcpyHostToDevice, s));
+    // error scales: GLK13 over the whole interval of every output of the batch
+    A.phase = 0;
+    A.nn = 13;
+    A.rule = rules;
+    A.in = lists[0];
+    A.nin = (int)nb;
+    A.out = lists[1];
     launch_adaptive(A, s);
     HIP_TRY(hipGetLastError());
-    int hc[2];
-    HIP_TRY(hipMemcpyAsync(hc, counters, sizeof hc, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (hc[1]) return fail(KQFT_ENOMEM, "adaptive work list overflow");
-    evals += 7 * nin;
-    accepted += nin - hc[0] / 6;
-    nin = hc[0];
-    cur ^= 1;
-    ++gens;
+    evals += 13 * nb;
+    // generations of GL4 / GLK7 steps
+    A.phase = 1;
+    A.nn = 7;
+    A.rule = rules + 39;
+    int cur = 0, gens = 0;
+    long long nin = nb;
+    while (nin > 0) {
+      if (gens > A.max_depth + 1) return fail(KQFT_ENOCONV, "adaptive bubble did not terminate");
+      HIP_TRY(hipMemsetAsync(counters, 0, sizeof(int), s));
+      A.in = lists[cur];
+      A.nin = (int)nin;
+      A.out = lists[cur ^ 1];
+      launch_adaptive(A, s);
+      HIP_TRY(hipGetLastError());
+      int hc[2];
+      HIP_TRY(hipMemcpyAsync(hc, counters, sizeof hc, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (hc[1]) return fail(KQFT_ENOMEM, "adaptive work list overflow");
+      evals += 7 * nin;
+      accepted += nin - hc[0] / 6;
+      nin = hc[0];
+      cur ^= 1;
+      ++gens;
+    }
+    gens_max = std::max(gens_max, gens);
   }
   if (info) {
     info->intervals = accepted;
-    info->generations = gens;
+    info->generations = gens_max;
     info->evaluations = evals;
   }
   return KQFT_OK;

