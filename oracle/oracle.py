@@ -569,6 +569,29 @@ def dual_vertex(V: Vertex, dr0: float = 0.0) -> Vertex:
     return Vertex(V.grid, V.r0, chans, dr0=dr0)
 
 
+# ------------------------------------------------------------------ crossed closure
+def t_closure(X: Vertex, P: Prop, q: Quad) -> np.ndarray:
+    """The 4-point object X closed with G between its legs 2' and 1 (external legs 1' and 2),
+    summed literally over the closed legs' Keldysh indices and spins (external spins up):
+    out[i][2 a1' + a2] = sum_j w_j/(2 pi i) sum_{a1, a2', s} X(1' = (a1', up, v_i),
+    2' = (a2', s, v_j) | 1 = (a1, s, v_j), 2 = (a2, up, v_i)) G^{a1|a2'}(v_j)."""
+    g = X.grid
+    v = g.nodes()
+    vq, wq = q.nodes_weights()
+    Gm = propagator(P, vq)
+    out = np.zeros((g.n, 4), complex)
+    idx = [(j, a1p, a2, a2p, a1, s) for j in range(len(vq)) for a1p in range(2) for a2 in range(2)
+           for a2p in range(2) for a1 in range(2) for s in range(2)]
+    for i in range(g.n):
+        al = np.array([[a1p, a2p, a1, a2] for (j, a1p, a2, a2p, a1, s) in idx])
+        sg = np.array([[0, s, s, 0] for (j, a1p, a2, a2p, a1, s) in idx])
+        nu = np.array([[v[i], vq[j], vq[j], v[i]] for (j, a1p, a2, a2p, a1, s) in idx])
+        vals = vertex_legs(X, al, sg, nu)
+        for val, (j, a1p, a2, a2p, a1, s) in zip(vals, idx):
+            out[i, 2 * a1p + a2] += wq[j] / (2j * np.pi) * val * Gm[j, a1, a2p]
+    return out
+
+
 # ------------------------------------------------------------------ Hartree term
 def occupation(E: float, Delta: float, T: float, q: Quad, grid: Optional[Grid] = None,
                sigma: Optional[np.ndarray] = None) -> float:

@@ -61,3 +61,26 @@ def test_anderson_accelerates_the_parquet_solver():
     _, _, And = O.parquet_solve(g, 1.0, 1.0, 0.1, q, q, alpha=0.5, iterations=8, depth=3)
     assert lin[:2] == And[:2]  # the first update has no history
     assert And[-1] < 0.2 * lin[-1]
+
+
+# ---------------------------------------------------------------- crossing of a closed bubble
+def _pt2_vertex(n, nq, U=1.0):
+    g, q, P = O.Grid(n), O.Quad(nq), O.Prop(1.0, 0.1)
+    k1 = O.pt2_k1(g, U, P, q)
+    z2, z3 = np.zeros((2, n, n, 16), complex), np.zeros((2, n, n, n, 16), complex)
+    return O.Vertex(g, U, [O.Channel(1.0, k1[r], z2, z2, z3) for r in range(3)]), g, q, P
+
+
+def test_crossed_closure_of_t_bubble_is_the_loop_of_the_mirrored_a_bubble():
+    """For a crossing-symmetric vertex (Gamma_0 plus the PT2 channels), the t bubble B_t(Gamma_0,
+    Gamma) closed between legs 2' and 1 (summed literally over Keldysh indices and spins) is
+    minus the loop of the a bubble B_a(Gamma, Gamma_0), exactly: the crossing 1 <-> 2 maps the
+    one onto the other in the discrete scheme (one grid for every channel)."""
+    V, g, q, P = _pt2_vertex(9, 31)
+    B = O.bare(g, 1.0)
+    bt = O.bubble(2, B, V, P, q)
+    ct = O.t_closure(O.Vertex(g, 0.0, [O.Channel(0.0), O.Channel(0.0), O.Channel(1.0, bt.K1, bt.K2, bt.K2p, bt.K3)]),
+                     P, q)
+    bm = O.bubble(0, V, B, P, q)
+    lm = O.loop(O.Vertex(g, 0.0, [O.Channel(1.0, bm.K1, bm.K2, bm.K2p, bm.K3), O.Channel(0.0), O.Channel(0.0)]), P, q)
+    assert np.abs(ct + lm).max() < 1e-13 * np.abs(ct).max()
