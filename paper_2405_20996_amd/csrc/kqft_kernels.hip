@@ -7,8 +7,13 @@
 //   zgemm_f64 / _f32   C = A . B per (w, spin combination) on MFMA, bordered epilogue
 //                      that de-diagonalises the spin combinations into X/Y and writes
 //                      K3 (main block), K2 (last column), K2' (last row), K1 (corner)
+//   adaptive_kernel    adaptive Gauss-Lobatto-Kronrod bubble, one wavefront per output interval
 //   loop_kernel        Schwinger-Dyson loop reduction
+//   vloop_kernel       loop of a full vertex (all channels through tables) with G, S or G s G
 //   chi_kernel         a-channel susceptibility double sum (table gathers + Pi contractions)
+//   parquet / flow helpers: sigma_split, maxdiff, axpby, lincomb, errnorm, dot, mix,
+//                      occupation (Hartree term)
+//   adjoint kernels    reverse pass of the bubble and of the Schwinger-Dyson loop
 //
 // The bubble (Eq. B_a and the BSEs of the paper) is written as one Keldysh-blocked
 // complex matrix product per transfer frequency: the 4x4 Keldysh matrices of the
