@@ -19,7 +19,7 @@ import pytest
 import torch
 
 import oracle as O
-from workload import C4_POINTS, seed_noise
+from workload import MULTILOOP_POINTS, seed_noise
 
 pytestmark = pytest.mark.gpu
 
@@ -69,7 +69,7 @@ def test_multiloop_batch_twelve_points():
     K = _K()
     noises = {}
     flop, seconds = 0.0, 0.0
-    for idx, (U, T, n) in enumerate(C4_POINTS):
+    for idx, (U, T, n) in enumerate(MULTILOOP_POINTS):
         nq = 10 * n - 9
         if n not in noises:
             noises[n] = seed_noise(n, 0)

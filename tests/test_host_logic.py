@@ -5,7 +5,7 @@ import sys
 
 import numpy as np
 
-from workload import CONFIGS, C4_POINTS, class_shape, complex_noise, random_channel, seed_noise
+from workload import CONFIGS, MULTILOOP_POINTS, class_shape, complex_noise, random_channel, seed_noise
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -33,9 +33,9 @@ def test_complex_noise_layout_matches_pairs_of_normals():
 
 
 def test_workloads():
-    c3 = CONFIGS["c3_bubble_a_n201"]
-    assert (c3.N, c3.Nq, c3.U, c3.T) == (201, 2001, 1.0, 0.1)
-    assert len(C4_POINTS) == 12 and {p[2] for p in C4_POINTS} == {51, 101, 151, 201}
+    w = CONFIGS["bubble_a_n201"]
+    assert (w.N, w.Nq, w.U, w.T) == (201, 2001, 1.0, 0.1)
+    assert len(MULTILOOP_POINTS) == 12 and {p[2] for p in MULTILOOP_POINTS} == {51, 101, 151, 201}
     rc = random_channel(3, 1)
     assert set(rc) == {"K1", "K2", "K2p", "K3"}
 

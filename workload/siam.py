@@ -35,15 +35,15 @@ class Workload:
 # for the parts the description leaves open (grid scale a = Delta, L = 20,
 # T = 0.1 where unstated).
 CONFIGS = {
-    "c1_bubble_a_n31": Workload("c1_bubble_a_n31", 31, 201, U=1.0, T=0.1),
-    "c2_bubbles_sde_n101": Workload("c2_bubbles_sde_n101", 101, 1001, U=1.0, T=0.05, channels=("a", "p", "t")),
-    "c3_bubble_a_n201": Workload("c3_bubble_a_n201", 201, 2001, U=1.0, T=0.1),
-    "c5_adjoint_n151": Workload("c5_adjoint_n151", 151, 1501, U=1.0, T=0.1),
+    "bubble_a_n31": Workload("bubble_a_n31", 31, 201, U=1.0, T=0.1),
+    "bubbles_sde_n101": Workload("bubbles_sde_n101", 101, 1001, U=1.0, T=0.05, channels=("a", "p", "t")),
+    "bubble_a_n201": Workload("bubble_a_n201", 201, 2001, U=1.0, T=0.1),
+    "adjoint_n151": Workload("adjoint_n151", 151, 1501, U=1.0, T=0.1),
 }
 C2_U_VALUES = (0.5, 1.0, 2.0)
 # twelve uneven parameter points of the batched multiloop workload:
 # U in {0.25, 0.5, 1, 1.5, 2, 3} (outer) x T in {0.01, 0.1}; N cycles through 51..201, Nq = 10N - 9
-C4_POINTS = [(U, T, [51, 101, 151, 201][i % 4]) for i, (U, T) in
+MULTILOOP_POINTS = [(U, T, [51, 101, 151, 201][i % 4]) for i, (U, T) in
              enumerate([(U, T) for U in (0.25, 0.5, 1.0, 1.5, 2.0, 3.0) for T in (0.01, 0.1)])]
 
 
