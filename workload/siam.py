@@ -40,7 +40,7 @@ CONFIGS = {
     "bubble_a_n201": Workload("bubble_a_n201", 201, 2001, U=1.0, T=0.1),
     "adjoint_n151": Workload("adjoint_n151", 151, 1501, U=1.0, T=0.1),
 }
-C2_U_VALUES = (0.5, 1.0, 2.0)
+THREE_CHANNEL_U_VALUES = (0.5, 1.0, 2.0)
 # twelve uneven parameter points of the batched multiloop workload:
 # U in {0.25, 0.5, 1, 1.5, 2, 3} (outer) x T in {0.01, 0.1}; N cycles through 51..201, Nq = 10N - 9
 MULTILOOP_POINTS = [(U, T, [51, 101, 151, 201][i % 4]) for i, (U, T) in
