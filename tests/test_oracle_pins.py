@@ -691,3 +691,23 @@ def test_flow_self_energy_matches_sde_pt2_up_to_discretisation():
         s2 = O.sde(O.bare(g, 0.05), O.Prop(1.0, T), q, q)
         devs.append(np.abs(sig - s2).max() / np.abs(s2).max())
     assert devs[0] < 0.1 and devs[1] < 0.75 * devs[0]
+
+
+def test_pt2_self_energy_obeys_kramers_kronig():
+    """Re Sigma^R(v) = (1/pi) P int dv' Im Sigma^R(v') / (v' - v) (Sec. Kramers-Kronig check), with
+    Im Sigma^R interpolated as the method interpolates it and zero beyond the grid; the residual
+    is the discretisation and shrinks with the grid."""
+    res = []
+    for N, Nq in ((41, 301), (81, 601)):
+        g = O.Grid(N)
+        s = O.sde(O.bare(g, U), O.Prop(D, T), O.Quad(Nq, 1, 0.0, 1.0), O.Quad(Nq, 1, 0.0, 1.0))
+        v = g.nodes()
+        th = np.arctan(g.L / g.a)
+        xs = np.arctan(v / g.a) / th
+        im = lambda x: np.interp(np.arctan(x / g.a) / th, xs, s[:, 1].imag)
+        worst = 0.0
+        for i in range(N // 2 - 6, N // 2 + 7, 3):
+            pv = si.quad(im, -g.L, g.L, weight="cauchy", wvar=v[i], limit=2000, epsabs=1e-13)[0] / np.pi
+            worst = max(worst, abs(pv - s[i, 1].real))
+        res.append(worst / np.abs(s[:, 1]).max())
+    assert res[0] < 2e-3 and res[1] < 0.6 * res[0], res
