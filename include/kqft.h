@@ -286,6 +286,9 @@ typedef struct {
                             iterations per right-hand side; 0: none */
   double se_tol_abs;     /* stop when max|Sigma_dot_new - Sigma_dot| <= abs + rel max|Sigma_dot_new| */
   double se_tol_rel;
+  int se_anderson;       /* Anderson depth of the correction iterations (0: plain iteration;
+                            else the next iterate is the Anderson step with mixing factor 1 over
+                            the last se_anderson iterations, as in kqft_parquet_solve) */
   int adaptive;          /* 0: classical RK4 in `steps` equal steps; 1: Cash-Karp step control */
   double ode_tol_abs;    /* accept a step when max_i |e_i| / (abs + rel max(|y_i|, |y4_i|)) <= 1 */
   double ode_tol_rel;

@@ -659,49 +659,66 @@ def parquet_iteration(V: Vertex, P: Prop, q_bubble: Quad, q_loop: Quad):
     return out, sde(V, P, q_bubble, q_loop)
 
 
-def fixed_point_solve(Fmap, x0: np.ndarray, residual, alpha: float = 0.5, depth: int = 0, iterations: int = 10,
-                      tol: float = 0.0, reduce_alpha: bool = False, alpha_min: float = 0.01):
-    """Fixed-point iteration x = F(x) on complex vectors (Sec. parquet solver: mixing and
-    Anderson acceleration).  Per iteration k: g_k = F(x_k), f_k = g_k - x_k, r_k =
-    residual(x_k, g_k).  With reduce_alpha, r_k > r_{k-1} halves alpha (not below alpha_min)
-    and clears the Anderson history.  Anderson (Walker and Ni 2011) of depth m over the real
-    inner product Re <a, b>: the columns dF_i = f_{i+1} - f_i, dG_i = g_{i+1} - g_i of the last
-    m iterations, gamma from the normal equations (dF^T dF + eps I) gamma = dF^T f_k with
-    eps = 1e-14 max_i (dF^T dF)_ii, and
+class AndersonMixer:
+    """One step of mixing or Anderson acceleration (Walker and Ni 2011) per call, over the real
+    inner product Re <a, b> of complex vectors: from x_k and g_k = F(x_k), f_k = g_k - x_k; the
+    columns dF_i = f_{i+1} - f_i, dG_i = g_{i+1} - g_i of the last `depth` calls; gamma from the
+    normal equations (dF^T dF + eps I) gamma = dF^T f_k with eps = 1e-14 max_i (dF^T dF)_ii;
         x_{k+1} = x_k + alpha f_k - sum_i gamma_i (dG_i - (1 - alpha) dF_i);
-    depth 0 (or an empty history) is linear mixing x_{k+1} = x_k + alpha f_k.  Stops after
-    the update of the first iteration with r_k < tol.  Returns (x, residuals, final alpha)."""
-    x = x0
-    res, dF, dG = [], [], []
-    f_prev = g_prev = None
-    for k in range(iterations):
-        g = Fmap(x)
+    depth 0 (or an empty history) is linear mixing x_{k+1} = x_k + alpha f_k.  reset() clears
+    the history (the next call still records its f, g for the following one)."""
+
+    def __init__(self, depth: int, alpha: float):
+        self.depth, self.alpha = depth, alpha
+        self.dF, self.dG = [], []
+        self.f_prev = self.g_prev = None
+
+    def reset(self):
+        self.dF, self.dG = [], []
+
+    def step(self, x: np.ndarray, g: np.ndarray, record: bool = True) -> np.ndarray:
         f = g - x
-        r = residual(x, g)
-        if reduce_alpha and res and r > res[-1]:
-            alpha = max(0.5 * alpha, alpha_min)
-            dF, dG = [], []
-        elif depth > 0 and f_prev is not None:
-            dF.append(f - f_prev)
-            dG.append(g - g_prev)
-            if len(dF) > depth:
-                dF.pop(0)
-                dG.pop(0)
-        res.append(r)
-        f_prev, g_prev = f, g
-        step = x + alpha * f
-        if dF:
-            m = len(dF)
-            A = np.array([[np.vdot(dF[i], dF[j]).real for j in range(m)] for i in range(m)])
-            b = np.array([np.vdot(dF[i], f).real for i in range(m)])
+        if record and self.depth > 0 and self.f_prev is not None:
+            self.dF.append(f - self.f_prev)
+            self.dG.append(g - self.g_prev)
+            if len(self.dF) > self.depth:
+                self.dF.pop(0)
+                self.dG.pop(0)
+        self.f_prev, self.g_prev = f, g
+        step = x + self.alpha * f
+        if self.dF:
+            m = len(self.dF)
+            A = np.array([[np.vdot(self.dF[i], self.dF[j]).real for j in range(m)] for i in range(m)])
+            b = np.array([np.vdot(self.dF[i], f).real for i in range(m)])
             A = A + 1e-14 * A.diagonal().max() * np.eye(m)
             gam = np.linalg.solve(A, b)
             for i in range(m):
-                step = step - gam[i] * (dG[i] - (1.0 - alpha) * dF[i])
-        x = step
+                step = step - gam[i] * (self.dG[i] - (1.0 - self.alpha) * self.dF[i])
+        return step
+
+
+def fixed_point_solve(Fmap, x0: np.ndarray, residual, alpha: float = 0.5, depth: int = 0, iterations: int = 10,
+                      tol: float = 0.0, reduce_alpha: bool = False, alpha_min: float = 0.01):
+    """Fixed-point iteration x = F(x) on complex vectors (Sec. parquet solver: mixing and
+    Anderson acceleration).  Per iteration k: g_k = F(x_k), r_k = residual(x_k, g_k), then one
+    AndersonMixer step of the given depth and mixing factor.  With reduce_alpha, r_k > r_{k-1}
+    halves alpha (not below alpha_min) and clears the Anderson history before the step.  Stops
+    after the update of the first iteration with r_k < tol.  Returns (x, residuals, final alpha)."""
+    x = x0
+    res = []
+    mix = AndersonMixer(depth, alpha)
+    for k in range(iterations):
+        g = Fmap(x)
+        r = residual(x, g)
+        grew = reduce_alpha and res and r > res[-1]
+        if grew:
+            mix.alpha = max(0.5 * mix.alpha, alpha_min)
+            mix.reset()
+        res.append(r)
+        x = mix.step(x, g, record=not grew)
         if r < tol:
             break
-    return x, res, alpha
+    return x, res, mix.alpha
 
 
 def _rel_residual(n: int):
@@ -846,6 +863,7 @@ class FlowOptions:
     se_iterations: int = 0
     se_atol: float = 1e-9
     se_rtol: float = 1e-5
+    se_anderson: int = 0  # Anderson depth of the self-energy correction iterations (0: plain)
     adaptive: bool = False
     atol: float = 1e-8
     rtol: float = 1e-5
@@ -862,13 +880,17 @@ def mfrg_rhs(grid: Grid, U: float, T: float, lam: float, nloops: int, q_bubble: 
       Sigma_dot_tbar = -L(gdot_{a,C} + gdot_{p,C}, G)          (centre terms summed over l)
       Sigma_dot_t    = -L(Gamma, G Sigma_dot_tbar G)
       Sigma_dot      = Sigma_dot^(1) + Sigma_dot_tbar + Sigma_dot_t,
-    re-evaluating Gamma_dot with the new Sigma_dot after each update."""
+    re-evaluating Gamma_dot with the new Sigma_dot after each update.  The correction loop is
+    the fixed-point iteration Sigma_dot = F(Sigma_dot); with se_anderson > 0 the next iterate
+    is the AndersonMixer step (mixing factor 1) of that depth instead of F(Sigma_dot) itself,
+    and the right-hand side returned is still F of the last iterate with its Gamma_dot."""
     fo = fo or FlowOptions()
     P = flow_prop(grid, fo.reg, lam, fo.Delta, T, sigma)
     V = Vertex(grid, U, chans)
     sd1 = -loop(V, P, q_loop, kind=1)
     sd = sd1
     it = 0
+    mixer = AndersonMixer(fo.se_anderson, 1.0)
     while True:
         Pk = flow_prop(grid, fo.reg, lam, fo.Delta, T, sigma, sd if fo.katanin else None)
         cen = []
@@ -881,10 +903,11 @@ def mfrg_rhs(grid: Grid, U: float, T: float, lam: float, nloops: int, q_bubble: 
         st = -loop(V, flow_prop(grid, fo.reg, lam, fo.Delta, T, sigma, tbar), q_loop, kind=2)
         new = sd1 + tbar + st
         change = float(np.abs(new - sd).max())
-        sd = new
         it += 1
         if change <= fo.se_atol + fo.se_rtol * float(np.abs(new).max()) or it >= fo.se_iterations:
+            sd = new
             break
+        sd = mixer.step(sd, new) if fo.se_anderson > 0 else new
     if info is not None:
         info["se_iterations"] = info.get("se_iterations", 0) + it
         info["rhs"] = info.get("rhs", 0) + 1

@@ -1315,6 +1315,61 @@ static double flow_dlambda_dt(int reg, double t) {
   return reg == KQFT_REG_DELTA ? 5.0 * fabs(t) * (2.0 - t * t) / pow(1.0 - t * t, 1.5) : 1.0;
 }
 
+// Anderson step (Walker and Ni 2011) on a small host vector of interleaved complex values, over
+// the real inner product: x_next = x + alpha f - sum_i gamma_i (dG_i - (1 - alpha) dF_i), f = g - x,
+// with the columns of the last `depth` calls and gamma from the shifted normal equations.
+struct HostAnderson {
+  int depth;
+  double alpha;
+  std::vector<std::vector<double>> dF, dG;
+  std::vector<double> fprev, gprev;
+  bool has_prev = false;
+  HostAnderson(int d, double a) : depth(d), alpha(a) {}
+  bool step(const std::vector<double>& x, const std::vector<double>& g, std::vector<double>& out) {
+    const size_t m = x.size();
+    std::vector<double> f(m);
+    for (size_t e = 0; e < m; ++e) f[e] = g[e] - x[e];
+    if (depth > 0 && has_prev) {
+      std::vector<double> a(m), b(m);
+      for (size_t e = 0; e < m; ++e) {
+        a[e] = f[e] - fprev[e];
+        b[e] = g[e] - gprev[e];
+      }
+      dF.push_back(a);
+      dG.push_back(b);
+      if ((int)dF.size() > depth) {
+        dF.erase(dF.begin());
+        dG.erase(dG.begin());
+      }
+    }
+    fprev = f;
+    gprev = g;
+    has_prev = true;
+    out.resize(m);
+    for (size_t e = 0; e < m; ++e) out[e] = x[e] + alpha * f[e];
+    const int nc = (int)dF.size();
+    if (nc == 0) return true;
+    std::vector<double> A((size_t)nc * nc), bb(nc), gam;
+    double dmax = 0.0;
+    for (int i = 0; i < nc; ++i) {
+      for (int j = 0; j < nc; ++j) {
+        double t = 0.0;
+        for (size_t e = 0; e < m; ++e) t += dF[i][e] * dF[j][e];
+        A[(size_t)i * nc + j] = t;
+      }
+      double t = 0.0;
+      for (size_t e = 0; e < m; ++e) t += dF[i][e] * f[e];
+      bb[i] = t;
+      dmax = std::max(dmax, A[(size_t)i * nc + i]);
+    }
+    for (int i = 0; i < nc; ++i) A[(size_t)i * nc + i] += 1e-14 * dmax;
+    if (!solve_small(A, bb, nc, gam)) return false;
+    for (int i = 0; i < nc; ++i)
+      for (size_t e = 0; e < m; ++e) out[e] -= gam[i] * (dG[i][e] - (1.0 - alpha) * dF[i][e]);
+    return true;
+  }
+};
+
 // Cash-Karp embedded pair (Cash and Karp 1990): nodes, stage matrix, fifth- and fourth-order weights.
 static const double kCkC[6] = {0.0, 1.0 / 5, 3.0 / 10, 3.0 / 5, 1.0, 7.0 / 8};
 static const double kCkA[6][5] = {{0, 0, 0, 0, 0},
@@ -1349,8 +1404,9 @@ int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, dou
   if ((rc = check_common(ctx, &Gc, q_bubble, opts))) return rc;
   if (!q_loop || q_loop->n < 1) return fail(KQFT_ESHAPE, "invalid loop quadrature");
   if (steps < 1 || nloops < 1) return fail(KQFT_EINVAL, "need steps >= 1 and nloops >= 1");
-  if (fo.se_iterations < 0 || !(fo.se_tol_abs >= 0) || !(fo.se_tol_rel >= 0))
-    return fail(KQFT_EINVAL, "self-energy correction settings must be non-negative");
+  if (fo.se_iterations < 0 || !(fo.se_tol_abs >= 0) || !(fo.se_tol_rel >= 0) || fo.se_anderson < 0 ||
+      fo.se_anderson > 32)
+    return fail(KQFT_EINVAL, "self-energy correction settings must be non-negative (Anderson depth <= 32)");
   if (fo.adaptive && (fo.max_steps < 1 || !(fo.ode_tol_abs >= 0) || !(fo.ode_tol_rel >= 0) ||
                       !(fo.ode_tol_abs + fo.ode_tol_rel > 0)))
     return fail(KQFT_EINVAL, "adaptive steps need max_steps >= 1 and positive tolerances");
@@ -1448,6 +1504,7 @@ int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, dou
     launch_axpby(sd1, -1.0, sd1, 0.0, sd1, (size_t)4 * n, s);
     launch_axpby(sd, 1.0, sd1, 0.0, sd1, (size_t)4 * n, s);
     BubbleOut centre[2] = {chan_view(cen), chan_view(cen + chc)};
+    HostAnderson mixer(fo.se_anderson, 1.0);
     for (int it = 0;;) {
       kqft_propagator Gk = G;
       if (fo.katanin) {
@@ -1476,10 +1533,21 @@ int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, dou
       lincomb(snew, sd1, 2, ks, cs, (size_t)4 * n);
       double md, mf;
       if ((e = maxdiff(sd, snew, (size_t)4 * n, md, mf))) return e;
-      launch_axpby(sd, 1.0, snew, 0.0, snew, (size_t)4 * n, s);
       ++it;
       ++inf.se_iterations;
-      if (md <= fo.se_tol_abs + fo.se_tol_rel * mf || it >= fo.se_iterations) break;
+      if (md <= fo.se_tol_abs + fo.se_tol_rel * mf || it >= fo.se_iterations || fo.se_anderson == 0) {
+        launch_axpby(sd, 1.0, snew, 0.0, snew, (size_t)4 * n, s);
+        if (md <= fo.se_tol_abs + fo.se_tol_rel * mf || it >= fo.se_iterations) break;
+        continue;
+      }
+      // Anderson step on the host (4n complex values)
+      std::vector<double> hx((size_t)8 * n), hg((size_t)8 * n), hn;
+      HIP_TRY(hipMemcpyAsync(hx.data(), sd, hx.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(hg.data(), snew, hg.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (!mixer.step(hx, hg, hn)) return fail(KQFT_ENOCONV, "singular Anderson system in the self-energy corrections");
+      HIP_TRY(hipMemcpyAsync(sd, hn.data(), hn.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      HIP_TRY(hipStreamSynchronize(s));
     }
     // Gamma_dot = sum over the loop orders; everything times dLambda/dt
     const double dl = flow_dlambda_dt(fo.reg, t);

@@ -51,7 +51,7 @@ class KqftPropagator(C.Structure):
 
 class KqftFlowOpts(C.Structure):
     _fields_ = [("reg", C.c_int), ("Delta", C.c_double), ("katanin", C.c_int), ("se_iterations", C.c_int),
-                ("se_tol_abs", C.c_double), ("se_tol_rel", C.c_double), ("adaptive", C.c_int),
+                ("se_tol_abs", C.c_double), ("se_tol_rel", C.c_double), ("se_anderson", C.c_int), ("adaptive", C.c_int),
                 ("ode_tol_abs", C.c_double), ("ode_tol_rel", C.c_double), ("max_steps", C.c_int)]
 
 
@@ -266,6 +266,7 @@ class FlowOptions:
     se_iterations: int = 0
     se_atol: float = 1e-9
     se_rtol: float = 1e-5
+    se_anderson: int = 0
     adaptive: bool = False
     atol: float = 1e-8
     rtol: float = 1e-5
@@ -273,7 +274,7 @@ class FlowOptions:
 
     def c(self) -> KqftFlowOpts:
         return KqftFlowOpts(self.reg, self.Delta, int(self.katanin), self.se_iterations, self.se_atol, self.se_rtol,
-                            int(self.adaptive), self.atol, self.rtol, self.max_steps)
+                            self.se_anderson, int(self.adaptive), self.atol, self.rtol, self.max_steps)
 
 
 def _opts(precision, class_mask, beta, omega_batch, overlap=0) -> KqftOpts:

@@ -90,8 +90,8 @@ def gpu_state(K, chans, sig):
 
 def _kflow(K, fo):
     return K.FlowOptions(reg=fo.reg, Delta=fo.Delta, katanin=fo.katanin, se_iterations=fo.se_iterations,
-                         se_atol=fo.se_atol, se_rtol=fo.se_rtol, adaptive=fo.adaptive, atol=fo.atol, rtol=fo.rtol,
-                         max_steps=fo.max_steps)
+                         se_atol=fo.se_atol, se_rtol=fo.se_rtol, se_anderson=fo.se_anderson, adaptive=fo.adaptive,
+                         atol=fo.atol, rtol=fo.rtol, max_steps=fo.max_steps)
 
 
 def _compare_state(kch, ksig, rch, rsig, tol):
@@ -109,6 +109,8 @@ FLOW_CASES = {
     "adaptive_corrections": (O.FlowOptions(adaptive=True, atol=1e-6, rtol=1e-4, se_iterations=2, se_atol=0.0,
                                            se_rtol=0.0), 2.0, 1.0, 1, 3),
     "adaptive_corrections_tol": (O.FlowOptions(adaptive=True, atol=1e-6, rtol=1e-4, se_iterations=10), 2.0, 1.0, 1, 4),
+    "adaptive_corrections_anderson": (O.FlowOptions(adaptive=True, atol=1e-6, rtol=1e-4, se_iterations=10,
+                                                    se_anderson=2), 2.0, 1.0, 1, 4),
     "rk4_interaction": (O.FlowOptions(reg=O.REG_U, Delta=1.0), 0.5, 1.0, 2, 2),
     "rk4_temperature": (O.FlowOptions(reg=O.REG_T, Delta=1.0), 0.3, 0.15, 2, 2),
     "rk4_frequency": (O.FlowOptions(reg=O.REG_NU, Delta=1.0), 2.0, 1.0, 2, 2),

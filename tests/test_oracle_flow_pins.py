@@ -210,3 +210,22 @@ def test_self_energy_corrections_are_fourth_order_and_converge():
         assert np.abs(s2 - s3).max() == 0.0
     # relative to Sigma_dot ~ U^2: the correction ratio falls by 2^2 = 4 (U^4 / U^2)
     assert 3.3 < diffs[0] / diffs[1] < 4.8, diffs
+
+
+def test_anderson_accelerated_self_energy_corrections_reach_the_same_fixed_point():
+    """Anderson acceleration of the self-energy correction iterations (Sec. mfRG) changes the
+    path, not the fixed point: at a tight tolerance the accelerated iteration ends at the plain
+    one's Sigma_dot and vertex flow, in no more iterations (fewer at depth 4, U = 2)."""
+    g, q = O.Grid(9), O.Quad(31)
+    ch, sg = O.pt2_state(g, 2.0, 1.0, T, q, q)
+    out = {}
+    for m in (0, 4):
+        info = {}
+        fo = O.FlowOptions(se_iterations=40, se_atol=0.0, se_rtol=1e-12, se_anderson=m)
+        gd, sd = O.mfrg_rhs(g, 2.0, T, 1.0, 4, q, q, ch, sg, fo, info)
+        out[m] = (gd, sd, info["se_iterations"])
+    assert np.abs(out[4][1] - out[0][1]).max() < 1e-10 * np.abs(out[0][1]).max()
+    for r in range(3):
+        a, b = out[4][0][r].K3, out[0][0][r].K3
+        assert np.abs(a - b).max() < 1e-9 * np.abs(b).max()
+    assert out[4][2] < out[0][2] < 40
