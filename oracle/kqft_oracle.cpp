@@ -896,7 +896,7 @@ static void loop_full(const OVert& Gv, const OProp& P, int kind, const OQuad& q,
 // w_k/(2 pi i); c = 0: X, c = 1: D = X + 2Y.  out[c][iw][16].
 template <class S>
 static void chi_full(const OVert& Gv, const OProp& P, const OQuad& q, Cx<S>* out, int nw = -1,
-                     const int* wlist = nullptr) {
+                     const int* wlist = nullptr, int r = 0) {
   Vtx<S> V = make_vtx<S>(Gv);
   int n = V.g.n;
   std::vector<double> qv, qw;
@@ -911,9 +911,13 @@ static void chi_full(const OVert& Gv, const OProp& P, const OQuad& q, Cx<S>* out
     double w = grid_node(V.g, iw);
     std::vector<Cx<S>> Pi((size_t)nq * 16);
     for (int k = 0; k < nq; ++k) {
-      bubble_pi<S>(P, 0, 0, w, qv[k], &Pi[(size_t)k * 16]);
+      bubble_pi<S>(P, r, 0, w, qv[k], &Pi[(size_t)k * 16]);
       for (int f = 0; f < 16; ++f) Pi[(size_t)k * 16 + f] = cmul(0.0, -qw[k] / (2.0 * M_PI), Pi[(size_t)k * 16 + f]);
     }
+    // the channel's two spin combinations: a: X, X + 2Y (spin, density); p: X + Y, X - Y;
+    // t: Y, 2X + Y
+    const double cx[3][2] = {{1.0, 1.0}, {1.0, 1.0}, {0.0, 2.0}};
+    const double cy[3][2] = {{0.0, 2.0}, {1.0, -1.0}, {1.0, 1.0}};
     for (int c = 0; c < 2; ++c) {
       Cx<S> acc[16];
       for (int f = 0; f < 16; ++f) acc[f] = czero<S>();
@@ -922,8 +926,8 @@ static void chi_full(const OVert& Gv, const OProp& P, const OQuad& q, Cx<S>* out
       for (int k = 0; k < nq; ++k)
         for (int l = 0; l < nq; ++l) {
           Cx<S> X[16], Y[16], G[16], M[16], T[16];
-          eval_vertex(V, 0, w, qv[k], qv[l], P_ALL, X, Y);
-          for (int f = 0; f < 16; ++f) G[f] = c == 0 ? X[f] : X[f] + 2.0 * Y[f];
+          eval_vertex(V, r, w, qv[k], qv[l], P_ALL, X, Y);
+          for (int f = 0; f < 16; ++f) G[f] = cx[r][c] * X[f] + cy[r][c] * Y[f];
           matmul4(&Pi[(size_t)k * 16], G, M);
           matmul4(M, &Pi[(size_t)l * 16], T);
           for (int f = 0; f < 16; ++f) acc[f] = acc[f] + T[f];
@@ -1044,7 +1048,13 @@ int oracle_loop(int dual, const OVert* G, const OProp* P, int kind, const OQuad*
 }
 
 int oracle_chi_points(const OVert* G, const OProp* P, const OQuad* q, int nw, const int* wlist, double* out) {
-  chi_full<double>(*G, *P, *q, (Cx<double>*)out, nw, wlist);
+  chi_full<double>(*G, *P, *q, (Cx<double>*)out, nw, wlist, 0);
+  return 0;
+}
+
+int oracle_chi_channel(int r, const OVert* G, const OProp* P, const OQuad* q, int nw, const int* wlist, double* out) {
+  if (r < 0 || r > 2) return -1;
+  chi_full<double>(*G, *P, *q, (Cx<double>*)out, nw, wlist, r);
   return 0;
 }
 

@@ -90,6 +90,8 @@ def lib():
         _lib.oracle_loop.argtypes = [C.c_int, P(OVert), P(OProp), C.c_int, P(OQuad), C.c_void_p]
         _lib.oracle_chi.argtypes = [C.c_int, P(OVert), P(OProp), P(OQuad), C.c_void_p]
         _lib.oracle_chi_points.argtypes = [P(OVert), P(OProp), P(OQuad), C.c_int, C.c_void_p, C.c_void_p]
+        _lib.oracle_chi_channel.argtypes = [C.c_int, P(OVert), P(OProp), P(OQuad), C.c_int, C.c_void_p,
+                                            C.c_void_p]
     return _lib
 
 
@@ -452,6 +454,22 @@ def chi_points(V: Vertex, P: Prop, q: Quad, iws) -> np.ndarray:
     keep = []
     vc, pc, qc = V.c(keep), P.c(keep), q.c()
     lib().oracle_chi_points(C.byref(vc), C.byref(pc), C.byref(qc), len(iws), iws.ctypes.data, out.ctypes.data)
+    return out
+
+
+def chi_channel(r: int, V: Vertex, P: Prop, q: Quad, iws=None) -> np.ndarray:
+    """Pair-space susceptibility of channel r (Sec. Susceptibilities: bare bubble plus bubble,
+    vertex in channel r's parametrization, bubble): chi_r^c(w) = sum_k Pi_r,k + sum_{k,l} Pi_r,k
+    Gamma_r^c(w; v''_k, v''_l) Pi_r,l with Pi carrying w_k/(2 pi i), for the channel's two spin
+    combinations c (a: X, X + 2Y; p: X + Y, X - Y; t: Y, 2X + Y).  [2, len(iws) or n, 16]."""
+    iws = np.arange(V.grid.n) if iws is None else np.atleast_1d(iws)
+    iws = np.ascontiguousarray(iws, dtype=np.int32)
+    out = np.zeros((2, len(iws), 16), dtype=np.complex128)
+    keep = []
+    vc, pc, qc = V.c(keep), P.c(keep), q.c()
+    if lib().oracle_chi_channel(r, C.byref(vc), C.byref(pc), C.byref(qc), len(iws), iws.ctypes.data,
+                                out.ctypes.data) != 0:
+        raise ValueError("channel must be 0, 1 or 2")
     return out
 
 

@@ -381,6 +381,41 @@ def test_chi_bare_vertex_closed_form_and_sign():
     assert P0.real < 0 and abs(cx[i0]) > abs(P0) > abs(cd[i0])
 
 
+def test_chi_of_every_channel_factorises_for_the_bare_vertex_and_diagonalises_its_bubble():
+    """With Gamma = Gamma_0 (constant in the fermionic frequencies) the double sum of the
+    susceptibility factorises exactly: chi_r^c = S_r + S_r Gamma_0^c S_r with S_r = chi_r at
+    U = 0, the sum of the weighted pair bubbles.  The same S_r builds the one-loop K1 class of the
+    Bethe-Salpeter bubble (itself pinned by closed forms and crossing symmetry):
+    B_r(Gamma_0, Gamma_0)^c = pref_r Gamma_0^c S_r Gamma_0^c with the channel prefactors +1, 1/2,
+    -1 -- which holds only when the two spin combinations c are the ones that diagonalise channel
+    r's spin sum (a: X, X + 2Y; p: X + Y, X - Y; t: Y, 2X + Y), and only when chi uses channel r's
+    bubble and pair order."""
+    g = O.Grid(7)
+    q = O.Quad(61)
+    P = O.Prop(D, T)
+    g0, zero = O.bare(g, U), O.bare(g, 0.0)
+    w = g.nodes()
+    combos = {0: ((1, 0), (1, 2)), 1: ((1, 1), (1, -1)), 2: ((0, 1), (2, 1))}
+    pref = (1.0, 0.5, -1.0)
+    for r in range(3):
+        S = O.chi_channel(r, zero, P, q)
+        assert np.abs(S[0] - S[1]).max() == 0.0
+        ch = O.chi_channel(r, g0, P, q)
+        K1 = O.bubble(r, g0, g0, P, q).K1
+        XY = O.vertex_eval(g0, r, [(wi, 0.37, -1.3) for wi in w])
+        for c, (mx, my) in enumerate(combos[r]):
+            for i in range(len(w)):
+                Gc = (mx * XY[i, 0] + my * XY[i, 1]).reshape(4, 4)
+                Sm = S[0, i].reshape(4, 4)
+                scale = np.abs(Sm).max()
+                assert scale > 1e-3
+                assert np.abs(ch[c, i].reshape(4, 4) - (Sm + Sm @ Gc @ Sm)).max() < 1e-13
+                k1 = (mx * K1[0][i] + my * K1[1][i]).reshape(4, 4)
+                assert np.abs(k1 - pref[r] * Gc @ Sm @ Gc).max() < 1e-13
+    # channel a is the susceptibility of the Schwinger-Dyson path
+    assert np.abs(O.chi_channel(0, g0, P, q) - O.chi(g0, P, q)).max() == 0.0
+
+
 # ---------------------------------------------------------------- P7: crossing symmetry
 def _legs_grid(n):
     rng = np.random.default_rng(5)
