@@ -216,6 +216,24 @@ int kqft_sde(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, 
              const kqft_quad* q_loop, const kqft_opts* opts, double* sigma, double* chi, void* stream);
 
 /*
+ * kqft_chi -- the pair-space susceptibility of one channel (Sec. "Susceptibilities": legs of
+ * the vertex contracted in pairs, here in channel r = `channel`):
+ *
+ *   chi_r^c(w) = sum_k Pi_r,k(w) + sum_{k,l} Pi_r,k(w) Gamma_r^c(w; v''_k, v''_l) Pi_r,l(w),
+ *
+ * Pi_r,k the 4x4 Keldysh pair-space bubble G G of channel r at v''_k times w_k/(2 pi i)
+ * (q), products of 4x4 matrices in channel r's pair order, and Gamma_r^c the full vertex
+ * (bare part, channel r's own classes, the two other channels) in channel r's
+ * parametrization and spin combination c: a: X (transverse spin), X + 2Y (density);
+ * p: X + Y, X - Y; t: Y, 2X + Y.  chi: device [2][n][16] complex on gamma->grid (c, w, pair
+ * entry 4*row + col), written completely.  FP64 throughout.  KQFT_EINVAL for a NULL
+ * argument or a channel outside 0..2, KQFT_ESHAPE for an invalid quadrature or q->n > 46340
+ * (the double sum is indexed in 32 bits).  channel = KQFT_CH_A gives kqft_sde's chi.
+ */
+int kqft_chi(kqft_ctx* ctx, int channel, const kqft_vertex* gamma, const kqft_propagator* G, const kqft_quad* q,
+             double* chi, void* stream);
+
+/*
  * kqft_loop -- the loop function of a full vertex (Sec. "loop": the self-energy-like
  * contraction of a vertex with one propagator line):
  *   L(Gamma, X)^{a1'|a1}(v_i) = sum_j w_j/(2 pi i) sum_{a2,a2'} [2 Gamma^X + Gamma^Y]

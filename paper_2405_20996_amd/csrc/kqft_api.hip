@@ -632,6 +632,60 @@ static int adjoint_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_v
 }
 
 // ------------------------------------------------------------------ C ABI
+// Susceptibility of channel r of the vertex `gamma` into chi [2][n][16] (arguments checked).
+static int chi_core(kqft_ctx* ctx, int r, const kqft_vertex& gamma, const DProp& P, const double* nodes,
+                    const kqft_quad& q_bubble, double* chi, hipStream_t s) {
+  int rc;
+  const int n = gamma.grid.n;
+  const double *cqv, *cqw;
+  if ((rc = get_quad(ctx, q_bubble, &cqv, &cqw))) return rc;
+  const int nq = q_bubble.n;
+  const int nblk = chi_blocks(nq);
+  const int nb = std::max(1, std::min(n, (int)((256L << 20) / ((long)nq * 256))));
+  if ((rc = ensure(ctx->pi[0], (size_t)nb * nq * 256))) return rc;
+  if ((rc = ensure(ctx->chi_part, (size_t)nb * nblk * 32 * 16))) return rc;
+  // the two other channels in channel r's Keldysh order with its spin combinations
+  SideTables tabs, unused;
+  if ((rc = build_tables(ctx, r, gamma, gamma, false, tabs, unused, s))) return rc;
+  for (int iw0 = 0; iw0 < n; iw0 += nb) {
+    const int cnt = std::min(nb, n - iw0);
+    PiArgs pa{r, KQFT_PI_GG, cnt, nq, iw0, P, nodes, cqv, cqw, (double2*)ctx->pi[0].p};
+    {
+      ProfScope ps(ctx, 0, s);
+      launch_pi(pa, s);
+    }
+    ChiArgs ca;
+    memset(&ca, 0, sizeof ca);
+    ca.r = r;
+    ca.nq = nq;
+    ca.nb = cnt;
+    ca.iw0 = iw0;
+    ca.g = make_dgrid(n, gamma.grid.L, gamma.grid.a);
+    ca.r0 = gamma.r0;
+    const kqft_chvert& own = gamma.ch[r];
+    ca.coef = own.coef;
+    if (own.coef != 0.0) {
+      ca.K[0] = (const double2*)own.K1;
+      ca.K[1] = (const double2*)own.K2;
+      ca.K[2] = (const double2*)own.K2p;
+      ca.K[3] = (const double2*)own.K3;
+    }
+    ca.T[0] = tabs.T[0];
+    ca.T[1] = tabs.T[1];
+    for (int u = 0; u < 4; ++u) ca.mix[u] = kMix[r][u];
+    ca.nodes = nodes;
+    ca.qv = cqv;
+    ca.pi = (const double2*)ctx->pi[0].p;
+    ca.partial = (double2*)ctx->chi_part.p;
+    ca.out = (double2*)chi;
+    {
+      ProfScope ps(ctx, 3, s);
+      launch_chi(ca, s);
+    }
+  }
+  return KQFT_OK;
+}
+
 // Sigma (and chi when given) of the vertex `gamma` (the body of kqft_sde; arguments checked).
 static int sde_core(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, const kqft_quad* q_bubble,
                     const kqft_quad* q_loop, const kqft_opts* opts, double* sigma, double* chi, hipStream_t s) {
@@ -662,53 +716,7 @@ static int sde_core(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagat
     ProfScope ps(ctx, 3, s);
     launch_loop(la, s);
   }
-  if (chi) {
-    const double *cqv, *cqw;
-    if ((rc = get_quad(ctx, *q_bubble, &cqv, &cqw))) return rc;
-    const int nq = q_bubble->n;
-    const int nblk = chi_blocks(nq);
-    const int nb = std::max(1, std::min(n, (int)((256L << 20) / ((long)nq * 256))));
-    if ((rc = ensure(ctx->pi[0], (size_t)nb * nq * 256))) return rc;
-    if ((rc = ensure(ctx->chi_part, (size_t)nb * nblk * 32 * 16))) return rc;
-    // the p and t channels in the a-channel Keldysh order with its spin combinations (X, D)
-    SideTables tabs, unused;
-    if ((rc = build_tables(ctx, KQFT_CH_A, *gamma, *gamma, false, tabs, unused, s))) return rc;
-    for (int iw0 = 0; iw0 < n; iw0 += nb) {
-      const int cnt = std::min(nb, n - iw0);
-      PiArgs pa{KQFT_CH_A, KQFT_PI_GG, cnt, nq, iw0, P, nodes, cqv, cqw, (double2*)ctx->pi[0].p};
-      {
-        ProfScope ps(ctx, 0, s);
-        launch_pi(pa, s);
-      }
-      ChiArgs ca;
-      memset(&ca, 0, sizeof ca);
-      ca.nq = nq;
-      ca.nb = cnt;
-      ca.iw0 = iw0;
-      ca.g = make_dgrid(n, gamma->grid.L, gamma->grid.a);
-      ca.r0 = gamma->r0;
-      const kqft_chvert& own = gamma->ch[KQFT_CH_A];
-      ca.coef = own.coef;
-      if (own.coef != 0.0) {
-        ca.K[0] = (const double2*)own.K1;
-        ca.K[1] = (const double2*)own.K2;
-        ca.K[2] = (const double2*)own.K2p;
-        ca.K[3] = (const double2*)own.K3;
-      }
-      ca.T[0] = tabs.T[0];
-      ca.T[1] = tabs.T[1];
-      for (int u = 0; u < 4; ++u) ca.mix[u] = kMix[KQFT_CH_A][u];
-      ca.nodes = nodes;
-      ca.qv = cqv;
-      ca.pi = (const double2*)ctx->pi[0].p;
-      ca.partial = (double2*)ctx->chi_part.p;
-      ca.out = (double2*)chi;
-      {
-        ProfScope ps(ctx, 3, s);
-        launch_chi(ca, s);
-      }
-    }
-  }
+  if (chi && (rc = chi_core(ctx, KQFT_CH_A, *gamma, P, nodes, *q_bubble, chi, s))) return rc;
   HIP_TRY(hipGetLastError());
   return KQFT_OK;
 }
@@ -1216,6 +1224,29 @@ int kqft_sde(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, 
   if (!sigma) return fail(KQFT_EINVAL, "sigma is NULL");
   HIP_TRY(hipSetDevice(ctx->device));
   return sde_core(ctx, gamma, G, q_bubble, q_loop, opts, sigma, chi, (hipStream_t)stream);
+}
+
+int kqft_chi(kqft_ctx* ctx, int channel, const kqft_vertex* gamma, const kqft_propagator* G, const kqft_quad* q,
+             double* chi, void* stream) {
+  int rc;
+  if (!ctx) return fail(KQFT_EINVAL, "ctx is NULL");
+  if (channel < KQFT_CH_A || channel > KQFT_CH_T) return fail(KQFT_EINVAL, "channel must be 0, 1 or 2");
+  if (!G || !q) return fail(KQFT_EINVAL, "propagator and quadrature must be given");
+  if (q->n < 1 || (q->map != KQFT_QUAD_TAN_FINITE && q->map != KQFT_QUAD_TAN_INFINITE) ||
+      (q->map == KQFT_QUAD_TAN_FINITE && !(q->L > 0)) || !(q->a > 0))
+    return fail(KQFT_ESHAPE, "invalid quadrature");
+  if (q->n > 46340) return fail(KQFT_ESHAPE, "chi needs q->n <= 46340");
+  if ((rc = check_vertex(gamma, "gamma"))) return rc;
+  if (!chi) return fail(KQFT_EINVAL, "chi is NULL");
+  DProp P;
+  if ((rc = to_dprop(*G, P))) return rc;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const double* nodes;
+  if ((rc = get_grid(ctx, gamma->grid, &nodes))) return rc;
+  const hipStream_t s = (hipStream_t)stream;
+  if ((rc = chi_core(ctx, channel, *gamma, P, nodes, *q, chi, s))) return rc;
+  HIP_TRY(hipGetLastError());
+  return KQFT_OK;
 }
 
 int kqft_loop(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, int kind, const kqft_quad* q,

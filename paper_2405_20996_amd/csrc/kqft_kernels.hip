@@ -10,7 +10,7 @@
 //   adaptive_kernel    adaptive Gauss-Lobatto-Kronrod bubble, one wavefront per output interval
 //   loop_kernel        Schwinger-Dyson loop reduction
 //   vloop_kernel       loop of a full vertex (all channels through tables) with G, S or G s G
-//   chi_kernel         a-channel susceptibility double sum (table gathers + Pi contractions)
+//   chi_kernel         susceptibility double sum of one channel (table gathers + Pi contractions)
 //   parquet / flow helpers: sigma_split, maxdiff, axpby, lincomb, errnorm, dot, mix,
 //                      occupation (Hartree term)
 //   adjoint kernels    reverse pass of the bubble and of the Schwinger-Dyson loop
@@ -1139,9 +1139,9 @@ __global__ __launch_bounds__(256) void vloop_kernel(VLoopArgs a) {
 }
 
 // ======================================================================== chi
-// chi_a^c(w)[p, m] = sum_k Pi_k[p, m]
+// chi_r^c(w)[p, m] = sum_k Pi_k[p, m]
 //   + sum_{k,l} sum_{row,q} Pi_k[p, row] Gamma_c(w; v''_k, v''_l)[row, q] Pi_l[q, m]
-// for c in {X, D = X + 2Y} (the a-channel spin combinations), Pi with the weights folded in.
+// for channel r's two spin combinations c, Pi (channel r) with the weights folded in.
 // One 8-lane group per node pair (k, l), grid-stride over the pairs of one transfer
 // frequency.  Lane l8 evaluates the full vertex (bare part, own classes, the other channels
 // through their target-order tables) at f = l8, l8 + 8 -- rows l8/4 and 2 + l8/4, column
@@ -1167,14 +1167,15 @@ __global__ __launch_bounds__(256) void chi_kernel(ChiArgs a) {
   for (unsigned t = grp; t < total; t += ngrp) {
     const int kq = (int)(t / (unsigned)a.nq), lq = (int)(t - (unsigned)kq * (unsigned)a.nq);
     const double vk = a.qv[kq], vl = a.qv[lq];
-    // grid locations: lane 0 v''_k, lane 1 v''_l, lanes 2-4 / 5-7 (w, v, v') of channels p / t
+    // grid locations: lane 0 v''_k, lane 1 v''_l, lanes 2-4 / 5-7 (w, v, v') of channels
+    // r + 1 / r + 2
     double arg = l8 == 0 ? vk : vl;
     if (l8 >= 2) {
       double L[4];
-      legs_of(0, w, vk, vl, L);
+      legs_of(a.r, w, vk, vl, L);
       const int d = l8 <= 4 ? 1 : 2, which = (l8 - 2) % 3;
       double w2, v2, vp2;
-      params_of(d, L, w2, v2, vp2);
+      params_of((a.r + d) % 3, L, w2, v2, vp2);
       arg = which == 0 ? w2 : (which == 1 ? v2 : vp2);
     }
     int ic;

@@ -80,16 +80,17 @@ struct VLoopArgs {
 };
 
 struct ChiArgs {
+  int r;  // channel of the susceptibility
   int nq, nb, iw0;
   DGrid g;
   double r0;
-  double coef;          // channel a coefficient
-  const double2* K[4];  // channel a K1, K2, K2', K3 (nullptr = absent)
-  const void* T[2];     // FP64 target-order tables of channels p and t (nullptr = inactive)
-  double mix[4];        // the a-channel spin combinations (X, X + 2Y)
+  double coef;          // channel r coefficient
+  const double2* K[4];  // channel r K1, K2, K2', K3 (nullptr = absent)
+  const void* T[2];     // FP64 target-order tables of channels r + 1 and r + 2 (nullptr = inactive)
+  double mix[4];        // channel r's spin combinations
   const double* nodes;
   const double* qv;
-  const double2* pi;  // [nb][nq][16], channel a, Pi = G G, weights folded
+  const double2* pi;  // [nb][nq][16], channel r, Pi = G G, weights folded
   double2* partial;   // [nb][nblk][32]
   double2* out;       // [2][n][16]
 };

@@ -108,6 +108,8 @@ def lib():
         _lib.kqft_bubble_adjoint.argtypes = [C.c_void_p, C.c_int, P(KqftVertex), P(KqftVertex), P(KqftPropagator),
                                              C.c_int, P(KqftQuad), P(KqftOpts), P(KqftChout), P(KqftChout),
                                              P(KqftChout), C.c_void_p, C.c_void_p]
+        _lib.kqft_chi.argtypes = [C.c_void_p, C.c_int, P(KqftVertex), P(KqftPropagator), P(KqftQuad), C.c_void_p,
+                                  C.c_void_p]
         _lib.kqft_loop.argtypes = [C.c_void_p, P(KqftVertex), P(KqftPropagator), C.c_int, P(KqftQuad), C.c_void_p,
                                    C.c_void_p]
         _lib.kqft_mfrg_flow.argtypes = [C.c_void_p, P(KqftGrid), C.c_double, C.c_double, C.c_double, C.c_double,
@@ -323,6 +325,17 @@ def sde(gamma: Vertex, G: Propagator, q_bubble: Quad, q_loop: Quad, precision: i
                           C.byref(_opts(precision, KALL, 0, omega_batch)), C.c_void_p(sigma.data_ptr()),
                           C.c_void_p(chi.data_ptr() if chi is not None else None), _stream(stream)))
     return sigma, chi
+
+
+def chi(channel: int, gamma: Vertex, G: Propagator, q: Quad, stream=None) -> torch.Tensor:
+    """Pair-space susceptibility of one channel: [2 (spin combinations), n, 16] complex."""
+    n = gamma.grid.n
+    dev = torch.device("cuda", torch.cuda.current_device())
+    out = torch.zeros((2, n, 16), dtype=torch.complex128, device=dev)
+    vc, gc, qc = gamma.c(), G.c(), q.c()
+    _check(lib().kqft_chi(ctx(), channel, C.byref(vc), C.byref(gc), C.byref(qc), C.c_void_p(out.data_ptr()),
+                          _stream(stream)))
+    return out
 
 
 def mloop_step(gammas: Sequence[Vertex], Gs: Sequence[Propagator], qs: Sequence[Quad], nloops: int,

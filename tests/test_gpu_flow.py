@@ -184,3 +184,28 @@ def test_mfrg_flow_n51_adaptive_with_corrections():
           f"rejected {info['rejected']}, rhs {info['rhs']}, se iterations {info['se_iterations']}", flush=True)
     assert info["lambdas"][-1] == pytest.approx(1.0, abs=1e-12)
     assert np.all(np.isfinite(ksig.cpu().numpy()))
+
+
+def test_mfrg_flow_resumed_from_a_checkpoint_equals_the_uninterrupted_flow():
+    """Checkpoint and resume (the state is the caller's arrays): RK4 from Delta = 2 to 1 in two
+    steps of t equals one step to the intermediate Delta the flow reports, a copy of the state
+    through host memory (as a checkpoint file would hold it), and one more step to 1."""
+    K = _K()
+    n, nq, U = 9, 31, 1.0
+    g, q = O.Grid(n), O.Quad(nq)
+    chans, sig = O.pt2_state(g, U, 2.0, T, q, q)
+    kch, ksig = gpu_state(K, chans, sig)
+    _, _, info = K.mfrg_flow(K.Grid(n), U, T, 2.0, 1.0, 2, 2, K.Quad(nq), K.Quad(nq), kch, ksig)
+    mid = info["lambdas"][1]
+    ach, asig = gpu_state(K, chans, sig)
+    K.mfrg_flow(K.Grid(n), U, T, 2.0, mid, 1, 2, K.Quad(nq), K.Quad(nq), ach, asig)
+    saved = ([{x: getattr(c, x).cpu().numpy() for x in CL} for c in ach], asig.cpu().numpy())
+    bch = [K.Channel(1.0, *[to_dev(d[x]) for x in CL]) for d in saved[0]]
+    bsig = to_dev(saved[1])
+    K.mfrg_flow(K.Grid(n), U, T, mid, 1.0, 1, 2, K.Quad(nq), K.Quad(nq), bch, bsig)
+    torch.cuda.synchronize()
+    for r in range(3):
+        for x in CL:
+            a, b = getattr(bch[r], x), getattr(kch[r], x)
+            assert float((a - b).abs().max()) <= 1e-12 * max(float(b.abs().max()), 1e-300), (r, x)
+    assert float((bsig - ksig).abs().max()) <= 1e-12 * float(ksig.abs().max())

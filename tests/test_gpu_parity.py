@@ -144,6 +144,24 @@ def test_sde_and_chi_match_oracle():
     assert rel(chi.cpu().numpy()[1], ref_chi[1]) < 1e-12
 
 
+@pytest.mark.parametrize("r", [0, 1, 2])
+def test_chi_of_every_channel_matches_oracle(r):
+    """kqft_chi in channel r for a vertex with every class of every channel non-zero (so the
+    own classes, both tables and the bare part all enter), a ragged quadrature."""
+    K = _K()
+    n, nq = 13, 37
+    ov, kv = make_pair(n, (31, 32, 33), r0=U, amp=0.2)
+    ref = O.chi_channel(r, ov, O.Prop(D, T), O.Quad(nq))
+    out = K.chi(r, kv, K.Propagator(D, T), K.Quad(nq)).cpu().numpy()
+    for c in range(2):
+        assert rel(out[c], ref[c]) < 1e-12
+    if r == 0:
+        _, chi_sde = K.sde(kv, K.Propagator(D, T), K.Quad(nq), K.Quad(nq))
+        assert np.array_equal(chi_sde.cpu().numpy(), out)
+    with pytest.raises(K.KqftError):
+        K.chi(3, kv, K.Propagator(D, T), K.Quad(nq))
+
+
 def test_mloop_three_loops_matches_oracle():
     K = _K()
     n, nq = 9, 25
