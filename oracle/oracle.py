@@ -518,6 +518,62 @@ def sde(V: Vertex, P: Prop, q_bubble: Quad, q_loop: Quad, dual: bool = False) ->
     return -0.5 * L
 
 
+def sde_p(V: Vertex, P: Prop, q_bubble: Quad, q_loop: Quad) -> np.ndarray:
+    """The SDE with the two lines between Gamma_0 and Gamma read as a p bubble (they run in
+    the same direction): Sigma = -L(B_p(Gamma_0, Gamma), G).  B_p carries its prefactor 1/2,
+    which takes the place of the symmetry factor 1/2 of the a-channel form; the loop closes the
+    legs 2' and 2 as in the a-channel form.  Phi_p = B_p(Gamma_0, Gamma) has the classes K1 and
+    K2' only (Gamma_0 on the left)."""
+    g0 = bare(V.grid, V.r0)
+    phi = bubble(1, g0, V, P, q_bubble, 0, C_K1 | C_K2P)
+    phi_v = Vertex(V.grid, r0=0.0, ch=[Channel(0.0), Channel(1.0, phi.K1, None, phi.K2p, None), Channel(0.0)])
+    return -loop(phi_v, P, q_loop)
+
+
+def closure_2_1p(X: Vertex, P: Prop, q: Quad) -> np.ndarray:
+    """The 4-point object X closed with G between its legs 2 and 1' (external legs 2' and 1),
+    summed literally over the closed legs' Keldysh indices and spins (external spins up):
+    out[i][2 a2' + a1] = sum_j w_j/(2 pi i) sum_{a2, a1', s} X(1' = (a1', s, v_j),
+    2' = (a2', up, v_i) | 1 = (a1, up, v_i), 2 = (a2, s, v_j)) G^{a2|a1'}(v_j)."""
+    g = X.grid
+    v = g.nodes()
+    vq, wq = q.nodes_weights()
+    Gm = propagator(P, vq)
+    out = np.zeros((g.n, 4), complex)
+    idx = [(j, a2p, a1, a2, a1p, s) for j in range(len(vq)) for a2p in range(2) for a1 in range(2)
+           for a2 in range(2) for a1p in range(2) for s in range(2)]
+    al = np.array([[a1p, a2p, a1, a2] for (j, a2p, a1, a2, a1p, s) in idx])
+    sg = np.array([[s, 0, 0, s] for (j, a2p, a1, a2, a1p, s) in idx])
+    jj = np.array([t[0] for t in idx])
+    fac = np.array([wq[j] / (2j * np.pi) * Gm[j, a2, a1p] for (j, a2p, a1, a2, a1p, s) in idx])
+    slot = np.array([2 * a2p + a1 for (j, a2p, a1, a2, a1p, s) in idx])
+    for i in range(g.n):
+        nu = np.stack([vq[jj], np.full(len(jj), v[i]), np.full(len(jj), v[i]), vq[jj]], axis=1)
+        vals = vertex_legs(X, al, sg, nu) * fac
+        out[i] = np.bincount(slot, weights=vals.real, minlength=4) + 1j * np.bincount(slot, weights=vals.imag,
+                                                                                        minlength=4)
+    return out
+
+
+def sde_t(V: Vertex, P: Prop, q_bubble: Quad, q_loop: Quad) -> np.ndarray:
+    """The SDE with the two lines between Gamma_0 and Gamma read as a t bubble: Phi_t =
+    B_t(Gamma_0, Gamma), closed between its legs 2 and 1' (which puts Gamma_0's outgoing leg and
+    Gamma's incoming leg outside, the topology of the SDE), Sigma = +1/2 of that closure (the
+    crossed closure flips the sign of the a-channel form's -1/2)."""
+    g0 = bare(V.grid, V.r0)
+    phi = bubble(2, g0, V, P, q_bubble, 0, C_K1 | C_K2P)
+    phi_v = Vertex(V.grid, r0=0.0, ch=[Channel(0.0), Channel(0.0), Channel(1.0, phi.K1, None, phi.K2p, None)])
+    return 0.5 * closure_2_1p(phi_v, P, q_loop)
+
+
+def sde_average(V: Vertex, P: Prop, q_bubble: Quad, q_loop: Quad) -> np.ndarray:
+    """The three ways of evaluating the SDE (its two inner lines read as an a, a p or a t bubble)
+    combined with equal weights (Sec. parquet solver).  Equal in the continuum; on a grid they
+    differ by the discretisation of the bubble, and their mean cancels the part that breaks the
+    evenness of Sigma in U at particle-hole symmetry at third order."""
+    return (sde(V, P, q_bubble, q_loop) + sde_p(V, P, q_bubble, q_loop) + sde_t(V, P, q_bubble, q_loop)) / 3.0
+
+
 def chi_scalar(chi_pair: np.ndarray) -> np.ndarray:
     """chi^R(w) = u^T chi v with u on pairs {(0,0),(1,1)} and v on {(0,1),(1,0)}."""
     m = chi_pair.reshape(chi_pair.shape[:-1] + (4, 4))
@@ -661,12 +717,15 @@ def sigma_prop(grid: Grid, Delta: float, T: float, sigma: Optional[np.ndarray]) 
                 SigK=np.ascontiguousarray(sigma[:, 0]))
 
 
-def parquet_iteration(V: Vertex, P: Prop, q_bubble: Quad, q_loop: Quad):
+def parquet_iteration(V: Vertex, P: Prop, q_bubble: Quad, q_loop: Quad, sde_forms: int = 1):
     """Right-hand sides of the parquet equations for the state (Gamma, Sigma) (Sec. parquet
     solver): the Bethe-Salpeter equations gamma_r = I_r Pi_r Gamma with the irreducible vertex
     I_r = Gamma - gamma_r, symmetrized as 1/2 [B_r(I_r, Gamma) + B_r(Gamma, I_r)], and the
-    Schwinger-Dyson equation (a-channel form) for Sigma.  P carries Sigma of the state.
+    Schwinger-Dyson equation for Sigma: its a-channel form, or with sde_forms = 3 the mean of
+    its three forms.  P carries Sigma of the state.
     Returns ([gamma_a', gamma_p', gamma_t'] as Channels, Sigma' [n, 4])."""
+    if sde_forms not in (1, 3):
+        raise ValueError("sde_forms must be 1 or 3")
     g = V.grid
     out = []
     for r in range(3):
@@ -674,7 +733,7 @@ def parquet_iteration(V: Vertex, P: Prop, q_bubble: Quad, q_loop: Quad):
         a = bubble(r, ir, V, P, q_bubble)
         b = bubble(r, V, ir, P, q_bubble)
         out.append(Channel(1.0, *[0.5 * (getattr(a, c) + getattr(b, c)) for c in CLASSES]))
-    return out, sde(V, P, q_bubble, q_loop)
+    return out, (sde_average if sde_forms == 3 else sde)(V, P, q_bubble, q_loop)
 
 
 class AndersonMixer:
@@ -756,7 +815,7 @@ def _rel_residual(n: int):
 def parquet_solve(grid: Grid, U: float, Delta: float, T: float, q_bubble: Quad, q_loop: Quad,
                   alpha: float = 0.5, iterations: int = 10, tol: float = 0.0, depth: int = 0,
                   reduce_alpha: bool = False, alpha_min: float = 0.01, eps_d: Optional[float] = None,
-                  q_hartree: Optional[Quad] = None, hartree_tol: float = 1e-12):
+                  q_hartree: Optional[Quad] = None, hartree_tol: float = 1e-12, sde_forms: int = 1):
     """Parquet solver (Sec. parquet solver): start from PT2 (vertex K1 in every channel,
     Sigma^(2) from the SDE of Gamma_0), then fixed_point_solve on the state (three channels,
     Sigma) with F = parquet_iteration at the propagator dressed by the state's Sigma; the
@@ -764,7 +823,9 @@ def parquet_solve(grid: Grid, U: float, Delta: float, T: float, q_bubble: Quad, 
     With eps_d (the asymmetric model, Sec. Hartree-Fock) the level of G is eps_d + Sigma_H:
     the PT2 start takes the self-consistent Sigma_H of the bare level, the state carries
     Sigma_H as one more entry, and F updates it once per iteration (one shot, U <n> of the
-    state's propagator).  Without eps_d the level is 0 (particle-hole symmetry).
+    state's propagator).  Without eps_d the level is 0 (particle-hole symmetry).  sde_forms = 3
+    takes Sigma from the mean of the SDE's three forms (the PT2 start is the same: the forms agree
+    at second order).
     Returns (channels, Sigma, residuals per step), plus Sigma_H with eps_d."""
     n = grid.n
     aam = eps_d is not None
@@ -778,7 +839,7 @@ def parquet_solve(grid: Grid, U: float, Delta: float, T: float, q_bubble: Quad, 
         P = sigma_prop(grid, Delta, T, sg)
         if aam:
             P.eps = eps_d + vec[-1].real
-        new, snew = parquet_iteration(Vertex(grid, U, ch), P, q_bubble, q_loop)
+        new, snew = parquet_iteration(Vertex(grid, U, ch), P, q_bubble, q_loop, sde_forms)
         out = state_pack(new, snew)
         if aam:
             h, _ = hartree(U, eps_d, Delta, T, q_hartree, grid, sg, self_consistent=False, sigma_H=vec[-1].real)
