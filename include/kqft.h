@@ -379,6 +379,15 @@ typedef struct {
   double eps_d;        /* bare level (hartree = 1) */
   kqft_quad q_hartree; /* quadrature of the occupation (hartree = 1; full-line map) */
   double hartree_tol;  /* bracket width of the self-consistent Hartree term of the PT2 start */
+  int sde_forms;       /* 1 (or 0): the self-energy from the a-channel form of the SDE (as
+                          kqft_sde); 3: the mean of the SDE's three forms (Sec. "parquet solver"),
+                          its two inner lines read as an a, a p or a t bubble:
+                            Sigma_a = -1/2 L(B_a(Gamma_0, Gamma), G),
+                            Sigma_p = -L(B_p(Gamma_0, Gamma), G),
+                            Sigma_t = +1/2 (B_t(Gamma_0, Gamma) closed between its legs 2 and 1');
+                          the t-form equals the a-form for the crossing-symmetric states of the
+                          solver, which evaluates (2 Sigma_a + Sigma_p) / 3.  Any other value:
+                          KQFT_EINVAL */
 } kqft_parquet_opts;
 
 /*

@@ -44,7 +44,7 @@ struct kqft_ctx {
   // consecutive transfer-frequency batches overlap, ordered by events
   hipStream_t sg = nullptr, sm = nullptr;
   rocblas_handle blas = nullptr;
-  DevBuf adjw, dkf[2][3], phigrad, pq, pqsig, pqred, vtab[3], flow, flowml, ctmp, flowred, pqx, adapt;
+  DevBuf adjw, dkf[2][3], phigrad, pq, pqsig, pqred, vtab[3], flow, flowml, ctmp, flowred, pqx, adapt, sdep;
   std::vector<hipEvent_t> events;
   size_t next_event = 0;
   bool prof = false;
@@ -725,9 +725,48 @@ static int sde_core(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagat
 // Right-hand sides of the parquet equations for the state `V` (Sec. parquet solver): the
 // symmetrized Bethe-Salpeter equations gamma_r' = 1/2 [B_r(I_r, Gamma) + B_r(Gamma, I_r)],
 // I_r = Gamma without channel r, and Sigma' from the Schwinger-Dyson equation.
+static int vloop_core(kqft_ctx* ctx, const kqft_vertex& V, const kqft_propagator& G, int kind, const kqft_quad& q,
+                      double* out, hipStream_t s);
+static void lincomb_n(double2* out, const double2* x, int nt, const double2* const* k, const double* c, size_t count,
+                      hipStream_t s);
+
+// Sigma as the mean of the three forms of the SDE (its two inner lines read as an a, a p or a
+// t bubble).  The t-form equals the a-form for every crossing-symmetric vertex (the crossing
+// 1 <-> 2 maps the one closure onto the other in the discrete scheme), which the states of the
+// parquet solver are; so Sigma = (2 Sigma_a + Sigma_p) / 3 with
+// Sigma_p = -L(B_p(Gamma_0, Gamma), G), B_p carrying its prefactor 1/2.
+static int sde_mean_core(kqft_ctx* ctx, const kqft_vertex& V, const kqft_propagator& G, const kqft_quad& qb,
+                         const kqft_quad& ql, const kqft_opts& opts, double* sigma, hipStream_t s) {
+  int rc;
+  if ((rc = sde_core(ctx, &V, &G, &qb, &ql, &opts, sigma, nullptr, s))) return rc;
+  const int n = V.grid.n;
+  const size_t k1b = (size_t)2 * n * 16 * 16;
+  double2* phiK1 = (double2*)ctx->phi.p;  // sized by sde_core for K1 and K2'
+  double2* phiK2p = (double2*)((char*)ctx->phi.p + k1b);
+  kqft_vertex bare;
+  memset(&bare, 0, sizeof bare);
+  bare.r0 = V.r0;
+  bare.grid = V.grid;
+  kqft_opts o = opts;
+  o.class_mask = KQFT_K1 | KQFT_K2P;
+  o.beta = 0;
+  BubbleOut po{phiK1, nullptr, phiK2p, nullptr};
+  if ((rc = bubble_core(ctx, KQFT_CH_P, bare, V, G, KQFT_PI_GG, qb, o, po, s))) return rc;
+  kqft_vertex pv;
+  memset(&pv, 0, sizeof pv);
+  pv.grid = V.grid;
+  pv.ch[KQFT_CH_P] = kqft_chvert{1.0, (const double*)phiK1, nullptr, (const double*)phiK2p, nullptr};
+  if ((rc = ensure(ctx->sdep, (size_t)n * 4 * sizeof(double2)))) return rc;
+  if ((rc = vloop_core(ctx, pv, G, KQFT_LINE_G, ql, (double*)ctx->sdep.p, s))) return rc;
+  const double2* k[2] = {(const double2*)sigma, (const double2*)ctx->sdep.p};
+  const double c[2] = {2.0 / 3.0, -1.0 / 3.0};
+  lincomb_n((double2*)sigma, nullptr, 2, k, c, (size_t)n * 4, s);
+  return KQFT_OK;
+}
+
 static int parquet_core(kqft_ctx* ctx, const kqft_vertex& V, const kqft_propagator& G, const kqft_quad& qb,
                         const kqft_quad& ql, const kqft_opts& opts, const BubbleOut out[3], double* sigma_out,
-                        hipStream_t s) {
+                        hipStream_t s, int sde_forms = 1) {
   int rc;
   kqft_opts o = opts;
   o.class_mask = KQFT_KALL;
@@ -739,6 +778,7 @@ static int parquet_core(kqft_ctx* ctx, const kqft_vertex& V, const kqft_propagat
     o.beta = 1;
     if ((rc = bubble_core(ctx, r, V, I, G, KQFT_PI_GG, qb, o, out[r], s, 0.5))) return rc;
   }
+  if (sde_forms == 3) return sde_mean_core(ctx, V, G, qb, ql, opts, sigma_out, s);
   return sde_core(ctx, &V, &G, &qb, &ql, &opts, sigma_out, nullptr, s);
 }
 
@@ -768,8 +808,8 @@ static int rel_change(kqft_ctx* ctx, const std::vector<std::pair<const double2*,
   return KQFT_OK;
 }
 
-// out = x + sum_{j < nt} c_j k_j (x may be null), in launches of at most six terms; out must
-// not alias any k_j
+// out = x + sum_{j < nt} c_j k_j (x may be null), in launches of at most six terms; out may
+// alias x, and alias a k_j only when nt <= 6 (one launch, each entry read before it is written)
 static void lincomb_n(double2* out, const double2* x, int nt, const double2* const* k, const double* c, size_t count,
                      hipStream_t s) {
   int j0 = 0;
@@ -929,7 +969,7 @@ int kqft_ctx_destroy(kqft_ctx* ctx) {
       if (b.p) (void)hipFree(b.p);
   if (ctx->adjw.p) (void)hipFree(ctx->adjw.p);
   for (DevBuf* b : {&ctx->pq, &ctx->pqsig, &ctx->pqred, &ctx->vtab[0], &ctx->vtab[1], &ctx->vtab[2], &ctx->flow,
-                    &ctx->flowml, &ctx->ctmp, &ctx->flowred, &ctx->pqx, &ctx->adapt})
+                    &ctx->flowml, &ctx->ctmp, &ctx->flowred, &ctx->pqx, &ctx->adapt, &ctx->sdep})
     if (b->p) (void)hipFree(b->p);
   if (ctx->phigrad.p) (void)hipFree(ctx->phigrad.p);
   if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
@@ -1743,6 +1783,8 @@ int kqft_parquet_solve(kqft_ctx* ctx, const kqft_grid* grid, double U, double De
   if (po.anderson_depth < 0 || po.anderson_depth > 32) return fail(KQFT_EINVAL, "need 0 <= anderson_depth <= 32");
   if (po.reduce_alpha && (!(po.alpha_min > 0) || po.alpha_min > po.alpha))
     return fail(KQFT_EINVAL, "need 0 < alpha_min <= alpha");
+  if (po.sde_forms != 0 && po.sde_forms != 1 && po.sde_forms != 3) return fail(KQFT_EINVAL, "sde_forms must be 1 or 3");
+  const int forms = po.sde_forms == 3 ? 3 : 1;
   const bool aam = po.hartree != 0;
   if (aam) {
     const kqft_quad& qh = po.q_hartree;
@@ -1855,7 +1897,7 @@ int kqft_parquet_solve(kqft_ctx* ctx, const kqft_grid* grid, double U, double De
       HIP_TRY(hipMemcpyAsync(g + 3 * chc + 4 * n, &hn, sizeof hn, hipMemcpyHostToDevice, s));
       HIP_TRY(hipStreamSynchronize(s));
     }
-    if ((rc = parquet_core(ctx, V, Gs, *q_bubble, *q_loop, *opts, F, (double*)(g + 3 * chc), s))) return rc;
+    if ((rc = parquet_core(ctx, V, Gs, *q_bubble, *q_loop, *opts, F, (double*)(g + 3 * chc), s, forms))) return rc;
     double res = 0.0;
     if ((rc = rel_change(ctx, xf, counts, s, &res))) return rc;
     {  // f = g - x

@@ -58,7 +58,8 @@ class KqftFlowOpts(C.Structure):
 class KqftParquetOpts(C.Structure):
     _fields_ = [("alpha", C.c_double), ("max_iterations", C.c_int), ("tol", C.c_double),
                 ("anderson_depth", C.c_int), ("reduce_alpha", C.c_int), ("alpha_min", C.c_double),
-                ("hartree", C.c_int), ("eps_d", C.c_double), ("q_hartree", KqftQuad), ("hartree_tol", C.c_double)]
+                ("hartree", C.c_int), ("eps_d", C.c_double), ("q_hartree", KqftQuad), ("hartree_tol", C.c_double),
+                ("sde_forms", C.c_int)]
 
 
 class KqftAdaptInfo(C.Structure):
@@ -434,9 +435,10 @@ def hartree(U: float, eps_d: float, G: Propagator, q: Quad, self_consistent: boo
 def parquet_solve(grid: Grid, U: float, Delta: float, T: float, q_bubble: Quad, q_loop: Quad, alpha: float = 0.5,
                   max_iterations: int = 20, tol: float = 0.0, precision: int = FP64, depth: int = 0,
                   reduce_alpha: bool = False, alpha_min: float = 0.01, eps_d: Optional[float] = None,
-                  q_hartree: Optional[Quad] = None, hartree_tol: float = 1e-12, stream=None):
+                  q_hartree: Optional[Quad] = None, hartree_tol: float = 1e-12, sde_forms: int = 1, stream=None):
     """Parquet solver from the PT2 state with linear mixing or Anderson acceleration of the
-    given depth; with eps_d, the asymmetric model with the Hartree term in the state.
+    given depth; with eps_d, the asymmetric model with the Hartree term in the state;
+    sde_forms = 3 takes the mean of the three forms of the SDE.
     Returns (channels, Sigma, residuals), plus Sigma_H with eps_d."""
     n = grid.n
     outs = [alloc_channel(n) for _ in range(3)]
@@ -452,7 +454,7 @@ def parquet_solve(grid: Grid, U: float, Delta: float, T: float, q_bubble: Quad, 
         raise ValueError("the asymmetric model needs q_hartree")
     qh = q_hartree.c() if aam else KqftQuad(1, QUAD_TAN_INFINITE, 0.0, 1.0)
     po = KqftParquetOpts(alpha, max_iterations, tol, depth, int(reduce_alpha), alpha_min, int(aam),
-                         eps_d if aam else 0.0, qh, hartree_tol)
+                         eps_d if aam else 0.0, qh, hartree_tol, sde_forms)
     _check(lib().kqft_parquet_solve(ctx(), C.byref(gc), C.c_double(U), C.c_double(Delta), C.c_double(T),
                                     C.byref(qb), C.byref(ql), C.byref(_opts(precision, KALL, 0, 0)), C.byref(po),
                                     D, C.c_void_p(sigma.data_ptr()), C.byref(sH), res, C.byref(its),

@@ -87,6 +87,41 @@ def test_parquet_solver_anderson_and_reduction_match_oracle(U_, alpha, depth, re
     assert np.abs(sig.cpu().numpy() - osig).max() < 1e-9 * np.abs(osig).max()
 
 
+@pytest.mark.parametrize("eps_d", [None, -0.3])
+def test_parquet_solver_with_the_mean_of_the_sde_forms_matches_oracle(eps_d):
+    """sde_forms = 3: the self-energy as the mean of the SDE's a-, p- and t-forms (the oracle
+    evaluates all three, the device (2 Sigma_a + Sigma_p) / 3 for the crossing-symmetric states);
+    residuals and final state as the oracle's, at particle-hole symmetry and in the asymmetric
+    model (whose states stay crossing symmetric too)."""
+    K = _K()
+    n, nq, iters = 9, 31, 6
+    qh = (4001, 1, 0.0, 1.0)
+    ow = {} if eps_d is None else {"eps_d": eps_d, "q_hartree": O.Quad(*qh), "hartree_tol": 1e-13}
+    kw = {} if eps_d is None else {"eps_d": eps_d, "q_hartree": K.Quad(*qh), "hartree_tol": 1e-13}
+    tol = 1e-11 if eps_d is None else 1e-9
+    ores = O.parquet_solve(O.Grid(n), U, D, T, O.Quad(nq), O.Quad(nq), alpha=0.5, iterations=iters, sde_forms=3, **ow)
+    kres = K.parquet_solve(K.Grid(n), U, D, T, K.Quad(nq), K.Quad(nq), alpha=0.5, max_iterations=iters, sde_forms=3,
+                           **kw)
+    torch.cuda.synchronize()
+    ochans, osig, ors = ores[:3]
+    chans, sig, res = kres[:3]
+    print(f"eps_d={eps_d}: residuals {['%.2e' % x for x in res]}", flush=True)
+    assert len(res) == iters
+    assert np.allclose(res, ors, rtol=100 * tol, atol=0)
+    for r in range(3):
+        for x in CL:
+            a, b = getattr(chans[r], x).cpu().numpy(), getattr(ochans[r], x)
+            assert np.abs(a - b).max() < tol * np.abs(b).max(), (r, x)
+    assert np.abs(sig.cpu().numpy() - osig).max() < tol * np.abs(osig).max()
+    if eps_d is not None:
+        assert abs(kres[3] - ores[3]) < 1e-10
+    # the a-form alone gives another self-energy: the option reaches the device
+    sig1 = K.parquet_solve(K.Grid(n), U, D, T, K.Quad(nq), K.Quad(nq), alpha=0.5, max_iterations=iters, **kw)[1]
+    assert float((sig1 - sig).abs().max()) > 1e-6 * float(sig.abs().max())
+    with pytest.raises(K.KqftError):
+        K.parquet_solve(K.Grid(n), U, D, T, K.Quad(nq), K.Quad(nq), max_iterations=1, sde_forms=2)
+
+
 def test_parquet_solver_n51_anderson_converges_faster():
     """N = 51, N_q = 501, U = 1: twelve iterations with Anderson depth 4 against linear mixing
     (split-FP32 bubbles); the accelerated residual ends an order of magnitude lower."""
