@@ -113,7 +113,9 @@ typedef struct {
 // reg selects the flow parameter Lambda of S = dG/dLambda at fixed Sigma (Sec. "Flow
 // schemes"): 0 Delta (Lambda = Delta), 1 interaction flow (G_0 -> Lambda G_0, Lambda = lam),
 // 2 temperature (Lambda = T), 3 frequency regulator Theta = v/(v + i lam) (Lambda = lam).
-// dSigR/dSigK: optional Sigma_dot on the Sigma grid (Katanin: S -> S + G Sigma_dot G).
+// dSigR/dSigK: optional Sigma_dot on the Sigma grid (Katanin: S -> S + G Sigma_dot G);
+// deps: a frequency-independent real part of Sigma_dot^R (the flow of the level eps), added to
+// dSigR in the G Sigma_dot G line.
 typedef struct {
   double Delta, dDelta, T, eps;
   int sn;
@@ -124,6 +126,7 @@ typedef struct {
   double lam;
   const double* dSigR;
   const double* dSigK;
+  double deps;
 } OProp;
 // quadrature: n Gauss-Legendre nodes, map 0 = tangent onto [-L, L] with scale a,
 // map 1 = v = a tan(pi y / 2) onto the real line.
@@ -299,9 +302,9 @@ template <class S> static void propagator(const OProp& P, int kind, double v, Cx
     R = SR;
     K = SR * br * GA + GR * dbr * GA + GR * br * conj(SR);
   }
-  if ((kind == 1 || kind == 2) && P.dSigR) {
+  if ((kind == 1 || kind == 2) && (P.dSigR || P.deps != 0.0)) {
     // G Sigma_dot G: R = G^R s^R G^R, K = G^R s^R G^K + G^R s^K G^A + G^K s^A G^A
-    const Cx<S> dR = sigma_interp<S>(P, P.dSigR, v);
+    const Cx<S> dR = sigma_interp<S>(P, P.dSigR, v) + lift<S>(P.deps, 0.0);
     const Cx<S> dK = sigma_interp<S>(P, P.dSigK, v);
     R = R + GR * dR * GR;
     K = K + GR * dR * GK + GR * dK * GA + GK * conj(dR) * GA;

@@ -53,7 +53,7 @@ class OProp(C.Structure):
     _fields_ = [("Delta", C.c_double), ("dDelta", C.c_double), ("T", C.c_double), ("eps", C.c_double),
                 ("sn", C.c_int), ("sL", C.c_double), ("sa", C.c_double),
                 ("SigR", C.c_void_p), ("SigK", C.c_void_p), ("reg", C.c_int), ("lam", C.c_double),
-                ("dSigR", C.c_void_p), ("dSigK", C.c_void_p)]
+                ("dSigR", C.c_void_p), ("dSigK", C.c_void_p), ("deps", C.c_double)]
 
 
 class OQuad(C.Structure):
@@ -143,7 +143,8 @@ class Prop:
     Sigma^R) with G_0^{-1,R} = v - eps + i Delta (regulator reg = REG_DELTA or REG_T),
     (v - eps + i Delta) / lam (REG_U) or (v - eps + i Delta)(v + i lam)/v (REG_NU); G^K by the
     general Keldysh relation with the FDR for the bath; optional dynamic Sigma on a grid and
-    optional Sigma_dot there (Katanin substitution in the single-scale propagator)."""
+    optional Sigma_dot there (Katanin substitution in the single-scale propagator); deps is a
+    frequency-independent real part of Sigma_dot^R (the flow of the level), added to it."""
     Delta: float = 1.0
     T: float = 0.1
     eps: float = 0.0
@@ -155,11 +156,12 @@ class Prop:
     lam: float = 1.0
     dSigR: Optional[np.ndarray] = None
     dSigK: Optional[np.ndarray] = None
+    deps: float = 0.0
 
     def c(self, keep: list) -> OProp:
         g = self.sigma_grid or Grid(2)
         p = OProp(self.Delta, self.dDelta, self.T, self.eps, g.n, g.L, g.a, None, None, self.reg, self.lam,
-                  None, None)
+                  None, None, self.deps)
         if (self.dSigR is None) != (self.dSigK is None):
             raise ValueError("Sigma_dot needs both its retarded and its Keldysh component")
         for name in ("SigR", "SigK", "dSigR", "dSigK"):
@@ -896,10 +898,13 @@ def flow_dlambda_dt(reg: int, t: float) -> float:
     return 5.0 * abs(t) * (2.0 - t * t) / (1.0 - t * t) ** 1.5 if reg == REG_DELTA else 1.0
 
 
-def flow_prop(grid: Grid, reg: int, lam: float, Delta: float, T: float, sigma, dsigma=None) -> Prop:
+def flow_prop(grid: Grid, reg: int, lam: float, Delta: float, T: float, sigma, dsigma=None, eps: float = 0.0,
+              deps: float = 0.0) -> Prop:
     """Propagator at flow parameter lam: the hybridization for the Delta-flow, the
-    temperature for the T-flow, the regulator parameter of the interaction and frequency flows."""
+    temperature for the T-flow, the regulator parameter of the interaction and frequency flows;
+    level eps, and deps the flow of the level in the G Sigma_dot G line."""
     P = sigma_prop(grid, Delta, T, sigma)
+    P.eps, P.deps = eps, deps
     if reg == REG_DELTA:
         P.Delta = lam
     elif reg == REG_T:
@@ -949,8 +954,28 @@ class FlowOptions:
     max_steps: int = 200
 
 
+def loop_static(V: Vertex, P: Prop, q: Quad, kind: int = 0) -> np.ndarray:
+    """The loop L(Gamma, X) for |v| beyond the grid, its asymptotic value (Sec. loop function: for
+    the asymmetric model it is taken from the Hartree term and the t-channel classes).  In the
+    loop's legs (v, v_j | v, v_j) the t channel has transfer frequency 0 and first fermionic
+    frequency v_j, so Gamma_0, K1_t(0) and K2_t(0, v_j) do not depend on v; every other class is
+    read at a frequency that grows with v and is zero beyond the grid.  Returns the [4] vector
+    (index 2 a1' + a1): the loop of that static part of Gamma, the same at every grid point."""
+    t = V.ch[2]
+    sv = Vertex(V.grid, V.r0, [Channel(0.0), Channel(0.0), Channel(t.coef, t.K1, t.K2, None, None)], dr0=V.dr0)
+    return loop(sv, P, q, kind)[0]
+
+
+def _split_level(full: np.ndarray, s: float) -> np.ndarray:
+    """Sigma_dot on the grid minus the real constant s in its retarded and advanced components."""
+    out = full.copy()
+    out[:, 1] -= s
+    out[:, 2] -= s
+    return out
+
+
 def mfrg_rhs(grid: Grid, U: float, T: float, lam: float, nloops: int, q_bubble: Quad, q_loop: Quad, chans, sigma,
-             fo: Optional[FlowOptions] = None, info: Optional[dict] = None):
+             fo: Optional[FlowOptions] = None, info: Optional[dict] = None, eps: Optional[float] = None):
     """Right-hand side of the flow (Sec. mfRG) at flow parameter lam:
       Sigma_dot^(1) = -L(Gamma, S)                            (one-loop self-energy flow)
       Gamma_dot     = sum_{l <= nloops} gdot^(l), with the l = 1 bubble differentiated along
@@ -962,16 +987,35 @@ def mfrg_rhs(grid: Grid, U: float, T: float, lam: float, nloops: int, q_bubble: 
     re-evaluating Gamma_dot with the new Sigma_dot after each update.  The correction loop is
     the fixed-point iteration Sigma_dot = F(Sigma_dot); with se_anderson > 0 the next iterate
     is the AndersonMixer step (mixing factor 1) of that depth instead of F(Sigma_dot) itself,
-    and the right-hand side returned is still F of the last iterate with its Gamma_dot."""
+    and the right-hand side returned is still F of the last iterate with its Gamma_dot.
+
+    With eps (the asymmetric model, level eps = eps_d + Sigma_inf of G) the self-energy is split
+    into the real constant Sigma_inf, its value beyond the grid, and the rest on the grid: every
+    loop L contributes ds = -Re of the retarded component of its asymptotic value (loop_static)
+    to d Sigma_inf and its grid values minus ds (retarded and advanced components) to the rest;
+    the G Sigma_dot G lines carry both (ds as the flow of the level).  The correction loop
+    -L(gdot_{a,C} + gdot_{p,C}, G) has no asymptotic part (no bare vertex, no t channel).
+    Returns (Gamma_dot, Sigma_dot of the rest), plus d Sigma_inf when eps is given."""
     fo = fo or FlowOptions()
-    P = flow_prop(grid, fo.reg, lam, fo.Delta, T, sigma)
+    aam = eps is not None
+    e0 = eps if aam else 0.0
+    P = flow_prop(grid, fo.reg, lam, fo.Delta, T, sigma, eps=e0)
     V = Vertex(grid, U, chans)
-    sd1 = -loop(V, P, q_loop, kind=1)
-    sd = sd1
+
+    def part(Px, kind):
+        full = -loop(V, Px, q_loop, kind=kind)
+        if not aam:
+            return full, 0.0
+        ds = float((-loop_static(V, Px, q_loop, kind))[1].real)
+        return _split_level(full, ds), ds
+
+    sd1, ds1 = part(P, 1)
+    sd, ds = sd1, ds1
     it = 0
     mixer = AndersonMixer(fo.se_anderson, 1.0)
     while True:
-        Pk = flow_prop(grid, fo.reg, lam, fo.Delta, T, sigma, sd if fo.katanin else None)
+        Pk = flow_prop(grid, fo.reg, lam, fo.Delta, T, sigma, sd if fo.katanin else None, eps=e0,
+                       deps=ds if fo.katanin else 0.0)
         cen = []
         ins = mloop(V, Pk, q_bubble, nloops, centres=cen)
         if fo.se_iterations <= 0 or nloops < 3:
@@ -979,19 +1023,26 @@ def mfrg_rhs(grid: Grid, U: float, T: float, lam: float, nloops: int, q_bubble: 
         ca = Channel(1.0, *[sum(getattr(cen[l][0], c) for l in range(len(cen))) for c in CLASSES])
         cp = Channel(1.0, *[sum(getattr(cen[l][1], c) for l in range(len(cen))) for c in CLASSES])
         tbar = -loop(Vertex(grid, 0.0, [ca, cp, Channel(0.0)]), P, q_loop, kind=0)
-        st = -loop(V, flow_prop(grid, fo.reg, lam, fo.Delta, T, sigma, tbar), q_loop, kind=2)
-        new = sd1 + tbar + st
-        change = float(np.abs(new - sd).max())
+        st, dst = part(flow_prop(grid, fo.reg, lam, fo.Delta, T, sigma, tbar, eps=e0), 2)
+        new, dnew = sd1 + tbar + st, ds1 + dst
+        change = max(float(np.abs(new - sd).max()), abs(dnew - ds))
         it += 1
-        if change <= fo.se_atol + fo.se_rtol * float(np.abs(new).max()) or it >= fo.se_iterations:
-            sd = new
+        if change <= fo.se_atol + fo.se_rtol * max(float(np.abs(new).max()), abs(dnew)) or it >= fo.se_iterations:
+            sd, ds = new, dnew
             break
-        sd = mixer.step(sd, new) if fo.se_anderson > 0 else new
+        if fo.se_anderson > 0:
+            if aam:
+                mixed = mixer.step(np.concatenate([sd.ravel(), [ds + 0j]]), np.concatenate([new.ravel(), [dnew + 0j]]))
+                sd, ds = mixed[:-1].reshape(sd.shape), float(mixed[-1].real)
+            else:
+                sd = mixer.step(sd, new)
+        else:
+            sd, ds = new, dnew
     if info is not None:
         info["se_iterations"] = info.get("se_iterations", 0) + it
         info["rhs"] = info.get("rhs", 0) + 1
     gdot = [Channel(1.0, *[sum(getattr(ins[l][r], c) for l in range(nloops)) for c in CLASSES]) for r in range(3)]
-    return gdot, sd
+    return (gdot, sd, ds) if aam else (gdot, sd)
 
 
 # Cash-Karp embedded Runge-Kutta pair (Cash and Karp 1990): nodes, stage matrix, weights of
@@ -1062,21 +1113,37 @@ def ode_solve(f, y0: np.ndarray, t0: float, t1: float, steps: int, adaptive: boo
 
 
 def mfrg_flow(grid: Grid, U: float, T: float, lam_i: float, lam_f: float, steps: int, nloops: int,
-              q_bubble: Quad, q_loop: Quad, chans, sigma, fo: Optional[FlowOptions] = None):
+              q_bubble: Quad, q_loop: Quad, chans, sigma, fo: Optional[FlowOptions] = None,
+              eps_d: Optional[float] = None, sigma_inf: float = 0.0):
     """Integrate the flow (mfrg_rhs) of the state (chans, sigma) from lam_i to lam_f (Sec. ODE
-    solver).  Returns (chans, sigma, info) with info["lambdas"] the accepted flow parameters."""
+    solver).  With eps_d, the asymmetric model: the state carries the real constant sigma_inf
+    (the self-energy beyond the grid; the level of G is eps_d + sigma_inf) as one more entry,
+    and sigma is the rest on the grid.  Returns (chans, sigma, info) with info["lambdas"] the
+    accepted flow parameters and, with eps_d, info["sigma_inf"]."""
     fo = fo or FlowOptions()
     n = grid.n
     info = {}
+    aam = eps_d is not None
 
     def f(t, vec):
+        if aam:
+            ch, sg = state_unpack(vec[:-1], n)
+            gd, sd, ds = mfrg_rhs(grid, U, T, flow_lambda(fo.reg, t), nloops, q_bubble, q_loop, ch, sg, fo, info,
+                                  eps=eps_d + vec[-1].real)
+            return flow_dlambda_dt(fo.reg, t) * np.concatenate([state_pack(gd, sd), [ds + 0j]])
         ch, sg = state_unpack(vec, n)
         gd, sd = mfrg_rhs(grid, U, T, flow_lambda(fo.reg, t), nloops, q_bubble, q_loop, ch, sg, fo, info)
         return flow_dlambda_dt(fo.reg, t) * state_pack(gd, sd)
 
-    y, ts, rej = ode_solve(f, state_pack(chans, sigma), flow_t(fo.reg, lam_i), flow_t(fo.reg, lam_f), steps,
+    y0 = state_pack(chans, sigma)
+    if aam:
+        y0 = np.concatenate([y0, [sigma_inf + 0j]])
+    y, ts, rej = ode_solve(f, y0, flow_t(fo.reg, lam_i), flow_t(fo.reg, lam_f), steps,
                            fo.adaptive, fo.atol, fo.rtol, fo.max_steps)
     info["lambdas"] = [flow_lambda(fo.reg, t) for t in ts]
     info["rejected"] = rej
+    if aam:
+        info["sigma_inf"] = float(y[-1].real)
+        y = y[:-1]
     ch, sg = state_unpack(y, n)
     return ch, sg, info

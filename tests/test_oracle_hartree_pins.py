@@ -2,7 +2,10 @@
 Lorentzian level against its closed form at finite temperature (digamma function), the
 self-consistent term at particle-hole symmetry, the Friedel sum rule as T -> 0, and the
 one-shot term with a dynamic self-energy against an independent adaptive integration, and
-the asymmetric parquet solver at eps_d = -U/2 reproducing the particle-hole symmetric one.""" 
+the asymmetric parquet solver at eps_d = -U/2 reproducing the particle-hole symmetric one.
+The asymmetric mfRG flow: the asymptotic value of the loop (Gamma_0 and the t-channel classes
+read at zero transfer frequency), its first-order flow as the Hartree term's, and the flow at
+eps_d = -U/2 reproducing the symmetric one."""
 import numpy as np
 import scipy.integrate as si
 import scipy.special as sp
@@ -93,3 +96,69 @@ def test_asymmetric_parquet_solver_contracts_with_the_hartree_entry():
     _, _, res, sH = O.parquet_solve(g, U, D, 0.1, q, q, iterations=6, eps_d=eps_d, q_hartree=Q)
     assert 0.0 < sH < U and res[-1] < 0.15 * res[0]
     assert res[-1] < res[-2] < res[-3]
+
+
+# ---------------------------------------------------------------- asymmetric mfRG flow
+def _zero_state(n):
+    z = lambda sh: np.zeros(sh, complex)
+    return [O.Channel(1.0, z((2, n, 16)), z((2, n, n, 16)), z((2, n, n, 16)), z((2, n, n, n, 16))) for _ in range(3)]
+
+
+def test_static_part_of_the_loop_is_the_same_at_every_frequency():
+    """In the loop's legs (v, v_j | v, v_j) the t channel sits at transfer frequency 0 with first
+    fermionic frequency v_j: a vertex made of Gamma_0, K1_t and K2_t gives the same loop at every
+    grid frequency -- the asymptotic value the flow of the asymmetric model carries beyond the
+    grid -- and loop_static is that value for any vertex; adding K2'_t (read at v) breaks it."""
+    from workload import random_channel
+    n = 9
+    g, q, P = O.Grid(n), O.Quad(31), O.Prop(D, 0.1, eps=0.3)
+    c = random_channel(n, 7, 0.3)
+    Vs = O.Vertex(g, 1.0, [O.Channel(0.0), O.Channel(0.0), O.Channel(0.8, c["K1"], c["K2"], None, None)])
+    L = O.loop(Vs, P, q)
+    assert np.abs(L - L[0]).max() < 1e-13 * np.abs(L).max()
+    full = [random_channel(n, s_, 0.3) for s_ in (1, 2)]
+    V = O.Vertex(g, 1.0, [O.Channel(1.0, *[f[x] for x in O.CLASSES]) for f in full]
+                 + [O.Channel(0.8, c["K1"], c["K2"], c["K2p"], c["K3"])])
+    assert np.abs(O.loop_static(V, P, q) - L[0]).max() < 1e-14 * np.abs(L).max()
+    Vp = O.Vertex(g, 1.0, [O.Channel(0.0), O.Channel(0.0), O.Channel(0.8, c["K1"], c["K2"], c["K2p"], None)])
+    Lp = O.loop(Vp, P, q)
+    assert np.abs(Lp - Lp[0]).max() > 1e-3 * np.abs(Lp).max()
+
+
+def test_asymmetric_flow_of_the_asymptotic_value_is_the_hartree_flow_at_first_order():
+    """Flowing the bare state (Gamma = Gamma_0, Sigma = 0) of the level eps_d from Delta = 2 to 1,
+    the self-energy beyond the grid changes by U [<n>(Delta = 1) - <n>(Delta = 2)] + O(U^2),
+    <n> the occupation of the bare level (pinned above against its closed form): the first-order
+    flow -L(Gamma_0, S) is the Delta-derivative of the Hartree term.  The relative deviation
+    halves with U."""
+    n = 9
+    g, qb, ql = O.Grid(n), O.Quad(31), O.Quad(401, 1, 0.0, 1.0)
+    T, ed = 0.1, 0.4
+    devs = []
+    for U in (0.1, 0.05):
+        _, _, info = O.mfrg_flow(g, U, T, 2.0, 1.0, 4, 1, qb, ql, _zero_state(n), np.zeros((n, 4), complex),
+                                 O.FlowOptions(), eps_d=ed, sigma_inf=0.0)
+        ref = U * (O.occupation(ed, 1.0, T, Q) - O.occupation(ed, 2.0, T, Q))
+        assert abs(ref) > 1e-3 * U
+        devs.append(abs(info["sigma_inf"] - ref) / abs(ref))
+    assert devs[0] < 0.03 and 0.4 < devs[1] / devs[0] < 0.6
+
+
+def test_asymmetric_flow_at_half_filling_is_the_symmetric_flow():
+    """At eps_d = -U/2 with the Hartree value U/2 as the initial self-energy beyond the grid, the
+    asymmetric flow (level eps_d + Sigma_inf, Sigma_inf flowing with the asymptotic value of the
+    loops) is the symmetric flow: Sigma_inf stays U/2 (the static part of Sigma vanishes at
+    particle-hole symmetry) and the channels and the rest of Sigma agree to rounding; multiloop
+    order 3, Katanin, self-energy corrections."""
+    n, U, T = 9, 1.0, 0.1
+    g, q = O.Grid(n), O.Quad(31)
+    chans, sig = O.pt2_state(g, U, 2.0, T, q, q)
+    fo = O.FlowOptions(se_iterations=3)
+    c1, s1, _ = O.mfrg_flow(g, U, T, 2.0, 1.0, 2, 3, q, q, chans, sig, fo)
+    c2, s2, info = O.mfrg_flow(g, U, T, 2.0, 1.0, 2, 3, q, q, chans, sig, fo, eps_d=-U / 2, sigma_inf=U / 2)
+    assert abs(info["sigma_inf"] - U / 2) < 1e-14
+    assert np.abs(s2 - s1).max() < 1e-13 * np.abs(s1).max()
+    for r in range(3):
+        for x in O.CLASSES:
+            a, b = getattr(c2[r], x), getattr(c1[r], x)
+            assert np.abs(a - b).max() <= 1e-13 * max(np.abs(b).max(), 1e-300), (r, x)
