@@ -123,7 +123,9 @@ typedef struct {
    FDR Sigma^K = 2i tanh(v/2T) Im Sigma^R).  dSigR/dSigK: optional Sigma_dot on sgrid (both
    or neither); with them the single-scale line becomes S + G Sigma_dot G (Katanin) and the
    GSG line of a loop is G Sigma_dot G,
-     (G s G)^R = G^R s^R G^R,  (G s G)^K = G^R s^R G^K + G^R s^K G^A + G^K s^A G^A.
+     (G s G)^R = G^R s^R G^R,  (G s G)^K = G^R s^R G^K + G^R s^K G^A + G^K s^A G^A;
+   deps, a real constant added to s^R and s^A at every frequency (the flow of the level eps),
+   enters the same lines (alone too, without dSigR/dSigK).
    A zero-initialised struct (reg 0, no Sigma_dot) is the plain Delta-regulated propagator. */
 typedef struct {
   double Delta, T, eps;
@@ -134,6 +136,7 @@ typedef struct {
   double lam; /* regulator parameter of reg U (> 0) and NU (> 0); unused otherwise */
   const double* dSigR;
   const double* dSigK;
+  double deps; /* 0 unless the level flows (asymmetric model) */
 } kqft_propagator;
 
 /* output classes of one channel (device arrays, layouts as above; NULL = skip) */
@@ -311,6 +314,12 @@ typedef struct {
   double ode_tol_abs;    /* accept a step when max_i |e_i| / (abs + rel max(|y_i|, |y4_i|)) <= 1 */
   double ode_tol_rel;
   int max_steps;         /* accepted + rejected steps (adaptive); KQFT_ENOCONV beyond */
+  int asymmetric;        /* 0: particle-hole symmetric model (level 0, Hartree U/2 absorbed);
+                            1: asymmetric model (Sec. "Hartree-Fock", Sec. "The loop function"):
+                            the level of G is eps_d + Sigma_inf, Sigma_inf the self-energy's
+                            asymptotic value (real, beyond the grid), one more state entry */
+  double eps_d;          /* bare level (asymmetric) */
+  double sigma_inf;      /* initial Sigma_inf (asymmetric; e.g. the Hartree term of kqft_hartree) */
 } kqft_flow_opts;
 
 /* what a flow did */
@@ -319,6 +328,7 @@ typedef struct {
   int rejected;          /* rejected trial steps */
   int rhs_evaluations;   /* right-hand sides evaluated */
   int se_iterations;     /* self-energy correction iterations, summed over the right-hand sides */
+  double sigma_inf;      /* final Sigma_inf (asymmetric; 0 otherwise) */
 } kqft_flow_info;
 
 /*
@@ -338,6 +348,15 @@ typedef struct {
  * the fourth-order solution with the first trial step (t_f - t_i)/steps, growth by
  * min(5, 0.9 err^-1/5) after an accepted and shrinkage by max(0.1, 0.9 err^-1/4) after a
  * rejected step, the last step cut to land on t_f.
+ * Asymmetric model (asymmetric = 1): Sigma = Sigma_inf + sigma with the real constant Sigma_inf
+ * carried as the level (G_0 at eps_d + Sigma_inf) and sigma on the grid, zero beyond it.
+ * Every loop L(Gamma, X) above also yields its asymptotic value: the loop of the part of Gamma
+ * that does not depend on the external frequency in the loop's legs (v, v_j | v, v_j) -- the
+ * bare vertex and the t-channel classes K1_t(0) and K2_t(0, v_j), the t channel sitting at
+ * transfer frequency 0 -- the same at every v; d Sigma_inf takes minus its real retarded part,
+ * and the grid values of that loop minus the same constant (retarded and advanced components)
+ * go to sigma_dot.  The G Sigma_dot G lines carry the constant as the flow of the level
+ * (kqft_propagator.deps).  The correction loop of the centre terms has no such part.
  * State in/out: gamma[3] (the three channels, all four classes, device) and sigma (device
  * [n][4], Sigma^K at index 0 and Sigma^R at 1, on grid).  lambdas (host, capacity
  * max_steps + 1 for adaptive, steps + 1 otherwise, or NULL): the accepted Lambda values,

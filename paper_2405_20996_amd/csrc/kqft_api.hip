@@ -221,6 +221,8 @@ static int to_dprop(const kqft_propagator& p, DProp& d) {
   d.lam = p.lam;
   d.dSigR = (const double2*)p.dSigR;
   d.dSigK = (const double2*)p.dSigK;
+  if (!std::isfinite(p.deps)) return fail(KQFT_EINVAL, "deps must be finite");
+  d.deps = p.deps;
   if (p.SigR || p.SigK || p.dSigR) {
     int rc = check_grid(p.sgrid, "propagator self-energy grid");
     if (rc) return rc;
@@ -1298,7 +1300,8 @@ int kqft_loop(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G,
       (q->map == KQFT_QUAD_TAN_FINITE && !(q->L > 0)) || !(q->a > 0))
     return fail(KQFT_ESHAPE, "invalid quadrature");
   if (kind < KQFT_LINE_G || kind > KQFT_LINE_GSG) return fail(KQFT_EINVAL, "kind must be a KQFT_LINE_* value");
-  if (kind == KQFT_LINE_GSG && !G->dSigR) return fail(KQFT_EINVAL, "the G Sigma_dot G line needs Sigma_dot");
+  if (kind == KQFT_LINE_GSG && !G->dSigR && G->deps == 0.0)
+    return fail(KQFT_EINVAL, "the G Sigma_dot G line needs Sigma_dot");
   if ((rc = check_vertex(gamma, "gamma"))) return rc;
   if (!out) return fail(KQFT_EINVAL, "out is NULL");
   HIP_TRY(hipSetDevice(ctx->device));
@@ -1367,7 +1370,8 @@ int kqft_hartree(kqft_ctx* ctx, double U, double eps_d, const kqft_propagator* G
   if (q->n < 1 || (q->map != KQFT_QUAD_TAN_FINITE && q->map != KQFT_QUAD_TAN_INFINITE) ||
       (q->map == KQFT_QUAD_TAN_FINITE && !(q->L > 0)) || !(q->a > 0))
     return fail(KQFT_ESHAPE, "invalid quadrature");
-  if (G->reg != KQFT_REG_DELTA || G->dSigR) return fail(KQFT_EINVAL, "the Hartree term takes the plain propagator");
+  if (G->reg != KQFT_REG_DELTA || G->dSigR || G->deps != 0.0)
+    return fail(KQFT_EINVAL, "the Hartree term takes the plain propagator");
   if (!(U >= 0)) return fail(KQFT_EINVAL, "the bracketing needs U >= 0");
   if (self_consistent && !(tol > 0)) return fail(KQFT_EINVAL, "tol must be positive");
   HIP_TRY(hipSetDevice(ctx->device));
@@ -1481,6 +1485,10 @@ int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, dou
   if (fo.adaptive && (fo.max_steps < 1 || !(fo.ode_tol_abs >= 0) || !(fo.ode_tol_rel >= 0) ||
                       !(fo.ode_tol_abs + fo.ode_tol_rel > 0)))
     return fail(KQFT_EINVAL, "adaptive steps need max_steps >= 1 and positive tolerances");
+  if (fo.asymmetric != 0 && fo.asymmetric != 1) return fail(KQFT_EINVAL, "asymmetric must be 0 or 1");
+  const bool aam = fo.asymmetric == 1;
+  if (aam && (!std::isfinite(fo.eps_d) || !std::isfinite(fo.sigma_inf)))
+    return fail(KQFT_EINVAL, "eps_d and sigma_inf must be finite");
   if (!gamma || !sigma) return fail(KQFT_EINVAL, "gamma and sigma must be given");
   for (int r = 0; r < 3; ++r)
     if (!gamma[r].K1 || !gamma[r].K2 || !gamma[r].K2p || !gamma[r].K3)
@@ -1490,13 +1498,14 @@ int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, dou
   const int n = grid->n;
   const size_t c1 = (size_t)2 * n * 16, c2 = (size_t)2 * n * n * 16, c3 = (size_t)2 * n * n * n * 16;
   const size_t cnt[4] = {c1, c2, c2, c3};
-  const size_t chc = c1 + 2 * c2 + c3;         // complex entries of one channel
-  const size_t stc = 3 * chc + (size_t)4 * n;  // of the state: channels a, p, t (K1, K2, K2', K3), Sigma
+  const size_t chc = c1 + 2 * c2 + c3;  // complex entries of one channel
+  // of the state: channels a, p, t (K1, K2, K2', K3), Sigma, and Sigma_inf (asymmetric)
+  const size_t stc = 3 * chc + (size_t)4 * n + (aam ? 1 : 0);
   const bool corr = fo.se_iterations > 0 && nloops >= 3;
   // states: Y, stage input, y4 and six stage derivatives (adaptive) or one (RK4) plus the
   // RK4 accumulator; then Sigma-sized work arrays and two centre sums
   const int nst = fo.adaptive ? 9 : 4;
-  const size_t aux = (size_t)22 * n;
+  const size_t aux = (size_t)30 * n;
   if ((rc = ensure(ctx->flow, ((size_t)nst * stc + aux + (corr ? 2 * chc : 0)) * sizeof(double2)))) return rc;
   if ((rc = ensure(ctx->flowml, (size_t)nloops * 3 * chc * sizeof(double2)))) return rc;
   const int nblk = (int)std::min<size_t>(1024, (stc + 255) / 256);
@@ -1507,6 +1516,7 @@ int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, dou
   double2* ax = buf + (size_t)nst * stc;
   double2 *sigR = ax, *sigK = ax + n, *dsR = ax + 2 * n, *dsK = ax + 3 * n, *tR = ax + 4 * n, *tK = ax + 5 * n;
   double2 *sd1 = ax + 6 * n, *tb = ax + 10 * n, *sdt = ax + 14 * n, *snew = ax + 18 * n;
+  double2 *stat = ax + 22 * n, *ra = ax + 26 * n;  // asymptotic loop, 1 on retarded and advanced
   double2* cen = ax + aux;
   double2* ml = (double2*)ctx->flowml.p;
   double* red = (double*)ctx->flowred.p;
@@ -1516,6 +1526,7 @@ int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, dou
     return base + off;
   };
   auto sig_of = [&](double2* base) { return base + 3 * chc; };
+  auto sinf_of = [&](double2* base) { return base + 3 * chc + (size_t)4 * n; };
   auto chan_view = [&](double2* b0) { return BubbleOut{b0, b0 + c1, b0 + c1 + c2, b0 + c1 + 2 * c2}; };
   auto lincomb = [&](double2* out, const double2* x, int nt, const double2* const* k, const double* c, size_t count) {
     LinComb a;
@@ -1544,6 +1555,45 @@ int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, dou
     }
     return KQFT_OK;
   };
+  auto read_real = [&](const double2* p, double* out) -> int {
+    double2 h;
+    HIP_TRY(hipMemcpyAsync(&h, p, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *out = h.x;
+    return KQFT_OK;
+  };
+  auto write_real = [&](double2* p, double v) -> int {
+    const double2 h = make_double2(v, 0.0);
+    HIP_TRY(hipMemcpyAsync(p, &h, sizeof h, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return KQFT_OK;
+  };
+  // asymptotic value of -L(V, X): the loop of the bare vertex and K1_t, K2_t of V (the part
+  // that does not depend on the external frequency in the loop's legs); ds = its real
+  // retarded component, the same at every grid point (read at the first)
+  auto static_part = [&](const kqft_vertex& V, const kqft_propagator& Gx, int kind, double* ds) -> int {
+    int e;
+    kqft_vertex Vs;
+    memset(&Vs, 0, sizeof Vs);
+    Vs.r0 = V.r0;
+    Vs.grid = V.grid;
+    const kqft_chvert& t = V.ch[KQFT_CH_T];
+    Vs.ch[KQFT_CH_T] = kqft_chvert{t.coef, t.K1, t.K2, nullptr, nullptr};
+    if ((e = vloop_core(ctx, Vs, Gx, kind, *q_loop, (double*)stat, s))) return e;
+    double v;
+    if ((e = read_real(stat + 1, &v))) return e;
+    *ds = -v;
+    return KQFT_OK;
+  };
+  if (aam) {
+    std::vector<double2> h((size_t)4 * n);
+    for (int i = 0; i < n; ++i) {
+      h[4 * (size_t)i] = h[4 * (size_t)i + 3] = make_double2(0.0, 0.0);
+      h[4 * (size_t)i + 1] = h[4 * (size_t)i + 2] = make_double2(1.0, 0.0);
+    }
+    HIP_TRY(hipMemcpyAsync(ra, h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
   kqft_flow_info inf;
   memset(&inf, 0, sizeof inf);
   // derivative dY/dt of the state yb at flow time t into kout
@@ -1561,6 +1611,11 @@ int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, dou
     G.sgrid = *grid;
     G.SigR = (const double*)sigR;
     G.SigK = (const double*)sigK;
+    if (aam) {
+      double si;
+      if ((e = read_real(sinf_of(yb), &si))) return e;
+      G.eps = fo.eps_d + si;
+    }
     kqft_vertex V;
     memset(&V, 0, sizeof V);
     V.r0 = U;
@@ -1573,6 +1628,14 @@ int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, dou
     // one-loop self-energy flow Sigma_dot^(1) = -L(Gamma, S)
     if ((e = vloop_core(ctx, V, G, KQFT_LINE_S, *q_loop, (double*)sd1, s))) return e;
     launch_axpby(sd1, -1.0, sd1, 0.0, sd1, (size_t)4 * n, s);
+    double ds1 = 0.0, ds = 0.0;  // d Sigma_inf (asymmetric)
+    if (aam) {
+      if ((e = static_part(V, G, KQFT_LINE_S, &ds1))) return e;
+      const double2* kr[1] = {ra};
+      const double cr[1] = {-ds1};
+      lincomb(sd1, sd1, 1, kr, cr, (size_t)4 * n);
+      ds = ds1;
+    }
     launch_axpby(sd, 1.0, sd1, 0.0, sd1, (size_t)4 * n, s);
     BubbleOut centre[2] = {chan_view(cen), chan_view(cen + chc)};
     HostAnderson mixer(fo.se_anderson, 1.0);
@@ -1582,6 +1645,7 @@ int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, dou
         launch_sigma_split(n, sd, dsR, dsK, s);
         Gk.dSigR = (const double*)dsR;
         Gk.dSigK = (const double*)dsK;
+        Gk.deps = ds;
       }
       if ((e = mloop_core(ctx, V, Gk, *q_bubble, nloops, *opts, dview, corr ? centre : nullptr, s))) return e;
       if (!corr) break;
@@ -1599,25 +1663,40 @@ int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, dou
       Gt.dSigR = (const double*)tR;
       Gt.dSigK = (const double*)tK;
       if ((e = vloop_core(ctx, V, Gt, KQFT_LINE_GSG, *q_loop, (double*)sdt, s))) return e;
-      const double2* ks[2] = {tb, sdt};
-      const double cs[2] = {1.0, -1.0};
-      lincomb(snew, sd1, 2, ks, cs, (size_t)4 * n);
+      double dst = 0.0;  // asymptotic part of Sigma_dot_t (the centre-term loop has none)
+      if (aam && (e = static_part(V, Gt, KQFT_LINE_GSG, &dst))) return e;
+      const double2* ks[3] = {tb, sdt, ra};
+      const double cs[3] = {1.0, -1.0, -dst};
+      lincomb(snew, sd1, aam ? 3 : 2, ks, cs, (size_t)4 * n);
+      const double dnew = ds1 + dst;
       double md, mf;
       if ((e = maxdiff(sd, snew, (size_t)4 * n, md, mf))) return e;
+      if (aam) {
+        md = std::max(md, fabs(dnew - ds));
+        mf = std::max(mf, fabs(dnew));
+      }
       ++it;
       ++inf.se_iterations;
       if (md <= fo.se_tol_abs + fo.se_tol_rel * mf || it >= fo.se_iterations || fo.se_anderson == 0) {
         launch_axpby(sd, 1.0, snew, 0.0, snew, (size_t)4 * n, s);
+        ds = dnew;
         if (md <= fo.se_tol_abs + fo.se_tol_rel * mf || it >= fo.se_iterations) break;
         continue;
       }
-      // Anderson step on the host (4n complex values)
-      std::vector<double> hx((size_t)8 * n), hg((size_t)8 * n), hn;
-      HIP_TRY(hipMemcpyAsync(hx.data(), sd, hx.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipMemcpyAsync(hg.data(), snew, hg.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      // Anderson step on the host (4n complex values, and d Sigma_inf)
+      const size_t m = (size_t)8 * n + (aam ? 2 : 0);
+      std::vector<double> hx(m), hg(m), hn;
+      HIP_TRY(hipMemcpyAsync(hx.data(), sd, (size_t)8 * n * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(hg.data(), snew, (size_t)8 * n * sizeof(double), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
+      if (aam) {
+        hx[8 * (size_t)n] = ds;
+        hg[8 * (size_t)n] = dnew;
+        hx[8 * (size_t)n + 1] = hg[8 * (size_t)n + 1] = 0.0;
+      }
       if (!mixer.step(hx, hg, hn)) return fail(KQFT_ENOCONV, "singular Anderson system in the self-energy corrections");
-      HIP_TRY(hipMemcpyAsync(sd, hn.data(), hn.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      if (aam) ds = hn[8 * (size_t)n];
+      HIP_TRY(hipMemcpyAsync(sd, hn.data(), (size_t)8 * n * sizeof(double), hipMemcpyHostToDevice, s));
       HIP_TRY(hipStreamSynchronize(s));
     }
     // Gamma_dot = sum over the loop orders; everything times dLambda/dt
@@ -1637,6 +1716,7 @@ int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, dou
         }
       }
     if (dl != 1.0) launch_axpby(sd, dl, sd, 0.0, sd, (size_t)4 * n, s);
+    if (aam && (e = write_real(sinf_of(kout), dl * ds))) return e;
     return KQFT_OK;
   };
   // the user's state into Y
@@ -1647,6 +1727,7 @@ int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, dou
       HIP_TRY(hipMemcpyAsync(cls(Y, r, c), src[c], cnt[c] * sizeof(double2), hipMemcpyDeviceToDevice, s));
   }
   HIP_TRY(hipMemcpyAsync(sig_of(Y), sigma, (size_t)4 * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  if (aam && (rc = write_real(sinf_of(Y), fo.sigma_inf))) return rc;
   const double ti = flow_t(fo.reg, Lambda_i), tf = flow_t(fo.reg, Lambda_f);
   int nl = 0;
   auto record = [&](double t) {
@@ -1738,6 +1819,7 @@ int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, dou
       HIP_TRY(hipMemcpyAsync(dst[c], cls(Y, r, c), cnt[c] * sizeof(double2), hipMemcpyDeviceToDevice, s));
   }
   HIP_TRY(hipMemcpyAsync(sigma, sig_of(Y), (size_t)4 * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  if (aam && (rc = read_real(sinf_of(Y), &inf.sigma_inf))) return rc;
   HIP_TRY(hipGetLastError());
   if (info) *info = inf;
   return status;
@@ -2093,7 +2175,7 @@ int kqft_mloop_step(kqft_ctx* ctx, int n_points, const kqft_vertex* gamma, const
 
 // The adjoints differentiate the Delta-regulated propagator without Sigma_dot only.
 static int check_adjoint_prop(const kqft_propagator& G) {
-  if (G.reg != KQFT_REG_DELTA || G.dSigR || G.dSigK)
+  if (G.reg != KQFT_REG_DELTA || G.dSigR || G.dSigK || G.deps != 0.0)
     return fail(KQFT_EINVAL, "adjoints take the Delta-regulated propagator without Sigma_dot");
   return KQFT_OK;
 }

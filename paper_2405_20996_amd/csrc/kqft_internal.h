@@ -71,6 +71,7 @@ struct DProp {
   double lam;
   const double2* dSigR;  // Sigma_dot on sg (Katanin, G Sigma_dot G), or null
   const double2* dSigK;
+  double deps;  // real constant added to Sigma_dot^R (the flow of the level), 0 if none
 };
 
 __device__ inline double2 sigma_at(const DGrid& g, const double2* arr, double v) {
@@ -143,8 +144,9 @@ __device__ inline void propagator(const DProp& P, int kind, double v, double2 m[
     R = SR;
     K = cadd(cadd(cmul(cmul(SR, br), GA), cmul(cmul(GR, dbr), GA)), cmul(cmul(GR, br), cconj(SR)));
   }
-  if (kind != 0 && P.dSigR) {
-    const double2 dR = sigma_at(P.sg, P.dSigR, v), dK = sigma_at(P.sg, P.dSigK, v);
+  if (kind != 0 && (P.dSigR || P.deps != 0.0)) {
+    const double2 dR = cadd(sigma_at(P.sg, P.dSigR, v), make_double2(P.deps, 0.0));
+    const double2 dK = sigma_at(P.sg, P.dSigK, v);
     R = cadd(R, cmul(cmul(GR, dR), GR));
     K = cadd(K, cadd(cadd(cmul(cmul(GR, dR), GK), cmul(cmul(GR, dK), GA)), cmul(cmul(GK, cconj(dR)), GA)));
   }

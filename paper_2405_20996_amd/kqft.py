@@ -46,13 +46,14 @@ class KqftVertex(C.Structure):
 class KqftPropagator(C.Structure):
     _fields_ = [("Delta", C.c_double), ("T", C.c_double), ("eps", C.c_double), ("sgrid", KqftGrid),
                 ("SigR", C.c_void_p), ("SigK", C.c_void_p), ("reg", C.c_int), ("lam", C.c_double),
-                ("dSigR", C.c_void_p), ("dSigK", C.c_void_p)]
+                ("dSigR", C.c_void_p), ("dSigK", C.c_void_p), ("deps", C.c_double)]
 
 
 class KqftFlowOpts(C.Structure):
     _fields_ = [("reg", C.c_int), ("Delta", C.c_double), ("katanin", C.c_int), ("se_iterations", C.c_int),
                 ("se_tol_abs", C.c_double), ("se_tol_rel", C.c_double), ("se_anderson", C.c_int), ("adaptive", C.c_int),
-                ("ode_tol_abs", C.c_double), ("ode_tol_rel", C.c_double), ("max_steps", C.c_int)]
+                ("ode_tol_abs", C.c_double), ("ode_tol_rel", C.c_double), ("max_steps", C.c_int),
+                ("asymmetric", C.c_int), ("eps_d", C.c_double), ("sigma_inf", C.c_double)]
 
 
 class KqftParquetOpts(C.Structure):
@@ -68,7 +69,7 @@ class KqftAdaptInfo(C.Structure):
 
 class KqftFlowInfo(C.Structure):
     _fields_ = [("accepted", C.c_int), ("rejected", C.c_int), ("rhs_evaluations", C.c_int),
-                ("se_iterations", C.c_int)]
+                ("se_iterations", C.c_int), ("sigma_inf", C.c_double)]
 
 
 class KqftChout(C.Structure):
@@ -240,7 +241,8 @@ class Vertex:
 @dataclass
 class Propagator:
     """G^R = 1/(G_0^{-1,R} - Sigma^R) with the regulator `reg` (lam for REG_U / REG_NU);
-    dSigR/dSigK: optional Sigma_dot (Katanin substitution, G Sigma_dot G line)."""
+    dSigR/dSigK: optional Sigma_dot (Katanin substitution, G Sigma_dot G line); deps: a real
+    constant added to Sigma_dot^R (the flow of the level)."""
     Delta: float = 1.0
     T: float = 0.1
     eps: float = 0.0
@@ -251,18 +253,21 @@ class Propagator:
     lam: float = 1.0
     dSigR: Optional[torch.Tensor] = None
     dSigK: Optional[torch.Tensor] = None
+    deps: float = 0.0
 
     def c(self) -> KqftPropagator:
         g = (self.sigma_grid or Grid(2, 1.0, 1.0)).c()
         n = self.sigma_grid.n if self.sigma_grid else None
         sh = (n,) if n else None
         return KqftPropagator(self.Delta, self.T, self.eps, g, _ptr(self.SigR, sh, "SigR"), _ptr(self.SigK, sh, "SigK"),
-                              self.reg, self.lam, _ptr(self.dSigR, sh, "dSigR"), _ptr(self.dSigK, sh, "dSigK"))
+                              self.reg, self.lam, _ptr(self.dSigR, sh, "dSigR"), _ptr(self.dSigK, sh, "dSigK"),
+                              self.deps)
 
 
 @dataclass
 class FlowOptions:
-    """kqft_flow_opts: regulator, Katanin substitution, self-energy corrections, ODE method."""
+    """kqft_flow_opts: regulator, Katanin substitution, self-energy corrections, ODE method;
+    eps_d (not None): the asymmetric model with level eps_d + Sigma_inf, starting at sigma_inf."""
     reg: int = REG_DELTA
     Delta: float = 1.0
     katanin: bool = True
@@ -274,10 +279,13 @@ class FlowOptions:
     atol: float = 1e-8
     rtol: float = 1e-5
     max_steps: int = 200
+    eps_d: Optional[float] = None
+    sigma_inf: float = 0.0
 
     def c(self) -> KqftFlowOpts:
         return KqftFlowOpts(self.reg, self.Delta, int(self.katanin), self.se_iterations, self.se_atol, self.se_rtol,
-                            self.se_anderson, int(self.adaptive), self.atol, self.rtol, self.max_steps)
+                            self.se_anderson, int(self.adaptive), self.atol, self.rtol, self.max_steps,
+                            int(self.eps_d is not None), self.eps_d or 0.0, self.sigma_inf)
 
 
 def _opts(precision, class_mask, beta, omega_batch, overlap=0) -> KqftOpts:
@@ -370,7 +378,8 @@ def mfrg_flow(grid: Grid, U: float, T: float, lam_i: float, lam_f: float, steps:
               q_bubble: Quad, q_loop: Quad, gamma: Sequence[Channel], sigma: torch.Tensor,
               flow: Optional[FlowOptions] = None, precision: int = FP64, stream=None):
     """Flow of the state (gamma[3] Channels, sigma [n][4]) from lam_i to lam_f, in place.
-    Returns (gamma, sigma, info) with info the accepted flow parameters and step counts."""
+    Returns (gamma, sigma, info) with info the accepted flow parameters and step counts (and
+    sigma_inf, the final asymptotic value of the self-energy, for the asymmetric model)."""
     n = grid.n
     fo = flow or FlowOptions()
     D = (KqftChout * 3)(*[_chout(c, n) for c in gamma])
@@ -385,7 +394,7 @@ def mfrg_flow(grid: Grid, U: float, T: float, lam_i: float, lam_f: float, steps:
                               lams, C.byref(inf), _stream(stream))
     _check(rc)
     info = {"lambdas": list(lams[:inf.accepted + 1]), "accepted": inf.accepted, "rejected": inf.rejected,
-            "rhs": inf.rhs_evaluations, "se_iterations": inf.se_iterations}
+            "rhs": inf.rhs_evaluations, "se_iterations": inf.se_iterations, "sigma_inf": inf.sigma_inf}
     return gamma, sigma, info
 
 

@@ -209,3 +209,60 @@ def test_mfrg_flow_resumed_from_a_checkpoint_equals_the_uninterrupted_flow():
             a, b = getattr(bch[r], x), getattr(kch[r], x)
             assert float((a - b).abs().max()) <= 1e-12 * max(float(b.abs().max()), 1e-300), (r, x)
     assert float((bsig - ksig).abs().max()) <= 1e-12 * float(ksig.abs().max())
+
+
+AAM_CASES = {
+    "rk4_delta_corrections": (O.FlowOptions(se_iterations=3), 2.0, 1.0, 2, 3),
+    "adaptive_corrections_anderson": (O.FlowOptions(adaptive=True, atol=1e-6, rtol=1e-4, se_iterations=10,
+                                                    se_anderson=2), 2.0, 1.0, 1, 4),
+    "rk4_interaction": (O.FlowOptions(reg=O.REG_U, Delta=1.0), 0.5, 1.0, 2, 2),
+}
+
+
+@pytest.mark.parametrize("case", list(AAM_CASES))
+def test_asymmetric_mfrg_flow_matches_oracle(case):
+    """Asymmetric model (level eps_d = -0.2 + Sigma_inf, the self-energy's asymptotic value
+    flowing with the static part of the loops): same accepted steps, state and Sigma_inf as the
+    oracle's flow, from the PT2 state of the self-consistent Hartree level (n = 9, N_q = 31)."""
+    K = _K()
+    fo, li, lf, steps, nl = AAM_CASES[case]
+    n, nq, U, ed = 9, 31, 1.0, -0.2
+    g, q = O.Grid(n), O.Quad(nq)
+    Dstart = li if fo.reg == O.REG_DELTA else fo.Delta
+    sH, _ = O.hartree(U, ed, Dstart, T, O.Quad(2001, 1, 0.0, 1.0), tol=1e-13)
+    chans, sig = O.pt2_state(g, U, Dstart, T, q, q, eps=ed + sH)
+    rch, rsig, rinfo = O.mfrg_flow(g, U, T, li, lf, steps, nl, q, q, chans, sig, fo, eps_d=ed, sigma_inf=sH)
+    kch, ksig = gpu_state(K, chans, sig)
+    kf = _kflow(K, fo)
+    kf.eps_d, kf.sigma_inf = ed, sH
+    _, _, kinfo = K.mfrg_flow(K.Grid(n), U, T, li, lf, steps, nl, K.Quad(nq), K.Quad(nq), kch, ksig, kf)
+    torch.cuda.synchronize()
+    print(f"{case}: Sigma_inf {sH:.6f} -> {kinfo['sigma_inf']:.10f}, lambdas {np.round(kinfo['lambdas'], 6).tolist()}, "
+          f"rejected {kinfo['rejected']}, rhs {kinfo['rhs']}, se iterations {kinfo['se_iterations']}", flush=True)
+    assert len(kinfo["lambdas"]) == len(rinfo["lambdas"]) and kinfo["rejected"] == rinfo["rejected"]
+    assert np.abs(np.array(kinfo["lambdas"]) - np.array(rinfo["lambdas"])).max() < 1e-12
+    assert kinfo["rhs"] == rinfo["rhs"] and kinfo["se_iterations"] == rinfo.get("se_iterations", 0)
+    assert abs(kinfo["sigma_inf"] - rinfo["sigma_inf"]) < 1e-10 * abs(rinfo["sigma_inf"])
+    assert abs(rinfo["sigma_inf"] - sH) > 1e-4  # the asymptotic value does flow away from half filling
+    _compare_state(kch, ksig, rch, rsig, 1e-10)
+
+
+def test_asymmetric_mfrg_flow_at_half_filling_is_the_symmetric_flow():
+    """eps_d = -U/2 with Sigma_inf = U/2: the asymmetric path reproduces the symmetric flow and
+    Sigma_inf stays U/2 (multiloop order 3, Katanin, self-energy corrections)."""
+    K = _K()
+    n, nq, U = 9, 31, 1.0
+    g, q = O.Grid(n), O.Quad(nq)
+    chans, sig = O.pt2_state(g, U, 2.0, T, q, q)
+    ach, asig = gpu_state(K, chans, sig)
+    K.mfrg_flow(K.Grid(n), U, T, 2.0, 1.0, 2, 3, K.Quad(nq), K.Quad(nq), ach, asig, K.FlowOptions(se_iterations=3))
+    bch, bsig = gpu_state(K, chans, sig)
+    _, _, info = K.mfrg_flow(K.Grid(n), U, T, 2.0, 1.0, 2, 3, K.Quad(nq), K.Quad(nq), bch, bsig,
+                             K.FlowOptions(se_iterations=3, eps_d=-U / 2, sigma_inf=U / 2))
+    torch.cuda.synchronize()
+    assert abs(info["sigma_inf"] - U / 2) < 1e-13
+    assert float((bsig - asig).abs().max()) <= 1e-12 * float(asig.abs().max())
+    for r in range(3):
+        for x in CL:
+            a, b = getattr(bch[r], x), getattr(ach[r], x)
+            assert float((a - b).abs().max()) <= 1e-12 * max(float(b.abs().max()), 1e-300), (r, x)
