@@ -9,10 +9,11 @@
  * Sec. "The loop function"), susceptibilities (Sec. "Susceptibilities"), the
  * multiloop flow insertions (Eqs. 1l-3l of the mfRG section) and the adjoint of
  * the bubble -- on one AMD Instinct MI355X (gfx950), and the algorithms around it:
- * the parquet solver (mixing, Anderson acceleration), the mfRG flow (regulators,
- * Katanin substitution, self-energy corrections, Cash-Karp step control), the
- * Hartree term of the asymmetric model and the bubble with adaptive Gauss-Lobatto-
- * Kronrod integration.
+ * the parquet solver (mixing, Anderson acceleration, the three forms of the SDE), the
+ * mfRG flow (regulators, Katanin substitution, self-energy corrections, Cash-Karp step
+ * control), the asymmetric model (Hartree term, parquet solver and flow with the
+ * self-energy's asymptotic value), susceptibilities of every channel and the bubble with
+ * adaptive Gauss-Lobatto-Kronrod integration.
  *
  * Conventions shared by every entry point
  *   Keldysh basis: rotated, alpha in {0,1}; G^{0|0}=0, G^{0|1}=G^A, G^{1|0}=G^R,
