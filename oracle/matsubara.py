@@ -1,0 +1,256 @@
+"""Finite-temperature Matsubara formalism (MF) of the bubble, loop and Schwinger-Dyson equation.
+
+TEST INFRASTRUCTURE ONLY, like the rest of this package.  The paper carries its diagrammatic
+functions over to discrete Matsubara sums in the finite-T MF (Sec. Introduction: flexibility,
+Sec. Vectorization: the Matsubara sums as matrix products); the formulas are the Keldysh ones
+with the Keldysh structure removed, written here directly:
+
+  frequencies   nu_n = (2n + 1) pi T (fermionic), Omega_m = 2 m pi T (bosonic);
+  legs (integer parametrisation, every leg frequency fermionic):
+      a: n2 = n, n1' = n + m, n2' = n', n1 = n' + m        (omega = nu1' - nu2)
+      p: n1' = n, n2' = m - n - 1, n1 = n', n2 = m - n' - 1  (omega = nu1' + nu2')
+      t: n2 = n, n2' = n + m, n1' = n', n1 = n' + m        (omega = nu2' - nu2)
+  classes       K1[s][m], K2[s][m][n], K2'[s][m][n'], K3[s][m][n][n'] on m in [-M, M],
+                n, n' in [-N, N), spin s = X (up-down|up-down), Y (up-down|down-up); zero outside;
+  bare vertex   X0 = -U, Y0 = +U;
+  propagator    G(i nu_n) = 1 / (i nu_n + i Delta sgn(nu_n) - Sigma(n)) (level 0: particle-hole
+                symmetry with U/2 absorbed; Sigma given on [-Ns, Ns), zero outside);
+  bubbles       B_r(L, R)(m; n, n') = pref_r T sum_{n''} L(m; n, n'') Pi_r(m, n'') R(m; n'', n')
+                (spin sums below), Pi_a = Pi_t = G(n'' + m) G(n''), Pi_p = G(n'') G(m - n'' - 1),
+                pref_r = +1, 1/2, -1; the sum over the window |2n'' + 1 + s m| <= 2 Nq - 1,
+                s = +1 (a, t) or -1 (p), symmetric about the bubble's centre;
+  asymptotic classes as in the Keldysh formalism: L^inf = Gamma_0 + K1 + K2' (own channel at
+                (m, n'')), R^inf = Gamma_0 + K1 + K2, K3 = (L - L^inf) Pi (R - R^inf) etc.;
+  loop          L(Gamma, G)(n) = T sum_{n'} [2 X + Y](legs n, n' | n, n') G(n'), window
+                |2n' + 1| <= 2 Nl - 1;  SDE  Sigma = -1/2 L(B_a(Gamma_0, Gamma), G).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+CLASSES = ("K1", "K2", "K2p", "K3")
+
+
+def nu(n, T: float):
+    return (2.0 * np.asarray(n) + 1.0) * np.pi * T
+
+
+def om(m, T: float):
+    return 2.0 * np.asarray(m) * np.pi * T
+
+
+@dataclass
+class MGrid:
+    """Bosonic box m in [-M, M], fermionic box n in [-N, N), temperature T."""
+    M: int
+    N: int
+    T: float
+
+    def shapes(self):
+        nb, nf = 2 * self.M + 1, 2 * self.N
+        return {"K1": (2, nb), "K2": (2, nb, nf), "K2p": (2, nb, nf), "K3": (2, nb, nf, nf)}
+
+
+@dataclass
+class MChannel:
+    coef: float = 1.0
+    K1: Optional[np.ndarray] = None
+    K2: Optional[np.ndarray] = None
+    K2p: Optional[np.ndarray] = None
+    K3: Optional[np.ndarray] = None
+
+
+@dataclass
+class MVertex:
+    grid: MGrid
+    U: float = 0.0
+    ch: list = field(default_factory=lambda: [MChannel(0.0), MChannel(0.0), MChannel(0.0)])
+
+
+def legs_of(r: int, m, n, npr):
+    """Leg indices (n1', n2', n1, n2) of channel r's parameters (m, n, n')."""
+    m, n, npr = np.asarray(m), np.asarray(n), np.asarray(npr)
+    if r == 0:
+        return n + m, npr, npr + m, n
+    if r == 1:
+        return n, m - n - 1, npr, m - npr - 1
+    return npr, n + m, npr + m, n
+
+
+def params_of(r: int, n1p, n2p, n1, n2):
+    """Channel r's parameters (m, n, n') of the legs (inverse of legs_of on conserving legs)."""
+    if r == 0:
+        return n1p - n2, n2, n2p
+    if r == 1:
+        return n1p + n2p + 1, n1p, n1
+    return n2p - n2, n2, n1p
+
+
+def _lookup(arr: Optional[np.ndarray], grid: MGrid, idx):
+    """arr[s][m + M][n + N]... at integer indices (per spin), zero outside the box or when absent."""
+    shape = np.broadcast(*idx).shape
+    out = np.zeros((2,) + shape, dtype=np.complex128)
+    if arr is None:
+        return out
+    offs = [grid.M] + [grid.N] * (len(idx) - 1)
+    lims = [2 * grid.M + 1] + [2 * grid.N] * (len(idx) - 1)
+    ii = [np.broadcast_to(np.asarray(x) + o, shape) for x, o in zip(idx, offs)]
+    ok = np.ones(shape, dtype=bool)
+    for x, lim in zip(ii, lims):
+        ok &= (x >= 0) & (x < lim)
+    safe = [np.where(ok, x, 0) for x in ii]
+    for s in range(2):
+        out[s] = np.where(ok, arr[s][tuple(safe)], 0.0)
+    return out
+
+
+def channel_value(c: MChannel, grid: MGrid, m, n, npr, parts=CLASSES):
+    """Sum of the selected classes of one channel at its own parameters: [2, ...] (X, Y)."""
+    m, n, npr = np.broadcast_arrays(np.asarray(m), np.asarray(n), np.asarray(npr))
+    v = np.zeros((2,) + m.shape, dtype=np.complex128)
+    if "K1" in parts:
+        v = v + _lookup(c.K1, grid, (m,))
+    if "K2" in parts:
+        v = v + _lookup(c.K2, grid, (m, n))
+    if "K2p" in parts:
+        v = v + _lookup(c.K2p, grid, (m, npr))
+    if "K3" in parts:
+        v = v + _lookup(c.K3, grid, (m, n, npr))
+    return c.coef * np.asarray(v)
+
+
+def vertex_eval(V: MVertex, r: int, m, n, npr):
+    """The full vertex Gamma_0 + sum_r' coef gamma_r' at channel r's parameters: [2, ...] (X, Y);
+    every channel is read at its own parameters of the same legs (exact indices, no
+    interpolation)."""
+    legs = legs_of(r, m, n, npr)
+    shape = np.broadcast(*legs).shape
+    out = np.zeros((2,) + shape, dtype=np.complex128)
+    out[0] += -V.U
+    out[1] += V.U
+    for r2 in range(3):
+        c = V.ch[r2]
+        if c.coef == 0.0:
+            continue
+        m2, n2, np2 = params_of(r2, *legs)
+        out += channel_value(c, V.grid, m2, n2, np2)
+    return out
+
+
+def vertex_legs(V: MVertex, spins, legs):
+    """Gamma_{s1' s2' | s1 s2}(n1', n2' | n1, n2) = X d(s1', s1) d(s2', s2) + Y d(s1', s2) d(s2', s1)
+    (SU(2), the spin structure of every channel), read through channel a's parameters."""
+    n1p, n2p, n1, n2 = [np.asarray(x) for x in legs]
+    s1p, s2p, s1, s2 = [np.asarray(x) for x in spins]
+    XY = vertex_eval(V, 0, *params_of(0, n1p, n2p, n1, n2))
+    return XY[0] * ((s1p == s1) & (s2p == s2)) + XY[1] * ((s1p == s2) & (s2p == s1))
+
+
+@dataclass
+class MProp:
+    """G(i nu_n) = 1/(i nu_n + i Delta sgn(nu_n) - Sigma(n)), Sigma on n in [-Ns, Ns) or none."""
+    Delta: float
+    T: float
+    sigma: Optional[np.ndarray] = None
+
+    def __call__(self, n):
+        n = np.asarray(n)
+        v = nu(n, self.T)
+        s = np.zeros(n.shape, dtype=np.complex128)
+        if self.sigma is not None:
+            Ns = len(self.sigma) // 2
+            ok = (n >= -Ns) & (n < Ns)
+            s = np.where(ok, self.sigma[np.where(ok, n + Ns, 0)], 0.0)
+        return 1.0 / (1j * v + 1j * self.Delta * np.sign(v) - s)
+
+
+def window(r: int, m: int, Nq: int) -> np.ndarray:
+    """Summation indices n'' of channel r's bubble at bosonic index m: |2n'' + 1 + s m| <= 2Nq - 1,
+    s = +1 for a and t (Pi symmetric about nu'' = -Omega/2), -1 for p (about +Omega/2)."""
+    s = -1 if r == 1 else 1
+    lo = int(np.ceil((-(2 * Nq - 1) - 1 - s * m) / 2.0))
+    hi = int(np.floor(((2 * Nq - 1) - 1 - s * m) / 2.0))
+    return np.arange(lo, hi + 1)
+
+
+def pi_r(r: int, P: MProp, m: int, k: np.ndarray) -> np.ndarray:
+    """T Pi_r(m, n'') for the window k."""
+    if r == 1:
+        return P.T * P(k) * P(m - k - 1)
+    return P.T * P(k + m) * P(k)
+
+
+def _spin_sum(r: int, LX, LY, pi, RX, RY):
+    """Literal spin sums of the three bubbles (with the channel prefactors)."""
+    def mm(A, B):
+        return (A * pi[None, :]) @ B
+    if r == 0:
+        return mm(LX, RX), mm(LX + LY, RY) + mm(LY, RX + RY)
+    if r == 1:
+        return 0.5 * (mm(LX, RX) + mm(LY, RY)), 0.5 * (mm(LX, RY) + mm(LY, RX))
+    return -(mm(LX, RX + RY) + mm(LX + LY, RX)), -mm(LY, RY)
+
+
+def bubble(r: int, L: MVertex, R: MVertex, P: MProp, Nq: int) -> MChannel:
+    """B_r(L, R) as the four asymptotic classes of channel r."""
+    g = L.grid
+    sh = g.shapes()
+    out = {k: np.zeros(s, dtype=np.complex128) for k, s in sh.items()}
+    nbox = np.arange(-g.N, g.N)
+    own_L, own_R = L.ch[r], R.ch[r]
+    for im, m in enumerate(range(-g.M, g.M + 1)):
+        k = window(r, m, Nq)
+        pi = pi_r(r, P, m, k)
+        # left: rows n (the box), columns n''; L^inf(m, n'') = Gamma_0 + K1 + K2' of the own channel
+        full_L = vertex_eval(L, r, m, nbox[:, None], k[None, :])
+        inf_L = channel_value(own_L, g, m, 0, k, ("K1", "K2p"))
+        inf_L[0] += -L.U
+        inf_L[1] += L.U
+        main_L = full_L - inf_L[:, None, :]
+        # right: rows n'', columns n'; R^inf(m, n'') = Gamma_0 + K1 + K2 of the own channel
+        full_R = vertex_eval(R, r, m, k[:, None], nbox[None, :])
+        inf_R = channel_value(own_R, g, m, k, 0, ("K1", "K2"))
+        inf_R[0] += -R.U
+        inf_R[1] += R.U
+        main_R = full_R - inf_R[:, :, None]
+        x3, y3 = _spin_sum(r, main_L[0], main_L[1], pi, main_R[0], main_R[1])
+        x2, y2 = _spin_sum(r, main_L[0], main_L[1], pi, inf_R[0][:, None], inf_R[1][:, None])
+        x2p, y2p = _spin_sum(r, inf_L[0][None, :], inf_L[1][None, :], pi, main_R[0], main_R[1])
+        x1, y1 = _spin_sum(r, inf_L[0][None, :], inf_L[1][None, :], pi, inf_R[0][:, None], inf_R[1][:, None])
+        out["K3"][0, im], out["K3"][1, im] = x3, y3
+        out["K2"][0, im], out["K2"][1, im] = x2[:, 0], y2[:, 0]
+        out["K2p"][0, im], out["K2p"][1, im] = x2p[0], y2p[0]
+        out["K1"][0, im], out["K1"][1, im] = x1[0, 0], y1[0, 0]
+    return MChannel(1.0, out["K1"], out["K2"], out["K2p"], out["K3"])
+
+
+def loop(V: MVertex, P: MProp, Nl: int) -> np.ndarray:
+    """L(Gamma, G)(n) for n in [-N, N): T sum_{n'} [2X + Y](n, n' | n, n') G(n') over
+    |2n' + 1| <= 2 Nl - 1."""
+    g = V.grid
+    n = np.arange(-g.N, g.N)
+    k = np.arange(-Nl, Nl)
+    XY = vertex_eval(V, 0, *params_of(0, n[:, None], k[None, :], n[:, None], k[None, :]))
+    return P.T * ((2.0 * XY[0] + XY[1]) * P(k)[None, :]).sum(axis=1)
+
+
+def bare(grid: MGrid, U: float) -> MVertex:
+    return MVertex(grid, U)
+
+
+def combine(grid: MGrid, U: float, parts) -> MVertex:
+    chans = [MChannel(0.0), MChannel(0.0), MChannel(0.0)]
+    for r, c, coef in parts:
+        chans[r] = MChannel(coef, c.K1, c.K2, c.K2p, c.K3)
+    return MVertex(grid, U, chans)
+
+
+def sde(V: MVertex, P: MProp, Nq: int, Nl: int) -> np.ndarray:
+    """Sigma(n) = -1/2 L(B_a(Gamma_0, Gamma), G) (the a-channel form of Eq. SDE; Hartree part
+    absorbed at particle-hole symmetry)."""
+    phi = bubble(0, bare(V.grid, V.U), V, P, Nq)
+    pv = MVertex(V.grid, 0.0, [MChannel(1.0, phi.K1, None, phi.K2p, None), MChannel(0.0), MChannel(0.0)])
+    return -0.5 * loop(pv, P, Nl)

@@ -1,0 +1,145 @@
+"""Pins of the oracle's finite-temperature Matsubara formalism (the bubble, loop and SDE of the
+paper carried over to discrete Matsubara sums): the bare bubble against its closed form
+(digamma functions) with the window's tail, the bubble of every channel against the literal
+compound-index sum over internal legs and spins, crossing symmetry of the vertex built from
+bubbles, and the second-order self-energy against the spectral representation of the Keldysh
+one (the pinned real-frequency oracle), which fixes sign and normalisation across formalisms."""
+import numpy as np
+import scipy.special as sp
+
+import oracle as O
+from oracle import matsubara as MF
+
+T, D, U = 0.1, 1.0, 1.0
+
+
+def _bare_bubble_closed_form(m, Dl=D, Tl=T):
+    """T sum_n G(n + m) G(n) over all n, G = 1/(i nu + i Dl sgn nu): the two regions where
+    both frequencies have the same sign give digamma differences, the m mixed terms are summed."""
+    m = abs(m)
+    d = Dl / (2 * np.pi * Tl)
+    c = 1.0 / (2 * np.pi * Tl) ** 2
+    same = c * (sp.polygamma(1, 0.5 + d) if m == 0 else (sp.digamma(0.5 + m + d) - sp.digamma(0.5 + d)) / m)
+    mixed = sum(1.0 / ((MF.nu(n + m, Tl) + Dl) * (MF.nu(n, Tl) - Dl)) for n in range(-m, 0))
+    return -Tl * (2 * same + mixed)
+
+
+def test_bare_bubble_converges_to_its_closed_form_with_the_tail_of_the_window():
+    """The window |2n + 1 + m| <= 2 Nq - 1 misses the tails T sum 1/nu^2 = 1/(2 pi^2 T Nq) to
+    leading order: (window sum - infinite sum) Nq -> 1/(2 pi^2 T); the p bubble at particle-hole
+    symmetry is minus the a bubble (G odd in nu)."""
+    P = MF.MProp(D, T)
+    for m in (0, 1, 2, 5, -3):
+        exact = _bare_bubble_closed_form(m)
+        for Nq in (1000, 8000):
+            k = MF.window(0, m, Nq)
+            s = MF.pi_r(0, P, m, k).sum()
+            assert abs(s.imag) < 1e-15
+            assert abs((s.real - exact) * Nq * 2 * np.pi ** 2 * T - 1.0) < 3.0 / Nq ** 0.5
+            sp_ = MF.pi_r(1, P, m, MF.window(1, m, Nq)).sum()
+            assert abs(sp_ + s) < 1e-12
+
+
+def _random_vertex(g, seed, amp=0.3):
+    rng = np.random.default_rng(seed)
+    sh = g.shapes()
+    chans = []
+    for r in range(3):
+        arrs = [amp * (rng.standard_normal(sh[c]) + 1j * rng.standard_normal(sh[c])) for c in MF.CLASSES]
+        chans.append(MF.MChannel(0.7 + 0.2 * r, *arrs))
+    return MF.MVertex(g, 0.8, chans)
+
+
+def _literal_bubble(r, L, R, P, Nq, m, n, npr, spins):
+    """The bubble of channel r at (m, n, n') and external spins, summed literally over the
+    internal legs' frequency (the window) and spins, from the compound-index definitions:
+      a: + L(1'4'|32) G(3) G(4) R(3'2'|14),  p: 1/2 L(1'2'|34) G(3) G(4) R(3'4'|12),
+      t: - L(4'2'|32) G(3) G(4) R(1'3'|14)."""
+    n1p, n2p, n1, n2 = MF.legs_of(r, m, n, npr)
+    s1p, s2p, s1, s2 = spins
+    tot = 0.0
+    for k in MF.window(r, m, Nq):
+        for s3 in (0, 1):
+            for s4 in (0, 1):
+                if r == 0:    # nu4 = nu'' , nu3 = nu'' + omega
+                    n4, n3 = k, k + m
+                    lv = MF.vertex_legs(L, (s1p, s4, s3, s2), (n1p, n4, n3, n2))
+                    rv = MF.vertex_legs(R, (s3, s2p, s1, s4), (n3, n2p, n1, n4))
+                    tot += T * lv * P(n3) * P(n4) * rv
+                elif r == 1:  # nu3 = nu'', nu4 = omega - nu''
+                    n3, n4 = k, m - k - 1
+                    lv = MF.vertex_legs(L, (s1p, s2p, s3, s4), (n1p, n2p, n3, n4))
+                    rv = MF.vertex_legs(R, (s3, s4, s1, s2), (n3, n4, n1, n2))
+                    tot += 0.5 * T * lv * P(n3) * P(n4) * rv
+                else:         # nu4 = nu'', nu3 = nu'' + omega
+                    n4, n3 = k, k + m
+                    lv = MF.vertex_legs(L, (s4, s2p, s3, s2), (n4, n2p, n3, n2))
+                    rv = MF.vertex_legs(R, (s1p, s3, s1, s4), (n1p, n3, n1, n4))
+                    tot -= T * lv * P(n3) * P(n4) * rv
+    return tot
+
+
+def test_bubble_of_every_channel_is_the_literal_sum_over_internal_legs_and_spins():
+    """K1 + K2 + K2' + K3 of the bubble (asymptotic decomposition, diagonalised spin sums) at
+    sample outputs equals the literal sum over the internal frequency and spins of random
+    vertices (every class of every channel non-zero) with a dynamic self-energy in G."""
+    g = MF.MGrid(3, 3, T)
+    L, R = _random_vertex(g, 1), _random_vertex(g, 2)
+    sig = 0.2 * np.exp(1j * np.linspace(0, 3, 16)) - 0.1j
+    P = MF.MProp(D, T, sig)
+    Nq = 5
+    rng = np.random.default_rng(4)
+    for r in range(3):
+        b = MF.bubble(r, L, R, P, Nq)
+        for _ in range(6):
+            m, n, npr = int(rng.integers(-3, 4)), int(rng.integers(-3, 3)), int(rng.integers(-3, 3))
+            val = MF.channel_value(b, g, m, n, npr)
+            lx = _literal_bubble(r, L, R, P, Nq, m, n, npr, (0, 1, 0, 1))
+            ly = _literal_bubble(r, L, R, P, Nq, m, n, npr, (0, 1, 1, 0))
+            scale = max(abs(lx), abs(ly))
+            assert scale > 1e-3
+            assert abs(val[0] - lx) < 1e-13 * scale and abs(val[1] - ly) < 1e-13 * scale, (r, m, n, npr)
+
+
+def _crossing_residual(V, lim, seed=3):
+    rng = np.random.default_rng(seed)
+    worst = scale = 0.0
+    for _ in range(200):
+        n1p, n2p, n1 = rng.integers(-lim, lim, 3)
+        n2 = n1p + n2p - n1
+        for s in ([0, 1, 0, 1], [0, 1, 1, 0], [0, 0, 0, 0]):
+            x = MF.vertex_legs(V, s, (n1p, n2p, n1, n2))
+            y = MF.vertex_legs(V, [s[0], s[1], s[3], s[2]], (n1p, n2p, n2, n1))
+            worst, scale = max(worst, abs(x + y)), max(scale, abs(x))
+    return worst / scale
+
+
+def test_vertex_from_bubbles_is_crossing_symmetric():
+    """Gamma(1'2'|21) = -Gamma(1'2'|12) for Gamma_1 = Gamma_0 + sum_r B_r(Gamma_0, Gamma_0) and for
+    Gamma_2 = Gamma_0 + sum_r B_r(Gamma_1, Gamma_1) (legs well inside the box): crossing maps
+    the a bubble onto the t bubble and the p bubble onto itself, so this checks the three
+    parametrisations, the prefactors and the spin sums together."""
+    g = MF.MGrid(12, 8, T)
+    P = MF.MProp(D, T)
+    g0 = MF.bare(g, U)
+    V1 = MF.combine(g, U, [(r, MF.bubble(r, g0, g0, P, 24), 1.0) for r in range(3)])
+    assert _crossing_residual(V1, 6) < 1e-14
+    V2 = MF.combine(g, U, [(r, MF.bubble(r, V1, V1, P, 24), 1.0) for r in range(3)])
+    assert _crossing_residual(V2, 2) < 1e-14
+
+
+def test_second_order_self_energy_is_the_spectral_representation_of_the_keldysh_one():
+    """Sigma^(2)(i nu_n) of the Matsubara SDE equals -1/pi int de Im Sigma^R(e) / (i nu_n - e)
+    with Sigma^R the Keldysh oracle's second-order self-energy (same Delta, T, U): the two
+    formalisms agree on sign and normalisation, up to the Keldysh grid and the Matsubara
+    windows (a few 1e-4)."""
+    g = O.Grid(201, 40.0, 2.0)
+    q = O.Quad(801, 1, 0.0, 1.0)
+    sk = O.sde(O.bare(g, U), O.Prop(D, T), q, q)
+    e, imS = g.nodes(), sk[:, 1].imag
+    N = 4
+    s_mf = MF.sde(MF.bare(MF.MGrid(210, N, T), U), MF.MProp(D, T), 200, 200)
+    v = MF.nu(np.arange(-N, N), T)
+    spec = np.array([np.trapezoid(-imS / np.pi / (1j * vv - e), e) for vv in v])
+    assert np.abs(s_mf - spec).max() < 2e-3 * np.abs(spec).max()
+    assert np.abs(s_mf.real).max() < 1e-14  # particle-hole symmetry: Sigma(i nu) imaginary
