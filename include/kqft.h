@@ -237,6 +237,53 @@ int kqft_sde(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, 
 int kqft_chi(kqft_ctx* ctx, int channel, const kqft_vertex* gamma, const kqft_propagator* G, const kqft_quad* q,
              double* chi, void* stream);
 
+/* ---------------------------------------------------------------- Matsubara formalism
+ * Finite temperature, imaginary frequencies (the paper's code also runs its diagrammatic
+ * functions with Matsubara sums; Sec. "Vectorization": the sums as matrix products).
+ * Frequencies nu_n = (2n + 1) pi T, Omega_m = 2 m pi T; legs of channel r's (m, n, n'), every
+ * leg fermionic:  a: n2 = n, n1' = n + m, n2' = n', n1 = n' + m;  p: n1' = n,
+ * n2' = m - n - 1, n1 = n', n2 = m - n' - 1;  t: n2 = n, n2' = n + m, n1' = n', n1 = n' + m.
+ * Classes (no Keldysh index): K1[s][m], K2[s][m][n], K2p[s][m][n'], K3[s][m][n][n'], s = X, Y,
+ * m in [-M, M] (index m + M), n, n' in [-N, N) (index n + N), complex, zero outside. */
+typedef struct {
+  int M;    /* bosonic box [-M, M], M >= 0 */
+  int N;    /* fermionic box [-N, N), N >= 1 */
+  double T; /* temperature > 0 */
+} kqft_mgrid;
+
+/* Gamma = Gamma_0 + sum_r coef_r gamma_r with X0 = -U, Y0 = +U */
+typedef struct {
+  kqft_mgrid grid;
+  double U;
+  kqft_chvert ch[3];
+} kqft_mvertex;
+
+/* G(i nu_n) = 1/(i nu_n + i Delta sgn(nu_n) - Sigma(n)) (level 0: particle-hole symmetric model
+   with U/2 absorbed); sigma: device complex on n in [-sigma_N, sigma_N) or NULL */
+typedef struct {
+  double Delta;
+  const double* sigma;
+  int sigma_N;
+} kqft_mprop;
+
+/*
+ * kqft_bubble_matsubara -- B_r(left, right) in the Matsubara formalism:
+ *   B_r(m; n, n') = pref_r T sum_{n''} left(m; n, n'') Pi_r(m, n'') right(m; n'', n')
+ * with the spin sums of the real-frequency bubble (the same two combinations per channel,
+ * prefactors +1, 1/2, -1), Pi_a = Pi_t = G(n'' + m) G(n''), Pi_p = G(n'') G(m - n'' - 1), the
+ * sum over the window |2n'' + 1 + s m| <= 2 Nq - 1 (s = +1 for a and t, -1 for p; symmetric
+ * about the bubble's centre, no tail correction), and the asymptotic classes as in kqft_bubble
+ * (L^inf = Gamma_0 + K1 + K2' of the own channel at (m, n''), R^inf = Gamma_0 + K1 + K2):
+ * K3 = (L - L^inf) Pi (R - R^inf), K2 = (L - L^inf) Pi R^inf, K2' = L^inf Pi (R - R^inf),
+ * K1 = L^inf Pi R^inf.  The product per bosonic frequency and combination is a complex
+ * (2N + 1) x 2Nq x (2N + 1) GEMM (rocBLAS ZGEMM, strided batched over m).  left and right on
+ * the same grid; out: all four classes (device, overwritten).  FP64.  KQFT_EINVAL for NULL
+ * arguments, a bad channel or non-positive T / Delta; KQFT_ESHAPE for mismatched grids, M < 0,
+ * N < 1, Nq < 1 or sizes whose panels exceed 2^31 entries.
+ */
+int kqft_bubble_matsubara(kqft_ctx* ctx, int channel, const kqft_mvertex* left, const kqft_mvertex* right,
+                          const kqft_mprop* G, int Nq, const kqft_chout* out, void* stream);
+
 /*
  * kqft_loop -- the loop function of a full vertex (Sec. "loop": the self-energy-like
  * contraction of a vertex with one propagator line):

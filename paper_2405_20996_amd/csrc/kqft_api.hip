@@ -44,7 +44,7 @@ struct kqft_ctx {
   // consecutive transfer-frequency batches overlap, ordered by events
   hipStream_t sg = nullptr, sm = nullptr;
   rocblas_handle blas = nullptr;
-  DevBuf adjw, dkf[2][3], phigrad, pq, pqsig, pqred, vtab[3], flow, flowml, ctmp, flowred, pqx, adapt, sdep;
+  DevBuf adjw, dkf[2][3], phigrad, pq, pqsig, pqred, vtab[3], flow, flowml, ctmp, flowred, pqx, adapt, sdep, mf;
   std::vector<hipEvent_t> events;
   size_t next_event = 0;
   bool prof = false;
@@ -971,7 +971,7 @@ int kqft_ctx_destroy(kqft_ctx* ctx) {
       if (b.p) (void)hipFree(b.p);
   if (ctx->adjw.p) (void)hipFree(ctx->adjw.p);
   for (DevBuf* b : {&ctx->pq, &ctx->pqsig, &ctx->pqred, &ctx->vtab[0], &ctx->vtab[1], &ctx->vtab[2], &ctx->flow,
-                    &ctx->flowml, &ctx->ctmp, &ctx->flowred, &ctx->pqx, &ctx->adapt, &ctx->sdep})
+                    &ctx->flowml, &ctx->ctmp, &ctx->flowred, &ctx->pqx, &ctx->adapt, &ctx->sdep, &ctx->mf})
     if (b->p) (void)hipFree(b->p);
   if (ctx->phigrad.p) (void)hipFree(ctx->phigrad.p);
   if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
@@ -1287,6 +1287,97 @@ int kqft_chi(kqft_ctx* ctx, int channel, const kqft_vertex* gamma, const kqft_pr
   if ((rc = get_grid(ctx, gamma->grid, &nodes))) return rc;
   const hipStream_t s = (hipStream_t)stream;
   if ((rc = chi_core(ctx, channel, *gamma, P, nodes, *q, chi, s))) return rc;
+  HIP_TRY(hipGetLastError());
+  return KQFT_OK;
+}
+
+int kqft_bubble_matsubara(kqft_ctx* ctx, int channel, const kqft_mvertex* left, const kqft_mvertex* right,
+                          const kqft_mprop* G, int Nq, const kqft_chout* out, void* stream) {
+  int rc;
+  if (!ctx) return fail(KQFT_EINVAL, "ctx is NULL");
+  if (!left || !right || !G || !out) return fail(KQFT_EINVAL, "vertices, propagator and outputs must be given");
+  if (channel < KQFT_CH_A || channel > KQFT_CH_T) return fail(KQFT_EINVAL, "channel must be 0, 1 or 2");
+  const kqft_mgrid g = left->grid;
+  if (g.M < 0 || g.N < 1 || Nq < 1) return fail(KQFT_ESHAPE, "need M >= 0, N >= 1, Nq >= 1");
+  if (right->grid.M != g.M || right->grid.N != g.N || right->grid.T != g.T)
+    return fail(KQFT_ESHAPE, "left and right must share the Matsubara grid");
+  if (!(g.T > 0) || !(G->Delta > 0)) return fail(KQFT_EINVAL, "T and Delta must be positive");
+  if (G->sigma_N < 0 || (G->sigma && G->sigma_N == 0)) return fail(KQFT_ESHAPE, "invalid self-energy box");
+  if (!out->K1 || !out->K2 || !out->K2p || !out->K3) return fail(KQFT_EINVAL, "all four output classes are required");
+  const long R = 2L * g.N + 1, Kw = 2L * Nq, nbos = 2L * g.M + 1;
+  if (R * Kw > (1L << 30) || R * R > (1L << 30)) return fail(KQFT_ESHAPE, "Matsubara panels too large");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  if (!ctx->blas && (rc = blas_ok(rocblas_create_handle(&ctx->blas), "rocblas_create_handle"))) return rc;
+  if ((rc = blas_ok(rocblas_set_stream(ctx->blas, s), "rocblas_set_stream"))) return rc;
+  // per bosonic frequency: A and B for two combinations, C for two
+  const size_t per_m = (size_t)(4 * R * Kw + 2 * R * R) * sizeof(double2);
+  const long nb = std::max(1L, std::min(nbos, (long)((size_t)(512u << 20) / per_m)));
+  if (nb * R * Kw > (1L << 31) - 1) return fail(KQFT_ESHAPE, "Matsubara panels too large");
+  if ((rc = ensure(ctx->mf, (size_t)nb * per_m))) return rc;
+  double2* base = (double2*)ctx->mf.p;
+  double2* A[2] = {base, base + (size_t)nb * R * Kw};
+  double2* B[2] = {base + 2 * (size_t)nb * R * Kw, base + 3 * (size_t)nb * R * Kw};
+  double2* Cm[2] = {base + 4 * (size_t)nb * R * Kw, base + 4 * (size_t)nb * R * Kw + (size_t)nb * R * R};
+  auto side = [&](const kqft_mvertex& v, double2* const* P, int m0, int cnt) {
+    MGatherArgs a;
+    memset(&a, 0, sizeof a);
+    a.r = channel;
+    a.M = g.M;
+    a.N = g.N;
+    a.Nq = Nq;
+    a.m0 = m0;
+    a.nb = cnt;
+    a.T = g.T;
+    a.Delta = G->Delta;
+    a.sigma = (const double2*)G->sigma;
+    a.Ns = G->sigma ? G->sigma_N : 0;
+    a.U = v.U;
+    for (int r = 0; r < 3; ++r)
+      a.ch[r] = MChan{v.ch[r].coef, {(const double2*)v.ch[r].K1, (const double2*)v.ch[r].K2,
+                                     (const double2*)v.ch[r].K2p, (const double2*)v.ch[r].K3}};
+    for (int u = 0; u < 4; ++u) a.mix[u] = kMix[channel][u];
+    a.P[0] = P[0];
+    a.P[1] = P[1];
+    return a;
+  };
+  const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
+  for (int m0 = -g.M; m0 <= g.M; m0 += (int)nb) {
+    const int cnt = (int)std::min<long>(nb, g.M - m0 + 1);
+    {
+      ProfScope ps(ctx, 1, s);
+      launch_mf_left(side(*left, A, m0, cnt), s);
+      launch_mf_right(side(*right, B, m0, cnt), s);
+    }
+    // row-major C = A B per frequency and combination, as column-major C^T = B^T A^T
+    for (int c = 0; c < 2; ++c) {
+      ProfScope ps(ctx, 2, s);
+      if ((rc = blas_ok(rocblas_zgemm_strided_batched(ctx->blas, rocblas_operation_none, rocblas_operation_none,
+                                                      (int)R, (int)R, (int)Kw, &one,
+                                                      (const rocblas_double_complex*)B[c], (int)R, R * Kw,
+                                                      (const rocblas_double_complex*)A[c], (int)Kw, R * Kw, &zero,
+                                                      (rocblas_double_complex*)Cm[c], (int)R, R * R, cnt),
+                        "rocblas_zgemm_strided_batched")))
+        return rc;
+    }
+    MEpiArgs e;
+    memset(&e, 0, sizeof e);
+    e.M = g.M;
+    e.N = g.N;
+    e.m0 = m0;
+    e.nb = cnt;
+    for (int u = 0; u < 4; ++u) e.unmix[u] = kUnmix[channel][u];
+    e.C[0] = Cm[0];
+    e.C[1] = Cm[1];
+    e.K[0] = (double2*)out->K1;
+    e.K[1] = (double2*)out->K2;
+    e.K[2] = (double2*)out->K2p;
+    e.K[3] = (double2*)out->K3;
+    {
+      ProfScope ps(ctx, 3, s);
+      launch_mf_epilogue(e, s);
+    }
+  }
   HIP_TRY(hipGetLastError());
   return KQFT_OK;
 }

@@ -2080,4 +2080,172 @@ void launch_mix(double2* x, const double2* f, size_t count, double alpha, hipStr
 }
 int chi_blocks(int nq) { return (int)std::min<long>(512, std::max<long>(1, ((long)nq * nq + 255) / 256)); }
 
+// ======================================================================== Matsubara formalism
+// Leg indices (n1', n2', n1, n2) of channel r's (m, n, n') and back, every leg fermionic:
+//   a: n2 = n, n1' = n + m, n2' = n', n1 = n' + m;  p: n1' = n, n2' = m - n - 1, n1 = n',
+//   n2 = m - n' - 1;  t: n2 = n, n2' = n + m, n1' = n', n1 = n' + m.
+__device__ inline void mf_legs(int r, int m, int n, int np, int L[4]) {
+  if (r == 0) {
+    L[0] = n + m; L[1] = np; L[2] = np + m; L[3] = n;
+  } else if (r == 1) {
+    L[0] = n; L[1] = m - n - 1; L[2] = np; L[3] = m - np - 1;
+  } else {
+    L[0] = np; L[1] = n + m; L[2] = np + m; L[3] = n;
+  }
+}
+__device__ inline void mf_params(int r, const int L[4], int& m, int& n, int& np) {
+  if (r == 0) {
+    m = L[0] - L[3]; n = L[3]; np = L[1];
+  } else if (r == 1) {
+    m = L[0] + L[1] + 1; n = L[0]; np = L[2];
+  } else {
+    m = L[1] - L[3]; n = L[3]; np = L[0];
+  }
+}
+
+// selected classes (bit 0 K1, 1 K2, 2 K2', 3 K3) of one channel at its own (m, n, n'), zero
+// outside the boxes: XY = {X, Y}
+__device__ inline void mf_chan(const MChan& c, int M, int N, int m, int n, int np, int parts, double2 XY[2]) {
+  if (c.coef == 0.0 || m < -M || m > M) return;
+  const size_t nb = 2 * (size_t)M + 1, nf = 2 * (size_t)N, im = (size_t)(m + M);
+  const bool in_n = n >= -N && n < N, in_np = np >= -N && np < N;
+  double2 acc[2] = {czero(), czero()};
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp) {
+    if ((parts & 1) && c.K[0]) acc[sp] = cadd(acc[sp], c.K[0][sp * nb + im]);
+    if ((parts & 2) && c.K[1] && in_n) acc[sp] = cadd(acc[sp], c.K[1][(sp * nb + im) * nf + (n + N)]);
+    if ((parts & 4) && c.K[2] && in_np) acc[sp] = cadd(acc[sp], c.K[2][(sp * nb + im) * nf + (np + N)]);
+    if ((parts & 8) && c.K[3] && in_n && in_np)
+      acc[sp] = cadd(acc[sp], c.K[3][((sp * nb + im) * nf + (n + N)) * nf + (np + N)]);
+    XY[sp] = cfma(c.coef, acc[sp], XY[sp]);
+  }
+}
+
+// the other two channels of the full vertex at channel r's (m, n, n')
+__device__ inline void mf_others(const MGatherArgs& a, int m, int n, int np, double2 XY[2]) {
+  int L[4];
+  mf_legs(a.r, m, n, np, L);
+#pragma unroll
+  for (int d = 1; d < 3; ++d) {
+    const int r2 = (a.r + d) % 3;
+    int m2, n2, np2;
+    mf_params(r2, L, m2, n2, np2);
+    mf_chan(a.ch[r2], a.M, a.N, m2, n2, np2, 15, XY);
+  }
+}
+
+// G(i nu_n) = 1/(i nu_n + i Delta sgn(nu_n) - Sigma(n))
+__device__ inline double2 mf_G(const MGatherArgs& a, int n) {
+  const double v = (2.0 * n + 1.0) * M_PI * a.T;
+  double2 sg = czero();
+  if (a.sigma && n >= -a.Ns && n < a.Ns) sg = a.sigma[n + a.Ns];
+  return cinv(make_double2(-sg.x, v + (v > 0.0 ? a.Delta : -a.Delta) - sg.y));
+}
+
+// first index and length of channel r's window |2n'' + 1 + s m| <= 2 Nq - 1 (s = -1 for p)
+__device__ inline int mf_window_lo(int r, int m, int Nq) {
+  const int sm = r == 1 ? -m : m;
+  const int x = -2 * Nq - sm;  // 2 lo >= -(2Nq - 1) - 1 - s m
+  return (x >= 0) ? (x + 1) / 2 : -((-x) / 2);
+}
+__device__ inline int mf_window_len(int m, int Nq) { return 2 * Nq - ((m & 1) ? 1 : 0); }
+
+__global__ __launch_bounds__(256) void mf_left_kernel(MGatherArgs a) {
+  const int R = 2 * a.N + 1, Kw = 2 * a.Nq;
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long per = (long)R * Kw;
+  if (tid >= per * a.nb) return;
+  const int b = (int)(tid / per), rem = (int)(tid - (long)b * per), i = rem / Kw, k = rem - i * Kw;
+  const int m = a.m0 + b;
+  const size_t off = (size_t)b * per + (size_t)i * Kw + k;
+  if (k >= mf_window_len(m, a.Nq)) {
+    a.P[0][off] = czero();
+    a.P[1][off] = czero();
+    return;
+  }
+  const int nq = mf_window_lo(a.r, m, a.Nq) + k;
+  const double2 pi = a.r == 1 ? cmul(mf_G(a, nq), mf_G(a, m - nq - 1)) : cmul(mf_G(a, nq + m), mf_G(a, nq));
+  double2 XY[2] = {czero(), czero()};
+  if (i < 2 * a.N) {  // L - L^inf: own K2(m, n) + K3(m, n, n''), the other channels
+    const int n = i - a.N;
+    mf_chan(a.ch[a.r], a.M, a.N, m, n, nq, 2 | 8, XY);
+    mf_others(a, m, n, nq, XY);
+  } else {  // L^inf = Gamma_0 + own K1(m) + K2'(m, n'')
+    XY[0] = make_double2(-a.U, 0.0);
+    XY[1] = make_double2(a.U, 0.0);
+    mf_chan(a.ch[a.r], a.M, a.N, m, 0, nq, 1 | 4, XY);
+  }
+  const double2 p = cscale(a.T, pi);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const double2 v = cadd(cscale(a.mix[2 * c], XY[0]), cscale(a.mix[2 * c + 1], XY[1]));
+    a.P[c][off] = cmul(v, p);
+  }
+}
+
+__global__ __launch_bounds__(256) void mf_right_kernel(MGatherArgs a) {
+  const int R = 2 * a.N + 1, Kw = 2 * a.Nq;
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long per = (long)R * Kw;
+  if (tid >= per * a.nb) return;
+  const int b = (int)(tid / per), rem = (int)(tid - (long)b * per), k = rem / R, j = rem - k * R;
+  const int m = a.m0 + b;
+  const size_t off = (size_t)b * per + (size_t)k * R + j;
+  if (k >= mf_window_len(m, a.Nq)) {
+    a.P[0][off] = czero();
+    a.P[1][off] = czero();
+    return;
+  }
+  const int nq = mf_window_lo(a.r, m, a.Nq) + k;
+  double2 XY[2] = {czero(), czero()};
+  if (j < 2 * a.N) {  // R - R^inf: own K2'(m, n') + K3(m, n'', n'), the other channels
+    const int np = j - a.N;
+    mf_chan(a.ch[a.r], a.M, a.N, m, nq, np, 4 | 8, XY);
+    mf_others(a, m, nq, np, XY);
+  } else {  // R^inf = Gamma_0 + own K1(m) + K2(m, n'')
+    XY[0] = make_double2(-a.U, 0.0);
+    XY[1] = make_double2(a.U, 0.0);
+    mf_chan(a.ch[a.r], a.M, a.N, m, nq, 0, 1 | 2, XY);
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c) a.P[c][off] = cadd(cscale(a.mix[2 * c], XY[0]), cscale(a.mix[2 * c + 1], XY[1]));
+}
+
+__global__ __launch_bounds__(256) void mf_epilogue_kernel(MEpiArgs a) {
+  const int R = 2 * a.N + 1, nf = 2 * a.N;
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long per = (long)R * R;
+  if (tid >= per * a.nb) return;
+  const int b = (int)(tid / per), rem = (int)(tid - (long)b * per), i = rem / R, j = rem - i * R;
+  const double2 P0 = a.C[0][tid], P1 = a.C[1][tid];
+  const double2 XY[2] = {cadd(cscale(a.unmix[0], P0), cscale(a.unmix[1], P1)),
+                         cadd(cscale(a.unmix[2], P0), cscale(a.unmix[3], P1))};
+  const size_t nb = 2 * (size_t)a.M + 1, im = (size_t)(a.m0 + b + a.M);
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp) {
+    if (i < nf && j < nf) {
+      if (a.K[3]) a.K[3][((sp * nb + im) * nf + i) * nf + j] = XY[sp];
+    } else if (i < nf) {
+      if (a.K[1]) a.K[1][(sp * nb + im) * nf + i] = XY[sp];
+    } else if (j < nf) {
+      if (a.K[2]) a.K[2][(sp * nb + im) * nf + j] = XY[sp];
+    } else {
+      if (a.K[0]) a.K[0][sp * nb + im] = XY[sp];
+    }
+  }
+}
+
+void launch_mf_left(const MGatherArgs& a, hipStream_t s) {
+  const long total = (long)(2 * a.N + 1) * (2 * a.Nq) * a.nb;
+  hipLaunchKernelGGL(mf_left_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);
+}
+void launch_mf_right(const MGatherArgs& a, hipStream_t s) {
+  const long total = (long)(2 * a.N + 1) * (2 * a.Nq) * a.nb;
+  hipLaunchKernelGGL(mf_right_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);
+}
+void launch_mf_epilogue(const MEpiArgs& a, hipStream_t s) {
+  const long total = (long)(2 * a.N + 1) * (2 * a.N + 1) * a.nb;
+  hipLaunchKernelGGL(mf_epilogue_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);
+}
+
 }  // namespace kqft

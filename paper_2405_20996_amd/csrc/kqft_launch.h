@@ -235,4 +235,36 @@ void launch_errnorm(const double2* err, const double2* y, const double2* y4, dou
 void launch_axpby(double2* out, double a, const double2* x, double b, const double2* y, size_t count,
                   hipStream_t s);
 
+// ------------------------------------------------------------------ Matsubara formalism
+// One channel on the Matsubara boxes: K1[s][m], K2[s][m][n], K2'[s][m][n'], K3[s][m][n][n'],
+// m in [-M, M], n, n' in [-N, N) (nullptr = absent).
+struct MChan {
+  double coef;
+  const double2* K[4];
+};
+// Panels of one side of a Matsubara bubble for the bosonic indices m = m0 + b, b < nb:
+// left A_c[b][i][k] (i < 2N: (L - L^inf)(m, n_i, n''_k) T Pi(m, n''_k); i = 2N: L^inf T Pi),
+// right B_c[b][k][j] (j < 2N: (R - R^inf)(m, n''_k, n'_j); j = 2N: R^inf), k < 2 Nq over the
+// window of channel r's bubble (zero past its end), c = 0, 1 the spin combinations of P[c].
+struct MGatherArgs {
+  int r, M, N, Nq, m0, nb;
+  double T, Delta;
+  const double2* sigma;  // G's self-energy on n in [-Ns, Ns), or null
+  int Ns;
+  double U;  // bare vertex X0 = -U, Y0 = +U
+  MChan ch[3];
+  double mix[4];
+  double2* P[2];
+};
+// C_c[b][i][j] (i, j <= 2N) -> classes of channel r at m = m0 + b (unmix with the prefactor)
+struct MEpiArgs {
+  int M, N, m0, nb;
+  double unmix[4];
+  const double2* C[2];
+  double2* K[4];
+};
+void launch_mf_left(const MGatherArgs& a, hipStream_t s);
+void launch_mf_right(const MGatherArgs& a, hipStream_t s);
+void launch_mf_epilogue(const MEpiArgs& a, hipStream_t s);
+
 }  // namespace kqft

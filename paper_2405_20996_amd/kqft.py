@@ -43,6 +43,18 @@ class KqftVertex(C.Structure):
     _fields_ = [("r0", C.c_double), ("grid", KqftGrid), ("ch", KqftChvert * 3)]
 
 
+class KqftMGrid(C.Structure):
+    _fields_ = [("M", C.c_int), ("N", C.c_int), ("T", C.c_double)]
+
+
+class KqftMVertex(C.Structure):
+    _fields_ = [("grid", KqftMGrid), ("U", C.c_double), ("ch", KqftChvert * 3)]
+
+
+class KqftMProp(C.Structure):
+    _fields_ = [("Delta", C.c_double), ("sigma", C.c_void_p), ("sigma_N", C.c_int)]
+
+
 class KqftPropagator(C.Structure):
     _fields_ = [("Delta", C.c_double), ("T", C.c_double), ("eps", C.c_double), ("sgrid", KqftGrid),
                 ("SigR", C.c_void_p), ("SigK", C.c_void_p), ("reg", C.c_int), ("lam", C.c_double),
@@ -112,6 +124,8 @@ def lib():
                                              P(KqftChout), C.c_void_p, C.c_void_p]
         _lib.kqft_chi.argtypes = [C.c_void_p, C.c_int, P(KqftVertex), P(KqftPropagator), P(KqftQuad), C.c_void_p,
                                   C.c_void_p]
+        _lib.kqft_bubble_matsubara.argtypes = [C.c_void_p, C.c_int, P(KqftMVertex), P(KqftMVertex), P(KqftMProp),
+                                               C.c_int, P(KqftChout), C.c_void_p]
         _lib.kqft_loop.argtypes = [C.c_void_p, P(KqftVertex), P(KqftPropagator), C.c_int, P(KqftQuad), C.c_void_p,
                                    C.c_void_p]
         _lib.kqft_mfrg_flow.argtypes = [C.c_void_p, P(KqftGrid), C.c_double, C.c_double, C.c_double, C.c_double,
@@ -292,6 +306,40 @@ def _opts(precision, class_mask, beta, omega_batch, overlap=0) -> KqftOpts:
     return KqftOpts(precision, class_mask, beta, omega_batch, overlap)
 
 
+@dataclass
+class MGrid:
+    """Matsubara boxes: bosonic m in [-M, M], fermionic n in [-N, N), temperature T."""
+    M: int
+    N: int
+    T: float
+
+    def c(self) -> KqftMGrid:
+        return KqftMGrid(self.M, self.N, self.T)
+
+    def shape(self, name: str) -> tuple:
+        nb, nf = 2 * self.M + 1, 2 * self.N
+        return {"K1": (2, nb), "K2": (2, nb, nf), "K2p": (2, nb, nf), "K3": (2, nb, nf, nf)}[name]
+
+
+@dataclass
+class MVertex:
+    """Matsubara vertex Gamma_0 (X0 = -U, Y0 = +U) + sum_r coef_r gamma_r (device tensors)."""
+    grid: MGrid
+    U: float = 0.0
+    ch: list = field(default_factory=lambda: [Channel(0.0), Channel(0.0), Channel(0.0)])
+
+    def c(self) -> KqftMVertex:
+        v = KqftMVertex()
+        v.grid = self.grid.c()
+        v.U = self.U
+        for r in range(3):
+            chn = self.ch[r]
+            v.ch[r].coef = chn.coef
+            for name in CLASSES:
+                setattr(v.ch[r], name, _ptr(getattr(chn, name), self.grid.shape(name), f"ch{r}.{name}"))
+        return v
+
+
 def alloc_channel(n: int, device=None, zero: bool = True) -> Channel:
     dev = device or torch.device("cuda", torch.cuda.current_device())
     f = torch.zeros if zero else torch.empty
@@ -344,6 +392,25 @@ def chi(channel: int, gamma: Vertex, G: Propagator, q: Quad, stream=None) -> tor
     vc, gc, qc = gamma.c(), G.c(), q.c()
     _check(lib().kqft_chi(ctx(), channel, C.byref(vc), C.byref(gc), C.byref(qc), C.c_void_p(out.data_ptr()),
                           _stream(stream)))
+    return out
+
+
+def bubble_matsubara(channel: int, left: MVertex, right: MVertex, Delta: float, Nq: int,
+                     sigma: Optional[torch.Tensor] = None, out: Optional[Channel] = None, stream=None) -> Channel:
+    """B_channel(left, right) in the Matsubara formalism (sum over 2 Nq fermionic frequencies about
+    the bubble's centre); sigma: Sigma(i nu_n) on n in [-Ns, Ns) (length 2 Ns) or None."""
+    g = left.grid
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if out is None:
+        out = Channel(1.0, *[torch.zeros(g.shape(c), dtype=torch.complex128, device=dev) for c in CLASSES])
+    ns = 0 if sigma is None else sigma.shape[0] // 2
+    if sigma is not None and sigma.shape[0] != 2 * ns:
+        raise ValueError("sigma needs an even length 2 Ns")
+    gp = KqftMProp(Delta, _ptr(sigma, None, "sigma"), ns)
+    oc = KqftChout(*[_ptr(getattr(out, c), g.shape(c), f"out.{c}") for c in CLASSES])
+    lc, rc = left.c(), right.c()
+    _check(lib().kqft_bubble_matsubara(ctx(), channel, C.byref(lc), C.byref(rc), C.byref(gp), Nq, C.byref(oc),
+                                       _stream(stream)))
     return out
 
 
