@@ -285,6 +285,18 @@ int kqft_bubble_matsubara(kqft_ctx* ctx, int channel, const kqft_mvertex* left, 
                           const kqft_mprop* G, int Nq, const kqft_chout* out, void* stream);
 
 /*
+ * kqft_sde_matsubara -- the Schwinger-Dyson self-energy in the Matsubara formalism (a-channel
+ * form, Hartree part absorbed at particle-hole symmetry):
+ *   Phi = B_a(Gamma_0, Gamma) (kqft_bubble_matsubara, window Nq; classes K1 and K2'),
+ *   Sigma(n) = -1/2 T sum_{n'} [2 Phi^X + Phi^Y](m = n - n', n', n') G(n'),  |2n' + 1| <= 2 Nl - 1,
+ * for n in [-N, N); Phi is zero outside its boxes (take M >= N + Nl to keep every term).
+ * sigma_out: device [2N] complex (index n + N).  FP64.  Errors as kqft_bubble_matsubara, and
+ * KQFT_ESHAPE for Nl < 1.
+ */
+int kqft_sde_matsubara(kqft_ctx* ctx, const kqft_mvertex* gamma, const kqft_mprop* G, int Nq, int Nl,
+                       double* sigma_out, void* stream);
+
+/*
  * kqft_loop -- the loop function of a full vertex (Sec. "loop": the self-energy-like
  * contraction of a vertex with one propagator line):
  *   L(Gamma, X)^{a1'|a1}(v_i) = sum_j w_j/(2 pi i) sum_{a2,a2'} [2 Gamma^X + Gamma^Y]

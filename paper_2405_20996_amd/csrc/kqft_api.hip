@@ -1382,6 +1382,47 @@ int kqft_bubble_matsubara(kqft_ctx* ctx, int channel, const kqft_mvertex* left, 
   return KQFT_OK;
 }
 
+int kqft_sde_matsubara(kqft_ctx* ctx, const kqft_mvertex* gamma, const kqft_mprop* G, int Nq, int Nl,
+                       double* sigma_out, void* stream) {
+  int rc;
+  if (!ctx) return fail(KQFT_EINVAL, "ctx is NULL");
+  if (!gamma || !G || !sigma_out) return fail(KQFT_EINVAL, "vertex, propagator and sigma_out must be given");
+  if (Nl < 1) return fail(KQFT_ESHAPE, "need Nl >= 1");
+  const kqft_mgrid g = gamma->grid;
+  if (g.M < 0 || g.N < 1) return fail(KQFT_ESHAPE, "need M >= 0, N >= 1");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  // Phi = B_a(Gamma_0, Gamma): all four classes into the scratch (K2 and K3 vanish)
+  const size_t nb = 2 * (size_t)g.M + 1, nf = 2 * (size_t)g.N;
+  const size_t c1 = 2 * nb, c2 = 2 * nb * nf, c3 = 2 * nb * nf * nf;
+  if ((rc = ensure(ctx->phi, (c1 + 2 * c2 + c3) * sizeof(double2)))) return rc;
+  double2* ph = (double2*)ctx->phi.p;
+  kqft_chout po{(double*)ph, (double*)(ph + c1), (double*)(ph + c1 + c2), (double*)(ph + c1 + 2 * c2)};
+  kqft_mvertex bare;
+  memset(&bare, 0, sizeof bare);
+  bare.grid = g;
+  bare.U = gamma->U;
+  if ((rc = kqft_bubble_matsubara(ctx, KQFT_CH_A, &bare, gamma, G, Nq, &po, stream))) return rc;
+  MLoopArgs la;
+  memset(&la, 0, sizeof la);
+  la.M = g.M;
+  la.N = g.N;
+  la.Nl = Nl;
+  la.T = g.T;
+  la.Delta = G->Delta;
+  la.sigma = (const double2*)G->sigma;
+  la.Ns = G->sigma ? G->sigma_N : 0;
+  la.K1 = ph;
+  la.K2p = ph + c1 + c2;
+  la.out = (double2*)sigma_out;
+  {
+    ProfScope ps(ctx, 3, s);
+    launch_mf_loop(la, s);
+  }
+  HIP_TRY(hipGetLastError());
+  return KQFT_OK;
+}
+
 int kqft_loop(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, int kind, const kqft_quad* q,
               double* out, void* stream) {
   int rc;

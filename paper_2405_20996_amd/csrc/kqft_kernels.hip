@@ -2235,6 +2235,35 @@ __global__ __launch_bounds__(256) void mf_epilogue_kernel(MEpiArgs a) {
   }
 }
 
+// one thread per output frequency; the sum runs in a fixed order (deterministic)
+__global__ __launch_bounds__(256) void mf_loop_kernel(MLoopArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * a.N) return;
+  const int n = i - a.N;
+  const size_t nb = 2 * (size_t)a.M + 1, nf = 2 * (size_t)a.N;
+  double2 acc = czero();
+  for (int k = -a.Nl; k < a.Nl; ++k) {
+    const int m = n - k;
+    if (m < -a.M || m > a.M) continue;
+    const size_t im = (size_t)(m + a.M);
+    double2 X = a.K1[im], Y = a.K1[nb + im];
+    if (k >= -a.N && k < a.N) {
+      X = cadd(X, a.K2p[im * nf + (k + a.N)]);
+      Y = cadd(Y, a.K2p[(nb + im) * nf + (k + a.N)]);
+    }
+    const double v = (2.0 * k + 1.0) * M_PI * a.T;
+    double2 sg = czero();
+    if (a.sigma && k >= -a.Ns && k < a.Ns) sg = a.sigma[k + a.Ns];
+    const double2 g = cinv(make_double2(-sg.x, v + (v > 0.0 ? a.Delta : -a.Delta) - sg.y));
+    acc = cadd(acc, cmul(cadd(cscale(2.0, X), Y), g));
+  }
+  a.out[i] = cscale(-0.5 * a.T, acc);
+}
+
+void launch_mf_loop(const MLoopArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(mf_loop_kernel, dim3((unsigned)((2 * a.N + 255) / 256)), dim3(256), 0, s, a);
+}
+
 void launch_mf_left(const MGatherArgs& a, hipStream_t s) {
   const long total = (long)(2 * a.N + 1) * (2 * a.Nq) * a.nb;
   hipLaunchKernelGGL(mf_left_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);

@@ -263,6 +263,18 @@ struct MEpiArgs {
   const double2* C[2];
   double2* K[4];
 };
+// Sigma(n) = -1/2 T sum_{n'} [2 Phi^X + Phi^Y](m = n - n', n', n') G(n') for n in [-N, N), n' in
+// [-Nl, Nl), Phi = K1 + K2' of an a-channel object on the boxes
+struct MLoopArgs {
+  int M, N, Nl;
+  double T, Delta;
+  const double2* sigma;  // G's self-energy on [-Ns, Ns), or null
+  int Ns;
+  const double2* K1;
+  const double2* K2p;
+  double2* out;
+};
+void launch_mf_loop(const MLoopArgs& a, hipStream_t s);
 void launch_mf_left(const MGatherArgs& a, hipStream_t s);
 void launch_mf_right(const MGatherArgs& a, hipStream_t s);
 void launch_mf_epilogue(const MEpiArgs& a, hipStream_t s);

@@ -126,6 +126,8 @@ def lib():
                                   C.c_void_p]
         _lib.kqft_bubble_matsubara.argtypes = [C.c_void_p, C.c_int, P(KqftMVertex), P(KqftMVertex), P(KqftMProp),
                                                C.c_int, P(KqftChout), C.c_void_p]
+        _lib.kqft_sde_matsubara.argtypes = [C.c_void_p, P(KqftMVertex), P(KqftMProp), C.c_int, C.c_int, C.c_void_p,
+                                            C.c_void_p]
         _lib.kqft_loop.argtypes = [C.c_void_p, P(KqftVertex), P(KqftPropagator), C.c_int, P(KqftQuad), C.c_void_p,
                                    C.c_void_p]
         _lib.kqft_mfrg_flow.argtypes = [C.c_void_p, P(KqftGrid), C.c_double, C.c_double, C.c_double, C.c_double,
@@ -411,6 +413,20 @@ def bubble_matsubara(channel: int, left: MVertex, right: MVertex, Delta: float, 
     lc, rc = left.c(), right.c()
     _check(lib().kqft_bubble_matsubara(ctx(), channel, C.byref(lc), C.byref(rc), C.byref(gp), Nq, C.byref(oc),
                                        _stream(stream)))
+    return out
+
+
+def sde_matsubara(gamma: MVertex, Delta: float, Nq: int, Nl: int, sigma: Optional[torch.Tensor] = None,
+                  stream=None) -> torch.Tensor:
+    """Sigma(i nu_n), n in [-N, N), from the Matsubara SDE (a-channel form) of gamma."""
+    g = gamma.grid
+    dev = torch.device("cuda", torch.cuda.current_device())
+    out = torch.zeros(2 * g.N, dtype=torch.complex128, device=dev)
+    ns = 0 if sigma is None else sigma.shape[0] // 2
+    gp = KqftMProp(Delta, _ptr(sigma, None, "sigma"), ns)
+    vc = gamma.c()
+    _check(lib().kqft_sde_matsubara(ctx(), C.byref(vc), C.byref(gp), Nq, Nl, C.c_void_p(out.data_ptr()),
+                                    _stream(stream)))
     return out
 
 

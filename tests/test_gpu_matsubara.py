@@ -110,3 +110,18 @@ def test_matsubara_bubble_time():
         print(f"Matsubara bubble r={r} M={M} N={N} Nq={Nq}: {dt * 1e3:.1f} ms, {flop / dt / 1e12:.1f} TFLOP/s "
               f"(algorithmic)", flush=True)
         assert bool(torch.isfinite(out.K3).all())
+
+
+def test_matsubara_sde_matches_oracle():
+    """Sigma from the Matsubara SDE (Phi = B_a(Gamma_0, Gamma) on the GPU, then the loop) for a
+    random vertex and a dynamic self-energy in G (M = N + Nl keeps every term)."""
+    K = _K()
+    M, N, Nq, Nl = 12, 4, 10, 8
+    ov, kv = _pair(M, N, 7, U=1.0)
+    Ns = 6
+    sig = 0.1 * np.exp(1j * np.linspace(0.0, 2.0, 2 * Ns)) - 0.05j
+    ref = MF.sde(ov, MF.MProp(D, T, sig), Nq, Nl)
+    out = K.sde_matsubara(kv, D, Nq, Nl, sigma=to_dev(sig)).cpu().numpy()
+    assert _rel(out, ref) < 1e-12
+    with pytest.raises(K.KqftError):
+        K.sde_matsubara(kv, D, Nq, 0)
