@@ -47,6 +47,15 @@
  *   NULL outputs) run before anything is enqueued.  `stream` is a hipStream_t
  *   (NULL = the default stream).  A kqft_ctx is not thread-safe: use one per
  *   stream.
+ *
+ * Graph capture
+ *   kqft_bubble and kqft_mloop_step enqueue no host synchronisation and no memset;
+ *   after one call with the same sizes (workspace grown, grids and quadratures
+ *   cached) they allocate nothing, so a call on a capturing stream records into the
+ *   graph -- the library's internal streams join through events recorded on
+ *   `stream` -- and the graph replays it (pointers as captured).  The solvers, the
+ *   flow, the Hartree term, the adaptive bubble and the adjoints synchronise or
+ *   clear memory and are not to be captured.
  */
 #ifndef KQFT_H
 #define KQFT_H
