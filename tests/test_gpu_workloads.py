@@ -163,3 +163,23 @@ def test_headline_workload_n201_sde_and_chi():
     ref_chi = O.chi_points(ov, op, oq, iws)
     c = chi.cpu().numpy()[:, iws]
     assert np.abs(c - ref_chi).max() < 1e-12 * np.abs(ref_chi).max()
+
+
+@pytest.mark.parametrize("r", [1, 2])
+def test_chi_of_the_p_and_t_channels_at_n101(r):
+    """kqft_chi in the p and t channels of the N = 101, Nq = 1001 seeded vertex (U = 1, T = 0.05),
+    FP64, against the oracle at four transfer frequencies (the edges and the middle)."""
+    K = _K()
+    n, nq = 101, 1001
+    noise = seed_noise(n, 0)
+    ov, kv, (og, oq, op), (g, q, P) = seeded(n, nq, 1.0, 0.05, noise)
+    import time
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chi = K.chi(r, kv, P, q)
+    torch.cuda.synchronize()
+    print(f"chi channel {r} at n={n}, nq={nq}: {time.perf_counter() - t0:.2f} s", flush=True)
+    iws = [0, 50, 51, 100]
+    ref = O.chi_channel(r, ov, op, oq, iws)
+    c = chi.cpu().numpy()[:, iws]
+    assert np.abs(c - ref).max() < 1e-12 * np.abs(ref).max()
