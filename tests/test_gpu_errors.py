@@ -79,3 +79,25 @@ def test_hartree_loop_propagator_and_adaptive_arguments():
     dout = K.alloc_channel(n)
     with pytest.raises(K.KqftError):  # adjoints take the plain Delta-regulated propagator
         K.bubble_adjoint(0, V, V, K.Propagator(D, T, reg=K.REG_U, lam=0.5), K.Quad(11), dout)
+
+
+def test_asymmetric_flow_level_flow_and_chi_arguments():
+    K = _K()
+    n = 5
+    g, q = K.Grid(n), K.Quad(11)
+    ch, sg = _state(K, n)
+    with pytest.raises(K.KqftError):  # the level must be finite
+        K.mfrg_flow(g, 1.0, T, 2.0, 1.0, 1, 1, q, q, ch, sg, K.FlowOptions(eps_d=float("nan")))
+    with pytest.raises(K.KqftError):
+        K.mfrg_flow(g, 1.0, T, 2.0, 1.0, 1, 1, q, q, ch, sg, K.FlowOptions(eps_d=0.1, sigma_inf=float("inf")))
+    V = K.Vertex(g, 1.0)
+    with pytest.raises(K.KqftError):  # a non-finite level flow
+        K.loop(V, K.Propagator(D, T, deps=float("nan")), q, K.LINE_S)
+    with pytest.raises(K.KqftError):  # adjoints take no level flow
+        K.bubble_adjoint(0, V, V, K.Propagator(D, T, deps=0.1), q, K.alloc_channel(n))
+    with pytest.raises(K.KqftError):  # the Hartree term takes no level flow
+        K.hartree(1.0, 0.0, K.Propagator(D, T, deps=0.1), K.Quad(101, 1, 0.0, 1.0))
+    with pytest.raises(K.KqftError):  # channel 0..2
+        K.chi(3, V, K.Propagator(D, T), q)
+    with pytest.raises(K.KqftError):  # chi indexes the double sum in 32 bits
+        K.chi(1, V, K.Propagator(D, T), K.Quad(46341))
