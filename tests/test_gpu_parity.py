@@ -162,6 +162,18 @@ def test_chi_of_every_channel_matches_oracle(r):
         K.chi(3, kv, K.Propagator(D, T), K.Quad(nq))
 
 
+@pytest.mark.parametrize("n,nq", [(2, 1), (3, 2), (5, 17)])
+def test_chi_edge_sizes(n, nq):
+    """kqft_chi at the smallest grids and quadratures (a single node, a single block of pairs)
+    in every channel."""
+    K = _K()
+    ov, kv = make_pair(n, (41, 42, 43), r0=U, amp=0.2)
+    for r in range(3):
+        ref = O.chi_channel(r, ov, O.Prop(D, T), O.Quad(nq))
+        out = K.chi(r, kv, K.Propagator(D, T), K.Quad(nq)).cpu().numpy()
+        assert rel(out, ref) < 1e-12, r
+
+
 def test_mloop_three_loops_matches_oracle():
     K = _K()
     n, nq = 9, 25
