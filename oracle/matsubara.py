@@ -254,3 +254,76 @@ def sde(V: MVertex, P: MProp, Nq: int, Nl: int) -> np.ndarray:
     phi = bubble(0, bare(V.grid, V.U), V, P, Nq)
     pv = MVertex(V.grid, 0.0, [MChannel(1.0, phi.K1, None, phi.K2p, None), MChannel(0.0), MChannel(0.0)])
     return -0.5 * loop(pv, P, Nl)
+
+
+# ------------------------------------------------------------------ parquet solver
+def state_pack(grid: MGrid, chans, sigma) -> np.ndarray:
+    """Channels a, p, t with classes K1, K2, K2', K3 each, then Sigma [2N], one flat vector."""
+    return np.concatenate([np.asarray(getattr(chans[r], c)).ravel() for r in range(3) for c in CLASSES]
+                          + [np.asarray(sigma).ravel()])
+
+
+def state_unpack(grid: MGrid, vec: np.ndarray):
+    sh = grid.shapes()
+    chans, off = [], 0
+    for r in range(3):
+        arrs = []
+        for c in CLASSES:
+            sz = int(np.prod(sh[c]))
+            arrs.append(vec[off:off + sz].reshape(sh[c]))
+            off += sz
+        chans.append(MChannel(1.0, *arrs))
+    return chans, vec[off:]
+
+
+def parquet_iteration(V: MVertex, P: MProp, Nq: int, Nl: int):
+    """Right-hand sides of the parquet equations in the Matsubara formalism: the symmetrized
+    Bethe-Salpeter equations gamma_r' = 1/2 [B_r(I_r, Gamma) + B_r(Gamma, I_r)], I_r = Gamma
+    without channel r, and the a-channel form of the SDE for Sigma (P carries Sigma)."""
+    out = []
+    for r in range(3):
+        ir = MVertex(V.grid, V.U, [V.ch[rr] if rr != r else MChannel(0.0) for rr in range(3)])
+        a = bubble(r, ir, V, P, Nq)
+        b = bubble(r, V, ir, P, Nq)
+        out.append(MChannel(1.0, *[0.5 * (getattr(a, c) + getattr(b, c)) for c in CLASSES]))
+    return out, sde(V, P, Nq, Nl)
+
+
+def pt2_state(grid: MGrid, U: float, Delta: float, Nq: int, Nl: int):
+    """PT2 start: K1_r = B_r(Gamma_0, Gamma_0) (the other classes vanish), Sigma^(2) = SDE(Gamma_0)."""
+    g0 = bare(grid, U)
+    P = MProp(Delta, grid.T)
+    chans = []
+    for r in range(3):
+        b = bubble(r, g0, g0, P, Nq)
+        chans.append(MChannel(1.0, b.K1, np.zeros_like(b.K2), np.zeros_like(b.K2p), np.zeros_like(b.K3)))
+    return chans, sde(g0, P, Nq, Nl)
+
+
+def parquet_solve(grid: MGrid, U: float, Delta: float, Nq: int, Nl: int, alpha: float = 0.5,
+                  iterations: int = 10, tol: float = 0.0, depth: int = 0, reduce_alpha: bool = False,
+                  alpha_min: float = 0.01):
+    """The parquet solver of the Keldysh oracle (PT2 start, mixing or Anderson acceleration,
+    residual = max over the arrays of max|F(x) - x| / max|F(x)|) on the Matsubara state, with G
+    dressed by the state's Sigma on [-N, N).  Returns (channels, Sigma, residuals)."""
+    from .oracle import fixed_point_solve
+    chans, sigma = pt2_state(grid, U, Delta, Nq, Nl)
+
+    def Fmap(vec):
+        ch, sg = state_unpack(grid, vec)
+        new, snew = parquet_iteration(MVertex(grid, U, ch), MProp(Delta, grid.T, np.array(sg)), Nq, Nl)
+        return state_pack(grid, new, snew)
+
+    def resid(x, g):
+        xc, xs = state_unpack(grid, x)
+        gc, gs = state_unpack(grid, g)
+        worst = 0.0
+        for a, f in [(getattr(xc[r], c), getattr(gc[r], c)) for r in range(3) for c in CLASSES] + [(xs, gs)]:
+            md, mf = float(np.abs(f - a).max()), float(np.abs(f).max())
+            worst = max(worst, md / mf if mf > 0 else (1.0 if md > 0 else 0.0))
+        return worst
+
+    x, res, _ = fixed_point_solve(Fmap, state_pack(grid, chans, sigma), resid, alpha, depth, iterations, tol,
+                                  reduce_alpha, alpha_min)
+    ch, sg = state_unpack(grid, x)
+    return ch, np.array(sg), res

@@ -143,3 +143,39 @@ def test_second_order_self_energy_is_the_spectral_representation_of_the_keldysh_
     spec = np.array([np.trapezoid(-imS / np.pi / (1j * vv - e), e) for vv in v])
     assert np.abs(s_mf - spec).max() < 2e-3 * np.abs(spec).max()
     assert np.abs(s_mf.real).max() < 1e-14  # particle-hole symmetry: Sigma(i nu) imaginary
+
+
+def test_matsubara_parquet_solution_third_order_expansion():
+    """The converged Matsubara parquet state, expanded in U, starts with the second- and
+    third-order diagrams: gamma_r = gamma_r^(2) + gamma_r^(3) + O(U^4) with gamma_r^(3) =
+    1/2 [B_r(Gamma_0, Gamma^(2)) + B_r(I_r^(2), Gamma_0) + B_r(Gamma_0, I_r^(2)) + B_r(Gamma^(2),
+    Gamma_0)] and Sigma = Sigma^(2) + Sigma^(3) + O(U^4) with Sigma^(3) = -1/2 L(B_a(Gamma_0,
+    Gamma^(2)), G): the remainders relative to the third-order terms shrink linearly with U."""
+    g = MF.MGrid(12, 4, T)
+    Nq, Nl = 12, 8
+    P0 = MF.MProp(D, T)
+    errs = []
+    for u in (0.1, 0.05):
+        chans, sig, res = MF.parquet_solve(g, u, D, Nq, Nl, alpha=1.0, iterations=40, tol=1e-14)
+        assert res[-1] < 1e-13
+        g0 = MF.bare(g, u)
+        k1 = [MF.bubble(r, g0, g0, P0, Nq).K1 for r in range(3)]
+        all2 = MF.MVertex(g, 0.0, [MF.MChannel(1.0, k1[r]) for r in range(3)])
+        e_g = 0.0
+        for r in range(3):
+            i2 = MF.MVertex(g, 0.0, [MF.MChannel(1.0, k1[rr]) if rr != r else MF.MChannel(0.0) for rr in range(3)])
+            terms = [MF.bubble(r, g0, all2, P0, Nq), MF.bubble(r, i2, g0, P0, Nq), MF.bubble(r, g0, i2, P0, Nq),
+                     MF.bubble(r, all2, g0, P0, Nq)]
+            for c in ("K1", "K2", "K2p"):
+                third = 0.5 * sum(getattr(t_, c) for t_ in terms)
+                second = k1[r] if c == "K1" else 0.0
+                e_g = max(e_g, np.abs(getattr(chans[r], c) - second - third).max() / np.abs(third).max())
+        s2 = MF.sde(g0, P0, Nq, Nl)
+        phi = MF.bubble(0, g0, all2, P0, Nq)
+        pv = MF.MVertex(g, 0.0, [MF.MChannel(1.0, phi.K1, None, phi.K2p, None), MF.MChannel(0.0), MF.MChannel(0.0)])
+        s3 = -0.5 * MF.loop(pv, P0, Nl)
+        e_s = np.abs(sig - s2 - s3).max() / np.abs(s3).max()
+        errs.append((e_g, e_s))
+    (g1, s1), (g2, s2_) = errs
+    assert g1 < 0.2 and s1 < 0.2
+    assert 0.3 < g2 / g1 < 0.7 and 0.3 < s2_ / s1 < 0.7
