@@ -505,6 +505,21 @@ int kqft_parquet_solve(kqft_ctx* ctx, const kqft_grid* grid, double U, double De
                        double* residuals, int* iterations, void* stream);
 
 /*
+ * kqft_parquet_solve_matsubara -- the parquet solver (kqft_parquet_solve: PT2 start, mixing or
+ * Anderson acceleration, automatic reduction of alpha, residual = max over the arrays of
+ * max|F(x) - x| / max|F(x)|) in the Matsubara formalism: F is the symmetrized Bethe-Salpeter
+ * equations with kqft_bubble_matsubara (window Nq) and the SDE of kqft_sde_matsubara (loop
+ * window Nl), G dressed by the state's Sigma on [-N, N).  popts: alpha, max_iterations, tol,
+ * anderson_depth, reduce_alpha, alpha_min; hartree must be 0 and sde_forms 0 or 1
+ * (KQFT_EINVAL otherwise).  gamma[3] (device, out; classes on grid), sigma (device [2N], out),
+ * residuals (host [max_iterations] or NULL), iterations (host, out).  FP64.  Synchronises
+ * `stream` once per iteration.  Working memory: (5 + 2m) states and one channel.
+ */
+int kqft_parquet_solve_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, double Delta, int Nq, int Nl,
+                                 const kqft_parquet_opts* popts, const kqft_chout* gamma, double* sigma,
+                                 double* residuals, int* iterations, void* stream);
+
+/*
  * kqft_mloop_step -- multiloop insertions of the mfRG flow (Eqs. 1l, 2l, 3l) for
  * n_points independent parameter points (ragged sizes allowed):
  *   l = 1:  gdot_r = B_r(Gamma, Gamma; Pidot),

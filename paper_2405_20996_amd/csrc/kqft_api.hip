@@ -44,7 +44,7 @@ struct kqft_ctx {
   // consecutive transfer-frequency batches overlap, ordered by events
   hipStream_t sg = nullptr, sm = nullptr;
   rocblas_handle blas = nullptr;
-  DevBuf adjw, dkf[2][3], phigrad, pq, pqsig, pqred, vtab[3], flow, flowml, ctmp, flowred, pqx, adapt, sdep, mf;
+  DevBuf adjw, dkf[2][3], phigrad, pq, pqsig, pqred, vtab[3], flow, flowml, ctmp, flowred, pqx, adapt, sdep, mf, mftmp;
   std::vector<hipEvent_t> events;
   size_t next_event = 0;
   bool prof = false;
@@ -971,7 +971,7 @@ int kqft_ctx_destroy(kqft_ctx* ctx) {
       if (b.p) (void)hipFree(b.p);
   if (ctx->adjw.p) (void)hipFree(ctx->adjw.p);
   for (DevBuf* b : {&ctx->pq, &ctx->pqsig, &ctx->pqred, &ctx->vtab[0], &ctx->vtab[1], &ctx->vtab[2], &ctx->flow,
-                    &ctx->flowml, &ctx->ctmp, &ctx->flowred, &ctx->pqx, &ctx->adapt, &ctx->sdep, &ctx->mf})
+                    &ctx->flowml, &ctx->ctmp, &ctx->flowred, &ctx->pqx, &ctx->adapt, &ctx->sdep, &ctx->mf, &ctx->mftmp})
     if (b->p) (void)hipFree(b->p);
   if (ctx->phigrad.p) (void)hipFree(ctx->phigrad.p);
   if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
@@ -1419,6 +1419,108 @@ int kqft_sde_matsubara(kqft_ctx* ctx, const kqft_mvertex* gamma, const kqft_mpro
     ProfScope ps(ctx, 3, s);
     launch_mf_loop(la, s);
   }
+  HIP_TRY(hipGetLastError());
+  return KQFT_OK;
+}
+
+static int fixed_point_core(kqft_ctx* ctx, size_t stc, double2* xb, double2* g, const kqft_parquet_opts& po,
+                            const std::function<int()>& eval, const std::function<int(double*)>& residual,
+                            double* residuals, int* iterations, hipStream_t s);
+
+int kqft_parquet_solve_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, double Delta, int Nq, int Nl,
+                                 const kqft_parquet_opts* popts, const kqft_chout* gamma, double* sigma,
+                                 double* residuals, int* iterations, void* stream) {
+  int rc;
+  if (!ctx) return fail(KQFT_EINVAL, "ctx is NULL");
+  if (!grid || !popts || !gamma || !sigma || !iterations)
+    return fail(KQFT_EINVAL, "grid, options, gamma, sigma and iterations must be given");
+  const kqft_mgrid g = *grid;
+  if (g.M < 0 || g.N < 1 || Nq < 1 || Nl < 1) return fail(KQFT_ESHAPE, "need M >= 0, N >= 1, Nq >= 1, Nl >= 1");
+  if (!(g.T > 0) || !(Delta > 0)) return fail(KQFT_EINVAL, "T and Delta must be positive");
+  const kqft_parquet_opts po = *popts;
+  if (!(po.alpha > 0) || po.alpha > 1 || po.max_iterations < 1)
+    return fail(KQFT_EINVAL, "need 0 < alpha <= 1, max_iterations >= 1");
+  if (po.anderson_depth < 0 || po.anderson_depth > 32) return fail(KQFT_EINVAL, "need 0 <= anderson_depth <= 32");
+  if (po.reduce_alpha && (!(po.alpha_min > 0) || po.alpha_min > po.alpha))
+    return fail(KQFT_EINVAL, "need 0 < alpha_min <= alpha");
+  if (po.hartree != 0 || (po.sde_forms != 0 && po.sde_forms != 1))
+    return fail(KQFT_EINVAL, "the Matsubara solver takes the symmetric model and the a-channel SDE");
+  for (int r = 0; r < 3; ++r)
+    if (!gamma[r].K1 || !gamma[r].K2 || !gamma[r].K2p || !gamma[r].K3)
+      return fail(KQFT_EINVAL, "gamma arrays must all be given");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const int m = po.anderson_depth;
+  const size_t nb = 2 * (size_t)g.M + 1, nf = 2 * (size_t)g.N;
+  const size_t cnt[4] = {2 * nb, 2 * nb * nf, 2 * nb * nf, 2 * nb * nf * nf};
+  const size_t chc = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+  const size_t stc = 3 * chc + nf;  // channels a, p, t (K1, K2, K2', K3), Sigma [2N]
+  if ((rc = ensure(ctx->pq, stc * sizeof(double2)))) return rc;
+  if ((rc = ensure(ctx->pqx, (size_t)(4 + 2 * m) * stc * sizeof(double2)))) return rc;
+  if ((rc = ensure(ctx->mftmp, chc * sizeof(double2)))) return rc;
+  double2* gb = (double2*)ctx->pq.p;
+  double2* xb = (double2*)ctx->pqx.p;
+  double2* tmp = (double2*)ctx->mftmp.p;
+  auto cls = [&](double2* base, int r, int c) {
+    size_t off = (size_t)r * chc;
+    for (int u = 0; u < c; ++u) off += cnt[u];
+    return base + off;
+  };
+  auto chout = [&](double2* base) {
+    return kqft_chout{(double*)base, (double*)(base + cnt[0]), (double*)(base + cnt[0] + cnt[1]),
+                      (double*)(base + cnt[0] + cnt[1] + cnt[2])};
+  };
+  double2* xsig = xb + 3 * chc;
+  // PT2 start: gamma_r = B_r(Gamma_0, Gamma_0) (K1 only), Sigma^(2) = SDE(Gamma_0), bare G
+  kqft_mvertex bare;
+  memset(&bare, 0, sizeof bare);
+  bare.grid = g;
+  bare.U = U;
+  const kqft_mprop G0{Delta, nullptr, 0};
+  for (int r = 0; r < 3; ++r) {
+    const kqft_chout o = chout(cls(xb, r, 0));
+    if ((rc = kqft_bubble_matsubara(ctx, r, &bare, &bare, &G0, Nq, &o, stream))) return rc;
+  }
+  if ((rc = kqft_sde_matsubara(ctx, &bare, &G0, Nq, Nl, (double*)xsig, stream))) return rc;
+  kqft_mvertex V;
+  memset(&V, 0, sizeof V);
+  V.grid = g;
+  V.U = U;
+  for (int r = 0; r < 3; ++r)
+    V.ch[r] = kqft_chvert{1.0, (const double*)cls(xb, r, 0), (const double*)cls(xb, r, 1),
+                          (const double*)cls(xb, r, 2), (const double*)cls(xb, r, 3)};
+  const kqft_mprop Gs{Delta, (const double*)xsig, g.N};
+  std::vector<std::pair<const double2*, const double2*>> xf;
+  std::vector<size_t> counts;
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 4; ++c) {
+      xf.push_back({cls(xb, r, c), cls(gb, r, c)});
+      counts.push_back(cnt[c]);
+    }
+  xf.push_back({xsig, gb + 3 * chc});
+  counts.push_back(nf);
+  // F: gamma_r' = 1/2 [B_r(I_r, Gamma) + B_r(Gamma, I_r)], Sigma' = SDE(Gamma) with the state's Sigma
+  auto eval = [&]() -> int {
+    for (int r = 0; r < 3; ++r) {
+      kqft_mvertex I = V;
+      I.ch[r] = kqft_chvert{0.0, nullptr, nullptr, nullptr, nullptr};
+      const kqft_chout o1 = chout(cls(gb, r, 0)), o2 = chout(tmp);
+      if ((rc = kqft_bubble_matsubara(ctx, r, &I, &V, &Gs, Nq, &o1, stream))) return rc;
+      if ((rc = kqft_bubble_matsubara(ctx, r, &V, &I, &Gs, Nq, &o2, stream))) return rc;
+      const double2* k[2] = {cls(gb, r, 0), tmp};
+      const double c[2] = {0.5, 0.5};
+      lincomb_n(cls(gb, r, 0), nullptr, 2, k, c, chc, s);
+    }
+    return kqft_sde_matsubara(ctx, &V, &Gs, Nq, Nl, (double*)(gb + 3 * chc), stream);
+  };
+  auto residual = [&](double* res) { return rel_change(ctx, xf, counts, s, res); };
+  if ((rc = fixed_point_core(ctx, stc, xb, gb, po, eval, residual, residuals, iterations, s))) return rc;
+  for (int r = 0; r < 3; ++r) {
+    double* dst[4] = {gamma[r].K1, gamma[r].K2, gamma[r].K2p, gamma[r].K3};
+    for (int c = 0; c < 4; ++c)
+      HIP_TRY(hipMemcpyAsync(dst[c], cls(xb, r, c), cnt[c] * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  }
+  HIP_TRY(hipMemcpyAsync(sigma, xsig, nf * sizeof(double2), hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipGetLastError());
   return KQFT_OK;
 }
@@ -1976,6 +2078,93 @@ int kqft_parquet_iteration(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_p
   return parquet_core(ctx, *gamma, *G, *q_bubble, *q_loop, *opts, out, sigma_out, (hipStream_t)stream);
 }
 
+// Fixed-point iteration x = F(x) of a device state vector of stc complex entries (Sec. parquet
+// solver): per iteration eval() writes g = F(x) for x = xb and residual() returns the relative
+// change; then x <- x + alpha f - sum_i gamma_i (dG_i - (1 - alpha) dF_i), f = g - x, with the
+// Anderson columns of the last m iterations and gamma from the shifted normal equations over
+// the real inner product; a growing residual halves alpha (reduce_alpha) and clears the
+// columns.  xb holds x, f, the previous f and g and the 2m columns (stc entries each).
+static int fixed_point_core(kqft_ctx* ctx, size_t stc, double2* xb, double2* g, const kqft_parquet_opts& po,
+                            const std::function<int()>& eval, const std::function<int(double*)>& residual,
+                            double* residuals, int* iterations, hipStream_t s) {
+  int rc;
+  const int m = po.anderson_depth;
+  double2 *fr = xb + stc, *fprev = xb + 2 * stc, *gprev = xb + 3 * stc;
+  std::vector<double2*> dF(m), dG(m);
+  for (int i = 0; i < m; ++i) {
+    dF[i] = xb + (size_t)(4 + i) * stc;
+    dG[i] = xb + (size_t)(4 + m + i) * stc;
+  }
+  double alpha = po.alpha, prev_res = 0.0;
+  int ncol = 0, head = 0, it = 0;
+  bool have_prev = false;
+  for (; it < po.max_iterations;) {
+    if ((rc = eval())) return rc;
+    double res = 0.0;
+    if ((rc = residual(&res))) return rc;
+    {  // f = g - x
+      const double2* k[2] = {g, xb};
+      const double c[2] = {1.0, -1.0};
+      lincomb_n(fr, nullptr, 2, k, c, stc, s);
+    }
+    if (po.reduce_alpha && it > 0 && res > prev_res) {
+      alpha = std::max(0.5 * alpha, po.alpha_min);
+      ncol = 0;
+    } else if (m > 0 && have_prev) {  // newest columns dF = f - f_prev, dG = g - g_prev
+      const int slot = head % m;
+      const double2* k[2] = {fr, fprev};
+      const double c[2] = {1.0, -1.0};
+      lincomb_n(dF[slot], nullptr, 2, k, c, stc, s);
+      const double2* kg[2] = {g, gprev};
+      lincomb_n(dG[slot], nullptr, 2, kg, c, stc, s);
+      ++head;
+      ncol = std::min(ncol + 1, m);
+    }
+    if (m > 0) {
+      HIP_TRY(hipMemcpyAsync(fprev, fr, stc * sizeof(double2), hipMemcpyDeviceToDevice, s));
+      HIP_TRY(hipMemcpyAsync(gprev, g, stc * sizeof(double2), hipMemcpyDeviceToDevice, s));
+      have_prev = true;
+    }
+    // x <- x + alpha f - sum_i gamma_i (dG_i - (1 - alpha) dF_i)
+    std::vector<const double2*> ks{fr};
+    std::vector<double> cs{alpha};
+    if (ncol > 0) {
+      std::vector<int> cols;
+      for (int i = 0; i < ncol; ++i) cols.push_back((head - ncol + i) % m);  // oldest first
+      std::vector<std::pair<const double2*, const double2*>> ab;
+      for (int i = 0; i < ncol; ++i)
+        for (int j = 0; j <= i; ++j) ab.push_back({dF[cols[i]], dF[cols[j]]});
+      for (int i = 0; i < ncol; ++i) ab.push_back({dF[cols[i]], fr});
+      std::vector<double> d;
+      if ((rc = dots(ctx, ab, stc, s, d))) return rc;
+      std::vector<double> A((size_t)ncol * ncol), b(ncol), gam;
+      size_t q = 0;
+      for (int i = 0; i < ncol; ++i)
+        for (int j = 0; j <= i; ++j, ++q) A[(size_t)i * ncol + j] = A[(size_t)j * ncol + i] = d[q];
+      double dmax = 0.0;
+      for (int i = 0; i < ncol; ++i) {
+        b[i] = d[q + i];
+        dmax = std::max(dmax, A[(size_t)i * ncol + i]);
+      }
+      for (int i = 0; i < ncol; ++i) A[(size_t)i * ncol + i] += 1e-14 * dmax;
+      if (!solve_small(A, b, ncol, gam)) return fail(KQFT_ENOCONV, "singular Anderson system");
+      for (int i = 0; i < ncol; ++i) {
+        ks.push_back(dG[cols[i]]);
+        cs.push_back(-gam[i]);
+        ks.push_back(dF[cols[i]]);
+        cs.push_back(gam[i] * (1.0 - alpha));
+      }
+    }
+    lincomb_n(xb, xb, (int)ks.size(), ks.data(), cs.data(), stc, s);
+    if (residuals) residuals[it] = res;
+    prev_res = res;
+    ++it;
+    if (res < po.tol) break;
+  }
+  *iterations = it;
+  return KQFT_OK;
+}
+
 int kqft_parquet_solve(kqft_ctx* ctx, const kqft_grid* grid, double U, double Delta, double T,
                        const kqft_quad* q_bubble, const kqft_quad* q_loop, const kqft_opts* opts,
                        const kqft_parquet_opts* popts, const kqft_chout* gamma, double* sigma, double* sigma_H,
@@ -2025,12 +2214,6 @@ int kqft_parquet_solve(kqft_ctx* ctx, const kqft_grid* grid, double U, double De
   if ((rc = ensure(ctx->pqsig, (size_t)2 * n * sizeof(double2)))) return rc;
   double2* g = (double2*)ctx->pq.p;
   double2* xb = (double2*)ctx->pqx.p;
-  double2 *fr = xb + stc, *fprev = xb + 2 * stc, *gprev = xb + 3 * stc;
-  std::vector<double2*> dF(m), dG(m);
-  for (int i = 0; i < m; ++i) {
-    dF[i] = xb + (size_t)(4 + i) * stc;
-    dG[i] = xb + (size_t)(4 + m + i) * stc;
-  }
   auto cls = [&](double2* base, int r, int c) {
     size_t off = (size_t)r * chc;
     for (int u = 0; u < c; ++u) off += cnt[u];
@@ -2094,10 +2277,7 @@ int kqft_parquet_solve(kqft_ctx* ctx, const kqft_grid* grid, double U, double De
     xf.push_back({xsig + 4 * n, g + 3 * chc + 4 * n});
     counts.push_back(1);
   }
-  double alpha = po.alpha, prev_res = 0.0;
-  int ncol = 0, head = 0, it = 0;
-  bool have_prev = false;
-  for (; it < po.max_iterations;) {
+  auto eval = [&]() -> int {
     launch_sigma_split(n, xsig, sigR, sigK, s);
     if (aam) {  // the state's Hartree term sets the level
       double2 hv;
@@ -2112,67 +2292,10 @@ int kqft_parquet_solve(kqft_ctx* ctx, const kqft_grid* grid, double U, double De
       HIP_TRY(hipStreamSynchronize(s));
     }
     if ((rc = parquet_core(ctx, V, Gs, *q_bubble, *q_loop, *opts, F, (double*)(g + 3 * chc), s, forms))) return rc;
-    double res = 0.0;
-    if ((rc = rel_change(ctx, xf, counts, s, &res))) return rc;
-    {  // f = g - x
-      const double2* k[2] = {g, xb};
-      const double c[2] = {1.0, -1.0};
-      lincomb_n(fr, nullptr, 2, k, c, stc, s);
-    }
-    if (po.reduce_alpha && it > 0 && res > prev_res) {
-      alpha = std::max(0.5 * alpha, po.alpha_min);
-      ncol = 0;
-    } else if (m > 0 && have_prev) {  // newest columns dF = f - f_prev, dG = g - g_prev
-      const int slot = head % m;
-      const double2* k[2] = {fr, fprev};
-      const double c[2] = {1.0, -1.0};
-      lincomb_n(dF[slot], nullptr, 2, k, c, stc, s);
-      const double2* kg[2] = {g, gprev};
-      lincomb_n(dG[slot], nullptr, 2, kg, c, stc, s);
-      ++head;
-      ncol = std::min(ncol + 1, m);
-    }
-    if (m > 0) {
-      HIP_TRY(hipMemcpyAsync(fprev, fr, stc * sizeof(double2), hipMemcpyDeviceToDevice, s));
-      HIP_TRY(hipMemcpyAsync(gprev, g, stc * sizeof(double2), hipMemcpyDeviceToDevice, s));
-      have_prev = true;
-    }
-    // x <- x + alpha f - sum_i gamma_i (dG_i - (1 - alpha) dF_i)
-    std::vector<const double2*> ks{fr};
-    std::vector<double> cs{alpha};
-    if (ncol > 0) {
-      std::vector<int> cols;
-      for (int i = 0; i < ncol; ++i) cols.push_back((head - ncol + i) % m);  // oldest first
-      std::vector<std::pair<const double2*, const double2*>> ab;
-      for (int i = 0; i < ncol; ++i)
-        for (int j = 0; j <= i; ++j) ab.push_back({dF[cols[i]], dF[cols[j]]});
-      for (int i = 0; i < ncol; ++i) ab.push_back({dF[cols[i]], fr});
-      std::vector<double> d;
-      if ((rc = dots(ctx, ab, stc, s, d))) return rc;
-      std::vector<double> A((size_t)ncol * ncol), b(ncol), gam;
-      size_t q = 0;
-      for (int i = 0; i < ncol; ++i)
-        for (int j = 0; j <= i; ++j, ++q) A[(size_t)i * ncol + j] = A[(size_t)j * ncol + i] = d[q];
-      double dmax = 0.0;
-      for (int i = 0; i < ncol; ++i) {
-        b[i] = d[q + i];
-        dmax = std::max(dmax, A[(size_t)i * ncol + i]);
-      }
-      for (int i = 0; i < ncol; ++i) A[(size_t)i * ncol + i] += 1e-14 * dmax;
-      if (!solve_small(A, b, ncol, gam)) return fail(KQFT_ENOCONV, "singular Anderson system");
-      for (int i = 0; i < ncol; ++i) {
-        ks.push_back(dG[cols[i]]);
-        cs.push_back(-gam[i]);
-        ks.push_back(dF[cols[i]]);
-        cs.push_back(gam[i] * (1.0 - alpha));
-      }
-    }
-    lincomb_n(xb, xb, (int)ks.size(), ks.data(), cs.data(), stc, s);
-    if (residuals) residuals[it] = res;
-    prev_res = res;
-    ++it;
-    if (res < po.tol) break;
-  }
+    return KQFT_OK;
+  };
+  auto residual = [&](double* res) { return rel_change(ctx, xf, counts, s, res); };
+  if ((rc = fixed_point_core(ctx, stc, xb, g, po, eval, residual, residuals, iterations, s))) return rc;
   // the state back into the caller's arrays
   for (int r = 0; r < 3; ++r) {
     double* dst[4] = {gamma[r].K1, gamma[r].K2, gamma[r].K2p, gamma[r].K3};
@@ -2187,7 +2310,6 @@ int kqft_parquet_solve(kqft_ctx* ctx, const kqft_grid* grid, double U, double De
     sH = hv.x;
   }
   if (sigma_H) *sigma_H = sH;
-  *iterations = it;
   HIP_TRY(hipGetLastError());
   return KQFT_OK;
 }

@@ -128,6 +128,9 @@ def lib():
                                                C.c_int, P(KqftChout), C.c_void_p]
         _lib.kqft_sde_matsubara.argtypes = [C.c_void_p, P(KqftMVertex), P(KqftMProp), C.c_int, C.c_int, C.c_void_p,
                                             C.c_void_p]
+        _lib.kqft_parquet_solve_matsubara.argtypes = [C.c_void_p, P(KqftMGrid), C.c_double, C.c_double, C.c_int,
+                                                      C.c_int, P(KqftParquetOpts), P(KqftChout), C.c_void_p,
+                                                      P(C.c_double), P(C.c_int), C.c_void_p]
         _lib.kqft_loop.argtypes = [C.c_void_p, P(KqftVertex), P(KqftPropagator), C.c_int, P(KqftQuad), C.c_void_p,
                                    C.c_void_p]
         _lib.kqft_mfrg_flow.argtypes = [C.c_void_p, P(KqftGrid), C.c_double, C.c_double, C.c_double, C.c_double,
@@ -428,6 +431,27 @@ def sde_matsubara(gamma: MVertex, Delta: float, Nq: int, Nl: int, sigma: Optiona
     _check(lib().kqft_sde_matsubara(ctx(), C.byref(vc), C.byref(gp), Nq, Nl, C.c_void_p(out.data_ptr()),
                                     _stream(stream)))
     return out
+
+
+def parquet_solve_matsubara(grid: MGrid, U: float, Delta: float, Nq: int, Nl: int, alpha: float = 0.5,
+                            max_iterations: int = 20, tol: float = 0.0, depth: int = 0, reduce_alpha: bool = False,
+                            alpha_min: float = 0.01, stream=None):
+    """Matsubara parquet solver from the PT2 state; returns (channels, Sigma [2N], residuals)."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    outs = [Channel(1.0, *[torch.zeros(grid.shape(c), dtype=torch.complex128, device=dev) for c in CLASSES])
+            for _ in range(3)]
+    sigma = torch.zeros(2 * grid.N, dtype=torch.complex128, device=dev)
+    res = (C.c_double * max_iterations)()
+    its = C.c_int(0)
+    D = (KqftChout * 3)(*[KqftChout(*[_ptr(getattr(o, c), grid.shape(c), f"out.{c}") for c in CLASSES])
+                          for o in outs])
+    po = KqftParquetOpts(alpha, max_iterations, tol, depth, int(reduce_alpha), alpha_min, 0, 0.0,
+                         KqftQuad(1, QUAD_TAN_INFINITE, 0.0, 1.0), 1e-12, 1)
+    gc = grid.c()
+    _check(lib().kqft_parquet_solve_matsubara(ctx(), C.byref(gc), C.c_double(U), C.c_double(Delta), Nq, Nl,
+                                              C.byref(po), D, C.c_void_p(sigma.data_ptr()), res, C.byref(its),
+                                              _stream(stream)))
+    return outs, sigma, [res[i] for i in range(its.value)]
 
 
 def mloop_step(gammas: Sequence[Vertex], Gs: Sequence[Propagator], qs: Sequence[Quad], nloops: int,

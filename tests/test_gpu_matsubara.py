@@ -125,3 +125,24 @@ def test_matsubara_sde_matches_oracle():
     assert _rel(out, ref) < 1e-12
     with pytest.raises(K.KqftError):
         K.sde_matsubara(kv, D, Nq, 0)
+
+
+@pytest.mark.parametrize("alpha,depth,reduce", [(0.5, 0, False), (0.5, 3, False), (1.0, 2, True)])
+def test_matsubara_parquet_solver_matches_oracle(alpha, depth, reduce):
+    """The Matsubara parquet solver (PT2 start; linear mixing, Anderson acceleration, alpha
+    reduction): residuals and final state as the oracle's (M = 12, N = 4, Nq = 12, Nl = 8)."""
+    K = _K()
+    M, N, Nq, Nl, U, iters = 12, 4, 12, 8, 1.0, 6
+    och, osig, ores = MF.parquet_solve(MF.MGrid(M, N, T), U, D, Nq, Nl, alpha=alpha, iterations=iters, depth=depth,
+                                       reduce_alpha=reduce)
+    kch, ksig, kres = K.parquet_solve_matsubara(K.MGrid(M, N, T), U, D, Nq, Nl, alpha=alpha, max_iterations=iters,
+                                                depth=depth, reduce_alpha=reduce)
+    torch.cuda.synchronize()
+    print(f"alpha={alpha} depth={depth}: residuals {['%.2e' % x for x in kres]}", flush=True)
+    assert len(kres) == iters and np.allclose(kres, ores, rtol=1e-9, atol=0)
+    for r in range(3):
+        for x in CL:
+            assert _rel(getattr(kch[r], x).cpu().numpy(), getattr(och[r], x)) < 1e-10, (r, x)
+    assert _rel(ksig.cpu().numpy(), osig) < 1e-10
+    with pytest.raises(K.KqftError):
+        K.parquet_solve_matsubara(K.MGrid(M, N, T), U, D, Nq, Nl, alpha=0.0)
