@@ -163,7 +163,7 @@ def test_autograd_chain_seed_bubble_sde():
 
     val, dsu = oracle_sigma(1.0, 0.0)
     _, dsd = oracle_sigma(0.0, 1.0)
-    assert abs(float(target) - (val[n // 2, 1].imag + 0.3 * val[:, 1].real.sum())) < 1e-12
+    assert abs(float(target.detach()) - (val[n // 2, 1].imag + 0.3 * val[:, 1].real.sum())) < 1e-12
     ref_u = dsu[n // 2, 1].imag + 0.3 * dsu[:, 1].real.sum()
     ref_d = dsd[n // 2, 1].imag + 0.3 * dsd[:, 1].real.sum()
     assert abs(float(gU) - ref_u) < 1e-10 * max(1.0, abs(ref_u))
