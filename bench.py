@@ -12,7 +12,7 @@ resident in HBM.  Algorithmic work per step:
 `value` is F / (ms per step) of the split-FP32 path when its error against the FP64
 path is <= 1e-6, otherwise of the FP64 path.
 
-Prints one JSON line.  --gpus above 1 is rejected: this build runs on one GPU.
+Prints one JSON line.  --gpus above 1 is rejected: the library runs on one GPU.
 """
 import argparse
 import json
@@ -81,7 +81,7 @@ def main():
                     help="only run a device-to-device copy of 1 GiB three times (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the bubble shards over transfer frequencies "
+        print("bench.py: the library runs on one GPU only (the bubble shards over transfer frequencies "
               "across GPUs by design, but no multi-GPU path is built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
