@@ -35,3 +35,17 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     import pytest
     with pytest.raises(RuntimeError):
         K.lib()
+
+
+def test_header_is_plain_c():
+    """include/kqft.h compiles as strict C99 (a C ABI: no C++ types in the signatures)."""
+    import subprocess
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "t.c")
+        with open(src, "w") as f:
+            f.write('#include "kqft.h"\nint main(void) { return 0; }\n')
+        res = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I",
+                              os.path.join(ROOT, "include"), "-c", src, "-o", os.path.join(d, "t.o")],
+                             capture_output=True, text=True)
+        assert res.returncode == 0, res.stderr
