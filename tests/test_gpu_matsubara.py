@@ -146,3 +146,20 @@ def test_matsubara_parquet_solver_matches_oracle(alpha, depth, reduce):
     assert _rel(ksig.cpu().numpy(), osig) < 1e-10
     with pytest.raises(K.KqftError):
         K.parquet_solve_matsubara(K.MGrid(M, N, T), U, D, Nq, Nl, alpha=0.0)
+
+
+def test_matsubara_parquet_solver_time():
+    """M = 96, N = 48, Nq = 96, Nl = 48 (every SDE term inside the boxes), U = 1, eight
+    iterations with Anderson depth 3: the time per iteration (six Matsubara bubbles, the SDE
+    bubble and loop, the mixing) and a contracting residual."""
+    K = _K()
+    M, N, Nq, Nl, iters = 96, 48, 96, 48, 8
+    K.parquet_solve_matsubara(K.MGrid(M, N, T), 1.0, D, Nq, Nl, max_iterations=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, res = K.parquet_solve_matsubara(K.MGrid(M, N, T), 1.0, D, Nq, Nl, alpha=0.5, max_iterations=iters, depth=3)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / iters
+    print(f"Matsubara parquet M={M} N={N} Nq={Nq}: {dt * 1e3:.1f} ms per iteration, residuals "
+          f"{['%.2e' % x for x in res]}", flush=True)
+    assert res[-1] < 0.1 * res[1]
