@@ -149,22 +149,41 @@ def vertex_legs(V: MVertex, spins, legs):
     return XY[0] * ((s1p == s1) & (s2p == s2)) + XY[1] * ((s1p == s2) & (s2p == s1))
 
 
+def _on_box(arr: Optional[np.ndarray], n: np.ndarray) -> np.ndarray:
+    """arr[n + Ns] on n in [-Ns, Ns) (len(arr) = 2 Ns), zero elsewhere or when absent."""
+    if arr is None:
+        return np.zeros(n.shape, dtype=np.complex128)
+    Ns = len(arr) // 2
+    ok = (n >= -Ns) & (n < Ns)
+    return np.where(ok, arr[np.where(ok, n + Ns, 0)], 0.0)
+
+
 @dataclass
 class MProp:
-    """G(i nu_n) = 1/(i nu_n + i Delta sgn(nu_n) - Sigma(n)), Sigma on n in [-Ns, Ns) or none."""
+    """G(i nu_n) = 1/(i nu_n + i Delta sgn(nu_n) - Sigma(n)), Sigma on n in [-Ns, Ns) or none.
+    The flow parameter of the Matsubara flow is Delta (hybridization flow): the single-scale
+    propagator is S = dG/dDelta at fixed Sigma = -i sgn(nu) G^2, plus G Sigma_dot G with the
+    optional dsigma (Katanin substitution)."""
     Delta: float
     T: float
     sigma: Optional[np.ndarray] = None
+    dsigma: Optional[np.ndarray] = None
 
     def __call__(self, n):
         n = np.asarray(n)
         v = nu(n, self.T)
-        s = np.zeros(n.shape, dtype=np.complex128)
-        if self.sigma is not None:
-            Ns = len(self.sigma) // 2
-            ok = (n >= -Ns) & (n < Ns)
-            s = np.where(ok, self.sigma[np.where(ok, n + Ns, 0)], 0.0)
-        return 1.0 / (1j * v + 1j * self.Delta * np.sign(v) - s)
+        return 1.0 / (1j * v + 1j * self.Delta * np.sign(v) - _on_box(self.sigma, n))
+
+    def line(self, n, kind: int = 0):
+        """kind 0: G; 1: S (+ G Sigma_dot G with dsigma); 2: G Sigma_dot G."""
+        n = np.asarray(n)
+        g = self(n)
+        if kind == 0:
+            return g
+        gsg = g * _on_box(self.dsigma, n) * g
+        if kind == 2:
+            return gsg
+        return -1j * np.sign(nu(n, self.T)) * g * g + gsg
 
 
 def window(r: int, m: int, Nq: int) -> np.ndarray:
@@ -176,11 +195,12 @@ def window(r: int, m: int, Nq: int) -> np.ndarray:
     return np.arange(lo, hi + 1)
 
 
-def pi_r(r: int, P: MProp, m: int, k: np.ndarray) -> np.ndarray:
-    """T Pi_r(m, n'') for the window k."""
-    if r == 1:
-        return P.T * P(k) * P(m - k - 1)
-    return P.T * P(k + m) * P(k)
+def pi_r(r: int, P: MProp, m: int, k: np.ndarray, kind: int = 0) -> np.ndarray:
+    """T Pi_r(m, n'') for the window k; kind 1: the differentiated bubble S G + G S."""
+    k1, k2 = (k, m - k - 1) if r == 1 else (k + m, k)
+    if kind == 1:
+        return P.T * (P.line(k1, 1) * P(k2) + P(k1) * P.line(k2, 1))
+    return P.T * P(k1) * P(k2)
 
 
 def _spin_sum(r: int, LX, LY, pi, RX, RY):
@@ -194,8 +214,8 @@ def _spin_sum(r: int, LX, LY, pi, RX, RY):
     return -(mm(LX, RX + RY) + mm(LX + LY, RX)), -mm(LY, RY)
 
 
-def bubble(r: int, L: MVertex, R: MVertex, P: MProp, Nq: int) -> MChannel:
-    """B_r(L, R) as the four asymptotic classes of channel r."""
+def bubble(r: int, L: MVertex, R: MVertex, P: MProp, Nq: int, kind: int = 0) -> MChannel:
+    """B_r(L, R) as the four asymptotic classes of channel r (kind 1: with Pi_dot)."""
     g = L.grid
     sh = g.shapes()
     out = {k: np.zeros(s, dtype=np.complex128) for k, s in sh.items()}
@@ -203,7 +223,7 @@ def bubble(r: int, L: MVertex, R: MVertex, P: MProp, Nq: int) -> MChannel:
     own_L, own_R = L.ch[r], R.ch[r]
     for im, m in enumerate(range(-g.M, g.M + 1)):
         k = window(r, m, Nq)
-        pi = pi_r(r, P, m, k)
+        pi = pi_r(r, P, m, k, kind)
         # left: rows n (the box), columns n''; L^inf(m, n'') = Gamma_0 + K1 + K2' of the own channel
         full_L = vertex_eval(L, r, m, nbox[:, None], k[None, :])
         inf_L = channel_value(own_L, g, m, 0, k, ("K1", "K2p"))
@@ -227,14 +247,14 @@ def bubble(r: int, L: MVertex, R: MVertex, P: MProp, Nq: int) -> MChannel:
     return MChannel(1.0, out["K1"], out["K2"], out["K2p"], out["K3"])
 
 
-def loop(V: MVertex, P: MProp, Nl: int) -> np.ndarray:
-    """L(Gamma, G)(n) for n in [-N, N): T sum_{n'} [2X + Y](n, n' | n, n') G(n') over
-    |2n' + 1| <= 2 Nl - 1."""
+def loop(V: MVertex, P: MProp, Nl: int, kind: int = 0) -> np.ndarray:
+    """L(Gamma, X)(n) for n in [-N, N): T sum_{n'} [2X + Y](n, n' | n, n') X(n') over
+    |2n' + 1| <= 2 Nl - 1, X = G, S or G Sigma_dot G (kind 0, 1, 2)."""
     g = V.grid
     n = np.arange(-g.N, g.N)
     k = np.arange(-Nl, Nl)
     XY = vertex_eval(V, 0, *params_of(0, n[:, None], k[None, :], n[:, None], k[None, :]))
-    return P.T * ((2.0 * XY[0] + XY[1]) * P(k)[None, :]).sum(axis=1)
+    return P.T * ((2.0 * XY[0] + XY[1]) * P.line(k, kind)[None, :]).sum(axis=1)
 
 
 def bare(grid: MGrid, U: float) -> MVertex:
@@ -327,3 +347,86 @@ def parquet_solve(grid: MGrid, U: float, Delta: float, Nq: int, Nl: int, alpha: 
                                   reduce_alpha, alpha_min)
     ch, sg = state_unpack(grid, x)
     return ch, np.array(sg), res
+
+
+# ------------------------------------------------------------------ mfRG flow (hybridization flow)
+def mloop(V: MVertex, P: MProp, Nq: int, nloops: int, centres: Optional[list] = None) -> list:
+    """Multiloop insertions (Eqs. 1l-3l) in the Matsubara formalism, as in the Keldysh oracle:
+    l = 1: B_r(Gamma, Gamma; Pi_dot); l = 2: B_r(gdot_rbar^(1), Gamma) + B_r(Gamma, gdot_rbar^(1));
+    l >= 3: + B_r(Gamma, B_r(gdot_rbar^(l-2), Gamma)).  Returns out[l-1][r]; centre terms are
+    appended to `centres` as centres[l-3][r] when it is given."""
+    g = V.grid
+    out = []
+    for ell in range(1, nloops + 1):
+        this = []
+        for r in range(3):
+            if ell == 1:
+                this.append(bubble(r, V, V, P, Nq, 1))
+                continue
+            prev = out[ell - 2]
+            rbar = combine(g, 0.0, [(rr, prev[rr], 1.0) for rr in range(3) if rr != r])
+            Lt = bubble(r, rbar, V, P, Nq)
+            Rt = bubble(r, V, rbar, P, Nq)
+            tot = {k: getattr(Lt, k) + getattr(Rt, k) for k in CLASSES}
+            if ell >= 3:
+                rbar2 = combine(g, 0.0, [(rr, out[ell - 3][rr], 1.0) for rr in range(3) if rr != r])
+                inner = bubble(r, rbar2, V, P, Nq)
+                Ct = bubble(r, V, combine(g, 0.0, [(r, inner, 1.0)]), P, Nq)
+                tot = {k: tot[k] + getattr(Ct, k) for k in tot}
+                if centres is not None:
+                    if r == 0:
+                        centres.append([])
+                    centres[-1].append(Ct)
+            this.append(MChannel(1.0, *[tot[k] for k in CLASSES]))
+        out.append(this)
+    return out
+
+
+def mfrg_rhs(grid: MGrid, U: float, lam: float, nloops: int, Nq: int, Nl: int, chans, sigma,
+             katanin: bool = True, se_iterations: int = 0, se_atol: float = 1e-9, se_rtol: float = 1e-5):
+    """Right-hand side of the Matsubara flow in the hybridization Delta = lam (the Keldysh
+    oracle's mfrg_rhs with the Matsubara bubble and loop): Sigma_dot^(1) = -L(Gamma, S),
+    Gamma_dot = sum_l gdot^(l) with the l = 1 bubble along S (+ G Sigma_dot G with katanin), and
+    with se_iterations (nloops >= 3) the corrections Sigma_dot_tbar = -L(gdot_{a,C} + gdot_{p,C},
+    G), Sigma_dot_t = -L(Gamma, G Sigma_dot_tbar G) iterated.  Returns (Gamma_dot, Sigma_dot)."""
+    V = MVertex(grid, U, chans)
+    P = MProp(lam, grid.T, np.asarray(sigma))
+    sd1 = -loop(V, P, Nl, 1)
+    sd = sd1
+    it = 0
+    while True:
+        Pk = MProp(lam, grid.T, np.asarray(sigma), sd if katanin else None)
+        cen = []
+        ins = mloop(V, Pk, Nq, nloops, centres=cen)
+        if se_iterations <= 0 or nloops < 3:
+            break
+        ca = MChannel(1.0, *[sum(getattr(cen[l][0], c) for l in range(len(cen))) for c in CLASSES])
+        cp = MChannel(1.0, *[sum(getattr(cen[l][1], c) for l in range(len(cen))) for c in CLASSES])
+        tbar = -loop(MVertex(grid, 0.0, [ca, cp, MChannel(0.0)]), P, Nl, 0)
+        st = -loop(V, MProp(lam, grid.T, np.asarray(sigma), tbar), Nl, 2)
+        new = sd1 + tbar + st
+        change = float(np.abs(new - sd).max())
+        it += 1
+        sd = new
+        if change <= se_atol + se_rtol * float(np.abs(new).max()) or it >= se_iterations:
+            break
+    gdot = [MChannel(1.0, *[sum(getattr(ins[l][r], c) for l in range(nloops)) for c in CLASSES]) for r in range(3)]
+    return gdot, sd
+
+
+def mfrg_flow(grid: MGrid, U: float, lam_i: float, lam_f: float, steps: int, nloops: int, Nq: int, Nl: int,
+              chans, sigma, katanin: bool = True, se_iterations: int = 0):
+    """Classical RK4 in `steps` equal steps of t with Delta = Lambda(t) = 5 t|t| / sqrt(1 - t^2)
+    (the Keldysh Delta-flow's parametrisation) from lam_i to lam_f.  Returns (chans, sigma)."""
+    from .oracle import REG_DELTA, flow_dlambda_dt, flow_lambda, flow_t, ode_solve
+
+    def f(t, vec):
+        ch, sg = state_unpack(grid, vec)
+        gd, sd = mfrg_rhs(grid, U, flow_lambda(REG_DELTA, t), nloops, Nq, Nl, ch, np.array(sg), katanin,
+                          se_iterations)
+        return flow_dlambda_dt(REG_DELTA, t) * state_pack(grid, gd, sd)
+
+    y, _, _ = ode_solve(f, state_pack(grid, chans, sigma), flow_t(REG_DELTA, lam_i), flow_t(REG_DELTA, lam_f),
+                        steps)
+    ch, sg = state_unpack(grid, y)
+    return ch, np.array(sg)

@@ -179,3 +179,48 @@ def test_matsubara_parquet_solution_third_order_expansion():
     (g1, s1), (g2, s2_) = errs
     assert g1 < 0.2 and s1 < 0.2
     assert 0.3 < g2 / g1 < 0.7 and 0.3 < s2_ / s1 < 0.7
+
+
+# ---------------------------------------------------------------- Matsubara flow
+def test_matsubara_single_scale_lines_are_derivatives():
+    """S = dG/dDelta at fixed Sigma and G Sigma_dot G = dG/dh along Sigma + h Sigma_dot (central
+    differences); the Pi_dot bubble and the loop with S are the Delta-derivatives of the bubble
+    and of the loop at fixed vertex and Sigma."""
+    sig = 0.1 * np.exp(1j * np.linspace(0, 2, 12)) - 0.05j
+    dsig = 0.2 * np.exp(-1j * np.linspace(0, 1, 12))
+    n = np.arange(-9, 9)
+    h = 1e-6
+    P = MF.MProp(1.3, T, sig)
+    fd = (MF.MProp(1.3 + h, T, sig)(n) - MF.MProp(1.3 - h, T, sig)(n)) / (2 * h)
+    assert np.abs(P.line(n, 1) - fd).max() < 1e-8 * np.abs(fd).max()
+    fd2 = (MF.MProp(1.3, T, sig + h * dsig)(n) - MF.MProp(1.3, T, sig - h * dsig)(n)) / (2 * h)
+    assert np.abs(MF.MProp(1.3, T, sig, dsig).line(n, 2) - fd2).max() < 1e-8 * np.abs(fd2).max()
+    g = MF.MGrid(3, 3, T)
+    V = _random_vertex(g, 5)
+    for r in range(3):
+        b = MF.bubble(r, V, V, P, 6, 1)
+        bp = MF.bubble(r, V, V, MF.MProp(1.3 + h, T, sig), 6)
+        bm = MF.bubble(r, V, V, MF.MProp(1.3 - h, T, sig), 6)
+        for c in MF.CLASSES:
+            d = (getattr(bp, c) - getattr(bm, c)) / (2 * h)
+            assert np.abs(getattr(b, c) - d).max() < 1e-7 * np.abs(d).max(), (r, c)
+    lp = MF.loop(V, MF.MProp(1.3 + h, T, sig), 7)
+    lm = MF.loop(V, MF.MProp(1.3 - h, T, sig), 7)
+    d = (lp - lm) / (2 * h)
+    assert np.abs(MF.loop(V, P, 7, 1) - d).max() < 1e-7 * np.abs(d).max()
+
+
+def test_matsubara_flow_of_pt2_reaches_pt2_to_second_order():
+    """The one-loop flow of the PT2 state from Delta = 2 to 1 reproduces the PT2 vertex at
+    Delta = 1 up to O(U^3) and the Runge-Kutta error: the relative deviation falls linearly
+    with U."""
+    g = MF.MGrid(12, 4, T)
+    Nq, Nl = 12, 8
+    devs = []
+    for u in (0.1, 0.05):
+        chans, sig = MF.pt2_state(g, u, 2.0, Nq, Nl)
+        ch, _ = MF.mfrg_flow(g, u, 2.0, 1.0, 4, 1, Nq, Nl, chans, sig)
+        ref, _ = MF.pt2_state(g, u, 1.0, Nq, Nl)
+        devs.append(max(np.abs(ch[r].K1 - ref[r].K1).max() / np.abs(ref[r].K1).max() for r in range(3)))
+    assert devs[0] < 0.05
+    assert 0.3 < devs[1] / devs[0] < 0.7
