@@ -268,16 +268,20 @@ typedef struct {
 } kqft_mvertex;
 
 /* G(i nu_n) = 1/(i nu_n + i Delta sgn(nu_n) - Sigma(n)) (level 0: particle-hole symmetric model
-   with U/2 absorbed); sigma: device complex on n in [-sigma_N, sigma_N) or NULL */
+   with U/2 absorbed); sigma: device complex on n in [-sigma_N, sigma_N) or NULL.  The flow
+   parameter of the Matsubara flow is Delta: S = dG/dDelta at fixed Sigma = -i sgn(nu) G^2,
+   plus G Sigma_dot G with dsigma (device complex on the same box, or NULL). */
 typedef struct {
   double Delta;
   const double* sigma;
   int sigma_N;
+  const double* dsigma;
 } kqft_mprop;
 
 /*
  * kqft_bubble_matsubara -- B_r(left, right) in the Matsubara formalism:
  *   B_r(m; n, n') = pref_r T sum_{n''} left(m; n, n'') Pi_r(m, n'') right(m; n'', n')
+ * (pi_kind KQFT_PI_GG: Pi = G G; KQFT_PI_DOT: Pi_dot = S G + G S with S of kqft_mprop)
  * with the spin sums of the real-frequency bubble (the same two combinations per channel,
  * prefactors +1, 1/2, -1), Pi_a = Pi_t = G(n'' + m) G(n''), Pi_p = G(n'') G(m - n'' - 1), the
  * sum over the window |2n'' + 1 + s m| <= 2 Nq - 1 (s = +1 for a and t, -1 for p; symmetric
@@ -291,7 +295,34 @@ typedef struct {
  * N < 1, Nq < 1 or sizes whose panels exceed 2^31 entries.
  */
 int kqft_bubble_matsubara(kqft_ctx* ctx, int channel, const kqft_mvertex* left, const kqft_mvertex* right,
-                          const kqft_mprop* G, int Nq, const kqft_chout* out, void* stream);
+                          const kqft_mprop* G, int pi_kind, int Nq, const kqft_chout* out, void* stream);
+
+/*
+ * kqft_loop_matsubara -- the loop of a full Matsubara vertex (bare part, every channel at its own
+ * parameters): L(Gamma, X)(n) = T sum_{n'} [2X + Y](legs n, n' | n, n') X(n'), |2n' + 1| <=
+ * 2 Nl - 1, X = G, S (+ G Sigma_dot G with dsigma) or G Sigma_dot G (KQFT_LINE_G, _S, _GSG).
+ * out: device [2N] complex.  FP64.  KQFT_EINVAL / KQFT_ESHAPE as kqft_bubble_matsubara.
+ */
+int kqft_loop_matsubara(kqft_ctx* ctx, const kqft_mvertex* gamma, const kqft_mprop* G, int kind, int Nl,
+                        double* out, void* stream);
+
+/*
+ * kqft_mfrg_flow_matsubara -- the mfRG flow (Sec. "mfRG") in the Matsubara formalism with the
+ * hybridization as flow parameter (Delta from Lambda_i to Lambda_f; the ODE in t with
+ * Delta = 5 t|t| / sqrt(1 - t^2), classical RK4 in `steps` equal steps):
+ *   Sigma_dot^(1) = -L(Gamma, S)                         (kqft_loop_matsubara, window Nl),
+ *   Gamma_dot     = sum_{l <= nloops} gdot^(l): l = 1 B_r(Gamma, Gamma; Pi_dot) along S
+ *                   (+ G Sigma_dot G with katanin), l = 2 B_r(gdot_rbar, Gamma) + B_r(Gamma,
+ *                   gdot_rbar), l >= 3 also B_r(Gamma, B_r(gdot_rbar^(l-2), Gamma))   (window Nq),
+ * and with se_iterations > 0 and nloops >= 3 the corrections Sigma_dot_tbar = -L(sum of the
+ * a and p centre terms, G), Sigma_dot_t = -L(Gamma, G Sigma_dot_tbar G), Sigma_dot = Sigma_dot^(1)
+ * + Sigma_dot_tbar + Sigma_dot_t, iterated until max|change| <= abs + rel max|Sigma_dot| or
+ * se_iterations times.  State in/out: gamma[3] (device classes on grid) and sigma (device [2N]).
+ * FP64.  Synchronises `stream` once per correction iteration.
+ */
+int kqft_mfrg_flow_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, double Lambda_i, double Lambda_f,
+                             int steps, int nloops, int Nq, int Nl, int katanin, int se_iterations, double se_tol_abs,
+                             double se_tol_rel, const kqft_chout* gamma, double* sigma, void* stream);
 
 /*
  * kqft_sde_matsubara -- the Schwinger-Dyson self-energy in the Matsubara formalism (a-channel

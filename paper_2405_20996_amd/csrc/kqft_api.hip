@@ -44,7 +44,8 @@ struct kqft_ctx {
   // consecutive transfer-frequency batches overlap, ordered by events
   hipStream_t sg = nullptr, sm = nullptr;
   rocblas_handle blas = nullptr;
-  DevBuf adjw, dkf[2][3], phigrad, pq, pqsig, pqred, vtab[3], flow, flowml, ctmp, flowred, pqx, adapt, sdep, mf, mftmp;
+  DevBuf adjw, dkf[2][3], phigrad, pq, pqsig, pqred, vtab[3], flow, flowml, ctmp, flowred, pqx, adapt, sdep, mf, mftmp,
+      mfflow;
   std::vector<hipEvent_t> events;
   size_t next_event = 0;
   bool prof = false;
@@ -971,7 +972,8 @@ int kqft_ctx_destroy(kqft_ctx* ctx) {
       if (b.p) (void)hipFree(b.p);
   if (ctx->adjw.p) (void)hipFree(ctx->adjw.p);
   for (DevBuf* b : {&ctx->pq, &ctx->pqsig, &ctx->pqred, &ctx->vtab[0], &ctx->vtab[1], &ctx->vtab[2], &ctx->flow,
-                    &ctx->flowml, &ctx->ctmp, &ctx->flowred, &ctx->pqx, &ctx->adapt, &ctx->sdep, &ctx->mf, &ctx->mftmp})
+                    &ctx->flowml, &ctx->ctmp, &ctx->flowred, &ctx->pqx, &ctx->adapt, &ctx->sdep, &ctx->mf, &ctx->mftmp,
+                    &ctx->mfflow})
     if (b->p) (void)hipFree(b->p);
   if (ctx->phigrad.p) (void)hipFree(ctx->phigrad.p);
   if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
@@ -1291,18 +1293,63 @@ int kqft_chi(kqft_ctx* ctx, int channel, const kqft_vertex* gamma, const kqft_pr
   return KQFT_OK;
 }
 
+static int check_mprop(const kqft_mprop& G) {
+  if (!(G.Delta > 0)) return fail(KQFT_EINVAL, "Delta must be positive");
+  if (G.sigma_N < 0 || ((G.sigma || G.dsigma) && G.sigma_N == 0)) return fail(KQFT_ESHAPE, "invalid self-energy box");
+  return KQFT_OK;
+}
+
+static MGatherArgs mf_side(const kqft_mgrid& g, int channel, int kind, int Nq, const kqft_mvertex& v,
+                           const kqft_mprop& G) {
+  MGatherArgs a;
+  memset(&a, 0, sizeof a);
+  a.r = channel;
+  a.M = g.M;
+  a.N = g.N;
+  a.Nq = Nq;
+  a.kind = kind;
+  a.T = g.T;
+  a.Delta = G.Delta;
+  a.sigma = (const double2*)G.sigma;
+  a.dsigma = (const double2*)G.dsigma;
+  a.Ns = (G.sigma || G.dsigma) ? G.sigma_N : 0;
+  a.U = v.U;
+  for (int r = 0; r < 3; ++r)
+    a.ch[r] = MChan{v.ch[r].coef, {(const double2*)v.ch[r].K1, (const double2*)v.ch[r].K2,
+                                   (const double2*)v.ch[r].K2p, (const double2*)v.ch[r].K3}};
+  for (int u = 0; u < 4; ++u) a.mix[u] = kMix[channel][u];
+  return a;
+}
+
+int kqft_loop_matsubara(kqft_ctx* ctx, const kqft_mvertex* gamma, const kqft_mprop* G, int kind, int Nl,
+                        double* out, void* stream) {
+  int rc;
+  if (!ctx) return fail(KQFT_EINVAL, "ctx is NULL");
+  if (!gamma || !G || !out) return fail(KQFT_EINVAL, "vertex, propagator and out must be given");
+  if (kind < KQFT_LINE_G || kind > KQFT_LINE_GSG) return fail(KQFT_EINVAL, "kind must be a KQFT_LINE_* value");
+  if (kind == KQFT_LINE_GSG && !G->dsigma) return fail(KQFT_EINVAL, "the G Sigma_dot G line needs Sigma_dot");
+  if (gamma->grid.M < 0 || gamma->grid.N < 1 || Nl < 1) return fail(KQFT_ESHAPE, "need M >= 0, N >= 1, Nl >= 1");
+  if (!(gamma->grid.T > 0)) return fail(KQFT_EINVAL, "T must be positive");
+  if ((rc = check_mprop(*G))) return rc;
+  HIP_TRY(hipSetDevice(ctx->device));
+  launch_mf_vloop(mf_side(gamma->grid, KQFT_CH_A, 0, 1, *gamma, *G), kind, Nl, (double2*)out, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return KQFT_OK;
+}
+
 int kqft_bubble_matsubara(kqft_ctx* ctx, int channel, const kqft_mvertex* left, const kqft_mvertex* right,
-                          const kqft_mprop* G, int Nq, const kqft_chout* out, void* stream) {
+                          const kqft_mprop* G, int pi_kind, int Nq, const kqft_chout* out, void* stream) {
   int rc;
   if (!ctx) return fail(KQFT_EINVAL, "ctx is NULL");
   if (!left || !right || !G || !out) return fail(KQFT_EINVAL, "vertices, propagator and outputs must be given");
   if (channel < KQFT_CH_A || channel > KQFT_CH_T) return fail(KQFT_EINVAL, "channel must be 0, 1 or 2");
+  if (pi_kind != KQFT_PI_GG && pi_kind != KQFT_PI_DOT) return fail(KQFT_EINVAL, "unknown bubble kind");
   const kqft_mgrid g = left->grid;
   if (g.M < 0 || g.N < 1 || Nq < 1) return fail(KQFT_ESHAPE, "need M >= 0, N >= 1, Nq >= 1");
   if (right->grid.M != g.M || right->grid.N != g.N || right->grid.T != g.T)
     return fail(KQFT_ESHAPE, "left and right must share the Matsubara grid");
-  if (!(g.T > 0) || !(G->Delta > 0)) return fail(KQFT_EINVAL, "T and Delta must be positive");
-  if (G->sigma_N < 0 || (G->sigma && G->sigma_N == 0)) return fail(KQFT_ESHAPE, "invalid self-energy box");
+  if (!(g.T > 0)) return fail(KQFT_EINVAL, "T must be positive");
+  if ((rc = check_mprop(*G))) return rc;
   if (!out->K1 || !out->K2 || !out->K2p || !out->K3) return fail(KQFT_EINVAL, "all four output classes are required");
   const long R = 2L * g.N + 1, Kw = 2L * Nq, nbos = 2L * g.M + 1;
   if (R * Kw > (1L << 30) || R * R > (1L << 30)) return fail(KQFT_ESHAPE, "Matsubara panels too large");
@@ -1320,23 +1367,9 @@ int kqft_bubble_matsubara(kqft_ctx* ctx, int channel, const kqft_mvertex* left, 
   double2* B[2] = {base + 2 * (size_t)nb * R * Kw, base + 3 * (size_t)nb * R * Kw};
   double2* Cm[2] = {base + 4 * (size_t)nb * R * Kw, base + 4 * (size_t)nb * R * Kw + (size_t)nb * R * R};
   auto side = [&](const kqft_mvertex& v, double2* const* P, int m0, int cnt) {
-    MGatherArgs a;
-    memset(&a, 0, sizeof a);
-    a.r = channel;
-    a.M = g.M;
-    a.N = g.N;
-    a.Nq = Nq;
+    MGatherArgs a = mf_side(g, channel, pi_kind, Nq, v, *G);
     a.m0 = m0;
     a.nb = cnt;
-    a.T = g.T;
-    a.Delta = G->Delta;
-    a.sigma = (const double2*)G->sigma;
-    a.Ns = G->sigma ? G->sigma_N : 0;
-    a.U = v.U;
-    for (int r = 0; r < 3; ++r)
-      a.ch[r] = MChan{v.ch[r].coef, {(const double2*)v.ch[r].K1, (const double2*)v.ch[r].K2,
-                                     (const double2*)v.ch[r].K2p, (const double2*)v.ch[r].K3}};
-    for (int u = 0; u < 4; ++u) a.mix[u] = kMix[channel][u];
     a.P[0] = P[0];
     a.P[1] = P[1];
     return a;
@@ -1402,7 +1435,7 @@ int kqft_sde_matsubara(kqft_ctx* ctx, const kqft_mvertex* gamma, const kqft_mpro
   memset(&bare, 0, sizeof bare);
   bare.grid = g;
   bare.U = gamma->U;
-  if ((rc = kqft_bubble_matsubara(ctx, KQFT_CH_A, &bare, gamma, G, Nq, &po, stream))) return rc;
+  if ((rc = kqft_bubble_matsubara(ctx, KQFT_CH_A, &bare, gamma, G, KQFT_PI_GG, Nq, &po, stream))) return rc;
   MLoopArgs la;
   memset(&la, 0, sizeof la);
   la.M = g.M;
@@ -1476,10 +1509,10 @@ int kqft_parquet_solve_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U
   memset(&bare, 0, sizeof bare);
   bare.grid = g;
   bare.U = U;
-  const kqft_mprop G0{Delta, nullptr, 0};
+  const kqft_mprop G0{Delta, nullptr, 0, nullptr};
   for (int r = 0; r < 3; ++r) {
     const kqft_chout o = chout(cls(xb, r, 0));
-    if ((rc = kqft_bubble_matsubara(ctx, r, &bare, &bare, &G0, Nq, &o, stream))) return rc;
+    if ((rc = kqft_bubble_matsubara(ctx, r, &bare, &bare, &G0, KQFT_PI_GG, Nq, &o, stream))) return rc;
   }
   if ((rc = kqft_sde_matsubara(ctx, &bare, &G0, Nq, Nl, (double*)xsig, stream))) return rc;
   kqft_mvertex V;
@@ -1489,7 +1522,7 @@ int kqft_parquet_solve_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U
   for (int r = 0; r < 3; ++r)
     V.ch[r] = kqft_chvert{1.0, (const double*)cls(xb, r, 0), (const double*)cls(xb, r, 1),
                           (const double*)cls(xb, r, 2), (const double*)cls(xb, r, 3)};
-  const kqft_mprop Gs{Delta, (const double*)xsig, g.N};
+  const kqft_mprop Gs{Delta, (const double*)xsig, g.N, nullptr};
   std::vector<std::pair<const double2*, const double2*>> xf;
   std::vector<size_t> counts;
   for (int r = 0; r < 3; ++r)
@@ -1505,8 +1538,8 @@ int kqft_parquet_solve_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U
       kqft_mvertex I = V;
       I.ch[r] = kqft_chvert{0.0, nullptr, nullptr, nullptr, nullptr};
       const kqft_chout o1 = chout(cls(gb, r, 0)), o2 = chout(tmp);
-      if ((rc = kqft_bubble_matsubara(ctx, r, &I, &V, &Gs, Nq, &o1, stream))) return rc;
-      if ((rc = kqft_bubble_matsubara(ctx, r, &V, &I, &Gs, Nq, &o2, stream))) return rc;
+      if ((rc = kqft_bubble_matsubara(ctx, r, &I, &V, &Gs, KQFT_PI_GG, Nq, &o1, stream))) return rc;
+      if ((rc = kqft_bubble_matsubara(ctx, r, &V, &I, &Gs, KQFT_PI_GG, Nq, &o2, stream))) return rc;
       const double2* k[2] = {cls(gb, r, 0), tmp};
       const double c[2] = {0.5, 0.5};
       lincomb_n(cls(gb, r, 0), nullptr, 2, k, c, chc, s);
@@ -1521,6 +1554,198 @@ int kqft_parquet_solve_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U
       HIP_TRY(hipMemcpyAsync(dst[c], cls(xb, r, c), cnt[c] * sizeof(double2), hipMemcpyDeviceToDevice, s));
   }
   HIP_TRY(hipMemcpyAsync(sigma, xsig, nf * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipGetLastError());
+  return KQFT_OK;
+}
+
+static double flow_lambda(int reg, double t);
+static double flow_t(int reg, double lam);
+static double flow_dlambda_dt(int reg, double t);
+
+int kqft_mfrg_flow_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, double Lambda_i, double Lambda_f,
+                             int steps, int nloops, int Nq, int Nl, int katanin, int se_iterations, double se_tol_abs,
+                             double se_tol_rel, const kqft_chout* gamma, double* sigma, void* stream) {
+  int rc;
+  if (!ctx) return fail(KQFT_EINVAL, "ctx is NULL");
+  if (!grid || !gamma || !sigma) return fail(KQFT_EINVAL, "grid, gamma and sigma must be given");
+  const kqft_mgrid g = *grid;
+  if (g.M < 0 || g.N < 1 || Nq < 1 || Nl < 1) return fail(KQFT_ESHAPE, "need M >= 0, N >= 1, Nq >= 1, Nl >= 1");
+  if (!(g.T > 0) || !(Lambda_i > 0) || !(Lambda_f > 0) || Lambda_i > 1e6 || Lambda_f > 1e6)
+    return fail(KQFT_EINVAL, "need T > 0 and 0 < Delta <= 1e6 along the flow");
+  if (steps < 1 || nloops < 1) return fail(KQFT_EINVAL, "need steps >= 1 and nloops >= 1");
+  if (se_iterations < 0 || !(se_tol_abs >= 0) || !(se_tol_rel >= 0))
+    return fail(KQFT_EINVAL, "self-energy correction settings must be non-negative");
+  for (int r = 0; r < 3; ++r)
+    if (!gamma[r].K1 || !gamma[r].K2 || !gamma[r].K2p || !gamma[r].K3)
+      return fail(KQFT_EINVAL, "gamma arrays must all be given");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const size_t nb = 2 * (size_t)g.M + 1, nf = 2 * (size_t)g.N;
+  const size_t cnt[4] = {2 * nb, 2 * nb * nf, 2 * nb * nf, 2 * nb * nf * nf};
+  const size_t chc = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+  const size_t stc = 3 * chc + nf;
+  const bool corr = se_iterations > 0 && nloops >= 3;
+  // Y, stage input, stage derivative, RK4 accumulator; insertions; centre sums; two scratch
+  // channels; Sigma-sized work arrays
+  const size_t total = 4 * stc + (size_t)nloops * 3 * chc + 2 * chc + 2 * chc + 6 * nf;
+  if ((rc = ensure(ctx->mfflow, total * sizeof(double2)))) return rc;
+  double2* base = (double2*)ctx->mfflow.p;
+  double2 *Y = base, *yt = base + stc, *kd = base + 2 * stc, *ys = base + 3 * stc;
+  double2* ml = base + 4 * stc;
+  double2* cen = ml + (size_t)nloops * 3 * chc;
+  double2 *t1 = cen + 2 * chc, *t2 = t1 + chc;
+  double2* ax = t2 + chc;
+  double2 *sd1 = ax, *tb = ax + nf, *sdt = ax + 2 * nf, *snew = ax + 3 * nf, *sdk = ax + 4 * nf;
+  auto cls = [&](double2* b0, int c) {
+    size_t off = 0;
+    for (int u = 0; u < c; ++u) off += cnt[u];
+    return b0 + off;
+  };
+  auto chout = [&](double2* b0) {
+    return kqft_chout{(double*)b0, (double*)cls(b0, 1), (double*)cls(b0, 2), (double*)cls(b0, 3)};
+  };
+  auto chvert = [&](double coef, double2* b0) {
+    return kqft_chvert{coef, (const double*)b0, (const double*)cls(b0, 1), (const double*)cls(b0, 2),
+                       (const double*)cls(b0, 3)};
+  };
+  auto ins = [&](int l, int r) { return ml + ((size_t)l * 3 + r) * chc; };
+  auto add_into = [&](double2* dst, const double2* src, size_t count) {
+    const double2* k[2] = {dst, src};
+    const double c[2] = {1.0, 1.0};
+    lincomb_n(dst, nullptr, 2, k, c, count, s);
+  };
+  auto rhs = [&](double t, double2* yb, double2* kout) -> int {
+    int e;
+    const double lam = flow_lambda(KQFT_REG_DELTA, t);
+    kqft_mvertex V;
+    memset(&V, 0, sizeof V);
+    V.grid = g;
+    V.U = U;
+    for (int r = 0; r < 3; ++r) V.ch[r] = chvert(1.0, yb + (size_t)r * chc);
+    const kqft_mprop G{lam, (const double*)(yb + 3 * chc), g.N, nullptr};
+    // Sigma_dot^(1) = -L(Gamma, S)
+    if ((e = kqft_loop_matsubara(ctx, &V, &G, KQFT_LINE_S, Nl, (double*)sd1, stream))) return e;
+    launch_axpby(sd1, -1.0, sd1, 0.0, sd1, nf, s);
+    launch_axpby(sdk, 1.0, sd1, 0.0, sd1, nf, s);
+    for (int it = 0;;) {
+      const kqft_mprop Gk{lam, (const double*)(yb + 3 * chc), g.N, katanin ? (const double*)sdk : nullptr};
+      for (int l = 0; l < nloops; ++l)
+        for (int r = 0; r < 3; ++r) {
+          const kqft_chout o = chout(ins(l, r));
+          if (l == 0) {
+            if ((e = kqft_bubble_matsubara(ctx, r, &V, &V, &Gk, KQFT_PI_DOT, Nq, &o, stream))) return e;
+            continue;
+          }
+          kqft_mvertex rbar;
+          memset(&rbar, 0, sizeof rbar);
+          rbar.grid = g;
+          for (int r2 = 0; r2 < 3; ++r2)
+            if (r2 != r) rbar.ch[r2] = chvert(1.0, ins(l - 1, r2));
+          const kqft_chout o1 = chout(t1);
+          if ((e = kqft_bubble_matsubara(ctx, r, &rbar, &V, &Gk, KQFT_PI_GG, Nq, &o, stream))) return e;
+          if ((e = kqft_bubble_matsubara(ctx, r, &V, &rbar, &Gk, KQFT_PI_GG, Nq, &o1, stream))) return e;
+          add_into(ins(l, r), t1, chc);
+          if (l >= 2) {  // centre: B_r(Gamma, B_r(gdot_rbar^(l-2), Gamma))
+            kqft_mvertex rbar2;
+            memset(&rbar2, 0, sizeof rbar2);
+            rbar2.grid = g;
+            for (int r2 = 0; r2 < 3; ++r2)
+              if (r2 != r) rbar2.ch[r2] = chvert(1.0, ins(l - 2, r2));
+            const kqft_chout o2 = chout(t2);
+            if ((e = kqft_bubble_matsubara(ctx, r, &rbar2, &V, &Gk, KQFT_PI_GG, Nq, &o2, stream))) return e;
+            kqft_mvertex inner;
+            memset(&inner, 0, sizeof inner);
+            inner.grid = g;
+            inner.ch[r] = chvert(1.0, t2);
+            if ((e = kqft_bubble_matsubara(ctx, r, &V, &inner, &Gk, KQFT_PI_GG, Nq, &o1, stream))) return e;
+            add_into(ins(l, r), t1, chc);
+            if (corr && r < 2) {
+              if (l == 2) {
+                HIP_TRY(hipMemcpyAsync(cen + (size_t)r * chc, t1, chc * sizeof(double2), hipMemcpyDeviceToDevice, s));
+              } else {
+                add_into(cen + (size_t)r * chc, t1, chc);
+              }
+            }
+          }
+        }
+      if (!corr) break;
+      // Sigma_dot_tbar = -L(centre_a + centre_p, G); Sigma_dot_t = -L(Gamma, G Sigma_dot_tbar G)
+      kqft_mvertex Vc;
+      memset(&Vc, 0, sizeof Vc);
+      Vc.grid = g;
+      for (int r = 0; r < 2; ++r) Vc.ch[r] = chvert(1.0, cen + (size_t)r * chc);
+      if ((e = kqft_loop_matsubara(ctx, &Vc, &G, KQFT_LINE_G, Nl, (double*)tb, stream))) return e;
+      launch_axpby(tb, -1.0, tb, 0.0, tb, nf, s);
+      const kqft_mprop Gt{lam, (const double*)(yb + 3 * chc), g.N, (const double*)tb};
+      if ((e = kqft_loop_matsubara(ctx, &V, &Gt, KQFT_LINE_GSG, Nl, (double*)sdt, stream))) return e;
+      const double2* ks[2] = {tb, sdt};
+      const double cs[2] = {1.0, -1.0};
+      lincomb_n(snew, sd1, 2, ks, cs, nf, s);
+      // max-norms of the change and of the new value (host, Sigma-sized)
+      std::vector<double2> ha(nf), hb(nf);
+      HIP_TRY(hipMemcpyAsync(ha.data(), sdk, nf * sizeof(double2), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(hb.data(), snew, nf * sizeof(double2), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      double md = 0.0, mv = 0.0;
+      for (size_t i = 0; i < nf; ++i) {
+        md = std::max(md, std::hypot(hb[i].x - ha[i].x, hb[i].y - ha[i].y));
+        mv = std::max(mv, std::hypot(hb[i].x, hb[i].y));
+      }
+      ++it;
+      launch_axpby(sdk, 1.0, snew, 0.0, snew, nf, s);
+      if (md <= se_tol_abs + se_tol_rel * mv || it >= se_iterations) break;
+    }
+    // Gamma_dot = sum over the loop orders, Sigma_dot; times dLambda/dt
+    const double dl = flow_dlambda_dt(KQFT_REG_DELTA, t);
+    for (int r = 0; r < 3; ++r) {
+      std::vector<const double2*> ks;
+      std::vector<double> cs;
+      for (int l = 0; l < nloops; ++l) {
+        ks.push_back(ins(l, r));
+        cs.push_back(dl);
+      }
+      lincomb_n(kout + (size_t)r * chc, nullptr, nloops, ks.data(), cs.data(), chc, s);
+    }
+    launch_axpby(kout + 3 * chc, dl, sdk, 0.0, sdk, nf, s);
+    return KQFT_OK;
+  };
+  for (int r = 0; r < 3; ++r) {
+    const double* src[4] = {gamma[r].K1, gamma[r].K2, gamma[r].K2p, gamma[r].K3};
+    for (int c = 0; c < 4; ++c)
+      HIP_TRY(hipMemcpyAsync(cls(Y + (size_t)r * chc, c), src[c], cnt[c] * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  }
+  HIP_TRY(hipMemcpyAsync(Y + 3 * chc, sigma, nf * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  const double ti = flow_t(KQFT_REG_DELTA, Lambda_i), tf = flow_t(KQFT_REG_DELTA, Lambda_f);
+  const double h = (tf - ti) / steps;
+  for (int k = 0; k < steps; ++k) {  // classical RK4
+    const double ta = ti + k * h;
+    const double2* kk[1] = {kd};
+    double c[1];
+    if ((rc = rhs(ta, Y, kd))) return rc;
+    c[0] = h / 6.0;
+    lincomb_n(ys, Y, 1, kk, c, stc, s);
+    c[0] = h / 2.0;
+    lincomb_n(yt, Y, 1, kk, c, stc, s);
+    if ((rc = rhs(ta + h / 2.0, yt, kd))) return rc;
+    c[0] = h / 3.0;
+    lincomb_n(ys, ys, 1, kk, c, stc, s);
+    c[0] = h / 2.0;
+    lincomb_n(yt, Y, 1, kk, c, stc, s);
+    if ((rc = rhs(ta + h / 2.0, yt, kd))) return rc;
+    c[0] = h / 3.0;
+    lincomb_n(ys, ys, 1, kk, c, stc, s);
+    c[0] = h;
+    lincomb_n(yt, Y, 1, kk, c, stc, s);
+    if ((rc = rhs(ta + h, yt, kd))) return rc;
+    c[0] = h / 6.0;
+    lincomb_n(Y, ys, 1, kk, c, stc, s);
+  }
+  for (int r = 0; r < 3; ++r) {
+    double* dst[4] = {gamma[r].K1, gamma[r].K2, gamma[r].K2p, gamma[r].K3};
+    for (int c = 0; c < 4; ++c)
+      HIP_TRY(hipMemcpyAsync(dst[c], cls(Y + (size_t)r * chc, c), cnt[c] * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  }
+  HIP_TRY(hipMemcpyAsync(sigma, Y + 3 * chc, nf * sizeof(double2), hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipGetLastError());
   return KQFT_OK;
 }

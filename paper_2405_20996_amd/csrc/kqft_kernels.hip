@@ -2142,6 +2142,19 @@ __device__ inline double2 mf_G(const MGatherArgs& a, int n) {
   return cinv(make_double2(-sg.x, v + (v > 0.0 ? a.Delta : -a.Delta) - sg.y));
 }
 
+// X(n) of the lines: 0 G, 1 S = -i sgn(nu) G^2 + G Sigma_dot G, 2 G Sigma_dot G
+__device__ inline double2 mf_line(const MGatherArgs& a, int n, int line) {
+  const double2 g = mf_G(a, n);
+  if (line == 0) return g;
+  double2 ds = czero();
+  if (a.dsigma && n >= -a.Ns && n < a.Ns) ds = a.dsigma[n + a.Ns];
+  const double2 gsg = cmul(cmul(g, ds), g);
+  if (line == 2) return gsg;
+  const double2 g2 = cmul(g, g);
+  const double sg = (2.0 * n + 1.0) > 0.0 ? 1.0 : -1.0;
+  return cadd(make_double2(sg * g2.y, -sg * g2.x), gsg);  // -i sgn G^2
+}
+
 // first index and length of channel r's window |2n'' + 1 + s m| <= 2 Nq - 1 (s = -1 for p)
 __device__ inline int mf_window_lo(int r, int m, int Nq) {
   const int sm = r == 1 ? -m : m;
@@ -2164,7 +2177,9 @@ __global__ __launch_bounds__(256) void mf_left_kernel(MGatherArgs a) {
     return;
   }
   const int nq = mf_window_lo(a.r, m, a.Nq) + k;
-  const double2 pi = a.r == 1 ? cmul(mf_G(a, nq), mf_G(a, m - nq - 1)) : cmul(mf_G(a, nq + m), mf_G(a, nq));
+  const int k1 = a.r == 1 ? nq : nq + m, k2 = a.r == 1 ? m - nq - 1 : nq;
+  const double2 pi = a.kind == 1 ? cadd(cmul(mf_line(a, k1, 1), mf_G(a, k2)), cmul(mf_G(a, k1), mf_line(a, k2, 1)))
+                                 : cmul(mf_G(a, k1), mf_G(a, k2));
   double2 XY[2] = {czero(), czero()};
   if (i < 2 * a.N) {  // L - L^inf: own K2(m, n) + K3(m, n, n''), the other channels
     const int n = i - a.N;
@@ -2258,6 +2273,26 @@ __global__ __launch_bounds__(256) void mf_loop_kernel(MLoopArgs a) {
     acc = cadd(acc, cmul(cadd(cscale(2.0, X), Y), g));
   }
   a.out[i] = cscale(-0.5 * a.T, acc);
+}
+
+__global__ __launch_bounds__(256) void mf_vloop_kernel(MGatherArgs a, int line, int Nl, double2* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * a.N) return;
+  const int n = i - a.N;
+  double2 acc = czero();
+  for (int k = -Nl; k < Nl; ++k) {
+    // legs (n, k | n, k) in channel a: m = n - k, n_a = k, n'_a = k
+    const int m = n - k;
+    double2 XY[2] = {make_double2(-a.U, 0.0), make_double2(a.U, 0.0)};
+    mf_chan(a.ch[0], a.M, a.N, m, k, k, 15, XY);
+    mf_others(a, m, k, k, XY);
+    acc = cadd(acc, cmul(cadd(cscale(2.0, XY[0]), XY[1]), mf_line(a, k, line)));
+  }
+  out[i] = cscale(a.T, acc);
+}
+
+void launch_mf_vloop(const MGatherArgs& v, int line, int Nl, double2* out, hipStream_t s) {
+  hipLaunchKernelGGL(mf_vloop_kernel, dim3((unsigned)((2 * v.N + 255) / 256)), dim3(256), 0, s, v, line, Nl, out);
 }
 
 void launch_mf_loop(const MLoopArgs& a, hipStream_t s) {

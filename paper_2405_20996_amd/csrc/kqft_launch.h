@@ -248,8 +248,10 @@ struct MChan {
 // window of channel r's bubble (zero past its end), c = 0, 1 the spin combinations of P[c].
 struct MGatherArgs {
   int r, M, N, Nq, m0, nb;
+  int kind;  // 0: Pi = G G; 1: Pi_dot = S G + G S (S = dG/dDelta + G Sigma_dot G)
   double T, Delta;
-  const double2* sigma;  // G's self-energy on n in [-Ns, Ns), or null
+  const double2* sigma;   // G's self-energy on n in [-Ns, Ns), or null
+  const double2* dsigma;  // Sigma_dot on the same box (Katanin), or null
   int Ns;
   double U;  // bare vertex X0 = -U, Y0 = +U
   MChan ch[3];
@@ -275,6 +277,10 @@ struct MLoopArgs {
   double2* out;
 };
 void launch_mf_loop(const MLoopArgs& a, hipStream_t s);
+// L(Gamma, X)(n) = T sum_{n'} [2X + Y](legs n, n' | n, n') X(n') for n in [-N, N), n' in
+// [-Nl, Nl), the full vertex of v (bare part, all channels and classes), X = G, S or G
+// Sigma_dot G (line 0, 1, 2); v.r = 0
+void launch_mf_vloop(const MGatherArgs& v, int line, int Nl, double2* out, hipStream_t s);
 void launch_mf_left(const MGatherArgs& a, hipStream_t s);
 void launch_mf_right(const MGatherArgs& a, hipStream_t s);
 void launch_mf_epilogue(const MEpiArgs& a, hipStream_t s);

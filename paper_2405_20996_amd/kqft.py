@@ -52,7 +52,7 @@ class KqftMVertex(C.Structure):
 
 
 class KqftMProp(C.Structure):
-    _fields_ = [("Delta", C.c_double), ("sigma", C.c_void_p), ("sigma_N", C.c_int)]
+    _fields_ = [("Delta", C.c_double), ("sigma", C.c_void_p), ("sigma_N", C.c_int), ("dsigma", C.c_void_p)]
 
 
 class KqftPropagator(C.Structure):
@@ -125,7 +125,12 @@ def lib():
         _lib.kqft_chi.argtypes = [C.c_void_p, C.c_int, P(KqftVertex), P(KqftPropagator), P(KqftQuad), C.c_void_p,
                                   C.c_void_p]
         _lib.kqft_bubble_matsubara.argtypes = [C.c_void_p, C.c_int, P(KqftMVertex), P(KqftMVertex), P(KqftMProp),
-                                               C.c_int, P(KqftChout), C.c_void_p]
+                                               C.c_int, C.c_int, P(KqftChout), C.c_void_p]
+        _lib.kqft_loop_matsubara.argtypes = [C.c_void_p, P(KqftMVertex), P(KqftMProp), C.c_int, C.c_int, C.c_void_p,
+                                             C.c_void_p]
+        _lib.kqft_mfrg_flow_matsubara.argtypes = [C.c_void_p, P(KqftMGrid), C.c_double, C.c_double, C.c_double,
+                                                  C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
+                                                  C.c_double, P(KqftChout), C.c_void_p, C.c_void_p]
         _lib.kqft_sde_matsubara.argtypes = [C.c_void_p, P(KqftMVertex), P(KqftMProp), C.c_int, C.c_int, C.c_void_p,
                                             C.c_void_p]
         _lib.kqft_parquet_solve_matsubara.argtypes = [C.c_void_p, P(KqftMGrid), C.c_double, C.c_double, C.c_int,
@@ -400,23 +405,58 @@ def chi(channel: int, gamma: Vertex, G: Propagator, q: Quad, stream=None) -> tor
     return out
 
 
+def _mprop(Delta: float, sigma: Optional[torch.Tensor], dsigma: Optional[torch.Tensor]) -> KqftMProp:
+    ref = sigma if sigma is not None else dsigma
+    ns = 0 if ref is None else ref.shape[0] // 2
+    for t in (sigma, dsigma):
+        if t is not None and t.shape[0] != 2 * ns:
+            raise ValueError("sigma and dsigma need the same even length 2 Ns")
+    return KqftMProp(Delta, _ptr(sigma, None, "sigma"), ns, _ptr(dsigma, None, "dsigma"))
+
+
 def bubble_matsubara(channel: int, left: MVertex, right: MVertex, Delta: float, Nq: int,
-                     sigma: Optional[torch.Tensor] = None, out: Optional[Channel] = None, stream=None) -> Channel:
+                     sigma: Optional[torch.Tensor] = None, out: Optional[Channel] = None, pi_kind: int = PI_GG,
+                     dsigma: Optional[torch.Tensor] = None, stream=None) -> Channel:
     """B_channel(left, right) in the Matsubara formalism (sum over 2 Nq fermionic frequencies about
-    the bubble's centre); sigma: Sigma(i nu_n) on n in [-Ns, Ns) (length 2 Ns) or None."""
+    the bubble's centre); sigma: Sigma(i nu_n) on n in [-Ns, Ns) (length 2 Ns) or None; pi_kind
+    PI_DOT: Pi_dot along S = dG/dDelta (+ G dsigma G)."""
     g = left.grid
     dev = torch.device("cuda", torch.cuda.current_device())
     if out is None:
         out = Channel(1.0, *[torch.zeros(g.shape(c), dtype=torch.complex128, device=dev) for c in CLASSES])
-    ns = 0 if sigma is None else sigma.shape[0] // 2
-    if sigma is not None and sigma.shape[0] != 2 * ns:
-        raise ValueError("sigma needs an even length 2 Ns")
-    gp = KqftMProp(Delta, _ptr(sigma, None, "sigma"), ns)
+    gp = _mprop(Delta, sigma, dsigma)
     oc = KqftChout(*[_ptr(getattr(out, c), g.shape(c), f"out.{c}") for c in CLASSES])
     lc, rc = left.c(), right.c()
-    _check(lib().kqft_bubble_matsubara(ctx(), channel, C.byref(lc), C.byref(rc), C.byref(gp), Nq, C.byref(oc),
-                                       _stream(stream)))
+    _check(lib().kqft_bubble_matsubara(ctx(), channel, C.byref(lc), C.byref(rc), C.byref(gp), pi_kind, Nq,
+                                       C.byref(oc), _stream(stream)))
     return out
+
+
+def loop_matsubara(gamma: MVertex, Delta: float, Nl: int, kind: int = LINE_G, sigma: Optional[torch.Tensor] = None,
+                   dsigma: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """L(Gamma, X)(i nu_n), n in [-N, N), X = G, S (+ G dsigma G) or G dsigma G."""
+    g = gamma.grid
+    out = torch.zeros(2 * g.N, dtype=torch.complex128, device=torch.device("cuda", torch.cuda.current_device()))
+    gp = _mprop(Delta, sigma, dsigma)
+    vc = gamma.c()
+    _check(lib().kqft_loop_matsubara(ctx(), C.byref(vc), C.byref(gp), kind, Nl, C.c_void_p(out.data_ptr()),
+                                     _stream(stream)))
+    return out
+
+
+def mfrg_flow_matsubara(grid: MGrid, U: float, lam_i: float, lam_f: float, steps: int, nloops: int, Nq: int, Nl: int,
+                        gamma: Sequence[Channel], sigma: torch.Tensor, katanin: bool = True, se_iterations: int = 0,
+                        se_atol: float = 1e-9, se_rtol: float = 1e-5, stream=None):
+    """The Matsubara hybridization flow of the state (gamma[3], sigma [2N]) from lam_i to lam_f,
+    in place (classical RK4)."""
+    D = (KqftChout * 3)(*[KqftChout(*[_ptr(getattr(c, x), grid.shape(x), f"gamma.{x}") for x in CLASSES])
+                          for c in gamma])
+    _ptr(sigma, (2 * grid.N,), "sigma")
+    gc = grid.c()
+    _check(lib().kqft_mfrg_flow_matsubara(ctx(), C.byref(gc), C.c_double(U), C.c_double(lam_i), C.c_double(lam_f),
+                                          steps, nloops, Nq, Nl, int(katanin), se_iterations, C.c_double(se_atol),
+                                          C.c_double(se_rtol), D, C.c_void_p(sigma.data_ptr()), _stream(stream)))
+    return gamma, sigma
 
 
 def sde_matsubara(gamma: MVertex, Delta: float, Nq: int, Nl: int, sigma: Optional[torch.Tensor] = None,
@@ -425,8 +465,7 @@ def sde_matsubara(gamma: MVertex, Delta: float, Nq: int, Nl: int, sigma: Optiona
     g = gamma.grid
     dev = torch.device("cuda", torch.cuda.current_device())
     out = torch.zeros(2 * g.N, dtype=torch.complex128, device=dev)
-    ns = 0 if sigma is None else sigma.shape[0] // 2
-    gp = KqftMProp(Delta, _ptr(sigma, None, "sigma"), ns)
+    gp = _mprop(Delta, sigma, None)
     vc = gamma.c()
     _check(lib().kqft_sde_matsubara(ctx(), C.byref(vc), C.byref(gp), Nq, Nl, C.c_void_p(out.data_ptr()),
                                     _stream(stream)))

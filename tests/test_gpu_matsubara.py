@@ -163,3 +163,58 @@ def test_matsubara_parquet_solver_time():
     print(f"Matsubara parquet M={M} N={N} Nq={Nq}: {dt * 1e3:.1f} ms per iteration, residuals "
           f"{['%.2e' % x for x in res]}", flush=True)
     assert res[-1] < 0.1 * res[1]
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_matsubara_loop_matches_oracle(kind):
+    """kqft_loop_matsubara of a random vertex (every channel and class, bare part) with G, S + G
+    Sigma_dot G or G Sigma_dot G, dynamic Sigma."""
+    K = _K()
+    M, N, Nl = 8, 5, 9
+    ov, kv = _pair(M, N, 13, U=0.7)
+    Ns = N + 2
+    sig = 0.1 * np.exp(1j * np.linspace(0.0, 2.0, 2 * Ns)) - 0.05j
+    dsig = 0.2 * np.exp(-1j * np.linspace(0.0, 1.0, 2 * Ns))
+    ref = MF.loop(ov, MF.MProp(1.3, T, sig, dsig), Nl, kind)
+    out = K.loop_matsubara(kv, 1.3, Nl, kind, sigma=to_dev(sig), dsigma=to_dev(dsig)).cpu().numpy()
+    assert _rel(out, ref) < 1e-12
+
+
+@pytest.mark.parametrize("r", [0, 1, 2])
+def test_matsubara_pidot_bubble_matches_oracle(r):
+    K = _K()
+    M, N, Nq = 4, 4, 7
+    oL, kL = _pair(M, N, 30 + r)
+    oR, kR = _pair(M, N, 40 + r, U=-0.4)
+    Ns = N + 3
+    sig = 0.2 * np.exp(1j * np.linspace(0.0, 3.0, 2 * Ns)) - 0.1j
+    dsig = 0.3 * np.exp(-1j * np.linspace(0.0, 2.0, 2 * Ns))
+    ref = MF.bubble(r, oL, oR, MF.MProp(D, T, sig, dsig), Nq, 1)
+    out = K.bubble_matsubara(r, kL, kR, D, Nq, sigma=to_dev(sig), dsigma=to_dev(dsig), pi_kind=K.PI_DOT)
+    torch.cuda.synchronize()
+    for x in CL:
+        assert _rel(getattr(out, x).cpu().numpy(), getattr(ref, x)) < 1e-12, x
+
+
+@pytest.mark.parametrize("steps,nloops,katanin,se", [(2, 1, False, 0), (1, 3, True, 3), (1, 2, True, 0)])
+def test_matsubara_flow_matches_oracle(steps, nloops, katanin, se):
+    """The Matsubara hybridization flow from the PT2 state (Delta 2 -> 1, U = 1, M = 8, N = 3):
+    one-loop RK4, three loops with Katanin and self-energy corrections, two loops with Katanin."""
+    K = _K()
+    M, N, Nq, Nl, U = 8, 3, 8, 6, 1.0
+    og = MF.MGrid(M, N, T)
+    chans, sig = MF.pt2_state(og, U, 2.0, Nq, Nl)
+    rch, rsig = MF.mfrg_flow(og, U, 2.0, 1.0, steps, nloops, Nq, Nl, chans, sig, katanin, se)
+    kch = [K.Channel(1.0, *[to_dev(getattr(c, x)) for x in CL]) for c in chans]
+    ksig = to_dev(sig)
+    K.mfrg_flow_matsubara(K.MGrid(M, N, T), U, 2.0, 1.0, steps, nloops, Nq, Nl, kch, ksig, katanin=katanin,
+                          se_iterations=se)
+    torch.cuda.synchronize()
+    for r in range(3):
+        for x in CL:
+            b = getattr(rch[r], x)
+            if np.abs(b).max() == 0.0:
+                assert float(getattr(kch[r], x).abs().max()) == 0.0
+                continue
+            assert _rel(getattr(kch[r], x).cpu().numpy(), b) < 1e-10, (r, x)
+    assert _rel(ksig.cpu().numpy(), rsig) < 1e-10
