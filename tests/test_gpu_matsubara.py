@@ -218,3 +218,24 @@ def test_matsubara_flow_matches_oracle(steps, nloops, katanin, se):
                 continue
             assert _rel(getattr(kch[r], x).cpu().numpy(), b) < 1e-10, (r, x)
     assert _rel(ksig.cpu().numpy(), rsig) < 1e-10
+
+
+def test_matsubara_flow_time():
+    """M = 48, N = 24, Nq = 48, Nl = 24, U = 1: two RK4 steps of the hybridization flow from the
+    PT2 state (Delta 2 -> 1), three loops with Katanin and up to three correction iterations; the
+    time per right-hand side and a finite state."""
+    K = _K()
+    M, N, Nq, Nl, U = 48, 24, 48, 24, 1.0
+    og = MF.MGrid(M, N, T)
+    chans, sig = MF.pt2_state(og, U, 2.0, Nq, Nl)
+    kch = [K.Channel(1.0, *[to_dev(getattr(c, x)) for x in CL]) for c in chans]
+    ksig = to_dev(sig)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    K.mfrg_flow_matsubara(K.MGrid(M, N, T), U, 2.0, 1.0, 2, 3, Nq, Nl, kch, ksig, katanin=True, se_iterations=3)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(f"Matsubara flow M={M} N={N} Nq={Nq}, l<=3, Katanin, corrections: {dt * 1e3:.1f} ms for 8 right-hand "
+          f"sides ({dt / 8 * 1e3:.1f} ms each)", flush=True)
+    assert all(bool(torch.isfinite(getattr(c, x)).all()) for c in kch for x in CL)
+    assert bool(torch.isfinite(ksig).all())
