@@ -214,8 +214,30 @@ def _spin_sum(r: int, LX, LY, pi, RX, RY):
     return -(mm(LX, RX + RY) + mm(LX + LY, RX)), -mm(LY, RY)
 
 
-def bubble(r: int, L: MVertex, R: MVertex, P: MProp, Nq: int, kind: int = 0) -> MChannel:
-    """B_r(L, R) as the four asymptotic classes of channel r (kind 1: with Pi_dot)."""
+def bare_bubble_sum(r: int, m: int, Delta: float, T: float) -> float:
+    """T sum over every n'' of the bare Pi_r(m, n''), G_0 = 1/(i nu + i Delta sgn nu) (Sec. asymptotic
+    corrections: the bare bubble is known in closed form).  a and t: the n'' where both
+    frequencies share a sign give digamma differences, the |m| mixed terms are summed; p: minus
+    the a sum (G_0 is odd in nu)."""
+    import scipy.special as sps
+    ma = abs(m)
+    d = Delta / (2.0 * np.pi * T)
+    c = 1.0 / (2.0 * np.pi * T) ** 2
+    same = c * (sps.polygamma(1, 0.5 + d) if ma == 0 else (sps.digamma(0.5 + ma + d) - sps.digamma(0.5 + d)) / ma)
+    mixed = sum(1.0 / ((nu(n + ma, T) + Delta) * (nu(n, T) - Delta)) for n in range(-ma, 0))
+    sa = -T * (2.0 * same + mixed)
+    return -sa if r == 1 else sa
+
+
+def bubble(r: int, L: MVertex, R: MVertex, P: MProp, Nq: int, kind: int = 0, tails: bool = False) -> MChannel:
+    """B_r(L, R) as the four asymptotic classes of channel r (kind 1: with Pi_dot).  With tails
+    (kind 0 only; Sec. asymptotic corrections, the analytic-tails option) the summands beyond the
+    window are added with the bare bubble: there Sigma has decayed and the vertices reach their
+    values at large n'', L -> Gamma_0 + K1 + K2(m, n), R -> Gamma_0 + K1 + K2'(m, n') of the own
+    channel, so each class gains its part of L(inf) t(m) R(inf) with t(m) = bare_bubble_sum - the
+    window's bare sum."""
+    if tails and kind != 0:
+        raise ValueError("the analytic tails are those of the bubble G G")
     g = L.grid
     sh = g.shapes()
     out = {k: np.zeros(s, dtype=np.complex128) for k, s in sh.items()}
@@ -244,6 +266,25 @@ def bubble(r: int, L: MVertex, R: MVertex, P: MProp, Nq: int, kind: int = 0) -> 
         out["K2"][0, im], out["K2"][1, im] = x2[:, 0], y2[:, 0]
         out["K2p"][0, im], out["K2p"][1, im] = x2p[0], y2p[0]
         out["K1"][0, im], out["K1"][1, im] = x1[0, 0], y1[0, 0]
+        if tails:
+            t = np.array([bare_bubble_sum(r, m, P.Delta, P.T) - pi_r(r, MProp(P.Delta, P.T), m, k).sum()])
+            lmain = channel_value(own_L, g, m, nbox, 0, ("K2",))      # [2, n]
+            linf = channel_value(own_L, g, m, 0, 0, ("K1",)) + np.array([-L.U, L.U])
+            rmain = channel_value(own_R, g, m, 0, nbox, ("K2p",))     # [2, n']
+            rinf = channel_value(own_R, g, m, 0, 0, ("K1",)) + np.array([-R.U, R.U])
+            x3, y3 = _spin_sum(r, lmain[0][:, None], lmain[1][:, None], t, rmain[0][None, :], rmain[1][None, :])
+            x2, y2 = _spin_sum(r, lmain[0][:, None], lmain[1][:, None], t, np.array([[rinf[0]]]), np.array([[rinf[1]]]))
+            x2p, y2p = _spin_sum(r, np.array([[linf[0]]]), np.array([[linf[1]]]), t, rmain[0][None, :], rmain[1][None, :])
+            x1, y1 = _spin_sum(r, np.array([[linf[0]]]), np.array([[linf[1]]]), t, np.array([[rinf[0]]]),
+                               np.array([[rinf[1]]]))
+            out["K3"][0, im] += x3
+            out["K3"][1, im] += y3
+            out["K2"][0, im] += x2[:, 0]
+            out["K2"][1, im] += y2[:, 0]
+            out["K2p"][0, im] += x2p[0]
+            out["K2p"][1, im] += y2p[0]
+            out["K1"][0, im] += x1[0, 0]
+            out["K1"][1, im] += y1[0, 0]
     return MChannel(1.0, out["K1"], out["K2"], out["K2p"], out["K3"])
 
 

@@ -224,3 +224,33 @@ def test_matsubara_flow_of_pt2_reaches_pt2_to_second_order():
         devs.append(max(np.abs(ch[r].K1 - ref[r].K1).max() / np.abs(ref[r].K1).max() for r in range(3)))
     assert devs[0] < 0.05
     assert 0.3 < devs[1] / devs[0] < 0.7
+
+
+def test_analytic_tails_make_the_bubble_independent_of_the_window():
+    """With the analytic tails the summands beyond the window enter through the bare bubble's
+    closed form and the vertices' large-frequency values: for Gamma_0 on both sides the K1 class
+    is the same for every window (and differs by the window's tail without them), and for random
+    vertices with a self-energy on a box the bubble no longer depends on the window once the
+    window covers every box (the tails are then exact) -- without them it changes by ten per cent."""
+    g = MF.MGrid(6, 4, T)
+    g0 = MF.bare(g, U)
+    P = MF.MProp(D, T)
+    for r in range(3):
+        a = MF.bubble(r, g0, g0, P, 5, tails=True).K1
+        b = MF.bubble(r, g0, g0, P, 60, tails=True).K1
+        c = MF.bubble(r, g0, g0, P, 60).K1
+        assert np.abs(a - b).max() < 1e-14 * np.abs(b).max()
+        assert np.abs(b - c).max() > 1e-2 * np.abs(b).max()
+    g = MF.MGrid(3, 3, T)
+    L, R = _random_vertex(g, 1), _random_vertex(g, 2)
+    Pd = MF.MProp(D, T, 0.2 * np.exp(1j * np.linspace(0, 3, 10)) - 0.1j)
+    for r in range(3):
+        ref = MF.bubble(r, L, R, Pd, 40, tails=True)
+        for Nq in (8, 20):
+            with_t = MF.bubble(r, L, R, Pd, Nq, tails=True)
+            without = MF.bubble(r, L, R, Pd, Nq)
+            for x in MF.CLASSES:
+                scale = np.abs(getattr(ref, x)).max()
+                assert np.abs(getattr(with_t, x) - getattr(ref, x)).max() < 1e-13 * scale, (r, Nq, x)
+            assert max(np.abs(getattr(without, x) - getattr(ref, x)).max() / np.abs(getattr(ref, x)).max()
+                       for x in MF.CLASSES) > 0.05
