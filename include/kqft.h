@@ -282,7 +282,12 @@ typedef struct {
 /*
  * kqft_bubble_matsubara -- B_r(left, right) in the Matsubara formalism:
  *   B_r(m; n, n') = pref_r T sum_{n''} left(m; n, n'') Pi_r(m, n'') right(m; n'', n')
- * (pi_kind KQFT_PI_GG: Pi = G G; KQFT_PI_DOT: Pi_dot = S G + G S with S of kqft_mprop)
+ * (pi_kind KQFT_PI_GG: Pi = G G; KQFT_PI_DOT: Pi_dot = S G + G S with S of kqft_mprop).
+ * tails = 1 (Pi = G G only; Sec. "asymptotic corrections", the analytic-tails option) adds the
+ * summands beyond the window through the bare bubble, whose full sum is known in closed form
+ * (digamma functions): t(m) = that sum minus the window's bare sum, times the vertices' values
+ * at large n'' (left Gamma_0 + K1 + K2(m, n), right Gamma_0 + K1 + K2'(m, n') of the channel),
+ * split over the classes like the bubble itself.
  * with the spin sums of the real-frequency bubble (the same two combinations per channel,
  * prefactors +1, 1/2, -1), Pi_a = Pi_t = G(n'' + m) G(n''), Pi_p = G(n'') G(m - n'' - 1), the
  * sum over the window |2n'' + 1 + s m| <= 2 Nq - 1 (s = +1 for a and t, -1 for p; symmetric
@@ -296,7 +301,7 @@ typedef struct {
  * N < 1, Nq < 1 or sizes whose panels exceed 2^31 entries.
  */
 int kqft_bubble_matsubara(kqft_ctx* ctx, int channel, const kqft_mvertex* left, const kqft_mvertex* right,
-                          const kqft_mprop* G, int pi_kind, int Nq, const kqft_chout* out, void* stream);
+                          const kqft_mprop* G, int pi_kind, int Nq, int tails, const kqft_chout* out, void* stream);
 
 /*
  * kqft_loop_matsubara -- the loop of a full Matsubara vertex (bare part, every channel at its own

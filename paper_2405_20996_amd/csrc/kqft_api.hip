@@ -3,6 +3,7 @@
 // for kqft_bubble, kqft_sde, kqft_mloop_step and kqft_bubble_adjoint.
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <functional>
@@ -45,7 +46,7 @@ struct kqft_ctx {
   hipStream_t sg = nullptr, sm = nullptr;
   rocblas_handle blas = nullptr;
   DevBuf adjw, dkf[2][3], phigrad, pq, pqsig, pqred, vtab[3], flow, flowml, ctmp, flowred, pqx, adapt, sdep, mf, mftmp,
-      mfflow;
+      mfflow, mftail;
   std::vector<hipEvent_t> events;
   size_t next_event = 0;
   bool prof = false;
@@ -973,7 +974,7 @@ int kqft_ctx_destroy(kqft_ctx* ctx) {
   if (ctx->adjw.p) (void)hipFree(ctx->adjw.p);
   for (DevBuf* b : {&ctx->pq, &ctx->pqsig, &ctx->pqred, &ctx->vtab[0], &ctx->vtab[1], &ctx->vtab[2], &ctx->flow,
                     &ctx->flowml, &ctx->ctmp, &ctx->flowred, &ctx->pqx, &ctx->adapt, &ctx->sdep, &ctx->mf, &ctx->mftmp,
-                    &ctx->mfflow})
+                    &ctx->mfflow, &ctx->mftail})
     if (b->p) (void)hipFree(b->p);
   if (ctx->phigrad.p) (void)hipFree(ctx->phigrad.p);
   if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
@@ -1337,13 +1338,51 @@ int kqft_loop_matsubara(kqft_ctx* ctx, const kqft_mvertex* gamma, const kqft_mpr
   return KQFT_OK;
 }
 
+// digamma and trigamma for x > 0: upward recurrence to x >= 10, then the asymptotic series in
+// 1/x^2 with Bernoulli-number coefficients (Abramowitz and Stegun 6.3.18, 6.4.12)
+static double digamma_pos(double x) {
+  double r = 0.0;
+  while (x < 10.0) {
+    r -= 1.0 / x;
+    x += 1.0;
+  }
+  const double f = 1.0 / (x * x);
+  return r + std::log(x) - 0.5 / x -
+         f * (1.0 / 12 - f * (1.0 / 120 - f * (1.0 / 252 - f * (1.0 / 240 - f * (1.0 / 132)))));
+}
+static double trigamma_pos(double x) {
+  double r = 0.0;
+  while (x < 10.0) {
+    r += 1.0 / (x * x);
+    x += 1.0;
+  }
+  const double f = 1.0 / (x * x);
+  return r + 1.0 / x + 0.5 * f + f / x * (1.0 / 6 - f * (1.0 / 30 - f * (1.0 / 42 - f * (1.0 / 30 - f * (5.0 / 66)))));
+}
+
+// T sum over every n'' of the bare Pi_r(m, n''), G_0 = 1/(i nu + i Delta sgn nu): for a and t the
+// n'' where both frequencies share a sign sum to digamma differences (twice the same value by
+// the reflection n'' -> -n'' - 1 - m), the |m| mixed terms are added; p is minus a (G_0 odd).
+static double mf_bare_bubble_sum(int r, int m, double Delta, double T) {
+  const int ma = std::abs(m);
+  const double d = Delta / (2.0 * M_PI * T), c = 1.0 / (4.0 * M_PI * M_PI * T * T);
+  const double same = c * (ma == 0 ? trigamma_pos(0.5 + d) : (digamma_pos(0.5 + ma + d) - digamma_pos(0.5 + d)) / ma);
+  double mixed = 0.0;
+  for (int n = -ma; n < 0; ++n)
+    mixed += 1.0 / (((2.0 * (n + ma) + 1.0) * M_PI * T + Delta) * ((2.0 * n + 1.0) * M_PI * T - Delta));
+  const double sa = -T * (2.0 * same + mixed);
+  return r == KQFT_CH_P ? -sa : sa;
+}
+
 int kqft_bubble_matsubara(kqft_ctx* ctx, int channel, const kqft_mvertex* left, const kqft_mvertex* right,
-                          const kqft_mprop* G, int pi_kind, int Nq, const kqft_chout* out, void* stream) {
+                          const kqft_mprop* G, int pi_kind, int Nq, int tails, const kqft_chout* out, void* stream) {
   int rc;
   if (!ctx) return fail(KQFT_EINVAL, "ctx is NULL");
   if (!left || !right || !G || !out) return fail(KQFT_EINVAL, "vertices, propagator and outputs must be given");
   if (channel < KQFT_CH_A || channel > KQFT_CH_T) return fail(KQFT_EINVAL, "channel must be 0, 1 or 2");
   if (pi_kind != KQFT_PI_GG && pi_kind != KQFT_PI_DOT) return fail(KQFT_EINVAL, "unknown bubble kind");
+  if (tails != 0 && (tails != 1 || pi_kind != KQFT_PI_GG))
+    return fail(KQFT_EINVAL, "tails must be 0 or 1, and 1 only for the bubble G G");
   const kqft_mgrid g = left->grid;
   if (g.M < 0 || g.N < 1 || Nq < 1) return fail(KQFT_ESHAPE, "need M >= 0, N >= 1, Nq >= 1");
   if (right->grid.M != g.M || right->grid.N != g.N || right->grid.T != g.T)
@@ -1411,6 +1450,48 @@ int kqft_bubble_matsubara(kqft_ctx* ctx, int channel, const kqft_mvertex* left, 
       launch_mf_epilogue(e, s);
     }
   }
+  if (tails) {  // the bare sum beyond each window, with the large-frequency vertices
+    std::vector<double2> t(nbos);
+    for (int m = -g.M; m <= g.M; ++m) {
+      const int sm = channel == KQFT_CH_P ? -m : m;
+      const int x = -2 * Nq - sm;
+      const int lo = x >= 0 ? (x + 1) / 2 : -((-x) / 2);
+      const int len = 2 * Nq - ((m & 1) ? 1 : 0);
+      std::complex<double> w = 0.0;
+      for (int k = lo; k < lo + len; ++k) {
+        const int k1 = channel == KQFT_CH_P ? k : k + m, k2 = channel == KQFT_CH_P ? m - k - 1 : k;
+        auto g0 = [&](int n) {
+          const double v = (2.0 * n + 1.0) * M_PI * g.T;
+          return 1.0 / std::complex<double>(0.0, v + (v > 0.0 ? G->Delta : -G->Delta));
+        };
+        w += g.T * g0(k1) * g0(k2);
+      }
+      const std::complex<double> tm = mf_bare_bubble_sum(channel, m, G->Delta, g.T) - w;
+      t[m + g.M] = make_double2(tm.real(), tm.imag());
+    }
+    if ((rc = ensure(ctx->mftail, (size_t)nbos * sizeof(double2)))) return rc;
+    HIP_TRY(hipMemcpyAsync(ctx->mftail.p, t.data(), t.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+    MTailArgs ta;
+    memset(&ta, 0, sizeof ta);
+    ta.M = g.M;
+    ta.N = g.N;
+    ta.t = (const double2*)ctx->mftail.p;
+    for (int u = 0; u < 4; ++u) {
+      ta.mix[u] = kMix[channel][u];
+      ta.unmix[u] = kUnmix[channel][u];
+    }
+    ta.UL = left->U;
+    ta.UR = right->U;
+    const kqft_chvert &cl = left->ch[channel], &cr = right->ch[channel];
+    ta.L = MChan{cl.coef, {(const double2*)cl.K1, (const double2*)cl.K2, (const double2*)cl.K2p, (const double2*)cl.K3}};
+    ta.R = MChan{cr.coef, {(const double2*)cr.K1, (const double2*)cr.K2, (const double2*)cr.K2p, (const double2*)cr.K3}};
+    ta.K[0] = (double2*)out->K1;
+    ta.K[1] = (double2*)out->K2;
+    ta.K[2] = (double2*)out->K2p;
+    ta.K[3] = (double2*)out->K3;
+    launch_mf_tail(ta, s);
+    HIP_TRY(hipStreamSynchronize(s));  // t lives on the host until the copy has run
+  }
   HIP_TRY(hipGetLastError());
   return KQFT_OK;
 }
@@ -1435,7 +1516,7 @@ int kqft_sde_matsubara(kqft_ctx* ctx, const kqft_mvertex* gamma, const kqft_mpro
   memset(&bare, 0, sizeof bare);
   bare.grid = g;
   bare.U = gamma->U;
-  if ((rc = kqft_bubble_matsubara(ctx, KQFT_CH_A, &bare, gamma, G, KQFT_PI_GG, Nq, &po, stream))) return rc;
+  if ((rc = kqft_bubble_matsubara(ctx, KQFT_CH_A, &bare, gamma, G, KQFT_PI_GG, Nq, 0, &po, stream))) return rc;
   MLoopArgs la;
   memset(&la, 0, sizeof la);
   la.M = g.M;
@@ -1512,7 +1593,7 @@ int kqft_parquet_solve_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U
   const kqft_mprop G0{Delta, nullptr, 0, nullptr};
   for (int r = 0; r < 3; ++r) {
     const kqft_chout o = chout(cls(xb, r, 0));
-    if ((rc = kqft_bubble_matsubara(ctx, r, &bare, &bare, &G0, KQFT_PI_GG, Nq, &o, stream))) return rc;
+    if ((rc = kqft_bubble_matsubara(ctx, r, &bare, &bare, &G0, KQFT_PI_GG, Nq, 0, &o, stream))) return rc;
   }
   if ((rc = kqft_sde_matsubara(ctx, &bare, &G0, Nq, Nl, (double*)xsig, stream))) return rc;
   kqft_mvertex V;
@@ -1538,8 +1619,8 @@ int kqft_parquet_solve_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U
       kqft_mvertex I = V;
       I.ch[r] = kqft_chvert{0.0, nullptr, nullptr, nullptr, nullptr};
       const kqft_chout o1 = chout(cls(gb, r, 0)), o2 = chout(tmp);
-      if ((rc = kqft_bubble_matsubara(ctx, r, &I, &V, &Gs, KQFT_PI_GG, Nq, &o1, stream))) return rc;
-      if ((rc = kqft_bubble_matsubara(ctx, r, &V, &I, &Gs, KQFT_PI_GG, Nq, &o2, stream))) return rc;
+      if ((rc = kqft_bubble_matsubara(ctx, r, &I, &V, &Gs, KQFT_PI_GG, Nq, 0, &o1, stream))) return rc;
+      if ((rc = kqft_bubble_matsubara(ctx, r, &V, &I, &Gs, KQFT_PI_GG, Nq, 0, &o2, stream))) return rc;
       const double2* k[2] = {cls(gb, r, 0), tmp};
       const double c[2] = {0.5, 0.5};
       lincomb_n(cls(gb, r, 0), nullptr, 2, k, c, chc, s);
@@ -1633,7 +1714,7 @@ int kqft_mfrg_flow_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, do
         for (int r = 0; r < 3; ++r) {
           const kqft_chout o = chout(ins(l, r));
           if (l == 0) {
-            if ((e = kqft_bubble_matsubara(ctx, r, &V, &V, &Gk, KQFT_PI_DOT, Nq, &o, stream))) return e;
+            if ((e = kqft_bubble_matsubara(ctx, r, &V, &V, &Gk, KQFT_PI_DOT, Nq, 0, &o, stream))) return e;
             continue;
           }
           kqft_mvertex rbar;
@@ -1642,8 +1723,8 @@ int kqft_mfrg_flow_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, do
           for (int r2 = 0; r2 < 3; ++r2)
             if (r2 != r) rbar.ch[r2] = chvert(1.0, ins(l - 1, r2));
           const kqft_chout o1 = chout(t1);
-          if ((e = kqft_bubble_matsubara(ctx, r, &rbar, &V, &Gk, KQFT_PI_GG, Nq, &o, stream))) return e;
-          if ((e = kqft_bubble_matsubara(ctx, r, &V, &rbar, &Gk, KQFT_PI_GG, Nq, &o1, stream))) return e;
+          if ((e = kqft_bubble_matsubara(ctx, r, &rbar, &V, &Gk, KQFT_PI_GG, Nq, 0, &o, stream))) return e;
+          if ((e = kqft_bubble_matsubara(ctx, r, &V, &rbar, &Gk, KQFT_PI_GG, Nq, 0, &o1, stream))) return e;
           add_into(ins(l, r), t1, chc);
           if (l >= 2) {  // centre: B_r(Gamma, B_r(gdot_rbar^(l-2), Gamma))
             kqft_mvertex rbar2;
@@ -1652,12 +1733,12 @@ int kqft_mfrg_flow_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, do
             for (int r2 = 0; r2 < 3; ++r2)
               if (r2 != r) rbar2.ch[r2] = chvert(1.0, ins(l - 2, r2));
             const kqft_chout o2 = chout(t2);
-            if ((e = kqft_bubble_matsubara(ctx, r, &rbar2, &V, &Gk, KQFT_PI_GG, Nq, &o2, stream))) return e;
+            if ((e = kqft_bubble_matsubara(ctx, r, &rbar2, &V, &Gk, KQFT_PI_GG, Nq, 0, &o2, stream))) return e;
             kqft_mvertex inner;
             memset(&inner, 0, sizeof inner);
             inner.grid = g;
             inner.ch[r] = chvert(1.0, t2);
-            if ((e = kqft_bubble_matsubara(ctx, r, &V, &inner, &Gk, KQFT_PI_GG, Nq, &o1, stream))) return e;
+            if ((e = kqft_bubble_matsubara(ctx, r, &V, &inner, &Gk, KQFT_PI_GG, Nq, 0, &o1, stream))) return e;
             add_into(ins(l, r), t1, chc);
             if (corr && r < 2) {
               if (l == 2) {

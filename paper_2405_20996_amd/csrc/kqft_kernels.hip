@@ -2299,6 +2299,61 @@ void launch_mf_loop(const MLoopArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(mf_loop_kernel, dim3((unsigned)((2 * a.N + 255) / 256)), dim3(256), 0, s, a);
 }
 
+__global__ __launch_bounds__(256) void mf_tail_kernel(MTailArgs a) {
+  const int R = 2 * a.N + 1, nf = 2 * a.N;
+  const long per = (long)R * R;
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nbos = 2L * a.M + 1;
+  if (tid >= per * nbos) return;
+  const int im = (int)(tid / per), rem = (int)(tid - (long)im * per), i = rem / R, j = rem - i * R;
+  const int m = im - a.M;
+  // left row: K2(m, n_i) for i < 2N, Gamma_0 + K1(m) on the border; right column alike with K2'
+  double2 lxy[2] = {czero(), czero()}, rxy[2] = {czero(), czero()};
+  if (i < nf) {
+    mf_chan(a.L, a.M, a.N, m, i - a.N, 0, 2, lxy);
+  } else {
+    lxy[0] = make_double2(-a.UL, 0.0);
+    lxy[1] = make_double2(a.UL, 0.0);
+    mf_chan(a.L, a.M, a.N, m, 0, 0, 1, lxy);
+  }
+  if (j < nf) {
+    mf_chan(a.R, a.M, a.N, m, 0, j - a.N, 4, rxy);
+  } else {
+    rxy[0] = make_double2(-a.UR, 0.0);
+    rxy[1] = make_double2(a.UR, 0.0);
+    mf_chan(a.R, a.M, a.N, m, 0, 0, 1, rxy);
+  }
+  double2 P[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const double2 l = cadd(cscale(a.mix[2 * c], lxy[0]), cscale(a.mix[2 * c + 1], lxy[1]));
+    const double2 r = cadd(cscale(a.mix[2 * c], rxy[0]), cscale(a.mix[2 * c + 1], rxy[1]));
+    P[c] = cmul(cmul(l, a.t[im]), r);
+  }
+  const double2 XY[2] = {cadd(cscale(a.unmix[0], P[0]), cscale(a.unmix[1], P[1])),
+                         cadd(cscale(a.unmix[2], P[0]), cscale(a.unmix[3], P[1]))};
+  const size_t nb = (size_t)nbos;
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp) {
+    double2* o;
+    if (i < nf && j < nf) {
+      o = a.K[3] + ((sp * nb + im) * nf + i) * nf + j;
+    } else if (i < nf) {
+      o = a.K[1] + (sp * nb + im) * nf + i;
+    } else if (j < nf) {
+      o = a.K[2] + (sp * nb + im) * nf + j;
+    } else {
+      o = a.K[0] + sp * nb + im;
+    }
+    *o = cadd(*o, XY[sp]);
+  }
+}
+
+void launch_mf_tail(const MTailArgs& a, hipStream_t s) {
+  const long total = (long)(2 * a.N + 1) * (2 * a.N + 1) * (2L * a.M + 1);
+  hipLaunchKernelGGL(mf_tail_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);
+}
+
 void launch_mf_left(const MGatherArgs& a, hipStream_t s) {
   const long total = (long)(2 * a.N + 1) * (2 * a.Nq) * a.nb;
   hipLaunchKernelGGL(mf_left_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);

@@ -281,6 +281,18 @@ void launch_mf_loop(const MLoopArgs& a, hipStream_t s);
 // [-Nl, Nl), the full vertex of v (bare part, all channels and classes), X = G, S or G
 // Sigma_dot G (line 0, 1, 2); v.r = 0
 void launch_mf_vloop(const MGatherArgs& v, int line, int Nl, double2* out, hipStream_t s);
+// analytic tails of a Matsubara bubble: adds, per m, the bubble of the large-frequency vertices
+// (left Gamma_0 + K1 + K2(m, n), right Gamma_0 + K1 + K2'(m, n') of channel r) with the scalar
+// t(m) (the bare sum beyond the window) to the four classes; v0 / v1 carry the two sides
+struct MTailArgs {
+  int M, N;
+  const double2* t;  // [2M + 1]
+  double mix[4], unmix[4];
+  double UL, UR;
+  MChan L, R;  // channel r of each side
+  double2* K[4];
+};
+void launch_mf_tail(const MTailArgs& a, hipStream_t s);
 void launch_mf_left(const MGatherArgs& a, hipStream_t s);
 void launch_mf_right(const MGatherArgs& a, hipStream_t s);
 void launch_mf_epilogue(const MEpiArgs& a, hipStream_t s);

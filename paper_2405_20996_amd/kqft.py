@@ -125,7 +125,7 @@ def lib():
         _lib.kqft_chi.argtypes = [C.c_void_p, C.c_int, P(KqftVertex), P(KqftPropagator), P(KqftQuad), C.c_void_p,
                                   C.c_void_p]
         _lib.kqft_bubble_matsubara.argtypes = [C.c_void_p, C.c_int, P(KqftMVertex), P(KqftMVertex), P(KqftMProp),
-                                               C.c_int, C.c_int, P(KqftChout), C.c_void_p]
+                                               C.c_int, C.c_int, C.c_int, P(KqftChout), C.c_void_p]
         _lib.kqft_loop_matsubara.argtypes = [C.c_void_p, P(KqftMVertex), P(KqftMProp), C.c_int, C.c_int, C.c_void_p,
                                              C.c_void_p]
         _lib.kqft_mfrg_flow_matsubara.argtypes = [C.c_void_p, P(KqftMGrid), C.c_double, C.c_double, C.c_double,
@@ -416,10 +416,10 @@ def _mprop(Delta: float, sigma: Optional[torch.Tensor], dsigma: Optional[torch.T
 
 def bubble_matsubara(channel: int, left: MVertex, right: MVertex, Delta: float, Nq: int,
                      sigma: Optional[torch.Tensor] = None, out: Optional[Channel] = None, pi_kind: int = PI_GG,
-                     dsigma: Optional[torch.Tensor] = None, stream=None) -> Channel:
+                     dsigma: Optional[torch.Tensor] = None, tails: bool = False, stream=None) -> Channel:
     """B_channel(left, right) in the Matsubara formalism (sum over 2 Nq fermionic frequencies about
     the bubble's centre); sigma: Sigma(i nu_n) on n in [-Ns, Ns) (length 2 Ns) or None; pi_kind
-    PI_DOT: Pi_dot along S = dG/dDelta (+ G dsigma G)."""
+    PI_DOT: Pi_dot along S = dG/dDelta (+ G dsigma G); tails: the analytic tails beyond the window."""
     g = left.grid
     dev = torch.device("cuda", torch.cuda.current_device())
     if out is None:
@@ -428,7 +428,7 @@ def bubble_matsubara(channel: int, left: MVertex, right: MVertex, Delta: float, 
     oc = KqftChout(*[_ptr(getattr(out, c), g.shape(c), f"out.{c}") for c in CLASSES])
     lc, rc = left.c(), right.c()
     _check(lib().kqft_bubble_matsubara(ctx(), channel, C.byref(lc), C.byref(rc), C.byref(gp), pi_kind, Nq,
-                                       C.byref(oc), _stream(stream)))
+                                       int(tails), C.byref(oc), _stream(stream)))
     return out
 
 
