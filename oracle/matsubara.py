@@ -471,3 +471,22 @@ def mfrg_flow(grid: MGrid, U: float, lam_i: float, lam_f: float, steps: int, nlo
                         steps)
     ch, sg = state_unpack(grid, y)
     return ch, np.array(sg)
+
+
+# ------------------------------------------------------------------ susceptibilities
+def chi(r: int, V: MVertex, P: MProp, Nq: int) -> np.ndarray:
+    """Susceptibility of channel r in the Matsubara formalism (Sec. Susceptibilities: the bubble
+    plus bubble, vertex, bubble): chi_r^c(m) = T sum_k Pi_r(m, k) + T^2 sum_{k,l} Pi_r(m, k)
+    Gamma_r^c(m; k, l) Pi_r(m, l) over the bubble's window, for the channel's two spin
+    combinations c (a: X, X + 2Y; p: X + Y, X - Y; t: Y, 2X + Y).  [2, 2M + 1]."""
+    g = V.grid
+    combos = {0: ((1, 0), (1, 2)), 1: ((1, 1), (1, -1)), 2: ((0, 1), (2, 1))}[r]
+    out = np.zeros((2, 2 * g.M + 1), dtype=np.complex128)
+    for im, m in enumerate(range(-g.M, g.M + 1)):
+        k = window(r, m, Nq)
+        pi = pi_r(r, P, m, k)
+        XY = vertex_eval(V, r, m, k[:, None], k[None, :])
+        for c, (cx, cy) in enumerate(combos):
+            gam = cx * XY[0] + cy * XY[1]
+            out[c, im] = pi.sum() + pi @ gam @ pi
+    return out

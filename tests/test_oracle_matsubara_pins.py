@@ -254,3 +254,27 @@ def test_analytic_tails_make_the_bubble_independent_of_the_window():
                 assert np.abs(getattr(with_t, x) - getattr(ref, x)).max() < 1e-13 * scale, (r, Nq, x)
             assert max(np.abs(getattr(without, x) - getattr(ref, x)).max() / np.abs(getattr(ref, x)).max()
                        for x in MF.CLASSES) > 0.05
+
+
+def test_matsubara_chi_factorises_for_the_bare_vertex_and_diagonalises_the_bubble():
+    """With Gamma = Gamma_0 the double sum factorises, chi_r^c = S_r + S_r Gamma_0^c S_r with
+    S_r = chi_r at U = 0 = T sum_k Pi_r, and the one-loop K1 class of the bubble is
+    pref_r Gamma_0^c S_r Gamma_0^c (prefactors +1, 1/2, -1) only for the channel's own spin
+    combinations; at particle-hole symmetry S_p = -S_a."""
+    g = MF.MGrid(4, 3, T)
+    P = MF.MProp(D, T)
+    g0, zero = MF.bare(g, U), MF.bare(g, 0.0)
+    combos = {0: ((1, 0), (1, 2)), 1: ((1, 1), (1, -1)), 2: ((0, 1), (2, 1))}
+    pref = (1.0, 0.5, -1.0)
+    Ss = {}
+    for r in range(3):
+        S = MF.chi(r, zero, P, 7)
+        assert np.abs(S[0] - S[1]).max() == 0.0
+        Ss[r] = S[0]
+        ch = MF.chi(r, g0, P, 7)
+        K1 = MF.bubble(r, g0, g0, P, 7).K1
+        for c, (mx, my) in enumerate(combos[r]):
+            G0c = mx * (-U) + my * U
+            assert np.abs(ch[c] - (S[0] + S[0] * G0c * S[0])).max() < 1e-14
+            assert np.abs((mx * K1[0] + my * K1[1]) - pref[r] * G0c * S[0] * G0c).max() < 1e-14
+    assert np.abs(Ss[1] + Ss[0]).max() < 1e-14
