@@ -313,6 +313,16 @@ int kqft_loop_matsubara(kqft_ctx* ctx, const kqft_mvertex* gamma, const kqft_mpr
                         double* out, void* stream);
 
 /*
+ * kqft_chi_matsubara -- susceptibility of channel r (`channel`) in the Matsubara formalism:
+ *   chi_r^c(m) = T sum_k Pi_r(m, k) + T^2 sum_{k,l} Pi_r(m, k) Gamma_r^c(m; k, l) Pi_r(m, l)
+ * over the bubble's window (Nq), the full vertex in channel r's parameters and spin combination
+ * c (a: X, X + 2Y; p: X + Y, X - Y; t: Y, 2X + Y).  chi: device [2][2M + 1] complex.  FP64.
+ * KQFT_ESHAPE also for Nq > 16384 (the pair count is indexed in 32 bits).
+ */
+int kqft_chi_matsubara(kqft_ctx* ctx, int channel, const kqft_mvertex* gamma, const kqft_mprop* G, int Nq,
+                       double* chi, void* stream);
+
+/*
  * kqft_mfrg_flow_matsubara -- the mfRG flow (Sec. "mfRG") in the Matsubara formalism with the
  * hybridization as flow parameter (Delta from Lambda_i to Lambda_f; the ODE in t with
  * Delta = 5 t|t| / sqrt(1 - t^2), classical RK4 in `steps` equal steps):

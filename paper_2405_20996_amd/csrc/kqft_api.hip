@@ -1374,6 +1374,22 @@ static double mf_bare_bubble_sum(int r, int m, double Delta, double T) {
   return r == KQFT_CH_P ? -sa : sa;
 }
 
+int kqft_chi_matsubara(kqft_ctx* ctx, int channel, const kqft_mvertex* gamma, const kqft_mprop* G, int Nq,
+                       double* chi, void* stream) {
+  int rc;
+  if (!ctx) return fail(KQFT_EINVAL, "ctx is NULL");
+  if (!gamma || !G || !chi) return fail(KQFT_EINVAL, "vertex, propagator and chi must be given");
+  if (channel < KQFT_CH_A || channel > KQFT_CH_T) return fail(KQFT_EINVAL, "channel must be 0, 1 or 2");
+  if (gamma->grid.M < 0 || gamma->grid.N < 1 || Nq < 1) return fail(KQFT_ESHAPE, "need M >= 0, N >= 1, Nq >= 1");
+  if (Nq > 16384) return fail(KQFT_ESHAPE, "chi needs Nq <= 16384");
+  if (!(gamma->grid.T > 0)) return fail(KQFT_EINVAL, "T must be positive");
+  if ((rc = check_mprop(*G))) return rc;
+  HIP_TRY(hipSetDevice(ctx->device));
+  launch_mf_chi(mf_side(gamma->grid, channel, 0, Nq, *gamma, *G), (double2*)chi, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return KQFT_OK;
+}
+
 int kqft_bubble_matsubara(kqft_ctx* ctx, int channel, const kqft_mvertex* left, const kqft_mvertex* right,
                           const kqft_mprop* G, int pi_kind, int Nq, int tails, const kqft_chout* out, void* stream) {
   int rc;

@@ -2349,6 +2349,52 @@ __global__ __launch_bounds__(256) void mf_tail_kernel(MTailArgs a) {
   }
 }
 
+__global__ __launch_bounds__(256) void mf_chi_kernel(MGatherArgs a, double2* out) {
+  const int im = blockIdx.x, m = im - a.M;
+  const int lo = mf_window_lo(a.r, m, a.Nq), len = mf_window_len(m, a.Nq);
+  auto pi = [&](int k) {
+    const int nq = lo + k;
+    const int k1 = a.r == 1 ? nq : nq + m, k2 = a.r == 1 ? m - nq - 1 : nq;
+    return cscale(a.T, cmul(mf_G(a, k1), mf_G(a, k2)));
+  };
+  double2 acc[2] = {czero(), czero()};
+  const int pairs = len * len;
+  for (int t = threadIdx.x; t < pairs; t += blockDim.x) {
+    const int k = t / len, l = t - k * len;
+    double2 XY[2] = {make_double2(-a.U, 0.0), make_double2(a.U, 0.0)};
+    mf_chan(a.ch[a.r], a.M, a.N, m, lo + k, lo + l, 15, XY);
+    mf_others(a, m, lo + k, lo + l, XY);
+    const double2 pp = cmul(pi(k), pi(l));
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+      acc[c] = cadd(acc[c], cmul(pp, cadd(cscale(a.mix[2 * c], XY[0]), cscale(a.mix[2 * c + 1], XY[1]))));
+  }
+  for (int t = threadIdx.x; t < len; t += blockDim.x) {  // the bare term T sum_k Pi
+    const double2 p = pi(t);
+    acc[0] = cadd(acc[0], p);
+    acc[1] = cadd(acc[1], p);
+  }
+  __shared__ double2 red[2][256];
+  red[0][threadIdx.x] = acc[0];
+  red[1][threadIdx.x] = acc[1];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      red[0][threadIdx.x] = cadd(red[0][threadIdx.x], red[0][threadIdx.x + w]);
+      red[1][threadIdx.x] = cadd(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[im] = red[0][0];
+    out[(2 * a.M + 1) + im] = red[1][0];
+  }
+}
+
+void launch_mf_chi(const MGatherArgs& v, double2* out, hipStream_t s) {
+  hipLaunchKernelGGL(mf_chi_kernel, dim3((unsigned)(2 * v.M + 1)), dim3(256), 0, s, v, out);
+}
+
 void launch_mf_tail(const MTailArgs& a, hipStream_t s) {
   const long total = (long)(2 * a.N + 1) * (2 * a.N + 1) * (2L * a.M + 1);
   hipLaunchKernelGGL(mf_tail_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);

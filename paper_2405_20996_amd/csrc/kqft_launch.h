@@ -293,6 +293,9 @@ struct MTailArgs {
   double2* K[4];
 };
 void launch_mf_tail(const MTailArgs& a, hipStream_t s);
+// chi_r^c(m) = T sum_k Pi(m, k) + T^2 sum_{k,l} Pi(m, k) Gamma_r^c(m; k, l) Pi(m, l) over channel
+// r's window for every m in [-M, M]: one workgroup per m, fixed reduction order; out [2][2M+1]
+void launch_mf_chi(const MGatherArgs& v, double2* out, hipStream_t s);
 void launch_mf_left(const MGatherArgs& a, hipStream_t s);
 void launch_mf_right(const MGatherArgs& a, hipStream_t s);
 void launch_mf_epilogue(const MEpiArgs& a, hipStream_t s);

@@ -126,6 +126,8 @@ def lib():
                                   C.c_void_p]
         _lib.kqft_bubble_matsubara.argtypes = [C.c_void_p, C.c_int, P(KqftMVertex), P(KqftMVertex), P(KqftMProp),
                                                C.c_int, C.c_int, C.c_int, P(KqftChout), C.c_void_p]
+        _lib.kqft_chi_matsubara.argtypes = [C.c_void_p, C.c_int, P(KqftMVertex), P(KqftMProp), C.c_int, C.c_void_p,
+                                            C.c_void_p]
         _lib.kqft_loop_matsubara.argtypes = [C.c_void_p, P(KqftMVertex), P(KqftMProp), C.c_int, C.c_int, C.c_void_p,
                                              C.c_void_p]
         _lib.kqft_mfrg_flow_matsubara.argtypes = [C.c_void_p, P(KqftMGrid), C.c_double, C.c_double, C.c_double,
@@ -429,6 +431,19 @@ def bubble_matsubara(channel: int, left: MVertex, right: MVertex, Delta: float, 
     lc, rc = left.c(), right.c()
     _check(lib().kqft_bubble_matsubara(ctx(), channel, C.byref(lc), C.byref(rc), C.byref(gp), pi_kind, Nq,
                                        int(tails), C.byref(oc), _stream(stream)))
+    return out
+
+
+def chi_matsubara(channel: int, gamma: MVertex, Delta: float, Nq: int, sigma: Optional[torch.Tensor] = None,
+                  stream=None) -> torch.Tensor:
+    """Susceptibility of one channel in the Matsubara formalism: [2 (combinations), 2M + 1]."""
+    g = gamma.grid
+    out = torch.zeros((2, 2 * g.M + 1), dtype=torch.complex128,
+                      device=torch.device("cuda", torch.cuda.current_device()))
+    gp = _mprop(Delta, sigma, None)
+    vc = gamma.c()
+    _check(lib().kqft_chi_matsubara(ctx(), channel, C.byref(vc), C.byref(gp), Nq, C.c_void_p(out.data_ptr()),
+                                    _stream(stream)))
     return out
 
 

@@ -263,3 +263,29 @@ def test_matsubara_bubble_with_analytic_tails_matches_oracle(r):
     assert float((a - b).abs().max()) < 1e-13 * float(b.abs().max())
     with pytest.raises(K.KqftError):
         K.bubble_matsubara(r, k0, k0, D, 2, tails=True, pi_kind=K.PI_DOT)
+
+
+@pytest.mark.parametrize("r", [0, 1, 2])
+@pytest.mark.parametrize("M,N,Nq", [(5, 6, 9), (0, 1, 1), (3, 2, 40)])
+def test_matsubara_chi_matches_oracle(r, M, N, Nq):
+    """chi_r^c(m) for a random vertex (every class and channel non-zero) and a dynamic
+    self-energy in G, against the oracle to 1e-12; the largest case spans more pairs per m
+    than one workgroup holds."""
+    K = _K()
+    ov, kv = _pair(M, N, 40 + r)
+    Ns = N + 2
+    sig = 0.15 * np.exp(1j * np.linspace(0.0, 2.0, 2 * Ns)) - 0.05j
+    ref = MF.chi(r, ov, MF.MProp(D, T, sig), Nq)
+    out = K.chi_matsubara(r, kv, D, Nq, sigma=to_dev(sig))
+    torch.cuda.synchronize()
+    e = _rel(out.cpu().numpy(), ref)
+    assert e < 1e-12, e
+
+
+def test_matsubara_chi_errors():
+    K = _K()
+    _, kv = _pair(2, 2, 3)
+    with pytest.raises(K.KqftError):
+        K.chi_matsubara(3, kv, D, 4)
+    with pytest.raises(K.KqftError):
+        K.chi_matsubara(0, kv, D, 0)
