@@ -101,12 +101,13 @@ typedef struct {
   const double* K2p;
   const double* K3;
 } OCh;
-// vertex = Gamma_0(r0) + sum_r coef_r gamma_r, all classes on one tangent grid (n, L, a)
+// vertex = Gamma_0(r0) + sum_r coef_r gamma_r, all classes on one grid (n, L, a, map)
 typedef struct {
   double r0, dr0;
   int n;
   double L, a;
   OCh ch[3];
+  int map;
 } OVert;
 // propagator: G^R = 1/(v - eps + i Delta - Sigma^R(v)),
 // G^K = G^R [Sigma^K - 2 i Delta tanh(v/2T)] G^A; Sigma optional on its own grid.
@@ -127,6 +128,7 @@ typedef struct {
   const double* dSigR;
   const double* dSigK;
   double deps;
+  int smap;  // map of the Sigma grid
 } OProp;
 // quadrature: n Gauss-Legendre nodes, map 0 = tangent onto [-L, L] with scale a,
 // map 1 = v = a tan(pi y / 2) onto the real line.
@@ -137,19 +139,38 @@ typedef struct {
 }
 
 // ---------------------------------------------------------------- grids
+// Sec. "Frequency grids": an equidistant auxiliary variable mapped to frequencies.
+// map 0 (tangent): v = a tan(W); map 1 (the paper's non-linear map): v = a W |W| / sqrt(1 - W^2),
+// W in (-1, 1).  Both are odd and increasing; the grid takes W_i = x_i theta with x_i
+// equidistant in [-1, 1] and theta the W of v = L.
+static double map_forward(int map, double W) {
+  if (map == 0) return std::tan(W);
+  return W * std::fabs(W) / std::sqrt(1.0 - W * W);
+}
+// inverse of map_forward for y = v/a: map 1 solves y^2 (1 - W^2) = W^4 for W^2 (the positive
+// root of the quadratic u^2 + y^2 u - y^2, written as 2|y| / (|y| + sqrt(y^2 + 4)))
+static double map_inverse(int map, double y) {
+  if (map == 0) return std::atan(y);
+  const double ay = std::fabs(y);
+  const double u = 2.0 * ay / (ay + std::sqrt(ay * ay + 4.0));
+  return y < 0 ? -std::sqrt(u) : std::sqrt(u);
+}
 struct Grid {
   int n;
   double L, a, theta;
+  int map;
 };
-static Grid make_grid(int n, double L, double a) { return Grid{n, L, a, std::atan(L / a)}; }
+static Grid make_grid(int n, double L, double a, int map = 0) {
+  return Grid{n, L, a, map_inverse(map, L / a), map};
+}
 static double grid_node(const Grid& g, int i) {
   double x = -1.0 + 2.0 * i / (g.n - 1);
-  return g.a * std::tan(x * g.theta);
+  return g.a * map_forward(g.map, x * g.theta);
 }
-// Locate v on the auxiliary variable x = atan(v/a)/theta; false if outside [-L, L]
+// Locate v on the auxiliary variable x = W(v/a)/theta; false if outside [-L, L]
 // (with a relative tolerance of 1e-10 on x so that grid end points count as inside).
 static bool grid_locate(const Grid& g, double v, int& i0, double& t) {
-  double x = std::atan(v / g.a) / g.theta;
+  double x = map_inverse(g.map, v / g.a) / g.theta;
   if (x > 1.0 + 1e-10 || x < -1.0 - 1e-10) return false;
   if (x > 1.0) x = 1.0;
   if (x < -1.0) x = -1.0;
@@ -222,7 +243,7 @@ template <class S>
 static Cx<S> sigma_interp(const OProp& P, const double* arr, double v) {
   Cx<S> z = czero<S>();
   if (!arr) return z;
-  Grid g = make_grid(P.sn, P.sL, P.sa);
+  Grid g = make_grid(P.sn, P.sL, P.sa, P.smap);
   int i0;
   double t;
   if (!grid_locate(g, v, i0, t)) return z;
@@ -392,7 +413,7 @@ template <> Dual param_r0<Dual>(const OVert& V) { return Dual{V.r0, V.dr0}; }
 template <class S> static Vtx<S> make_vtx(const OVert& V) {
   Vtx<S> o;
   o.r0 = param_r0<S>(V);
-  o.g = make_grid(V.n, V.L, V.a);
+  o.g = make_grid(V.n, V.L, V.a, V.map);
   for (int r = 0; r < 3; ++r) {
     o.coef[r] = V.ch[r].coef;
     o.K[r][0] = (const Cx<S>*)V.ch[r].K1;
@@ -943,8 +964,8 @@ static void chi_full(const OVert& Gv, const OProp& P, const OQuad& q, Cx<S>* out
 // ---------------------------------------------------------------- C ABI
 extern "C" {
 
-void oracle_grid_nodes(int n, double L, double a, double* nodes) {
-  Grid g = make_grid(n, L, a);
+void oracle_grid_nodes(int n, double L, double a, int map, double* nodes) {
+  Grid g = make_grid(n, L, a, map);
   for (int i = 0; i < n; ++i) nodes[i] = grid_node(g, i);
 }
 void oracle_gauss_legendre(int n, double* x, double* w) { gauss_legendre(n, x, w); }
@@ -956,8 +977,8 @@ void oracle_quad(const OQuad* q, double* nodes, double* weights) {
     weights[k] = w[k];
   }
 }
-int oracle_grid_locate(int n, double L, double a, double v, int* i0, double* t) {
-  Grid g = make_grid(n, L, a);
+int oracle_grid_locate(int n, double L, double a, int map, double v, int* i0, double* t) {
+  Grid g = make_grid(n, L, a, map);
   return grid_locate(g, v, *i0, *t) ? 1 : 0;
 }
 

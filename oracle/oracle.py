@@ -46,14 +46,14 @@ class OCh(C.Structure):
 
 class OVert(C.Structure):
     _fields_ = [("r0", C.c_double), ("dr0", C.c_double), ("n", C.c_int), ("L", C.c_double),
-                ("a", C.c_double), ("ch", OCh * 3)]
+                ("a", C.c_double), ("ch", OCh * 3), ("map", C.c_int)]
 
 
 class OProp(C.Structure):
     _fields_ = [("Delta", C.c_double), ("dDelta", C.c_double), ("T", C.c_double), ("eps", C.c_double),
                 ("sn", C.c_int), ("sL", C.c_double), ("sa", C.c_double),
                 ("SigR", C.c_void_p), ("SigK", C.c_void_p), ("reg", C.c_int), ("lam", C.c_double),
-                ("dSigR", C.c_void_p), ("dSigK", C.c_void_p), ("deps", C.c_double)]
+                ("dSigR", C.c_void_p), ("dSigK", C.c_void_p), ("deps", C.c_double), ("smap", C.c_int)]
 
 
 class OQuad(C.Structure):
@@ -68,11 +68,11 @@ def lib():
     if _lib is None:
         _lib = C.CDLL(build())
         P = C.POINTER
-        _lib.oracle_grid_nodes.argtypes = [C.c_int, C.c_double, C.c_double, C.c_void_p]
+        _lib.oracle_grid_nodes.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, C.c_void_p]
         _lib.oracle_gauss_legendre.argtypes = [C.c_int, C.c_void_p, C.c_void_p]
         _lib.oracle_quad.argtypes = [P(OQuad), C.c_void_p, C.c_void_p]
-        _lib.oracle_grid_locate.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, P(C.c_int),
-                                            P(C.c_double)]
+        _lib.oracle_grid_locate.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double,
+                                            P(C.c_int), P(C.c_double)]
         _lib.oracle_propagator.argtypes = [C.c_int, P(OProp), C.c_int, C.c_int, C.c_void_p, C.c_void_p]
         _lib.oracle_bubble_pi.argtypes = [C.c_int, P(OProp), C.c_int, C.c_int, C.c_double, C.c_double,
                                           C.c_void_p]
@@ -98,14 +98,17 @@ def lib():
 # ------------------------------------------------------------------ data model
 @dataclass
 class Grid:
-    """Tangent grid v_i = a tan(x_i atan(L/a)), x_i equidistant in [-1, 1]."""
+    """Frequency grid (Sec. "Frequency grids"): x_i equidistant in [-1, 1], W_i = x_i theta with
+    theta the auxiliary value of L.  map 0: v = a tan(W); map 1 (the paper's non-linear map):
+    v = a W |W| / sqrt(1 - W^2)."""
     n: int
     L: float = 20.0
     a: float = 1.0
+    map: int = 0
 
     def nodes(self) -> np.ndarray:
         out = np.zeros(self.n)
-        lib().oracle_grid_nodes(self.n, self.L, self.a, out.ctypes.data)
+        lib().oracle_grid_nodes(self.n, self.L, self.a, self.map, out.ctypes.data)
         return out
 
 
@@ -161,7 +164,7 @@ class Prop:
     def c(self, keep: list) -> OProp:
         g = self.sigma_grid or Grid(2)
         p = OProp(self.Delta, self.dDelta, self.T, self.eps, g.n, g.L, g.a, None, None, self.reg, self.lam,
-                  None, None, self.deps)
+                  None, None, self.deps, g.map)
         if (self.dSigR is None) != (self.dSigK is None):
             raise ValueError("Sigma_dot needs both its retarded and its Keldysh component")
         for name in ("SigR", "SigK", "dSigR", "dSigK"):
@@ -201,6 +204,7 @@ class Vertex:
     def c(self, keep: list) -> OVert:
         v = OVert()
         v.r0, v.dr0, v.n, v.L, v.a = self.r0, self.dr0, self.grid.n, self.grid.L, self.grid.a
+        v.map = self.grid.map
         for r in range(3):
             chn = self.ch[r]
             v.ch[r].coef = chn.coef

@@ -88,12 +88,12 @@ def test_grid_map_and_locate():
     assert np.all(np.diff(v) > 0) and np.allclose(v, -v[::-1], atol=1e-13)
     i0, t = O.C.c_int(), O.C.c_double()
     for i in (0, 7, 29, 30):
-        assert O.lib().oracle_grid_locate(31, 20.0, 1.0, v[i], O.C.byref(i0), O.C.byref(t)) == 1
+        assert O.lib().oracle_grid_locate(31, 20.0, 1.0, 0, v[i], O.C.byref(i0), O.C.byref(t)) == 1
         assert i0.value + t.value == pytest.approx(i, abs=1e-9)
-    assert O.lib().oracle_grid_locate(31, 20.0, 1.0, 20.5, O.C.byref(i0), O.C.byref(t)) == 0
+    assert O.lib().oracle_grid_locate(31, 20.0, 1.0, 0, 20.5, O.C.byref(i0), O.C.byref(t)) == 0
     # the interpolation variable is the auxiliary x: a point halfway in x gets t = 1/2
     x_mid = (-1 + 2 * 3.5 / 30) * np.arctan(20.0)
-    O.lib().oracle_grid_locate(31, 20.0, 1.0, np.tan(x_mid), O.C.byref(i0), O.C.byref(t))
+    O.lib().oracle_grid_locate(31, 20.0, 1.0, 0, np.tan(x_mid), O.C.byref(i0), O.C.byref(t))
     assert i0.value == 3 and t.value == pytest.approx(0.5, abs=1e-12)
 
 
