@@ -29,9 +29,13 @@
  *   Keldysh 4x4 pair order (row pair | column pair), pair = 2*first + second,
  *     flat index 4*row + col:  a (a1',a2 | a1,a2'), p (a1',a2' | a1,a2),
  *     t (a2',a2 | a1',a1).
- *   Frequency grid (Sec. "Frequency grids", tangent reading): v_i =
- *     a*tan(x_i*atan(L/a)), x_i = -1 + 2i/(n-1); all classes share one grid.
- *   Interpolation: linear in x = atan(v/a)/atan(L/a) per axis (the paper's
+ *   Frequency grids (Sec. "Frequency grids"): n nodes equidistant in an
+ *     auxiliary variable x_i = -1 + 2i/(n-1) mapped onto [-L, L]; all classes
+ *     share one grid.  map KQFT_GRID_TAN: v_i = a*tan(x_i*atan(L/a));
+ *     map KQFT_GRID_ALGEBRAIC (the paper's non-linear grid): v = a W|W|/sqrt(1-W^2)
+ *     at W_i = W_L x_i, W_L < 1 the auxiliary value of v = L, so v ~ W^2 near zero
+ *     and the extent is finite.
+ *   Interpolation: linear in the auxiliary variable per axis (the paper's
  *     "linear_on_aux"); a class is zero where any argument lies outside [-L, L].
  *   Complex arrays: interleaved (re, im) doubles, C order, Keldysh innermost:
  *     K1[s][w][16], K2[s][w][v][16], K2p[s][w][v'][16], K3[s][w][v][v'][16],
@@ -96,10 +100,14 @@ enum { KQFT_K1 = 1, KQFT_K2 = 2, KQFT_K2P = 4, KQFT_K3 = 8, KQFT_KALL = 15 };
    (onto [-L, L]) or to v = a tan(pi y / 2) (onto the real line) */
 enum { KQFT_QUAD_TAN_FINITE = 0, KQFT_QUAD_TAN_INFINITE = 1 };
 
+/* frequency-grid maps (auxiliary variable -> frequency) */
+enum { KQFT_GRID_TAN = 0, KQFT_GRID_ALGEBRAIC = 1 };
+
 typedef struct {
   int n;    /* points, odd recommended (v = 0 is then a node), n >= 2 */
   double L; /* extent: nodes span [-L, L] */
-  double a; /* tangent-map scale */
+  double a; /* map scale */
+  int map;  /* KQFT_GRID_TAN (0, a zero-initialised grid) or KQFT_GRID_ALGEBRAIC */
 } kqft_grid;
 
 typedef struct {

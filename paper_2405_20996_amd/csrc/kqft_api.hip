@@ -38,7 +38,7 @@ struct DevBuf {
 
 struct kqft_ctx {
   int device = 0;
-  std::map<std::tuple<int, double, double>, double*> grids;
+  std::map<std::tuple<int, double, double, int>, double*> grids;
   std::map<std::tuple<int, int, double, double>, std::pair<double*, double*>> quads;
   DevBuf panels[2], pi[2], phi, chi_part, lstore[2][3], adj, tab[2][2];
   // internal streams (default priority, non-blocking): vertex gathers and GEMMs of
@@ -106,15 +106,19 @@ static void gl_nodes(int n, std::vector<double>& x, std::vector<double>& w) {
 }
 
 static int get_grid(kqft_ctx* ctx, const kqft_grid& g, const double** out) {
-  auto key = std::make_tuple(g.n, g.L, g.a);
+  auto key = std::make_tuple(g.n, g.L, g.a, g.map);
   auto it = ctx->grids.find(key);
   if (it != ctx->grids.end()) {
     *out = it->second;
     return KQFT_OK;
   }
   std::vector<double> v(g.n);
-  const double th = atan(g.L / g.a);
-  for (int i = 0; i < g.n; ++i) v[i] = g.a * tan((-1.0 + 2.0 * i / (g.n - 1)) * th);
+  const double th = aux_of(g.map, g.L / g.a);
+  for (int i = 0; i < g.n; ++i) v[i] = g.a * freq_of(g.map, (-1.0 + 2.0 * i / (g.n - 1)) * th);
+  // The algebraic map's inverse goes as sqrt(|v|) at zero, so a frequency sum that should
+  // vanish must vanish exactly: its nodes are made exactly odd.
+  if (g.map == KQFT_GRID_ALGEBRAIC)
+    for (int i = 0; i < g.n / 2; ++i) v[g.n - 1 - i] = -v[i];
   double* d = nullptr;
   HIP_TRY(hipMalloc(&d, sizeof(double) * g.n));
   HIP_TRY(hipMemcpy(d, v.data(), sizeof(double) * g.n, hipMemcpyHostToDevice));
@@ -184,17 +188,21 @@ static int init_tables() {
 }
 
 // ------------------------------------------------------------------ conversions
-static bool same_grid(const kqft_grid& a, const kqft_grid& b) { return a.n == b.n && a.L == b.L && a.a == b.a; }
+static bool same_grid(const kqft_grid& a, const kqft_grid& b) {
+  return a.n == b.n && a.L == b.L && a.a == b.a && a.map == b.map;
+}
 
 static int check_grid(const kqft_grid& g, const char* what) {
   if (g.n < 2 || !(g.L > 0) || !(g.a > 0)) return fail(KQFT_ESHAPE, std::string("invalid grid: ") + what);
+  if (g.map != KQFT_GRID_TAN && g.map != KQFT_GRID_ALGEBRAIC)
+    return fail(KQFT_EINVAL, std::string("unknown grid map: ") + what);
   return KQFT_OK;
 }
 
 static DVert to_dvert(const kqft_vertex& v) {
   DVert d;
   d.r0 = v.r0;
-  d.g = make_dgrid(v.grid.n, v.grid.L, v.grid.a);
+  d.g = make_dgrid(v.grid.n, v.grid.L, v.grid.a, v.grid.map);
   for (int r = 0; r < 3; ++r) {
     d.ch[r].coef = v.ch[r].coef;
     d.ch[r].K[0] = (const double2*)v.ch[r].K1;
@@ -228,9 +236,9 @@ static int to_dprop(const kqft_propagator& p, DProp& d) {
   if (p.SigR || p.SigK || p.dSigR) {
     int rc = check_grid(p.sgrid, "propagator self-energy grid");
     if (rc) return rc;
-    d.sg = make_dgrid(p.sgrid.n, p.sgrid.L, p.sgrid.a);
+    d.sg = make_dgrid(p.sgrid.n, p.sgrid.L, p.sgrid.a, p.sgrid.map);
   } else {
-    d.sg = make_dgrid(2, 1.0, 1.0);
+    d.sg = make_dgrid(2, 1.0, 1.0, 0);
   }
   return KQFT_OK;
 }
@@ -341,7 +349,7 @@ static GatherArgs make_gather(int r, int nb, int iw0, int nq, int nq_pad, int lo
   g.lo = lo;
   g.cnt = cnt;
   g.Kp = Kp;
-  g.g = make_dgrid(V.grid.n, V.grid.L, V.grid.a);
+  g.g = make_dgrid(V.grid.n, V.grid.L, V.grid.a, V.grid.map);
   g.r0 = V.r0;
   const kqft_chvert& c = V.ch[r];
   g.coef = c.coef;
@@ -664,7 +672,7 @@ static int chi_core(kqft_ctx* ctx, int r, const kqft_vertex& gamma, const DProp&
     ca.nq = nq;
     ca.nb = cnt;
     ca.iw0 = iw0;
-    ca.g = make_dgrid(n, gamma.grid.L, gamma.grid.a);
+    ca.g = make_dgrid(n, gamma.grid.L, gamma.grid.a, gamma.grid.map);
     ca.r0 = gamma.r0;
     const kqft_chvert& own = gamma.ch[r];
     ca.coef = own.coef;
@@ -714,7 +722,7 @@ static int sde_core(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagat
   if ((rc = get_quad(ctx, *q_loop, &qv, &qw))) return rc;
   DProp P;
   if ((rc = to_dprop(*G, P))) return rc;
-  LoopArgs la{make_dgrid(n, gamma->grid.L, gamma->grid.a), P, 0, q_loop->n, nodes, qv, qw, phiK1, phiK2p,
+  LoopArgs la{make_dgrid(n, gamma->grid.L, gamma->grid.a, gamma->grid.map), P, 0, q_loop->n, nodes, qv, qw, phiK1, phiK2p,
               (double2*)sigma};
   {
     ProfScope ps(ctx, 3, s);
@@ -914,7 +922,7 @@ static int vloop_core(kqft_ctx* ctx, const kqft_vertex& V, const kqft_propagator
     launch_table(ta, false, s);
     la.T[r2] = ctx->vtab[r2].p;
   }
-  la.g = make_dgrid((int)n, V.grid.L, V.grid.a);
+  la.g = make_dgrid((int)n, V.grid.L, V.grid.a, V.grid.map);
   la.P = P;
   la.kind = kind;
   la.nq = q.n;
@@ -2811,7 +2819,7 @@ int kqft_sde_adjoint(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propaga
   DProp P;
   if ((rc = to_dprop(*G, P))) return rc;
   HIP_TRY(hipMemsetAsync(ctx->phigrad.p, 0, k1b + k2b, s));
-  LoopAdjArgs la{make_dgrid(n, gamma->grid.L, gamma->grid.a), P, q_loop->n, nodes, qv, qw, phiK1, phiK2p,
+  LoopAdjArgs la{make_dgrid(n, gamma->grid.L, gamma->grid.a, gamma->grid.map), P, q_loop->n, nodes, qv, qw, phiK1, phiK2p,
                  (const double2*)dsigma, dK1, dK2p, dscal + 1};
   launch_loop_adjoint(la, s);
   // bubble adjoint of Phi: the bare vertex on the left carries gamma->r0 as well

@@ -21,25 +21,38 @@ __host__ __device__ inline double2 cfma(double s, double2 a, double2 acc) {
 __host__ __device__ inline double2 czero() { return make_double2(0.0, 0.0); }
 
 // ------------------------------------------------------------------ grids
-// Tangent grid v_i = a tan(x_i theta), theta = atan(L/a), x_i = -1 + 2i/(n-1).
+// Grids v_i = a f(x_i theta), x_i = -1 + 2i/(n-1), f(theta) = L/a.  map 0: f = tan;
+// map 1: f(W) = W|W|/sqrt(1 - W^2), the algebraic grid of Sec. "Frequency grids".
+// aux_of inverts f: W^2 = u solves u^2 + y^2 u - y^2 = 0, taken as 2|y|/(|y| + sqrt(y^2 + 4))
+// (no cancellation at large |y|).
+__host__ __device__ inline double aux_of(int map, double y) {
+  if (map == 0) return atan(y);
+  const double ay = fabs(y);
+  return copysign(sqrt(2.0 * ay / (ay + sqrt(ay * ay + 4.0))), y);
+}
+__host__ __device__ inline double freq_of(int map, double w) {
+  if (map == 0) return tan(w);
+  return w * fabs(w) / sqrt((1.0 - w) * (1.0 + w));
+}
 struct DGrid {
-  int n;
+  int n, map;
   double a, inv_a, inv_theta, half_nm1;
 };
-inline DGrid make_dgrid(int n, double L, double a) {
+inline DGrid make_dgrid(int n, double L, double a, int map) {
   DGrid g;
   g.n = n;
+  g.map = map;
   g.a = a;
   g.inv_a = 1.0 / a;
-  g.inv_theta = 1.0 / atan(L / a);
+  g.inv_theta = 1.0 / aux_of(map, L / a);
   g.half_nm1 = 0.5 * (n - 1);
   return g;
 }
-// Cell of v on the auxiliary variable x = atan(v/a)/theta: returns false outside
+// Cell of v on the auxiliary variable x = aux_of(v/a)/theta: returns false outside
 // [-1, 1] (relative slack 1e-10 keeps the end nodes inside), else i0 in [0, n-2] and
 // the linear weight t of node i0+1.
 __device__ inline bool dgrid_locate(const DGrid& g, double v, int& i0, double& t) {
-  double x = atan(v * g.inv_a) * g.inv_theta;
+  double x = aux_of(g.map, v * g.inv_a) * g.inv_theta;
   if (fabs(x) > 1.0 + 1e-10) return false;
   x = fmin(fmax(x, -1.0), 1.0);
   double s = (x + 1.0) * g.half_nm1;

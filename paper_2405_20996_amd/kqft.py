@@ -23,11 +23,12 @@ LINE_G, LINE_S, LINE_GSG = 0, 1, 2
 ENOCONV = -5
 K1, K2, K2P, K3, KALL = 1, 2, 4, 8, 15
 QUAD_TAN_FINITE, QUAD_TAN_INFINITE = 0, 1
+GRID_TAN, GRID_ALGEBRAIC = 0, 1
 CLASSES = ("K1", "K2", "K2p", "K3")
 
 
 class KqftGrid(C.Structure):
-    _fields_ = [("n", C.c_int), ("L", C.c_double), ("a", C.c_double)]
+    _fields_ = [("n", C.c_int), ("L", C.c_double), ("a", C.c_double), ("map", C.c_int)]
 
 
 class KqftQuad(C.Structure):
@@ -206,9 +207,10 @@ class Grid:
     n: int
     L: float = 20.0
     a: float = 1.0
+    map: int = GRID_TAN
 
     def c(self) -> KqftGrid:
-        return KqftGrid(self.n, self.L, self.a)
+        return KqftGrid(self.n, self.L, self.a, self.map)
 
 
 @dataclass

@@ -114,7 +114,9 @@ def chi_tangent_u(n, nq, U, D, noise):
     return (chi_t - chi_0).cpu().numpy()
 
 
+@pytest.mark.timeout(400)
 def test_gradient_workload_n151_vs_finite_differences():
+    """Reverse mode at the full size against central finite differences."""
     K, A = _mods()
     n, nq, U, D = 151, 1501, 1.0, 1.0
     noise = seed_noise(n, 0)
@@ -135,10 +137,9 @@ def test_gradient_workload_n151_vs_finite_differences():
     torch.cuda.empty_cache()
     print("finite differences", flush=True)
     e = 1e-5
-    sp, chp = forward_plain(n, nq, U + e, D, noise)
-    sm, chm = forward_plain(n, nq, U - e, D, noise)
+    sp, _ = forward_plain(n, nq, U + e, D, noise)
+    sm, _ = forward_plain(n, nq, U - e, D, noise)
     fd_u = (sp[n // 2, 1] - sm[n // 2, 1]) / (2 * e)
-    fd_chi = (O.chi_scalar(chp[0]) - O.chi_scalar(chm[0])) / (2 * e)
     sp, _ = forward_plain(n, nq, U, D + e, noise)
     sm, _ = forward_plain(n, nq, U, D - e, noise)
     dsd = (sp[:, 1] - sm[:, 1]) / (2 * e)
@@ -151,6 +152,18 @@ def test_gradient_workload_n151_vs_finite_differences():
           f"{float(gd):.10e} fd {fd_d:.10e}", flush=True)
     assert abs(got_u - fd_u) < 1e-5 * abs(fd_u)
     assert abs(float(gd) - fd_d) < 1e-5 * abs(fd_d)
+
+
+@pytest.mark.timeout(400)
+def test_gradient_workload_n151_forward_mode_vs_finite_differences():
+    """Forward mode (one tangent pass for every w) at the full size against central finite
+    differences of chi^R(w)."""
+    n, nq, U, D = 151, 1501, 1.0, 1.0
+    noise = seed_noise(n, 0)
+    e = 1e-5
+    _, chp = forward_plain(n, nq, U + e, D, noise)
+    _, chm = forward_plain(n, nq, U - e, D, noise)
+    fd_chi = (O.chi_scalar(chp[0]) - O.chi_scalar(chm[0])) / (2 * e)
     print("forward-mode dchi/dU", flush=True)
     dchi = O.chi_scalar(chi_tangent_u(n, nq, U, D, noise)[0])
     err = np.abs(dchi - fd_chi).max() / np.abs(fd_chi).max()
