@@ -107,7 +107,8 @@ typedef struct {
   int n;    /* points, odd recommended (v = 0 is then a node), n >= 2 */
   double L; /* extent: nodes span [-L, L] */
   double a; /* map scale */
-  int map;  /* KQFT_GRID_TAN (0, a zero-initialised grid) or KQFT_GRID_ALGEBRAIC */
+  int map;  /* KQFT_GRID_TAN (0, a zero-initialised grid) or KQFT_GRID_ALGEBRAIC; another value:
+               KQFT_EINVAL.  Left and right vertices of a bubble must agree in n, L, a and map. */
 } kqft_grid;
 
 typedef struct {
