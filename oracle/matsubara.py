@@ -229,13 +229,15 @@ def bare_bubble_sum(r: int, m: int, Delta: float, T: float) -> float:
     return -sa if r == 1 else sa
 
 
-def bubble(r: int, L: MVertex, R: MVertex, P: MProp, Nq: int, kind: int = 0, tails: bool = False) -> MChannel:
+def bubble(r: int, L: MVertex, R: MVertex, P: MProp, Nq: int, kind: int = 0, tails: bool = False,
+           ms=None) -> MChannel:
     """B_r(L, R) as the four asymptotic classes of channel r (kind 1: with Pi_dot).  With tails
     (kind 0 only; Sec. asymptotic corrections, the analytic-tails option) the summands beyond the
     window are added with the bare bubble: there Sigma has decayed and the vertices reach their
     values at large n'', L -> Gamma_0 + K1 + K2(m, n), R -> Gamma_0 + K1 + K2'(m, n') of the own
     channel, so each class gains its part of L(inf) t(m) R(inf) with t(m) = bare_bubble_sum - the
-    window's bare sum."""
+    window's bare sum.  ms: only these bosonic indices (the others stay zero), for samples of
+    large boxes."""
     if tails and kind != 0:
         raise ValueError("the analytic tails are those of the bubble G G")
     g = L.grid
@@ -244,6 +246,8 @@ def bubble(r: int, L: MVertex, R: MVertex, P: MProp, Nq: int, kind: int = 0, tai
     nbox = np.arange(-g.N, g.N)
     own_L, own_R = L.ch[r], R.ch[r]
     for im, m in enumerate(range(-g.M, g.M + 1)):
+        if ms is not None and m not in ms:
+            continue
         k = window(r, m, Nq)
         pi = pi_r(r, P, m, k, kind)
         # left: rows n (the box), columns n''; L^inf(m, n'') = Gamma_0 + K1 + K2' of the own channel
@@ -474,15 +478,18 @@ def mfrg_flow(grid: MGrid, U: float, lam_i: float, lam_f: float, steps: int, nlo
 
 
 # ------------------------------------------------------------------ susceptibilities
-def chi(r: int, V: MVertex, P: MProp, Nq: int) -> np.ndarray:
+def chi(r: int, V: MVertex, P: MProp, Nq: int, ms=None) -> np.ndarray:
     """Susceptibility of channel r in the Matsubara formalism (Sec. Susceptibilities: the bubble
     plus bubble, vertex, bubble): chi_r^c(m) = T sum_k Pi_r(m, k) + T^2 sum_{k,l} Pi_r(m, k)
     Gamma_r^c(m; k, l) Pi_r(m, l) over the bubble's window, for the channel's two spin
-    combinations c (a: X, X + 2Y; p: X + Y, X - Y; t: Y, 2X + Y).  [2, 2M + 1]."""
+    combinations c (a: X, X + 2Y; p: X + Y, X - Y; t: Y, 2X + Y).  [2, 2M + 1]; ms: only these
+    bosonic indices (the others stay zero)."""
     g = V.grid
     combos = {0: ((1, 0), (1, 2)), 1: ((1, 1), (1, -1)), 2: ((0, 1), (2, 1))}[r]
     out = np.zeros((2, 2 * g.M + 1), dtype=np.complex128)
     for im, m in enumerate(range(-g.M, g.M + 1)):
+        if ms is not None and m not in ms:
+            continue
         k = window(r, m, Nq)
         pi = pi_r(r, P, m, k)
         XY = vertex_eval(V, r, m, k[:, None], k[None, :])

@@ -95,10 +95,13 @@ def test_matsubara_invalid_arguments_raise():
 
 def test_matsubara_bubble_time():
     """M = 100, N = 100, Nq = 200: (2N + 1) x 2Nq x (2N + 1) complex products for 201 bosonic
-    frequencies and two spin combinations (52 GFLOP); all three channels."""
+    frequencies and two spin combinations (52 GFLOP); all three channels, each sampled at five
+    bosonic frequencies (both box edges, the centre, an odd and an even index) against the
+    oracle to 1e-12."""
     K = _K()
     M, N, Nq = 100, 100, 200
-    _, kv = _pair(M, N, 5, amp=0.05)
+    ov, kv = _pair(M, N, 5, amp=0.05)
+    ms = [-M, -37, 0, 64, M]
     K.bubble_matsubara(0, kv, kv, D, Nq)
     torch.cuda.synchronize()
     for r in range(3):
@@ -109,7 +112,12 @@ def test_matsubara_bubble_time():
         flop = 8.0 * (2 * N + 1) ** 2 * 2 * Nq * 2 * (2 * M + 1)
         print(f"Matsubara bubble r={r} M={M} N={N} Nq={Nq}: {dt * 1e3:.1f} ms, {flop / dt / 1e12:.1f} TFLOP/s "
               f"(algorithmic)", flush=True)
-        assert bool(torch.isfinite(out.K3).all())
+        ref = MF.bubble(r, ov, ov, MF.MProp(D, T), Nq, ms=ms)
+        im = [m + M for m in ms]
+        for x in CL:
+            a, b = getattr(out, x).cpu().numpy()[:, im], getattr(ref, x)[:, im]
+            e = _rel(a, b)
+            assert e < 1e-12, (r, x, e)
 
 
 def test_matsubara_sde_matches_oracle():
@@ -289,3 +297,25 @@ def test_matsubara_chi_errors():
         K.chi_matsubara(3, kv, D, 4)
     with pytest.raises(K.KqftError):
         K.chi_matsubara(0, kv, D, 0)
+
+
+def test_matsubara_chi_full_box_time_and_samples():
+    """M = N = 100, Nq = 200 (201 bosonic frequencies x 400^2 full-vertex lookups): timing, and
+    five bosonic frequencies of every channel against the oracle to 1e-12."""
+    K = _K()
+    M, N, Nq = 100, 100, 200
+    ov, kv = _pair(M, N, 6, amp=0.05)
+    ms = [-M, -37, 0, 64, M]
+    K.chi_matsubara(0, kv, D, Nq)
+    torch.cuda.synchronize()
+    for r in range(3):
+        t0 = time.perf_counter()
+        out = K.chi_matsubara(r, kv, D, Nq)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(f"Matsubara chi r={r} M={M} N={N} Nq={Nq}: {dt * 1e3:.2f} ms "
+              f"({(2 * M + 1) * (2 * Nq) ** 2 / dt / 1e9:.1f} G vertex lookups/s)", flush=True)
+        ref = MF.chi(r, ov, MF.MProp(D, T), Nq, ms=ms)
+        im = [m + M for m in ms]
+        e = _rel(out.cpu().numpy()[:, im], ref[:, im])
+        assert e < 1e-12, (r, e)
