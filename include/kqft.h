@@ -105,7 +105,7 @@ enum { KQFT_GRID_TAN = 0, KQFT_GRID_ALGEBRAIC = 1 };
 
 typedef struct {
   int n;    /* points, odd recommended (v = 0 is then a node), n >= 2 */
-  double L; /* extent: nodes span [-L, L] */
+  double L; /* extent: nodes span [-L, L]; L and a finite and positive, else KQFT_ESHAPE */
   double a; /* map scale */
   int map;  /* KQFT_GRID_TAN (0, a zero-initialised grid) or KQFT_GRID_ALGEBRAIC; another value:
                KQFT_EINVAL.  Left and right vertices of a bubble must agree in n, L, a and map. */

@@ -93,6 +93,9 @@ def test_grid_map_errors():
     bad = K.Vertex(K.Grid(n, 20.0, 0.8, 2), 0.7)
     with pytest.raises(K.KqftError):
         K.bubble(0, bad, bad, K.Propagator(D, T), K.Quad(9))
+    inf = K.Vertex(K.Grid(n, float("inf"), 0.8, K.GRID_ALGEBRAIC), 0.7)
+    with pytest.raises(K.KqftError):  # the extent must be finite
+        K.bubble(0, inf, inf, K.Propagator(D, T), K.Quad(9))
 
 
 def test_parquet_solver_on_the_algebraic_grid_matches_oracle_iterates():
