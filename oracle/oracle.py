@@ -1151,3 +1151,46 @@ def mfrg_flow(grid: Grid, U: float, T: float, lam_i: float, lam_f: float, steps:
         y = y[:-1]
     ch, sg = state_unpack(y, n)
     return ch, sg, info
+
+
+def regrid(src: Grid, dst: Grid, chans=None, sigma=None):
+    """Classes and self-energy carried from grid src onto grid dst by the lookup every evaluation
+    uses (Sec. Interpolation routines: linear in each auxiliary variable, zero outside the
+    extent): each class of channel r is read by vertex_eval in r's own parametrisation at the
+    nodes of dst; sigma [n][4] is interpolated on src's auxiliary variable node by node.
+    Returns (chans, sigma) on dst (None where not given)."""
+    v = dst.nodes()
+    nd = dst.n
+    out_ch = None
+    if chans is not None:
+        out_ch = []
+        for r, ch in enumerate(chans):
+            chs = [Channel(0.0), Channel(0.0), Channel(0.0)]
+            chs[r] = Channel(1.0, ch.K1, ch.K2, ch.K2p, ch.K3)
+            V = Vertex(src, 0.0, chs)
+            new = {}
+            if ch.K1 is not None:
+                pts = np.stack([v, 0 * v, 0 * v], 1)
+                new["K1"] = np.transpose(vertex_eval(V, r, pts, P_K1), (1, 0, 2)).copy()
+            W, X = np.meshgrid(v, v, indexing="ij")
+            if ch.K2 is not None:
+                pts = np.stack([W.ravel(), X.ravel(), 0 * W.ravel()], 1)
+                new["K2"] = np.transpose(vertex_eval(V, r, pts, P_K2).reshape(nd, nd, 2, 16), (2, 0, 1, 3)).copy()
+            if ch.K2p is not None:
+                pts = np.stack([W.ravel(), 0 * W.ravel(), X.ravel()], 1)
+                new["K2p"] = np.transpose(vertex_eval(V, r, pts, P_K2P).reshape(nd, nd, 2, 16), (2, 0, 1, 3)).copy()
+            if ch.K3 is not None:
+                W3, X3, Y3 = np.meshgrid(v, v, v, indexing="ij")
+                pts = np.stack([W3.ravel(), X3.ravel(), Y3.ravel()], 1)
+                new["K3"] = np.transpose(vertex_eval(V, r, pts, P_K3).reshape(nd, nd, nd, 2, 16),
+                                         (3, 0, 1, 2, 4)).copy()
+            out_ch.append(Channel(ch.coef, new.get("K1"), new.get("K2"), new.get("K2p"), new.get("K3")))
+    out_sig = None
+    if sigma is not None:
+        sigma = np.asarray(sigma)
+        out_sig = np.zeros((nd, 4), dtype=np.complex128)
+        i0, t = C.c_int(), C.c_double()
+        for i in range(nd):
+            if lib().oracle_grid_locate(src.n, src.L, src.a, src.map, v[i], C.byref(i0), C.byref(t)):
+                out_sig[i] = (1.0 - t.value) * sigma[i0.value] + t.value * sigma[i0.value + 1]
+    return out_ch, out_sig
