@@ -322,6 +322,19 @@ int kqft_loop_matsubara(kqft_ctx* ctx, const kqft_mvertex* gamma, const kqft_mpr
                         double* out, void* stream);
 
 /*
+ * kqft_regrid -- a state's classes and self-energy carried from grid `src` onto grid `dst` by the
+ * interpolation every lookup uses (Sec. Interpolation routines: multilinear on the auxiliary
+ * variable; zero where an argument lies outside src's extent), e.g. to rescale the frequency
+ * grids between segments of a hybridization flow (Sec. Frequency grids).  gamma_in/gamma_out:
+ * three channels, classes in the vertex layouts on src resp. dst (a NULL class is skipped and
+ * must be NULL on both sides); sigma_in/sigma_out: [n][4] complex on src resp. dst, or both NULL.
+ * Inputs are read only; outputs are overwritten and must not alias the inputs.  FP64, enqueued
+ * on `stream`.  KQFT_EINVAL for missing or aliased arguments, KQFT_ESHAPE for invalid grids.
+ */
+int kqft_regrid(kqft_ctx* ctx, const kqft_grid* src, const kqft_grid* dst, const kqft_chout* gamma_in,
+                const double* sigma_in, const kqft_chout* gamma_out, double* sigma_out, void* stream);
+
+/*
  * kqft_chi_matsubara -- susceptibility of channel r (`channel`) in the Matsubara formalism:
  *   chi_r^c(m) = T sum_k Pi_r(m, k) + T^2 sum_{k,l} Pi_r(m, k) Gamma_r^c(m; k, l) Pi_r(m, l)
  * over the bubble's window (Nq), the full vertex in channel r's parameters and spin combination

@@ -1383,6 +1383,62 @@ static double mf_bare_bubble_sum(int r, int m, double Delta, double T) {
   return r == KQFT_CH_P ? -sa : sa;
 }
 
+int kqft_regrid(kqft_ctx* ctx, const kqft_grid* src, const kqft_grid* dst, const kqft_chout* gamma_in,
+                const double* sigma_in, const kqft_chout* gamma_out, double* sigma_out, void* stream) {
+  int rc;
+  if (!ctx) return fail(KQFT_EINVAL, "ctx is NULL");
+  if (!src || !dst) return fail(KQFT_EINVAL, "both grids must be given");
+  if ((rc = check_grid(*src, "source grid")) || (rc = check_grid(*dst, "destination grid"))) return rc;
+  if ((gamma_in == nullptr) != (gamma_out == nullptr) || (sigma_in == nullptr) != (sigma_out == nullptr))
+    return fail(KQFT_EINVAL, "inputs and outputs must be given together");
+  if (!gamma_in && !sigma_in) return fail(KQFT_EINVAL, "nothing to regrid");
+  if (gamma_in)
+    for (int r = 0; r < 3; ++r) {
+      const double* iv[4] = {gamma_in[r].K1, gamma_in[r].K2, gamma_in[r].K2p, gamma_in[r].K3};
+      const double* ov[4] = {gamma_out[r].K1, gamma_out[r].K2, gamma_out[r].K2p, gamma_out[r].K3};
+      for (int c = 0; c < 4; ++c) {
+        if ((iv[c] == nullptr) != (ov[c] == nullptr))
+          return fail(KQFT_EINVAL, "a class must be given on both sides or on neither");
+        if (iv[c] && iv[c] == ov[c]) return fail(KQFT_EINVAL, "regridding cannot run in place");
+      }
+    }
+  if (sigma_in && sigma_in == sigma_out) return fail(KQFT_EINVAL, "regridding cannot run in place");
+  const double* nodes = nullptr;
+  HIP_TRY(hipSetDevice(ctx->device));
+  if ((rc = get_grid(ctx, *dst, &nodes))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  RegridArgs a;
+  memset(&a, 0, sizeof a);
+  a.src = make_dgrid(src->n, src->L, src->a, src->map);
+  a.dst = nodes;
+  a.nd = dst->n;
+  if (gamma_in)
+    for (int r = 0; r < 3; ++r) {
+      const double* iv[4] = {gamma_in[r].K1, gamma_in[r].K2, gamma_in[r].K2p, gamma_in[r].K3};
+      double* ov[4] = {gamma_out[r].K1, gamma_out[r].K2, gamma_out[r].K2p, gamma_out[r].K3};
+      const int dims[4] = {1, 2, 2, 3};
+      for (int c = 0; c < 4; ++c) {
+        if (!iv[c]) continue;
+        a.dims = dims[c];
+        a.nspin = 2;
+        a.ncomp = 16;
+        a.in = (const double2*)iv[c];
+        a.out = (double2*)ov[c];
+        launch_regrid(a, s);
+      }
+    }
+  if (sigma_in) {
+    a.dims = 1;
+    a.nspin = 1;
+    a.ncomp = 4;
+    a.in = (const double2*)sigma_in;
+    a.out = (double2*)sigma_out;
+    launch_regrid(a, s);
+  }
+  HIP_TRY(hipGetLastError());
+  return KQFT_OK;
+}
+
 int kqft_chi_matsubara(kqft_ctx* ctx, int channel, const kqft_mvertex* gamma, const kqft_mprop* G, int Nq,
                        double* chi, void* stream) {
   int rc;

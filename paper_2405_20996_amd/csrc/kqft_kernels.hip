@@ -2068,6 +2068,45 @@ void launch_adaptive(const AdaptArgs& a, hipStream_t s) {
 void launch_dot(const double2* a, const double2* b, size_t count, double* partial, int nblk, hipStream_t s) {
   hipLaunchKernelGGL(dot_kernel, dim3(nblk), dim3(256), 0, s, a, b, count, partial);
 }
+__global__ __launch_bounds__(256) void regrid_kernel(RegridArgs a) {
+  const long nd = a.nd, ns = a.src.n;
+  long outer = a.nspin;
+  for (int d = 0; d < a.dims; ++d) outer *= nd;
+  const long total = outer * a.ncomp;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int c = (int)(e % a.ncomp);
+    long rest = e / a.ncomp;
+    int idx[3] = {0, 0, 0};
+    for (int d = a.dims - 1; d >= 0; --d) {
+      idx[d] = (int)(rest % nd);
+      rest /= nd;
+    }
+    const long sp = rest;  // spin block
+    int i0[3] = {0, 0, 0};
+    double t[3] = {0.0, 0.0, 0.0};
+    bool in = true;
+    for (int d = 0; d < a.dims; ++d) in = in && dgrid_locate(a.src, a.dst[idx[d]], i0[d], t[d]);
+    double2 acc = czero();
+    if (in) {
+      for (int corner = 0; corner < (1 << a.dims); ++corner) {
+        double w = 1.0;
+        long off = sp;
+        for (int d = 0; d < a.dims; ++d) {
+          const int up = (corner >> d) & 1;
+          w *= up ? t[d] : 1.0 - t[d];
+          off = off * ns + i0[d] + up;
+        }
+        acc = cfma(w, a.in[off * a.ncomp + c], acc);
+      }
+    }
+    a.out[e] = acc;
+  }
+}
+
+void launch_regrid(const RegridArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(regrid_kernel, dim3(2048), dim3(256), 0, s, a);
+}
+
 void launch_lincomb(const LinComb& a, hipStream_t s) {
   hipLaunchKernelGGL(lincomb_kernel, dim3(2048), dim3(256), 0, s, a);
 }

@@ -198,6 +198,17 @@ struct LinComb {
   size_t count;
 };
 void launch_lincomb(const LinComb& a, hipStream_t s);
+// out[s][i1..id][c] = the multilinear interpolation (on src's auxiliary variable) of
+// in[s][..][c] at the destination nodes (dims 1..3 frequency axes, nspin leading blocks,
+// ncomp complex components innermost); zero where any argument lies outside src's extent
+struct RegridArgs {
+  DGrid src;
+  const double* dst;  // destination nodes [nd]
+  int nd, dims, nspin, ncomp;
+  const double2* in;
+  double2* out;
+};
+void launch_regrid(const RegridArgs& a, hipStream_t s);
 // adaptive bubble: one work item = one output and one interval of the auxiliary variable
 struct AdaptItem {
   double ya, yb;

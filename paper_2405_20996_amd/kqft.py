@@ -127,6 +127,8 @@ def lib():
                                   C.c_void_p]
         _lib.kqft_bubble_matsubara.argtypes = [C.c_void_p, C.c_int, P(KqftMVertex), P(KqftMVertex), P(KqftMProp),
                                                C.c_int, C.c_int, C.c_int, P(KqftChout), C.c_void_p]
+        _lib.kqft_regrid.argtypes = [C.c_void_p, P(KqftGrid), P(KqftGrid), C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p]
         _lib.kqft_chi_matsubara.argtypes = [C.c_void_p, C.c_int, P(KqftMVertex), P(KqftMProp), C.c_int, C.c_void_p,
                                             C.c_void_p]
         _lib.kqft_loop_matsubara.argtypes = [C.c_void_p, P(KqftMVertex), P(KqftMProp), C.c_int, C.c_int, C.c_void_p,
@@ -434,6 +436,33 @@ def bubble_matsubara(channel: int, left: MVertex, right: MVertex, Delta: float, 
     _check(lib().kqft_bubble_matsubara(ctx(), channel, C.byref(lc), C.byref(rc), C.byref(gp), pi_kind, Nq,
                                        int(tails), C.byref(oc), _stream(stream)))
     return out
+
+
+def regrid(src: Grid, dst: Grid, gamma: Optional[Sequence[Channel]] = None, sigma: Optional[torch.Tensor] = None,
+           stream=None):
+    """The channels' classes (coefficients kept) and the self-energy [n][4] carried from grid src onto
+    grid dst.  Returns (channels, sigma) on dst (None where not given)."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    gin = gout = None
+    new = None
+    keep = []
+    if gamma is not None:
+        new = [Channel(c.coef, *[None if getattr(c, x) is None else
+                                 torch.zeros(class_shape(x, dst.n), dtype=torch.complex128, device=dev)
+                                 for x in CLASSES]) for c in gamma]
+        gin = (KqftChout * 3)(*[_chout(c, src.n) for c in gamma])
+        gout = (KqftChout * 3)(*[_chout(c, dst.n) for c in new])
+        keep += [gin, gout]
+    sig = None
+    if sigma is not None:
+        _ptr(sigma, (src.n, 4), "sigma")
+        sig = torch.zeros((dst.n, 4), dtype=torch.complex128, device=dev)
+    sc, dc = src.c(), dst.c()
+    _check(lib().kqft_regrid(ctx(), C.byref(sc), C.byref(dc), C.cast(gin, C.c_void_p) if gin else None,
+                             C.c_void_p(sigma.data_ptr()) if sigma is not None else None,
+                             C.cast(gout, C.c_void_p) if gout else None,
+                             C.c_void_p(sig.data_ptr()) if sig is not None else None, _stream(stream)))
+    return new, sig
 
 
 def chi_matsubara(channel: int, gamma: MVertex, Delta: float, Nq: int, sigma: Optional[torch.Tensor] = None,
