@@ -460,9 +460,13 @@ def mfrg_rhs(grid: MGrid, U: float, lam: float, nloops: int, Nq: int, Nl: int, c
 
 
 def mfrg_flow(grid: MGrid, U: float, lam_i: float, lam_f: float, steps: int, nloops: int, Nq: int, Nl: int,
-              chans, sigma, katanin: bool = True, se_iterations: int = 0):
-    """Classical RK4 in `steps` equal steps of t with Delta = Lambda(t) = 5 t|t| / sqrt(1 - t^2)
-    (the Keldysh Delta-flow's parametrisation) from lam_i to lam_f.  Returns (chans, sigma)."""
+              chans, sigma, katanin: bool = True, se_iterations: int = 0, adaptive: bool = False,
+              atol: float = 1e-8, rtol: float = 1e-5, max_steps: int = 200, info: Optional[dict] = None):
+    """The ODE in t with Delta = Lambda(t) = 5 t|t| / sqrt(1 - t^2) (the Keldysh Delta-flow's
+    parametrisation) from lam_i to lam_f: classical RK4 in `steps` equal steps, or (adaptive) the
+    Cash-Karp step control of the Keldysh flow (Sec. ODE solver) with first trial step
+    (t_f - t_i) / steps.  Returns (chans, sigma); info (if given) receives the accepted Delta
+    values and the number of rejected steps."""
     from .oracle import REG_DELTA, flow_dlambda_dt, flow_lambda, flow_t, ode_solve
 
     def f(t, vec):
@@ -471,8 +475,11 @@ def mfrg_flow(grid: MGrid, U: float, lam_i: float, lam_f: float, steps: int, nlo
                           se_iterations)
         return flow_dlambda_dt(REG_DELTA, t) * state_pack(grid, gd, sd)
 
-    y, _, _ = ode_solve(f, state_pack(grid, chans, sigma), flow_t(REG_DELTA, lam_i), flow_t(REG_DELTA, lam_f),
-                        steps)
+    y, ts, rejected = ode_solve(f, state_pack(grid, chans, sigma), flow_t(REG_DELTA, lam_i),
+                                flow_t(REG_DELTA, lam_f), steps, adaptive, atol, rtol, max_steps)
+    if info is not None:
+        info["lambdas"] = [flow_lambda(REG_DELTA, t) for t in ts]
+        info["rejected"] = rejected
     ch, sg = state_unpack(grid, y)
     return ch, np.array(sg)
 

@@ -278,3 +278,34 @@ def test_matsubara_chi_factorises_for_the_bare_vertex_and_diagonalises_the_bubbl
             assert np.abs(ch[c] - (S[0] + S[0] * G0c * S[0])).max() < 1e-14
             assert np.abs((mx * K1[0] + my * K1[1]) - pref[r] * G0c * S[0] * G0c).max() < 1e-14
     assert np.abs(Ss[1] + Ss[0]).max() < 1e-14
+
+
+def test_matsubara_flow_step_control_converges_onto_the_extrapolated_rk4_flow():
+    """Cash-Karp step control on the Matsubara flow (two loops, Katanin): at tight tolerances it
+    lands on the Richardson extrapolation of RK4 with 6 and 12 steps (the ODE's solution to
+    O(h^5)) well inside RK4's own error; a loose tolerance takes fewer steps; the accepted Delta
+    values run from 2 to 1."""
+    g = MF.MGrid(4, 2, T)
+    Nq, Nl, u = 6, 4, 0.8
+    chans, sig = MF.pt2_state(g, u, 2.0, Nq, Nl)
+    c6, s6 = MF.mfrg_flow(g, u, 2.0, 1.0, 6, 2, Nq, Nl, chans, sig)
+    c12, s12 = MF.mfrg_flow(g, u, 2.0, 1.0, 12, 2, Nq, Nl, chans, sig)
+    tight, loose = {}, {}
+    ch, sg = MF.mfrg_flow(g, u, 2.0, 1.0, 2, 2, Nq, Nl, chans, sig, adaptive=True, atol=1e-10, rtol=1e-8,
+                          info=tight)
+    MF.mfrg_flow(g, u, 2.0, 1.0, 2, 2, Nq, Nl, chans, sig, adaptive=True, atol=1e-5, rtol=1e-4, info=loose)
+    e_ad = e_rk = 0.0
+    for r in range(3):
+        for x in ("K1", "K2", "K2p", "K3"):
+            a, b6, b12 = getattr(ch[r], x), getattr(c6[r], x), getattr(c12[r], x)
+            ext = b12 + (b12 - b6) / 15.0
+            scale = np.abs(b12).max()
+            assert np.abs(a - ext).max() < 1e-6 * scale, (r, x)
+            e_ad = max(e_ad, np.abs(a - ext).max() / scale)
+            e_rk = max(e_rk, np.abs(b12 - ext).max() / scale)
+    assert e_ad < 0.2 * e_rk
+    ext = s12 + (s12 - s6) / 15.0
+    assert np.abs(sg - ext).max() < 1e-8 * np.abs(s12).max()
+    assert len(loose["lambdas"]) < len(tight["lambdas"])
+    for inf in (tight, loose):
+        assert abs(inf["lambdas"][0] - 2.0) < 1e-12 and abs(inf["lambdas"][-1] - 1.0) < 1e-12
