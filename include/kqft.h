@@ -345,24 +345,6 @@ int kqft_chi_matsubara(kqft_ctx* ctx, int channel, const kqft_mvertex* gamma, co
                        double* chi, void* stream);
 
 /*
- * kqft_mfrg_flow_matsubara -- the mfRG flow (Sec. "mfRG") in the Matsubara formalism with the
- * hybridization as flow parameter (Delta from Lambda_i to Lambda_f; the ODE in t with
- * Delta = 5 t|t| / sqrt(1 - t^2), classical RK4 in `steps` equal steps):
- *   Sigma_dot^(1) = -L(Gamma, S)                         (kqft_loop_matsubara, window Nl),
- *   Gamma_dot     = sum_{l <= nloops} gdot^(l): l = 1 B_r(Gamma, Gamma; Pi_dot) along S
- *                   (+ G Sigma_dot G with katanin), l = 2 B_r(gdot_rbar, Gamma) + B_r(Gamma,
- *                   gdot_rbar), l >= 3 also B_r(Gamma, B_r(gdot_rbar^(l-2), Gamma))   (window Nq),
- * and with se_iterations > 0 and nloops >= 3 the corrections Sigma_dot_tbar = -L(sum of the
- * a and p centre terms, G), Sigma_dot_t = -L(Gamma, G Sigma_dot_tbar G), Sigma_dot = Sigma_dot^(1)
- * + Sigma_dot_tbar + Sigma_dot_t, iterated until max|change| <= abs + rel max|Sigma_dot| or
- * se_iterations times.  State in/out: gamma[3] (device classes on grid) and sigma (device [2N]).
- * FP64.  Synchronises `stream` once per correction iteration.
- */
-int kqft_mfrg_flow_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, double Lambda_i, double Lambda_f,
-                             int steps, int nloops, int Nq, int Nl, int katanin, int se_iterations, double se_tol_abs,
-                             double se_tol_rel, const kqft_chout* gamma, double* sigma, void* stream);
-
-/*
  * kqft_sde_matsubara -- the Schwinger-Dyson self-energy in the Matsubara formalism (a-channel
  * form, Hartree part absorbed at particle-hole symmetry):
  *   Phi = B_a(Gamma_0, Gamma) (kqft_bubble_matsubara, window Nq; classes K1 and K2'),
@@ -506,6 +488,32 @@ int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, dou
                    int steps, int nloops, const kqft_quad* q_bubble, const kqft_quad* q_loop, const kqft_opts* opts,
                    const kqft_flow_opts* flow, const kqft_chout* gamma, double* sigma, double* lambdas,
                    kqft_flow_info* info, void* stream);
+
+/*
+ * kqft_mfrg_flow_matsubara -- the mfRG flow (Sec. "mfRG") in the Matsubara formalism with the
+ * hybridization as flow parameter (Delta from Lambda_i to Lambda_f; the ODE in t with
+ * Delta = 5 t|t| / sqrt(1 - t^2): classical RK4 in `steps` equal steps, or with adaptive = 1
+ * the Cash-Karp step control of kqft_mfrg_flow (tolerances ode_tol_abs/ode_tol_rel on the
+ * whole state, first trial step (t_f - t_i)/steps, at most max_steps trial steps, else
+ * KQFT_ENOCONV with the state where it stopped)):
+ *   Sigma_dot^(1) = -L(Gamma, S)                         (kqft_loop_matsubara, window Nl),
+ *   Gamma_dot     = sum_{l <= nloops} gdot^(l): l = 1 B_r(Gamma, Gamma; Pi_dot) along S
+ *                   (+ G Sigma_dot G with katanin), l = 2 B_r(gdot_rbar, Gamma) + B_r(Gamma,
+ *                   gdot_rbar), l >= 3 also B_r(Gamma, B_r(gdot_rbar^(l-2), Gamma))   (window Nq),
+ * and with se_iterations > 0 and nloops >= 3 the corrections Sigma_dot_tbar = -L(sum of the
+ * a and p centre terms, G), Sigma_dot_t = -L(Gamma, G Sigma_dot_tbar G), Sigma_dot = Sigma_dot^(1)
+ * + Sigma_dot_tbar + Sigma_dot_t, iterated until max|change| <= abs + rel max|Sigma_dot| or
+ * se_iterations times.  State in/out: gamma[3] (device classes on grid) and sigma (device [2N]).
+ * lambdas (host, capacity max_steps + 1 for adaptive, steps + 1 otherwise, or NULL): the
+ * accepted Delta values from Lambda_i; info (host, or NULL): step and evaluation counts
+ * (sigma_inf unused).  FP64.  Synchronises `stream` once per correction iteration and per
+ * trial step (adaptive).
+ */
+int kqft_mfrg_flow_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, double Lambda_i, double Lambda_f,
+                             int steps, int nloops, int Nq, int Nl, int katanin, int se_iterations, double se_tol_abs,
+                             double se_tol_rel, int adaptive, double ode_tol_abs, double ode_tol_rel, int max_steps,
+                             const kqft_chout* gamma, double* sigma, double* lambdas, kqft_flow_info* info,
+                             void* stream);
 
 /*
  * kqft_parquet_iteration -- right-hand sides of the parquet equations (Sec. "parquet

@@ -1724,9 +1724,22 @@ static double flow_lambda(int reg, double t);
 static double flow_t(int reg, double lam);
 static double flow_dlambda_dt(int reg, double t);
 
+// Cash-Karp embedded pair (Cash and Karp 1990): nodes, stage matrix, fifth- and fourth-order weights.
+static const double kCkC[6] = {0.0, 1.0 / 5, 3.0 / 10, 3.0 / 5, 1.0, 7.0 / 8};
+static const double kCkA[6][5] = {{0, 0, 0, 0, 0},
+                                  {1.0 / 5, 0, 0, 0, 0},
+                                  {3.0 / 40, 9.0 / 40, 0, 0, 0},
+                                  {3.0 / 10, -9.0 / 10, 6.0 / 5, 0, 0},
+                                  {-11.0 / 54, 5.0 / 2, -70.0 / 27, 35.0 / 27, 0},
+                                  {1631.0 / 55296, 175.0 / 512, 575.0 / 13824, 44275.0 / 110592, 253.0 / 4096}};
+static const double kCkB5[6] = {37.0 / 378, 0.0, 250.0 / 621, 125.0 / 594, 0.0, 512.0 / 1771};
+static const double kCkB4[6] = {2825.0 / 27648, 0.0, 18575.0 / 48384, 13525.0 / 55296, 277.0 / 14336, 1.0 / 4};
+
 int kqft_mfrg_flow_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, double Lambda_i, double Lambda_f,
                              int steps, int nloops, int Nq, int Nl, int katanin, int se_iterations, double se_tol_abs,
-                             double se_tol_rel, const kqft_chout* gamma, double* sigma, void* stream) {
+                             double se_tol_rel, int adaptive, double ode_tol_abs, double ode_tol_rel, int max_steps,
+                             const kqft_chout* gamma, double* sigma, double* lambdas, kqft_flow_info* info,
+                             void* stream) {
   int rc;
   if (!ctx) return fail(KQFT_EINVAL, "ctx is NULL");
   if (!grid || !gamma || !sigma) return fail(KQFT_EINVAL, "grid, gamma and sigma must be given");
@@ -1737,6 +1750,9 @@ int kqft_mfrg_flow_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, do
   if (steps < 1 || nloops < 1) return fail(KQFT_EINVAL, "need steps >= 1 and nloops >= 1");
   if (se_iterations < 0 || !(se_tol_abs >= 0) || !(se_tol_rel >= 0))
     return fail(KQFT_EINVAL, "self-energy correction settings must be non-negative");
+  if (adaptive != 0 && adaptive != 1) return fail(KQFT_EINVAL, "adaptive must be 0 or 1");
+  if (adaptive && (max_steps < 1 || !(ode_tol_abs >= 0) || !(ode_tol_rel >= 0) || !(ode_tol_abs + ode_tol_rel > 0)))
+    return fail(KQFT_EINVAL, "adaptive steps need max_steps >= 1 and positive tolerances");
   for (int r = 0; r < 3; ++r)
     if (!gamma[r].K1 || !gamma[r].K2 || !gamma[r].K2p || !gamma[r].K3)
       return fail(KQFT_EINVAL, "gamma arrays must all be given");
@@ -1747,17 +1763,24 @@ int kqft_mfrg_flow_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, do
   const size_t chc = cnt[0] + cnt[1] + cnt[2] + cnt[3];
   const size_t stc = 3 * chc + nf;
   const bool corr = se_iterations > 0 && nloops >= 3;
-  // Y, stage input, stage derivative, RK4 accumulator; insertions; centre sums; two scratch
-  // channels; Sigma-sized work arrays
-  const size_t total = 4 * stc + (size_t)nloops * 3 * chc + 2 * chc + 2 * chc + 6 * nf;
+  // states: Y, stage input, then the RK4 stage derivative and accumulator, or y4 and the six
+  // Cash-Karp stage derivatives; insertions; centre sums; two scratch channels; Sigma-sized
+  // work arrays; the step-error partial maxima
+  const int nst = adaptive ? 9 : 4;
+  const int nblk = (int)std::min<size_t>(1024, (stc + 255) / 256);
+  const size_t total = (size_t)nst * stc + (size_t)nloops * 3 * chc + 2 * chc + 2 * chc + 6 * nf + nblk;
   if ((rc = ensure(ctx->mfflow, total * sizeof(double2)))) return rc;
   double2* base = (double2*)ctx->mfflow.p;
   double2 *Y = base, *yt = base + stc, *kd = base + 2 * stc, *ys = base + 3 * stc;
-  double2* ml = base + 4 * stc;
+  double2* ml = base + (size_t)nst * stc;
   double2* cen = ml + (size_t)nloops * 3 * chc;
   double2 *t1 = cen + 2 * chc, *t2 = t1 + chc;
   double2* ax = t2 + chc;
   double2 *sd1 = ax, *tb = ax + nf, *sdt = ax + 2 * nf, *snew = ax + 3 * nf, *sdk = ax + 4 * nf;
+  double* red = (double*)(ax + 6 * nf);
+  kqft_flow_info inf;
+  memset(&inf, 0, sizeof inf);
+  int status = KQFT_OK;
   auto cls = [&](double2* b0, int c) {
     size_t off = 0;
     for (int u = 0; u < c; ++u) off += cnt[u];
@@ -1779,6 +1802,7 @@ int kqft_mfrg_flow_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, do
   auto rhs = [&](double t, double2* yb, double2* kout) -> int {
     int e;
     const double lam = flow_lambda(KQFT_REG_DELTA, t);
+    ++inf.rhs_evaluations;
     kqft_mvertex V;
     memset(&V, 0, sizeof V);
     V.grid = g;
@@ -1854,6 +1878,7 @@ int kqft_mfrg_flow_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, do
         mv = std::max(mv, std::hypot(hb[i].x, hb[i].y));
       }
       ++it;
+      ++inf.se_iterations;
       launch_axpby(sdk, 1.0, snew, 0.0, snew, nf, s);
       if (md <= se_tol_abs + se_tol_rel * mv || it >= se_iterations) break;
     }
@@ -1878,8 +1903,14 @@ int kqft_mfrg_flow_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, do
   }
   HIP_TRY(hipMemcpyAsync(Y + 3 * chc, sigma, nf * sizeof(double2), hipMemcpyDeviceToDevice, s));
   const double ti = flow_t(KQFT_REG_DELTA, Lambda_i), tf = flow_t(KQFT_REG_DELTA, Lambda_f);
+  int nrec = 0;
+  auto record = [&](double t) {
+    if (lambdas) lambdas[nrec] = flow_lambda(KQFT_REG_DELTA, t);
+    ++nrec;
+  };
+  record(ti);
   const double h = (tf - ti) / steps;
-  for (int k = 0; k < steps; ++k) {  // classical RK4
+  for (int k = 0; k < steps && !adaptive; ++k) {  // classical RK4
     const double ta = ti + k * h;
     const double2* kk[1] = {kd};
     double c[1];
@@ -1901,6 +1932,56 @@ int kqft_mfrg_flow_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, do
     if ((rc = rhs(ta + h, yt, kd))) return rc;
     c[0] = h / 6.0;
     lincomb_n(Y, ys, 1, kk, c, stc, s);
+    ++inf.accepted;
+    record(ti + (k + 1) * h);
+  }
+  if (adaptive) {  // Cash-Karp, advancing with the fourth-order solution (as the Keldysh flow)
+    double2* y4 = base + 2 * stc;
+    double2* K[6];
+    for (int k = 0; k < 6; ++k) K[k] = base + (size_t)(3 + k) * stc;
+    const double dir = tf >= ti ? 1.0 : -1.0;
+    double t = ti, hh = (tf - ti) / steps;
+    bool have_k1 = false, done = false;
+    std::vector<double> hr(nblk);
+    for (int trial = 0; trial < max_steps && !done; ++trial) {
+      const bool last = (t + hh - tf) * dir >= 0.0;
+      if (last) hh = tf - t;
+      if (!have_k1) {
+        if ((rc = rhs(t, Y, K[0]))) return rc;
+        have_k1 = true;
+      }
+      for (int i = 1; i < 6; ++i) {
+        double c[5];
+        for (int j = 0; j < i; ++j) c[j] = hh * kCkA[i][j];
+        lincomb_n(yt, Y, i, K, c, stc, s);
+        if ((rc = rhs(t + kCkC[i] * hh, yt, K[i]))) return rc;
+      }
+      double c4[6], ce[6];
+      for (int j = 0; j < 6; ++j) {
+        c4[j] = hh * kCkB4[j];
+        ce[j] = hh * (kCkB5[j] - kCkB4[j]);
+      }
+      lincomb_n(y4, Y, 6, K, c4, stc, s);
+      lincomb_n(yt, nullptr, 6, K, ce, stc, s);
+      launch_errnorm(yt, Y, y4, ode_tol_abs, ode_tol_rel, stc, red, nblk, s);
+      HIP_TRY(hipMemcpyAsync(hr.data(), red, (size_t)nblk * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      double err = 0.0;
+      for (int b = 0; b < nblk; ++b) err = std::max(err, hr[b]);
+      if (err <= 1.0) {
+        std::swap(Y, y4);
+        t = last ? tf : t + hh;
+        have_k1 = false;
+        ++inf.accepted;
+        record(t);
+        if (last) done = true;
+        hh *= err == 0.0 ? 5.0 : std::min(5.0, 0.9 * pow(err, -0.2));
+      } else {
+        ++inf.rejected;
+        hh *= std::max(0.1, 0.9 * pow(err, -0.25));
+      }
+    }
+    if (!done) status = fail(KQFT_ENOCONV, "flow step limit reached before Lambda_f");
   }
   for (int r = 0; r < 3; ++r) {
     double* dst[4] = {gamma[r].K1, gamma[r].K2, gamma[r].K2p, gamma[r].K3};
@@ -1909,7 +1990,8 @@ int kqft_mfrg_flow_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, do
   }
   HIP_TRY(hipMemcpyAsync(sigma, Y + 3 * chc, nf * sizeof(double2), hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipGetLastError());
-  return KQFT_OK;
+  if (info) *info = inf;
+  return status;
 }
 
 int kqft_loop(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, int kind, const kqft_quad* q,
@@ -2066,16 +2148,6 @@ struct HostAnderson {
   }
 };
 
-// Cash-Karp embedded pair (Cash and Karp 1990): nodes, stage matrix, fifth- and fourth-order weights.
-static const double kCkC[6] = {0.0, 1.0 / 5, 3.0 / 10, 3.0 / 5, 1.0, 7.0 / 8};
-static const double kCkA[6][5] = {{0, 0, 0, 0, 0},
-                                  {1.0 / 5, 0, 0, 0, 0},
-                                  {3.0 / 40, 9.0 / 40, 0, 0, 0},
-                                  {3.0 / 10, -9.0 / 10, 6.0 / 5, 0, 0},
-                                  {-11.0 / 54, 5.0 / 2, -70.0 / 27, 35.0 / 27, 0},
-                                  {1631.0 / 55296, 175.0 / 512, 575.0 / 13824, 44275.0 / 110592, 253.0 / 4096}};
-static const double kCkB5[6] = {37.0 / 378, 0.0, 250.0 / 621, 125.0 / 594, 0.0, 512.0 / 1771};
-static const double kCkB4[6] = {2825.0 / 27648, 0.0, 18575.0 / 48384, 13525.0 / 55296, 277.0 / 14336, 1.0 / 4};
 
 int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, double Lambda_i, double Lambda_f,
                    int steps, int nloops, const kqft_quad* q_bubble, const kqft_quad* q_loop, const kqft_opts* opts,

@@ -135,7 +135,8 @@ def lib():
                                              C.c_void_p]
         _lib.kqft_mfrg_flow_matsubara.argtypes = [C.c_void_p, P(KqftMGrid), C.c_double, C.c_double, C.c_double,
                                                   C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
-                                                  C.c_double, P(KqftChout), C.c_void_p, C.c_void_p]
+                                                  C.c_double, C.c_int, C.c_double, C.c_double, C.c_int,
+                                                  P(KqftChout), C.c_void_p, C.c_void_p, P(KqftFlowInfo), C.c_void_p]
         _lib.kqft_sde_matsubara.argtypes = [C.c_void_p, P(KqftMVertex), P(KqftMProp), C.c_int, C.c_int, C.c_void_p,
                                             C.c_void_p]
         _lib.kqft_parquet_solve_matsubara.argtypes = [C.c_void_p, P(KqftMGrid), C.c_double, C.c_double, C.c_int,
@@ -492,17 +493,25 @@ def loop_matsubara(gamma: MVertex, Delta: float, Nl: int, kind: int = LINE_G, si
 
 def mfrg_flow_matsubara(grid: MGrid, U: float, lam_i: float, lam_f: float, steps: int, nloops: int, Nq: int, Nl: int,
                         gamma: Sequence[Channel], sigma: torch.Tensor, katanin: bool = True, se_iterations: int = 0,
-                        se_atol: float = 1e-9, se_rtol: float = 1e-5, stream=None):
+                        se_atol: float = 1e-9, se_rtol: float = 1e-5, adaptive: bool = False, atol: float = 1e-8,
+                        rtol: float = 1e-5, max_steps: int = 200, stream=None):
     """The Matsubara hybridization flow of the state (gamma[3], sigma [2N]) from lam_i to lam_f,
-    in place (classical RK4)."""
+    in place (classical RK4, or Cash-Karp step control with adaptive).  Returns (gamma, sigma,
+    info) with info the accepted Delta values and the step counts."""
     D = (KqftChout * 3)(*[KqftChout(*[_ptr(getattr(c, x), grid.shape(x), f"gamma.{x}") for x in CLASSES])
                           for c in gamma])
     _ptr(sigma, (2 * grid.N,), "sigma")
     gc = grid.c()
+    lams = (C.c_double * ((max_steps if adaptive else steps) + 1))()
+    inf = KqftFlowInfo()
     _check(lib().kqft_mfrg_flow_matsubara(ctx(), C.byref(gc), C.c_double(U), C.c_double(lam_i), C.c_double(lam_f),
                                           steps, nloops, Nq, Nl, int(katanin), se_iterations, C.c_double(se_atol),
-                                          C.c_double(se_rtol), D, C.c_void_p(sigma.data_ptr()), _stream(stream)))
-    return gamma, sigma
+                                          C.c_double(se_rtol), int(adaptive), C.c_double(atol), C.c_double(rtol),
+                                          max_steps, D, C.c_void_p(sigma.data_ptr()), lams, C.byref(inf),
+                                          _stream(stream)))
+    info = {"lambdas": list(lams[:inf.accepted + 1]), "accepted": inf.accepted, "rejected": inf.rejected,
+            "rhs": inf.rhs_evaluations, "se_iterations": inf.se_iterations}
+    return gamma, sigma, info
 
 
 def sde_matsubara(gamma: MVertex, Delta: float, Nq: int, Nl: int, sigma: Optional[torch.Tensor] = None,

@@ -228,6 +228,37 @@ def test_matsubara_flow_matches_oracle(steps, nloops, katanin, se):
     assert _rel(ksig.cpu().numpy(), rsig) < 1e-10
 
 
+def test_matsubara_adaptive_flow_matches_oracle():
+    """Cash-Karp step control on the Matsubara flow (M = 8, N = 3, two loops, Katanin, Delta
+    2 -> 1, tolerances 1e-7 / 1e-5): the same accepted Delta values and rejected steps as the
+    oracle, and the same final state to 1e-10."""
+    K = _K()
+    M, N, Nq, Nl, U = 8, 3, 8, 6, 1.0
+    og = MF.MGrid(M, N, T)
+    chans, sig = MF.pt2_state(og, U, 2.0, Nq, Nl)
+    rinfo = {}
+    rch, rsig = MF.mfrg_flow(og, U, 2.0, 1.0, 2, 2, Nq, Nl, chans, sig, True, 0, adaptive=True, atol=1e-7,
+                             rtol=1e-5, info=rinfo)
+    kch = [K.Channel(1.0, *[to_dev(getattr(c, x)) for x in CL]) for c in chans]
+    ksig = to_dev(sig)
+    _, _, kinfo = K.mfrg_flow_matsubara(K.MGrid(M, N, T), U, 2.0, 1.0, 2, 2, Nq, Nl, kch, ksig, katanin=True,
+                                        adaptive=True, atol=1e-7, rtol=1e-5)
+    torch.cuda.synchronize()
+    print(f"adaptive Matsubara flow: Delta {np.round(kinfo['lambdas'], 6).tolist()}, rejected {kinfo['rejected']}, "
+          f"rhs {kinfo['rhs']}", flush=True)
+    assert len(kinfo["lambdas"]) == len(rinfo["lambdas"]) and kinfo["rejected"] == rinfo["rejected"]
+    assert np.abs(np.array(kinfo["lambdas"]) - np.array(rinfo["lambdas"])).max() < 1e-12
+    # six stages per accepted trial, five per rejected one (its first stage is reused)
+    assert kinfo["rhs"] == 6 * (len(rinfo["lambdas"]) - 1) + 5 * rinfo["rejected"]
+    for r in range(3):
+        for x in CL:
+            assert _rel(getattr(kch[r], x).cpu().numpy(), getattr(rch[r], x)) < 1e-10, (r, x)
+    assert _rel(ksig.cpu().numpy(), rsig) < 1e-10
+    with pytest.raises(K.KqftError):  # step limit
+        K.mfrg_flow_matsubara(K.MGrid(M, N, T), U, 2.0, 1.0, 2, 1, Nq, Nl, kch, ksig, adaptive=True, atol=1e-14,
+                              rtol=1e-14, max_steps=2)
+
+
 def test_matsubara_flow_time():
     """M = 48, N = 24, Nq = 48, Nl = 24, U = 1: two RK4 steps of the hybridization flow from the
     PT2 state (Delta 2 -> 1), three loops with Katanin and up to three correction iterations; the
