@@ -161,18 +161,25 @@ def _on_box(arr: Optional[np.ndarray], n: np.ndarray) -> np.ndarray:
 @dataclass
 class MProp:
     """G(i nu_n) = 1/(i nu_n + i Delta sgn(nu_n) - Sigma(n)), Sigma on n in [-Ns, Ns) or none.
-    The flow parameter of the Matsubara flow is Delta (hybridization flow): the single-scale
-    propagator is S = dG/dDelta at fixed Sigma = -i sgn(nu) G^2, plus G Sigma_dot G with the
-    optional dsigma (Katanin substitution)."""
+    The flow parameter is Delta (reg 0, hybridization flow; S = dG/dDelta at fixed Sigma =
+    -i sgn(nu) G^2) or lam (reg 1, interaction flow, Sec. Flow schemes: G_0 -> lam G_0, so
+    G = 1/(G_0^-1/lam - Sigma) and S = dG/dlam at fixed Sigma = G G_0^-1 G / lam^2), plus
+    G Sigma_dot G with the optional dsigma (Katanin substitution)."""
     Delta: float
     T: float
     sigma: Optional[np.ndarray] = None
     dsigma: Optional[np.ndarray] = None
+    reg: int = 0
+    lam: float = 1.0
+
+    def g0inv(self, n):
+        v = nu(np.asarray(n), self.T)
+        return 1j * v + 1j * self.Delta * np.sign(v)
 
     def __call__(self, n):
         n = np.asarray(n)
-        v = nu(n, self.T)
-        return 1.0 / (1j * v + 1j * self.Delta * np.sign(v) - _on_box(self.sigma, n))
+        scale = 1.0 / self.lam if self.reg == 1 else 1.0
+        return 1.0 / (self.g0inv(n) * scale - _on_box(self.sigma, n))
 
     def line(self, n, kind: int = 0):
         """kind 0: G; 1: S (+ G Sigma_dot G with dsigma); 2: G Sigma_dot G."""
@@ -183,7 +190,12 @@ class MProp:
         gsg = g * _on_box(self.dsigma, n) * g
         if kind == 2:
             return gsg
+        if self.reg == 1:
+            return g * self.g0inv(n) * g / self.lam ** 2 + gsg
         return -1j * np.sign(nu(n, self.T)) * g * g + gsg
+
+
+_MProp = MProp
 
 
 def window(r: int, m: int, Nq: int) -> np.ndarray:
@@ -238,8 +250,8 @@ def bubble(r: int, L: MVertex, R: MVertex, P: MProp, Nq: int, kind: int = 0, tai
     channel, so each class gains its part of L(inf) t(m) R(inf) with t(m) = bare_bubble_sum - the
     window's bare sum.  ms: only these bosonic indices (the others stay zero), for samples of
     large boxes."""
-    if tails and kind != 0:
-        raise ValueError("the analytic tails are those of the bubble G G")
+    if tails and (kind != 0 or P.reg != 0):
+        raise ValueError("the analytic tails are those of the bubble G G of the unregulated G_0")
     g = L.grid
     sh = g.shapes()
     out = {k: np.zeros(s, dtype=np.complex128) for k, s in sh.items()}
@@ -354,10 +366,11 @@ def parquet_iteration(V: MVertex, P: MProp, Nq: int, Nl: int):
     return out, sde(V, P, Nq, Nl)
 
 
-def pt2_state(grid: MGrid, U: float, Delta: float, Nq: int, Nl: int):
-    """PT2 start: K1_r = B_r(Gamma_0, Gamma_0) (the other classes vanish), Sigma^(2) = SDE(Gamma_0)."""
+def pt2_state(grid: MGrid, U: float, Delta: float, Nq: int, Nl: int, reg: int = 0, lam: float = 1.0):
+    """PT2 start: K1_r = B_r(Gamma_0, Gamma_0) (the other classes vanish), Sigma^(2) = SDE(Gamma_0)
+    (reg 1: with G_0 -> lam G_0)."""
     g0 = bare(grid, U)
-    P = MProp(Delta, grid.T)
+    P = MProp(Delta, grid.T, reg=reg, lam=lam)
     chans = []
     for r in range(3):
         b = bubble(r, g0, g0, P, Nq)
@@ -428,12 +441,18 @@ def mloop(V: MVertex, P: MProp, Nq: int, nloops: int, centres: Optional[list] = 
 
 
 def mfrg_rhs(grid: MGrid, U: float, lam: float, nloops: int, Nq: int, Nl: int, chans, sigma,
-             katanin: bool = True, se_iterations: int = 0, se_atol: float = 1e-9, se_rtol: float = 1e-5):
+             katanin: bool = True, se_iterations: int = 0, se_atol: float = 1e-9, se_rtol: float = 1e-5,
+             reg: int = 0, Delta: float = 1.0):
     """Right-hand side of the Matsubara flow in the hybridization Delta = lam (the Keldysh
     oracle's mfrg_rhs with the Matsubara bubble and loop): Sigma_dot^(1) = -L(Gamma, S),
     Gamma_dot = sum_l gdot^(l) with the l = 1 bubble along S (+ G Sigma_dot G with katanin), and
     with se_iterations (nloops >= 3) the corrections Sigma_dot_tbar = -L(gdot_{a,C} + gdot_{p,C},
-    G), Sigma_dot_t = -L(Gamma, G Sigma_dot_tbar G) iterated.  Returns (Gamma_dot, Sigma_dot)."""
+    G), Sigma_dot_t = -L(Gamma, G Sigma_dot_tbar G) iterated.  reg 1: the interaction flow in lam at fixed Delta.  Returns (Gamma_dot,
+    Sigma_dot)."""
+
+    def MProp(lam_, T_, sig_, dsig_=None):  # the propagator along the flow
+        return _MProp(Delta, T_, sig_, dsig_, 1, lam_) if reg == 1 else _MProp(lam_, T_, sig_, dsig_)
+
     V = MVertex(grid, U, chans)
     P = MProp(lam, grid.T, np.asarray(sigma))
     sd1 = -loop(V, P, Nl, 1)
@@ -461,24 +480,26 @@ def mfrg_rhs(grid: MGrid, U: float, lam: float, nloops: int, Nq: int, Nl: int, c
 
 def mfrg_flow(grid: MGrid, U: float, lam_i: float, lam_f: float, steps: int, nloops: int, Nq: int, Nl: int,
               chans, sigma, katanin: bool = True, se_iterations: int = 0, adaptive: bool = False,
-              atol: float = 1e-8, rtol: float = 1e-5, max_steps: int = 200, info: Optional[dict] = None):
+              atol: float = 1e-8, rtol: float = 1e-5, max_steps: int = 200, info: Optional[dict] = None,
+              reg: int = 0, Delta: float = 1.0):
     """The ODE in t with Delta = Lambda(t) = 5 t|t| / sqrt(1 - t^2) (the Keldysh Delta-flow's
     parametrisation) from lam_i to lam_f: classical RK4 in `steps` equal steps, or (adaptive) the
     Cash-Karp step control of the Keldysh flow (Sec. ODE solver) with first trial step
     (t_f - t_i) / steps.  Returns (chans, sigma); info (if given) receives the accepted Delta
-    values and the number of rejected steps."""
-    from .oracle import REG_DELTA, flow_dlambda_dt, flow_lambda, flow_t, ode_solve
+    values and the number of rejected steps.  reg 1: the interaction flow (G_0 -> lam G_0 at fixed
+    Delta, the ODE in lam itself) from lam_i to lam_f."""
+    from .oracle import flow_dlambda_dt, flow_lambda, flow_t, ode_solve
 
     def f(t, vec):
         ch, sg = state_unpack(grid, vec)
-        gd, sd = mfrg_rhs(grid, U, flow_lambda(REG_DELTA, t), nloops, Nq, Nl, ch, np.array(sg), katanin,
-                          se_iterations)
-        return flow_dlambda_dt(REG_DELTA, t) * state_pack(grid, gd, sd)
+        gd, sd = mfrg_rhs(grid, U, flow_lambda(reg, t), nloops, Nq, Nl, ch, np.array(sg), katanin,
+                          se_iterations, reg=reg, Delta=Delta)
+        return flow_dlambda_dt(reg, t) * state_pack(grid, gd, sd)
 
-    y, ts, rejected = ode_solve(f, state_pack(grid, chans, sigma), flow_t(REG_DELTA, lam_i),
-                                flow_t(REG_DELTA, lam_f), steps, adaptive, atol, rtol, max_steps)
+    y, ts, rejected = ode_solve(f, state_pack(grid, chans, sigma), flow_t(reg, lam_i), flow_t(reg, lam_f), steps,
+                                adaptive, atol, rtol, max_steps)
     if info is not None:
-        info["lambdas"] = [flow_lambda(REG_DELTA, t) for t in ts]
+        info["lambdas"] = [flow_lambda(reg, t) for t in ts]
         info["rejected"] = rejected
     ch, sg = state_unpack(grid, y)
     return ch, np.array(sg)

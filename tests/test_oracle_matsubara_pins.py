@@ -309,3 +309,34 @@ def test_matsubara_flow_step_control_converges_onto_the_extrapolated_rk4_flow():
     assert len(loose["lambdas"]) < len(tight["lambdas"])
     for inf in (tight, loose):
         assert abs(inf["lambdas"][0] - 2.0) < 1e-12 and abs(inf["lambdas"][-1] - 1.0) < 1e-12
+
+
+def test_matsubara_interaction_regulator():
+    """Interaction flow (G_0 -> lam G_0): S is dG/dlam at fixed Sigma, the Pi_dot bubble is the
+    lam-derivative of the bubble, the PT2 vertex scales exactly as lam^2, and the one-loop flow of
+    the PT2 state from lam = 0.5 to 1 reaches the PT2 vertex at lam = 1 up to O(U^3)."""
+    g = MF.MGrid(6, 3, T)
+    Nq, Nl = 8, 6
+    sig = 0.2 * np.exp(1j * np.linspace(0.0, 2.0, 10)) - 0.05j
+    P = MF.MProp(1.3, T, sig, reg=1, lam=0.7)
+    n, h = np.arange(-8, 8), 1e-5
+    d = (MF.MProp(1.3, T, sig, reg=1, lam=0.7 + h)(n) - MF.MProp(1.3, T, sig, reg=1, lam=0.7 - h)(n)) / (2 * h)
+    assert np.abs(P.line(n, 1) - d).max() < 1e-8 * np.abs(d).max()
+    V = MF.bare(g, 1.0)
+    bp = MF.bubble(0, V, V, MF.MProp(1.3, T, sig, reg=1, lam=0.7 + h), Nq)
+    bm = MF.bubble(0, V, V, MF.MProp(1.3, T, sig, reg=1, lam=0.7 - h), Nq)
+    b1 = MF.bubble(0, V, V, P, Nq, 1)
+    dk = (bp.K1 - bm.K1) / (2 * h)
+    assert np.abs(b1.K1 - dk).max() < 1e-7 * np.abs(dk).max()
+    k_half = MF.pt2_state(g, 1.0, 1.0, Nq, Nl, reg=1, lam=0.5)[0]
+    k_one = MF.pt2_state(g, 1.0, 1.0, Nq, Nl, reg=1, lam=1.0)[0]
+    for r in range(3):
+        assert np.abs(k_half[r].K1 - 0.25 * k_one[r].K1).max() < 1e-14 * np.abs(k_one[r].K1).max()
+    devs = []
+    for u in (0.2, 0.1):
+        chans, s0 = MF.pt2_state(g, u, 1.0, Nq, Nl, reg=1, lam=0.5)
+        ch, _ = MF.mfrg_flow(g, u, 0.5, 1.0, 4, 1, Nq, Nl, chans, s0, reg=1, Delta=1.0)
+        ref, _ = MF.pt2_state(g, u, 1.0, Nq, Nl, reg=1, lam=1.0)
+        devs.append(max(np.abs(ch[r].K1 - ref[r].K1).max() / np.abs(ref[r].K1).max() for r in range(3)))
+    assert devs[0] < 0.05
+    assert 0.3 < devs[1] / devs[0] < 0.7
