@@ -279,13 +279,18 @@ typedef struct {
 
 /* G(i nu_n) = 1/(i nu_n + i Delta sgn(nu_n) - Sigma(n)) (level 0: particle-hole symmetric model
    with U/2 absorbed); sigma: device complex on n in [-sigma_N, sigma_N) or NULL.  The flow
-   parameter of the Matsubara flow is Delta: S = dG/dDelta at fixed Sigma = -i sgn(nu) G^2,
-   plus G Sigma_dot G with dsigma (device complex on the same box, or NULL). */
+   parameter is Delta (reg KQFT_REG_DELTA, 0): S = dG/dDelta at fixed Sigma = -i sgn(nu) G^2;
+   or lam (reg KQFT_REG_U, the interaction flow of Sec. "Flow schemes"): G_0 -> lam G_0, so
+   G = 1/(G_0^-1/lam - Sigma) and S = dG/dlam at fixed Sigma = G G_0^-1 G / lam^2 (lam > 0);
+   plus G Sigma_dot G with dsigma (device complex on the same box, or NULL).  Another reg:
+   KQFT_EINVAL. */
 typedef struct {
   double Delta;
   const double* sigma;
   int sigma_N;
   const double* dsigma;
+  int reg;
+  double lam;
 } kqft_mprop;
 
 /*
@@ -492,7 +497,8 @@ int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, dou
 /*
  * kqft_mfrg_flow_matsubara -- the mfRG flow (Sec. "mfRG") in the Matsubara formalism with the
  * hybridization as flow parameter (Delta from Lambda_i to Lambda_f; the ODE in t with
- * Delta = 5 t|t| / sqrt(1 - t^2): classical RK4 in `steps` equal steps, or with adaptive = 1
+ * Delta = 5 t|t| / sqrt(1 - t^2); with reg = KQFT_REG_U the interaction flow G_0 -> Lambda G_0
+ * at the fixed hybridization `Delta` (unused otherwise), the ODE in Lambda itself): classical RK4 in `steps` equal steps, or with adaptive = 1
  * the Cash-Karp step control of kqft_mfrg_flow (tolerances ode_tol_abs/ode_tol_rel on the
  * whole state, first trial step (t_f - t_i)/steps, at most max_steps trial steps, else
  * KQFT_ENOCONV with the state where it stopped)):
@@ -510,7 +516,7 @@ int kqft_mfrg_flow(kqft_ctx* ctx, const kqft_grid* grid, double U, double T, dou
  * trial step (adaptive).
  */
 int kqft_mfrg_flow_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, double Lambda_i, double Lambda_f,
-                             int steps, int nloops, int Nq, int Nl, int katanin, int se_iterations, double se_tol_abs,
+                             int reg, double Delta, int steps, int nloops, int Nq, int Nl, int katanin, int se_iterations, double se_tol_abs,
                              double se_tol_rel, int adaptive, double ode_tol_abs, double ode_tol_rel, int max_steps,
                              const kqft_chout* gamma, double* sigma, double* lambdas, kqft_flow_info* info,
                              void* stream);

@@ -1305,6 +1305,8 @@ int kqft_chi(kqft_ctx* ctx, int channel, const kqft_vertex* gamma, const kqft_pr
 
 static int check_mprop(const kqft_mprop& G) {
   if (!(G.Delta > 0)) return fail(KQFT_EINVAL, "Delta must be positive");
+  if (G.reg != KQFT_REG_DELTA && G.reg != KQFT_REG_U) return fail(KQFT_EINVAL, "unknown Matsubara regulator");
+  if (G.reg == KQFT_REG_U && !(G.lam > 0)) return fail(KQFT_EINVAL, "the interaction regulator needs lam > 0");
   if (G.sigma_N < 0 || ((G.sigma || G.dsigma) && G.sigma_N == 0)) return fail(KQFT_ESHAPE, "invalid self-energy box");
   return KQFT_OK;
 }
@@ -1324,6 +1326,8 @@ static MGatherArgs mf_side(const kqft_mgrid& g, int channel, int kind, int Nq, c
   a.dsigma = (const double2*)G.dsigma;
   a.Ns = (G.sigma || G.dsigma) ? G.sigma_N : 0;
   a.U = v.U;
+  a.reg = G.reg;
+  a.lam = G.lam;
   for (int r = 0; r < 3; ++r)
     a.ch[r] = MChan{v.ch[r].coef, {(const double2*)v.ch[r].K1, (const double2*)v.ch[r].K2,
                                    (const double2*)v.ch[r].K2p, (const double2*)v.ch[r].K3}};
@@ -1464,6 +1468,8 @@ int kqft_bubble_matsubara(kqft_ctx* ctx, int channel, const kqft_mvertex* left, 
   if (pi_kind != KQFT_PI_GG && pi_kind != KQFT_PI_DOT) return fail(KQFT_EINVAL, "unknown bubble kind");
   if (tails != 0 && (tails != 1 || pi_kind != KQFT_PI_GG))
     return fail(KQFT_EINVAL, "tails must be 0 or 1, and 1 only for the bubble G G");
+  if (tails && G && G->reg != KQFT_REG_DELTA)
+    return fail(KQFT_EINVAL, "the analytic tails need the unregulated G_0 (reg = KQFT_REG_DELTA)");
   const kqft_mgrid g = left->grid;
   if (g.M < 0 || g.N < 1 || Nq < 1) return fail(KQFT_ESHAPE, "need M >= 0, N >= 1, Nq >= 1");
   if (right->grid.M != g.M || right->grid.N != g.N || right->grid.T != g.T)
@@ -1605,6 +1611,8 @@ int kqft_sde_matsubara(kqft_ctx* ctx, const kqft_mvertex* gamma, const kqft_mpro
   la.Nl = Nl;
   la.T = g.T;
   la.Delta = G->Delta;
+  la.reg = G->reg;
+  la.lam = G->lam;
   la.sigma = (const double2*)G->sigma;
   la.Ns = G->sigma ? G->sigma_N : 0;
   la.K1 = ph;
@@ -1736,7 +1744,7 @@ static const double kCkB5[6] = {37.0 / 378, 0.0, 250.0 / 621, 125.0 / 594, 0.0, 
 static const double kCkB4[6] = {2825.0 / 27648, 0.0, 18575.0 / 48384, 13525.0 / 55296, 277.0 / 14336, 1.0 / 4};
 
 int kqft_mfrg_flow_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, double Lambda_i, double Lambda_f,
-                             int steps, int nloops, int Nq, int Nl, int katanin, int se_iterations, double se_tol_abs,
+                             int reg, double Delta, int steps, int nloops, int Nq, int Nl, int katanin, int se_iterations, double se_tol_abs,
                              double se_tol_rel, int adaptive, double ode_tol_abs, double ode_tol_rel, int max_steps,
                              const kqft_chout* gamma, double* sigma, double* lambdas, kqft_flow_info* info,
                              void* stream) {
@@ -1745,8 +1753,11 @@ int kqft_mfrg_flow_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, do
   if (!grid || !gamma || !sigma) return fail(KQFT_EINVAL, "grid, gamma and sigma must be given");
   const kqft_mgrid g = *grid;
   if (g.M < 0 || g.N < 1 || Nq < 1 || Nl < 1) return fail(KQFT_ESHAPE, "need M >= 0, N >= 1, Nq >= 1, Nl >= 1");
-  if (!(g.T > 0) || !(Lambda_i > 0) || !(Lambda_f > 0) || Lambda_i > 1e6 || Lambda_f > 1e6)
-    return fail(KQFT_EINVAL, "need T > 0 and 0 < Delta <= 1e6 along the flow");
+  if (reg != KQFT_REG_DELTA && reg != KQFT_REG_U) return fail(KQFT_EINVAL, "the Matsubara flow runs in Delta or U");
+  if (!(g.T > 0) || !(Lambda_i > 0) || !(Lambda_f > 0) || (reg == KQFT_REG_U && !(Delta > 0)))
+    return fail(KQFT_EINVAL, "need T > 0, a positive flow parameter and Delta > 0");
+  if (reg == KQFT_REG_DELTA && (Lambda_i > 1e6 || Lambda_f > 1e6))
+    return fail(KQFT_EINVAL, "Delta-flow parameter beyond the reparametrisation's range");
   if (steps < 1 || nloops < 1) return fail(KQFT_EINVAL, "need steps >= 1 and nloops >= 1");
   if (se_iterations < 0 || !(se_tol_abs >= 0) || !(se_tol_rel >= 0))
     return fail(KQFT_EINVAL, "self-energy correction settings must be non-negative");
@@ -1801,20 +1812,25 @@ int kqft_mfrg_flow_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, do
   };
   auto rhs = [&](double t, double2* yb, double2* kout) -> int {
     int e;
-    const double lam = flow_lambda(KQFT_REG_DELTA, t);
+    const double lam = flow_lambda(reg, t);
     ++inf.rhs_evaluations;
+    // the propagator at the flow parameter: Delta = lam, or G_0 -> lam G_0 at fixed Delta
+    auto prop = [&](const double* sg, const double* dsg) {
+      kqft_mprop p{reg == KQFT_REG_U ? Delta : lam, sg, g.N, dsg, reg, reg == KQFT_REG_U ? lam : 1.0};
+      return p;
+    };
     kqft_mvertex V;
     memset(&V, 0, sizeof V);
     V.grid = g;
     V.U = U;
     for (int r = 0; r < 3; ++r) V.ch[r] = chvert(1.0, yb + (size_t)r * chc);
-    const kqft_mprop G{lam, (const double*)(yb + 3 * chc), g.N, nullptr};
+    const kqft_mprop G = prop((const double*)(yb + 3 * chc), nullptr);
     // Sigma_dot^(1) = -L(Gamma, S)
     if ((e = kqft_loop_matsubara(ctx, &V, &G, KQFT_LINE_S, Nl, (double*)sd1, stream))) return e;
     launch_axpby(sd1, -1.0, sd1, 0.0, sd1, nf, s);
     launch_axpby(sdk, 1.0, sd1, 0.0, sd1, nf, s);
     for (int it = 0;;) {
-      const kqft_mprop Gk{lam, (const double*)(yb + 3 * chc), g.N, katanin ? (const double*)sdk : nullptr};
+      const kqft_mprop Gk = prop((const double*)(yb + 3 * chc), katanin ? (const double*)sdk : nullptr);
       for (int l = 0; l < nloops; ++l)
         for (int r = 0; r < 3; ++r) {
           const kqft_chout o = chout(ins(l, r));
@@ -1862,7 +1878,7 @@ int kqft_mfrg_flow_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, do
       for (int r = 0; r < 2; ++r) Vc.ch[r] = chvert(1.0, cen + (size_t)r * chc);
       if ((e = kqft_loop_matsubara(ctx, &Vc, &G, KQFT_LINE_G, Nl, (double*)tb, stream))) return e;
       launch_axpby(tb, -1.0, tb, 0.0, tb, nf, s);
-      const kqft_mprop Gt{lam, (const double*)(yb + 3 * chc), g.N, (const double*)tb};
+      const kqft_mprop Gt = prop((const double*)(yb + 3 * chc), (const double*)tb);
       if ((e = kqft_loop_matsubara(ctx, &V, &Gt, KQFT_LINE_GSG, Nl, (double*)sdt, stream))) return e;
       const double2* ks[2] = {tb, sdt};
       const double cs[2] = {1.0, -1.0};
@@ -1883,7 +1899,7 @@ int kqft_mfrg_flow_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, do
       if (md <= se_tol_abs + se_tol_rel * mv || it >= se_iterations) break;
     }
     // Gamma_dot = sum over the loop orders, Sigma_dot; times dLambda/dt
-    const double dl = flow_dlambda_dt(KQFT_REG_DELTA, t);
+    const double dl = flow_dlambda_dt(reg, t);
     for (int r = 0; r < 3; ++r) {
       std::vector<const double2*> ks;
       std::vector<double> cs;
@@ -1902,10 +1918,10 @@ int kqft_mfrg_flow_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U, do
       HIP_TRY(hipMemcpyAsync(cls(Y + (size_t)r * chc, c), src[c], cnt[c] * sizeof(double2), hipMemcpyDeviceToDevice, s));
   }
   HIP_TRY(hipMemcpyAsync(Y + 3 * chc, sigma, nf * sizeof(double2), hipMemcpyDeviceToDevice, s));
-  const double ti = flow_t(KQFT_REG_DELTA, Lambda_i), tf = flow_t(KQFT_REG_DELTA, Lambda_f);
+  const double ti = flow_t(reg, Lambda_i), tf = flow_t(reg, Lambda_f);
   int nrec = 0;
   auto record = [&](double t) {
-    if (lambdas) lambdas[nrec] = flow_lambda(KQFT_REG_DELTA, t);
+    if (lambdas) lambdas[nrec] = flow_lambda(reg, t);
     ++nrec;
   };
   record(ti);

@@ -2178,7 +2178,8 @@ __device__ inline double2 mf_G(const MGatherArgs& a, int n) {
   const double v = (2.0 * n + 1.0) * M_PI * a.T;
   double2 sg = czero();
   if (a.sigma && n >= -a.Ns && n < a.Ns) sg = a.sigma[n + a.Ns];
-  return cinv(make_double2(-sg.x, v + (v > 0.0 ? a.Delta : -a.Delta) - sg.y));
+  const double d0 = (v + (v > 0.0 ? a.Delta : -a.Delta)) * (a.reg ? 1.0 / a.lam : 1.0);
+  return cinv(make_double2(-sg.x, d0 - sg.y));
 }
 
 // X(n) of the lines: 0 G, 1 S = -i sgn(nu) G^2 + G Sigma_dot G, 2 G Sigma_dot G
@@ -2190,6 +2191,11 @@ __device__ inline double2 mf_line(const MGatherArgs& a, int n, int line) {
   const double2 gsg = cmul(cmul(g, ds), g);
   if (line == 2) return gsg;
   const double2 g2 = cmul(g, g);
+  if (a.reg) {  // G G_0^-1 G / lam^2 with G_0^-1 = i (nu + Delta sgn nu)
+    const double v = (2.0 * n + 1.0) * M_PI * a.T;
+    const double w = (v + (v > 0.0 ? a.Delta : -a.Delta)) / (a.lam * a.lam);
+    return cadd(make_double2(-w * g2.y, w * g2.x), gsg);
+  }
   const double sg = (2.0 * n + 1.0) > 0.0 ? 1.0 : -1.0;
   return cadd(make_double2(sg * g2.y, -sg * g2.x), gsg);  // -i sgn G^2
 }
@@ -2308,7 +2314,8 @@ __global__ __launch_bounds__(256) void mf_loop_kernel(MLoopArgs a) {
     const double v = (2.0 * k + 1.0) * M_PI * a.T;
     double2 sg = czero();
     if (a.sigma && k >= -a.Ns && k < a.Ns) sg = a.sigma[k + a.Ns];
-    const double2 g = cinv(make_double2(-sg.x, v + (v > 0.0 ? a.Delta : -a.Delta) - sg.y));
+    const double d0 = (v + (v > 0.0 ? a.Delta : -a.Delta)) * (a.reg ? 1.0 / a.lam : 1.0);
+    const double2 g = cinv(make_double2(-sg.x, d0 - sg.y));
     acc = cadd(acc, cmul(cadd(cscale(2.0, X), Y), g));
   }
   a.out[i] = cscale(-0.5 * a.T, acc);

@@ -265,6 +265,8 @@ struct MGatherArgs {
   const double2* dsigma;  // Sigma_dot on the same box (Katanin), or null
   int Ns;
   double U;  // bare vertex X0 = -U, Y0 = +U
+  int reg;     // 0: G_0^-1 = i nu + i Delta sgn nu; 1: G_0 -> lam G_0 (interaction flow)
+  double lam;
   MChan ch[3];
   double mix[4];
   double2* P[2];
@@ -281,6 +283,8 @@ struct MEpiArgs {
 struct MLoopArgs {
   int M, N, Nl;
   double T, Delta;
+  int reg;  // as MGatherArgs
+  double lam;
   const double2* sigma;  // G's self-energy on [-Ns, Ns), or null
   int Ns;
   const double2* K1;

@@ -53,7 +53,8 @@ class KqftMVertex(C.Structure):
 
 
 class KqftMProp(C.Structure):
-    _fields_ = [("Delta", C.c_double), ("sigma", C.c_void_p), ("sigma_N", C.c_int), ("dsigma", C.c_void_p)]
+    _fields_ = [("Delta", C.c_double), ("sigma", C.c_void_p), ("sigma_N", C.c_int), ("dsigma", C.c_void_p),
+                ("reg", C.c_int), ("lam", C.c_double)]
 
 
 class KqftPropagator(C.Structure):
@@ -134,7 +135,7 @@ def lib():
         _lib.kqft_loop_matsubara.argtypes = [C.c_void_p, P(KqftMVertex), P(KqftMProp), C.c_int, C.c_int, C.c_void_p,
                                              C.c_void_p]
         _lib.kqft_mfrg_flow_matsubara.argtypes = [C.c_void_p, P(KqftMGrid), C.c_double, C.c_double, C.c_double,
-                                                  C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
+                                                  C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
                                                   C.c_double, C.c_int, C.c_double, C.c_double, C.c_int,
                                                   P(KqftChout), C.c_void_p, C.c_void_p, P(KqftFlowInfo), C.c_void_p]
         _lib.kqft_sde_matsubara.argtypes = [C.c_void_p, P(KqftMVertex), P(KqftMProp), C.c_int, C.c_int, C.c_void_p,
@@ -412,18 +413,20 @@ def chi(channel: int, gamma: Vertex, G: Propagator, q: Quad, stream=None) -> tor
     return out
 
 
-def _mprop(Delta: float, sigma: Optional[torch.Tensor], dsigma: Optional[torch.Tensor]) -> KqftMProp:
+def _mprop(Delta: float, sigma: Optional[torch.Tensor], dsigma: Optional[torch.Tensor], reg: int = 0,
+           lam: float = 1.0) -> KqftMProp:
     ref = sigma if sigma is not None else dsigma
     ns = 0 if ref is None else ref.shape[0] // 2
     for t in (sigma, dsigma):
         if t is not None and t.shape[0] != 2 * ns:
             raise ValueError("sigma and dsigma need the same even length 2 Ns")
-    return KqftMProp(Delta, _ptr(sigma, None, "sigma"), ns, _ptr(dsigma, None, "dsigma"))
+    return KqftMProp(Delta, _ptr(sigma, None, "sigma"), ns, _ptr(dsigma, None, "dsigma"), reg, lam)
 
 
 def bubble_matsubara(channel: int, left: MVertex, right: MVertex, Delta: float, Nq: int,
                      sigma: Optional[torch.Tensor] = None, out: Optional[Channel] = None, pi_kind: int = PI_GG,
-                     dsigma: Optional[torch.Tensor] = None, tails: bool = False, stream=None) -> Channel:
+                     dsigma: Optional[torch.Tensor] = None, tails: bool = False, reg: int = 0, lam: float = 1.0,
+                     stream=None) -> Channel:
     """B_channel(left, right) in the Matsubara formalism (sum over 2 Nq fermionic frequencies about
     the bubble's centre); sigma: Sigma(i nu_n) on n in [-Ns, Ns) (length 2 Ns) or None; pi_kind
     PI_DOT: Pi_dot along S = dG/dDelta (+ G dsigma G); tails: the analytic tails beyond the window."""
@@ -431,7 +434,7 @@ def bubble_matsubara(channel: int, left: MVertex, right: MVertex, Delta: float, 
     dev = torch.device("cuda", torch.cuda.current_device())
     if out is None:
         out = Channel(1.0, *[torch.zeros(g.shape(c), dtype=torch.complex128, device=dev) for c in CLASSES])
-    gp = _mprop(Delta, sigma, dsigma)
+    gp = _mprop(Delta, sigma, dsigma, reg, lam)
     oc = KqftChout(*[_ptr(getattr(out, c), g.shape(c), f"out.{c}") for c in CLASSES])
     lc, rc = left.c(), right.c()
     _check(lib().kqft_bubble_matsubara(ctx(), channel, C.byref(lc), C.byref(rc), C.byref(gp), pi_kind, Nq,
@@ -480,11 +483,12 @@ def chi_matsubara(channel: int, gamma: MVertex, Delta: float, Nq: int, sigma: Op
 
 
 def loop_matsubara(gamma: MVertex, Delta: float, Nl: int, kind: int = LINE_G, sigma: Optional[torch.Tensor] = None,
-                   dsigma: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+                   dsigma: Optional[torch.Tensor] = None, reg: int = 0, lam: float = 1.0,
+                   stream=None) -> torch.Tensor:
     """L(Gamma, X)(i nu_n), n in [-N, N), X = G, S (+ G dsigma G) or G dsigma G."""
     g = gamma.grid
     out = torch.zeros(2 * g.N, dtype=torch.complex128, device=torch.device("cuda", torch.cuda.current_device()))
-    gp = _mprop(Delta, sigma, dsigma)
+    gp = _mprop(Delta, sigma, dsigma, reg, lam)
     vc = gamma.c()
     _check(lib().kqft_loop_matsubara(ctx(), C.byref(vc), C.byref(gp), kind, Nl, C.c_void_p(out.data_ptr()),
                                      _stream(stream)))
@@ -494,7 +498,7 @@ def loop_matsubara(gamma: MVertex, Delta: float, Nl: int, kind: int = LINE_G, si
 def mfrg_flow_matsubara(grid: MGrid, U: float, lam_i: float, lam_f: float, steps: int, nloops: int, Nq: int, Nl: int,
                         gamma: Sequence[Channel], sigma: torch.Tensor, katanin: bool = True, se_iterations: int = 0,
                         se_atol: float = 1e-9, se_rtol: float = 1e-5, adaptive: bool = False, atol: float = 1e-8,
-                        rtol: float = 1e-5, max_steps: int = 200, stream=None):
+                        rtol: float = 1e-5, max_steps: int = 200, reg: int = 0, Delta: float = 1.0, stream=None):
     """The Matsubara hybridization flow of the state (gamma[3], sigma [2N]) from lam_i to lam_f,
     in place (classical RK4, or Cash-Karp step control with adaptive).  Returns (gamma, sigma,
     info) with info the accepted Delta values and the step counts."""
@@ -505,7 +509,7 @@ def mfrg_flow_matsubara(grid: MGrid, U: float, lam_i: float, lam_f: float, steps
     lams = (C.c_double * ((max_steps if adaptive else steps) + 1))()
     inf = KqftFlowInfo()
     _check(lib().kqft_mfrg_flow_matsubara(ctx(), C.byref(gc), C.c_double(U), C.c_double(lam_i), C.c_double(lam_f),
-                                          steps, nloops, Nq, Nl, int(katanin), se_iterations, C.c_double(se_atol),
+                                          reg, C.c_double(Delta), steps, nloops, Nq, Nl, int(katanin), se_iterations, C.c_double(se_atol),
                                           C.c_double(se_rtol), int(adaptive), C.c_double(atol), C.c_double(rtol),
                                           max_steps, D, C.c_void_p(sigma.data_ptr()), lams, C.byref(inf),
                                           _stream(stream)))

@@ -350,3 +350,55 @@ def test_matsubara_chi_full_box_time_and_samples():
         im = [m + M for m in ms]
         e = _rel(out.cpu().numpy()[:, im], ref[:, im])
         assert e < 1e-12, (r, e)
+
+
+@pytest.mark.parametrize("r", [0, 1, 2])
+def test_matsubara_interaction_regulator_matches_oracle(r):
+    """G_0 -> lam G_0 (lam = 0.7): the G G and the S G + G S bubbles (with Sigma and Sigma_dot)
+    and the S loop against the oracle to 1e-12; the analytic tails refuse the regulated G_0."""
+    K = _K()
+    M, N, Nq = 5, 6, 9
+    oL, kL = _pair(M, N, 70 + r)
+    oR, kR = _pair(M, N, 80 + r, U=-0.5)
+    Ns = N + 2
+    sig = 0.2 * np.exp(1j * np.linspace(0.0, 3.0, 2 * Ns)) - 0.1j
+    dsig = 0.3 * np.exp(-1j * np.linspace(0.0, 2.0, 2 * Ns))
+    P = MF.MProp(D, T, sig, dsig, reg=1, lam=0.7)
+    for kind in (0, 1):
+        ref = MF.bubble(r, oL, oR, P, Nq, kind)
+        out = K.bubble_matsubara(r, kL, kR, D, Nq, sigma=to_dev(sig), dsigma=to_dev(dsig), pi_kind=kind, reg=1,
+                                 lam=0.7)
+        torch.cuda.synchronize()
+        for x in CL:
+            assert _rel(getattr(out, x).cpu().numpy(), getattr(ref, x)) < 1e-12, (kind, x)
+    if r == 0:
+        ref = MF.loop(oL, P, 7, 1)
+        out = K.loop_matsubara(kL, D, 7, K.LINE_S, sigma=to_dev(sig), dsigma=to_dev(dsig), reg=1, lam=0.7)
+        assert _rel(out.cpu().numpy(), ref) < 1e-12
+        with pytest.raises(K.KqftError):
+            K.bubble_matsubara(0, kL, kR, D, Nq, tails=True, reg=1, lam=0.7)
+        with pytest.raises(K.KqftError):
+            K.bubble_matsubara(0, kL, kR, D, Nq, reg=1, lam=0.0)
+
+
+def test_matsubara_interaction_flow_matches_oracle():
+    """The Matsubara interaction flow from the PT2 state at lam = 0.5 to lam = 1 (Delta = 1,
+    M = 8, N = 3, two loops, Katanin, one RK4 step) against the oracle to 1e-10."""
+    K = _K()
+    M, N, Nq, Nl, U = 8, 3, 8, 6, 1.0
+    og = MF.MGrid(M, N, T)
+    chans, sig = MF.pt2_state(og, U, 1.0, Nq, Nl, reg=1, lam=0.5)
+    rch, rsig = MF.mfrg_flow(og, U, 0.5, 1.0, 1, 2, Nq, Nl, chans, sig, True, 0, reg=1, Delta=1.0)
+    kch = [K.Channel(1.0, *[to_dev(getattr(c, x)) for x in CL]) for c in chans]
+    ksig = to_dev(sig)
+    _, _, info = K.mfrg_flow_matsubara(K.MGrid(M, N, T), U, 0.5, 1.0, 1, 2, Nq, Nl, kch, ksig, katanin=True,
+                                       reg=1, Delta=1.0)
+    torch.cuda.synchronize()
+    assert np.abs(np.array(info["lambdas"]) - [0.5, 1.0]).max() < 1e-14
+    for r in range(3):
+        for x in CL:
+            b = getattr(rch[r], x)
+            if np.abs(b).max() == 0.0:
+                continue
+            assert _rel(getattr(kch[r], x).cpu().numpy(), b) < 1e-10, (r, x)
+    assert _rel(ksig.cpu().numpy(), rsig) < 1e-10
