@@ -13,8 +13,10 @@
  * mfRG flow (regulators, Katanin substitution, self-energy corrections, Cash-Karp step
  * control), the asymmetric model (Hartree term, parquet solver and flow with the
  * self-energy's asymptotic value), susceptibilities of every channel, the bubble with
- * adaptive Gauss-Lobatto-Kronrod integration, and the finite-temperature Matsubara
- * formalism (bubble, SDE, loop, parquet solver, hybridization flow).
+ * adaptive Gauss-Lobatto-Kronrod integration, the paper's algebraic frequency grid and the
+ * regridding of a state between grids, and the finite-temperature Matsubara formalism
+ * (bubble with analytic tails, SDE, loop, susceptibilities, parquet solver, hybridization
+ * and interaction flows).
  *
  * Conventions shared by every entry point
  *   Keldysh basis: rotated, alpha in {0,1}; G^{0|0}=0, G^{0|1}=G^A, G^{1|0}=G^R,
