@@ -2321,12 +2321,13 @@ __global__ __launch_bounds__(256) void mf_loop_kernel(MLoopArgs a) {
   a.out[i] = cscale(-0.5 * a.T, acc);
 }
 
-__global__ __launch_bounds__(256) void mf_vloop_kernel(MGatherArgs a, int line, int Nl, double2* out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 2 * a.N) return;
+// one wavefront per output frequency: the lanes stride over the summation index, then a
+// fixed-order LDS reduction (deterministic)
+__global__ __launch_bounds__(64) void mf_vloop_kernel(MGatherArgs a, int line, int Nl, double2* out) {
+  const int i = blockIdx.x;
   const int n = i - a.N;
   double2 acc = czero();
-  for (int k = -Nl; k < Nl; ++k) {
+  for (int k = -Nl + (int)threadIdx.x; k < Nl; k += 64) {
     // legs (n, k | n, k) in channel a: m = n - k, n_a = k, n'_a = k
     const int m = n - k;
     double2 XY[2] = {make_double2(-a.U, 0.0), make_double2(a.U, 0.0)};
@@ -2334,11 +2335,18 @@ __global__ __launch_bounds__(256) void mf_vloop_kernel(MGatherArgs a, int line, 
     mf_others(a, m, k, k, XY);
     acc = cadd(acc, cmul(cadd(cscale(2.0, XY[0]), XY[1]), mf_line(a, k, line)));
   }
-  out[i] = cscale(a.T, acc);
+  __shared__ double2 red[64];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 32; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = cscale(a.T, red[0]);
 }
 
 void launch_mf_vloop(const MGatherArgs& v, int line, int Nl, double2* out, hipStream_t s) {
-  hipLaunchKernelGGL(mf_vloop_kernel, dim3((unsigned)((2 * v.N + 255) / 256)), dim3(256), 0, s, v, line, Nl, out);
+  hipLaunchKernelGGL(mf_vloop_kernel, dim3((unsigned)(2 * v.N)), dim3(64), 0, s, v, line, Nl, out);
 }
 
 void launch_mf_loop(const MLoopArgs& a, hipStream_t s) {
