@@ -131,7 +131,9 @@ typedef struct {
   int smap;  // map of the Sigma grid
 } OProp;
 // quadrature: n Gauss-Legendre nodes, map 0 = tangent onto [-L, L] with scale a,
-// map 1 = v = a tan(pi y / 2) onto the real line.
+// map 1 = v = a tan(pi y / 2) onto the real line; map 2 = the n nodes of the tangent grid
+// (n, L, a) themselves with trapezoid weights on its auxiliary variable (a rule whose nodes
+// are grid points, so that a vertex stored on that grid is read back without interpolation).
 typedef struct {
   int n, map;
   double L, a;
@@ -222,10 +224,22 @@ static void gauss_legendre(int n, double* x, double* w) {
 }
 
 static void make_quad(const OQuad& q, std::vector<double>& nu, std::vector<double>& wt) {
-  std::vector<double> y(q.n), gw(q.n);
-  gauss_legendre(q.n, y.data(), gw.data());
   nu.resize(q.n);
   wt.resize(q.n);
+  if (q.map == 2) {
+    // trapezoid rule in x on the grid's own nodes: v = a tan(x theta), dv = a theta sec^2 dx
+    Grid g = make_grid(q.n, q.L, q.a, 0);
+    const double h = 2.0 / (q.n - 1);
+    for (int k = 0; k < q.n; ++k) {
+      double x = -1.0 + 2.0 * k / (q.n - 1);
+      double c = std::cos(x * g.theta);
+      nu[k] = grid_node(g, k);
+      wt[k] = ((k == 0 || k == q.n - 1) ? 0.5 : 1.0) * h * q.a * g.theta / (c * c);
+    }
+    return;
+  }
+  std::vector<double> y(q.n), gw(q.n);
+  gauss_legendre(q.n, y.data(), gw.data());
   for (int k = 0; k < q.n; ++k) {
     if (q.map == 0) {
       double th = std::atan(q.L / q.a);

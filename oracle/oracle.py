@@ -114,7 +114,9 @@ class Grid:
 
 @dataclass
 class Quad:
-    """n Gauss-Legendre nodes mapped by the tangent map to [-L, L] (map 0) or to R (map 1)."""
+    """n Gauss-Legendre nodes mapped by the tangent map to [-L, L] (map 0) or to R (map 1); map 2:
+    the n nodes of the tangent grid Grid(n, L, a) with trapezoid weights on its auxiliary
+    variable (its nodes are grid points, so vertices on that grid enter without interpolation)."""
     n: int
     map: int = 0
     L: float = 20.0

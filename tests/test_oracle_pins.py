@@ -527,9 +527,9 @@ def test_one_loop_insertion_is_delta_derivative_of_pt2():
         assert np.abs(d1 - fd).max() < 1e-8 * np.abs(d1).max()
 
 
-def test_multiloop_orders_are_multilinear_and_l2_symmetric():
-    """At l = 2, the left and right insertions of a vertex symmetric under exchange of its two
-    sides give mirror-image K2/K2' classes; every order l scales as U^(l+1) for Gamma = Gamma_0."""
+def test_multiloop_orders_scale_as_powers_of_U():
+    """Every multiloop order l is (l+1)-linear in the vertex, so for Gamma = Gamma_0 it scales
+    as U^(l+1) (Eqs. 1l-3l); at l = 1 the insertion of the bare vertex has K1 only."""
     g = O.Grid(7, 8.0, 1.0)
     q = O.Quad(21, 0, 8.0, 1.0)
     P = O.Prop(D, T)
@@ -540,46 +540,202 @@ def test_multiloop_orders_are_multilinear_and_l2_symmetric():
             for c in ("K1", "K2", "K2p", "K3"):
                 a, b = getattr(o1[ell][r], c), getattr(o2[ell][r], c)
                 assert np.allclose(b, 2.0 ** (ell + 2) * a, rtol=1e-12, atol=1e-300)
-    # Gamma_0 inputs: l = 1 has K1 only; l = 2 has K1 (from the rbar vertex's K1 inside) etc.
-    assert np.abs(o1[0][0].K3).max() == 0.0
+    assert all(np.abs(getattr(o1[0][r], c)).max() == 0.0 for r in range(3) for c in ("K2", "K2p", "K3"))
 
 
-def test_multiloop_total_derivative_at_third_order():
-    """The multiloop flow reproduces the total derivative of the parquet vertex (Sec. mfRG:
-    multiloop flow equations).  At third order in U the parquet vertex of channel r is
-    gamma_r^(3) = B_r(Gamma_0, Gamma^(2)) + B_r(I_r^(2), Gamma_0) with Gamma^(2) = sum_r' gamma_r'^(2),
-    I_r^(2) = sum_{r' != r} gamma_r'^(2), gamma^(2) = the PT2 K1; its Delta-derivative (dual
-    numbers) equals the third-order part of the l = 1 and l = 2 insertions of
-    Gamma_0 + gamma^(2): B_r(Gamma_0, Gamma^(2); Pidot) + B_r(Gamma^(2), Gamma_0; Pidot)
-    + B_r(gdot_rbar^(2), Gamma_0) + B_r(Gamma_0, gdot_rbar^(2)), gdot^(2) = B_r'(Gamma_0, Gamma_0; Pidot).
-    The identity is exact in the discrete scheme (the bubble is linear in each vertex and the
-    vertices enter on the grid), so a wrong channel sum, prefactor or Pidot fails it."""
-    g, q = O.Grid(9), O.Quad(31)
+# The multiloop pins below take the insertions from a multiloop implementation passed in
+# (O.mloop itself, or a copy with a planted mistake in the mutation test), so that what they
+# pin is that code, not a hand composition of bubbles.
+def _chan_add(*chs):
+    return O.Channel(1.0, *[sum(getattr(c, k) for c in chs) for k in ("K1", "K2", "K2p", "K3")])
+
+
+def _eps_dual(arr):
+    """Dual array with value 0 and derivative arr: a vertex Gamma_0 + eps*gamma evaluated with it
+    gives, in the derivative part, exactly the term of a multilinear map linear in gamma."""
+    d = np.zeros(arr.shape + (4,))
+    d[..., 1] = arr.real
+    d[..., 3] = arr.imag
+    return d
+
+
+def _parquet_orders(g, q, Ul):
+    """Orders U^2, U^3, U^4 of the parquet vertex in the parquet approximation (R = Gamma_0,
+    Bethe-Salpeter equations gamma_r = B_r(I_r, Gamma), I_r = Gamma_0 + sum_{r' != r} gamma_r',
+    Gamma = Gamma_0 + sum_r gamma_r; Sec. parquet solver) with Sigma = 0, as dual arrays carrying
+    their Delta-derivative: gamma^(2)_r = B_r(G0, G0), gamma^(3)_r = B_r(G0, Gamma^(2)) +
+    B_r(I^(2)_r, G0), gamma^(4)_r = B_r(G0, Gamma^(3)) + B_r(I^(2)_r, Gamma^(2)) + B_r(I^(3)_r, G0)."""
     Pd = O.Prop(D, T, dDelta=1.0)
+    g0 = O.bare(g, Ul)
+
+    def vert(chs, skip=None):
+        return O.Vertex(g, 0.0, [O.Channel(0.0) if rr == skip else chs[rr] for rr in range(3)])
+
+    def B(r, a, b):
+        return O.bubble(r, a, b, Pd, q, 0, O.C_ALL, dual=True)
+
+    g2 = [B(r, g0, g0) for r in range(3)]
+    g3 = [_chan_add(B(r, g0, vert(g2)), B(r, vert(g2, r), g0)) for r in range(3)]
+    g4 = [_chan_add(B(r, g0, vert(g3)), B(r, vert(g2, r), vert(g2)), B(r, vert(g3, r), g0)) for r in range(3)]
+    return g2, g3, g4
+
+
+def _value(ch):
+    return O.Channel(1.0, *[O.dual_parts(getattr(ch, k))[0] for k in ("K1", "K2", "K2p", "K3")])
+
+
+def _deriv(ch):
+    return O.Channel(1.0, *[O.dual_parts(getattr(ch, k))[1] for k in ("K1", "K2", "K2p", "K3")])
+
+
+def _rel_max(a_list, b_list):
+    """max over channels and classes of |a - b|_inf / max |b|_inf."""
+    scale = max(np.abs(getattr(b, k)).max() for b in b_list for k in ("K1", "K2", "K2p", "K3"))
+    assert scale > 0
+    return max(np.abs(getattr(a, k) - getattr(b, k)).max() for a, b in zip(a_list, b_list)
+               for k in ("K1", "K2", "K2p", "K3")) / scale
+
+
+def _total_derivative_residuals(mloop, g, q, Ul=U):
+    """The multiloop flow equations (Sec. mfRG, Eqs. 1l-3l) summed over l reproduce the total
+    Delta-derivative of the parquet vertex (with Sigma fixed, no Katanin term).  Order by order in
+    U, with Gamma = Gamma_0 + gamma^(2) + gamma^(3) and f_l the l-loop insertion (an (l+1)-linear
+    map of Gamma):
+      U^3:  d gamma^(3)/dDelta = [f_1 linear in gamma^(2) at Gamma_0] + f_2(Gamma_0),
+      U^4:  d gamma^(4)/dDelta = [f_1 linear in gamma^(3)] + f_1(gamma^(2)) + [f_2 linear in
+            gamma^(2)] + f_3(Gamma_0),
+    where "linear in gamma" is the derivative part of f_l(Gamma_0 + eps gamma) with dual numbers.
+    Returns the relative residuals (third order, fourth order)."""
     P = O.Prop(D, T)
-    g0d = O.bare(g, U)
-    g0 = O.bare(g, U)
-    k1d = [O.bubble(rr, g0d, g0d, Pd, q, 0, O.C_K1, dual=True).K1 for rr in range(3)]
-    k1 = [O.dual_parts(x)[0] for x in k1d]
-    kdot = [O.bubble(rr, g0, g0, P, q, 1, O.C_K1).K1 for rr in range(3)]
-    # the PT2 derivative itself is the l = 1 insertion of Gamma_0
-    for rr in range(3):
-        assert np.abs(O.dual_parts(k1d[rr])[1] - kdot[rr]).max() < 1e-12 * np.abs(kdot[rr]).max()
-    for r in range(3):
-        all2d = O.Vertex(g, 0.0, [O.Channel(1.0, k1d[rr]) for rr in range(3)])
-        i2d = O.Vertex(g, 0.0, [O.Channel(1.0, k1d[rr]) if rr != r else O.Channel(0.0) for rr in range(3)])
-        a = O.bubble(r, g0d, all2d, Pd, q, 0, O.C_ALL, dual=True)
-        b = O.bubble(r, i2d, g0d, Pd, q, 0, O.C_ALL, dual=True)
-        all2 = O.Vertex(g, 0.0, [O.Channel(1.0, k1[rr]) for rr in range(3)])
-        rbar = O.Vertex(g, 0.0, [O.Channel(1.0, kdot[rr]) if rr != r else O.Channel(0.0) for rr in range(3)])
-        parts = [O.bubble(r, g0, all2, P, q, 1), O.bubble(r, all2, g0, P, q, 1),
-                 O.bubble(r, rbar, g0, P, q, 0), O.bubble(r, g0, rbar, P, q, 0)]
-        scale = max(np.abs(sum(getattr(x, c) for x in parts)).max() for c in ("K1", "K2", "K2p"))
+    g2d, g3d, g4d = _parquet_orders(g, q, Ul)
+    g2 = [_value(c) for c in g2d]
+    g3 = [_value(c) for c in g3d]
+
+    def eps_vertex(chs):
+        return O.Vertex(g, Ul, [O.Channel(1.0, *[_eps_dual(getattr(c, k)) for k in ("K1", "K2", "K2p", "K3")])
+                                for c in chs])
+
+    f_bare = mloop(O.bare(g, Ul), P, q, 3)
+    f_g2 = mloop(eps_vertex(g2), P, q, 2, dual=True)
+    f_g3 = mloop(eps_vertex(g3), P, q, 1, dual=True)
+    f1_g2g2 = mloop(O.Vertex(g, 0.0, g2), P, q, 1)
+    m3 = [_chan_add(_deriv(f_g2[0][r]), f_bare[1][r]) for r in range(3)]
+    m4 = [_chan_add(_deriv(f_g3[0][r]), f1_g2g2[0][r], _deriv(f_g2[1][r]), f_bare[2][r]) for r in range(3)]
+    return (_rel_max(m3, [_deriv(c) for c in g3d]), _rel_max(m4, [_deriv(c) for c in g4d]))
+
+
+def _grid_rule(n, L=20.0, a=1.0):
+    return O.Quad(n, 2, L, a)
+
+
+def test_grid_node_rule_is_a_quadrature_on_the_grid():
+    """The rule used by the fourth-order pin: its nodes are the grid's nodes, and it integrates
+    1/(1 + v^2) over [-L, L] (a linear function of the auxiliary variable, exact for the
+    trapezoid rule) to 2 atan(L)."""
+    g = O.Grid(9)
+    v, w = _grid_rule(9).nodes_weights()
+    assert np.array_equal(v, g.nodes())
+    assert abs(np.sum(w / (1 + v * v)) - 2 * np.arctan(20.0)) < 1e-14
+
+
+def test_multiloop_total_derivative_at_third_and_fourth_order():
+    """The multiloop insertions of O.mloop reproduce the total Delta-derivative of the parquet
+    vertex at third order (l = 1, 2) and fourth order (l = 1, 2, 3 with the centre term) in U.
+    Both identities are exact in the discrete scheme when the within-channel compositions
+    associate: at third order every own-channel object is a K1 (a matrix per transfer frequency),
+    so any Gauss-Legendre rule will do; at fourth order own-channel K2/K2' objects are read back
+    at the loop frequencies, which associates exactly only when the loop frequencies are grid
+    nodes (then every bubble is a plain matrix product over the nodes), hence the grid-node rule.
+    With Gauss-Legendre nodes the fourth-order residual is the interpolation error of those
+    reads (O(h^2)), not zero."""
+    g = O.Grid(9)
+    r3, _ = _total_derivative_residuals(O.mloop, g, O.Quad(31))
+    assert r3 < 1e-12
+    r3, r4 = _total_derivative_residuals(O.mloop, g, _grid_rule(9))
+    assert r3 < 1e-12 and r4 < 1e-12, (r3, r4)
+
+
+def _mirror_residual(mloop, eps=0.0):
+    """At l = 2 the insertion of Gamma_0 is L + R with L = B_r(gdot_rbar, Gamma_0) (class K2 only)
+    and R = B_r(Gamma_0, gdot_rbar) (K2' only).  Reading the bubble with its two sides exchanged
+    maps L onto R: in the t channel K2'(w, v) = K2(-w, v)^T in the Keldysh pair indices; in a and p
+    this holds combined with particle-hole symmetry, K2'(w, v) = K2(-w, -v)^T."""
+    g = O.Grid(7, 8.0, 1.0)
+    q = O.Quad(21, 0, 8.0, 1.0)
+    o = mloop(O.bare(g, 1.0), O.Prop(D, T, eps=eps), q, 2)[1]
+    res = 0.0
+    for r in (range(3) if eps == 0.0 else (2,)):
+        A = o[r].K2.reshape(2, 7, 7, 4, 4).transpose(0, 1, 2, 4, 3)[:, ::-1]
+        if r != 2:
+            A = A[:, :, ::-1]
+        Bm = o[r].K2p.reshape(2, 7, 7, 4, 4)
+        scale = max(np.abs(Bm).max(), np.abs(A).max())
         assert scale > 0
-        for c in ("K1", "K2", "K2p", "K3"):  # third order: K3 vanishes on both sides
-            deriv = O.dual_parts(getattr(a, c))[1] + O.dual_parts(getattr(b, c))[1]
-            ml = sum(getattr(x, c) for x in parts)
-            assert np.abs(deriv - ml).max() < 1e-12 * scale, (r, c)
+        # K1 and K3 must vanish: neither insertion has a part constant in both fermionic arguments
+        res = max(res, np.abs(A - Bm).max() / scale, np.abs(o[r].K1).max() / scale,
+                  np.abs(o[r].K3).max() / scale)
+    return res
+
+
+def test_multiloop_l2_left_and_right_insertions_are_mirror_images():
+    assert _mirror_residual(O.mloop) < 1e-13
+    assert _mirror_residual(O.mloop, eps=0.3) < 1e-13
+
+
+def _mloop_with_mistake(mistake):
+    """A copy of the oracle's multiloop recursion with one planted mistake (CPU only)."""
+    def mloop(V, P, q, nloops, dual=False, centres=None):
+        g = V.grid
+        out = []
+        for ell in range(1, nloops + 1):
+            this = []
+            for r in range(3):
+                if ell == 1:
+                    this.append(O.bubble(r, V, V, P, q, 1, O.C_ALL, dual))
+                    continue
+                prev = out[ell - 2]
+                others = [rr for rr in range(3) if rr != r or mistake == "rbar_includes_r"]
+                rbar = O.combine(g, [(rr, prev[rr], 1.0) for rr in others])
+                if mistake == "right_insertion_twice":
+                    Lt = O.bubble(r, V, rbar, P, q, 0, O.C_ALL, dual)
+                else:
+                    Lt = O.bubble(r, rbar, V, P, q, 0, O.C_ALL, dual)
+                Rt = O.bubble(r, V, rbar, P, q, 0, O.C_ALL, dual)
+                tot = _chan_add(Lt, Rt)
+                if ell >= 3:
+                    prev2 = out[ell - 2] if mistake == "centre_from_previous_order" else out[ell - 3]
+                    rbar2 = O.combine(g, [(rr, prev2[rr], 1.0) for rr in range(3) if rr != r])
+                    if mistake == "centre_inner_mirrored":
+                        inner = O.bubble(r, V, rbar2, P, q, 0, O.C_ALL, dual)
+                    else:
+                        inner = O.bubble(r, rbar2, V, P, q, 0, O.C_ALL, dual)
+                    iv = O.combine(g, [(r, inner, 1.0)])
+                    if mistake == "centre_outer_mirrored":
+                        Ct = O.bubble(r, iv, V, P, q, 0, O.C_ALL, dual)
+                    else:
+                        Ct = O.bubble(r, V, iv, P, q, 0, O.C_ALL, dual)
+                    tot = _chan_add(tot, Ct)
+                this.append(tot)
+            out.append(this)
+        return out
+    return mloop
+
+
+@pytest.mark.parametrize("mistake", ["none", "rbar_includes_r", "right_insertion_twice",
+                                     "centre_from_previous_order", "centre_inner_mirrored",
+                                     "centre_outer_mirrored"])
+def test_multiloop_pins_catch_planted_mistakes(mistake):
+    """The multiloop pins above detect each plausible mistake in the recursion: the channel sum
+    rbar containing r itself, the left insertion replaced by a second right one, the centre term
+    built from order l-1 instead of l-2, or its inner or outer bubble with the sides exchanged."""
+    f = _mloop_with_mistake(mistake)
+    r3, r4 = _total_derivative_residuals(f, O.Grid(9), _grid_rule(9))
+    mirror = _mirror_residual(f)
+    worst = max(r3, r4, mirror)
+    if mistake == "none":
+        assert worst < 1e-12
+    else:
+        assert worst > 1e-3, (r3, r4, mirror)
 
 
 # ---------------------------------------------------------------- P13: sum rule
