@@ -10,7 +10,9 @@ asymptotic classes (propagator pairs, vertex gathers, GEMMs, epilogue) with the 
 resident in HBM.  Algorithmic work per step:
     F = 2 * N * 8 * (4N + 4) * 4 Nq * (4N + 4)   real flops (= 16.81 TFLOP).
 `value` is F / (ms per step) of the split-FP32 path when its error against the FP64
-path is <= 1e-6, otherwise of the FP64 path.
+path is <= 1e-6, otherwise of the FP64 path.  The split-FP32 path is the lowest rung of the
+split ladder: operands rounded once to FP32 (no hi*lo correction products), FP32 MFMA with
+FP32 partial sums over 64 complex terms promoted to FP64.
 
 Prints one JSON line.  --gpus above 1 is rejected: the library runs on one GPU.
 """
@@ -166,6 +168,31 @@ def main():
             a, b = getattr(outs["split"], c), getattr(outs["fp64"], c)
             err[c] = float((a - b).abs().max() / b.abs().max())
         log(f"split vs fp64 max-norm relative errors: {err}")
+    # Sigma(v) and chi(w) from the bubble's vertex: Gamma' = Gamma_0 + gamma_a' + the seed's p and t
+    # channels, with gamma_a' = the bubble of each path; the SDE's own bubble in the same path,
+    # its loop and the chi reduction in FP64.  Errors of the split path against the FP64 path.
+    derived = {}
+    sd_err = {}
+    for name, out in outs.items():
+        Vd = K.Vertex(g, U, [out, chans[1], chans[2]])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sig, chi = K.sde(Vd, P, q, q, precision=precs[name], omega_batch=args.omega_batch)
+        torch.cuda.synchronize()
+        derived[name] = (sig, chi, time.perf_counter() - t0)
+        log(f"{name}: Sigma and chi of the updated vertex in {derived[name][2]:.2f} s")
+    if "split" in derived and "fp64" in derived:
+        (s32, c32, _), (s64, c64, _) = derived["split"], derived["fp64"]
+
+        def chi_r(c):  # chi^R(w) = u^T chi^X(w) v, u on pairs {00, 11}, v on {01, 10}
+            m = c[0].reshape(-1, 4, 4)
+            return m[:, [0, 3]][:, :, [1, 2]].sum(dim=(1, 2))
+
+        sd_err = {"Sigma": float((s32 - s64).abs().max() / s64.abs().max()),
+                  "SigmaR": float((s32[:, 1] - s64[:, 1]).abs().max() / s64[:, 1].abs().max()),
+                  "chi_pair": float((c32 - c64).abs().max() / c64.abs().max()),
+                  "chiR": float((chi_r(c32) - chi_r(c64)).abs().max() / chi_r(c64).abs().max())}
+        log(f"split vs fp64, Sigma and chi of the updated vertex: {sd_err}")
     split_ok = bool(err) and max(err.values()) <= 1e-6
     head = "split" if (split_ok or args.only == "split") else "fp64"
     if args.only == "fp64":
@@ -223,8 +250,17 @@ def main():
         pts = pts[:done]
         ref = np.concatenate(refs)
         flops_per_block = 2.0 * 8 * 16 * 4 * nq
+        cpu_model = "unknown"
+        try:
+            with open("/proc/cpuinfo", encoding="utf-8") as f:
+                for ln in f:
+                    if ln.startswith("model name"):
+                        cpu_model = ln.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
         cpu = {"value": round(npts * flops_per_block / tc / 1e9, 3), "unit": "GFLOP/s", "cores": cores,
-               "kind": "oracle", "seconds": round(tc, 2),
+               "kind": "oracle", "seconds": round(tc, 2), "cpu_model": cpu_model,
                "sample": f"{npts} random (w, v, v') output blocks (4x4 Keldysh x 2 spins) of the same "
                          f"channel-a bubble, mostly K3, at n={n}, nq={nq}"}
         # parity of both GPU paths on the sample (denominator: max-norm of the full FP64 array),
@@ -275,6 +311,8 @@ def main():
         "paths": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                   for k, v in results.items()},
         "split_vs_fp64_rel_err": err,
+        "split_vs_fp64_sigma_chi_rel_err": sd_err,
+        "sigma_chi_seconds": {k: round(v[2], 3) for k, v in derived.items()},
         "sampled_rel_err_vs_oracle": oracle_err,
     }
     print(json.dumps(line), flush=True)

@@ -72,7 +72,10 @@ class _Bubble(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g1, g2, g2p, g3):
-        channel, kind, grid, q, T, eps, coefsL, coefsR, _, _ = ctx.meta
+        channel, kind, grid, q, T, eps, coefsL, coefsR, _, cmask = ctx.meta
+        # classes outside the mask are returned as constant zeros: their cotangents do not flow
+        g1, g2, g2p, g3 = [g if (cmask & bit) else None
+                           for g, bit in zip((g1, g2, g2p, g3), (K.K1, K.K2, K.K2P, K.K3))]
         saved = ctx.saved_tensors
         r0L, r0R, Delta = saved[:3]
         fl, fr = list(saved[3:15]), list(saved[15:27])

@@ -49,10 +49,12 @@ def _at(out, p):
     return out.K1[:, iw]
 
 
-@pytest.mark.parametrize("r,kind", [(0, 0), (1, 0), (2, 0), (0, 1)])
-def test_adaptive_bubble_matches_oracle(r, kind):
+@pytest.mark.parametrize("n,eps,r,kind", [(5, 1e-8, 0, 0), (5, 1e-8, 1, 0), (5, 1e-8, 2, 0), (5, 1e-8, 0, 1),
+                                          (9, 1e-5, 0, 0), (9, 1e-5, 1, 1), (9, 1e-5, 2, 1), (11, 1e-5, 0, 1)])
+def test_adaptive_bubble_matches_oracle(n, eps, r, kind):
+    """Per-output adaptive integrals at sampled outputs of every class; at eps = 1e-5 the
+    intervals are refined a few times per kink of the interpolated vertex (80-290 per output)."""
     K = _K()
-    n, eps = 5, 1e-8
     ov, kv = _vertices(n)
     pts = _pts(n)
     ref, counts = O.bubble_adaptive_points(r, ov, ov, O.Prop(1.0, 0.1), O.Quad(1), pts, eps, kind)

@@ -168,3 +168,27 @@ def test_autograd_chain_seed_bubble_sde():
     ref_d = dsd[n // 2, 1].imag + 0.3 * dsd[:, 1].real.sum()
     assert abs(float(gU) - ref_u) < 1e-10 * max(1.0, abs(ref_u))
     assert abs(float(gD) - ref_d) < 1e-10 * max(1.0, abs(ref_d))
+
+
+def test_autograd_class_mask_drops_unselected_cotangents():
+    """Classes outside the bubble's class mask come back as constant zeros, so a loss that reads
+    them must not change the gradient: the masked bubble's U and Delta gradients equal those of
+    the full bubble with a loss on the selected classes only."""
+    K = _K()
+    from paper_2405_20996_amd import autograd as A
+    n, nq = 7, 15
+    _, kv = pair(n, (11, 12, 13), (1.0, 0.8, 0.6))
+    q = K.Quad(nq)
+    grads = []
+    for mask in (K.K1 | K.K2, K.KALL):
+        Ut = torch.tensor(U, dtype=torch.float64, requires_grad=True)
+        Dt = torch.tensor(D, dtype=torch.float64, requires_grad=True)
+        V = A.TVertex(kv.grid, Ut, (1.0, 0.8, 0.6),
+                      [{x: getattr(kv.ch[r], x) for x in K.CLASSES} for r in range(3)])
+        out = A.bubble(1, V, V, Dt, q, T, class_mask=mask)
+        loss = out["K1"].abs().square().sum() + out["K2"].real.sum()
+        if mask != K.KALL:  # the unselected classes are zeros; reading them adds nothing
+            loss = loss + out["K3"].real.sum() + 2.0 * out["K2p"].imag.sum()
+        grads.append([float(x) for x in torch.autograd.grad(loss, (Ut, Dt))])
+    for a, b in zip(*grads):
+        assert abs(a - b) <= 1e-12 * max(1.0, abs(b)), grads

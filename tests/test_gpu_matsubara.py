@@ -174,11 +174,13 @@ def test_matsubara_parquet_solver_time():
 
 
 @pytest.mark.parametrize("kind", [0, 1, 2])
-def test_matsubara_loop_matches_oracle(kind):
+@pytest.mark.parametrize("Nl", [9, 70])
+def test_matsubara_loop_matches_oracle(kind, Nl):
     """kqft_loop_matsubara of a random vertex (every channel and class, bare part) with G, S + G
-    Sigma_dot G or G Sigma_dot G, dynamic Sigma."""
+    Sigma_dot G or G Sigma_dot G, dynamic Sigma.  Nl = 70 puts 140 loop frequencies on the 64
+    lanes of a wavefront, so every lane sums several of them before the LDS reduction."""
     K = _K()
-    M, N, Nl = 8, 5, 9
+    M, N = 8, 5
     ov, kv = _pair(M, N, 13, U=0.7)
     Ns = N + 2
     sig = 0.1 * np.exp(1j * np.linspace(0.0, 2.0, 2 * Ns)) - 0.05j

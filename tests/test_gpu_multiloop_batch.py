@@ -4,13 +4,13 @@ l = 1..4 in all three channels (27 bubbles per point), Pidot from the Delta-flow
 single-scale propagator, on the PT2 seed + 1e-3 noise.
 
 Each point runs through kqft_mloop_step on the split-FP32 path; the test reports the
-algorithmic throughput over the batch.  Parity: on the points with N <= 151 every order,
-channel and class of the split path agrees with the FP64 path to 1e-6 (relative to each
-array's max-norm); on the points with N <= 101 the first order (l = 1, the Pidot bubble
-of the seed vertex) agrees with the oracle on sampled outputs, FP64 to 1e-12 and split to
-1e-6.  Higher orders are checked against the oracle in full at small sizes
-(test_gpu_parity.py); at these sizes the oracle cannot build the lower-order insertions
-they take as input.
+algorithmic throughput over the batch.  Parity: on every point every order, channel and
+class of the split path agrees with the FP64 path to 1e-6 (relative to each array's
+max-norm); on the points with N <= 101 the first order (l = 1, the Pidot bubble of the seed
+vertex) agrees with the oracle on sampled outputs, FP64 to 1e-12 and split to 1e-6.  Orders
+2-4 are checked against the oracle one order at a time at N = 51: the oracle takes the GPU's
+FP64 insertions of the orders below as its input and evaluates sampled outputs of the next
+order (left, right and centre terms).
 """
 import time
 
@@ -85,29 +85,93 @@ def test_multiloop_batch_twelve_points():
         flop += f
         seconds += dt
         print(f"   split mloop l<=4: {dt * 1e3:.1f} ms, {f / dt / 1e12:.2f} TFLOP/s", flush=True)
-        if n <= 151:
-            ref = K.mloop_step([V], [P], [q], NLOOPS)[0]
-            torch.cuda.synchronize()
-            worst = 0.0
-            for ell in range(NLOOPS):
-                for r in range(3):
-                    for x in CL:
-                        a, b = getattr(out[ell][r], x), getattr(ref[ell][r], x)
-                        worst = max(worst, float((a - b).abs().max() / b.abs().max()))
-            print(f"   split vs fp64 (all orders, channels, classes): {worst:.3e}", flush=True)
-            assert worst < 1e-6
-            if n <= 101:
-                og, oq, op = O.Grid(n), O.Quad(nq), O.Prop(1.0, T)
-                ov = O.seeded_vertex(og, U, op, oq, noise)
-                for r in range(3):
-                    pts = sample_points(n, 12, 100 * idx + r)
-                    pref = O.bubble_points(r, ov, ov, op, oq, pts, kind=1)
-                    e64 = sampled_error(ref[0][r], pts, pref)
-                    e32 = sampled_error(out[0][r], pts, pref)
-                    assert e64 < 1e-12, (idx, r, e64)
-                    assert e32 < 1e-6, (idx, r, e32)
-            del ref
+        for ell in range(NLOOPS):
+            for r in range(3):
+                assert all(bool(torch.isfinite(getattr(out[ell][r], x)).all()) for x in CL), (idx, ell, r)
+        ref = K.mloop_step([V], [P], [q], NLOOPS)[0]
+        torch.cuda.synchronize()
+        worst = 0.0
+        for ell in range(NLOOPS):
+            for r in range(3):
+                for x in CL:
+                    a, b = getattr(out[ell][r], x), getattr(ref[ell][r], x)
+                    worst = max(worst, float((a - b).abs().max() / b.abs().max()))
+        print(f"   split vs fp64 (all orders, channels, classes): {worst:.3e}", flush=True)
+        assert worst < 1e-6
+        if n <= 101:
+            og, oq, op = O.Grid(n), O.Quad(nq), O.Prop(1.0, T)
+            ov = O.seeded_vertex(og, U, op, oq, noise)
+            for r in range(3):
+                pts = sample_points(n, 12, 100 * idx + r)
+                pref = O.bubble_points(r, ov, ov, op, oq, pts, kind=1)
+                e64 = sampled_error(ref[0][r], pts, pref)
+                e32 = sampled_error(out[0][r], pts, pref)
+                assert e64 < 1e-12, (idx, r, e64)
+                assert e32 < 1e-6, (idx, r, e32)
+        del ref
         del out, V
         torch.cuda.empty_cache()
     print(f"batch: {flop / 1e15:.3f} PFLOP algorithmic in {seconds:.2f} s of mloop calls = "
           f"{flop / seconds / 1e12:.2f} TFLOP/s", flush=True)
+
+
+def sample_at(n, m, seed, iws):
+    """m sampled outputs per transfer frequency in iws, every class."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for iw in iws:
+        cls = np.array([1, 2, 4, 8] + [8] * (m - 4))
+        rows.append(np.stack([cls, np.full(m, iw), rng.integers(0, n, m), rng.integers(0, n, m)], 1))
+    return np.concatenate(rows)
+
+
+def test_multiloop_orders_two_to_four_against_oracle():
+    """Orders l = 2, 3, 4 of one N = 51 point of the batch (U = 1, T = 0.01, Nq = 501), each
+    against the oracle fed with the GPU's FP64 orders below it: left B_r(gdot_rbar^(l-1), Gamma),
+    right B_r(Gamma, gdot_rbar^(l-1)) and, from l = 3, centre B_r(Gamma, B_r(gdot_rbar^(l-2),
+    Gamma)) with the inner bubble evaluated by the oracle on the grid at the sampled transfer
+    frequencies (a bubble in channel r keeps its transfer frequency, so the inner is needed only
+    there).  Bar 1e-12 relative to the GPU array's max-norm."""
+    K = _K()
+    idx = 4
+    U, T, n = MULTILOOP_POINTS[idx]
+    assert n == 51
+    nq = 10 * n - 9
+    noise = seed_noise(n, 0)
+    V, P, q = gpu_seed(K, n, nq, U, T, noise)
+    out = K.mloop_step([V], [P], [q], NLOOPS)[0]
+    torch.cuda.synchronize()
+    host = [[{x: getattr(out[ell][r], x).cpu().numpy() for x in CL} for r in range(3)] for ell in range(NLOOPS)]
+    og, oq, op = O.Grid(n), O.Quad(nq), O.Prop(1.0, T)
+    ov = O.seeded_vertex(og, U, op, oq, noise)
+    iws = [7, 30]
+    grid_pts = np.array([[8, 0, i, j] for i in range(n) for j in range(n)] + [[2, 0, i, 0] for i in range(n)]
+                        + [[4, 0, 0, j] for j in range(n)] + [[1, 0, 0, 0]])
+
+    def rbar_of(order, r):
+        return O.Vertex(og, 0.0, [O.Channel(0.0) if rr == r else O.Channel(1.0, *[order[rr][x] for x in CL])
+                                  for rr in range(3)])
+
+    for ell in range(2, NLOOPS + 1):
+        for r in range(3):
+            pts = sample_at(n, 6, 100 * ell + r, iws)
+            rb = rbar_of(host[ell - 2], r)
+            ref = O.bubble_points(r, rb, ov, op, oq, pts) + O.bubble_points(r, ov, rb, op, oq, pts)
+            if ell >= 3:
+                rb2 = rbar_of(host[ell - 3], r)
+                inner = {x: np.zeros(O.class_shapes(n)[x], complex) for x in CL}
+                for iw in iws:
+                    gp = grid_pts.copy()
+                    gp[:, 1] = iw
+                    vals = O.bubble_points(r, rb2, ov, op, oq, gp)  # [pts, 2, 16]
+                    n2 = n * n
+                    inner["K3"][:, iw] = vals[:n2].transpose(1, 0, 2).reshape(2, n, n, 16)
+                    inner["K2"][:, iw] = vals[n2:n2 + n].transpose(1, 0, 2)
+                    inner["K2p"][:, iw] = vals[n2 + n:n2 + 2 * n].transpose(1, 0, 2)
+                    inner["K1"][:, iw] = vals[-1]
+                iv = O.Vertex(og, 0.0, [O.Channel(1.0, *[inner[x] for x in CL]) if rr == r else O.Channel(0.0)
+                                        for rr in range(3)])
+                ref = ref + O.bubble_points(r, ov, iv, op, oq, pts)
+            e = sampled_error(out[ell - 1][r], pts, ref)
+            print(f"order {ell} channel {r}: sampled relative error vs oracle {e:.2e}", flush=True)
+            assert e < 1e-12, (ell, r, e)

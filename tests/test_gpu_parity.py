@@ -174,32 +174,36 @@ def test_chi_edge_sizes(n, nq):
         assert rel(out, ref) < 1e-12, r
 
 
-def test_mloop_three_loops_matches_oracle():
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-6)])
+def test_mloop_four_loops_matches_oracle(prec, tol):
+    """Every order l = 1..4 per channel and class: l = 4 is the first order whose centre term
+    reads the left insertion kept from two orders back (the rotation of the stored insertions)."""
     K = _K()
     n, nq = 9, 25
     ov, kv = make_pair(n, (51, 52, 53), r0=U, amp=0.05)
-    ref = O.mloop(ov, O.Prop(D, T), O.Quad(nq), 3)
-    out = K.mloop_step([kv], [K.Propagator(D, T)], [K.Quad(nq)], 3)
+    ref = O.mloop(ov, O.Prop(D, T), O.Quad(nq), 4)
+    out = K.mloop_step([kv], [K.Propagator(D, T)], [K.Quad(nq)], 4, precision=prec)
     torch.cuda.synchronize()
-    for ell in range(3):
+    for ell in range(4):
         for r in range(3):
-            compare(out[0][ell][r], ref[ell][r], 1e-12)
+            compare(out[0][ell][r], ref[ell][r], tol)
 
 
 def test_mloop_ragged_points():
+    """Three points of different grids, quadratures, U and T in one call, orders l = 1..4."""
     K = _K()
-    pts = [(7, 19, 0.5, 0.1), (11, 31, 1.5, 0.01)]
+    pts = [(7, 19, 0.5, 0.1), (11, 31, 1.5, 0.01), (5, 13, 1.0, 0.05)]
     kvs, Ps, qs, refs = [], [], [], []
     for i, (n, nq, Ul, Tl) in enumerate(pts):
         ov, kv = make_pair(n, (60 + i, 70 + i, 80 + i), r0=Ul, amp=0.05)
-        refs.append(O.mloop(ov, O.Prop(D, Tl), O.Quad(nq), 2))
+        refs.append(O.mloop(ov, O.Prop(D, Tl), O.Quad(nq), 4))
         kvs.append(kv)
         Ps.append(K.Propagator(D, Tl))
         qs.append(K.Quad(nq))
-    out = K.mloop_step(kvs, Ps, qs, 2)
+    out = K.mloop_step(kvs, Ps, qs, 4)
     torch.cuda.synchronize()
-    for p in range(2):
-        for ell in range(2):
+    for p in range(len(pts)):
+        for ell in range(4):
             for r in range(3):
                 compare(out[p][ell][r], refs[p][ell][r], 1e-12)
 
