@@ -655,6 +655,47 @@ int kqft_sde_adjoint(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propaga
                      const kqft_quad* q_loop, const kqft_opts* opts, const double* dsigma, const kqft_chout* dgamma,
                      double* dscal, void* stream);
 
+/*
+ * kqft_mloop_adjoint -- vector-Jacobian product of kqft_mloop_step for one parameter point
+ * (not in the paper; the forward map is the multiloop recursion of Eqs. 1l, 2l, 3l with the
+ * Delta-flow single-scale propagator, no Katanin term).  Given the cotangents dgdot[l][r]
+ * (host array of nloops * 3 kqft_chout, order-major; a NULL class counts as zero) of the
+ * insertions gdot_r^(l) that kqft_mloop_step returns, accumulates
+ *   dgamma[r] += dL/d(class arrays of gamma's channel r)   (host array of 3; NULL classes skipped),
+ *   dscal[0]  += dL/d gamma->r0,   dscal[1] += dL/d G->Delta   (device array of 2 doubles),
+ * PyTorch's convention for complex cotangents.  The insertions are not stored: going down
+ * from l = nloops, orders 1..l-1 are recomputed (checkpointing) into two alternating
+ * order buffers, and every bubble of order l is reversed with kqft_bubble_adjoint's kernels --
+ * the left insertion B_r(gdot_rbar^(l-1), Gamma) with the cotangent of its order plus the one
+ * the centre term of order l+1 passes back, the right insertion B_r(Gamma, gdot_rbar^(l-1)),
+ * and the centre term B_r(Gamma, gdot_{r,L}^(l-1)); the cotangents of gdot_rbar^(l-1) are
+ * accumulated into the order below.  Recomputes sum_{l < nloops} l orders of insertions.
+ * Working memory: 6 channel buffers of cotangents, 6 of recomputed insertions (each
+ * 2(n + 2n^2 + n^3) x 16 complex), plus the bubble adjoint's workspace.  FP64 throughout;
+ * same propagator restrictions and atomics as kqft_bubble_adjoint.
+ */
+int kqft_mloop_adjoint(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, const kqft_quad* q,
+                       int nloops, const kqft_opts* opts, const kqft_chout* dgdot, const kqft_chout* dgamma,
+                       double* dscal, void* stream);
+
+/*
+ * kqft_mloop_jvp -- Jacobian-vector product of kqft_mloop_step for one parameter point along
+ * a tangent of the vertex at a fixed propagator (not in the paper).  The insertions are
+ * multilinear in Gamma (Eqs. 1l, 2l, 3l: every bubble is bilinear), so the tangent of each
+ * bubble B(L, R) is B(dL, R) + B(L, dR) and the recursion carries the tangents of the
+ * lower orders and of the stored left insertions along.  tangent: a vertex on gamma's grid
+ * holding d r0 and the class tangents (channel coefficients as in gamma).  out, dout: host
+ * arrays of nloops * 3 kqft_chout (order-major, all four classes given) receiving the
+ * insertions (as kqft_mloop_step) and their tangents.  Bubbles in opts->precision.
+ */
+int kqft_mloop_jvp(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_vertex* tangent, const kqft_propagator* G,
+                   const kqft_quad* q, int nloops, const kqft_opts* opts, const kqft_chout* out,
+                   const kqft_chout* dout, void* stream);
+
+/* Device bytes held by the library's workspaces (every context of the process): current
+   and peak since the library was loaded.  Either pointer may be NULL, not both. */
+int kqft_workspace_bytes(size_t* current, size_t* peak);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,8 +1,10 @@
 """torch.autograd Functions over the HIP bubble and Schwinger-Dyson entry points.
 
-Forward calls kqft_bubble / kqft_sde; backward calls kqft_bubble_adjoint /
-kqft_sde_adjoint, which recompute the panels (no activation storage beyond the
-vertex tensors themselves).  Differentiable inputs: the class tensors of every
+Forward calls kqft_bubble / kqft_sde / kqft_mloop_step; backward calls
+kqft_bubble_adjoint / kqft_sde_adjoint / kqft_mloop_adjoint, which recompute the panels
+and the multiloop insertions (no activation storage beyond the vertex tensors
+themselves); forward-mode tangents of the insertions come from kqft_mloop_jvp.  This
+module only marshals tensors: every sum of the method runs in the library.  Differentiable inputs: the class tensors of every
 channel (complex128), the bare-vertex strength r0 and the hybridization Delta
 (0-dim float64 tensors on the CPU).  Gradients follow PyTorch's convention for
 complex tensors (dL/dRe z + i dL/dIm z).
@@ -129,40 +131,46 @@ def sde(gamma: TVertex, Delta: torch.Tensor, q_bubble: K.Quad, q_loop: K.Quad, T
     return _SDE.apply(meta, gamma.r0, Delta, *gamma.flat())
 
 
-def _sum(a: dict, b: dict) -> dict:
-    return {x: a[x] + b[x] for x in K.CLASSES}
+class _MLoop(torch.autograd.Function):
+    """Multiloop insertions of kqft_mloop_step; backward through kqft_mloop_adjoint, which
+    recomputes the insertions order by order (only the vertex tensors are saved)."""
+
+    @staticmethod
+    def forward(ctx, meta, r0, Delta, *tensors):
+        grid, q, T, eps, coefs, nloops, precision = meta
+        V = _kvertex(grid, r0, coefs, list(tensors))
+        out = K.mloop_step([V], [K.Propagator(float(Delta), T, eps)], [q], nloops, precision=precision)[0]
+        ctx.meta = meta
+        ctx.save_for_backward(r0, Delta, *tensors)
+        return tuple(getattr(out[l][r], x) for l in range(nloops) for r in range(3) for x in K.CLASSES)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        grid, q, T, eps, coefs, nloops, _ = ctx.meta
+        saved = ctx.saved_tensors
+        r0, Delta = saved[:2]
+        flat = list(saved[2:])
+        V = _kvertex(grid, r0, coefs, flat)
+        dgdot = [[None] * 3 for _ in range(nloops)]
+        for l in range(nloops):
+            for r in range(3):
+                g4 = grads[4 * (3 * l + r): 4 * (3 * l + r) + 4]
+                if any(g is not None for g in g4):
+                    dgdot[l][r] = K.Channel(1.0, *[(g.contiguous() if g is not None else None) for g in g4])
+        dG = _grads_like(flat, coefs)
+        dscal = K.mloop_adjoint(V, K.Propagator(float(Delta), T, eps), q, nloops, dgdot, dgamma=dG).cpu()
+        return (None, dscal[0], dscal[1], *_flat_grads(dG))
 
 
 def mloop(gamma: TVertex, Delta: torch.Tensor, q: K.Quad, T: float, nloops: int, eps: float = 0.0,
           precision: int = K.FP64) -> list:
-    """Multiloop insertions through differentiable bubbles (mfRG flow, Eqs. 1l-3l; Delta-flow
-    single-scale propagator, no Katanin term):
-      l = 1:  gdot_r = B_r(Gamma, Gamma; Pidot)
-      l = 2:  gdot_r = B_r(gdot_rbar^(1), Gamma) + B_r(Gamma, gdot_rbar^(1))
-      l >= 3: the same plus the centre term B_r(Gamma, L_r^(l-1)), L_r^(l-1) = B_r(gdot_rbar^(l-2), Gamma)
-    with gdot_rbar the sum of the two channels other than r.  Returns out[l-1][r] (class dicts)."""
-    g = gamma.grid
-    zero = torch.zeros((), dtype=torch.float64)
-    out, lefts = [], []
-    for ell in range(1, nloops + 1):
-        this, this_l = [], []
-        for r in range(3):
-            if ell == 1:
-                this.append(bubble(r, gamma, gamma, Delta, q, T, eps, kind=K.PI_DOT, precision=precision))
-                this_l.append(None)
-                continue
-            prev = out[ell - 2]
-            rbar = TVertex(g, zero, (1.0, 1.0, 1.0), [dict(prev[rr]) if rr != r else {} for rr in range(3)])
-            lt = bubble(r, rbar, gamma, Delta, q, T, eps, precision=precision)
-            tot = _sum(lt, bubble(r, gamma, rbar, Delta, q, T, eps, precision=precision))
-            if ell >= 3:
-                inner = TVertex(g, zero, (1.0, 1.0, 1.0), [dict(lefts[ell - 2][r]) if rr == r else {} for rr in range(3)])
-                tot = _sum(tot, bubble(r, gamma, inner, Delta, q, T, eps, precision=precision))
-            this.append(tot)
-            this_l.append(lt)
-        out.append(this)
-        lefts.append(this_l)
-    return out
+    """Multiloop insertions of the mfRG flow (Eqs. 1l-3l; Delta-flow single-scale propagator,
+    no Katanin term) as a differentiable function of the vertex, r0 and Delta: out[l-1][r] is a
+    dict of class tensors of the order-l insertion of channel r (left + right + centre)."""
+    meta = (gamma.grid, q, T, eps, gamma.coefs, nloops, precision)
+    outs = _MLoop.apply(meta, gamma.r0, Delta, *gamma.flat())
+    return [[dict(zip(K.CLASSES, outs[4 * (3 * l + r): 4 * (3 * l + r) + 4])) for r in range(3)]
+            for l in range(nloops)]
 
 
 # ------------------------------------------------------------------ forward mode
@@ -178,46 +186,8 @@ def bubble_jvp(channel: int, L: K.Vertex, dL: K.Vertex, R: K.Vertex, dR: K.Verte
     return out, dout
 
 
-def _vertex(grid: K.Grid, r0: float, chans) -> K.Vertex:
-    return K.Vertex(grid, r0, [c if c is not None else K.Channel(0.0) for c in chans])
-
-
-def _add(a: K.Channel, b: K.Channel, s: float = 1.0) -> K.Channel:
-    return K.Channel(1.0, *[getattr(a, x) + s * getattr(b, x) for x in K.CLASSES])
-
-
 def mloop_jvp(gamma: K.Vertex, dgamma: K.Vertex, G: K.Propagator, q: K.Quad, nloops: int,
               precision: int = K.FP64):
-    """Multiloop insertions (as `mloop`) and their tangents along the vertex tangent dgamma, at a
-    fixed propagator.  Returns (out, dout), each out[l-1][r] a Channel."""
-    g = gamma.grid
-    out, dout, lefts, dlefts = [], [], [], []
-    for ell in range(1, nloops + 1):
-        this, dthis, this_l, dthis_l = [], [], [], []
-        for r in range(3):
-            if ell == 1:
-                o, d = bubble_jvp(r, gamma, dgamma, gamma, dgamma, G, q, K.PI_DOT, precision)
-                this.append(o)
-                dthis.append(d)
-                this_l.append(None)
-                dthis_l.append(None)
-                continue
-            rbar = _vertex(g, 0.0, [out[ell - 2][rr] if rr != r else None for rr in range(3)])
-            drbar = _vertex(g, 0.0, [dout[ell - 2][rr] if rr != r else None for rr in range(3)])
-            lt, dlt = bubble_jvp(r, rbar, drbar, gamma, dgamma, G, q, K.PI_GG, precision)
-            rt, drt = bubble_jvp(r, gamma, dgamma, rbar, drbar, G, q, K.PI_GG, precision)
-            tot, dtot = _add(lt, rt), _add(dlt, drt)
-            if ell >= 3:
-                inner = _vertex(g, 0.0, [lefts[ell - 2][r] if rr == r else None for rr in range(3)])
-                dinner = _vertex(g, 0.0, [dlefts[ell - 2][r] if rr == r else None for rr in range(3)])
-                ct, dct = bubble_jvp(r, gamma, dgamma, inner, dinner, G, q, K.PI_GG, precision)
-                tot, dtot = _add(tot, ct), _add(dtot, dct)
-            this.append(tot)
-            dthis.append(dtot)
-            this_l.append(lt)
-            dthis_l.append(dlt)
-        out.append(this)
-        dout.append(dthis)
-        lefts.append(this_l)
-        dlefts.append(dthis_l)
-    return out, dout
+    """Multiloop insertions and their tangents along the vertex tangent dgamma at a fixed
+    propagator (kqft_mloop_jvp).  Returns (out, dout), each out[l-1][r] a Channel."""
+    return K.mloop_jvp(gamma, dgamma, G, q, nloops, precision=precision)

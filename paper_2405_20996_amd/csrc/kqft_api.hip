@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <atomic>
 #include <map>
 #include <string>
 #include <tuple>
@@ -47,6 +48,9 @@ struct kqft_ctx {
   rocblas_handle blas = nullptr;
   DevBuf adjw, dkf[2][3], phigrad, pq, pqsig, pqred, vtab[3], flow, flowml, ctmp, flowred, pqx, adapt, sdep, mf, mftmp,
       mfflow, mftail;
+  // multiloop adjoint / tangent: recomputed insertions, cotangent accumulators and the
+  // extra cotangents of the stored left insertions (two orders each, per channel)
+  DevBuf mlrec[2][3], mlbar[2][3], mlext[2][3], mlscr;
   std::vector<hipEvent_t> events;
   size_t next_event = 0;
   bool prof = false;
@@ -150,19 +154,32 @@ static int get_quad(kqft_ctx* ctx, const kqft_quad& q, const double** qv, const 
   return KQFT_OK;
 }
 
-static int ensure(DevBuf& b, size_t bytes) {
-  if (b.bytes >= bytes) return KQFT_OK;
-  if (b.p) {  // the old buffer may still be read by work of an earlier call
-    (void)hipDeviceSynchronize();
+// device bytes held by the workspaces of every context of the process, and their peak
+static std::atomic<size_t> g_ws_bytes{0}, g_ws_peak{0};
+
+static void free_buf(DevBuf& b) {
+  if (b.p) {
     (void)hipFree(b.p);
+    g_ws_bytes -= b.bytes;
   }
   b.p = nullptr;
   b.bytes = 0;
+}
+
+static int ensure(DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes) return KQFT_OK;
+  if (b.p) (void)hipDeviceSynchronize();  // the old buffer may still be read by work of an earlier call
+  free_buf(b);
   if (hipMalloc(&b.p, bytes) != hipSuccess) {
     (void)hipGetLastError();
+    b.p = nullptr;
     return fail(KQFT_ENOMEM, "workspace allocation of " + std::to_string(bytes) + " bytes failed");
   }
   b.bytes = bytes;
+  const size_t now = (g_ws_bytes += bytes);
+  size_t pk = g_ws_peak.load();
+  while (now > pk && !g_ws_peak.compare_exchange_weak(pk, now)) {
+  }
   return KQFT_OK;
 }
 
@@ -969,23 +986,27 @@ int kqft_ctx_destroy(kqft_ctx* ctx) {
   DevBuf* bufs[] = {&ctx->panels[0], &ctx->panels[1], &ctx->pi[0], &ctx->pi[1], &ctx->phi, &ctx->chi_part,
                     &ctx->adj};
   for (DevBuf* b : bufs)
-    if (b->p) (void)hipFree(b->p);
+    if (b->p) free_buf(*b);
   for (auto& row : ctx->lstore)
     for (auto& b : row)
-      if (b.p) (void)hipFree(b.p);
+      if (b.p) free_buf(b);
   for (auto& row : ctx->tab)
     for (auto& b : row)
-      if (b.p) (void)hipFree(b.p);
+      if (b.p) free_buf(b);
   for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
   for (auto& row : ctx->dkf)
     for (auto& b : row)
-      if (b.p) (void)hipFree(b.p);
-  if (ctx->adjw.p) (void)hipFree(ctx->adjw.p);
+      if (b.p) free_buf(b);
+  free_buf(ctx->adjw);
   for (DevBuf* b : {&ctx->pq, &ctx->pqsig, &ctx->pqred, &ctx->vtab[0], &ctx->vtab[1], &ctx->vtab[2], &ctx->flow,
                     &ctx->flowml, &ctx->ctmp, &ctx->flowred, &ctx->pqx, &ctx->adapt, &ctx->sdep, &ctx->mf, &ctx->mftmp,
                     &ctx->mfflow, &ctx->mftail})
-    if (b->p) (void)hipFree(b->p);
-  if (ctx->phigrad.p) (void)hipFree(ctx->phigrad.p);
+    if (b->p) free_buf(*b);
+  free_buf(ctx->phigrad);
+  for (auto* set : {&ctx->mlrec, &ctx->mlbar, &ctx->mlext})
+    for (auto& row : *set)
+      for (auto& b : row) free_buf(b);
+  free_buf(ctx->mlscr);
   if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
   if (ctx->sg) (void)hipStreamDestroy(ctx->sg);
   if (ctx->sm) (void)hipStreamDestroy(ctx->sm);
@@ -2029,7 +2050,7 @@ int kqft_loop(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G,
 
 static int mloop_core(kqft_ctx* ctx, const kqft_vertex& V, const kqft_propagator& G, const kqft_quad& q, int nloops,
                       kqft_opts o, const std::function<BubbleOut(int, int)>& dview, const BubbleOut* centre,
-                      hipStream_t s);
+                      hipStream_t s, bool keep_last_left = false);
 
 // <n_sigma> = 1/2 + (1/2 pi) sum_j w_j tanh(v_j/2T) Im G^R(v_j) at level E (Eq. Hartree with the
 // spectral sum rule for the constant half); device partial sums, host total
@@ -2791,10 +2812,13 @@ int kqft_parquet_solve(kqft_ctx* ctx, const kqft_grid* grid, double U, double De
 
 // Multiloop insertions of one parameter point into dview(l - 1, r) (Eqs. 1l, 2l, 3l).  With
 // `centre` (two outputs, channels a and p), the centre terms of those channels are also
-// summed over l >= 3 into centre[0], centre[1] (written when nloops >= 3).
+// summed over l >= 3 into centre[0], centre[1] (written when nloops >= 3).  dview(l - 1, .)
+// is read only while order l + 1 is formed, so a caller may map the orders onto two
+// alternating buffers.  keep_last_left: the left insertions of the last order (nloops >= 2)
+// stay in ctx->lstore[nloops & 1] as well.
 static int mloop_core(kqft_ctx* ctx, const kqft_vertex& V, const kqft_propagator& G, const kqft_quad& q, int nloops,
                       kqft_opts o, const std::function<BubbleOut(int, int)>& dview, const BubbleOut* centre,
-                      hipStream_t s) {
+                      hipStream_t s, bool keep_last_left) {
   int rc;
   o.class_mask = KQFT_KALL;
   const int n = V.grid.n;
@@ -2802,7 +2826,7 @@ static int mloop_core(kqft_ctx* ctx, const kqft_vertex& V, const kqft_propagator
   const size_t s1 = c1 * sizeof(double2), s2 = c2 * sizeof(double2), s3 = c3 * sizeof(double2);
   const size_t chb = s1 + 2 * s2 + s3;
   // left insertions of the previous and the current order, per channel
-  if (nloops >= 3)
+  if (nloops >= 3 || (keep_last_left && nloops >= 2))
     for (int x = 0; x < 2; ++x)
       for (int r = 0; r < 3; ++r)
         if ((rc = ensure(ctx->lstore[x][r], chb))) return rc;
@@ -2839,7 +2863,7 @@ static int mloop_core(kqft_ctx* ctx, const kqft_vertex& V, const kqft_propagator
       // left insertion: into dst, and kept for the next order's centre term
       o.beta = 0;
       if ((rc = bubble_core(ctx, r, rbar, V, G, KQFT_PI_GG, q, o, dst, s))) return rc;
-      if (l + 1 <= nloops && l >= 2) {
+      if ((l + 1 <= nloops || keep_last_left) && l >= 2) {
         BubbleOut lv = view_of(ctx->lstore[cur][r].p);
         HIP_TRY(hipMemcpyAsync(lv.K1, dst.K1, s1, hipMemcpyDeviceToDevice, s));
         HIP_TRY(hipMemcpyAsync(lv.K2, dst.K2, s2, hipMemcpyDeviceToDevice, s));
@@ -2973,6 +2997,225 @@ int kqft_sde_adjoint(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propaga
   memset(none, 0, sizeof none);
   return adjoint_core(ctx, KQFT_CH_A, bare, *gamma, *G, KQFT_PI_GG, *q_bubble, dphi, none, dgamma, dscal, dscal,
                       dscal + 1, s);
+}
+
+
+// Views of the four classes of one channel packed back to back in a buffer.
+static BubbleOut class_view(void* p, int n) {
+  const size_t s1 = (size_t)2 * n * 16 * sizeof(double2), s2 = (size_t)2 * n * n * 16 * sizeof(double2);
+  char* b = (char*)p;
+  return BubbleOut{(double2*)b, (double2*)(b + s1), (double2*)(b + s1 + s2), (double2*)(b + s1 + 2 * s2)};
+}
+static kqft_chout chout_of(const BubbleOut& v) {
+  return kqft_chout{(double*)v.K1, (double*)v.K2, (double*)v.K2p, (double*)v.K3};
+}
+static kqft_chvert chvert_of(const BubbleOut& v, double coef = 1.0) {
+  return kqft_chvert{coef, (const double*)v.K1, (const double*)v.K2, (const double*)v.K2p, (const double*)v.K3};
+}
+// dst (+)= src class by class; a NULL src class counts as zero
+static int copy_classes(const BubbleOut& dst, const kqft_chout& src, int n, bool add, hipStream_t s) {
+  const size_t c[4] = {(size_t)2 * n * 16, (size_t)2 * n * n * 16, (size_t)2 * n * n * 16, (size_t)2 * n * n * n * 16};
+  double2* d[4] = {dst.K1, dst.K2, dst.K2p, dst.K3};
+  const double2* x[4] = {(const double2*)src.K1, (const double2*)src.K2, (const double2*)src.K2p,
+                         (const double2*)src.K3};
+  for (int k = 0; k < 4; ++k) {
+    if (x[k])
+      launch_axpby(d[k], 1.0, x[k], add ? 1.0 : 0.0, add ? d[k] : x[k], c[k], s);
+    else if (!add)
+      HIP_TRY(hipMemsetAsync(d[k], 0, c[k] * sizeof(double2), s));
+  }
+  return KQFT_OK;
+}
+
+int kqft_mloop_adjoint(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, const kqft_quad* q,
+                       int nloops, const kqft_opts* opts, const kqft_chout* dgdot, const kqft_chout* dgamma,
+                       double* dscal, void* stream) {
+  int rc;
+  if ((rc = check_common(ctx, G, q, opts))) return rc;
+  if ((rc = check_adjoint_prop(*G))) return rc;
+  if ((rc = check_vertex(gamma, "gamma"))) return rc;
+  if (nloops < 1) return fail(KQFT_EINVAL, "nloops must be >= 1");
+  if (!dgdot || !dgamma || !dscal) return fail(KQFT_EINVAL, "dgdot, dgamma and dscal must be given");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const int n = gamma->grid.n;
+  const size_t chb = ((size_t)2 * n * 16 + (size_t)4 * n * n * 16 + (size_t)2 * n * n * n * 16) * sizeof(double2);
+  const int depth = nloops >= 2 ? 2 : 0;
+  for (int x = 0; x < depth; ++x)
+    for (int r = 0; r < 3; ++r)
+      if ((rc = ensure(ctx->mlrec[x][r], chb)) || (rc = ensure(ctx->mlbar[x][r], chb)) ||
+          (rc = ensure(ctx->mlext[x][r], chb)))
+        return rc;
+  if ((rc = ensure(ctx->mlscr, 4 * sizeof(double)))) return rc;
+  double* dr0_drop = (double*)ctx->mlscr.p;  // r0 cotangents of insertion vertices (r0 = 0, no parameter)
+  kqft_opts o = *opts;
+  o.precision = KQFT_FP64;
+  o.class_mask = KQFT_KALL;
+  o.beta = 0;
+  o.overlap = 0;
+  auto rec = [&](int l0, int r) { return class_view(ctx->mlrec[l0 & 1][r].p, n); };  // order l0 + 1
+  auto bar = [&](int l0, int r) { return class_view(ctx->mlbar[l0 & 1][r].p, n); };
+  auto ext = [&](int l0, int r) { return class_view(ctx->mlext[l0 & 1][r].p, n); };
+  kqft_chout none[3];
+  memset(none, 0, sizeof none);
+  // cotangent accumulators of the top order: the caller's cotangents (NULL classes = 0)
+  if (nloops >= 2)
+    for (int r = 0; r < 3; ++r) {
+      if ((rc = copy_classes(bar(nloops - 1, r), dgdot[(size_t)(nloops - 1) * 3 + r], n, false, s))) return rc;
+      if ((rc = copy_classes(ext(nloops - 1, r), kqft_chout{}, n, false, s))) return rc;
+    }
+  for (int l = nloops; l >= 2; --l) {
+    // recompute orders 1..l-1 (two alternating buffers) and the left insertions of order l-1
+    auto dview = [&](int l0, int r) { return rec(l0, r); };
+    if ((rc = mloop_core(ctx, *gamma, *G, *q, l - 1, o, dview, nullptr, s, true))) return rc;
+    // accumulators of order l-1: the caller's cotangents, zero extras
+    for (int r = 0; r < 3; ++r) {
+      if ((rc = copy_classes(bar(l - 2, r), dgdot[(size_t)(l - 2) * 3 + r], n, false, s))) return rc;
+      if ((rc = copy_classes(ext(l - 2, r), kqft_chout{}, n, false, s))) return rc;
+    }
+    for (int r = 0; r < 3; ++r) {
+      // gdot_rbar^(l-1): the other two channels of order l-1; their cotangents accumulate
+      kqft_vertex rbar;
+      memset(&rbar, 0, sizeof rbar);
+      rbar.grid = gamma->grid;
+      kqft_chout drbar[3];
+      memset(drbar, 0, sizeof drbar);
+      for (int r2 = 0; r2 < 3; ++r2) {
+        if (r2 == r) continue;
+        rbar.ch[r2] = chvert_of(rec(l - 2, r2));
+        drbar[r2] = chout_of(bar(l - 2, r2));
+      }
+      const BubbleOut dtot = bar(l - 1, r);
+      // left insertion L_r^l = B_r(rbar, Gamma): cotangent = that of the order plus the one the
+      // centre term of order l+1 passed back (already summed into ext)
+      const BubbleOut dl = ext(l - 1, r);
+      if ((rc = copy_classes(dl, chout_of(dtot), n, true, s))) return rc;
+      if ((rc = adjoint_core(ctx, r, rbar, *gamma, *G, KQFT_PI_GG, *q, chout_of(dl), drbar, dgamma, dr0_drop,
+                             dscal, dscal + 1, s)))
+        return rc;
+      // right insertion B_r(Gamma, rbar)
+      if ((rc = adjoint_core(ctx, r, *gamma, rbar, *G, KQFT_PI_GG, *q, chout_of(dtot), dgamma, drbar, dscal,
+                             dr0_drop, dscal + 1, s)))
+        return rc;
+      if (l >= 3) {  // centre term B_r(Gamma, L_r^(l-1)): its right cotangent goes to L_r^(l-1)
+        kqft_vertex lv;
+        memset(&lv, 0, sizeof lv);
+        lv.grid = gamma->grid;
+        lv.ch[r] = chvert_of(class_view(ctx->lstore[(l - 1) & 1][r].p, n));
+        kqft_chout dlv[3];
+        memset(dlv, 0, sizeof dlv);
+        dlv[r] = chout_of(ext(l - 2, r));
+        if ((rc = adjoint_core(ctx, r, *gamma, lv, *G, KQFT_PI_GG, *q, chout_of(dtot), dgamma, dlv, dscal,
+                               dr0_drop, dscal + 1, s)))
+          return rc;
+      }
+    }
+  }
+  // order 1: B_r(Gamma, Gamma; Pidot); its cotangent is the caller's plus what order 2 passed down
+  for (int r = 0; r < 3; ++r) {
+    kqft_chout d1 = dgdot[r];
+    if (nloops >= 2) d1 = chout_of(bar(0, r));
+    if (!d1.K1 && !d1.K2 && !d1.K2p && !d1.K3) continue;
+    if (nloops < 2) {  // the caller's cotangent may leave classes NULL: give the adjoint zeros
+      if ((rc = ensure(ctx->mlbar[0][r], chb))) return rc;
+      if ((rc = copy_classes(class_view(ctx->mlbar[0][r].p, n), d1, n, false, s))) return rc;
+      d1 = chout_of(class_view(ctx->mlbar[0][r].p, n));
+    }
+    if ((rc = adjoint_core(ctx, r, *gamma, *gamma, *G, KQFT_PI_DOT, *q, d1, dgamma, dgamma, dscal, dscal,
+                           dscal + 1, s)))
+      return rc;
+  }
+  HIP_TRY(hipGetLastError());
+  return KQFT_OK;
+}
+
+int kqft_mloop_jvp(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_vertex* tangent, const kqft_propagator* G,
+                   const kqft_quad* q, int nloops, const kqft_opts* opts, const kqft_chout* out,
+                   const kqft_chout* dout, void* stream) {
+  int rc;
+  if ((rc = check_common(ctx, G, q, opts))) return rc;
+  if ((rc = check_vertex(gamma, "gamma")) || (rc = check_vertex(tangent, "tangent"))) return rc;
+  if (!same_grid(gamma->grid, tangent->grid)) return fail(KQFT_ESHAPE, "gamma and its tangent must share one grid");
+  if (nloops < 1 || !out || !dout) return fail(KQFT_EINVAL, "jvp needs nloops >= 1, out and dout");
+  for (int k = 0; k < nloops * 3; ++k)
+    if (!out[k].K1 || !out[k].K2 || !out[k].K2p || !out[k].K3 || !dout[k].K1 || !dout[k].K2 || !dout[k].K2p ||
+        !dout[k].K3)
+      return fail(KQFT_EINVAL, "out and dout arrays must all be given");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const int n = gamma->grid.n;
+  const size_t chb = ((size_t)2 * n * 16 + (size_t)4 * n * n * 16 + (size_t)2 * n * n * n * 16) * sizeof(double2);
+  const size_t cls[4] = {(size_t)2 * n * 16, (size_t)2 * n * n * 16, (size_t)2 * n * n * 16,
+                         (size_t)2 * n * n * n * 16};
+  if (nloops >= 3)
+    for (int x = 0; x < 2; ++x)
+      for (int r = 0; r < 3; ++r)
+        if ((rc = ensure(ctx->mlrec[x][r], chb)) || (rc = ensure(ctx->mlbar[x][r], chb))) return rc;
+  kqft_opts o = *opts;
+  o.class_mask = KQFT_KALL;
+  o.overlap = 0;
+  auto view = [&](const kqft_chout* a, int l0, int r) {
+    const kqft_chout& c = a[(size_t)l0 * 3 + r];
+    return BubbleOut{(double2*)c.K1, (double2*)c.K2, (double2*)c.K2p, (double2*)c.K3};
+  };
+  auto keep = [&](DevBuf (&buf)[2][3], int l, int r, const BubbleOut& src) -> int {
+    const BubbleOut d = class_view(buf[l & 1][r].p, n);
+    const double2* x[4] = {src.K1, src.K2, src.K2p, src.K3};
+    double2* y[4] = {d.K1, d.K2, d.K2p, d.K3};
+    for (int k = 0; k < 4; ++k)
+      HIP_TRY(hipMemcpyAsync(y[k], x[k], cls[k] * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    return KQFT_OK;
+  };
+  // B(L, R) and its tangent B(dL, R) + B(L, dR) at the fixed propagator (bilinear bubble)
+  auto bub = [&](int r, const kqft_vertex& L, const kqft_vertex& dL, const kqft_vertex& R, const kqft_vertex& dR,
+                 int kind, const BubbleOut& o1, const BubbleOut& d1, int beta) -> int {
+    int e;
+    o.beta = beta;
+    if ((e = bubble_core(ctx, r, L, R, *G, kind, *q, o, o1, s))) return e;
+    if ((e = bubble_core(ctx, r, dL, R, *G, kind, *q, o, d1, s))) return e;
+    o.beta = 1;
+    return bubble_core(ctx, r, L, dR, *G, kind, *q, o, d1, s);
+  };
+  for (int l = 1; l <= nloops; ++l) {
+    for (int r = 0; r < 3; ++r) {
+      const BubbleOut o1 = view(out, l - 1, r), d1 = view(dout, l - 1, r);
+      if (l == 1) {
+        if ((rc = bub(r, *gamma, *tangent, *gamma, *tangent, KQFT_PI_DOT, o1, d1, 0))) return rc;
+        continue;
+      }
+      kqft_vertex rb, drb;
+      memset(&rb, 0, sizeof rb);
+      memset(&drb, 0, sizeof drb);
+      rb.grid = drb.grid = gamma->grid;
+      for (int r2 = 0; r2 < 3; ++r2) {
+        if (r2 == r) continue;
+        rb.ch[r2] = chvert_of(view(out, l - 2, r2));
+        drb.ch[r2] = chvert_of(view(dout, l - 2, r2));
+      }
+      if ((rc = bub(r, rb, drb, *gamma, *tangent, KQFT_PI_GG, o1, d1, 0))) return rc;  // left
+      if (l + 1 <= nloops && l >= 2)  // kept for the centre term of order l + 1
+        if ((rc = keep(ctx->mlrec, l, r, o1)) || (rc = keep(ctx->mlbar, l, r, d1))) return rc;
+      if ((rc = bub(r, *gamma, *tangent, rb, drb, KQFT_PI_GG, o1, d1, 1))) return rc;  // right
+      if (l >= 3) {  // centre B_r(Gamma, L_r^(l-1))
+        kqft_vertex lv, dlv;
+        memset(&lv, 0, sizeof lv);
+        memset(&dlv, 0, sizeof dlv);
+        lv.grid = dlv.grid = gamma->grid;
+        lv.ch[r] = chvert_of(class_view(ctx->mlrec[(l - 1) & 1][r].p, n));
+        dlv.ch[r] = chvert_of(class_view(ctx->mlbar[(l - 1) & 1][r].p, n));
+        if ((rc = bub(r, *gamma, *tangent, lv, dlv, KQFT_PI_GG, o1, d1, 1))) return rc;
+      }
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  return KQFT_OK;
+}
+
+int kqft_workspace_bytes(size_t* current, size_t* peak) {
+  if (!current && !peak) return fail(KQFT_EINVAL, "current and peak are both NULL");
+  if (current) *current = g_ws_bytes.load();
+  if (peak) *peak = g_ws_peak.load();
+  return KQFT_OK;
 }
 
 }  // extern "C"

@@ -124,6 +124,11 @@ def lib():
         _lib.kqft_bubble_adjoint.argtypes = [C.c_void_p, C.c_int, P(KqftVertex), P(KqftVertex), P(KqftPropagator),
                                              C.c_int, P(KqftQuad), P(KqftOpts), P(KqftChout), P(KqftChout),
                                              P(KqftChout), C.c_void_p, C.c_void_p]
+        _lib.kqft_mloop_adjoint.argtypes = [C.c_void_p, P(KqftVertex), P(KqftPropagator), P(KqftQuad), C.c_int,
+                                            P(KqftOpts), P(KqftChout), P(KqftChout), C.c_void_p, C.c_void_p]
+        _lib.kqft_mloop_jvp.argtypes = [C.c_void_p, P(KqftVertex), P(KqftVertex), P(KqftPropagator), P(KqftQuad),
+                                        C.c_int, P(KqftOpts), P(KqftChout), P(KqftChout), C.c_void_p]
+        _lib.kqft_workspace_bytes.argtypes = [P(C.c_size_t), P(C.c_size_t)]
         _lib.kqft_chi.argtypes = [C.c_void_p, C.c_int, P(KqftVertex), P(KqftPropagator), P(KqftQuad), C.c_void_p,
                                   C.c_void_p]
         _lib.kqft_bubble_matsubara.argtypes = [C.c_void_p, C.c_int, P(KqftMVertex), P(KqftMVertex), P(KqftMProp),
@@ -165,7 +170,8 @@ def lib():
 def exported_symbols() -> list:
     names = ["kqft_ctx_create", "kqft_ctx_destroy", "kqft_last_error", "kqft_ctx_profile", "kqft_ctx_profile_read",
              "kqft_bubble_workspace", "kqft_bubble",
-             "kqft_sde", "kqft_mloop_step", "kqft_bubble_adjoint", "kqft_sde_adjoint"]
+             "kqft_sde", "kqft_mloop_step", "kqft_bubble_adjoint", "kqft_sde_adjoint", "kqft_mloop_adjoint",
+             "kqft_mloop_jvp", "kqft_workspace_bytes"]
     L = lib()
     return [n for n in names if hasattr(L, n)]
 
@@ -709,3 +715,51 @@ def sde_adjoint(gamma: Vertex, G: Propagator, q_bubble: Quad, q_loop: Quad, dsig
                                   C.byref(_opts(FP64, KALL, 0, 0)), C.c_void_p(ds.data_ptr()), DG,
                                   C.c_void_p(dscal.data_ptr()), _stream(stream)))
     return dscal
+
+
+def mloop_adjoint(gamma: Vertex, G: Propagator, q: Quad, nloops: int, dgdot: Sequence[Sequence[Optional[Channel]]],
+                  dgamma: Optional[list] = None, stream=None):
+    """Vector-Jacobian product of mloop_step for one point: dgdot[l][r] is the cotangent of
+    the order-(l+1) insertion of channel r (a Channel, None = zero; a class left None counts as
+    zero).  Accumulates into dgamma[r] (Channels, or None to skip) and returns the device
+    tensor dscal = (d gamma.r0, d G.Delta)."""
+    n = gamma.grid.n
+    dev = torch.device("cuda", torch.cuda.current_device())
+    dscal = torch.zeros(2, dtype=torch.float64, device=dev)
+    empty = KqftChout(None, None, None, None)
+
+    def co(c):
+        if c is None:
+            return empty
+        return KqftChout(*[_ptr(getattr(c, x), class_shape(x, n), x) if getattr(c, x) is not None else None
+                           for x in CLASSES])
+
+    D = (KqftChout * (nloops * 3))(*[co(dgdot[l][r]) for l in range(nloops) for r in range(3)])
+    DG = (KqftChout * 3)(*[_chout_opt(d, n) for d in (dgamma or [None] * 3)])
+    vc, gc, qc = gamma.c(), G.c(), q.c()
+    _check(lib().kqft_mloop_adjoint(ctx(), C.byref(vc), C.byref(gc), C.byref(qc), nloops,
+                                    C.byref(_opts(FP64, KALL, 0, 0)), D, DG, C.c_void_p(dscal.data_ptr()),
+                                    _stream(stream)))
+    return dscal
+
+
+def mloop_jvp(gamma: Vertex, tangent: Vertex, G: Propagator, q: Quad, nloops: int, precision: int = FP64,
+              omega_batch: int = 0, stream=None):
+    """Insertions of mloop_step for one point and their tangents along the vertex tangent
+    (fixed propagator): (out, dout), each out[l][r] a Channel."""
+    n = gamma.grid.n
+    outs = [[alloc_channel(n) for _ in range(3)] for _ in range(nloops)]
+    douts = [[alloc_channel(n) for _ in range(3)] for _ in range(nloops)]
+    O_ = (KqftChout * (nloops * 3))(*[_chout(outs[l][r], n) for l in range(nloops) for r in range(3)])
+    D_ = (KqftChout * (nloops * 3))(*[_chout(douts[l][r], n) for l in range(nloops) for r in range(3)])
+    vc, tc, gc, qc = gamma.c(), tangent.c(), G.c(), q.c()
+    _check(lib().kqft_mloop_jvp(ctx(), C.byref(vc), C.byref(tc), C.byref(gc), C.byref(qc), nloops,
+                                C.byref(_opts(precision, KALL, 0, omega_batch)), O_, D_, _stream(stream)))
+    return outs, douts
+
+
+def workspace_bytes():
+    """(current, peak) device bytes of the library's workspaces."""
+    cur, pk = C.c_size_t(), C.c_size_t()
+    _check(lib().kqft_workspace_bytes(C.byref(cur), C.byref(pk)))
+    return cur.value, pk.value

@@ -192,3 +192,70 @@ def test_autograd_class_mask_drops_unselected_cotangents():
         grads.append([float(x) for x in torch.autograd.grad(loss, (Ut, Dt))])
     for a, b in zip(*grads):
         assert abs(a - b) <= 1e-12 * max(1.0, abs(b)), grads
+
+
+def _dual_arr(v, d):
+    out = np.zeros(v.shape + (4,))
+    out[..., 0], out[..., 1], out[..., 2], out[..., 3] = v.real, d.real, v.imag, d.imag
+    return out
+
+
+def _dual_vertex_along(ov, Z, dr0):
+    """The oracle vertex with derivative parts Z[r][class] on its classes and dr0 on r0."""
+    return O.Vertex(ov.grid, ov.r0, [O.Channel(c.coef, *[_dual_arr(getattr(c, x), Z[r][x]) for x in CL])
+                                     for r, c in enumerate(ov.ch)], dr0=dr0)
+
+
+@pytest.mark.parametrize("nloops", [1, 2, 3, 4])
+def test_mloop_adjoint_matches_oracle_duals(nloops):
+    """kqft_mloop_adjoint: d/dU, d/dDelta and the class cotangents of a random linear functional
+    of every order's insertions, against the oracle's forward-mode dual numbers of O.mloop
+    (U and Delta seeds, and a random direction in the class arrays); bar 1e-10."""
+    K = _K()
+    n, nq = 7, 15
+    ov, kv = pair(n, (31, 32, 33), (1.0, 0.9, 1.1), amp=0.1)
+    q = O.Quad(nq, 0, 20.0, 1.0)
+    cots = [[cot(n, 100 + 3 * l + r) for r in range(3)] for l in range(nloops)]
+    dgdot = [[K.Channel(1.0, *[to_dev(cots[l][r][x]) for x in CL]) for r in range(3)] for l in range(nloops)]
+    dgdot[0][1] = None  # an order/channel without cotangent
+    cots[0][1] = {x: np.zeros_like(cots[0][0][x]) for x in CL}
+    dG = [K.Channel(1.0, *[torch.zeros_like(getattr(kv.ch[r], x)) for x in CL]) for r in range(3)]
+    dscal = K.mloop_adjoint(kv, K.Propagator(D, T), K.Quad(nq), nloops, dgdot, dgamma=dG).cpu().numpy()
+
+    def functional(ins):
+        return sum(inner(cots[l][r], {x: O.dual_parts(getattr(ins[l][r], x))[1] for x in CL})
+                   for l in range(nloops) for r in range(3))
+
+    zero = [{x: np.zeros_like(getattr(ov.ch[r], x)) for x in CL} for r in range(3)]
+    ref_u = functional(O.mloop(_dual_vertex_along(ov, zero, 1.0), O.Prop(D, T), q, nloops, dual=True))
+    ref_d = functional(O.mloop(_dual_vertex_along(ov, zero, 0.0), O.Prop(D, T, dDelta=1.0), q, nloops, dual=True))
+    Z = [cot(n, 300 + r) for r in range(3)]
+    ref_z = functional(O.mloop(_dual_vertex_along(ov, Z, 0.0), O.Prop(D, T), q, nloops, dual=True))
+    got_z = sum(inner({x: getattr(dG[r], x).cpu().numpy() for x in CL}, Z[r]) for r in range(3))
+    for got, ref in ((dscal[0], ref_u), (dscal[1], ref_d), (got_z, ref_z)):
+        assert abs(got - ref) < 1e-10 * max(1.0, abs(ref)), (nloops, got, ref)
+
+
+@pytest.mark.parametrize("nloops,prec,tol", [(1, 0, 1e-12), (3, 0, 1e-12), (4, 0, 1e-12), (3, 1, 1e-6)])
+def test_mloop_jvp_matches_oracle_duals(nloops, prec, tol):
+    """kqft_mloop_jvp: insertions and their tangents along a random direction of the classes and
+    of r0, against the oracle's dual numbers of O.mloop (value and derivative parts)."""
+    K = _K()
+    n, nq = 7, 15
+    ov, kv = pair(n, (41, 42, 43), (1.0, 0.9, 1.1), amp=0.1)
+    Z = [cot(n, 400 + r) for r in range(3)]
+    tv = K.Vertex(kv.grid, 0.7, [K.Channel(kv.ch[r].coef, *[to_dev(Z[r][x]) for x in CL]) for r in range(3)])
+    out, dout = K.mloop_jvp(kv, tv, K.Propagator(D, T), K.Quad(nq), nloops, precision=prec)
+    ref = O.mloop(_dual_vertex_along(ov, Z, 0.7), O.Prop(D, T), O.Quad(nq, 0, 20.0, 1.0), nloops, dual=True)
+    torch.cuda.synchronize()
+    for l in range(nloops):
+        for r in range(3):
+            for x in CL:
+                val, der = O.dual_parts(getattr(ref[l][r], x))
+                for got, want in ((getattr(out[l][r], x), val), (getattr(dout[l][r], x), der)):
+                    g = got.cpu().numpy()
+                    sc = np.abs(want).max()
+                    if sc == 0.0:
+                        assert np.abs(g).max() == 0.0
+                        continue
+                    assert np.abs(g - want).max() < tol * sc, (l, r, x)

@@ -5,7 +5,8 @@
     Gamma'           = Gamma + h dGamma,   h = 0.1
     Sigma            = SDE(Gamma'),        chi = chi_a(Gamma')
 
-Reverse mode (torch.autograd over the hand-written bubble and SDE adjoints) gives
+Reverse mode (torch.autograd over the hand-written bubble, multiloop and SDE adjoints; the
+multiloop adjoint recomputes the insertions order by order instead of storing them) gives
 d Sigma^R(v = 0) / dU and projections of d Sigma^R(v) / dDelta; forward mode (the bubble is
 bilinear in its vertices) gives d chi^R(w) / dU for all w in one tangent pass.  At the full
 size (N = 151, Nq = 1501) they are checked against central finite differences of the FP64
@@ -123,6 +124,7 @@ def test_gradient_workload_n151_vs_finite_differences():
     rng = np.random.default_rng(5)
     cr, ci = rng.standard_normal(n), rng.standard_normal(n)
     print(f"gradient workload n={n} nq={nq}: autograd forward", flush=True)
+    torch.cuda.reset_peak_memory_stats()
     Ut = torch.tensor(U, dtype=torch.float64, requires_grad=True)
     Dt = torch.tensor(D, dtype=torch.float64, requires_grad=True)
     sig = forward_autograd(n, nq, Ut, Dt, noise)
@@ -132,6 +134,10 @@ def test_gradient_workload_n151_vs_finite_differences():
     gu_re, = torch.autograd.grad(s0.real, Ut, retain_graph=True)
     gu_im, = torch.autograd.grad(s0.imag, Ut, retain_graph=True)
     gd, = torch.autograd.grad(projD, Dt)
+    ws_now, ws_peak = K.workspace_bytes()
+    print(f"peak device memory: torch tensors {torch.cuda.max_memory_allocated() / 2**30:.2f} GiB, library "
+          f"workspaces {ws_peak / 2**30:.2f} GiB (insertions recomputed in the backward pass, not stored)",
+          flush=True)
     sig_val = sig.detach().cpu().numpy()
     del sig, s0, projD
     torch.cuda.empty_cache()
