@@ -692,6 +692,25 @@ int kqft_mloop_jvp(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_vertex* t
                    const kqft_quad* q, int nloops, const kqft_opts* opts, const kqft_chout* out,
                    const kqft_chout* dout, void* stream);
 
+/*
+ * kqft_chi_noalloc -- kqft_chi for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * susceptibility chi_r (same kernels, same arguments and layout of chi, no context), with
+ * every buffer the kernels need beyond gamma, G and chi -- grid nodes, quadrature nodes and
+ * weights (computed on the device), the other channels' target-order tables, Pi and the block
+ * partials -- carved out of one static device array of 64 MiB (kept per device until the
+ * process ends; the first call on a device looks its address up).  It calls no hipMalloc,
+ * hipFree or allocating library routine.  The transfer frequencies run in batches sized to
+ * what the array leaves; a vertex whose tables and one transfer frequency do not fit
+ * (about n^3 + 2 n^2 + n <= 65000 with both other channels active, e.g. n <= 39) returns
+ * KQFT_ENOMEM with the sizes in kqft_last_error().  Every call on a device shares that
+ * device's array and leaves its contents behind; nothing in it needs to start at zero.
+ * Calls that overlap on one device (two streams, or two host threads) race on the array:
+ * order them on one stream.  Launches on `stream` only; no host synchronisation.
+ */
+int kqft_chi_noalloc(int channel, const kqft_vertex* gamma, const kqft_propagator* G, const kqft_quad* q,
+                     double* chi, void* stream);
+
 /* Device bytes held by the library's workspaces (every context of the process): current
    and peak since the library was loaded.  Either pointer may be NULL, not both. */
 int kqft_workspace_bytes(size_t* current, size_t* peak);

@@ -9,6 +9,7 @@
 #include <functional>
 #include <atomic>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -64,7 +65,7 @@ struct ProfScope {
   hipStream_t s;
   hipEvent_t a = nullptr, b = nullptr;
   ProfScope(kqft_ctx* c_, int kind_, hipStream_t s_) : c(c_), kind(kind_), s(s_) {
-    if (c->prof && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) (void)hipEventRecord(a, s);
+    if (c && c->prof && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) (void)hipEventRecord(a, s);
   }
   ~ProfScope() {
     if (a && b) {
@@ -315,6 +316,24 @@ struct SideTables {
   const void* T[2] = {nullptr, nullptr};
 };
 
+// Table of channel r2 (classes c) in channel r's order into `out`.
+static TableArgs table_args(int r, int r2, const kqft_chvert& c, int n, void* out) {
+  TableArgs ta;
+  memset(&ta, 0, sizeof ta);
+  ta.n = n;
+  ta.r = r;
+  ta.r2 = r2;
+  ta.coef = c.coef;
+  for (int u = 0; u < 4; ++u) ta.mix[u] = kMix[r][u];
+  ta.K[0] = (const double2*)c.K1;
+  ta.K[1] = (const double2*)c.K2;
+  ta.K[2] = (const double2*)c.K2p;
+  ta.K[3] = (const double2*)c.K3;
+  ta.out = out;
+  return ta;
+}
+static bool table_active(const kqft_chvert& c) { return c.coef != 0.0 && (c.K1 || c.K2 || c.K2p || c.K3); }
+
 static int build_tables(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_vertex& R, bool f32,
                         SideTables& tl, SideTables& tr, hipStream_t s) {
   const size_t n = L.grid.n;
@@ -326,28 +345,16 @@ static int build_tables(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_v
       const int r2 = (r + 1 + d) % 3;
       out[sd]->T[d] = nullptr;
       const kqft_chvert& c = side[sd]->ch[r2];
-      if (c.coef == 0.0 || (!c.K1 && !c.K2 && !c.K2p && !c.K3)) continue;
+      if (!table_active(c)) continue;
       if (sd == 1 && same_channel(L.ch[r2], c) && tl.T[d]) {
         tr.T[d] = tl.T[d];
         continue;
       }
       int rc = ensure(ctx->tab[sd][d], bytes);
       if (rc) return rc;
-      TableArgs ta;
-      memset(&ta, 0, sizeof ta);
-      ta.n = (int)n;
-      ta.r = r;
-      ta.r2 = r2;
-      ta.coef = c.coef;
-      for (int u = 0; u < 4; ++u) ta.mix[u] = kMix[r][u];
-      ta.K[0] = (const double2*)c.K1;
-      ta.K[1] = (const double2*)c.K2;
-      ta.K[2] = (const double2*)c.K2p;
-      ta.K[3] = (const double2*)c.K3;
-      ta.out = ctx->tab[sd][d].p;
       {
         ProfScope ps(ctx, 1, s);
-        launch_table(ta, f32, s);
+        launch_table(table_args(r, r2, c, (int)n, ctx->tab[sd][d].p), f32, s);
       }
       out[sd]->T[d] = ctx->tab[sd][d].p;
     }
@@ -663,25 +670,29 @@ static int adjoint_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_v
 
 // ------------------------------------------------------------------ C ABI
 // Susceptibility of channel r of the vertex `gamma` into chi [2][n][16] (arguments checked).
-static int chi_core(kqft_ctx* ctx, int r, const kqft_vertex& gamma, const DProp& P, const double* nodes,
-                    const kqft_quad& q_bubble, double* chi, hipStream_t s) {
-  int rc;
+// Device buffers of one susceptibility evaluation: grid nodes, quadrature nodes and weights,
+// the other channels' target-order tables (nullptr = inactive), Pi and the block partials of
+// nb transfer frequencies.
+struct ChiBufs {
+  const double* nodes;
+  const double* qv;
+  const double* qw;
+  const void* T[2];
+  double2* pi;
+  double2* partial;
+  int nb;
+};
+
+// chi_r of `gamma` into chi [2][n][16] in batches of b.nb transfer frequencies.  prof: the
+// context whose profiling flag brackets the launches (nullptr: none).
+static void chi_run(kqft_ctx* prof, int r, const kqft_vertex& gamma, const DProp& P, int nq, const ChiBufs& b,
+                    double* chi, hipStream_t s) {
   const int n = gamma.grid.n;
-  const double *cqv, *cqw;
-  if ((rc = get_quad(ctx, q_bubble, &cqv, &cqw))) return rc;
-  const int nq = q_bubble.n;
-  const int nblk = chi_blocks(nq);
-  const int nb = std::max(1, std::min(n, (int)((256L << 20) / ((long)nq * 256))));
-  if ((rc = ensure(ctx->pi[0], (size_t)nb * nq * 256))) return rc;
-  if ((rc = ensure(ctx->chi_part, (size_t)nb * nblk * 32 * 16))) return rc;
-  // the two other channels in channel r's Keldysh order with its spin combinations
-  SideTables tabs, unused;
-  if ((rc = build_tables(ctx, r, gamma, gamma, false, tabs, unused, s))) return rc;
-  for (int iw0 = 0; iw0 < n; iw0 += nb) {
-    const int cnt = std::min(nb, n - iw0);
-    PiArgs pa{r, KQFT_PI_GG, cnt, nq, iw0, P, nodes, cqv, cqw, (double2*)ctx->pi[0].p};
+  for (int iw0 = 0; iw0 < n; iw0 += b.nb) {
+    const int cnt = std::min(b.nb, n - iw0);
+    PiArgs pa{r, KQFT_PI_GG, cnt, nq, iw0, P, b.nodes, b.qv, b.qw, b.pi};
     {
-      ProfScope ps(ctx, 0, s);
+      ProfScope ps(prof, 0, s);
       launch_pi(pa, s);
     }
     ChiArgs ca;
@@ -700,19 +711,42 @@ static int chi_core(kqft_ctx* ctx, int r, const kqft_vertex& gamma, const DProp&
       ca.K[2] = (const double2*)own.K2p;
       ca.K[3] = (const double2*)own.K3;
     }
-    ca.T[0] = tabs.T[0];
-    ca.T[1] = tabs.T[1];
+    ca.T[0] = b.T[0];
+    ca.T[1] = b.T[1];
     for (int u = 0; u < 4; ++u) ca.mix[u] = kMix[r][u];
-    ca.nodes = nodes;
-    ca.qv = cqv;
-    ca.pi = (const double2*)ctx->pi[0].p;
-    ca.partial = (double2*)ctx->chi_part.p;
+    ca.nodes = b.nodes;
+    ca.qv = b.qv;
+    ca.pi = b.pi;
+    ca.partial = b.partial;
     ca.out = (double2*)chi;
     {
-      ProfScope ps(ctx, 3, s);
+      ProfScope ps(prof, 3, s);
       launch_chi(ca, s);
     }
   }
+}
+
+static int chi_core(kqft_ctx* ctx, int r, const kqft_vertex& gamma, const DProp& P, const double* nodes,
+                    const kqft_quad& q_bubble, double* chi, hipStream_t s) {
+  int rc;
+  const int n = gamma.grid.n;
+  ChiBufs b;
+  memset(&b, 0, sizeof b);
+  b.nodes = nodes;
+  if ((rc = get_quad(ctx, q_bubble, &b.qv, &b.qw))) return rc;
+  const int nq = q_bubble.n;
+  const int nblk = chi_blocks(nq);
+  b.nb = std::max(1, std::min(n, (int)((256L << 20) / ((long)nq * 256))));
+  if ((rc = ensure(ctx->pi[0], (size_t)b.nb * nq * 256))) return rc;
+  if ((rc = ensure(ctx->chi_part, (size_t)b.nb * nblk * 32 * 16))) return rc;
+  b.pi = (double2*)ctx->pi[0].p;
+  b.partial = (double2*)ctx->chi_part.p;
+  // the two other channels in channel r's Keldysh order with its spin combinations
+  SideTables tabs, unused;
+  if ((rc = build_tables(ctx, r, gamma, gamma, false, tabs, unused, s))) return rc;
+  b.T[0] = tabs.T[0];
+  b.T[1] = tabs.T[1];
+  chi_run(ctx, r, gamma, P, nq, b, chi, s);
   return KQFT_OK;
 }
 
@@ -3215,6 +3249,102 @@ int kqft_workspace_bytes(size_t* current, size_t* peak) {
   if (!current && !peak) return fail(KQFT_EINVAL, "current and peak are both NULL");
   if (current) *current = g_ws_bytes.load();
   if (peak) *peak = g_ws_peak.load();
+  return KQFT_OK;
+}
+
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ allocation-free chi
+// Static scratch of kqft_chi_noalloc: one copy per device, held until the process ends.  In
+// host code `scratch` is only a host-side stand-in; the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current, and only that address
+// is handed to kernels.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+static int scratch_of_current_device(void** ptr) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(KQFT_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(KQFT_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return KQFT_OK;
+}
+
+extern "C" {
+
+int kqft_chi_noalloc(int channel, const kqft_vertex* gamma, const kqft_propagator* G, const kqft_quad* q,
+                     double* chi, void* stream) {
+  int rc;
+  if (channel < KQFT_CH_A || channel > KQFT_CH_T) return fail(KQFT_EINVAL, "channel must be 0, 1 or 2");
+  if (!G || !q) return fail(KQFT_EINVAL, "propagator and quadrature must be given");
+  if (q->n < 1 || (q->map != KQFT_QUAD_TAN_FINITE && q->map != KQFT_QUAD_TAN_INFINITE) ||
+      (q->map == KQFT_QUAD_TAN_FINITE && !(q->L > 0)) || !(q->a > 0))
+    return fail(KQFT_ESHAPE, "invalid quadrature");
+  if (q->n > 46340) return fail(KQFT_ESHAPE, "chi needs q->n <= 46340");
+  if ((rc = check_vertex(gamma, "gamma"))) return rc;
+  if (!chi) return fail(KQFT_EINVAL, "chi is NULL");
+  DProp P;
+  if ((rc = to_dprop(*G, P))) return rc;
+  void* base = nullptr;
+  if ((rc = scratch_of_current_device(&base))) return rc;
+  const int r = channel, n = gamma->grid.n, nq = q->n, nblk = chi_blocks(nq);
+  // layout: grid nodes | quadrature nodes, weights | tables of the active other channels |
+  // Pi and block partials of nb transfer frequencies (256-byte aligned pieces)
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t tbytes = ((size_t)n * n * n + 2 * (size_t)n * n + n) * 32 * sizeof(double2);
+  size_t fixed = up(n * sizeof(double)) + 2 * up(nq * sizeof(double));
+  bool act[2];
+  for (int d = 0; d < 2; ++d) {
+    act[d] = table_active(gamma->ch[(r + 1 + d) % 3]);
+    if (act[d]) fixed += up(tbytes);
+  }
+  const size_t per_w = (size_t)nq * 256 + (size_t)nblk * 32 * sizeof(double2);
+  const long nb = fixed + up(per_w) + 512 <= kScratchBytes ? (long)((kScratchBytes - fixed - 512) / per_w) : 0;
+  if (nb < 1)
+    return fail(KQFT_ENOMEM, "kqft_chi_noalloc: n = " + std::to_string(n) + ", nq = " + std::to_string(nq) +
+                                 " needs " + std::to_string(fixed + per_w) +
+                                 " bytes of scratch; the static maximum is " + std::to_string(kScratchBytes));
+  char* p = (char*)base;
+  ChiBufs b;
+  memset(&b, 0, sizeof b);
+  double* nodes = (double*)p;
+  p += up(n * sizeof(double));
+  double* qv = (double*)p;
+  p += up(nq * sizeof(double));
+  double* qw = (double*)p;
+  p += up(nq * sizeof(double));
+  b.nodes = nodes;
+  b.qv = qv;
+  b.qw = qw;
+  const hipStream_t s = (hipStream_t)stream;
+  for (int d = 0; d < 2; ++d)
+    if (act[d]) {
+      const int r2 = (r + 1 + d) % 3;
+      launch_table(table_args(r, r2, gamma->ch[r2], n, p), false, s);
+      b.T[d] = p;
+      p += up(tbytes);
+    }
+  b.nb = (int)std::min<long>(n, nb);
+  b.pi = (double2*)p;
+  p += up((size_t)b.nb * nq * 256);
+  b.partial = (double2*)p;
+  launch_grid_nodes(n, gamma->grid.map, gamma->grid.a, aux_of(gamma->grid.map, gamma->grid.L / gamma->grid.a), nodes,
+                    s);
+  launch_quad_nodes(nq, q->a, q->map == KQFT_QUAD_TAN_FINITE ? atan(q->L / q->a) : 0.5 * M_PI, qv, qw, s);
+  chi_run(nullptr, r, *gamma, P, nq, b, chi, s);
+  HIP_TRY(hipGetLastError());
   return KQFT_OK;
 }
 

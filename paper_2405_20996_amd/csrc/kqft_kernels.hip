@@ -2119,6 +2119,60 @@ void launch_mix(double2* x, const double2* f, size_t count, double alpha, hipStr
 }
 int chi_blocks(int nq) { return (int)std::min<long>(512, std::max<long>(1, ((long)nq * nq + 255) / 256)); }
 
+// ======================================================================== grids on the device
+// Frequency-grid nodes v_i = a f(x_i theta), x_i = -1 + 2i/(n-1) (the algebraic map exactly
+// odd: the upper half mirrors the lower), and the tangent-mapped Gauss-Legendre rule: the
+// same recurrences as the host tables, evaluated on the device so that a caller without
+// host-to-device staging can have them in its own buffer.
+__global__ void grid_nodes_kernel(int n, int map, double a, double theta, double* v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool mirror = map == 1 && i >= n - n / 2;
+  const int j = mirror ? n - 1 - i : i;
+  const double x = a * freq_of(map, (-1.0 + 2.0 * j / (n - 1)) * theta);
+  v[i] = mirror ? -x : x;
+}
+
+__global__ void quad_nodes_kernel(int nq, double a, double th, double* qv, double* qw) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (nq + 1) / 2) return;
+  double z = cos(M_PI * (i + 0.75) / (nq + 0.5)), dp = 1.0;
+  for (int it = 0; it < 100; ++it) {  // Newton on the Legendre recurrence
+    double p1 = 1.0, p2 = 0.0;
+    for (int j = 1; j <= nq; ++j) {
+      const double p3 = p2;
+      p2 = p1;
+      p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+    }
+    dp = nq * (z * p1 - p2) / (z * z - 1.0);
+    const double dz = p1 / dp;
+    z -= dz;
+    if (fabs(dz) < 1e-16) break;
+  }
+  double p1 = 1.0, p2 = 0.0;
+  for (int j = 1; j <= nq; ++j) {
+    const double p3 = p2;
+    p2 = p1;
+    p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+  }
+  dp = nq * (z * p1 - p2) / (z * z - 1.0);
+  const double gw = 2.0 / ((1.0 - z * z) * dp * dp);
+  const bool centre = (nq & 1) && i == nq / 2;
+  const double y = centre ? 0.0 : z;
+  const double c = cos(y * th), v = a * tan(y * th), w = gw * a * th / (c * c);
+  qv[nq - 1 - i] = v;
+  qw[nq - 1 - i] = w;
+  qv[i] = -v;
+  qw[i] = w;
+}
+
+void launch_grid_nodes(int n, int map, double a, double theta, double* v, hipStream_t s) {
+  hipLaunchKernelGGL(grid_nodes_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, map, a, theta, v);
+}
+void launch_quad_nodes(int nq, double a, double th, double* qv, double* qw, hipStream_t s) {
+  hipLaunchKernelGGL(quad_nodes_kernel, dim3(blocks_for((nq + 1) / 2, 64)), dim3(64), 0, s, nq, a, th, qv, qw);
+}
+
 // ======================================================================== Matsubara formalism
 // Leg indices (n1', n2', n1, n2) of channel r's (m, n, n') and back, every leg fermionic:
 //   a: n2 = n, n1' = n + m, n2' = n', n1 = n' + m;  p: n1' = n, n2' = m - n - 1, n1 = n',

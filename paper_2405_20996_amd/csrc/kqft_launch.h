@@ -185,6 +185,8 @@ void launch_loop(const LoopArgs& a, hipStream_t s);
 void launch_vloop(const VLoopArgs& a, hipStream_t s);
 void launch_chi(const ChiArgs& a, hipStream_t s);
 int chi_blocks(int nq);
+void launch_grid_nodes(int n, int map, double a, double theta, double* v, hipStream_t s);
+void launch_quad_nodes(int nq, double a, double th, double* qv, double* qw, hipStream_t s);
 void launch_sigma_split(int n, const double2* sigma, double2* sigR, double2* sigK, hipStream_t s);
 void launch_maxdiff(const double2* x, const double2* f, size_t count, double* partial, int nblk, hipStream_t s);
 void launch_mix(double2* x, const double2* f, size_t count, double alpha, hipStream_t s);

@@ -129,6 +129,8 @@ def lib():
         _lib.kqft_mloop_jvp.argtypes = [C.c_void_p, P(KqftVertex), P(KqftVertex), P(KqftPropagator), P(KqftQuad),
                                         C.c_int, P(KqftOpts), P(KqftChout), P(KqftChout), C.c_void_p]
         _lib.kqft_workspace_bytes.argtypes = [P(C.c_size_t), P(C.c_size_t)]
+        _lib.kqft_chi_noalloc.argtypes = [C.c_int, P(KqftVertex), P(KqftPropagator), P(KqftQuad), C.c_void_p,
+                                          C.c_void_p]
         _lib.kqft_chi.argtypes = [C.c_void_p, C.c_int, P(KqftVertex), P(KqftPropagator), P(KqftQuad), C.c_void_p,
                                   C.c_void_p]
         _lib.kqft_bubble_matsubara.argtypes = [C.c_void_p, C.c_int, P(KqftMVertex), P(KqftMVertex), P(KqftMProp),
@@ -171,7 +173,7 @@ def exported_symbols() -> list:
     names = ["kqft_ctx_create", "kqft_ctx_destroy", "kqft_last_error", "kqft_ctx_profile", "kqft_ctx_profile_read",
              "kqft_bubble_workspace", "kqft_bubble",
              "kqft_sde", "kqft_mloop_step", "kqft_bubble_adjoint", "kqft_sde_adjoint", "kqft_mloop_adjoint",
-             "kqft_mloop_jvp", "kqft_workspace_bytes"]
+             "kqft_mloop_jvp", "kqft_workspace_bytes", "kqft_chi_noalloc"]
     L = lib()
     return [n for n in names if hasattr(L, n)]
 
@@ -756,6 +758,17 @@ def mloop_jvp(gamma: Vertex, tangent: Vertex, G: Propagator, q: Quad, nloops: in
     _check(lib().kqft_mloop_jvp(ctx(), C.byref(vc), C.byref(tc), C.byref(gc), C.byref(qc), nloops,
                                 C.byref(_opts(precision, KALL, 0, omega_batch)), O_, D_, _stream(stream)))
     return outs, douts
+
+
+def chi_noalloc(channel: int, gamma: Vertex, G: Propagator, q: Quad, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """kqft_chi without device allocations: writes chi_r into the caller's out [2, n, 16]
+    complex128 (the library's static scratch holds every intermediate)."""
+    n = gamma.grid.n
+    _ptr(out, (2, n, 16), "out")
+    vc, gc, qc = gamma.c(), G.c(), q.c()
+    _check(lib().kqft_chi_noalloc(channel, C.byref(vc), C.byref(gc), C.byref(qc), C.c_void_p(out.data_ptr()),
+                                  _stream(stream)))
+    return out
 
 
 def workspace_bytes():
