@@ -315,7 +315,7 @@ typedef struct {
  * (L^inf = Gamma_0 + K1 + K2' of the own channel at (m, n''), R^inf = Gamma_0 + K1 + K2):
  * K3 = (L - L^inf) Pi (R - R^inf), K2 = (L - L^inf) Pi R^inf, K2' = L^inf Pi (R - R^inf),
  * K1 = L^inf Pi R^inf.  The product per bosonic frequency and combination is a complex
- * (2N + 1) x 2Nq x (2N + 1) GEMM (rocBLAS ZGEMM, strided batched over m).  left and right on
+ * (2N + 1) x 2Nq x (2N + 1) GEMM (the library's FP64 MFMA GEMM, batched over m).  left and right on
  * the same grid; out: all four classes (device, overwritten).  FP64.  KQFT_EINVAL for NULL
  * arguments, a bad channel or non-positive T / Delta; KQFT_ESHAPE for mismatched grids, M < 0,
  * N < 1, Nq < 1 or sizes whose panels exceed 2^31 entries.
@@ -635,8 +635,11 @@ int kqft_mloop_step(kqft_ctx* ctx, int n_points, const kqft_vertex* gamma, const
  * where class-array cotangents already include the channel coefficient.  The A/B panels
  * are recomputed (checkpointing) rather than stored.  Dynamic self-energies inside G
  * are held fixed.  dleft, dright: host arrays of 3 kqft_chout with device pointers;
- * dscal: device array of 3 doubles.  FP64 throughout; the scatter into class arrays uses
- * FP64 atomics (summation order not deterministic).
+ * dscal: device array of 3 doubles.  The transposed products conj(dA) = conj(dP) B^T and
+ * conj(dB) = conj(dP)^T A per transfer frequency run on the library's own MFMA GEMM, in FP64,
+ * or with opts->precision = KQFT_SPLIT_FP32 on FP32 MFMA (operands rounded to FP32, partial
+ * sums of 64 terms promoted to FP64); everything else in FP64.  The scatter into class arrays
+ * uses FP64 atomics (summation order not deterministic).
  */
 int kqft_bubble_adjoint(kqft_ctx* ctx, int channel, const kqft_vertex* left, const kqft_vertex* right,
                         const kqft_propagator* G, int pi_kind, const kqft_quad* q, const kqft_opts* opts,
@@ -671,8 +674,9 @@ int kqft_sde_adjoint(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propaga
  * and the centre term B_r(Gamma, gdot_{r,L}^(l-1)); the cotangents of gdot_rbar^(l-1) are
  * accumulated into the order below.  Recomputes sum_{l < nloops} l orders of insertions.
  * Working memory: 6 channel buffers of cotangents, 6 of recomputed insertions (each
- * 2(n + 2n^2 + n^3) x 16 complex), plus the bubble adjoint's workspace.  FP64 throughout;
- * same propagator restrictions and atomics as kqft_bubble_adjoint.
+ * 2(n + 2n^2 + n^3) x 16 complex), plus the bubble adjoint's workspace.  Recomputed
+ * insertions and transposed products in opts->precision, the rest in FP64; same propagator
+ * restrictions and atomics as kqft_bubble_adjoint.
  */
 int kqft_mloop_adjoint(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, const kqft_quad* q,
                        int nloops, const kqft_opts* opts, const kqft_chout* dgdot, const kqft_chout* dgamma,

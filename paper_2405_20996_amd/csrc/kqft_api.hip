@@ -14,7 +14,6 @@
 #include <tuple>
 #include <vector>
 
-#include <rocblas/rocblas.h>
 
 #include "kqft.h"
 #include "kqft_launch.h"
@@ -46,7 +45,6 @@ struct kqft_ctx {
   // internal streams (default priority, non-blocking): vertex gathers and GEMMs of
   // consecutive transfer-frequency batches overlap, ordered by events
   hipStream_t sg = nullptr, sm = nullptr;
-  rocblas_handle blas = nullptr;
   DevBuf adjw, dkf[2][3], phigrad, pq, pqsig, pqred, vtab[3], flow, flowml, ctmp, flowred, pqx, adapt, sdep, mf, mftmp,
       mfflow, mftail;
   // multiloop adjoint / tangent: recomputed insertions, cotangent accumulators and the
@@ -525,24 +523,17 @@ static int check_common(kqft_ctx* ctx, const kqft_propagator* G, const kqft_quad
 }
 
 // ------------------------------------------------------------------ adjoint core
-static int blas_ok(rocblas_status st, const char* what) {
-  if (st != rocblas_status_success) return fail(KQFT_EDEVICE, std::string(what) + ": rocBLAS status " + std::to_string((int)st));
-  return KQFT_OK;
-}
 
-// Reverse pass of one bubble (FP64).  dr0_left / dr0_right / dDelta: device doubles that
+// Reverse pass of one bubble: FP64, or with the two transposed products per transfer frequency
+// on FP32 MFMA (precision KQFT_SPLIT_FP32).  dr0_left / dr0_right / dDelta: device doubles that
 // receive the accumulated cotangents (dr0_left may equal dr0_right).
 static int adjoint_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_vertex& R, const kqft_propagator& G,
                         int kind, const kqft_quad& q, const kqft_chout& dout, const kqft_chout* dleft,
                         const kqft_chout* dright, double* dr0_left, double* dr0_right, double* dDelta,
-                        hipStream_t s) {
+                        hipStream_t s, int precision = KQFT_FP64) {
   int rc;
   const int n = L.grid.n;
   if ((rc = init_tables())) return rc;
-  if (!ctx->blas) {
-    if ((rc = blas_ok(rocblas_create_handle(&ctx->blas), "rocblas_create_handle"))) return rc;
-  }
-  if ((rc = blas_ok(rocblas_set_stream(ctx->blas, s), "rocblas_set_stream"))) return rc;
   const double *nodes, *qv, *qw;
   if ((rc = get_grid(ctx, L.grid, &nodes))) return rc;
   if ((rc = get_quad(ctx, q, &qv, &qw))) return rc;
@@ -591,7 +582,6 @@ static int adjoint_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_v
       }
     }
   }
-  const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
   for (int iw0 = 0; iw0 < n; iw0 += nb) {
     const int cnt = std::min(nb, n - iw0);
     PiArgs pa{r, kind, cnt, nq, iw0, P, nodes, qv, qw, pi};
@@ -607,20 +597,36 @@ static int adjoint_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_v
                   (const double2*)dout.K3, Dp[0], Dp[1]};
     launch_dpanel(dp, s);
     for (int c = 0; c < 2; ++c) {
-      // conj(dA)^T = B . conj(dP)^T  (column-major views of the row-major panels)
-      if ((rc = blas_ok(rocblas_zgemm_strided_batched(
-               ctx->blas, rocblas_operation_none, rocblas_operation_none, (int)Kp, (int)M, (int)M, &one,
-               (const rocblas_double_complex*)Bp[c], (int)Kp, M * Kp, (const rocblas_double_complex*)Dp[c], (int)M,
-               M * M, &zero, (rocblas_double_complex*)GA[c], (int)Kp, M * Kp, cnt),
-                        "zgemm dA")))
-        return rc;
-      // conj(dB) = A^T . conj(dP)
-      if ((rc = blas_ok(rocblas_zgemm_strided_batched(
-               ctx->blas, rocblas_operation_none, rocblas_operation_transpose, (int)Kp, (int)M, (int)M, &one,
-               (const rocblas_double_complex*)Ap[c], (int)Kp, M * Kp, (const rocblas_double_complex*)Dp[c],
-               (int)M, M * M, &zero, (rocblas_double_complex*)GB[c], (int)Kp, M * Kp, cnt),
-                        "zgemm dB")))
-        return rc;
+      // conj(dA) = conj(dP) . B^T-panel and conj(dB) (as a B^T panel) = conj(dP)^T . A, per
+      // transfer frequency, on the project's FP64 MFMA GEMM (row-major operands)
+      ZgemmArgs za;
+      memset(&za, 0, sizeof za);
+      za.M = (int)M;
+      za.N = (int)Kp;
+      za.K = (int)M;
+      za.batch = cnt;
+      za.A = Dp[c];
+      za.lda = M;
+      za.strideA = M * M;
+      za.ldb = za.ldc = Kp;
+      za.strideB = za.strideC = M * Kp;
+      ZgemmArgs zb = za;
+      za.B = Bp[c];
+      za.C = GA[c];
+      za.TA = 0;
+      zb.B = Ap[c];
+      zb.C = GB[c];
+      zb.TA = 1;
+      {
+        ProfScope ps(ctx, 2, s);
+        if (precision == KQFT_SPLIT_FP32) {
+          launch_zgemm_nn_f32(za, s);
+          launch_zgemm_nn_f32(zb, s);
+        } else {
+          launch_zgemm_nn(za, s);
+          launch_zgemm_nn(zb, s);
+        }
+      }
     }
     AdjScatterArgs al = sa[0];
     al.r = r;
@@ -1041,7 +1047,6 @@ int kqft_ctx_destroy(kqft_ctx* ctx) {
     for (auto& row : *set)
       for (auto& b : row) free_buf(b);
   free_buf(ctx->mlscr);
-  if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
   if (ctx->sg) (void)hipStreamDestroy(ctx->sg);
   if (ctx->sm) (void)hipStreamDestroy(ctx->sm);
   delete ctx;
@@ -1536,8 +1541,6 @@ int kqft_bubble_matsubara(kqft_ctx* ctx, int channel, const kqft_mvertex* left, 
   if (R * Kw > (1L << 30) || R * R > (1L << 30)) return fail(KQFT_ESHAPE, "Matsubara panels too large");
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
-  if (!ctx->blas && (rc = blas_ok(rocblas_create_handle(&ctx->blas), "rocblas_create_handle"))) return rc;
-  if ((rc = blas_ok(rocblas_set_stream(ctx->blas, s), "rocblas_set_stream"))) return rc;
   // per bosonic frequency: A and B for two combinations, C for two
   const size_t per_m = (size_t)(4 * R * Kw + 2 * R * R) * sizeof(double2);
   const long nb = std::max(1L, std::min(nbos, (long)((size_t)(512u << 20) / per_m)));
@@ -1555,7 +1558,6 @@ int kqft_bubble_matsubara(kqft_ctx* ctx, int channel, const kqft_mvertex* left, 
     a.P[1] = P[1];
     return a;
   };
-  const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
   for (int m0 = -g.M; m0 <= g.M; m0 += (int)nb) {
     const int cnt = (int)std::min<long>(nb, g.M - m0 + 1);
     {
@@ -1563,16 +1565,25 @@ int kqft_bubble_matsubara(kqft_ctx* ctx, int channel, const kqft_mvertex* left, 
       launch_mf_left(side(*left, A, m0, cnt), s);
       launch_mf_right(side(*right, B, m0, cnt), s);
     }
-    // row-major C = A B per frequency and combination, as column-major C^T = B^T A^T
+    // C = A B per bosonic frequency and combination on the project's FP64 MFMA GEMM
     for (int c = 0; c < 2; ++c) {
+      ZgemmArgs z;
+      memset(&z, 0, sizeof z);
+      z.A = A[c];
+      z.B = B[c];
+      z.C = Cm[c];
+      z.M = (int)R;
+      z.N = (int)R;
+      z.K = (int)Kw;
+      z.batch = cnt;
+      z.lda = Kw;
+      z.ldb = R;
+      z.ldc = R;
+      z.strideA = R * Kw;
+      z.strideB = R * Kw;
+      z.strideC = R * R;
       ProfScope ps(ctx, 2, s);
-      if ((rc = blas_ok(rocblas_zgemm_strided_batched(ctx->blas, rocblas_operation_none, rocblas_operation_none,
-                                                      (int)R, (int)R, (int)Kw, &one,
-                                                      (const rocblas_double_complex*)B[c], (int)R, R * Kw,
-                                                      (const rocblas_double_complex*)A[c], (int)Kw, R * Kw, &zero,
-                                                      (rocblas_double_complex*)Cm[c], (int)R, R * R, cnt),
-                        "rocblas_zgemm_strided_batched")))
-        return rc;
+      launch_zgemm_nn(z, s);
     }
     MEpiArgs e;
     memset(&e, 0, sizeof e);
@@ -2981,7 +2992,7 @@ int kqft_bubble_adjoint(kqft_ctx* ctx, int channel, const kqft_vertex* left, con
   if (!dout || !dleft || !dright || !dscal) return fail(KQFT_EINVAL, "dout, dleft, dright and dscal must be given");
   HIP_TRY(hipSetDevice(ctx->device));
   return adjoint_core(ctx, channel, *left, *right, *G, pi_kind, *q, *dout, dleft, dright, dscal, dscal + 1,
-                      dscal + 2, (hipStream_t)stream);
+                      dscal + 2, (hipStream_t)stream, opts->precision);
 }
 
 int kqft_sde_adjoint(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagator* G, const kqft_quad* q_bubble,
@@ -3082,8 +3093,8 @@ int kqft_mloop_adjoint(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propa
         return rc;
   if ((rc = ensure(ctx->mlscr, 4 * sizeof(double)))) return rc;
   double* dr0_drop = (double*)ctx->mlscr.p;  // r0 cotangents of insertion vertices (r0 = 0, no parameter)
-  kqft_opts o = *opts;
-  o.precision = KQFT_FP64;
+  kqft_opts o = *opts;  // recomputed insertions and transposed products in opts->precision
+  const int prec = o.precision;
   o.class_mask = KQFT_KALL;
   o.beta = 0;
   o.overlap = 0;
@@ -3125,11 +3136,11 @@ int kqft_mloop_adjoint(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propa
       const BubbleOut dl = ext(l - 1, r);
       if ((rc = copy_classes(dl, chout_of(dtot), n, true, s))) return rc;
       if ((rc = adjoint_core(ctx, r, rbar, *gamma, *G, KQFT_PI_GG, *q, chout_of(dl), drbar, dgamma, dr0_drop,
-                             dscal, dscal + 1, s)))
+                             dscal, dscal + 1, s, prec)))
         return rc;
       // right insertion B_r(Gamma, rbar)
       if ((rc = adjoint_core(ctx, r, *gamma, rbar, *G, KQFT_PI_GG, *q, chout_of(dtot), dgamma, drbar, dscal,
-                             dr0_drop, dscal + 1, s)))
+                             dr0_drop, dscal + 1, s, prec)))
         return rc;
       if (l >= 3) {  // centre term B_r(Gamma, L_r^(l-1)): its right cotangent goes to L_r^(l-1)
         kqft_vertex lv;
@@ -3140,7 +3151,7 @@ int kqft_mloop_adjoint(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propa
         memset(dlv, 0, sizeof dlv);
         dlv[r] = chout_of(ext(l - 2, r));
         if ((rc = adjoint_core(ctx, r, *gamma, lv, *G, KQFT_PI_GG, *q, chout_of(dtot), dgamma, dlv, dscal,
-                               dr0_drop, dscal + 1, s)))
+                               dr0_drop, dscal + 1, s, prec)))
           return rc;
       }
     }
@@ -3156,7 +3167,7 @@ int kqft_mloop_adjoint(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propa
       d1 = chout_of(class_view(ctx->mlbar[0][r].p, n));
     }
     if ((rc = adjoint_core(ctx, r, *gamma, *gamma, *G, KQFT_PI_DOT, *q, d1, dgamma, dgamma, dscal, dscal,
-                           dscal + 1, s)))
+                           dscal + 1, s, prec)))
       return rc;
   }
   HIP_TRY(hipGetLastError());

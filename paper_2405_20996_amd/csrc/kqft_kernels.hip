@@ -968,6 +968,230 @@ __global__ __launch_bounds__(256, 2) void zgemm_f32_kernel(GemmArgs g) {
   }
 }
 
+// ======================================================================== general complex GEMM
+// C[b] = op(A[b]) . B[b] in FP64 complex on v_mfma_f64_16x16x4f64, row-major operands:
+// op(A)[m][k] = A[m][k] (TA = false, lda = row length of A) or A[k][m] (TA = true), B[k][n],
+// C[m][n] overwritten.  Arbitrary M, N, K (edges zero-filled and masked).  64x64 complex
+// tile per 256-thread workgroup, four waves of 32x32, K blocks of 16 staged through a double
+// LDS buffer [k][m|n], three real products per complex multiply-add (Gauss), tiles of one
+// batch entry row-major and spread over the XCDs as in the bubble GEMMs.  Used by the
+// adjoint's transposed products and the Matsubara bubble.
+__global__ __launch_bounds__(256, 2) void zgemm_nn_kernel(ZgemmArgs g) {
+  using namespace f64g;
+  __shared__ double sA[2][2][BK][LDP];
+  __shared__ double sB[2][2][BK][LDP];
+  const int tiles = g.tiles_m * g.tiles_n;
+  const int total = g.batch * tiles;
+  const int per_xcd = (total + kXcds - 1) / kXcds;
+  const int logical = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+  const int b = logical / tiles;
+  if (b >= g.batch) return;
+  const int t = logical - b * tiles;
+  const int tm = t / g.tiles_n, tn = t % g.tiles_n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const double2* A = g.A + (size_t)b * g.strideA;
+  const double2* B = g.B + (size_t)b * g.strideB;
+  // global -> register staging: four consecutive complex entries per thread per operand
+  // A, TA = false: row m = tm*64 + tid/4, k = 4 (tid % 4) + e;  TA = true: k = tid/16, m = tm*64 + 4 (tid % 16) + e
+  // B: k = tid/16, n = tn*64 + 4 (tid % 16) + e
+  const int a_r = g.TA ? tid >> 4 : tid >> 2, a_c = g.TA ? (tid & 15) * 4 : (tid & 3) * 4;
+  const int b_k = tid >> 4, b_n = (tid & 15) * 4;
+  double2 ra[4], rb[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int m, k;
+      if (g.TA) {
+        k = k0 + a_r;
+        m = tm * BM + a_c + e;
+      } else {
+        m = tm * BM + a_r;
+        k = k0 + a_c + e;
+      }
+      ra[e] = (m < g.M && k < g.K) ? (g.TA ? A[(size_t)k * g.lda + m] : A[(size_t)m * g.lda + k]) : czero();
+      const int kb = k0 + b_k, nb = tn * BM + b_n + e;
+      rb[e] = (kb < g.K && nb < g.N) ? B[(size_t)kb * g.ldb + nb] : czero();
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int kk = g.TA ? a_r : a_c + e, mm = g.TA ? a_c + e : a_r;
+      sA[buf][0][kk][mm] = ra[e].x;
+      sA[buf][1][kk][mm] = ra[e].y;
+      sB[buf][0][b_k][b_n + e] = rb[e].x;
+      sB[buf][1][b_k][b_n + e] = rb[e].y;
+    }
+  };
+  d4 p[3][2][2];
+#pragma unroll
+  for (int x = 0; x < 3; ++x)
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) p[x][mb][nb] = d4{0.0, 0.0, 0.0, 0.0};
+  const int nk = (g.K + BK - 1) / BK;
+  load(0);
+  stash(0);
+  __syncthreads();
+  for (int kb = 0; kb < nk; ++kb) {
+    const int buf = kb & 1;
+    if (kb + 1 < nk) load((kb + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      const int kr = kk * 4 + (lane >> 4);
+      double ar[2], ai[2], br[2], bi[2], sa[2], sb[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        ar[u] = sA[buf][0][kr][wm * 32 + u * 16 + (lane & 15)];
+        ai[u] = sA[buf][1][kr][wm * 32 + u * 16 + (lane & 15)];
+        br[u] = sB[buf][0][kr][wn * 32 + u * 16 + (lane & 15)];
+        bi[u] = sB[buf][1][kr][wn * 32 + u * 16 + (lane & 15)];
+        sa[u] = ar[u] + ai[u];
+        sb[u] = br[u] + bi[u];
+      }
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+          p[0][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[mb], br[nb], p[0][mb][nb], 0, 0, 0);
+          p[1][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[mb], bi[nb], p[1][mb][nb], 0, 0, 0);
+          p[2][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[mb], sb[nb], p[2][mb][nb], 0, 0, 0);
+        }
+    }
+    if (kb + 1 < nk) stash(buf ^ 1);
+    __syncthreads();
+  }
+  double2* C = g.C + (size_t)b * g.strideC;
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = tm * BM + wm * 32 + mb * 16 + 4 * v + (lane >> 4);
+        const int col = tn * BM + wn * 32 + nb * 16 + (lane & 15);
+        if (row < g.M && col < g.N)
+          C[(size_t)row * g.ldc + col] =
+              make_double2(p[0][mb][nb][v] - p[1][mb][nb][v], p[2][mb][nb][v] - p[0][mb][nb][v] - p[1][mb][nb][v]);
+      }
+}
+
+// The same product with FP64 operands rounded to FP32 as they are staged into LDS (the split
+// path's rung: FP32 operands, no hi/lo correction), v_mfma_f32_32x32x2f32 with FP32 partial
+// sums over 64 complex terms promoted to FP64, FP64 output.  K blocks of 32; one 32x32
+// complex block per wave (lane l: A row l%32 / k l/32; D rows 8(v/4) + 4(l/32) + v%4, col l%32).
+__global__ __launch_bounds__(256, 2) void zgemm_nn_f32_kernel(ZgemmArgs g) {
+  using namespace f32g;
+  __shared__ float sA[2][2][BK][LDP];
+  __shared__ float sB[2][2][BK][LDP];
+  const int tiles = g.tiles_m * g.tiles_n;
+  const int total = g.batch * tiles;
+  const int per_xcd = (total + kXcds - 1) / kXcds;
+  const int logical = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+  const int b = logical / tiles;
+  if (b >= g.batch) return;
+  const int t = logical - b * tiles;
+  const int tm = t / g.tiles_n, tn = t % g.tiles_n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const double2* A = g.A + (size_t)b * g.strideA;
+  const double2* B = g.B + (size_t)b * g.strideB;
+  // A, TA = false: m = tm*64 + tid/4, k = 8 (tid % 4) + e;  TA = true: k = tid/8, m = tm*64 + 8 (tid % 8) + e
+  // B: k = tid/8, n = tn*64 + 8 (tid % 8) + e
+  const int a_r = g.TA ? tid >> 3 : tid >> 2, a_c = g.TA ? (tid & 7) * 8 : (tid & 3) * 8;
+  const int b_k = tid >> 3, b_n = (tid & 7) * 8;
+  float2 ra[8], rb[8];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      int m, k;
+      if (g.TA) {
+        k = k0 + a_r;
+        m = tm * BM + a_c + e;
+      } else {
+        m = tm * BM + a_r;
+        k = k0 + a_c + e;
+      }
+      const double2 x =
+          (m < g.M && k < g.K) ? (g.TA ? A[(size_t)k * g.lda + m] : A[(size_t)m * g.lda + k]) : czero();
+      ra[e] = make_float2((float)x.x, (float)x.y);
+      const int kb = k0 + b_k, nb = tn * BM + b_n + e;
+      const double2 y = (kb < g.K && nb < g.N) ? B[(size_t)kb * g.ldb + nb] : czero();
+      rb[e] = make_float2((float)y.x, (float)y.y);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int kk = g.TA ? a_r : a_c + e, mm = g.TA ? a_c + e : a_r;
+      sA[buf][0][kk][mm] = ra[e].x;
+      sA[buf][1][kk][mm] = ra[e].y;
+      sB[buf][0][b_k][b_n + e] = rb[e].x;
+      sB[buf][1][b_k][b_n + e] = rb[e].y;
+    }
+  };
+  const int am = wm * 32 + (lane & 31), bn = wn * 32 + (lane & 31);
+  double acc[2][16];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[x][v] = 0.0;
+  f16v p1, p2, p3;
+  const int nk = (g.K + BK - 1) / BK;
+  load(0);
+  stash(0);
+  __syncthreads();
+  for (int kb = 0; kb < nk; ++kb) {
+    const int buf = kb & 1;
+    if ((kb & 1) == 0)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) p1[v] = p2[v] = p3[v] = 0.f;
+    if (kb + 1 < nk) load((kb + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK / 2; ++kk) {
+      const int kr = kk * 2 + (lane >> 5);
+      const float ar = sA[buf][0][kr][am], ai = sA[buf][1][kr][am];
+      const float br = sB[buf][0][kr][bn], bi = sB[buf][1][kr][bn];
+      p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, p1, 0, 0, 0);
+      p2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bi, p2, 0, 0, 0);
+      p3 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar + ai, br + bi, p3, 0, 0, 0);
+    }
+    if (kb + 1 < nk) stash(buf ^ 1);
+    __syncthreads();
+    if ((kb & 1) == 1 || kb + 1 == nk)  // FP32 partial sums of 64 complex terms -> FP64
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        acc[0][v] += (double)(p1[v] - p2[v]);
+        acc[1][v] += (double)(p3[v] - p1[v] - p2[v]);
+      }
+  }
+  double2* C = g.C + (size_t)b * g.strideC;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int row = tm * BM + wm * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    const int col = tn * BM + wn * 32 + (lane & 31);
+    if (row < g.M && col < g.N) C[(size_t)row * g.ldc + col] = make_double2(acc[0][v], acc[1][v]);
+  }
+}
+
+void launch_zgemm_nn_f32(ZgemmArgs g, hipStream_t s) {
+  g.tiles_m = (g.M + 63) / 64;
+  g.tiles_n = (g.N + 63) / 64;
+  const long total = (long)g.batch * g.tiles_m * g.tiles_n;
+  const long grid = (total + kXcds - 1) / kXcds * kXcds;
+  hipLaunchKernelGGL(zgemm_nn_f32_kernel, dim3((unsigned)grid), dim3(256), 0, s, g);
+}
+
+void launch_zgemm_nn(ZgemmArgs g, hipStream_t s) {
+  g.tiles_m = (g.M + 63) / 64;
+  g.tiles_n = (g.N + 63) / 64;
+  const long total = (long)g.batch * g.tiles_m * g.tiles_n;
+  const long grid = (total + kXcds - 1) / kXcds * kXcds;
+  hipLaunchKernelGGL(zgemm_nn_kernel, dim3((unsigned)grid), dim3(256), 0, s, g);
+}
+
 // ======================================================================== SDE loop
 // Sigma^{a1'|a1}(v_i) = -1/2 sum_j w_j/(2 pi i) sum_{a2,a2'} [2 Phi^X + Phi^Y]
 //   (w = v_i - v_j, v' = (v_i + v_j)/2) G^{a2|a2'}(v_j);  Phi = K1(w) + K2'(w, v').

@@ -38,6 +38,20 @@ struct TableArgs {
   void* out;            // F3 [n^3] | F2v [n^2] | F2p [n^2] | F1 [n] records of 32 values
 };
 
+// C[b] = op(A[b]) . B[b], complex FP64, row-major (see zgemm_nn_kernel)
+struct ZgemmArgs {
+  const double2* A;
+  const double2* B;
+  double2* C;
+  long lda, ldb, ldc;
+  long strideA, strideB, strideC;
+  int M, N, K, batch;
+  int TA;                // op(A) = A^T when 1
+  int tiles_m, tiles_n;  // set by the launcher
+};
+void launch_zgemm_nn(ZgemmArgs g, hipStream_t s);
+void launch_zgemm_nn_f32(ZgemmArgs g, hipStream_t s);
+
 struct GemmArgs {
   const void* A[2];
   const void* B[2];

@@ -687,9 +687,10 @@ def parquet_solve(grid: Grid, U: float, Delta: float, T: float, q_bubble: Quad, 
 
 def bubble_adjoint(channel: int, left: Vertex, right: Vertex, G: Propagator, q: Quad, dout: Channel,
                    pi_kind: int = PI_GG, dleft: Optional[list] = None, dright: Optional[list] = None,
-                   omega_batch: int = 0, stream=None):
+                   omega_batch: int = 0, stream=None, precision: int = FP64):
     """Accumulates cotangents into dleft[r] / dright[r] (Channels, or None to skip) and returns
-    the device tensor dscal = (d left.r0, d right.r0, d G.Delta)."""
+    the device tensor dscal = (d left.r0, d right.r0, d G.Delta).  precision: FP64, or
+    SPLIT_FP32 for the transposed products on FP32 MFMA."""
     n = left.grid.n
     dev = torch.device("cuda", torch.cuda.current_device())
     dscal = torch.zeros(3, dtype=torch.float64, device=dev)
@@ -697,7 +698,7 @@ def bubble_adjoint(channel: int, left: Vertex, right: Vertex, G: Propagator, q: 
     DR = (KqftChout * 3)(*[_chout_opt(d, n) for d in (dright or [None] * 3)])
     lc, rc, gc, qc, oc = left.c(), right.c(), G.c(), q.c(), _chout(dout, n)
     _check(lib().kqft_bubble_adjoint(ctx(), channel, C.byref(lc), C.byref(rc), C.byref(gc), pi_kind, C.byref(qc),
-                                     C.byref(_opts(FP64, KALL, 1, omega_batch)), C.byref(oc), DL, DR,
+                                     C.byref(_opts(precision, KALL, 1, omega_batch)), C.byref(oc), DL, DR,
                                      C.c_void_p(dscal.data_ptr()), _stream(stream)))
     return dscal
 
@@ -720,7 +721,7 @@ def sde_adjoint(gamma: Vertex, G: Propagator, q_bubble: Quad, q_loop: Quad, dsig
 
 
 def mloop_adjoint(gamma: Vertex, G: Propagator, q: Quad, nloops: int, dgdot: Sequence[Sequence[Optional[Channel]]],
-                  dgamma: Optional[list] = None, stream=None):
+                  dgamma: Optional[list] = None, stream=None, precision: int = FP64):
     """Vector-Jacobian product of mloop_step for one point: dgdot[l][r] is the cotangent of
     the order-(l+1) insertion of channel r (a Channel, None = zero; a class left None counts as
     zero).  Accumulates into dgamma[r] (Channels, or None to skip) and returns the device
@@ -740,7 +741,7 @@ def mloop_adjoint(gamma: Vertex, G: Propagator, q: Quad, nloops: int, dgdot: Seq
     DG = (KqftChout * 3)(*[_chout_opt(d, n) for d in (dgamma or [None] * 3)])
     vc, gc, qc = gamma.c(), G.c(), q.c()
     _check(lib().kqft_mloop_adjoint(ctx(), C.byref(vc), C.byref(gc), C.byref(qc), nloops,
-                                    C.byref(_opts(FP64, KALL, 0, 0)), D, DG, C.c_void_p(dscal.data_ptr()),
+                                    C.byref(_opts(precision, KALL, 0, 0)), D, DG, C.c_void_p(dscal.data_ptr()),
                                     _stream(stream)))
     return dscal
 

@@ -259,3 +259,52 @@ def test_mloop_jvp_matches_oracle_duals(nloops, prec, tol):
                         assert np.abs(g).max() == 0.0
                         continue
                     assert np.abs(g - want).max() < tol * sc, (l, r, x)
+
+
+@pytest.mark.parametrize("r,kind", [(0, 0), (1, 1), (2, 0)])
+def test_bubble_adjoint_split_transposed_products(r, kind):
+    """The bubble adjoint with its transposed products on FP32 MFMA agrees with the FP64 adjoint
+    to 1e-6 (class cotangents of both sides, the r0 and Delta cotangents)."""
+    K = _K()
+    n, nq = 21, 67
+    _, kvL = pair(n, (1, 2, 3), (1.0, 0.7, 0.9))
+    _, kvR = pair(n, (4, 5, 6), (0.8, 1.0, 1.2))
+    c = cot(n, 9)
+    dout = K.Channel(1.0, *[to_dev(c[x]) for x in CL])
+    res = []
+    for prec in (K.FP64, K.SPLIT_FP32):
+        dL = [K.Channel(1.0, *[torch.zeros_like(getattr(kvL.ch[rr], x)) for x in CL]) for rr in range(3)]
+        dR = [K.Channel(1.0, *[torch.zeros_like(getattr(kvR.ch[rr], x)) for x in CL]) for rr in range(3)]
+        ds = K.bubble_adjoint(r, kvL, kvR, K.Propagator(D, T), K.Quad(nq), dout, pi_kind=kind, dleft=dL, dright=dR,
+                              precision=prec)
+        res.append((ds.cpu().numpy(), dL, dR))
+    (s64, L64, R64), (s32, L32, R32) = res
+    assert np.abs(s32 - s64).max() < 1e-6 * np.abs(s64).max()
+    for a_, b_ in ((L32, L64), (R32, R64)):
+        for rr in range(3):
+            for x in CL:
+                a, b = getattr(a_[rr], x), getattr(b_[rr], x)
+                assert float((a - b).abs().max()) < 1e-6 * float(b.abs().max()), (rr, x)
+
+
+def test_mloop_adjoint_split_matches_fp64():
+    """kqft_mloop_adjoint with recomputed insertions and transposed products in split FP32
+    against the FP64 adjoint (l <= 3)."""
+    K = _K()
+    n, nq = 11, 31
+    _, kv = pair(n, (51, 52, 53), (1.0, 0.9, 1.1), amp=0.1)
+    cots = [[cot(n, 500 + 3 * l + r) for r in range(3)] for l in range(3)]
+    dg = [[K.Channel(1.0, *[to_dev(cots[l][r][x]) for x in CL]) for r in range(3)] for l in range(3)]
+    res = []
+    for prec in (K.FP64, K.SPLIT_FP32):
+        dG = [K.Channel(1.0, *[torch.zeros_like(getattr(kv.ch[r], x)) for x in CL]) for r in range(3)]
+        ds = K.mloop_adjoint(kv, K.Propagator(D, T), K.Quad(nq), 3, dg, dgamma=dG, precision=prec)
+        res.append((ds.cpu().numpy(), dG))
+    (s64, G64), (s32, G32) = res
+    # the r0 and Delta cotangents are sums over every class entry of every order with
+    # cancelling signs: 1e-5 of their size (the arrays keep the split path's 1e-6)
+    assert np.abs(s32 - s64).max() < 1e-5 * np.abs(s64).max()
+    for r in range(3):
+        for x in CL:
+            a, b = getattr(G32[r], x), getattr(G64[r], x)
+            assert float((a - b).abs().max()) < 1e-6 * float(b.abs().max()), (r, x)

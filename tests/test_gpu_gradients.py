@@ -13,6 +13,8 @@ size (N = 151, Nq = 1501) they are checked against central finite differences of
 GPU forward map (step 1e-5, relative 1e-5); at a reduced size against the oracle's
 dual-number derivatives of the same map (relative 1e-10).
 """
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -127,13 +129,21 @@ def test_gradient_workload_n151_vs_finite_differences():
     torch.cuda.reset_peak_memory_stats()
     Ut = torch.tensor(U, dtype=torch.float64, requires_grad=True)
     Dt = torch.tensor(D, dtype=torch.float64, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     sig = forward_autograd(n, nq, Ut, Dt, noise)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
     s0 = sig[n // 2, 1]  # Sigma^R(v = 0)
     projD = (torch.from_numpy(cr).cuda() * sig[:, 1].real).sum() + (torch.from_numpy(ci).cuda() * sig[:, 1].imag).sum()
     print("reverse passes", flush=True)
+    t0 = time.perf_counter()
     gu_re, = torch.autograd.grad(s0.real, Ut, retain_graph=True)
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
     gu_im, = torch.autograd.grad(s0.imag, Ut, retain_graph=True)
     gd, = torch.autograd.grad(projD, Dt)
+    print(f"forward (seed, l <= 3 insertions, SDE) {t_fwd:.2f} s; one backward pass {t_bwd:.2f} s", flush=True)
     ws_now, ws_peak = K.workspace_bytes()
     print(f"peak device memory: torch tensors {torch.cuda.max_memory_allocated() / 2**30:.2f} GiB, library "
           f"workspaces {ws_peak / 2**30:.2f} GiB (insertions recomputed in the backward pass, not stored)",
