@@ -155,6 +155,7 @@ def main():
             "gemm_tflops": F / (gemm_ms_step * 1e-3) / 1e12,
             "gather_ms_per_step": prof["gather"][0] / args.steps,
             "pi_ms_per_step": prof["pi"][0] / args.steps,
+            "unmix_ms_per_step": prof["reduce"][0] / args.steps,
             "dtype": dtype,
         }
         outs[name] = out

@@ -50,6 +50,7 @@ struct kqft_ctx {
   // multiloop adjoint / tangent: recomputed insertions, cotangent accumulators and the
   // extra cotangents of the stored left insertions (two orders each, per channel)
   DevBuf mlrec[2][3], mlbar[2][3], mlext[2][3], mlscr;
+  DevBuf gemmP;  // split-path GEMM products of one batch, both spin combinations
   std::vector<hipEvent_t> events;
   size_t next_event = 0;
   bool prof = false;
@@ -426,6 +427,9 @@ static int bubble_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_ve
     if ((rc = ensure(ctx->panels[x], 4 * pbytes * nb))) return rc;
     if ((rc = ensure(ctx->pi[x], (size_t)nb * nq * 256))) return rc;
   }
+  // split path: the two combinations' products of a batch (GEMM and unmix run in order on sm)
+  const size_t prod = (size_t)nb * M * M * sizeof(double2);
+  if (f32 && (rc = ensure(ctx->gemmP, 2 * prod))) return rc;
   SideTables TL, TR;
   ctx->next_event = 0;
   hipEvent_t start;
@@ -491,9 +495,17 @@ static int bubble_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_ve
     g.K2 = out.K2;
     g.K2p = out.K2p;
     g.K3 = out.K3;
+    if (f32) {
+      g.P[0] = (double2*)ctx->gemmP.p;
+      g.P[1] = (double2*)((char*)ctx->gemmP.p + prod);
+    }
     {
       ProfScope ps(ctx, 2, ctx->sm);
       launch_gemm(g, o.precision, ctx->sm);
+    }
+    if (f32) {
+      ProfScope ps(ctx, 3, ctx->sm);
+      launch_unmix(g, ctx->sm);
     }
     HIP_TRY(hipEventRecord(mdone, ctx->sm));
     gemm_done.push_back(mdone);
@@ -1047,6 +1059,7 @@ int kqft_ctx_destroy(kqft_ctx* ctx) {
     for (auto& row : *set)
       for (auto& b : row) free_buf(b);
   free_buf(ctx->mlscr);
+  free_buf(ctx->gemmP);
   if (ctx->sg) (void)hipStreamDestroy(ctx->sg);
   if (ctx->sm) (void)hipStreamDestroy(ctx->sm);
   delete ctx;
@@ -1089,7 +1102,9 @@ size_t kqft_bubble_workspace(int n, int nq, int omega_batch, int precision) {
   // two panel buffers, two propagator-pair buffers, up to four target-order class tables
   const size_t nn = n;
   const size_t table = (nn * nn * nn + 2 * nn * nn + nn) * 32 * (precision == KQFT_SPLIT_FP32 ? 8 : 16);
-  return 2 * (per_w + (size_t)nq * 256) * nb + 4 * table;
+  // the split path's per-combination products of one batch
+  const size_t prod = precision == KQFT_SPLIT_FP32 ? 2 * (size_t)nb * 16 * (4 * nn + 4) * (4 * nn + 4) : 0;
+  return 2 * (per_w + (size_t)nq * 256) * nb + 4 * table + prod;
 }
 
 int kqft_bubble(kqft_ctx* ctx, int channel, const kqft_vertex* left, const kqft_vertex* right,
@@ -2916,26 +2931,34 @@ static int mloop_core(kqft_ctx* ctx, const kqft_vertex& V, const kqft_propagator
         HIP_TRY(hipMemcpyAsync(lv.K3, dst.K3, s3, hipMemcpyDeviceToDevice, s));
       }
       o.beta = 1;
+      const bool own_centre = l >= 3 && centre && r < 2;  // the centre term is wanted on its own
+      if (l >= 3 && !own_centre) {
+        // right insertion + centre term = B_r(Gamma, gdot_rbar^(l-1) + gdot_{r,L}^(l-1)): the
+        // bubble is linear in its right vertex, so one bubble of the combined vertex (the other
+        // channels from order l-1, channel r the stored left insertion) replaces two
+        BubbleOut lv = view_of(ctx->lstore[prev][r].p);
+        kqft_vertex rc_vert = rbar;
+        rc_vert.ch[r] = kqft_chvert{1.0, (const double*)lv.K1, (const double*)lv.K2, (const double*)lv.K2p,
+                                    (const double*)lv.K3};
+        if ((rc = bubble_core(ctx, r, V, rc_vert, G, KQFT_PI_GG, q, o, dst, s))) return rc;
+        continue;
+      }
       if ((rc = bubble_core(ctx, r, V, rbar, G, KQFT_PI_GG, q, o, dst, s))) return rc;
-      if (l >= 3) {  // centre term B_r(Gamma, gdot_{r,L}^(l-1))
+      if (own_centre) {  // centre term B_r(Gamma, gdot_{r,L}^(l-1)), kept apart for the Sigma_dot corrections
         BubbleOut lv = view_of(ctx->lstore[prev][r].p);
         kqft_vertex lvert;
         memset(&lvert, 0, sizeof lvert);
         lvert.grid = V.grid;
         lvert.ch[r] = kqft_chvert{1.0, (const double*)lv.K1, (const double*)lv.K2, (const double*)lv.K2p,
                                   (const double*)lv.K3};
-        if (centre && r < 2) {
-          BubbleOut ct = view_of(ctx->ctmp.p);
-          o.beta = 0;
-          if ((rc = bubble_core(ctx, r, V, lvert, G, KQFT_PI_GG, q, o, ct, s))) return rc;
-          comb(dst, 1.0, dst, 1.0, ct);
-          if (l == 3)
-            comb(centre[r], 1.0, ct, 0.0, ct);
-          else
-            comb(centre[r], 1.0, centre[r], 1.0, ct);
-        } else {
-          if ((rc = bubble_core(ctx, r, V, lvert, G, KQFT_PI_GG, q, o, dst, s))) return rc;
-        }
+        BubbleOut ct = view_of(ctx->ctmp.p);
+        o.beta = 0;
+        if ((rc = bubble_core(ctx, r, V, lvert, G, KQFT_PI_GG, q, o, ct, s))) return rc;
+        comb(dst, 1.0, dst, 1.0, ct);
+        if (l == 3)
+          comb(centre[r], 1.0, ct, 0.0, ct);
+        else
+          comb(centre[r], 1.0, centre[r], 1.0, ct);
       }
     }
   }

@@ -864,22 +864,35 @@ __global__ __launch_bounds__(256, 2) void zgemm_f64_kernel(GemmArgs g) {
 }
 
 // ======================================================================== split-FP32 GEMM
-// FP32 operands on v_mfma_f32_32x32x2f32 with FP32 accumulation over two K blocks of 32
-// complex, promoted to FP64 between them.  One 32x32 complex block per wave (lane l:
-// A row l%32 / k l/32; D rows 8(v/4) + 4(l/32) + v%4, col l%32).  Complex products take
-// three real products (Gauss): P1 = ar br, P2 = ai bi, P3 = (ar + ai)(br + bi), so that
-// Re = P1 - P2 and Im = P3 - P1 - P2 -- 6 instead of 8 real flops per complex multiply-add.
+// FP32 operands on v_mfma_f32_32x32x2f32, one spin combination per workgroup (grid = both
+// combinations x tiles), 64x64 complex tile, four waves of 32x32 complex (lane l: A row l%32 /
+// k l/32; D rows 8(v/4) + 4(l/32) + v%4, col l%32).  K blocks of 32 complex staged through a
+// single LDS buffer -- 33 KB, so three workgroups share a CU and one's MFMAs cover another's
+// staging and barriers -- with the next block's global loads in registers and each step's LDS
+// operands read one step ahead.  Complex products by three real products (Gauss): P1 = ar br,
+// P2 = ai bi, P3 = (ar + ai)(br + bi), Re = P1 - P2, Im = P3 - P1 - P2 -- 6 instead of 8 real
+// flops per complex multiply-add.  FP32 partial sums over four K blocks (128 complex terms),
+// promoted to FP64.  The combination's product goes to the workspace P[c][w][row][col];
+// unmix_kernel then undoes the spin diagonalisation into the classes.
 namespace f32g {
 constexpr int BM = 64, BK = 32, LDP = BM + 1;  // odd pitch: conflict-free transposed LDS stores
+constexpr int PROMO = 4;                      // K blocks per FP64 promotion
 }
 
-__global__ __launch_bounds__(256, 2) void zgemm_f32_kernel(GemmArgs g) {
+__global__ __launch_bounds__(256, 3) void zgemm_f32_kernel(GemmArgs g) {
   using namespace f32g;
-  __shared__ float sA[2][2][BK][LDP];
-  __shared__ float sB[2][2][BK][LDP];
-  int b, tm, tn;
-  tile_coords(g, b, tm, tn);
+  __shared__ float sA[2][BK][LDP];
+  __shared__ float sB[2][BK][LDP];
+  const int tiles = g.tms * g.tns;
+  const int total = 2 * g.nb * tiles;
+  const int per_xcd = (total + kXcds - 1) / kXcds;
+  int logical = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+  const int c = logical >= g.nb * tiles ? 1 : 0;  // combination-major order
+  logical -= c * g.nb * tiles;
+  const int b = logical / tiles;
   if (b >= g.nb) return;
+  const int t = logical - b * tiles;
+  const int tm = g.tm0 + t / g.tns, tn = g.tn0 + t % g.tns;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int lrow = tid >> 2, lk = (tid & 3) * 8;
@@ -888,83 +901,94 @@ __global__ __launch_bounds__(256, 2) void zgemm_f32_kernel(GemmArgs g) {
   const int brow = min(tn * BM + lrow, Mtot - 1);
   const int nk = Kp / BK;
   const int am = wm * 32 + (lane & 31), bn = wn * 32 + (lane & 31);
-  double acc64[2][2][16];  // [combo][re/im][v]
+  double acc[2][16];  // [re/im][v]
 #pragma unroll
-  for (int c = 0; c < 2; ++c)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int v = 0; v < 16; ++v) acc[x][v] = 0.0;
+  const float2* Ap = (const float2*)g.A[c] + (size_t)b * g.strideA + (size_t)arow * Kp + lk;
+  const float2* Bp = (const float2*)g.B[c] + (size_t)b * g.strideB + (size_t)brow * Kp + lk;
+  float2 ra[8], rb[8];
 #pragma unroll
-      for (int v = 0; v < 16; ++v) acc64[c][x][v] = 0.0;
-
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    const float2* Ap = (const float2*)g.A[c] + (size_t)b * g.strideA + (size_t)arow * Kp + lk;
-    const float2* Bp = (const float2*)g.B[c] + (size_t)b * g.strideB + (size_t)brow * Kp + lk;
-    float2 ra[8], rb[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      ra[e] = Ap[e];
-      rb[e] = Bp[e];
-    }
-    __syncthreads();
+  for (int e = 0; e < 8; ++e) {
+    ra[e] = Ap[e];
+    rb[e] = Bp[e];
+  }
+  auto stash = [&]() {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      sA[0][0][lk + e][lrow] = ra[e].x;
-      sA[0][1][lk + e][lrow] = ra[e].y;
-      sB[0][0][lk + e][lrow] = rb[e].x;
-      sB[0][1][lk + e][lrow] = rb[e].y;
+      sA[0][lk + e][lrow] = ra[e].x;
+      sA[1][lk + e][lrow] = ra[e].y;
+      sB[0][lk + e][lrow] = rb[e].x;
+      sB[1][lk + e][lrow] = rb[e].y;
     }
+  };
+  stash();
+  __syncthreads();
+  f16v p1, p2, p3;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) p1[v] = p2[v] = p3[v] = 0.f;
+  for (int kb = 0; kb < nk; ++kb) {
+    if (kb + 1 < nk) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        ra[e] = Ap[(size_t)(kb + 1) * BK + e];
+        rb[e] = Bp[(size_t)(kb + 1) * BK + e];
+      }
+    }
+    float ar[2], ai[2], br[2], bi[2];
+    ar[0] = sA[0][lane >> 5][am];
+    ai[0] = sA[1][lane >> 5][am];
+    br[0] = sB[0][lane >> 5][bn];
+    bi[0] = sB[1][lane >> 5][bn];
+#pragma unroll
+    for (int kk = 0; kk < BK / 2; ++kk) {
+      const int cur = kk & 1, nx = cur ^ 1;
+      if (kk + 1 < BK / 2) {
+        const int kr = (kk + 1) * 2 + (lane >> 5);
+        ar[nx] = sA[0][kr][am];
+        ai[nx] = sA[1][kr][am];
+        br[nx] = sB[0][kr][bn];
+        bi[nx] = sB[1][kr][bn];
+      }
+      p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[cur], br[cur], p1, 0, 0, 0);
+      p2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[cur], bi[cur], p2, 0, 0, 0);
+      p3 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[cur] + ai[cur], br[cur] + bi[cur], p3, 0, 0, 0);
+    }
+    __syncthreads();  // every wave is done with this block
+    if (kb + 1 < nk) stash();
     __syncthreads();
-    f16v p1, p2, p3;
-    // one K block from LDS buffer kb & 1, prefetching block kb + 1 through registers
-    auto kblock = [&](int kb) {
-      const int buf = kb & 1;
-      if (kb + 1 < nk) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          ra[e] = Ap[(size_t)(kb + 1) * BK + e];
-          rb[e] = Bp[(size_t)(kb + 1) * BK + e];
-        }
-      }
-#pragma unroll
-      for (int kk = 0; kk < BK / 2; ++kk) {
-        const int kr = kk * 2 + (lane >> 5);
-        const float ar = sA[buf][0][kr][am], ai = sA[buf][1][kr][am];
-        const float br = sB[buf][0][kr][bn], bi = sB[buf][1][kr][bn];
-        p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, p1, 0, 0, 0);
-        p2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bi, p2, 0, 0, 0);
-        p3 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar + ai, br + bi, p3, 0, 0, 0);
-      }
-      if (kb + 1 < nk) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          sA[buf ^ 1][0][lk + e][lrow] = ra[e].x;
-          sA[buf ^ 1][1][lk + e][lrow] = ra[e].y;
-          sB[buf ^ 1][0][lk + e][lrow] = rb[e].x;
-          sB[buf ^ 1][1][lk + e][lrow] = rb[e].y;
-        }
-      }
-      __syncthreads();
-    };
-    // FP32 partial sums over two K blocks (64 complex terms), then promoted to FP64
-    for (int kb = 0; kb < nk; kb += 2) {
-#pragma unroll
-      for (int v = 0; v < 16; ++v) p1[v] = p2[v] = p3[v] = 0.f;
-      kblock(kb);
-      if (kb + 1 < nk) kblock(kb + 1);
+    if (kb % PROMO == PROMO - 1 || kb + 1 == nk) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        acc64[c][0][v] += (double)(p1[v] - p2[v]);
-        acc64[c][1][v] += (double)(p3[v] - p1[v] - p2[v]);
+        acc[0][v] += (double)(p1[v] - p2[v]);
+        acc[1][v] += (double)(p3[v] - p1[v] - p2[v]);
+        p1[v] = p2[v] = p3[v] = 0.f;
       }
     }
   }
+  double2* P = g.P[c] + (size_t)b * Mtot * Mtot;
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
     const int row = tm * BM + wm * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
     const int col = tn * BM + wn * 32 + (lane & 31);
-    epilogue_store(g, b, row, col, make_double2(acc64[0][0][v], acc64[0][1][v]),
-                   make_double2(acc64[1][0][v], acc64[1][1][v]));
+    if (row < Mtot && col < Mtot) P[(size_t)row * Mtot + col] = make_double2(acc[0][v], acc[1][v]);
+  }
+}
+
+// The two combinations' products of the GEMM's tile range into the classes (epilogue_store).
+__global__ __launch_bounds__(256) void unmix_kernel(GemmArgs g) {
+  const int Mtot = g.M;
+  const int r0 = g.tm0 * 64, r1 = min((g.tm0 + g.tms) * 64, Mtot);
+  const int c0 = g.tn0 * 64, c1 = min((g.tn0 + g.tns) * 64, Mtot);
+  const long rows = r1 - r0, cols = c1 - c0;
+  const long total = (long)g.nb * rows * cols;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int col = c0 + (int)(e % cols);
+    const int row = r0 + (int)((e / cols) % rows);
+    const int b = (int)(e / (cols * rows));
+    const size_t off = ((size_t)b * Mtot + row) * Mtot + col;
+    epilogue_store(g, b, row, col, g.P[0][off], g.P[1][off]);
   }
 }
 
@@ -2232,11 +2256,14 @@ void launch_gather(const GatherArgs& a, bool left, bool f32, hipStream_t s) {
 void launch_gemm(const GemmArgs& g, int precision, hipStream_t s) {
   const int total = g.nb * g.tms * g.tns;
   dim3 grid((unsigned)(((total + kXcds - 1) / kXcds) * kXcds));
-  if (precision == 0)
+  if (precision == 0) {
     hipLaunchKernelGGL(zgemm_f64_kernel, grid, dim3(256), 0, s, g);
-  else
-    hipLaunchKernelGGL(zgemm_f32_kernel, grid, dim3(256), 0, s, g);
+  } else {
+    dim3 grid2((unsigned)(((2 * total + kXcds - 1) / kXcds) * kXcds));
+    hipLaunchKernelGGL(zgemm_f32_kernel, grid2, dim3(256), 0, s, g);
+  }
 }
+void launch_unmix(const GemmArgs& g, hipStream_t s) { hipLaunchKernelGGL(unmix_kernel, dim3(4096), dim3(256), 0, s, g); }
 void launch_loop(const LoopArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(loop_kernel, dim3(a.g.n), dim3(256), 0, s, a);
 }

@@ -65,6 +65,7 @@ struct GemmArgs {
   double2* K2;
   double2* K2p;
   double2* K3;
+  double2* P[2];  // split path: per-combination products [nb][M][M] (workspace)
 };
 
 struct LoopArgs {
@@ -195,6 +196,8 @@ void launch_table(const TableArgs& a, bool f32, hipStream_t s);
 void launch_pi(const PiArgs& a, hipStream_t s);
 void launch_gather(const GatherArgs& a, bool left, bool f32, hipStream_t s);
 void launch_gemm(const GemmArgs& g, int precision, hipStream_t s);
+// split path: the two combinations' products into the classes (after launch_gemm, same stream)
+void launch_unmix(const GemmArgs& g, hipStream_t s);
 void launch_loop(const LoopArgs& a, hipStream_t s);
 void launch_vloop(const VLoopArgs& a, hipStream_t s);
 void launch_chi(const ChiArgs& a, hipStream_t s);
