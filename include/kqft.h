@@ -60,7 +60,10 @@
  *   after one call with the same sizes (workspace grown, grids and quadratures
  *   cached) they allocate nothing, so a call on a capturing stream records into the
  *   graph -- the library's internal streams join through events recorded on
- *   `stream` -- and the graph replays it (pointers as captured).  The solvers, the
+ *   `stream` -- and the graph replays it (pointers as captured).  Under capture each
+ *   bubble must run in one transfer-frequency batch (opts->omega_batch >= n, or an
+ *   automatic or tuned batch covering the grid): a multi-batch schedule is rejected
+ *   with KQFT_EINVAL (its capture crashed the runtime's graph instantiation).  The solvers, the
  *   flow, the Hartree term, the adaptive bubble and the adjoints synchronise or
  *   clear memory and are not to be captured.
  */
@@ -617,7 +620,8 @@ int kqft_parquet_solve_matsubara(kqft_ctx* ctx, const kqft_mgrid* grid, double U
  *   l >= 3: gdot_r = L + R + B_r(Gamma, gdot_{r,L}^(l-1)),
  * with gdot_rbar the sum of the two channels other than r at the previous order and
  * the centre term reusing the stored left insertion of order l-1 (which equals
- * B_r(gdot_rbar^(l-2), Gamma)).  Delta-flow single-scale propagator, no Katanin term.
+ * B_r(gdot_rbar^(l-2), Gamma)); R and the centre term are evaluated as one bubble of the
+ * combined right vertex gdot_rbar^(l-1) + gdot_{r,L}^(l-1) (the bubble is linear in it).  Delta-flow single-scale propagator, no Katanin term.
  * gamma, G, q: host arrays of n_points structs.  dgamma: host array of
  * n_points * nloops * 3 kqft_chout (point-major, then order, then channel) whose
  * device arrays (all four classes required) receive each order's sum of insertions.
@@ -696,6 +700,21 @@ int kqft_mloop_adjoint(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propa
 int kqft_mloop_jvp(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_vertex* tangent, const kqft_propagator* G,
                    const kqft_quad* q, int nloops, const kqft_opts* opts, const kqft_chout* out,
                    const kqft_chout* dout, void* stream);
+
+/*
+ * kqft_bubble_tune -- autotuner of the bubble's schedule (not in the paper): times kqft_bubble
+ * with the given arguments for transfer-frequency batches of the whole grid divided into 1, 2,
+ * 3, 4, 6, 8, 12 or 16 parts, down to about 8 frequencies (those whose workspace, kqft_bubble_workspace, stays
+ * within max_workspace bytes; 0 = no limit), one warm-up and one timed call each, and keeps the
+ * fastest in the context for (n, q->n, opts->precision): from then on every bubble of that
+ * shape with opts->omega_batch = 0 -- kqft_bubble, kqft_mloop_step, the solvers and the flows --
+ * uses it.  Returns it in *omega_batch and its time in *ms (may be NULL).  `out` is
+ * overwritten (scratch while tuning; beta is ignored).  Synchronises `stream`; not to be
+ * captured.
+ */
+int kqft_bubble_tune(kqft_ctx* ctx, int channel, const kqft_vertex* left, const kqft_vertex* right,
+                     const kqft_propagator* G, int pi_kind, const kqft_quad* q, const kqft_opts* opts,
+                     const kqft_chout* out, size_t max_workspace, int* omega_batch, double* ms, void* stream);
 
 /*
  * kqft_chi_noalloc -- kqft_chi for callers that cannot allocate device memory (code under HIP

@@ -51,6 +51,8 @@ struct kqft_ctx {
   // extra cotangents of the stored left insertions (two orders each, per channel)
   DevBuf mlrec[2][3], mlbar[2][3], mlext[2][3], mlscr;
   DevBuf gemmP;  // split-path GEMM products of one batch, both spin combinations
+  // autotuned transfer-frequency batch per (n, nq, precision), used when opts.omega_batch = 0
+  std::map<std::tuple<int, int, int>, int> tuned_nb;
   std::vector<hipEvent_t> events;
   size_t next_event = 0;
   bool prof = false;
@@ -421,7 +423,22 @@ static int bubble_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_ve
   // batch of transfer frequencies (two panel buffers in flight)
   const size_t per_w = panel_bytes_per_w(n, nq, o.precision);
   int nb = o.omega_batch > 0 ? o.omega_batch : (int)std::max<size_t>(1, ((size_t)4 << 30) / per_w);
+  if (o.omega_batch <= 0) {
+    auto it = ctx->tuned_nb.find(std::make_tuple(n, nq, o.precision));
+    if (it != ctx->tuned_nb.end()) nb = it->second;
+  }
   nb = std::min(nb, n);
+  {
+    // A schedule of several transfer-frequency batches (gathers of the next batch ordered
+    // after the GEMM of the previous one across the two internal streams) crashed the
+    // runtime's graph instantiation when captured; a one-batch schedule captures and replays
+    // bit for bit.  Under capture only the latter is accepted.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone && nb < n)
+      return fail(KQFT_EINVAL, "under stream capture a bubble must run in one transfer-frequency batch "
+                               "(omega_batch >= n)");
+  }
   const size_t pbytes = (size_t)M * Kp * elt;  // one panel of one transfer frequency
   for (int x = 0; x < 2; ++x) {
     if ((rc = ensure(ctx->panels[x], 4 * pbytes * nb))) return rc;
@@ -1125,6 +1142,58 @@ int kqft_bubble(kqft_ctx* ctx, int channel, const kqft_vertex* left, const kqft_
   HIP_TRY(hipSetDevice(ctx->device));
   BubbleOut o{(double2*)out->K1, (double2*)out->K2, (double2*)out->K2p, (double2*)out->K3};
   return bubble_core(ctx, channel, *left, *right, *G, pi_kind, *q, *opts, o, (hipStream_t)stream);
+}
+
+int kqft_bubble_tune(kqft_ctx* ctx, int channel, const kqft_vertex* left, const kqft_vertex* right,
+                     const kqft_propagator* G, int pi_kind, const kqft_quad* q, const kqft_opts* opts,
+                     const kqft_chout* out, size_t max_workspace, int* omega_batch, double* ms, void* stream) {
+  int rc;
+  if (!omega_batch) return fail(KQFT_EINVAL, "omega_batch is NULL");
+  if ((rc = check_common(ctx, G, q, opts))) return rc;
+  if ((rc = check_vertex(left, "left vertex")) || (rc = check_vertex(right, "right vertex"))) return rc;
+  const int n = left->grid.n;
+  kqft_opts o = *opts;
+  o.beta = 0;  // the outputs are scratch while tuning
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  // candidates: the whole grid and its halves, thirds, ... down to about 8 frequencies
+  std::vector<int> cand;
+  for (int parts : {1, 2, 3, 4, 6, 8, 12, 16}) {
+    const int nb = (n + parts - 1) / parts;
+    if (!cand.empty() && cand.back() == nb) continue;
+    if (nb < 8 && !cand.empty()) break;
+    if (max_workspace && kqft_bubble_workspace(n, q->n, nb, o.precision) > max_workspace) continue;
+    cand.push_back(nb);
+  }
+  if (cand.empty()) return fail(KQFT_ENOMEM, "no transfer-frequency batch fits the workspace limit");
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int best = cand[0];
+  float best_ms = 1e30f;
+  for (int nb : cand) {
+    o.omega_batch = nb;
+    if ((rc = kqft_bubble(ctx, channel, left, right, G, pi_kind, q, &o, out, stream))) break;  // warm-up, sizes
+    float t = 0.f;
+    if (hipEventRecord(e0, s) != hipSuccess || (rc = kqft_bubble(ctx, channel, left, right, G, pi_kind, q, &o, out,
+                                                                 stream)) ||
+        hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+      if (!rc) rc = fail(KQFT_EDEVICE, "event timing failed while tuning");
+      break;
+    }
+    if (t < best_ms) {
+      best_ms = t;
+      best = nb;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  ctx->tuned_nb[std::make_tuple(n, q->n, o.precision)] = best;
+  *omega_batch = best;
+  if (ms) *ms = best_ms;
+  return KQFT_OK;
 }
 
 // Gauss-Lobatto-Kronrod rules on [-1, 1] (Sec. Frequency integration).  GL4 and its 7-point

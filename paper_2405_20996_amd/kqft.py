@@ -129,6 +129,9 @@ def lib():
         _lib.kqft_mloop_jvp.argtypes = [C.c_void_p, P(KqftVertex), P(KqftVertex), P(KqftPropagator), P(KqftQuad),
                                         C.c_int, P(KqftOpts), P(KqftChout), P(KqftChout), C.c_void_p]
         _lib.kqft_workspace_bytes.argtypes = [P(C.c_size_t), P(C.c_size_t)]
+        _lib.kqft_bubble_tune.argtypes = [C.c_void_p, C.c_int, P(KqftVertex), P(KqftVertex), P(KqftPropagator),
+                                          C.c_int, P(KqftQuad), P(KqftOpts), P(KqftChout), C.c_size_t,
+                                          P(C.c_int), P(C.c_double), C.c_void_p]
         _lib.kqft_chi_noalloc.argtypes = [C.c_int, P(KqftVertex), P(KqftPropagator), P(KqftQuad), C.c_void_p,
                                           C.c_void_p]
         _lib.kqft_chi.argtypes = [C.c_void_p, C.c_int, P(KqftVertex), P(KqftPropagator), P(KqftQuad), C.c_void_p,
@@ -173,7 +176,7 @@ def exported_symbols() -> list:
     names = ["kqft_ctx_create", "kqft_ctx_destroy", "kqft_last_error", "kqft_ctx_profile", "kqft_ctx_profile_read",
              "kqft_bubble_workspace", "kqft_bubble",
              "kqft_sde", "kqft_mloop_step", "kqft_bubble_adjoint", "kqft_sde_adjoint", "kqft_mloop_adjoint",
-             "kqft_mloop_jvp", "kqft_workspace_bytes", "kqft_chi_noalloc"]
+             "kqft_mloop_jvp", "kqft_workspace_bytes", "kqft_chi_noalloc", "kqft_bubble_tune"]
     L = lib()
     return [n for n in names if hasattr(L, n)]
 
@@ -777,3 +780,18 @@ def workspace_bytes():
     cur, pk = C.c_size_t(), C.c_size_t()
     _check(lib().kqft_workspace_bytes(C.byref(cur), C.byref(pk)))
     return cur.value, pk.value
+
+
+def bubble_tune(channel: int, left: Vertex, right: Vertex, G: Propagator, q: Quad, pi_kind: int = PI_GG,
+                precision: int = FP64, max_workspace: int = 0, out: Optional[Channel] = None, stream=None):
+    """Autotune the transfer-frequency batch of this bubble shape (kqft_bubble_tune); the
+    context keeps the winner for every later call with omega_batch = 0.  Returns (batch, ms)."""
+    n = left.grid.n
+    if out is None:
+        out = alloc_channel(n)
+    nb, ms = C.c_int(), C.c_double()
+    lc, rc, gc, qc, oc = left.c(), right.c(), G.c(), q.c(), _chout(out, n)
+    _check(lib().kqft_bubble_tune(ctx(), channel, C.byref(lc), C.byref(rc), C.byref(gc), pi_kind, C.byref(qc),
+                                  C.byref(_opts(precision, KALL, 0, 0)), C.byref(oc), max_workspace, C.byref(nb),
+                                  C.byref(ms), _stream(stream)))
+    return nb.value, ms.value

@@ -123,3 +123,19 @@ def test_multiloop_step_replays_from_a_graph():
     t_graph = _time(g.replay, 5)
     print(f"multiloop step, two points (n = 9, 15), orders <= 3: eager {t_eager * 1e3:.2f} ms, graph replay "
           f"{t_graph * 1e3:.2f} ms", flush=True)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_bubble_tune_keeps_the_result(precision):
+    """The autotuner picks one of its candidate batches, the context applies it to later calls
+    with omega_batch = 0, and the result does not depend on the batch (bit for bit)."""
+    K = _K()
+    n, nq = 21, 61
+    V, P, q = _seed(K, n, nq)
+    nb, ms = K.bubble_tune(1, V, V, P, q, precision=precision)
+    assert nb in {(n + p - 1) // p for p in (1, 2, 3, 4, 6, 8, 12, 16)} and ms > 0
+    auto = K.bubble(1, V, V, P, q, precision=precision)
+    for b in (1, 5, n):
+        ref = K.bubble(1, V, V, P, q, precision=precision, omega_batch=b)
+        for x in CL:
+            assert torch.equal(getattr(auto, x), getattr(ref, x)), (b, x)

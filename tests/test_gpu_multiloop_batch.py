@@ -3,8 +3,11 @@ T in {0.01, 0.1}, N cycling through 51, 101, 151, 201 with Nq = 10 N - 9, loop o
 l = 1..4 in all three channels (27 bubbles per point), Pidot from the Delta-flow
 single-scale propagator, on the PT2 seed + 1e-3 noise.
 
-Each point runs through kqft_mloop_step on the split-FP32 path; the test reports the
-algorithmic throughput over the batch.  Parity: on every point every order, channel and
+Each point runs through kqft_mloop_step on the split-FP32 path with the transfer-frequency
+batch the autotuner (kqft_bubble_tune) picked for its grid size, and -- at N <= 101, where one
+transfer-frequency batch per bubble fits (the only schedule the library captures) -- again as
+a HIP graph replay of the same step (equal to the eager result bit for bit); the test reports
+the batch time, the replay times and the GEMM efficiency per grid size.  Parity: on every point every order, channel and
 class of the split path agrees with the FP64 path to 1e-6 (relative to each array's
 max-norm); on the points with N <= 101 the first order (l = 1, the Pidot bubble of the seed
 vertex) agrees with the oracle on sampled outputs, FP64 to 1e-12 and split to 1e-6.  Orders
@@ -65,10 +68,26 @@ def sampled_error(out, pts, ref):
     return worst
 
 
+def _capture(fn):
+    """fn recorded into a HIP graph after one warm-up call on a side stream."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        res = fn()
+    return g, res
+
+
 def test_multiloop_batch_twelve_points():
     K = _K()
     noises = {}
-    flop, seconds = 0.0, 0.0
+    flop_def, flop_exec, seconds, seconds_graph = 0.0, 0.0, 0.0, 0.0
+    tuned = {}
+    per_n = {}
     for idx, (U, T, n) in enumerate(MULTILOOP_POINTS):
         nq = 10 * n - 9
         if n not in noises:
@@ -76,15 +95,31 @@ def test_multiloop_batch_twelve_points():
         noise = noises[n]
         print(f"point {idx}: U={U} T={T} n={n} nq={nq}", flush=True)
         V, P, q = gpu_seed(K, n, nq, U, T, noise)
+        if n not in tuned:  # the autotuner picks the transfer-frequency batch of this shape
+            tuned[n] = K.bubble_tune(0, V, V, P, q, pi_kind=K.PI_GG, precision=K.SPLIT_FP32,
+                                     max_workspace=48 << 30)
+            print(f"   autotuned batch for n={n}: {tuned[n][0]} frequencies ({tuned[n][1]:.2f} ms per bubble)",
+                  flush=True)
         torch.cuda.synchronize()
+        K.profile(True)
         t0 = time.perf_counter()
         out = K.mloop_step([V], [P], [q], NLOOPS, precision=K.SPLIT_FP32)[0]
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        f = 27 * 2.0 * n * 8.0 * (4 * n + 4) * 4.0 * nq * (4 * n + 4)
-        flop += f
+        prof = K.profile_read()
+        K.profile(False)
+        f1 = 2.0 * n * 8.0 * (4 * n + 4) * 4.0 * nq * (4 * n + 4)  # one bubble
+        flop_def += 27 * f1  # l <= 4: 3 + 6 + 9 + 9 bubbles as the flow equations write them
+        flop_exec += 21 * f1  # right insertion and centre term merged from l = 3 on
         seconds += dt
-        print(f"   split mloop l<=4: {dt * 1e3:.1f} ms, {f / dt / 1e12:.2f} TFLOP/s", flush=True)
+        gemm_ms = prof["gemm"][0]
+        e = per_n.setdefault(n, [0.0, 0.0])
+        e[0] += 21 * f1
+        e[1] += gemm_ms * 1e-3
+        print(f"   split mloop l<=4: {dt * 1e3:.1f} ms, {21 * f1 / dt / 1e12:.2f} TFLOP/s executed, "
+              f"{27 * f1 / dt / 1e12:.2f} TFLOP/s per the 27 bubbles of the equations; GEMMs "
+              f"{gemm_ms:.1f} ms = {21 * f1 / (gemm_ms * 1e-3) / 1e12:.1f} TFLOP/s, gathers {prof['gather'][0]:.1f} ms",
+              flush=True)
         for ell in range(NLOOPS):
             for r in range(3):
                 assert all(bool(torch.isfinite(getattr(out[ell][r], x)).all()) for x in CL), (idx, ell, r)
@@ -109,10 +144,36 @@ def test_multiloop_batch_twelve_points():
                 assert e64 < 1e-12, (idx, r, e64)
                 assert e32 < 1e-6, (idx, r, e32)
         del ref
-        del out, V
         torch.cuda.empty_cache()
-    print(f"batch: {flop / 1e15:.3f} PFLOP algorithmic in {seconds:.2f} s of mloop calls = "
-          f"{flop / seconds / 1e12:.2f} TFLOP/s", flush=True)
+        if n > 101:
+            # under capture every bubble runs in one transfer-frequency batch (the library
+            # rejects a multi-batch schedule there); at N >= 151 one batch of panels does not fit
+            print("   graph replay: not captured at this size (one batch of panels needs > 40 GB)", flush=True)
+            del out, V
+            torch.cuda.empty_cache()
+            continue
+        # the same step recorded into a HIP graph and replayed: equal to the eager result
+        g, gout = _capture(lambda: K.mloop_step([V], [P], [q], NLOOPS, precision=K.SPLIT_FP32, omega_batch=n)[0])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.replay()
+        torch.cuda.synchronize()
+        dg = time.perf_counter() - t0
+        seconds_graph += dg
+        for ell in range(NLOOPS):
+            for r in range(3):
+                for x in CL:
+                    assert torch.equal(getattr(gout[ell][r], x), getattr(out[ell][r], x)), (idx, ell, r, x)
+        print(f"   graph replay {dg * 1e3:.1f} ms (eager {dt * 1e3:.1f} ms)", flush=True)
+        del g, gout, out, V
+        torch.cuda.empty_cache()
+    for n, (f, t) in sorted(per_n.items()):
+        print(f"GEMM efficiency n={n}: {f / t / 1e12:.1f} TFLOP/s = {f / t / 1e12 / 157.3:.3f} of the FP32 MFMA peak "
+              f"(algorithmic)", flush=True)
+    print(f"batch: {flop_exec / 1e15:.3f} PFLOP executed ({flop_def / 1e15:.3f} PFLOP as 27 bubbles per point) in "
+          f"{seconds:.2f} s of eager mloop calls = {flop_exec / seconds / 1e12:.2f} TFLOP/s executed, "
+          f"{flop_def / seconds / 1e12:.2f} TFLOP/s per the equations; graph replays of the N <= 101 points "
+          f"{seconds_graph:.2f} s", flush=True)
 
 
 def sample_at(n, m, seed, iws):
