@@ -51,6 +51,7 @@ struct kqft_ctx {
   // extra cotangents of the stored left insertions (two orders each, per channel)
   DevBuf mlrec[2][3], mlbar[2][3], mlext[2][3], mlscr;
   DevBuf gemmP;  // split-path GEMM products of one batch, both spin combinations
+  DevBuf chi_proj;  // susceptibility: grid projection of Pi and the own-channel part
   // autotuned transfer-frequency batch per (n, nq, precision), used when opts.omega_batch = 0
   std::map<std::tuple<int, int, int>, int> tuned_nb;
   std::vector<hipEvent_t> events;
@@ -715,8 +716,13 @@ struct ChiBufs {
   const void* T[2];
   double2* pi;
   double2* partial;
+  double2* pt;   // grid projection of Pi, [nb][n + 1][16] (nullptr: own channel in the pair loop)
+  double2* own;  // [nb][2][16]
   int nb;
+  int f32;  // tables in FP32
 };
+// bytes per transfer frequency of the grid projection (Pt and the own part)
+static size_t chi_proj_bytes(int n) { return ((size_t)(n + 1) * 16 + 32) * sizeof(double2); }
 
 // chi_r of `gamma` into chi [2][n][16] in batches of b.nb transfer frequencies.  prof: the
 // context whose profiling flag brackets the launches (nullptr: none).
@@ -754,6 +760,11 @@ static void chi_run(kqft_ctx* prof, int r, const kqft_vertex& gamma, const DProp
     ca.pi = b.pi;
     ca.partial = b.partial;
     ca.out = (double2*)chi;
+    ca.f32 = b.f32;
+    if (b.pt) {
+      ca.pt = b.pt;
+      ca.own = b.own;
+    }
     {
       ProfScope ps(prof, 3, s);
       launch_chi(ca, s);
@@ -762,12 +773,13 @@ static void chi_run(kqft_ctx* prof, int r, const kqft_vertex& gamma, const DProp
 }
 
 static int chi_core(kqft_ctx* ctx, int r, const kqft_vertex& gamma, const DProp& P, const double* nodes,
-                    const kqft_quad& q_bubble, double* chi, hipStream_t s) {
+                    const kqft_quad& q_bubble, double* chi, hipStream_t s, bool f32 = false) {
   int rc;
   const int n = gamma.grid.n;
   ChiBufs b;
   memset(&b, 0, sizeof b);
   b.nodes = nodes;
+  b.f32 = f32;
   if ((rc = get_quad(ctx, q_bubble, &b.qv, &b.qw))) return rc;
   const int nq = q_bubble.n;
   const int nblk = chi_blocks(nq);
@@ -776,9 +788,14 @@ static int chi_core(kqft_ctx* ctx, int r, const kqft_vertex& gamma, const DProp&
   if ((rc = ensure(ctx->chi_part, (size_t)b.nb * nblk * 32 * 16))) return rc;
   b.pi = (double2*)ctx->pi[0].p;
   b.partial = (double2*)ctx->chi_part.p;
+  if (n <= kChiProjMaxN) {
+    if ((rc = ensure(ctx->chi_proj, (size_t)b.nb * chi_proj_bytes(n)))) return rc;
+    b.pt = (double2*)ctx->chi_proj.p;
+    b.own = b.pt + (size_t)b.nb * (n + 1) * 16;
+  }
   // the two other channels in channel r's Keldysh order with its spin combinations
   SideTables tabs, unused;
-  if ((rc = build_tables(ctx, r, gamma, gamma, false, tabs, unused, s))) return rc;
+  if ((rc = build_tables(ctx, r, gamma, gamma, f32, tabs, unused, s))) return rc;
   b.T[0] = tabs.T[0];
   b.T[1] = tabs.T[1];
   chi_run(ctx, r, gamma, P, nq, b, chi, s);
@@ -815,7 +832,8 @@ static int sde_core(kqft_ctx* ctx, const kqft_vertex* gamma, const kqft_propagat
     ProfScope ps(ctx, 3, s);
     launch_loop(la, s);
   }
-  if (chi && (rc = chi_core(ctx, KQFT_CH_A, *gamma, P, nodes, *q_bubble, chi, s))) return rc;
+  if (chi && (rc = chi_core(ctx, KQFT_CH_A, *gamma, P, nodes, *q_bubble, chi, s, opts->precision == KQFT_SPLIT_FP32)))
+    return rc;
   HIP_TRY(hipGetLastError());
   return KQFT_OK;
 }
@@ -1077,6 +1095,7 @@ int kqft_ctx_destroy(kqft_ctx* ctx) {
       for (auto& b : row) free_buf(b);
   free_buf(ctx->mlscr);
   free_buf(ctx->gemmP);
+  free_buf(ctx->chi_proj);
   if (ctx->sg) (void)hipStreamDestroy(ctx->sg);
   if (ctx->sm) (void)hipStreamDestroy(ctx->sm);
   delete ctx;
@@ -3413,7 +3432,8 @@ int kqft_chi_noalloc(int channel, const kqft_vertex* gamma, const kqft_propagato
     act[d] = table_active(gamma->ch[(r + 1 + d) % 3]);
     if (act[d]) fixed += up(tbytes);
   }
-  const size_t per_w = (size_t)nq * 256 + (size_t)nblk * 32 * sizeof(double2);
+  const bool proj = n <= kChiProjMaxN;
+  const size_t per_w = (size_t)nq * 256 + (size_t)nblk * 32 * sizeof(double2) + (proj ? chi_proj_bytes(n) : 0);
   const long nb = fixed + up(per_w) + 512 <= kScratchBytes ? (long)((kScratchBytes - fixed - 512) / per_w) : 0;
   if (nb < 1)
     return fail(KQFT_ENOMEM, "kqft_chi_noalloc: n = " + std::to_string(n) + ", nq = " + std::to_string(nq) +
@@ -3443,6 +3463,11 @@ int kqft_chi_noalloc(int channel, const kqft_vertex* gamma, const kqft_propagato
   b.pi = (double2*)p;
   p += up((size_t)b.nb * nq * 256);
   b.partial = (double2*)p;
+  p += up((size_t)b.nb * nblk * 32 * sizeof(double2));
+  if (proj) {
+    b.pt = (double2*)p;
+    b.own = b.pt + (size_t)b.nb * (n + 1) * 16;
+  }
   launch_grid_nodes(n, gamma->grid.map, gamma->grid.a, aux_of(gamma->grid.map, gamma->grid.L / gamma->grid.a), nodes,
                     s);
   launch_quad_nodes(nq, q->a, q->map == KQFT_QUAD_TAN_FINITE ? atan(q->L / q->a) : 0.5 * M_PI, qv, qw, s);

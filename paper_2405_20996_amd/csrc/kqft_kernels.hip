@@ -1396,7 +1396,7 @@ __global__ __launch_bounds__(256) void vloop_kernel(VLoopArgs a) {
 // q = l8 % 4 -- multiplies by Pi_l from the right through quad broadcasts and by Pi_k from
 // the left for its two rows.  Per-lane partial sums, reduced over the block in a fixed tree;
 // chi_finalize_kernel adds the per-block partials in fixed order (deterministic).
-__global__ __launch_bounds__(256) void chi_kernel(ChiArgs a) {
+template <class TT> __global__ __launch_bounds__(256) void chi_kernel(ChiArgs a) {
   const int b = blockIdx.y, iw = a.iw0 + b;
   const int l8 = threadIdx.x & 7, h = l8 >> 2, q4 = l8 & 3;
   // 32-bit indices: the host keeps nq * nq below 2^31
@@ -1464,7 +1464,7 @@ __global__ __launch_bounds__(256) void chi_kernel(ChiArgs a) {
     for (int d = 0; d < 2; ++d)
       if (a.T[d]) {
         const int s0 = 2 + 3 * d;
-        table_taps((const double2*)a.T[d], n, __shfl(ic, s0, 8), __shfl(tc, s0, 8), __shfl(ic, s0 + 1, 8),
+        table_taps((const TT*)a.T[d], n, __shfl(ic, s0, 8), __shfl(tc, s0, 8), __shfl(ic, s0 + 1, 8),
                    __shfl(tc, s0 + 1, 8), __shfl(ic, s0 + 2, 8), __shfl(tc, s0 + 2, 8), l8, acc);
       }
     apply_pi(pis + (size_t)lq * 16, q4, acc);  // (Gamma . Pi_l)[row, m]
@@ -1501,7 +1501,7 @@ __global__ __launch_bounds__(256) void chi_kernel(ChiArgs a) {
   }
 }
 
-// out[c][w][f] = sum of the block partials (fixed order) + sum_k Pi_k[f]
+// out[c][w][f] = sum of the block partials (fixed order) + sum_k Pi_k[f] (+ the own part)
 __global__ void chi_finalize_kernel(ChiArgs a, int nblk) {
   const int b = blockIdx.x;  // transfer frequency within the batch
   const int e = threadIdx.x; // 0..31 = c*16 + f
@@ -1511,7 +1511,124 @@ __global__ void chi_finalize_kernel(ChiArgs a, int nblk) {
   const int c = e >> 4, f = e & 15;
   const double2* pis = a.pi + (size_t)b * a.nq * 16;
   for (int k = 0; k < a.nq; ++k) s = cadd(s, pis[(size_t)k * 16 + f]);
+  if (a.own) s = cadd(s, a.own[((size_t)b * 2 + c) * 16 + f]);
   a.out[((size_t)c * a.g.n + a.iw0 + b) * 16 + f] = s;
+}
+
+// The own channel r enters chi at (w; v''_k, v''_l) through its classes, each linear in the
+// loop frequencies on the grid: K(v''_k) = sum_i c_ki K_i with the interpolation weights c_ki
+// (two per k, zero beyond the grid).  So its part of sum_{k,l} Pi_k Gamma Pi_l is
+//   sum_{i,j} Pt_i K3_ij Pt_j + (sum_i Pt_i K2_i) Pibar + Pibar (sum_j K2'_j Pt_j) + Pibar (K1 + R) Pibar
+// with Pt_i = sum_k c_ki Pi_k and Pibar = sum_k Pi_k -- the same discrete sum reordered, O(n^2)
+// instead of O(nq^2) per transfer frequency.
+// chi_proj_kernel: block (node i or n, batch entry b), 64 threads = 16 entries x 4 parts of k.
+__global__ __launch_bounds__(64) void chi_proj_kernel(ChiArgs a) {
+  __shared__ double2 red[4][16];
+  const int i = blockIdx.x, b = blockIdx.y, n = a.g.n;
+  const int f = threadIdx.x & 15, part = threadIdx.x >> 4;
+  const double2* pis = a.pi + (size_t)b * a.nq * 16;
+  int klo = 0, khi = a.nq - 1;
+  if (i < n) {  // loop nodes between the neighbouring grid nodes (sorted), widened by one
+    const double lo = i > 0 ? a.nodes[i - 1] : -1e300, hi = i + 1 < n ? a.nodes[i + 1] : 1e300;
+    int x = 0, y = a.nq;
+    while (x < y) {  // first k with v''_k >= lo
+      const int m = (x + y) >> 1;
+      if (a.qv[m] < lo) x = m + 1; else y = m;
+    }
+    klo = max(x - 1, 0);
+    x = 0;
+    y = a.nq;
+    while (x < y) {  // first k with v''_k > hi
+      const int m = (x + y) >> 1;
+      if (a.qv[m] <= hi) x = m + 1; else y = m;
+    }
+    khi = min(x, a.nq - 1);
+  }
+  double2 acc = czero();
+  for (int k = klo + part; k <= khi; k += 4) {
+    double w = 1.0;
+    if (i < n) {
+      int ic;
+      double tc;
+      if (!dgrid_locate(a.g, a.qv[k], ic, tc)) continue;
+      w = ic == i ? 1.0 - tc : (ic + 1 == i ? tc : 0.0);
+      if (w == 0.0) continue;
+    }
+    acc = cfma(w, pis[(size_t)k * 16 + f], acc);
+  }
+  red[part][f] = acc;
+  __syncthreads();
+  if (part == 0)
+    a.pt[((size_t)b * (n + 1) + i) * 16 + f] = cadd(cadd(red[0][f], red[1][f]), cadd(red[2][f], red[3][f]));
+}
+
+// own-channel class entry f of combination c at (iw, i, j): coef (mix0 X + mix1 Y)
+__device__ inline double2 own_combo(const double2* K, size_t sstride, size_t off, double coef, double m0, double m1) {
+  const double2 X = K[off], Y = K[sstride + off];
+  return make_double2(coef * (m0 * X.x + m1 * Y.x), coef * (m0 * X.y + m1 * Y.y));
+}
+
+// chi_own_kernel: block (combination c, batch entry b), 256 threads; dynamic LDS of
+// (2n + 1) x 16 complex: Pt (n + 1 rows, the last Pibar) and W_j = sum_i Pt_i K3_ij + Pibar K2'_j.
+__global__ __launch_bounds__(256) void chi_own_kernel(ChiArgs a) {
+  extern __shared__ double2 lds[];
+  const int c = blockIdx.x, b = blockIdx.y, n = a.g.n, iw = a.iw0 + b;
+  double2* Pt = lds;                   // [n + 1][16]
+  double2* W = lds + (size_t)(n + 1) * 16;  // [n][16]
+  __shared__ double2 V[16];            // sum_i Pt_i K2_i + Pibar (K1 + R)
+  for (int e = threadIdx.x; e < (n + 1) * 16; e += blockDim.x) Pt[e] = a.pt[(size_t)b * (n + 1) * 16 + e];
+  __syncthreads();
+  const double m0 = a.mix[2 * c], m1 = a.mix[2 * c + 1];
+  const size_t nn = n, n2 = nn * nn, n3 = n2 * nn;
+  const double2* Pb = Pt + (size_t)n * 16;
+  for (int e = threadIdx.x; e < n * 16; e += blockDim.x) {
+    const int j = e >> 4, p = (e >> 2) & 3, q = e & 3;
+    double2 s = czero();
+    if (a.coef != 0.0) {
+      if (a.K[3])
+        for (int i = 0; i < n; ++i)
+#pragma unroll
+          for (int row = 0; row < 4; ++row)
+            s = cadd(s, cmul(Pt[i * 16 + 4 * p + row],
+                             own_combo(a.K[3], n3 * 16, (((size_t)iw * nn + i) * nn + j) * 16 + 4 * row + q, a.coef, m0,
+                                       m1)));
+      if (a.K[2])
+#pragma unroll
+        for (int row = 0; row < 4; ++row)
+          s = cadd(s, cmul(Pb[4 * p + row],
+                           own_combo(a.K[2], n2 * 16, ((size_t)iw * nn + j) * 16 + 4 * row + q, a.coef, m0, m1)));
+    }
+    W[e] = s;
+  }
+  if (threadIdx.x < 16) {
+    const int p = threadIdx.x >> 2, q = threadIdx.x & 3;
+    double2 s = czero();
+    if (a.coef != 0.0 && a.K[1])
+      for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int row = 0; row < 4; ++row)
+          s = cadd(s, cmul(Pt[i * 16 + 4 * p + row],
+                           own_combo(a.K[1], n2 * 16, ((size_t)iw * nn + i) * 16 + 4 * row + q, a.coef, m0, m1)));
+#pragma unroll
+    for (int row = 0; row < 4; ++row) {
+      const int f = 4 * row + q;
+      double2 k1 = (a.coef != 0.0 && a.K[0]) ? own_combo(a.K[0], nn * 16, (size_t)iw * 16 + f, a.coef, m0, m1) : czero();
+      if (bare_odd(f)) k1.x += (m1 - m0) * 0.5 * a.r0;  // the bare vertex R in combination c
+      s = cadd(s, cmul(Pb[4 * p + row], k1));
+    }
+    V[threadIdx.x] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    const int p = threadIdx.x >> 2, m = threadIdx.x & 3;
+    double2 s = czero();
+    for (int j = 0; j < n; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s = cadd(s, cmul(W[j * 16 + 4 * p + q], Pt[j * 16 + 4 * q + m]));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s = cadd(s, cmul(V[4 * p + q], Pb[4 * q + m]));
+    a.own[((size_t)b * 2 + c) * 16 + threadIdx.x] = s;
+  }
 }
 
 // ======================================================================== parquet helpers
@@ -2272,7 +2389,20 @@ void launch_vloop(const VLoopArgs& a, hipStream_t s) {
 }
 void launch_chi(const ChiArgs& a, hipStream_t s) {
   const int nblk = chi_blocks(a.nq);
-  hipLaunchKernelGGL(chi_kernel, dim3(nblk, a.nb), dim3(256), 0, s, a);
+  ChiArgs pl = a;  // the pair loop: without the own channel and the bare vertex when projected
+  if (a.own) {
+    const size_t lds = (size_t)(2 * a.g.n + 1) * 16 * sizeof(double2);
+    (void)hipFuncSetAttribute((const void*)chi_own_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(chi_proj_kernel, dim3(a.g.n + 1, a.nb), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(chi_own_kernel, dim3(2, a.nb), dim3(256), lds, s, a);
+    pl.coef = 0.0;
+    pl.r0 = 0.0;
+    for (int u = 0; u < 4; ++u) pl.K[u] = nullptr;
+  }
+  if (a.f32)
+    hipLaunchKernelGGL(chi_kernel<float2>, dim3(nblk, a.nb), dim3(256), 0, s, pl);
+  else
+    hipLaunchKernelGGL(chi_kernel<double2>, dim3(nblk, a.nb), dim3(256), 0, s, pl);
   hipLaunchKernelGGL(chi_finalize_kernel, dim3(a.nb), dim3(64), 0, s, a, nblk);
 }
 void launch_loop_adjoint(const LoopAdjArgs& a, hipStream_t s) {

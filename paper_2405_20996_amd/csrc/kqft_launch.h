@@ -108,7 +108,16 @@ struct ChiArgs {
   const double2* pi;  // [nb][nq][16], channel r, Pi = G G, weights folded
   double2* partial;   // [nb][nblk][32]
   double2* out;       // [2][n][16]
+  int f32;            // tables in FP32 (float2 records) instead of FP64
+  // own channel and bare vertex through the grid projection (chi_proj / chi_own kernels):
+  // pt[b][i][16] = sum_k c_ki Pi_k (i < n; c_ki the interpolation weight of node i at v''_k),
+  // pt[b][n][16] = sum_k Pi_k; own[b][c][16] their contribution to chi (nullptr: own channel
+  // and bare vertex evaluated in the pair loop instead)
+  double2* pt;
+  double2* own;
 };
+// largest grid whose projection fits the own-channel kernel's LDS
+constexpr int kChiProjMaxN = 300;
 
 
 // ------------------------------------------------------------------ adjoint
@@ -200,7 +209,7 @@ void launch_gemm(const GemmArgs& g, int precision, hipStream_t s);
 void launch_unmix(const GemmArgs& g, hipStream_t s);
 void launch_loop(const LoopArgs& a, hipStream_t s);
 void launch_vloop(const VLoopArgs& a, hipStream_t s);
-void launch_chi(const ChiArgs& a, hipStream_t s);
+void launch_chi(const ChiArgs& a, hipStream_t s);  // projection + own part (when a.own) + pair loop + finalize
 int chi_blocks(int nq);
 void launch_grid_nodes(int n, int map, double a, double theta, double* v, hipStream_t s);
 void launch_quad_nodes(int nq, double a, double th, double* qv, double* qw, hipStream_t s);
