@@ -517,13 +517,18 @@ static int bubble_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_ve
       g.P[0] = (double2*)ctx->gemmP.p;
       g.P[1] = (double2*)((char*)ctx->gemmP.p + prod);
     }
-    {
+    if (!main_rows) {  // only the border row block: a streaming row product, no GEMM tile
       ProfScope ps(ctx, 2, ctx->sm);
-      launch_gemm(g, o.precision, ctx->sm);
-    }
-    if (f32) {
-      ProfScope ps(ctx, 3, ctx->sm);
-      launch_unmix(g, ctx->sm);
+      launch_rowpanel(g, o.precision, ctx->sm);
+    } else {
+      {
+        ProfScope ps(ctx, 2, ctx->sm);
+        launch_gemm(g, o.precision, ctx->sm);
+      }
+      if (f32) {
+        ProfScope ps(ctx, 3, ctx->sm);
+        launch_unmix(g, ctx->sm);
+      }
     }
     HIP_TRY(hipEventRecord(mdone, ctx->sm));
     gemm_done.push_back(mdone);

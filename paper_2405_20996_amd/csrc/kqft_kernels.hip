@@ -992,6 +992,71 @@ __global__ __launch_bounds__(256) void unmix_kernel(GemmArgs g) {
   }
 }
 
+// ======================================================================== border-row product
+// A bubble whose outputs are only the classes of the border row block (K1 and K2': the bare
+// vertex or another constant-in-v vertex on the left, as in the Schwinger-Dyson bubble
+// B_a(Gamma_0, Gamma)) needs the four rows 4n .. 4n+3 of C = A B only.  One wavefront per
+// output column and transfer frequency streams the B^T panel row once (HBM-bound: the panel is
+// read exactly once) against the four A rows (L2-resident, shared by every column), both
+// spin combinations, products and sums in FP64 (FP32 panels widened), a fixed-order wavefront
+// reduction, and stores through the bubble epilogue -- instead of a 64-row GEMM tile of which
+// 60 rows are discarded.
+template <class T> __global__ __launch_bounds__(256) void rowpanel_kernel(GemmArgs g) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = g.tn0 * 64 + blockIdx.x * 4 + wave;
+  const int b = blockIdx.y;
+  const int c1 = min((g.tn0 + g.tns) * 64, g.M);
+  if (col >= c1) return;  // whole wavefronts
+  const size_t rowA = 4 * (size_t)g.n;
+  double2 acc[2][4];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int h = 0; h < 4; ++h) acc[c][h] = czero();
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const T* A = (const T*)g.A[c] + (size_t)b * g.strideA + rowA * g.Kp;
+    const T* B = (const T*)g.B[c] + (size_t)b * g.strideB + (size_t)col * g.Kp;
+    for (int k = lane; k < g.Kp; k += 64) {
+      const T bv = B[k];
+      const double2 y = make_double2((double)bv.x, (double)bv.y);
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const T av = A[(size_t)h * g.Kp + k];
+        acc[c][h] = cadd(acc[c][h], cmul(make_double2((double)av.x, (double)av.y), y));
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        acc[c][h].x += __shfl_xor(acc[c][h].x, o);
+        acc[c][h].y += __shfl_xor(acc[c][h].y, o);
+      }
+  if (lane < 4) {
+    double2 p0 = acc[0][0], p1 = acc[1][0];
+#pragma unroll
+    for (int h = 1; h < 4; ++h)
+      if (lane == h) {
+        p0 = acc[0][h];
+        p1 = acc[1][h];
+      }
+    epilogue_store(g, b, (int)rowA + lane, col, p0, p1);
+  }
+}
+
+void launch_rowpanel(const GemmArgs& g, int precision, hipStream_t s) {
+  const int cols = min((g.tn0 + g.tns) * 64, g.M) - g.tn0 * 64;
+  dim3 grid((unsigned)((cols + 3) / 4), (unsigned)g.nb);
+  if (precision == 0)
+    hipLaunchKernelGGL(rowpanel_kernel<double2>, grid, dim3(256), 0, s, g);
+  else
+    hipLaunchKernelGGL(rowpanel_kernel<float2>, grid, dim3(256), 0, s, g);
+}
+
 // ======================================================================== general complex GEMM
 // C[b] = op(A[b]) . B[b] in FP64 complex on v_mfma_f64_16x16x4f64, row-major operands:
 // op(A)[m][k] = A[m][k] (TA = false, lda = row length of A) or A[k][m] (TA = true), B[k][n],

@@ -207,6 +207,8 @@ void launch_gather(const GatherArgs& a, bool left, bool f32, hipStream_t s);
 void launch_gemm(const GemmArgs& g, int precision, hipStream_t s);
 // split path: the two combinations' products into the classes (after launch_gemm, same stream)
 void launch_unmix(const GemmArgs& g, hipStream_t s);
+// only the border row block (rows 4n .. 4n+3) of C = A B, both precisions, through the epilogue
+void launch_rowpanel(const GemmArgs& g, int precision, hipStream_t s);
 void launch_loop(const LoopArgs& a, hipStream_t s);
 void launch_vloop(const VLoopArgs& a, hipStream_t s);
 void launch_chi(const ChiArgs& a, hipStream_t s);  // projection + own part (when a.own) + pair loop + finalize
