@@ -756,6 +756,7 @@ __global__ __launch_bounds__(256, 2) void zgemm_f64_kernel(GemmArgs g) {
   const int arow = min(tm * BM + lrow, Mtot - 1);
   const int brow = min(tn * BM + lrow, Mtot - 1);
   const int nk = Kp / BK;
+  const bool live = tm * BM + wm * 32 < Mtot && tn * BM + wn * 32 < Mtot;  // as in the split kernel
   d4 acc[2][2][2][2];  // [combo][re/im][mb][nb]
 #pragma unroll
   for (int c = 0; c < 2; ++c)
@@ -801,34 +802,36 @@ __global__ __launch_bounds__(256, 2) void zgemm_f64_kernel(GemmArgs g) {
           rb[e] = Bp[(size_t)(kb + 1) * BK + e];
         }
       }
+      if (live) {
 #pragma unroll
-      for (int kk = 0; kk < BK / 4; ++kk) {
-        const int kr = kk * 4 + (lane >> 4);
-        double ar[2], ai[2], br[2], bi[2];
+        for (int kk = 0; kk < BK / 4; ++kk) {
+          const int kr = kk * 4 + (lane >> 4);
+          double ar[2], ai[2], br[2], bi[2];
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb) {
-          ar[mb] = sA[buf][0][kr][wm * 32 + mb * 16 + (lane & 15)];
-          ai[mb] = sA[buf][1][kr][wm * 32 + mb * 16 + (lane & 15)];
-        }
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-          br[nb] = sB[buf][0][kr][wn * 32 + nb * 16 + (lane & 15)];
-          bi[nb] = sB[buf][1][kr][wn * 32 + nb * 16 + (lane & 15)];
-        }
-        double sa[2], sb[2];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          sa[u] = ar[u] + ai[u];
-          sb[u] = br[u] + bi[u];
-        }
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
+          for (int mb = 0; mb < 2; ++mb) {
+            ar[mb] = sA[buf][0][kr][wm * 32 + mb * 16 + (lane & 15)];
+            ai[mb] = sA[buf][1][kr][wm * 32 + mb * 16 + (lane & 15)];
+          }
 #pragma unroll
           for (int nb = 0; nb < 2; ++nb) {
-            p[0][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[mb], br[nb], p[0][mb][nb], 0, 0, 0);
-            p[1][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[mb], bi[nb], p[1][mb][nb], 0, 0, 0);
-            p[2][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[mb], sb[nb], p[2][mb][nb], 0, 0, 0);
+            br[nb] = sB[buf][0][kr][wn * 32 + nb * 16 + (lane & 15)];
+            bi[nb] = sB[buf][1][kr][wn * 32 + nb * 16 + (lane & 15)];
           }
+          double sa[2], sb[2];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            sa[u] = ar[u] + ai[u];
+            sb[u] = br[u] + bi[u];
+          }
+#pragma unroll
+          for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+              p[0][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[mb], br[nb], p[0][mb][nb], 0, 0, 0);
+              p[1][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[mb], bi[nb], p[1][mb][nb], 0, 0, 0);
+              p[2][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[mb], sb[nb], p[2][mb][nb], 0, 0, 0);
+            }
+        }
       }
       if (kb + 1 < nk) {
 #pragma unroll
@@ -867,9 +870,10 @@ __global__ __launch_bounds__(256, 2) void zgemm_f64_kernel(GemmArgs g) {
 // FP32 operands on v_mfma_f32_32x32x2f32, one spin combination per workgroup (grid = both
 // combinations x tiles), 64x64 complex tile, four waves of 32x32 complex (lane l: A row l%32 /
 // k l/32; D rows 8(v/4) + 4(l/32) + v%4, col l%32).  K blocks of 32 complex staged through a
-// single LDS buffer -- 33 KB, so three workgroups share a CU and one's MFMAs cover another's
-// staging and barriers -- with the next block's global loads in registers and each step's LDS
-// operands read one step ahead.  Complex products by three real products (Gauss): P1 = ar br,
+// single LDS buffer of (re, im) pairs -- 33 KB, so three workgroups share a CU and one's MFMAs
+// cover another's staging and barriers -- with the next block's global loads in registers and
+// each step's LDS operands read one step ahead; waves raise their issue priority while they
+// run MFMAs.  A wave whose 32-row or 32-column block lies past the ragged edge skips its MFMAs.  Complex products by three real products (Gauss): P1 = ar br,
 // P2 = ai bi, P3 = (ar + ai)(br + bi), Re = P1 - P2, Im = P3 - P1 - P2 -- 6 instead of 8 real
 // flops per complex multiply-add.  FP32 partial sums over four K blocks (128 complex terms),
 // promoted to FP64.  The combination's product goes to the workspace P[c][w][row][col];
@@ -881,8 +885,8 @@ constexpr int PROMO = 4;                      // K blocks per FP64 promotion
 
 __global__ __launch_bounds__(256, 3) void zgemm_f32_kernel(GemmArgs g) {
   using namespace f32g;
-  __shared__ float sA[2][BK][LDP];
-  __shared__ float sB[2][BK][LDP];
+  __shared__ float2 sA[BK][LDP];  // (re, im) pairs: one 8-byte LDS access per operand and step
+  __shared__ float2 sB[BK][LDP];
   const int tiles = g.tms * g.tns;
   const int total = 2 * g.nb * tiles;
   const int per_xcd = (total + kXcds - 1) / kXcds;
@@ -901,6 +905,9 @@ __global__ __launch_bounds__(256, 3) void zgemm_f32_kernel(GemmArgs g) {
   const int brow = min(tn * BM + lrow, Mtot - 1);
   const int nk = Kp / BK;
   const int am = wm * 32 + (lane & 31), bn = wn * 32 + (lane & 31);
+  // a wave whose 32-row or 32-column block lies wholly past the ragged edge of the product
+  // only helps stage the operands (its MFMAs would produce discarded entries)
+  const bool live = tm * BM + wm * 32 < Mtot && tn * BM + wn * 32 < Mtot;
   double acc[2][16];  // [re/im][v]
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -917,10 +924,8 @@ __global__ __launch_bounds__(256, 3) void zgemm_f32_kernel(GemmArgs g) {
   auto stash = [&]() {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      sA[0][lk + e][lrow] = ra[e].x;
-      sA[1][lk + e][lrow] = ra[e].y;
-      sB[0][lk + e][lrow] = rb[e].x;
-      sB[1][lk + e][lrow] = rb[e].y;
+      sA[lk + e][lrow] = ra[e];
+      sB[lk + e][lrow] = rb[e];
     }
   };
   stash();
@@ -936,24 +941,32 @@ __global__ __launch_bounds__(256, 3) void zgemm_f32_kernel(GemmArgs g) {
         rb[e] = Bp[(size_t)(kb + 1) * BK + e];
       }
     }
-    float ar[2], ai[2], br[2], bi[2];
-    ar[0] = sA[0][lane >> 5][am];
-    ai[0] = sA[1][lane >> 5][am];
-    br[0] = sB[0][lane >> 5][bn];
-    bi[0] = sB[1][lane >> 5][bn];
-#pragma unroll
-    for (int kk = 0; kk < BK / 2; ++kk) {
-      const int cur = kk & 1, nx = cur ^ 1;
-      if (kk + 1 < BK / 2) {
-        const int kr = (kk + 1) * 2 + (lane >> 5);
-        ar[nx] = sA[0][kr][am];
-        ai[nx] = sA[1][kr][am];
-        br[nx] = sB[0][kr][bn];
-        bi[nx] = sB[1][kr][bn];
+    if (live) {
+      __builtin_amdgcn_s_setprio(1);  // waves in their MFMA phase issue ahead of staging waves
+      float ar[2], ai[2], br[2], bi[2];
+      {
+        const float2 x = sA[lane >> 5][am], y = sB[lane >> 5][bn];
+        ar[0] = x.x;
+        ai[0] = x.y;
+        br[0] = y.x;
+        bi[0] = y.y;
       }
-      p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[cur], br[cur], p1, 0, 0, 0);
-      p2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[cur], bi[cur], p2, 0, 0, 0);
-      p3 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[cur] + ai[cur], br[cur] + bi[cur], p3, 0, 0, 0);
+#pragma unroll
+      for (int kk = 0; kk < BK / 2; ++kk) {
+        const int cur = kk & 1, nx = cur ^ 1;
+        if (kk + 1 < BK / 2) {
+          const int kr = (kk + 1) * 2 + (lane >> 5);
+          const float2 x = sA[kr][am], y = sB[kr][bn];
+          ar[nx] = x.x;
+          ai[nx] = x.y;
+          br[nx] = y.x;
+          bi[nx] = y.y;
+        }
+        p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[cur], br[cur], p1, 0, 0, 0);
+        p2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[cur], bi[cur], p2, 0, 0, 0);
+        p3 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[cur] + ai[cur], br[cur] + bi[cur], p3, 0, 0, 0);
+      }
+      __builtin_amdgcn_s_setprio(0);
     }
     __syncthreads();  // every wave is done with this block
     if (kb + 1 < nk) stash();
@@ -1922,295 +1935,189 @@ __global__ __launch_bounds__(256) void apply_pi_kernel(ApplyPiArgs a) {
   }
 }
 
-// Transpose of add_channel: coef * weight * (dX, dY) into the class cotangents of one
-// channel, through the fused cotangent table where all three arguments are on the grid.
-__device__ inline void scatter_channel(double2* const dK[4], double2* dKf, double coef, const DGrid& g, double w2,
-                                       double v2, double vp2, const int f2[4], const double2 dX[4],
-                                       const double2 dY[4]) {
-  int iw, iv = 0, ivp = 0;
-  double tw, tv = 0.0, tvp = 0.0;
-  if (!dgrid_locate(g, w2, iw, tw)) return;
-  const bool inv = dgrid_locate(g, v2, iv, tv);
-  const bool invp = dgrid_locate(g, vp2, ivp, tvp);
-  const int n = g.n;
-  for (int s = 0; s < 2; ++s) {
-    const double2* d = s ? dY : dX;
-    for (int cw = 0; cw < 2; ++cw) {
-      const double ww = coef * (cw ? tw : 1.0 - tw);
-      const size_t sw = (size_t)s * n + iw + cw;
-      if (inv && invp && dKf) {
-        for (int c = 0; c < 2; ++c)
-          for (int c2 = 0; c2 < 2; ++c2) {
-            const double wt = ww * (c ? tv : 1.0 - tv) * (c2 ? tvp : 1.0 - tvp);
-            double2* p = dKf + ((sw * n + iv + c) * n + ivp + c2) * 16;
-            for (int e = 0; e < 4; ++e) atomic_c(p + f2[e], cscale(wt, d[e]));
-          }
-        continue;
-      }
-      if (dK[0]) {
-        double2* p = dK[0] + sw * 16;
-        for (int e = 0; e < 4; ++e) atomic_c(p + f2[e], cscale(ww, d[e]));
-      }
-      for (int c = 0; c < 2; ++c) {
-        if (inv && dK[1]) {
-          double2* p = dK[1] + (sw * n + iv + c) * 16;
-          const double wt = ww * (c ? tv : 1.0 - tv);
-          for (int e = 0; e < 4; ++e) atomic_c(p + f2[e], cscale(wt, d[e]));
-        }
-        if (invp && dK[2]) {
-          double2* p = dK[2] + (sw * n + ivp + c) * 16;
-          const double wt = ww * (c ? tvp : 1.0 - tvp);
-          for (int e = 0; e < 4; ++e) atomic_c(p + f2[e], cscale(wt, d[e]));
-        }
-        if (inv && invp && dK[3])
-          for (int c2 = 0; c2 < 2; ++c2) {
-            double2* p = dK[3] + ((sw * n + iv + c) * n + ivp + c2) * 16;
-            const double wt = ww * (c ? tv : 1.0 - tv) * (c2 ? tvp : 1.0 - tvp);
-            for (int e = 0; e < 4; ++e) atomic_c(p + f2[e], cscale(wt, d[e]));
-          }
-      }
+// Transpose of the gathers, accumulated along runs of loop nodes.  One wavefront per (row
+// block i of the left panel or column block j of the right panel, transfer frequency, chunk of
+// consecutive loop nodes); lane = (other channel h, spin s, Keldysh index rc of the block's
+// row or column, entry e) = 2 x 2 x 4 x 4.  Each lane carries one cotangent stream d_k (the
+// conj(dA) panel times conj(Pi_k) on the left, conj(dB) on the right, recombined into spin s)
+// and walks the chunk's nodes in order.  Consecutive nodes share the interpolation cell of the
+// other channel a few at a time and the own-channel cell about ten at a time, so the weighted
+// values are summed in registers per cell corner and reach memory (FP64 atomics) only when the
+// cell changes and at the end of the chunk; arguments off the grid (the partial classes) go
+// to memory at once.  The own channel's class that does not depend on the loop node (K2 / K2'
+// of the main blocks, K1 of the border) and the bare vertex's cotangent are summed over the
+// chunk.
+
+struct Corner8 {  // register accumulators of the current cell of one lane's target table
+  int iw = -1, iv = 0, ivp = 0;
+  double2 c[8];
+};
+
+// cell (iw, iv, ivp) of a table of n^3 records of 16 entries per spin; x = corner 4cw + 2cv + cp
+__device__ inline void flush8(double2* T, int n, int s, int f, const Corner8& q) {
+  if (q.iw < 0) return;
+#pragma unroll
+  for (int x = 0; x < 8; ++x) {
+    const int cw = x >> 2, cv = (x >> 1) & 1, cp = x & 1;
+    const size_t rec = (((size_t)s * n + q.iw + cw) * n + q.iv + cv) * n + q.ivp + cp;
+    atomic_c(T + rec * 16 + f, q.c[x]);
+  }
+}
+
+// partial classes of another channel (an argument off the grid, or no fused table): the
+// transpose of the table taps into K1, K2, K2', K3 at once, as in the forward tables
+__device__ inline void scatter_partial(double2* const dK[4], int n, int s, int f, int iw, double tw, bool inv,
+                                       int iv, double tv, bool invp, int ivp, double tvp, double2 d) {
+#pragma unroll
+  for (int cw = 0; cw < 2; ++cw) {
+    const double ww = cw ? tw : 1.0 - tw;
+    const size_t sw = (size_t)s * n + iw + cw;
+    if (dK[0]) atomic_c(dK[0] + sw * 16 + f, cscale(ww, d));
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (inv && dK[1]) atomic_c(dK[1] + (sw * n + iv + c) * 16 + f, cscale(ww * (c ? tv : 1.0 - tv), d));
+      if (invp && dK[2]) atomic_c(dK[2] + (sw * n + ivp + c) * 16 + f, cscale(ww * (c ? tvp : 1.0 - tvp), d));
+      if (inv && invp && dK[3])
+#pragma unroll
+        for (int c2 = 0; c2 < 2; ++c2)
+          atomic_c(dK[3] + ((sw * n + iv + c) * n + ivp + c2) * 16 + f,
+                   cscale(ww * (c ? tv : 1.0 - tv) * (c2 ? tvp : 1.0 - tvp), d));
     }
   }
 }
 
-__device__ inline void scatter_others(const AdjScatterArgs& a, double w, double v, double vp, int mode, int rc,
-                                      const double2 dX[4], const double2 dY[4]) {
-  double L[4];
-  legs_of(a.r, w, v, vp, L);
-  for (int d = 1; d < 3; ++d) {
-    const int r2 = (a.r + d) % 3;
-    if (a.V.ch[r2].coef == 0.0) continue;
-    double w2, v2, vp2;
-    params_of(r2, L, w2, v2, vp2);
-    int f2[4];
-    for (int e = 0; e < 4; ++e) f2[e] = c_perm[a.r][r2][mode == 0 ? 4 * rc + e : 4 * e + rc];
-    scatter_channel(a.dK[r2], a.dKf[r2], a.V.ch[r2].coef, a.V.g, w2, v2, vp2, f2, dX, dY);
-  }
-}
-
-// Sum over the 64 slots (lane bits 2..5 and the four waves) of per-thread partials that
-// share the lane's row (or column) index; returns the sums in the threads 0..3.
-__device__ inline void reduce_slots(double2 x[8], double& r, double2 (*red)[4][8], double* redr) {
-#pragma unroll
-  for (int q = 0; q < 8; ++q)
-#pragma unroll
-    for (int o = 4; o < 64; o <<= 1) {
-      x[q].x += __shfl_xor(x[q].x, o);
-      x[q].y += __shfl_xor(x[q].y, o);
-    }
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) r += __shfl_xor(r, o);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane < 4)
-#pragma unroll
-    for (int q = 0; q < 8; ++q) red[wave][lane][q] = x[q];
-  if (lane == 0) redr[wave] = r;
-  __syncthreads();
-  if (threadIdx.x < 4) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      x[q] = czero();
-      for (int wv = 0; wv < 4; ++wv) x[q] = cadd(x[q], red[wv][threadIdx.x][q]);
-    }
-    r = redr[0] + redr[1] + redr[2] + redr[3];
-  }
-}
-
-// Left side: block (i, batch), threads = 64 quadrature slots x 4 pair rows.
-__global__ __launch_bounds__(256) void adj_left_kernel(AdjScatterArgs a) {
-  __shared__ double2 red[4][4][8];
-  __shared__ double redr[4];
+template <bool LEFT>
+__global__ __launch_bounds__(256) void adj_run_kernel(AdjScatterArgs a, int chunk) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int e = lane & 3, rc = (lane >> 2) & 3, s = (lane >> 4) & 1, h = lane >> 5;
   const int i = blockIdx.x, b = blockIdx.y;
-  const int row = threadIdx.x & 3, slot = threadIdx.x >> 2;
-  const int n = a.V.g.n, iw = a.iw0 + b;
-  const size_t M = 4 * (size_t)(n + 1);
+  const int k0 = (blockIdx.z * 4 + wv) * chunk;
+  if (k0 >= a.nq) return;  // a whole wavefront; the kernel has no barriers
+  const int k1 = min(a.nq, k0 + chunk);
+  const int n = a.V.g.n, iw = a.iw0 + b, r = a.r;
+  const size_t M = 4 * (size_t)(n + 1), nn = n;
   const double w = a.nodes[iw];
-  const DChan& own = a.V.ch[a.r];
-  const double co = own.coef;
-  double2* const* dKo = a.dK[a.r];
-  double2 acc[8];  // own K2 (i < n) or own K1 (i = n) cotangent partials, X then Y
+  const bool mainb = i < n;
+  // entry of the lane in the own channel's Keldysh order (row rc / column rc of the block)
+  const int fo = LEFT ? 4 * rc + e : 4 * e + rc;
+  const double co = a.V.ch[r].coef;
+  double2* const* dKo = a.dK[r];
+  // own class along the loop node: K3 (main) or K2' (left border) / K2 (right border)
+  double2* tapT = nullptr;
+  size_t tapBase = 0, tapStep = 16;
+  // own class constant along the loop node: K2 / K2' (main) or K1 (border)
+  double2* cT = nullptr;
+  size_t cOff = 0;
+  if (co != 0.0 && h == 0) {
+    if (mainb) {
+      tapT = dKo[3];
+      tapBase = LEFT ? ((((size_t)s * nn + iw) * nn + i) * nn) * 16 : ((((size_t)s * nn + iw) * nn) * nn + i) * 16;
+      tapStep = LEFT ? 16 : nn * 16;
+      cT = LEFT ? dKo[1] : dKo[2];
+      cOff = (((size_t)s * nn + iw) * nn + i) * 16;
+    } else {
+      tapT = LEFT ? dKo[2] : dKo[1];
+      tapBase = (((size_t)s * nn + iw) * nn) * 16;
+      tapStep = 16;
+      cT = dKo[0];
+      cOff = ((size_t)s * nn + iw) * 16;
+    }
+  }
+  int tj = -1;  // current own cell (node index along v'')
+  double2 t0 = czero(), t1 = czero(), cacc = czero();
+  double racc = 0.0;
+  const bool bare = !mainb && bare_odd(fo) && h == 0;
+  // other channel r + 1 + h (main blocks only)
+  const int r2 = (r + 1 + h) % 3;
+  const double co2 = a.V.ch[r2].coef;
+  const bool oth = mainb && co2 != 0.0;
+  const int f2 = c_perm[r][r2][fo];
+  double2* const dKf2 = a.dKf[r2];
+  Corner8 q;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = czero();
-  double accr = 0.0;
-  for (int k = slot; k < a.nq; k += 64) {
-    const size_t off = ((size_t)b * M + 4 * (size_t)i + row) * a.Kp + 4 * (size_t)k;
-    const double2* pk = a.pi + ((size_t)b * a.nq + k) * 16;
-    double2 dX[4], dY[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      double2 l0 = czero(), l1 = czero();
+  for (int x = 0; x < 8; ++x) q.c[x] = czero();
+  const double vfix = a.nodes[min(i, n - 1)];
+  for (int k = k0; k < k1; ++k) {
+    const size_t off = ((size_t)b * M + 4 * (size_t)i + rc) * a.Kp + 4 * (size_t)k;
+    double2 l0, l1;
+    if (LEFT) {
+      const double2* pk = a.pi + ((size_t)b * a.nq + k) * 16;
+      l0 = l1 = czero();
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        const double2 cp = cconj(pk[4 * q + m]);
+        const double2 cp = cconj(pk[4 * e + m]);
         l0 = cadd(l0, cmul(cconj(a.G0[off + m]), cp));
         l1 = cadd(l1, cmul(cconj(a.G1[off + m]), cp));
       }
-      dX[q] = make_double2(a.mix[0] * l0.x + a.mix[2] * l1.x, a.mix[0] * l0.y + a.mix[2] * l1.y);
-      dY[q] = make_double2(a.mix[1] * l0.x + a.mix[3] * l1.x, a.mix[1] * l0.y + a.mix[3] * l1.y);
-    }
-    const double vq = a.qv[k];
-    if (i < n) {
-      if (co != 0.0) {
-        if (dKo[1])
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            acc[e] = cfma(co, dX[e], acc[e]);
-            acc[4 + e] = cfma(co, dY[e], acc[4 + e]);
-          }
-        int j0;
-        double t;
-        if (dKo[3] && dgrid_locate(a.V.g, vq, j0, t))
-          for (int s = 0; s < 2; ++s) {
-            double2* p = dKo[3] + ((((size_t)s * n + iw) * n + i) * n + j0) * 16 + 4 * row;
-            const double2* d = s ? dY : dX;
-            for (int e = 0; e < 4; ++e) {
-              atomic_c(p + e, cscale(co * (1.0 - t), d[e]));
-              atomic_c(p + 16 + e, cscale(co * t, d[e]));
-            }
-          }
-      }
-      scatter_others(a, w, a.nodes[i], vq, 0, row, dX, dY);
     } else {
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (bare_odd(4 * row + e)) accr += -0.5 * dX[e].x + 0.5 * dY[e].x;
-      if (co != 0.0) {
-        if (dKo[0])
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            acc[e] = cfma(co, dX[e], acc[e]);
-            acc[4 + e] = cfma(co, dY[e], acc[4 + e]);
-          }
-        int j0;
-        double t;
-        if (dKo[2] && dgrid_locate(a.V.g, vq, j0, t))
-          for (int s = 0; s < 2; ++s) {
-            double2* p = dKo[2] + (((size_t)s * n + iw) * n + j0) * 16 + 4 * row;
-            const double2* d = s ? dY : dX;
-            for (int e = 0; e < 4; ++e) {
-              atomic_c(p + e, cscale(co * (1.0 - t), d[e]));
-              atomic_c(p + 16 + e, cscale(co * t, d[e]));
-            }
-          }
-      }
+      l0 = cconj(a.G0[off + e]);
+      l1 = cconj(a.G1[off + e]);
     }
-  }
-  reduce_slots(acc, accr, red, redr);
-  if (threadIdx.x < 4) {
-    const int rw = threadIdx.x;
-    double2* tgt = nullptr;
-    size_t base = 0, sstride = 0;
-    if (i < n && dKo[1]) {
-      tgt = dKo[1];
-      base = (((size_t)iw) * n + i) * 16;
-      sstride = (size_t)n * n * 16;
-    } else if (i == n && dKo[0]) {
-      tgt = dKo[0];
-      base = (size_t)iw * 16;
-      sstride = (size_t)n * 16;
-    }
-    if (tgt && co != 0.0)
-      for (int e = 0; e < 4; ++e) {
-        atomic_c(tgt + base + 4 * rw + e, acc[e]);
-        atomic_c(tgt + sstride + base + 4 * rw + e, acc[4 + e]);
-      }
-    if (rw == 0 && i == n && a.dr0) atomicAdd(a.dr0, accr);
-  }
-}
-
-// Right side: block (j, batch), threads = 64 quadrature slots x 4 pair columns.
-__global__ __launch_bounds__(256) void adj_right_kernel(AdjScatterArgs a) {
-  __shared__ double2 red[4][4][8];
-  __shared__ double redr[4];
-  const int j = blockIdx.x, b = blockIdx.y;
-  const int col = threadIdx.x & 3, slot = threadIdx.x >> 2;
-  const int n = a.V.g.n, iw = a.iw0 + b;
-  const size_t M = 4 * (size_t)(n + 1);
-  const double w = a.nodes[iw];
-  const DChan& own = a.V.ch[a.r];
-  const double co = own.coef;
-  double2* const* dKo = a.dK[a.r];
-  double2 acc[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = czero();
-  double accr = 0.0;
-  for (int k = slot; k < a.nq; k += 64) {
-    const size_t off = ((size_t)b * M + 4 * (size_t)j + col) * a.Kp + 4 * (size_t)k;
-    double2 dX[4], dY[4];  // cotangents of R[m][col], m = 0..3
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const double2 g0 = cconj(a.G0[off + m]), g1 = cconj(a.G1[off + m]);
-      dX[m] = make_double2(a.mix[0] * g0.x + a.mix[2] * g1.x, a.mix[0] * g0.y + a.mix[2] * g1.y);
-      dY[m] = make_double2(a.mix[1] * g0.x + a.mix[3] * g1.x, a.mix[1] * g0.y + a.mix[3] * g1.y);
-    }
+    const double m0 = s ? a.mix[1] : a.mix[0], m1 = s ? a.mix[3] : a.mix[2];
+    const double2 d = make_double2(m0 * l0.x + m1 * l1.x, m0 * l0.y + m1 * l1.y);
     const double vq = a.qv[k];
-    if (j < n) {
-      if (co != 0.0) {
-        if (dKo[2])
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            acc[e] = cfma(co, dX[e], acc[e]);
-            acc[4 + e] = cfma(co, dY[e], acc[4 + e]);
+    if (bare) racc += (s ? 0.5 : -0.5) * d.x;
+    if (cT) cacc = cfma(co, d, cacc);
+    if (tapT) {
+      int j0;
+      double t;
+      if (dgrid_locate(a.V.g, vq, j0, t)) {
+        if (j0 != tj) {
+          if (tj >= 0) {
+            atomic_c(tapT + tapBase + (size_t)tj * tapStep + fo, t0);
+            atomic_c(tapT + tapBase + (size_t)(tj + 1) * tapStep + fo, t1);
           }
-        int i0;
-        double t;
-        if (dKo[3] && dgrid_locate(a.V.g, vq, i0, t))
-          for (int s = 0; s < 2; ++s) {
-            double2* p = dKo[3] + ((((size_t)s * n + iw) * n + i0) * n + j) * 16 + col;
-            const size_t step = (size_t)n * 16;
-            const double2* d = s ? dY : dX;
-            for (int e = 0; e < 4; ++e) {
-              atomic_c(p + 4 * e, cscale(co * (1.0 - t), d[e]));
-              atomic_c(p + step + 4 * e, cscale(co * t, d[e]));
-            }
-          }
+          tj = j0;
+          t0 = t1 = czero();
+        }
+        t0 = cfma(co * (1.0 - t), d, t0);
+        t1 = cfma(co * t, d, t1);
       }
-      scatter_others(a, w, vq, a.nodes[j], 1, col, dX, dY);
-    } else {
+    }
+    if (oth) {
+      double L[4];
+      if (LEFT)
+        legs_of(r, w, vfix, vq, L);
+      else
+        legs_of(r, w, vq, vfix, L);
+      double w2, v2, vp2;
+      params_of(r2, L, w2, v2, vp2);
+      int jw, jv = 0, jvp = 0;
+      double tw, tv = 0.0, tvp = 0.0;
+      if (dgrid_locate(a.V.g, w2, jw, tw)) {
+        const bool inv = dgrid_locate(a.V.g, v2, jv, tv);
+        const bool invp = dgrid_locate(a.V.g, vp2, jvp, tvp);
+        const double2 dc = cscale(co2, d);
+        if (inv && invp && dKf2) {
+          if (jw != q.iw || jv != q.iv || jvp != q.ivp) {
+            flush8(dKf2, n, s, f2, q);
+            q.iw = jw;
+            q.iv = jv;
+            q.ivp = jvp;
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (bare_odd(4 * e + col)) accr += -0.5 * dX[e].x + 0.5 * dY[e].x;
-      if (co != 0.0) {
-        if (dKo[0])
+            for (int x = 0; x < 8; ++x) q.c[x] = czero();
+          }
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            acc[e] = cfma(co, dX[e], acc[e]);
-            acc[4 + e] = cfma(co, dY[e], acc[4 + e]);
+          for (int x = 0; x < 8; ++x) {
+            const double wt = ((x >> 2) ? tw : 1.0 - tw) * (((x >> 1) & 1) ? tv : 1.0 - tv) * ((x & 1) ? tvp : 1.0 - tvp);
+            q.c[x] = cfma(wt, dc, q.c[x]);
           }
-        int i0;
-        double t;
-        if (dKo[1] && dgrid_locate(a.V.g, vq, i0, t))
-          for (int s = 0; s < 2; ++s) {
-            double2* p = dKo[1] + (((size_t)s * n + iw) * n + i0) * 16 + col;
-            const double2* d = s ? dY : dX;
-            for (int e = 0; e < 4; ++e) {
-              atomic_c(p + 4 * e, cscale(co * (1.0 - t), d[e]));
-              atomic_c(p + 16 + 4 * e, cscale(co * t, d[e]));
-            }
-          }
+        } else {
+          scatter_partial(a.dK[r2], n, s, f2, jw, tw, inv, jv, tv, invp, jvp, tvp, dc);
+        }
       }
     }
   }
-  reduce_slots(acc, accr, red, redr);
-  if (threadIdx.x < 4) {
-    const int cl = threadIdx.x;
-    double2* tgt = nullptr;
-    size_t base = 0, sstride = 0;
-    if (j < n && dKo[2]) {
-      tgt = dKo[2];
-      base = (((size_t)iw) * n + j) * 16;
-      sstride = (size_t)n * n * 16;
-    } else if (j == n && dKo[0]) {
-      tgt = dKo[0];
-      base = (size_t)iw * 16;
-      sstride = (size_t)n * 16;
-    }
-    if (tgt && co != 0.0)
-      for (int e = 0; e < 4; ++e) {
-        atomic_c(tgt + base + 4 * e + cl, acc[e]);
-        atomic_c(tgt + sstride + base + 4 * e + cl, acc[4 + e]);
-      }
-    if (cl == 0 && j == n && a.dr0) atomicAdd(a.dr0, accr);
+  if (oth && dKf2) flush8(dKf2, n, s, f2, q);
+  if (tapT && tj >= 0) {
+    atomic_c(tapT + tapBase + (size_t)tj * tapStep + fo, t0);
+    atomic_c(tapT + tapBase + (size_t)(tj + 1) * tapStep + fo, t1);
+  }
+  if (cT) atomic_c(cT + cOff + fo, cacc);
+  if (!mainb && a.dr0) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) racc += __shfl_xor(racc, o);
+    if (lane == 0) atomicAdd(a.dr0, racc);
   }
 }
 
@@ -2479,11 +2386,25 @@ void launch_dpanel(const DPanelArgs& a, hipStream_t s) {
 void launch_apply_pi(const ApplyPiArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(apply_pi_kernel, dim3(4096), dim3(256), 0, s, a);
 }
+// about 8192 wavefronts per launch, chunks of at least 32 loop nodes
+static void adj_run_grid(const AdjScatterArgs& a, dim3& grid, int& chunk) {
+  const long units = (long)(a.V.g.n + 1) * a.nb;
+  const long want = std::max<long>(1, std::min<long>((a.nq + 31) / 32, (8192 + units - 1) / units));
+  chunk = (int)((a.nq + want - 1) / want);
+  const int nchunks = (a.nq + chunk - 1) / chunk;
+  grid = dim3(a.V.g.n + 1, a.nb, (nchunks + 3) / 4);
+}
 void launch_adj_left(const AdjScatterArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(adj_left_kernel, dim3(a.V.g.n + 1, a.nb), dim3(256), 0, s, a);
+  dim3 grid;
+  int chunk;
+  adj_run_grid(a, grid, chunk);
+  hipLaunchKernelGGL(adj_run_kernel<true>, grid, dim3(256), 0, s, a, chunk);
 }
 void launch_adj_right(const AdjScatterArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(adj_right_kernel, dim3(a.V.g.n + 1, a.nb), dim3(256), 0, s, a);
+  dim3 grid;
+  int chunk;
+  adj_run_grid(a, grid, chunk);
+  hipLaunchKernelGGL(adj_run_kernel<false>, grid, dim3(256), 0, s, a, chunk);
 }
 void launch_dpi(const DPiArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(dpi_kernel, dim3(a.nq, a.nb), dim3(256), 0, s, a);
