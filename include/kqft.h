@@ -736,8 +736,13 @@ int kqft_chi_noalloc(int channel, const kqft_vertex* gamma, const kqft_propagato
                      double* chi, void* stream);
 
 /* Device bytes held by the library's workspaces (every context of the process): current
-   and peak since the library was loaded.  Either pointer may be NULL, not both. */
+   and peak since the library was loaded or the last kqft_workspace_reset_peak.  Either
+   pointer may be NULL, not both. */
 int kqft_workspace_bytes(size_t* current, size_t* peak);
+
+/* Restart the peak of kqft_workspace_bytes at the current bytes (to measure one workload's
+   peak in a process that ran others before).  Always returns KQFT_OK. */
+int kqft_workspace_reset_peak(void);
 
 #ifdef __cplusplus
 }

@@ -3379,6 +3379,11 @@ int kqft_workspace_bytes(size_t* current, size_t* peak) {
   return KQFT_OK;
 }
 
+int kqft_workspace_reset_peak(void) {
+  g_ws_peak.store(g_ws_bytes.load());
+  return KQFT_OK;
+}
+
 
 }  // extern "C"
 

@@ -129,6 +129,7 @@ def lib():
         _lib.kqft_mloop_jvp.argtypes = [C.c_void_p, P(KqftVertex), P(KqftVertex), P(KqftPropagator), P(KqftQuad),
                                         C.c_int, P(KqftOpts), P(KqftChout), P(KqftChout), C.c_void_p]
         _lib.kqft_workspace_bytes.argtypes = [P(C.c_size_t), P(C.c_size_t)]
+        _lib.kqft_workspace_reset_peak.argtypes = []
         _lib.kqft_bubble_tune.argtypes = [C.c_void_p, C.c_int, P(KqftVertex), P(KqftVertex), P(KqftPropagator),
                                           C.c_int, P(KqftQuad), P(KqftOpts), P(KqftChout), C.c_size_t,
                                           P(C.c_int), P(C.c_double), C.c_void_p]
@@ -176,7 +177,8 @@ def exported_symbols() -> list:
     names = ["kqft_ctx_create", "kqft_ctx_destroy", "kqft_last_error", "kqft_ctx_profile", "kqft_ctx_profile_read",
              "kqft_bubble_workspace", "kqft_bubble",
              "kqft_sde", "kqft_mloop_step", "kqft_bubble_adjoint", "kqft_sde_adjoint", "kqft_mloop_adjoint",
-             "kqft_mloop_jvp", "kqft_workspace_bytes", "kqft_chi_noalloc", "kqft_bubble_tune"]
+             "kqft_mloop_jvp", "kqft_workspace_bytes", "kqft_workspace_reset_peak", "kqft_chi_noalloc",
+             "kqft_bubble_tune"]
     L = lib()
     return [n for n in names if hasattr(L, n)]
 
@@ -780,6 +782,11 @@ def workspace_bytes():
     cur, pk = C.c_size_t(), C.c_size_t()
     _check(lib().kqft_workspace_bytes(C.byref(cur), C.byref(pk)))
     return cur.value, pk.value
+
+
+def workspace_reset_peak() -> None:
+    """Restart the workspace peak at the current bytes (kqft_workspace_reset_peak)."""
+    _check(lib().kqft_workspace_reset_peak())
 
 
 def bubble_tune(channel: int, left: Vertex, right: Vertex, G: Propagator, q: Quad, pi_kind: int = PI_GG,

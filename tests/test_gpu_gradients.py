@@ -127,6 +127,7 @@ def test_gradient_workload_n151_vs_finite_differences():
     cr, ci = rng.standard_normal(n), rng.standard_normal(n)
     print(f"gradient workload n={n} nq={nq}: autograd forward", flush=True)
     torch.cuda.reset_peak_memory_stats()
+    K.workspace_reset_peak()
     Ut = torch.tensor(U, dtype=torch.float64, requires_grad=True)
     Dt = torch.tensor(D, dtype=torch.float64, requires_grad=True)
     torch.cuda.synchronize()
