@@ -308,3 +308,44 @@ def test_mloop_adjoint_split_matches_fp64():
         for x in CL:
             a, b = getattr(G32[r], x), getattr(G64[r], x)
             assert float((a - b).abs().max()) < 1e-6 * float(b.abs().max()), (r, x)
+
+
+@pytest.mark.parametrize("r", [0, 1, 2])
+def test_bubble_adjoint_partial_class_targets(r):
+    """Cotangents requested for some classes only (no K3 target: the other channels' taps go to
+    K1, K2, K2' at once instead of through the fused table; an own channel without K2') equal
+    the same classes of the full request.  Grid and quadrature put nodes on and off the grid;
+    chunks of the scatter span runs of equal cells and their boundaries (nq not a multiple of
+    the chunk)."""
+    K = _K()
+    n, nq = 9, 37
+    ovL, kvL = pair(n, (31, 32, 33), (1.0, 0.7, 0.9))
+    ovR, kvR = pair(n, (34, 35, 36), (0.8, 1.0, 1.2))
+    c = cot(n, 37)
+    dout = K.Channel(1.0, *[to_dev(c[x]) for x in CL])
+    P, q = K.Propagator(D, T), K.Quad(nq)
+    fL = [K.alloc_channel(n) for _ in range(3)]
+    fR = [K.alloc_channel(n) for _ in range(3)]
+    full = K.bubble_adjoint(r, kvL, kvR, P, q, dout, dleft=fL, dright=fR)
+    keep = {"K1": True, "K2": True, "K2p": True, "K3": False}
+    pL, pR = [], []
+    for side, dst in ((fL, pL), (fR, pR)):
+        for rr in range(3):
+            ch = K.alloc_channel(n)
+            if rr == r:  # own channel: K2' not requested either
+                dst.append(K.Channel(1.0, ch.K1, ch.K2, None, ch.K3))
+            else:
+                dst.append(K.Channel(1.0, *[getattr(ch, x) if keep[x] else None for x in CL]))
+    part = K.bubble_adjoint(r, kvL, kvR, P, q, dout, dleft=pL, dright=pR)
+    torch.cuda.synchronize()
+    full, part = full.cpu().numpy(), part.cpu().numpy()
+    assert np.abs(full - part).max() < 1e-12 * max(1.0, np.abs(full).max())
+    for fs, ps in ((fL, pL), (fR, pR)):
+        for rr in range(3):
+            for x in CL:
+                got = getattr(ps[rr], x)
+                if got is None:
+                    continue
+                want = getattr(fs[rr], x).cpu().numpy()
+                sc = max(np.abs(want).max(), 1e-300)
+                assert np.abs(got.cpu().numpy() - want).max() < 1e-12 * sc, (rr, x)
