@@ -113,7 +113,7 @@ enum { KQFT_QUAD_TAN_FINITE = 0, KQFT_QUAD_TAN_INFINITE = 1 };
 enum { KQFT_GRID_TAN = 0, KQFT_GRID_ALGEBRAIC = 1 };
 
 typedef struct {
-  int n;    /* points, odd recommended (v = 0 is then a node), n >= 2 */
+  int n;    /* points, odd recommended (v = 0 is then a node), 2 <= n <= 600 (KQFT_ESHAPE) */
   double L; /* extent: nodes span [-L, L]; L and a finite and positive, else KQFT_ESHAPE */
   double a; /* map scale */
   int map;  /* KQFT_GRID_TAN (0, a zero-initialised grid) or KQFT_GRID_ALGEBRAIC; another value:

@@ -215,6 +215,9 @@ static bool same_grid(const kqft_grid& a, const kqft_grid& b) {
 static int check_grid(const kqft_grid& g, const char* what) {
   if (g.n < 2 || !(g.L > 0) || !(g.a > 0) || !std::isfinite(g.L) || !std::isfinite(g.a))
     return fail(KQFT_ESHAPE, std::string("invalid grid: ") + what);
+  // the kernels index table records (n^3 + 2n^2 + n per table) in 32 bits; a K3 class at
+  // n = 600 already takes 110 GB per channel
+  if (g.n > 600) return fail(KQFT_ESHAPE, std::string("grid of more than 600 points: ") + what);
   if (g.map != KQFT_GRID_TAN && g.map != KQFT_GRID_ALGEBRAIC)
     return fail(KQFT_EINVAL, std::string("unknown grid map: ") + what);
   return KQFT_OK;

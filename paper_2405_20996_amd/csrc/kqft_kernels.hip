@@ -102,27 +102,30 @@ __host__ __device__ inline int rec_pos(int f, int c, bool f32) {
 __device__ inline void st2(double2* p, double2 v) { *p = v; }
 __device__ inline void st2(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
 
+// Record indices in 32 bits: grids have at most 600 points (checked at the entry points), so
+// 16 threads per record stay below 2^32.
 template <class TT> __global__ __launch_bounds__(256) void table_kernel(TableArgs a) {
-  const size_t n = a.n, n2 = n * n, n3 = n2 * n;
-  const size_t total = (n3 + 2 * n2 + n) * 16;
+  const unsigned n = a.n, n2 = n * n, n3 = n2 * n;
+  const unsigned total = (n3 + 2 * n2 + n) * 16;
   const bool f32 = sizeof(TT) == sizeof(float2);
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+  for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
     const int f = (int)(e & 15);
-    const size_t rec = e >> 4;
-    size_t w, v = 0, vp = 0;
+    const unsigned rec = e >> 4;
+    unsigned w, v = 0, vp = 0;
     bool has_v = false, has_vp = false;
     if (rec < n3) {
-      vp = rec % n;
-      v = (rec / n) % n;
-      w = rec / n2;
+      const unsigned wv = rec / n;
+      vp = rec - wv * n;
+      w = wv / n;
+      v = wv - w * n;
       has_v = has_vp = true;
     } else if (rec < n3 + n2) {
-      v = (rec - n3) % n;
       w = (rec - n3) / n;
+      v = rec - n3 - w * n;
       has_v = true;
     } else if (rec < n3 + 2 * n2) {
-      vp = (rec - n3 - n2) % n;
       w = (rec - n3 - n2) / n;
+      vp = rec - n3 - n2 - w * n;
       has_vp = true;
     } else {
       w = rec - n3 - 2 * n2;
@@ -139,7 +142,7 @@ template <class TT> __global__ __launch_bounds__(256) void table_kernel(TableArg
       if (has_v && has_vp && a.K[3]) x = cadd(x, a.K[3][((sw * n + v) * n + vp) * 16 + pf]);
       xy[s] = x;
     }
-    TT* out = (TT*)a.out + rec * 32;
+    TT* out = (TT*)a.out + (size_t)rec * 32;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const double m0 = a.coef * a.mix[2 * c], m1 = a.coef * a.mix[2 * c + 1];
