@@ -101,3 +101,15 @@ def test_asymmetric_flow_level_flow_and_chi_arguments():
         K.chi(3, V, K.Propagator(D, T), q)
     with pytest.raises(K.KqftError):  # chi indexes the double sum in 32 bits
         K.chi(1, V, K.Propagator(D, T), K.Quad(46341))
+
+
+def test_grid_size_limit():
+    """A grid of more than 600 points is rejected (table records are indexed in 32 bits); the
+    vertex's class arrays are never touched, so a tiny placeholder vertex suffices."""
+    K = _K()
+    g = K.Grid(601)
+    V = K.Vertex(g, 1.0)  # bare vertex: no class arrays
+    with pytest.raises(K.KqftError):
+        K.chi(0, V, K.Propagator(D, T), K.Quad(11))
+    with pytest.raises(K.KqftError):
+        K.sde(V, K.Propagator(D, T), K.Quad(11), K.Quad(11))
