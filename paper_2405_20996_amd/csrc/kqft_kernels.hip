@@ -1946,7 +1946,8 @@ __global__ __launch_bounds__(256) void apply_pi_kernel(ApplyPiArgs a) {
 // and walks the chunk's nodes in order.  Consecutive nodes share the interpolation cell of the
 // other channel a few at a time and the own-channel cell about ten at a time, so the weighted
 // values are summed in registers per cell corner and reach memory (FP64 atomics) only when the
-// cell changes and at the end of the chunk; arguments off the grid (the partial classes) go
+// cell changes -- and then only the corners the next cell does not share, when it is one node
+// further along one axis -- and at the end of the chunk; arguments off the grid (the partial classes) go
 // to memory at once.  The own channel's class that does not depend on the loop node (K2 / K2'
 // of the main blocks, K1 of the border) and the bare vertex's cotangent are summed over the
 // chunk.
@@ -1957,7 +1958,7 @@ struct Corner8 {  // register accumulators of the current cell of one lane's tar
 };
 
 // cell (iw, iv, ivp) of a table of n^3 records of 16 entries per spin; x = corner 4cw + 2cv + cp
-__device__ inline void flush8(double2* T, int n, int s, int f, const Corner8& q) {
+__device__ __forceinline__ void flush8(double2* T, int n, int s, int f, const Corner8& q) {
   if (q.iw < 0) return;
 #pragma unroll
   for (int x = 0; x < 8; ++x) {
@@ -1965,6 +1966,64 @@ __device__ inline void flush8(double2* T, int n, int s, int f, const Corner8& q)
     const size_t rec = (((size_t)s * n + q.iw + cw) * n + q.iv + cv) * n + q.ivp + cp;
     atomic_c(T + rec * 16 + f, q.c[x]);
   }
+}
+
+// one corner x of the current cell to memory
+__device__ __forceinline__ void flush1(double2* T, int n, int s, int f, const Corner8& q, int x) {
+  const int cw = x >> 2, cv = (x >> 1) & 1, cp = x & 1;
+  const size_t rec = (((size_t)s * n + q.iw + cw) * n + q.iv + cv) * n + q.ivp + cp;
+  atomic_c(T + rec * 16 + f, q.c[x]);
+}
+
+// move the accumulators to cell (jw, jv, jvp).  After a step of one node along one axis the
+// four corners the two cells share keep their sums and only the other four go to memory;
+// otherwise all eight do.  (Corner indices stay compile-time constants: selects, no indexed
+// register array.)
+__device__ __forceinline__ void move8(double2* T, int n, int s, int f, Corner8& q, int jw, int jv, int jvp) {
+  const int dw = jw - q.iw, dv = jv - q.iv, dp = jvp - q.ivp;
+  const bool valid = q.iw >= 0;
+  int sw = 0, sv = 0, sp = 0;
+  if (valid && dv == 0 && dp == 0 && (dw == 1 || dw == -1))
+    sw = dw;
+  else if (valid && dw == 0 && dp == 0 && (dv == 1 || dv == -1))
+    sv = dv;
+  else if (valid && dw == 0 && dv == 0 && (dp == 1 || dp == -1))
+    sp = dp;
+  if (valid) {
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+      const bool bw = x & 4, bv = x & 2, bp = x & 1;
+      const bool kept = (sw > 0 && bw) || (sw < 0 && !bw) || (sv > 0 && bv) || (sv < 0 && !bv) ||
+                        (sp > 0 && bp) || (sp < 0 && !bp);
+      if (!kept) flush1(T, n, s, f, q, x);
+    }
+  }
+  double2 nc[8];
+#pragma unroll
+  for (int x = 0; x < 8; ++x) {
+    double2 v = czero();
+    if (x & 4) {
+      if (sw < 0) v = q.c[x & 3];
+    } else {
+      if (sw > 0) v = q.c[x | 4];
+    }
+    if (x & 2) {
+      if (sv < 0) v = q.c[x & 5];
+    } else {
+      if (sv > 0) v = q.c[x | 2];
+    }
+    if (x & 1) {
+      if (sp < 0) v = q.c[x & 6];
+    } else {
+      if (sp > 0) v = q.c[x | 1];
+    }
+    nc[x] = v;
+  }
+#pragma unroll
+  for (int x = 0; x < 8; ++x) q.c[x] = nc[x];
+  q.iw = jw;
+  q.iv = jv;
+  q.ivp = jvp;
 }
 
 // partial classes of another channel (an argument off the grid, or no fused table): the
@@ -2065,13 +2124,23 @@ __global__ __launch_bounds__(256) void adj_run_kernel(AdjScatterArgs a, int chun
       int j0;
       double t;
       if (dgrid_locate(a.V.g, vq, j0, t)) {
-        if (j0 != tj) {
-          if (tj >= 0) {
+        if (j0 != tj) {  // a step of one node keeps the shared corner's sum
+          if (tj >= 0 && j0 == tj + 1) {
             atomic_c(tapT + tapBase + (size_t)tj * tapStep + fo, t0);
+            t0 = t1;
+            t1 = czero();
+          } else if (tj >= 0 && j0 == tj - 1) {
             atomic_c(tapT + tapBase + (size_t)(tj + 1) * tapStep + fo, t1);
+            t1 = t0;
+            t0 = czero();
+          } else {
+            if (tj >= 0) {
+              atomic_c(tapT + tapBase + (size_t)tj * tapStep + fo, t0);
+              atomic_c(tapT + tapBase + (size_t)(tj + 1) * tapStep + fo, t1);
+            }
+            t0 = t1 = czero();
           }
           tj = j0;
-          t0 = t1 = czero();
         }
         t0 = cfma(co * (1.0 - t), d, t0);
         t1 = cfma(co * t, d, t1);
@@ -2092,14 +2161,7 @@ __global__ __launch_bounds__(256) void adj_run_kernel(AdjScatterArgs a, int chun
         const bool invp = dgrid_locate(a.V.g, vp2, jvp, tvp);
         const double2 dc = cscale(co2, d);
         if (inv && invp && dKf2) {
-          if (jw != q.iw || jv != q.iv || jvp != q.ivp) {
-            flush8(dKf2, n, s, f2, q);
-            q.iw = jw;
-            q.iv = jv;
-            q.ivp = jvp;
-#pragma unroll
-            for (int x = 0; x < 8; ++x) q.c[x] = czero();
-          }
+          if (jw != q.iw || jv != q.iv || jvp != q.ivp) move8(dKf2, n, s, f2, q, jw, jv, jvp);
 #pragma unroll
           for (int x = 0; x < 8; ++x) {
             const double wt = ((x >> 2) ? tw : 1.0 - tw) * (((x >> 1) & 1) ? tv : 1.0 - tv) * ((x & 1) ? tvp : 1.0 - tvp);
