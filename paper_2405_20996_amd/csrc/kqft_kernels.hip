@@ -2266,8 +2266,7 @@ __global__ __launch_bounds__(256) void unfuse_kernel(UnfuseArgs a, int cls) {
   const size_t n = a.n;
   size_t total;
   if (cls == 3) total = 2 * n * n * n * 16;
-  else if (cls == 0) total = 2 * n * 16;
-  else total = 2 * n * n * 16;
+  else total = 2 * n * n * 16;  // K2, K2' (K1: unfuse_k1_kernel)
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
     const size_t f = e & 15;
     if (cls == 3) {
@@ -2275,12 +2274,7 @@ __global__ __launch_bounds__(256) void unfuse_kernel(UnfuseArgs a, int cls) {
       continue;
     }
     double2 s = czero();
-    if (cls == 0) {  // K1[s][w]: sum over v, v'
-      const size_t sw = e >> 4;
-      for (size_t v = 0; v < n; ++v)
-        for (size_t vp = 0; vp < n; ++vp) s = cadd(s, a.dKf[((sw * n + v) * n + vp) * 16 + f]);
-      a.dK1[e] = cadd(a.dK1[e], s);
-    } else if (cls == 1) {  // K2[s][w][v]: sum over v'
+    if (cls == 1) {  // K2[s][w][v]: sum over v'
       const size_t swv = e >> 4;
       for (size_t vp = 0; vp < n; ++vp) s = cadd(s, a.dKf[(swv * n + vp) * 16 + f]);
       a.dK2[e] = cadd(a.dK2[e], s);
@@ -2292,6 +2286,25 @@ __global__ __launch_bounds__(256) void unfuse_kernel(UnfuseArgs a, int cls) {
   }
 }
 
+
+// K1[s][w] += sum over (v, v') of the fused table: one workgroup per (s, w), sixteen slices of
+// the n^2 records per entry f, summed in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void unfuse_k1_kernel(UnfuseArgs a) {
+  __shared__ double2 part[16][16];
+  const int f = threadIdx.x & 15, sl = threadIdx.x >> 4;
+  const size_t n = a.n, n2 = n * n, sw = blockIdx.x;
+  const double2* src = a.dKf + sw * n2 * 16 + f;
+  double2 acc = czero();
+  for (size_t q = sl; q < n2; q += 16) acc = cadd(acc, src[q * 16]);
+  part[sl][f] = acc;
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    double2 t = czero();
+#pragma unroll
+    for (int x = 0; x < 16; ++x) t = cadd(t, part[x][f]);
+    a.dK1[sw * 16 + f] = cadd(a.dK1[sw * 16 + f], t);
+  }
+}
 
 // Transpose of loop_kernel.  With M = 2 Phi^X + Phi^Y and c = 2 a1' + a1:
 //   dM[f(a1',a2',a1,a2)] = conj(wgt G^{a2|a2'}) dSigma[c],  dPhi^X = 2 dM, dPhi^Y = dM,
@@ -2478,7 +2491,7 @@ void launch_unfuse(const UnfuseArgs& a, hipStream_t s) {
   if (a.dK3) hipLaunchKernelGGL(unfuse_kernel, dim3(4096), dim3(256), 0, s, a, 3);
   if (a.dK2) hipLaunchKernelGGL(unfuse_kernel, dim3(1024), dim3(256), 0, s, a, 1);
   if (a.dK2p) hipLaunchKernelGGL(unfuse_kernel, dim3(1024), dim3(256), 0, s, a, 2);
-  if (a.dK1) hipLaunchKernelGGL(unfuse_kernel, dim3(64), dim3(256), 0, s, a, 0);
+  if (a.dK1) hipLaunchKernelGGL(unfuse_k1_kernel, dim3(2 * a.n), dim3(256), 0, s, a);
 }
 void launch_sigma_split(int n, const double2* sigma, double2* sigR, double2* sigK, hipStream_t s) {
   hipLaunchKernelGGL(sigma_split_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, sigma, sigR, sigK);
