@@ -1910,31 +1910,38 @@ __global__ __launch_bounds__(256) void dpanel_kernel(DPanelArgs a) {
   }
 }
 
+// One thread per panel entry (row, k, m): the lane loads its own raw entry L[row][(k, m)]
+// (coalesced), takes the quad's four q through quad-permute broadcasts, and writes
+// A[row][(k, m)] = sum_q L[row][(k, q)] Pi_k[q][m].
 __global__ __launch_bounds__(256) void apply_pi_kernel(ApplyPiArgs a) {
   const long M = 4L * (a.n + 1);
-  const long total = (long)a.nb * M * a.nq_pad;
+  const long total = (long)a.nb * M * a.Kp;  // Kp = 4 nq_pad: whole quads of entries
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
-    const int k = (int)(e % a.nq_pad);
-    const long R = (e / a.nq_pad) % M;
-    const int b = (int)(e / (a.nq_pad * M));
-    const size_t off = ((size_t)b * M + R) * a.Kp + 4 * (size_t)k;
-    if (k >= a.nq) {
+    const int km = (int)(e % a.Kp), k = km >> 2, m = km & 3;
+    const long R = (e / a.Kp) % M;
+    const int b = (int)(e / (a.Kp * M));
+    const size_t off = ((size_t)b * M + R) * a.Kp + km;
+    const bool real = k < a.nq;  // padding nodes: zero (uniform per quad)
+    const double2 x0 = real ? a.L0[off] : czero(), x1 = real ? a.L1[off] : czero();
+    double2 s0 = czero(), s1 = czero();
+    const double2* pk = a.pi + ((size_t)b * a.nq + (real ? k : 0)) * 16;
+    double2 p[4];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) a.A0[off + m] = a.A1[off + m] = czero();
-      continue;
+    for (int q = 0; q < 4; ++q) p[q] = real ? pk[4 * q + m] : czero();
+#define KQFT_APPLY_Q(Q)                                                                        \
+    {                                                                                          \
+      const double2 l0 = make_double2(quad_bcast<Q>(x0.x), quad_bcast<Q>(x0.y));               \
+      const double2 l1 = make_double2(quad_bcast<Q>(x1.x), quad_bcast<Q>(x1.y));               \
+      s0 = cadd(s0, cmul(l0, p[Q]));                                                           \
+      s1 = cadd(s1, cmul(l1, p[Q]));                                                           \
     }
-    const double2* pk = a.pi + ((size_t)b * a.nq + k) * 16;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      double2 s0 = czero(), s1 = czero();
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        s0 = cadd(s0, cmul(a.L0[off + q], pk[4 * q + m]));
-        s1 = cadd(s1, cmul(a.L1[off + q], pk[4 * q + m]));
-      }
-      a.A0[off + m] = s0;
-      a.A1[off + m] = s1;
-    }
+    KQFT_APPLY_Q(0)
+    KQFT_APPLY_Q(1)
+    KQFT_APPLY_Q(2)
+    KQFT_APPLY_Q(3)
+#undef KQFT_APPLY_Q
+    a.A0[off] = s0;
+    a.A1[off] = s1;
   }
 }
 
