@@ -432,19 +432,34 @@ template <class T> __global__ __launch_bounds__(256) void gather_right_kernel(Ga
   const size_t off1 = off0 + 2;
   T* o0 = (T*)a.P0;
   T* o1 = (T*)a.P1;
-  if (k >= a.nq) {
-    store_c(o0 + off0, czero());
-    store_c(o1 + off0, czero());
-    store_c(o0 + off1, czero());
-    store_c(o1 + off1, czero());
-    return;
-  }
   double2 acc[4];
-  right_vals<T>(a, l, iw, j, j < n, a.qv[k], acc);
-  store_c(o0 + off0, acc[0]);
-  store_c(o1 + off0, acc[1]);
-  store_c(o0 + off1, acc[2]);
-  store_c(o1 + off1, acc[3]);
+  if (k < a.nq) {
+    right_vals<T>(a, l, iw, j, j < n, a.qv[k], acc);
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = czero();
+  }
+  if constexpr (sizeof(T) == sizeof(float2)) {
+    // FP32 panels: lanes l and l ^ 4 (rows e = h, h + 2 of one column) trade one value per
+    // combination so that each stores the two adjacent entries e = 2h, 2h + 1 as one 16-byte
+    // store; the group's stores then cover whole 32-byte column runs of each panel row.
+    float2 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = make_float2((float)acc[u].x, (float)acc[u].y);
+    const float2 s0 = h ? v[0] : v[2], s1 = h ? v[1] : v[3];
+    const float2 r0 = make_float2(__shfl_xor(s0.x, 4), __shfl_xor(s0.y, 4));
+    const float2 r1 = make_float2(__shfl_xor(s1.x, 4), __shfl_xor(s1.y, 4));
+    const float4 c0 = h ? make_float4(r0.x, r0.y, v[2].x, v[2].y) : make_float4(v[0].x, v[0].y, r0.x, r0.y);
+    const float4 c1 = h ? make_float4(r1.x, r1.y, v[3].x, v[3].y) : make_float4(v[1].x, v[1].y, r1.x, r1.y);
+    const size_t offs = ((size_t)b * Ncol + 4 * (size_t)j + q4) * a.Kp + 4 * (size_t)k + 2 * h;
+    *reinterpret_cast<float4*>(o0 + offs) = c0;
+    *reinterpret_cast<float4*>(o1 + offs) = c1;
+  } else {
+    store_c(o0 + off0, acc[0]);
+    store_c(o1 + off0, acc[1]);
+    store_c(o0 + off1, acc[2]);
+    store_c(o1 + off1, acc[3]);
+  }
 }
 
 // ======================================================================== adaptive bubble
