@@ -143,10 +143,19 @@ template <class TT> __global__ __launch_bounds__(256) void table_kernel(TableArg
       xy[s] = x;
     }
     TT* out = (TT*)a.out + (size_t)rec * 32;
+    double2 cv[2];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const double m0 = a.coef * a.mix[2 * c], m1 = a.coef * a.mix[2 * c + 1];
-      st2(out + rec_pos(f, c, f32), make_double2(m0 * xy[0].x + m1 * xy[1].x, m0 * xy[0].y + m1 * xy[1].y));
+      cv[c] = make_double2(m0 * xy[0].x + m1 * xy[1].x, m0 * xy[0].y + m1 * xy[1].y);
+    }
+    if constexpr (sizeof(TT) == sizeof(float2)) {
+      // (f, 0) and (f, 1) are adjacent in an FP32 record: one 16-byte store
+      *reinterpret_cast<float4*>(out + rec_pos(f, 0, true)) =
+          make_float4((float)cv[0].x, (float)cv[0].y, (float)cv[1].x, (float)cv[1].y);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 2; ++c) st2(out + rec_pos(f, c, f32), cv[c]);
     }
   }
 }
