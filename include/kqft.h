@@ -197,7 +197,7 @@ const char* kqft_last_error(void);
 /* Kernel timing for measurement: while enabled, every kernel launch of the library is
    bracketed by HIP events on the caller's stream.  kqft_ctx_profile_read synchronises
    those events and returns, per kernel kind (0 = propagator pair, 1 = gather, 2 = GEMM,
-   3 = loop / susceptibility reductions and the split path's unmix epilogue), the summed
+   3 = loop / susceptibility reductions and the GEMMs' unmix epilogue), the summed
    milliseconds and the launch counts,
    then clears them.  ms and launches: host arrays of 4. */
 int kqft_ctx_profile(kqft_ctx* ctx, int enable);

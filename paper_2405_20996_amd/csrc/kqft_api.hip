@@ -50,7 +50,7 @@ struct kqft_ctx {
   // multiloop adjoint / tangent: recomputed insertions, cotangent accumulators and the
   // extra cotangents of the stored left insertions (two orders each, per channel)
   DevBuf mlrec[2][3], mlbar[2][3], mlext[2][3], mlscr;
-  DevBuf gemmP;  // split-path GEMM products of one batch, both spin combinations
+  DevBuf gemmP;  // GEMM products of one batch, both spin combinations (FP64 entries)
   DevBuf chi_proj;  // susceptibility: grid projection of Pi and the own-channel part
   // autotuned transfer-frequency batch per (n, nq, precision), used when opts.omega_batch = 0
   std::map<std::tuple<int, int, int>, int> tuned_nb;
@@ -448,9 +448,9 @@ static int bubble_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_ve
     if ((rc = ensure(ctx->panels[x], 4 * pbytes * nb))) return rc;
     if ((rc = ensure(ctx->pi[x], (size_t)nb * nq * 256))) return rc;
   }
-  // split path: the two combinations' products of a batch (GEMM and unmix run in order on sm)
+  // the two combinations' products of a batch (GEMM and unmix run in order on sm)
   const size_t prod = (size_t)nb * M * M * sizeof(double2);
-  if (f32 && (rc = ensure(ctx->gemmP, 2 * prod))) return rc;
+  if (main_rows && (rc = ensure(ctx->gemmP, 2 * prod))) return rc;
   SideTables TL, TR;
   ctx->next_event = 0;
   hipEvent_t start;
@@ -516,7 +516,7 @@ static int bubble_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_ve
     g.K2 = out.K2;
     g.K2p = out.K2p;
     g.K3 = out.K3;
-    if (f32) {
+    if (main_rows) {
       g.P[0] = (double2*)ctx->gemmP.p;
       g.P[1] = (double2*)((char*)ctx->gemmP.p + prod);
     }
@@ -528,7 +528,7 @@ static int bubble_core(kqft_ctx* ctx, int r, const kqft_vertex& L, const kqft_ve
         ProfScope ps(ctx, 2, ctx->sm);
         launch_gemm(g, o.precision, ctx->sm);
       }
-      if (f32) {
+      {
         ProfScope ps(ctx, 3, ctx->sm);
         launch_unmix(g, ctx->sm);
       }
@@ -1146,8 +1146,8 @@ size_t kqft_bubble_workspace(int n, int nq, int omega_batch, int precision) {
   // two panel buffers, two propagator-pair buffers, up to four target-order class tables
   const size_t nn = n;
   const size_t table = (nn * nn * nn + 2 * nn * nn + nn) * 32 * (precision == KQFT_SPLIT_FP32 ? 8 : 16);
-  // the split path's per-combination products of one batch
-  const size_t prod = precision == KQFT_SPLIT_FP32 ? 2 * (size_t)nb * 16 * (4 * nn + 4) * (4 * nn + 4) : 0;
+  // the per-combination products of one batch (FP64 entries on both paths)
+  const size_t prod = 2 * (size_t)nb * 16 * (4 * nn + 4) * (4 * nn + 4);
   return 2 * (per_w + (size_t)nq * 256) * nb + 4 * table + prod;
 }
 

@@ -747,35 +747,37 @@ __device__ inline void epilogue_store(const GemmArgs& g, int b, int row, int col
 // Workgroups are dispatched round-robin over the eight XCDs (block id mod 8), each with
 // its own L2.  Give every XCD a contiguous range of logical tiles -- consecutive tiles of
 // one transfer frequency, row-major -- so that the workgroups sharing an A row strip or a
-// B column strip run on the same XCD at the same time and reuse it from that L2.
+// B column strip run on the same XCD at the same time and reuse it from that L2 (padding
+// blocks of the last XCD find a transfer frequency index >= nb and exit).
 constexpr int kXcds = 8;
-__device__ inline void tile_coords(const GemmArgs& g, int& b, int& tm, int& tn) {
-  const int tiles = g.tms * g.tns;
-  const int total = g.nb * tiles;
-  const int per_xcd = (total + kXcds - 1) / kXcds;
-  const int bid = blockIdx.x;
-  const int logical = (bid % kXcds) * per_xcd + bid / kXcds;
-  b = logical / tiles;  // >= nb for the padding blocks of the last XCD: they exit
-  const int t = logical - b * tiles;
-  tm = g.tm0 + t / g.tns;
-  tn = g.tn0 + t % g.tns;
-}
 
 // ======================================================================== FP64 GEMM
-// 64x64 complex tile per workgroup, four waves of 32x32, v_mfma_f64_16x16x4f64
-// (lane l: A row l%16 / k l/16, B k l/16 / col l%16, D rows 4v + l/16, col l%16); three
-// real products per complex multiply-add (Gauss), as in the split-FP32 kernel.
+// One spin combination per workgroup (grid = both combinations x tiles, combination-major,
+// XCD-spread as the split kernel), 64x64 complex tile, four waves of 32x32 on
+// v_mfma_f64_16x16x4f64 (lane l: A row l%16 / k l/16, B k l/16 / col l%16, D rows 4v + l/16,
+// col l%16); three real products per complex multiply-add (Gauss), as in the split-FP32
+// kernel.  K blocks of 16 complex through a single LDS buffer (34 KB), so three workgroups
+// share a CU; waves raise their issue priority while they run MFMAs; a wave whose 32-row or
+// 32-column block lies wholly past the ragged edge skips its MFMAs.  The combination's product
+// goes to the workspace P[c][w][row][col]; unmix_kernel undoes the spin diagonalisation.
 namespace f64g {
 constexpr int BM = 64, BK = 16, LDP = BM + 2;
 }
 
-__global__ __launch_bounds__(256, 2) void zgemm_f64_kernel(GemmArgs g) {
+__global__ __launch_bounds__(256, 3) void zgemm_f64_kernel(GemmArgs g) {
   using namespace f64g;
-  __shared__ double sA[2][2][BK][LDP];
-  __shared__ double sB[2][2][BK][LDP];
-  int b, tm, tn;
-  tile_coords(g, b, tm, tn);
+  __shared__ double sA[2][BK][LDP];
+  __shared__ double sB[2][BK][LDP];
+  const int tiles = g.tms * g.tns;
+  const int total = 2 * g.nb * tiles;
+  const int per_xcd = (total + kXcds - 1) / kXcds;
+  int logical = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+  const int c = logical >= g.nb * tiles ? 1 : 0;  // combination-major order
+  logical -= c * g.nb * tiles;
+  const int b = logical / tiles;
   if (b >= g.nb) return;
+  const int t = logical - b * tiles;
+  const int tm = g.tm0 + t / g.tns, tn = g.tn0 + t % g.tns;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int lrow = tid >> 2, lk = (tid & 3) * 4;
@@ -783,102 +785,79 @@ __global__ __launch_bounds__(256, 2) void zgemm_f64_kernel(GemmArgs g) {
   const int arow = min(tm * BM + lrow, Mtot - 1);
   const int brow = min(tn * BM + lrow, Mtot - 1);
   const int nk = Kp / BK;
-  const bool live = tm * BM + wm * 32 < Mtot && tn * BM + wn * 32 < Mtot;  // as in the split kernel
-  d4 acc[2][2][2][2];  // [combo][re/im][mb][nb]
+  const bool live = tm * BM + wm * 32 < Mtot && tn * BM + wn * 32 < Mtot;
+  const double2* Ap = (const double2*)g.A[c] + (size_t)b * g.strideA + (size_t)arow * Kp + lk;
+  const double2* Bp = (const double2*)g.B[c] + (size_t)b * g.strideB + (size_t)brow * Kp + lk;
+  d4 p[3][2][2];  // Gauss products ar br, ai bi, (ar + ai)(br + bi)
 #pragma unroll
-  for (int c = 0; c < 2; ++c)
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) acc[c][x][mb][nb] = d4{0.0, 0.0, 0.0, 0.0};
-
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    const double2* Ap = (const double2*)g.A[c] + (size_t)b * g.strideA + (size_t)arow * Kp + lk;
-    const double2* Bp = (const double2*)g.B[c] + (size_t)b * g.strideB + (size_t)brow * Kp + lk;
-    d4 p[3][2][2];  // Gauss products ar br, ai bi, (ar + ai)(br + bi) of this combination
-#pragma unroll
-    for (int x = 0; x < 3; ++x)
-#pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) p[x][mb][nb] = d4{0.0, 0.0, 0.0, 0.0};
-    double2 ra[4], rb[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      ra[e] = Ap[e];
-      rb[e] = Bp[e];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      sA[0][0][lk + e][lrow] = ra[e].x;
-      sA[0][1][lk + e][lrow] = ra[e].y;
-      sB[0][0][lk + e][lrow] = rb[e].x;
-      sB[0][1][lk + e][lrow] = rb[e].y;
-    }
-    __syncthreads();
-    for (int kb = 0; kb < nk; ++kb) {
-      const int buf = kb & 1;
-      if (kb + 1 < nk) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          ra[e] = Ap[(size_t)(kb + 1) * BK + e];
-          rb[e] = Bp[(size_t)(kb + 1) * BK + e];
-        }
-      }
-      if (live) {
-#pragma unroll
-        for (int kk = 0; kk < BK / 4; ++kk) {
-          const int kr = kk * 4 + (lane >> 4);
-          double ar[2], ai[2], br[2], bi[2];
-#pragma unroll
-          for (int mb = 0; mb < 2; ++mb) {
-            ar[mb] = sA[buf][0][kr][wm * 32 + mb * 16 + (lane & 15)];
-            ai[mb] = sA[buf][1][kr][wm * 32 + mb * 16 + (lane & 15)];
-          }
-#pragma unroll
-          for (int nb = 0; nb < 2; ++nb) {
-            br[nb] = sB[buf][0][kr][wn * 32 + nb * 16 + (lane & 15)];
-            bi[nb] = sB[buf][1][kr][wn * 32 + nb * 16 + (lane & 15)];
-          }
-          double sa[2], sb[2];
-#pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            sa[u] = ar[u] + ai[u];
-            sb[u] = br[u] + bi[u];
-          }
-#pragma unroll
-          for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-            for (int nb = 0; nb < 2; ++nb) {
-              p[0][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[mb], br[nb], p[0][mb][nb], 0, 0, 0);
-              p[1][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[mb], bi[nb], p[1][mb][nb], 0, 0, 0);
-              p[2][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[mb], sb[nb], p[2][mb][nb], 0, 0, 0);
-            }
-        }
-      }
-      if (kb + 1 < nk) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          sA[buf ^ 1][0][lk + e][lrow] = ra[e].x;
-          sA[buf ^ 1][1][lk + e][lrow] = ra[e].y;
-          sB[buf ^ 1][0][lk + e][lrow] = rb[e].x;
-          sB[buf ^ 1][1][lk + e][lrow] = rb[e].y;
-        }
-      }
-      __syncthreads();
-    }
+  for (int x = 0; x < 3; ++x)
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-      for (int nb = 0; nb < 2; ++nb) {
-        acc[c][0][mb][nb] = p[0][mb][nb] - p[1][mb][nb];
-        acc[c][1][mb][nb] = p[2][mb][nb] - p[0][mb][nb] - p[1][mb][nb];
-      }
+      for (int nb = 0; nb < 2; ++nb) p[x][mb][nb] = d4{0.0, 0.0, 0.0, 0.0};
+  double2 ra[4], rb[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    ra[e] = Ap[e];
+    rb[e] = Bp[e];
   }
+  auto stash = [&]() {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      sA[0][lk + e][lrow] = ra[e].x;
+      sA[1][lk + e][lrow] = ra[e].y;
+      sB[0][lk + e][lrow] = rb[e].x;
+      sB[1][lk + e][lrow] = rb[e].y;
+    }
+  };
+  stash();
+  __syncthreads();
+  for (int kb = 0; kb < nk; ++kb) {
+    if (kb + 1 < nk) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        ra[e] = Ap[(size_t)(kb + 1) * BK + e];
+        rb[e] = Bp[(size_t)(kb + 1) * BK + e];
+      }
+    }
+    if (live) {
+      __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+      for (int kk = 0; kk < BK / 4; ++kk) {
+        const int kr = kk * 4 + (lane >> 4);
+        double ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+          ar[mb] = sA[0][kr][wm * 32 + mb * 16 + (lane & 15)];
+          ai[mb] = sA[1][kr][wm * 32 + mb * 16 + (lane & 15)];
+        }
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+          br[nb] = sB[0][kr][wn * 32 + nb * 16 + (lane & 15)];
+          bi[nb] = sB[1][kr][wn * 32 + nb * 16 + (lane & 15)];
+        }
+        double sa[2], sb[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          sa[u] = ar[u] + ai[u];
+          sb[u] = br[u] + bi[u];
+        }
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb) {
+            p[0][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[mb], br[nb], p[0][mb][nb], 0, 0, 0);
+            p[1][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[mb], bi[nb], p[1][mb][nb], 0, 0, 0);
+            p[2][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[mb], sb[nb], p[2][mb][nb], 0, 0, 0);
+          }
+      }
+      __builtin_amdgcn_s_setprio(0);
+    }
+    __syncthreads();  // every wave is done with this block
+    if (kb + 1 < nk) stash();
+    __syncthreads();
+  }
+  double2* P = g.P[c] + (size_t)b * Mtot * Mtot;
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
@@ -887,9 +866,9 @@ __global__ __launch_bounds__(256, 2) void zgemm_f64_kernel(GemmArgs g) {
       for (int v = 0; v < 4; ++v) {
         const int row = tm * BM + wm * 32 + mb * 16 + 4 * v + (lane >> 4);
         const int col = tn * BM + wn * 32 + nb * 16 + (lane & 15);
-        double2 P0 = make_double2(acc[0][0][mb][nb][v], acc[0][1][mb][nb][v]);
-        double2 P1 = make_double2(acc[1][0][mb][nb][v], acc[1][1][mb][nb][v]);
-        epilogue_store(g, b, row, col, P0, P1);
+        const double re = p[0][mb][nb][v] - p[1][mb][nb][v];
+        const double im = p[2][mb][nb][v] - p[0][mb][nb][v] - p[1][mb][nb][v];
+        if (row < Mtot && col < Mtot) P[(size_t)row * Mtot + col] = make_double2(re, im);
       }
 }
 
@@ -2453,13 +2432,11 @@ void launch_gather(const GatherArgs& a, bool left, bool f32, hipStream_t s) {
 }
 void launch_gemm(const GemmArgs& g, int precision, hipStream_t s) {
   const int total = g.nb * g.tms * g.tns;
-  dim3 grid((unsigned)(((total + kXcds - 1) / kXcds) * kXcds));
-  if (precision == 0) {
-    hipLaunchKernelGGL(zgemm_f64_kernel, grid, dim3(256), 0, s, g);
-  } else {
-    dim3 grid2((unsigned)(((2 * total + kXcds - 1) / kXcds) * kXcds));
+  dim3 grid2((unsigned)(((2 * total + kXcds - 1) / kXcds) * kXcds));  // both combinations
+  if (precision == 0)
+    hipLaunchKernelGGL(zgemm_f64_kernel, grid2, dim3(256), 0, s, g);
+  else
     hipLaunchKernelGGL(zgemm_f32_kernel, grid2, dim3(256), 0, s, g);
-  }
 }
 void launch_unmix(const GemmArgs& g, hipStream_t s) { hipLaunchKernelGGL(unmix_kernel, dim3(4096), dim3(256), 0, s, g); }
 void launch_loop(const LoopArgs& a, hipStream_t s) {
