@@ -33,8 +33,8 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2405_20996_amd", "csrc", "kqft_kernels.hi
 # 1 GiB), valid for the GEMM source they were taken on (first 16 hex digits of the SHA-256
 # of the kernel file's GEMM section) and the batch of 67 transfer frequencies.
 MEASURED_TRAFFIC = {
-    "zgemm_f32_kernel": {"src": "3c017d3dc2a9abae", "omega_batch": 67, "n": 201, "nq": 2001,
-                         "read_bytes": 67.313e9, "write_bytes": 1.446e9},
+    "zgemm_f32_kernel": {"src": "fe80ed420dcc9468", "omega_batch": 67, "n": 201, "nq": 2001,
+                         "read_bytes": 67.352e9, "write_bytes": 1.446e9},
 }
 
 
