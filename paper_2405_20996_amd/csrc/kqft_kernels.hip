@@ -1080,14 +1080,15 @@ void launch_rowpanel(const GemmArgs& g, int precision, hipStream_t s) {
 // C[b] = op(A[b]) . B[b] in FP64 complex on v_mfma_f64_16x16x4f64, row-major operands:
 // op(A)[m][k] = A[m][k] (TA = false, lda = row length of A) or A[k][m] (TA = true), B[k][n],
 // C[m][n] overwritten.  Arbitrary M, N, K (edges zero-filled and masked).  64x64 complex
-// tile per 256-thread workgroup, four waves of 32x32, K blocks of 16 staged through a double
-// LDS buffer [k][m|n], three real products per complex multiply-add (Gauss), tiles of one
+// tile per 256-thread workgroup, four waves of 32x32, K blocks of 16 staged through a single
+// LDS buffer [k][m|n] (34 KB: three workgroups per CU), three real products per complex
+// multiply-add (Gauss), tiles of one
 // batch entry row-major and spread over the XCDs as in the bubble GEMMs.  Used by the
 // adjoint's transposed products and the Matsubara bubble.
-__global__ __launch_bounds__(256, 2) void zgemm_nn_kernel(ZgemmArgs g) {
+__global__ __launch_bounds__(256, 3) void zgemm_nn_kernel(ZgemmArgs g) {
   using namespace f64g;
-  __shared__ double sA[2][2][BK][LDP];
-  __shared__ double sB[2][2][BK][LDP];
+  __shared__ double sA[2][BK][LDP];  // single buffer: three workgroups per CU
+  __shared__ double sB[2][BK][LDP];
   const int tiles = g.tiles_m * g.tiles_n;
   const int total = g.batch * tiles;
   const int per_xcd = (total + kXcds - 1) / kXcds;
@@ -1122,14 +1123,14 @@ __global__ __launch_bounds__(256, 2) void zgemm_nn_kernel(ZgemmArgs g) {
       rb[e] = (kb < g.K && nb < g.N) ? B[(size_t)kb * g.ldb + nb] : czero();
     }
   };
-  auto stash = [&](int buf) {
+  auto stash = [&]() {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int kk = g.TA ? a_r : a_c + e, mm = g.TA ? a_c + e : a_r;
-      sA[buf][0][kk][mm] = ra[e].x;
-      sA[buf][1][kk][mm] = ra[e].y;
-      sB[buf][0][b_k][b_n + e] = rb[e].x;
-      sB[buf][1][b_k][b_n + e] = rb[e].y;
+      sA[0][kk][mm] = ra[e].x;
+      sA[1][kk][mm] = ra[e].y;
+      sB[0][b_k][b_n + e] = rb[e].x;
+      sB[1][b_k][b_n + e] = rb[e].y;
     }
   };
   d4 p[3][2][2];
@@ -1141,10 +1142,9 @@ __global__ __launch_bounds__(256, 2) void zgemm_nn_kernel(ZgemmArgs g) {
       for (int nb = 0; nb < 2; ++nb) p[x][mb][nb] = d4{0.0, 0.0, 0.0, 0.0};
   const int nk = (g.K + BK - 1) / BK;
   load(0);
-  stash(0);
+  stash();
   __syncthreads();
   for (int kb = 0; kb < nk; ++kb) {
-    const int buf = kb & 1;
     if (kb + 1 < nk) load((kb + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
@@ -1152,10 +1152,10 @@ __global__ __launch_bounds__(256, 2) void zgemm_nn_kernel(ZgemmArgs g) {
       double ar[2], ai[2], br[2], bi[2], sa[2], sb[2];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        ar[u] = sA[buf][0][kr][wm * 32 + u * 16 + (lane & 15)];
-        ai[u] = sA[buf][1][kr][wm * 32 + u * 16 + (lane & 15)];
-        br[u] = sB[buf][0][kr][wn * 32 + u * 16 + (lane & 15)];
-        bi[u] = sB[buf][1][kr][wn * 32 + u * 16 + (lane & 15)];
+        ar[u] = sA[0][kr][wm * 32 + u * 16 + (lane & 15)];
+        ai[u] = sA[1][kr][wm * 32 + u * 16 + (lane & 15)];
+        br[u] = sB[0][kr][wn * 32 + u * 16 + (lane & 15)];
+        bi[u] = sB[1][kr][wn * 32 + u * 16 + (lane & 15)];
         sa[u] = ar[u] + ai[u];
         sb[u] = br[u] + bi[u];
       }
@@ -1168,7 +1168,8 @@ __global__ __launch_bounds__(256, 2) void zgemm_nn_kernel(ZgemmArgs g) {
           p[2][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[mb], sb[nb], p[2][mb][nb], 0, 0, 0);
         }
     }
-    if (kb + 1 < nk) stash(buf ^ 1);
+    __syncthreads();  // every wave is done with this block
+    if (kb + 1 < nk) stash();
     __syncthreads();
   }
   double2* C = g.C + (size_t)b * g.strideC;
