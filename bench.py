@@ -33,18 +33,18 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2405_20996_amd", "csrc", "kqft_kernels.hi
 # 1 GiB), valid for the GEMM source they were taken on (first 16 hex digits of the SHA-256
 # of the kernel file's GEMM section) and the batch of 67 transfer frequencies.
 MEASURED_TRAFFIC = {
-    "zgemm_f32_kernel": {"src": "fe80ed420dcc9468", "omega_batch": 67, "n": 201, "nq": 2001,
+    "zgemm_f32_kernel": {"src": "629fd9fe3706776f", "omega_batch": 67, "n": 201, "nq": 2001,
                          "read_bytes": 67.352e9, "write_bytes": 1.446e9},
 }
 
 
 def kernel_src_digest() -> str:
-    """Digest of the GEMM section of the kernel source (epilogue, tile order, both GEMMs)."""
+    """Digest of the split-FP32 GEMM kernel's source (its section of the kernel file)."""
     import hashlib
     with open(KERNEL_SRC, "r", encoding="utf-8") as f:
         src = f.read()
-    a = src.index("// ======================================================================== epilogue")
-    b = src.index("// ======================================================================== SDE loop")
+    a = src.index("// ======================================================================== split-FP32 GEMM")
+    b = src.index("// The two combinations' products of the GEMM's tile range into the classes", a)
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
