@@ -210,7 +210,9 @@ def main():
                 "per_launch": {"algorithmic_flop": F / max(hr["gemm_launches_per_step"], 1),
                                "avg_ms": round(hr["gemm_avg_launch_ms"], 4)},
                 "executed_flop_per_complex_mac": 6,
-                "executed_frac": round(0.75 * hr["gemm_tflops"] / peak, 4)}
+                "executed_frac": round(0.75 * hr["gemm_tflops"] / peak, 4),
+                "frac_note": "frac counts 8 algorithmic flops per complex multiply-add; the MFMAs execute 6 "
+                             "(three real products), so frac may exceed 1 while executed_frac stays below it"}
 
     # CPU baseline: the FP64 oracle on a bounded sample of the same outputs
     cpu = None
