@@ -1141,32 +1141,36 @@ __global__ __launch_bounds__(256, 3) void zgemm_nn_kernel(ZgemmArgs g) {
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb) p[x][mb][nb] = d4{0.0, 0.0, 0.0, 0.0};
   const int nk = (g.K + BK - 1) / BK;
+  // a wave whose 32-row or 32-column block lies wholly past the edge of C skips its MFMAs
+  const bool live = tm * BM + wm * 32 < g.M && tn * BM + wn * 32 < g.N;
   load(0);
   stash();
   __syncthreads();
   for (int kb = 0; kb < nk; ++kb) {
     if (kb + 1 < nk) load((kb + 1) * BK);
+    if (live) {
 #pragma unroll
-    for (int kk = 0; kk < BK / 4; ++kk) {
-      const int kr = kk * 4 + (lane >> 4);
-      double ar[2], ai[2], br[2], bi[2], sa[2], sb[2];
+      for (int kk = 0; kk < BK / 4; ++kk) {
+        const int kr = kk * 4 + (lane >> 4);
+        double ar[2], ai[2], br[2], bi[2], sa[2], sb[2];
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        ar[u] = sA[0][kr][wm * 32 + u * 16 + (lane & 15)];
-        ai[u] = sA[1][kr][wm * 32 + u * 16 + (lane & 15)];
-        br[u] = sB[0][kr][wn * 32 + u * 16 + (lane & 15)];
-        bi[u] = sB[1][kr][wn * 32 + u * 16 + (lane & 15)];
-        sa[u] = ar[u] + ai[u];
-        sb[u] = br[u] + bi[u];
-      }
-#pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-          p[0][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[mb], br[nb], p[0][mb][nb], 0, 0, 0);
-          p[1][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[mb], bi[nb], p[1][mb][nb], 0, 0, 0);
-          p[2][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[mb], sb[nb], p[2][mb][nb], 0, 0, 0);
+        for (int u = 0; u < 2; ++u) {
+          ar[u] = sA[0][kr][wm * 32 + u * 16 + (lane & 15)];
+          ai[u] = sA[1][kr][wm * 32 + u * 16 + (lane & 15)];
+          br[u] = sB[0][kr][wn * 32 + u * 16 + (lane & 15)];
+          bi[u] = sB[1][kr][wn * 32 + u * 16 + (lane & 15)];
+          sa[u] = ar[u] + ai[u];
+          sb[u] = br[u] + bi[u];
         }
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb) {
+            p[0][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[mb], br[nb], p[0][mb][nb], 0, 0, 0);
+            p[1][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[mb], bi[nb], p[1][mb][nb], 0, 0, 0);
+            p[2][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[mb], sb[nb], p[2][mb][nb], 0, 0, 0);
+          }
+      }
     }
     __syncthreads();  // every wave is done with this block
     if (kb + 1 < nk) stash();
