@@ -51,3 +51,21 @@ def test_bench_flop_count():
     import bench
     assert abs(bench.algorithmic_flops(201, 2001) / 1e12 - 16.8053) < 1e-3
     assert abs(bench.algorithmic_flops(31, 201) / 1e9 - 6.5337) < 1e-3
+
+
+def test_bench_traffic_is_tied_to_the_measured_kernel_source():
+    """The roofline traffic is reported only for the split GEMM source it was measured on: the
+    digest reads that kernel's own section of the kernel file, and a different digest (any edit
+    of the kernel) turns the traffic off."""
+    sys.path.insert(0, ROOT)
+    import bench
+    d = bench.kernel_src_digest()
+    assert len(d) == 16 and all(c in "0123456789abcdef" for c in d)
+    m = bench.MEASURED_TRAFFIC["zgemm_f32_kernel"]
+    got = bench.measured_traffic("zgemm_f32_kernel", m["n"], m["nq"], m["omega_batch"])
+    if m["src"] == d:
+        assert got == round(m["read_bytes"] + m["write_bytes"], 0)
+    else:
+        assert got is None
+    assert bench.measured_traffic("zgemm_f32_kernel", m["n"] + 2, m["nq"], m["omega_batch"]) is None
+    assert bench.measured_traffic("zgemm_f64_kernel", m["n"], m["nq"], m["omega_batch"]) is None
