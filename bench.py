@@ -64,6 +64,64 @@ def algorithmic_flops(n, nq, n_w=None):
     return 2.0 * n_w * 8.0 * (4 * n + 4) * 4.0 * nq * (4 * n + 4)
 
 
+def seeded_vertex(K, torch, dev, n, q, P, U, noise):
+    """PT2 seed (K1 of the bare bubble in each channel) plus the seeded noise on every class."""
+    g = K.Grid(n)
+    bare = K.Vertex(g, U)
+    chans = []
+    for r in range(3):
+        k1 = K.bubble(r, bare, bare, P, q, class_mask=K.K1).K1
+        c = K.Channel(1.0, *[torch.from_numpy(noise[r][x]).to(dev) for x in K.CLASSES])
+        c.K1 = c.K1 + k1
+        chans.append(c)
+    return K.Vertex(g, U, chans)
+
+
+def small_workload(K, torch, dev, seed_noise, with_cpu):
+    """The channel-a bubble (all classes) at N = 31, Nq = 201, seeded as the headline workload:
+    GPU time per call on both paths (median of 10 after 3 warm-ups), and with the oracle its
+    whole-array max-norm errors and the oracle's time on all host cores and on one core."""
+    import numpy as np
+    n1, nq1, U, T, Dl = 31, 201, 1.0, 0.1, 1.0
+    noise = seed_noise(n1, 0)
+    q, P = K.Quad(nq1), K.Propagator(Dl, T)
+    V = seeded_vertex(K, torch, dev, n1, q, P, U, noise)
+    res = {"workload": f"channel-a bubble (K1, K2, K2', K3), N={n1}, Nq={nq1}, same seeding as the headline",
+           "gflop": round(algorithmic_flops(n1, nq1) / 1e9, 3)}
+    outs = {}
+    for name, prec in (("fp64", K.FP64), ("split", K.SPLIT_FP32)):
+        out = K.alloc_channel(n1)
+        for _ in range(3):
+            K.bubble(0, V, V, P, q, precision=prec, out=out)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(10):
+            t0 = time.perf_counter()
+            K.bubble(0, V, V, P, q, precision=prec, out=out)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        res[f"gpu_ms_{name}"] = round(1e3 * float(np.median(ts)), 3)
+        outs[name] = out
+    if with_cpu:
+        import oracle as O
+        from threadpoolctl import threadpool_limits
+        og, oq, op = O.Grid(n1), O.Quad(nq1), O.Prop(Dl, T)
+        ov = O.seeded_vertex(og, U, op, oq, noise)
+        t0 = time.perf_counter()
+        ref = O.bubble(0, ov, ov, op, oq)
+        res["oracle_seconds_all_cores"] = round(time.perf_counter() - t0, 3)
+        res["oracle_cores"] = len(os.sched_getaffinity(0))
+        with threadpool_limits(limits=1, user_api="openmp"):
+            t0 = time.perf_counter()
+            O.bubble(0, ov, ov, op, oq)
+            res["oracle_seconds_one_core"] = round(time.perf_counter() - t0, 3)
+        for name, out in outs.items():
+            res[f"rel_err_vs_oracle_{name}"] = max(
+                float(np.abs(getattr(out, c).cpu().numpy() - getattr(ref, c)).max() / np.abs(getattr(ref, c)).max())
+                for c in K.CLASSES)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,14 +168,8 @@ def main():
     noise = seed_noise(n, 0)
     log(f"noise ready in {time.time() - t0:.1f}s; uploading")
     g, q, P = K.Grid(n), K.Quad(nq), K.Propagator(Dl, T)
-    bare = K.Vertex(g, U)
-    chans = []
-    for r in range(3):
-        k1 = K.bubble(r, bare, bare, P, q, class_mask=K.K1).K1
-        c = K.Channel(1.0, *[torch.from_numpy(noise[r][x]).to(dev) for x in K.CLASSES])
-        c.K1 = c.K1 + k1
-        chans.append(c)
-    V = K.Vertex(g, U, chans)
+    V = seeded_vertex(K, torch, dev, n, q, P, U, noise)
+    chans = V.ch
     torch.cuda.synchronize()
     log("vertex resident on the device")
 
@@ -289,6 +341,9 @@ def main():
             oracle_err[name] = worst
         log(f"sampled relative error vs oracle: {oracle_err}")
 
+    small = small_workload(K, torch, dev, seed_noise, not args.no_cpu_baseline)
+    log(f"small workload: {small}")
+
     line = {
         "metric": METRIC,
         "value": round(hr["gflops"], 2),
@@ -315,6 +370,7 @@ def main():
         "split_vs_fp64_sigma_chi_rel_err": sd_err,
         "sigma_chi_seconds": {k: round(v[2], 3) for k, v in derived.items()},
         "sampled_rel_err_vs_oracle": oracle_err,
+        "small_workload": small,
     }
     print(json.dumps(line), flush=True)
 
