@@ -12,7 +12,7 @@ resident in HBM.  Algorithmic work per step:
 `value` is F / (ms per step) of the split-FP32 path when its error against the FP64
 path is <= 1e-6, otherwise of the FP64 path.  The split-FP32 path is the lowest rung of the
 split ladder: operands rounded once to FP32 (no hi*lo correction products), FP32 MFMA with
-FP32 partial sums over 64 complex terms promoted to FP64.
+FP32 partial sums over 128 complex terms promoted to FP64.
 
 Prints one JSON line.  --gpus above 1 is rejected: the library runs on one GPU.
 """

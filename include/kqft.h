@@ -88,8 +88,8 @@ enum { KQFT_CH_A = 0, KQFT_CH_P = 1, KQFT_CH_T = 2 };
 /* arithmetic of the bubble contraction: FP64 MFMA, or KQFT_SPLIT_FP32, the lowest rung of
    the split-precision ladder: every panel operand (vertex times Pi, formed in FP64) is rounded
    once to FP32 -- its hi part; the lo remainder is dropped, no hi*lo correction products are
-   formed -- and multiplied on FP32 MFMA with FP32 partial sums over 64 complex terms promoted
-   to FP64 between them.  Max-norm error about 1.5e-7 of the FP64 result at N = 201, within the
+   formed -- and multiplied on FP32 MFMA with FP32 partial sums over 128 complex terms promoted
+   to FP64 between them.  Max-norm error about 3.3e-7 of the FP64 result at N = 201, within the
    1e-6 bound, so the compensated rungs (extra hi*lo + lo*hi products) are not built. */
 enum { KQFT_FP64 = 0, KQFT_SPLIT_FP32 = 1 };
 /* propagator pair: Pi = G G, or the differentiated Pidot = S G + G S with the
